@@ -1,0 +1,257 @@
+"""TEST INFRASTRUCTURE ONLY: ctypes binding of the plain FP64 CPU oracle.
+
+The oracle (``mg_oracle.c``) is a slow, obviously correct implementation of
+the Q1 finite-element multigrid Poisson solver of HONEI (arXiv 0904.4152,
+Sec. 2.1 and Sec. 6.2).  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may import this package; the GPU product
+path never does.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "mg_oracle.c")
+_LIB = os.path.join(_HERE, "libmg_oracle.so")
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_fp = ctypes.POINTER(ctypes.c_float)
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (plain -O2, no FMA contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared",
+                               "-ffp-contract=off", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class OrOpts(ctypes.Structure):
+    _fields_ = [("nu_pre", ctypes.c_int), ("nu_post", ctypes.c_int),
+                ("omega", ctypes.c_double), ("rel_tol", ctypes.c_double),
+                ("max_cycles", ctypes.c_int), ("fixed_cycles", ctypes.c_int),
+                ("inner_reduction", ctypes.c_double), ("inner_max_cycles", ctypes.c_int)]
+
+
+class OrStats(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("cycles", ctypes.c_int),
+                ("outer_steps", ctypes.c_int), ("bnorm", ctypes.c_double),
+                ("rel_res", ctypes.c_double), ("n_hist", ctypes.c_int),
+                ("res_hist", ctypes.c_double * 256)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = ctypes.CDLL(build())
+        L = _lib
+        L.or_element_stiffness.argtypes = [_dp, _dp, _dp]
+        L.or_assemble.argtypes = [ctypes.c_int, _dp, ctypes.c_int, _dp]
+        L.or_load_vector.argtypes = [ctypes.c_int, _dp, ctypes.c_int, ctypes.c_int, _dp]
+        L.or_l2_error_sinsin.argtypes = [ctypes.c_int, _dp, _dp]
+        L.or_l2_error_sinsin.restype = ctypes.c_double
+        L.or_spmv.argtypes = [ctypes.c_int, _dp, _dp, _dp]
+        L.or_defect.argtypes = [ctypes.c_int, _dp, _dp, _dp, _dp]
+        L.or_jacobi.argtypes = [ctypes.c_int, _dp, _dp, _dp, _dp, ctypes.c_double]
+        L.or_restrict.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_int]
+        L.or_prolong_add.argtypes = [ctypes.c_int, _dp, _dp]
+        L.or_norm2.argtypes = [ctypes.c_size_t, _dp]
+        L.or_norm2.restype = ctypes.c_double
+        L.or_cholesky.argtypes = [ctypes.c_int, _dp]
+        L.or_cholesky_solve.argtypes = [ctypes.c_int, _dp, _dp]
+        L.or_spmv_f32.argtypes = [ctypes.c_int, _fp, _fp, _fp]
+        L.or_jacobi_f32.argtypes = [ctypes.c_int, _fp, _fp, _fp, _fp, ctypes.c_float]
+        L.or_restrict_f32.argtypes = [ctypes.c_int, _fp, _fp]
+        L.or_prolong_add_f32.argtypes = [ctypes.c_int, _fp, _fp]
+        L.or_hier_create.argtypes = [ctypes.c_int, ctypes.c_int, _dp]
+        L.or_hier_create.restype = ctypes.c_void_p
+        L.or_hier_destroy.argtypes = [ctypes.c_void_p]
+        L.or_hier_N.argtypes = [ctypes.c_void_p, ctypes.c_int]
+        L.or_hier_bands.argtypes = [ctypes.c_void_p, ctypes.c_int]
+        L.or_hier_bands.restype = _dp
+        L.or_hier_coords.argtypes = [ctypes.c_void_p, ctypes.c_int]
+        L.or_hier_coords.restype = _dp
+        L.or_vcycle.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp, _dp, ctypes.POINTER(OrOpts)]
+        L.or_solve_fp64.argtypes = [ctypes.c_void_p, _dp, _dp, ctypes.POINTER(OrOpts),
+                                    ctypes.POINTER(OrStats)]
+        L.or_solve_mixed_emulated.argtypes = [ctypes.c_void_p, _dp, _dp,
+                                              ctypes.POINTER(OrOpts), ctypes.POINTER(OrStats)]
+    return _lib
+
+
+def _d(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(_dp)
+
+
+def _f(a: np.ndarray):
+    assert a.dtype == np.float32 and a.flags.c_contiguous
+    return a.ctypes.data_as(_fp)
+
+
+def opts(nu_pre=2, nu_post=2, omega=0.7, rel_tol=1e-8, max_cycles=100, fixed_cycles=0,
+         inner_reduction=1e-2, inner_max_cycles=8) -> OrOpts:
+    return OrOpts(nu_pre, nu_post, omega, rel_tol, max_cycles, fixed_cycles,
+                  inner_reduction, inner_max_cycles)
+
+
+def element_stiffness(xq, yq) -> np.ndarray:
+    xq = np.ascontiguousarray(xq, dtype=np.float64)
+    yq = np.ascontiguousarray(yq, dtype=np.float64)
+    K = np.zeros(16)
+    lib().or_element_stiffness(_d(xq), _d(yq), _d(K))
+    return K.reshape(4, 4)
+
+
+def assemble(N: int, xy: np.ndarray, dirichlet: bool = True) -> np.ndarray:
+    xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1)
+    bands = np.zeros(9 * N * N)
+    lib().or_assemble(N, _d(xy), int(dirichlet), _d(bands))
+    return bands.reshape(9, N * N)
+
+
+def load_vector(N: int, xy: np.ndarray, fn: int = 0, dirichlet: bool = True) -> np.ndarray:
+    xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1)
+    b = np.zeros(N * N)
+    lib().or_load_vector(N, _d(xy), fn, int(dirichlet), _d(b))
+    return b
+
+
+def l2_error_sinsin(N: int, xy: np.ndarray, u: np.ndarray) -> float:
+    xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1)
+    return lib().or_l2_error_sinsin(N, _d(xy), _d(np.ascontiguousarray(u)))
+
+
+def spmv(N, bands, x):
+    y = np.zeros(N * N)
+    lib().or_spmv(N, _d(np.ascontiguousarray(bands).reshape(-1)), _d(x), _d(y))
+    return y
+
+
+def defect(N, bands, b, x):
+    d = np.zeros(N * N)
+    lib().or_defect(N, _d(np.ascontiguousarray(bands).reshape(-1)), _d(b), _d(x), _d(d))
+    return d
+
+
+def jacobi(N, bands, b, x, omega=0.7):
+    y = np.zeros(N * N)
+    lib().or_jacobi(N, _d(np.ascontiguousarray(bands).reshape(-1)), _d(b), _d(x), _d(y), omega)
+    return y
+
+
+def restrict(Nf, d_f, filter=True):
+    Nc = (Nf - 1) // 2 + 1
+    bc = np.zeros(Nc * Nc)
+    lib().or_restrict(Nf, _d(d_f), _d(bc), int(filter))
+    return bc
+
+
+def prolong_add(Nf, x_c, x_f):
+    out = np.array(x_f, dtype=np.float64, copy=True)
+    lib().or_prolong_add(Nf, _d(np.ascontiguousarray(x_c)), _d(out))
+    return out
+
+
+def norm2(v) -> float:
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    return lib().or_norm2(v.size, _d(v))
+
+
+def cholesky(A: np.ndarray):
+    Lf = np.array(A, dtype=np.float64, copy=True, order="C")
+    rc = lib().or_cholesky(Lf.shape[0], _d(Lf))
+    return rc, Lf
+
+
+def spmv_f32(N, bands32, x32):
+    y = np.zeros(N * N, dtype=np.float32)
+    lib().or_spmv_f32(N, _f(np.ascontiguousarray(bands32).reshape(-1)), _f(x32), _f(y))
+    return y
+
+
+def jacobi_f32(N, bands32, b32, x32, omega=0.7):
+    y = np.zeros(N * N, dtype=np.float32)
+    lib().or_jacobi_f32(N, _f(np.ascontiguousarray(bands32).reshape(-1)), _f(b32), _f(x32),
+                        _f(y), omega)
+    return y
+
+
+def restrict_f32(Nf, d_f32):
+    Nc = (Nf - 1) // 2 + 1
+    bc = np.zeros(Nc * Nc, dtype=np.float32)
+    lib().or_restrict_f32(Nf, _f(d_f32), _f(bc))
+    return bc
+
+
+def prolong_add_f32(Nf, x_c32, x_f32):
+    out = np.array(x_f32, dtype=np.float32, copy=True)
+    lib().or_prolong_add_f32(Nf, _f(np.ascontiguousarray(x_c32)), _f(out))
+    return out
+
+
+class Hierarchy:
+    """Oracle multigrid hierarchy on the finest coordinates ``xy`` (2*n)."""
+
+    def __init__(self, L: int, xy: np.ndarray, Lc: int = 1):
+        self.L, self.Lc = L, Lc
+        self._xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1)
+        self._h = lib().or_hier_create(L, Lc, _d(self._xy))
+        if not self._h:
+            raise ValueError("oracle hierarchy creation failed (L=%d, Lc=%d)" % (L, Lc))
+
+    def close(self):
+        if self._h:
+            lib().or_hier_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def N(self, l: int) -> int:
+        return (1 << l) + 1
+
+    def bands(self, l: int) -> np.ndarray:
+        n = self.N(l) ** 2
+        ptr = lib().or_hier_bands(self._h, l)
+        return np.ctypeslib.as_array(ptr, shape=(9 * n,)).copy().reshape(9, n)
+
+    def coords(self, l: int) -> np.ndarray:
+        n = self.N(l) ** 2
+        ptr = lib().or_hier_coords(self._h, l)
+        return np.ctypeslib.as_array(ptr, shape=(2 * n,)).copy()
+
+    def vcycle(self, l: int, x: np.ndarray, b: np.ndarray, o: OrOpts | None = None):
+        x = np.array(x, dtype=np.float64, copy=True)
+        lib().or_vcycle(self._h, l, _d(x), _d(np.ascontiguousarray(b)),
+                        ctypes.byref(o or opts()))
+        return x
+
+    def solve_fp64(self, b: np.ndarray, x0: np.ndarray | None = None, o: OrOpts | None = None):
+        n = self.N(self.L) ** 2
+        x = np.zeros(n) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
+        st = OrStats()
+        lib().or_solve_fp64(self._h, _d(np.ascontiguousarray(b)), _d(x),
+                            ctypes.byref(o or opts()), ctypes.byref(st))
+        return x, st
+
+    def solve_mixed_emulated(self, b, x0=None, o: OrOpts | None = None):
+        n = self.N(self.L) ** 2
+        x = np.zeros(n) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
+        st = OrStats()
+        lib().or_solve_mixed_emulated(self._h, _d(np.ascontiguousarray(b)), _d(x),
+                                      ctypes.byref(o or opts()), ctypes.byref(st))
+        return x, st
+
+
+def hist(st: OrStats):
+    return [st.res_hist[i] for i in range(st.n_hist)]
