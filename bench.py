@@ -1,0 +1,247 @@
+#!/usr/bin/env python3
+"""Benchmark of the MI355X multigrid Poisson hot path (HONEI, arXiv 0904.4152).
+
+A step is one mixed-precision solve (FP32 V(2,2) cycles inside an FP64 defect
+correction) to 1e-8 relative residual of the 4097 x 4097 (L = 12) Q1 Poisson
+problem on a grid jittered by +-0.2 h with a Gaussian right-hand side; the
+hierarchy (bands of all levels) and b are resident in HBM before timing.
+Prints one JSON line with solves/s (value), the band-kernel roofline of the
+dominant kernel (finest-level FP32 Jacobi sweep), the band-SpMV GB/s, the
+plain FP64 solve time beside the mixed one, the L = 10 and L = 6 workloads
+and the oracle timed on the host CPU.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, published
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel-iters", type=int, default=50)
+    ap.add_argument("--only-kernels", action="store_true",
+                    help="time the band kernels only (for profiler runs)")
+    return ap.parse_args()
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_0904_4152_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel_key: str):
+    """HBM bytes per launch measured with rocprofv3 counters, if the summary
+    under profiles/ was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_hash") != kernel_source_hash():
+        return None
+    return rec.get("kernels", {}).get(kernel_key)
+
+
+def time_launches(fn, iters, torch):
+    """Average duration of fn() launches, timed with HIP events recorded on
+    the stream the kernels are launched on (torch's current stream)."""
+    st = torch.cuda.current_stream()
+    for _ in range(5):
+        fn()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(iters):
+        fn()
+    e1.record(st)
+    e1.synchronize()
+    return e0.elapsed_time(e1) * 1e-3 / iters
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build measures one GPU only (each problem and each solve "
+              "runs on a single MI355X); --gpus must be 1", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_0904_4152_amd as mg
+    import synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    ctx = mg.Context(0)
+    out = {}
+
+    # ---------------- headline workload: L = 12, jitter 0.2 h, Gaussian RHS
+    L, jit, gseed, rseed = 12, 0.2, 1003, 2003
+    t = time.perf_counter()
+    h = mg.Hierarchy(ctx, L, jitter=jit, seed=gseed)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t
+    n = h.n
+    b = torch.from_numpy(synth.rhs_gaussian(L, rseed)).to(dev)
+    x = torch.zeros_like(b)
+
+    # band kernels at full size (FP32 bands 604 MB: larger than the 256 MB
+    # Infinity Cache, so these are HBM rates)
+    rng = np.random.default_rng(0)
+    x32 = torch.from_numpy(rng.standard_normal(n).astype(np.float32)).to(dev)
+    y32 = torch.empty_like(x32)
+    b32 = torch.from_numpy(rng.standard_normal(n).astype(np.float32)).to(dev)
+    x64 = x32.double()
+    y64 = torch.empty_like(x64)
+    it = args.kernel_iters
+    t_spmv32 = time_launches(lambda: h.spmv(L, x32, y32), it, torch)
+    t_spmv64 = time_launches(lambda: h.spmv(L, x64, y64), it, torch)
+    t_jac32 = time_launches(lambda: h.jacobi(L, b32, x32, y32, 0.7), it, torch)
+    bytes_spmv32 = 11 * 4 * n
+    bytes_spmv64 = 11 * 8 * n
+    bytes_jac32 = 12 * 4 * n
+    gbs = lambda by, s: by / s / 1e9
+    out["band_kernels"] = {
+        "spmv_fp32": {"us": t_spmv32 * 1e6, "alg_bytes": bytes_spmv32,
+                      "GB_s": gbs(bytes_spmv32, t_spmv32),
+                      "frac_hbm_peak": gbs(bytes_spmv32, t_spmv32) / PEAK_HBM_GBS},
+        "spmv_fp64": {"us": t_spmv64 * 1e6, "alg_bytes": bytes_spmv64,
+                      "GB_s": gbs(bytes_spmv64, t_spmv64),
+                      "frac_hbm_peak": gbs(bytes_spmv64, t_spmv64) / PEAK_HBM_GBS},
+        "jacobi_fp32": {"us": t_jac32 * 1e6, "alg_bytes": bytes_jac32,
+                        "GB_s": gbs(bytes_jac32, t_jac32),
+                        "frac_hbm_peak": gbs(bytes_jac32, t_jac32) / PEAK_HBM_GBS},
+    }
+    del x32, y32, b32, x64, y64
+    if args.only_kernels:
+        print(json.dumps(out))
+        return
+
+    mixed = mg.default_opts(precision=mg.MG_PREC_MIXED, rel_tol=1e-8)
+    fp64 = mg.default_opts(precision=mg.MG_PREC_FP64, rel_tol=1e-8)
+
+    def solve(hh, bb, xx, o):
+        xx.zero_()
+        st = hh.solve(bb, xx, o)
+        if st.status != 0 or st.rel_res > 1e-8:
+            raise RuntimeError("solve did not reach 1e-8: status %d rel_res %g"
+                               % (st.status, st.rel_res))
+        return st
+
+    for _ in range(args.warmup):
+        solve(h, b, x, mixed)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = [solve(h, b, x, mixed) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t_mixed = (time.perf_counter() - t0) / args.steps
+    st_m = stats[-1]
+
+    st_f = solve(h, b, x, fp64)  # warm the FP64 graphs
+    t0 = time.perf_counter()
+    nf = 2
+    for _ in range(nf):
+        st_f = solve(h, b, x, fp64)
+    torch.cuda.synchronize()
+    t_fp64 = (time.perf_counter() - t0) / nf
+    out["L12"] = {
+        "n": n, "setup_s": t_setup,
+        "mixed": {"ms": t_mixed * 1e3, "outer_steps": st_m.outer_steps,
+                  "inner_cycles": st_m.cycles, "rel_res": st_m.rel_res,
+                  "alg_GB_s": st_m.alg_bytes / t_mixed / 1e9},
+        "fp64": {"ms": t_fp64 * 1e3, "cycles": st_f.cycles, "rel_res": st_f.rel_res,
+                 "alg_GB_s": st_f.alg_bytes / t_fp64 / 1e9},
+        "mixed_speedup_vs_fp64": t_fp64 / t_mixed,
+    }
+    h.close()
+    del b, x
+    torch.cuda.empty_cache()
+
+    # ---------------- L = 10 (FP64 vs mixed) and L = 6 (sin sin, FP64)
+    for name, (LL, a, gs, kind, reps) in {"L10": (10, 0.2, 1002, "uniform", 5),
+                                          "L6": (6, 0.0, 0, "sinsin", 20)}.items():
+        hh = mg.Hierarchy(ctx, LL, jitter=a, seed=gs)
+        if kind == "uniform":
+            bb = torch.from_numpy(synth.rhs_uniform(LL, 2002)).to(dev)
+        else:
+            bb = torch.empty(hh.n, dtype=torch.float64, device=dev)
+            hh.rhs_sinsin(bb)
+        xx = torch.zeros_like(bb)
+        rec = {}
+        for pname, o in (("fp64", fp64), ("mixed", mixed)):
+            solve(hh, bb, xx, o)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                s = solve(hh, bb, xx, o)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / reps
+            rec[pname] = {"ms": dt * 1e3, "solves_s": 1.0 / dt, "cycles": s.cycles,
+                          "outer_steps": s.outer_steps, "rel_res": s.rel_res}
+        out[name] = rec
+        hh.close()
+
+    # ---------------- oracle on the host CPU (bounded sample)
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        xy = synth.coords(L, jit, gseed)
+        bh = synth.rhs_gaussian(L, rseed)
+        oh = oracle.Hierarchy(L, xy)
+        t0 = time.perf_counter()
+        _, ost = oh.solve_fp64(bh, o=oracle.opts(rel_tol=1e-8))
+        dt = time.perf_counter() - t0
+        cpu = {"value": 1.0 / dt, "unit": "solves/s", "cores": 1, "kind": "oracle",
+               "sample": "one plain FP64 V(2,2) solve to 1e-8 of the same L=12 problem "
+                         "(%d cycles, %.1f s, assembly excluded), single thread" % (ost.cycles, dt)}
+        oh.close()
+
+    roof_achieved = out["band_kernels"]["jacobi_fp32"]["GB_s"]
+    line = {
+        "metric": "MG solves/s & band-SpMV GB/s (mixed vs FP64 @1e-8 rel.res); serving p99",
+        "value": 1.0 / t_mixed,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t_mixed * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "Q1 Poisson mixed-precision MG solve, 4097x4097 (L=12), "
+                               "jitter 0.2h seed 1003, Gaussian RHS seed 2003, V(2,2) "
+                               "omega 0.7, rel.res 1e-8",
+                   "L": L, "unknowns": n},
+        "roofline": {"bound": "hbm", "achieved": roof_achieved, "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": roof_achieved / PEAK_HBM_GBS,
+                     "kernel": "k_stencil<float, OP_JACOBI> (finest-level FP32 Jacobi sweep)",
+                     "traffic": traffic_from_profiles("jacobi_fp32")},
+        "cpu_baseline": cpu,
+    }
+    line.update(out)
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

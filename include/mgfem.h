@@ -1,0 +1,192 @@
+/*
+ * mgfem.h -- C ABI of the MI355X multigrid Poisson library.
+ *
+ * The library solves the Poisson problem -Laplace(u) = f on the unit square
+ * (HONEI, arXiv 0904.4152, Sec. 2.1, eq. 1) discretised with conforming
+ * bilinear Q1 finite elements on a tensor-product grid that may be deformed
+ * (jittered), fully assembled into nine bands (Sec. 2.1; Sec. 4.1 banded
+ * matrices with fixed band positions), with a geometric V-cycle of two damped
+ * Jacobi pre- and post-smoothing steps (Sec. 6.2), in FP64 or as an FP64
+ * defect correction around single-precision multigrid cycles (Sec. 6.2,
+ * mixed precision).
+ *
+ * Conventions shared by every call:
+ *   - level l has N = 2^l + 1 nodes per side and n = N*N unknowns (Sec. 2.1:
+ *     level L gives (2^L+1)^2 unknowns); node (i,j) (i along x) has index
+ *     p = j*N + i;
+ *   - band k = 0..8 holds A[p][p + off_k] at index p, off_k =
+ *     (k/3 - 1)*N + (k%3 - 1), i.e. offsets -N-1, -N, -N+1, -1, 0, 1, N-1,
+ *     N, N+1;
+ *   - homogeneous Dirichlet conditions on the whole boundary: boundary rows
+ *     and columns are zero except a unit diagonal;
+ *   - every vector argument named dev_* or documented as "device" is a
+ *     contiguous, unpadded device buffer of n elements in index order p,
+ *     owned by the caller; the library never keeps such a pointer after the
+ *     call returns;
+ *   - stream arguments are hipStream_t values passed as void* (NULL is the
+ *     default stream); asynchronous calls only enqueue work on it;
+ *   - every call returns an mg_status; on a non-OK status the outputs are
+ *     unspecified and mg_last_error() describes the failure (thread local).
+ *     No C++ exception crosses this boundary.
+ */
+#ifndef MGFEM_H
+#define MGFEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MG_OK = 0,
+    MG_ERR_INVALID = 1,  /* bad argument (level, pointer, size, option) */
+    MG_ERR_NOMEM = 2,    /* device memory budget or device memory exhausted */
+    MG_ERR_NOCONV = 3,   /* max_cycles reached before rel_tol */
+    MG_ERR_NUMERIC = 4,  /* NaN/Inf or divergence (residual > 1e3 ||b||) */
+    MG_ERR_DEVICE = 5,   /* HIP runtime error */
+    MG_ERR_BUSY = 6      /* server: ticket still pending */
+} mg_status;
+
+typedef enum { MG_PREC_FP64 = 0, MG_PREC_MIXED = 1 } mg_precision;
+typedef enum { MG_F64 = 0, MG_F32 = 1 } mg_dtype;
+
+typedef struct mg_context mg_context;
+typedef struct mg_hierarchy mg_hierarchy;
+typedef struct mg_server mg_server;
+
+#define MG_MAX_LEVEL 14
+#define MG_MAX_COARSE_LEVEL 3
+#define MG_HIST 128
+
+/* Solver options (Sec. 6.2: V cycle, two damped Jacobi pre- and
+ * post-smoothing steps; mixed precision defect correction). */
+typedef struct {
+    int nu_pre;              /* pre-smoothing sweeps (2) */
+    int nu_post;             /* post-smoothing sweeps (2) */
+    double omega;            /* Jacobi damping (0.7) */
+    double rel_tol;          /* stop when ||b - A x||_2 <= rel_tol ||b||_2 (1e-8) */
+    int max_cycles;          /* FP64: V-cycles; mixed: outer steps (100) */
+    mg_precision precision;  /* MG_PREC_FP64 or MG_PREC_MIXED */
+    double inner_reduction;  /* mixed: FP32 residual reduction per outer step (1e-2) */
+    int inner_max_cycles;    /* mixed: cap on FP32 cycles per outer step (8) */
+    int fixed_cycles;        /* > 0: run exactly this many cycles / outer steps */
+    int use_graph;           /* 1: replay captured HIP graphs for the cycles (1) */
+} mg_solve_opts;
+
+typedef struct {
+    mg_status status;
+    int cycles;              /* FP64 V-cycles, or FP32 V-cycles of the mixed solve */
+    int outer_steps;         /* mixed: FP64 defect-correction updates */
+    double bnorm;            /* ||b||_2 */
+    double rel_res;          /* ||b - A x||_2 / ||b||_2 at exit, evaluated in FP64 */
+    double seconds;          /* host wall time of the call */
+    double alg_bytes;        /* algorithmic HBM bytes of the kernels launched */
+    int n_hist;
+    double res_hist[MG_HIST]; /* relative residual after each cycle / outer step */
+} mg_stats;
+
+/* Defaults: 2, 2, 0.7, 1e-8, 100, FP64, 1e-2, 8, 0, 1. */
+void mg_default_opts(mg_solve_opts* opts);
+const char* mg_last_error(void);
+const char* mg_status_string(mg_status s);
+
+/* ---- context -------------------------------------------------------------
+ * A context binds one HIP device and a device-memory budget in bytes (0:
+ * no limit beyond the device).  Every allocation of the library is charged
+ * against it; a request that would exceed it fails with MG_ERR_NOMEM and
+ * leaves nothing allocated (Sec. 4.2: device memory is a hard limit and the
+ * library fails cleanly when more is requested).  One context per thread. */
+mg_status mg_context_create(int device, size_t hbm_budget_bytes, mg_context** out);
+mg_status mg_context_destroy(mg_context* ctx);
+mg_status mg_context_memory(const mg_context* ctx, size_t* in_use, size_t* high_water);
+
+/* ---- hierarchy -----------------------------------------------------------
+ * Device-resident grid hierarchy for levels coarse_level..L (Sec. 2.1,
+ * geometric multigrid): node coordinates, nine FP64 bands per level and
+ * their round-to-nearest FP32 copies, and the work vectors of both solvers.
+ * Geometry: host_xy (nullable, 2n doubles interleaved x,y for the finest
+ * level, copied) or, when NULL, the uniform grid moved at interior nodes by
+ * dx = (2u-1)*jitter*h, dy = (2u'-1)*jitter*h with u, u' the SplitMix64
+ * draws 2p and 2p+1 of geom_seed, generated on the device.  Coarse levels
+ * use the finest coordinates sampled every 2^(L-l) nodes.
+ * 1 <= coarse_level <= min(L, 3); L <= 14.  Returns MG_ERR_NOMEM without
+ * allocating anything when the hierarchy does not fit the budget. */
+mg_status mg_hierarchy_create(mg_context* ctx, int L, int coarse_level, double jitter,
+                              uint64_t geom_seed, const double* host_xy, mg_hierarchy** out);
+/* Device bytes mg_hierarchy_create would charge for (L, coarse_level). */
+size_t mg_hierarchy_bytes(int L, int coarse_level);
+/* Assemble all levels (Sec. 2.1: the matrix is assembled fully): 2x2 Gauss
+ * element matrices on the isoparametric bilinear map, Dirichlet treatment,
+ * FP32 copy, and the Cholesky factor of the coarsest interior block.
+ * Synchronous.  MG_ERR_NUMERIC if the coarse block is not positive definite
+ * (a tangled grid). */
+mg_status mg_hierarchy_assemble(mg_hierarchy* h, void* stream);
+mg_status mg_hierarchy_destroy(mg_hierarchy* h);
+mg_status mg_hierarchy_info(const mg_hierarchy* h, int* L, int* coarse_level, int64_t* n_finest);
+/* Copy the 9*n band values of one level to host memory, band-major
+ * (host_out[k*n + p]); dtype selects the FP64 or FP32 copy.  Synchronous. */
+mg_status mg_get_bands(const mg_hierarchy* h, int level, mg_dtype dtype, void* host_out);
+/* Copy the 2n coordinates (x,y interleaved) of one level to host memory. */
+mg_status mg_get_coords(const mg_hierarchy* h, int level, double* host_out);
+
+/* Right-hand sides on the finest level (asynchronous on stream):
+ * mg_rhs_sinsin: load vector of f = 2 pi^2 sin(pi x) sin(pi y) (3x3 Gauss),
+ * whose exact solution is u = sin(pi x) sin(pi y) (Sec. 6.2.1 accuracy test
+ * with an analytically known solution); mg_rhs_uniform: b_p = 2u - 1 with u
+ * the SplitMix64 draw p of seed, at interior nodes.  Boundary entries 0. */
+mg_status mg_rhs_sinsin(const mg_hierarchy* h, double* dev_b, void* stream);
+mg_status mg_rhs_uniform(const mg_hierarchy* h, uint64_t seed, double* dev_b, void* stream);
+
+/* ---- solve (Sec. 6.2) -------------------------------------------------------
+ * Solve A x = b on the finest level.  dev_x is in/out (initial guess, then
+ * the solution).  FP64: V-cycles until ||b - A x|| <= rel_tol ||b||.  Mixed:
+ * FP64 defect d = b - A x and norm s, d32 = float(d / s), FP32 V-cycles on
+ * A32 c = d32 from c = 0 until the FP32 residual drops by inner_reduction
+ * (at most inner_max_cycles), x += s * double(c); the coarsest solve is
+ * always FP64.  Returns after the result is in dev_x (synchronises stream).
+ * Not thread safe per hierarchy.  stats may be NULL. */
+mg_status mg_solve(mg_hierarchy* h, const double* dev_b, double* dev_x,
+                   const mg_solve_opts* opts, void* stream, mg_stats* stats);
+
+/* ---- single operators (asynchronous; for parity tests and benchmarks) -----
+ * x, y, b, d: device vectors of the level's n elements in dtype. */
+/* y = A x (Sec. 4.1/4.2 banded matrix-vector product). */
+mg_status mg_spmv(const mg_hierarchy* h, int level, mg_dtype dtype, const void* x, void* y,
+                  void* stream);
+/* d = b - A x; if host_norm is non-NULL also ||d||_2 (accumulated in FP64,
+ * deterministic order), which makes the call synchronous.  d may be NULL
+ * when only the norm is wanted (Sec. 6.3.1: a norm of a residual built
+ * from one banded product). */
+mg_status mg_defect(const mg_hierarchy* h, int level, mg_dtype dtype, const void* b,
+                    const void* x, void* d, double* host_norm, void* stream);
+/* sweeps damped Jacobi steps x <- x + omega (b - A x) / diag(A) (Sec. 6.2),
+ * out of place internally, result in x. */
+mg_status mg_smooth(const mg_hierarchy* h, int level, mg_dtype dtype, const void* b, void* x,
+                    int sweeps, double omega, void* stream);
+/* One damped Jacobi sweep out of place, a single kernel launch:
+ * x_out = x + omega (b - A x) / diag(A) (Sec. 6.2).  x_out must not alias x
+ * or b. */
+mg_status mg_jacobi(const mg_hierarchy* h, int level, mg_dtype dtype, const void* b,
+                    const void* x, void* x_out, double omega, void* stream);
+/* b_c = P^T d_f with the coarse boundary set to 0; P is bilinear
+ * interpolation in index space (weights 1, 1/2, 1/4). */
+mg_status mg_restrict(const mg_hierarchy* h, int fine_level, mg_dtype dtype, const void* d_f,
+                      void* b_c, void* stream);
+/* x_f += P x_c. */
+mg_status mg_prolong(const mg_hierarchy* h, int fine_level, mg_dtype dtype, const void* x_c,
+                     void* x_f, void* stream);
+/* Direct solve on the coarsest level (FP64 Cholesky, cast in/out for F32):
+ * interior unknowns from the factor, boundary x = b. */
+mg_status mg_coarse_solve(const mg_hierarchy* h, mg_dtype dtype, const void* b, void* x,
+                          void* stream);
+/* One V(nu_pre, nu_post) cycle at `level` in place on x (levels below use the
+ * hierarchy's own work vectors). */
+mg_status mg_vcycle(mg_hierarchy* h, int level, mg_dtype dtype, const void* b, void* x,
+                    int nu_pre, int nu_post, double omega, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -33,7 +33,10 @@ static double dphi_dxi(int a, double eta) { return 0.25 * XI_A[a] * (1.0 + ETA_A
 static double dphi_deta(int a, double xi) { return 0.25 * ETA_A[a] * (1.0 + XI_A[a] * xi); }
 
 /* Isoparametric bilinear map at (xi, eta): physical point, Jacobian
- * determinant and physical gradients of the four shape functions. */
+ * determinant and physical gradients of the four shape functions.  The
+ * derivatives of the map are summed over corner coordinates taken relative
+ * to the first corner (the shape-function derivatives sum to zero, so this
+ * is the same map); it avoids cancelling O(1) coordinates to O(h) results. */
 static void map_point(const double* xq, const double* yq, double xi, double eta,
                       double* px, double* py, double* detJ, double* gx, double* gy) {
     double x_xi = 0, x_eta = 0, y_xi = 0, y_eta = 0, x = 0, y = 0;
@@ -42,10 +45,10 @@ static void map_point(const double* xq, const double* yq, double xi, double eta,
         double dxi = dphi_dxi(a, eta), deta = dphi_deta(a, xi);
         x += p * xq[a];
         y += p * yq[a];
-        x_xi += dxi * xq[a];
-        x_eta += deta * xq[a];
-        y_xi += dxi * yq[a];
-        y_eta += deta * yq[a];
+        x_xi += dxi * (xq[a] - xq[0]);
+        x_eta += deta * (xq[a] - xq[0]);
+        y_xi += dxi * (yq[a] - yq[0]);
+        y_eta += deta * (yq[a] - yq[0]);
     }
     double det = x_xi * y_eta - x_eta * y_xi;
     if (px) *px = x;

@@ -1,0 +1,15 @@
+"""MI355X multigrid Poisson solver (Q1 finite elements, HONEI arXiv 0904.4152).
+
+Thin ctypes binding of ``libmgfem.so`` (C ABI in ``include/mgfem.h``): every
+function has the C name and only marshals arguments; all computation runs in
+the library's HIP kernels.  Torch supplies device memory and streams.  The
+module refuses to load when the built library is missing -- there is no
+fallback path.
+"""
+from __future__ import annotations
+
+from ._binding import (  # noqa: F401
+    MG_OK, MG_ERR_INVALID, MG_ERR_NOMEM, MG_ERR_NOCONV, MG_ERR_NUMERIC, MG_ERR_DEVICE,
+    MG_ERR_BUSY, MG_PREC_FP64, MG_PREC_MIXED, MG_F64, MG_F32, MgError, SolveOpts, Stats,
+    lib, library_path, default_opts, Context, Hierarchy, check,
+)

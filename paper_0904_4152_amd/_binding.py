@@ -1,0 +1,276 @@
+"""ctypes marshalling for libmgfem.so (see include/mgfem.h for semantics)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # loads the HIP runtime the library links against (one runtime per process)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libmgfem.so")
+
+MG_OK, MG_ERR_INVALID, MG_ERR_NOMEM, MG_ERR_NOCONV, MG_ERR_NUMERIC, MG_ERR_DEVICE, MG_ERR_BUSY = \
+    range(7)
+MG_PREC_FP64, MG_PREC_MIXED = 0, 1
+MG_F64, MG_F32 = 0, 1
+MG_HIST = 128
+
+_vp = ctypes.c_void_p
+_i = ctypes.c_int
+_d = ctypes.c_double
+_sz = ctypes.c_size_t
+_u64 = ctypes.c_uint64
+_i64 = ctypes.c_int64
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("nu_pre", _i), ("nu_post", _i), ("omega", _d), ("rel_tol", _d),
+                ("max_cycles", _i), ("precision", _i), ("inner_reduction", _d),
+                ("inner_max_cycles", _i), ("fixed_cycles", _i), ("use_graph", _i)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("status", _i), ("cycles", _i), ("outer_steps", _i), ("bnorm", _d),
+                ("rel_res", _d), ("seconds", _d), ("alg_bytes", _d), ("n_hist", _i),
+                ("res_hist", _d * MG_HIST)]
+
+    def hist(self):
+        return [self.res_hist[k] for k in range(self.n_hist)]
+
+
+class MgError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s: %s" % (_status_name(status), msg))
+        self.status = status
+
+
+_SIGS = {
+    "mg_default_opts": (None, [ctypes.POINTER(SolveOpts)]),
+    "mg_last_error": (ctypes.c_char_p, []),
+    "mg_status_string": (ctypes.c_char_p, [_i]),
+    "mg_context_create": (_i, [_i, _sz, ctypes.POINTER(_vp)]),
+    "mg_context_destroy": (_i, [_vp]),
+    "mg_context_memory": (_i, [_vp, ctypes.POINTER(_sz), ctypes.POINTER(_sz)]),
+    "mg_hierarchy_create": (_i, [_vp, _i, _i, _d, _u64, _vp, ctypes.POINTER(_vp)]),
+    "mg_hierarchy_bytes": (_sz, [_i, _i]),
+    "mg_hierarchy_assemble": (_i, [_vp, _vp]),
+    "mg_hierarchy_destroy": (_i, [_vp]),
+    "mg_hierarchy_info": (_i, [_vp, ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i64)]),
+    "mg_get_bands": (_i, [_vp, _i, _i, _vp]),
+    "mg_get_coords": (_i, [_vp, _i, _vp]),
+    "mg_rhs_sinsin": (_i, [_vp, _vp, _vp]),
+    "mg_rhs_uniform": (_i, [_vp, _u64, _vp, _vp]),
+    "mg_solve": (_i, [_vp, _vp, _vp, ctypes.POINTER(SolveOpts), _vp, ctypes.POINTER(Stats)]),
+    "mg_spmv": (_i, [_vp, _i, _i, _vp, _vp, _vp]),
+    "mg_defect": (_i, [_vp, _i, _i, _vp, _vp, _vp, ctypes.POINTER(_d), _vp]),
+    "mg_smooth": (_i, [_vp, _i, _i, _vp, _vp, _i, _d, _vp]),
+    "mg_jacobi": (_i, [_vp, _i, _i, _vp, _vp, _vp, _d, _vp]),
+    "mg_restrict": (_i, [_vp, _i, _i, _vp, _vp, _vp]),
+    "mg_prolong": (_i, [_vp, _i, _i, _vp, _vp, _vp]),
+    "mg_coarse_solve": (_i, [_vp, _i, _vp, _vp, _vp]),
+    "mg_vcycle": (_i, [_vp, _i, _i, _vp, _vp, _i, _i, _d, _vp]),
+}
+
+_lib = None
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise ImportError("libmgfem.so is not built (run __graft_entry__.build() or "
+                              "python paper_0904_4152_amd/build.py)")
+        L = ctypes.CDLL(_LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _status_name(s: int) -> str:
+    try:
+        return lib().mg_status_string(s).decode()
+    except Exception:  # library not loadable
+        return "status %d" % s
+
+
+def check(status: int) -> int:
+    if status != MG_OK:
+        raise MgError(status, lib().mg_last_error().decode())
+    return status
+
+
+def default_opts(**kw) -> SolveOpts:
+    o = SolveOpts()
+    lib().mg_default_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise AttributeError(k)
+        setattr(o, k, v)
+    return o
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous device tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _dt(t) -> int:
+    if t.dtype == torch.float64:
+        return MG_F64
+    if t.dtype == torch.float32:
+        return MG_F32
+    raise TypeError("tensors must be float64 or float32")
+
+
+class Context:
+    def __init__(self, device: int = 0, budget_bytes: int = 0):
+        h = _vp()
+        check(lib().mg_context_create(device, budget_bytes, ctypes.byref(h)))
+        self._h = h
+        self.device = device
+
+    @property
+    def handle(self):
+        return self._h
+
+    def memory(self):
+        a, b = _sz(), _sz()
+        check(lib().mg_context_memory(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def close(self):
+        if self._h:
+            lib().mg_context_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Hierarchy:
+    """Device hierarchy; methods call the C ABI with tensor pointers."""
+
+    def __init__(self, ctx: Context, L: int, coarse_level: int = 1, jitter: float = 0.0,
+                 seed: int = 0, xy=None, assemble: bool = True):
+        h = _vp()
+        xy_ptr = None
+        if xy is not None:
+            import numpy as np
+            self._xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1)
+            xy_ptr = self._xy.ctypes.data_as(_vp)
+        check(lib().mg_hierarchy_create(ctx.handle, L, coarse_level, jitter, seed, xy_ptr,
+                                        ctypes.byref(h)))
+        self._h = h
+        self.ctx = ctx
+        self.L = L
+        self.Lc = coarse_level
+        self.N = (1 << L) + 1
+        self.n = self.N * self.N
+        if assemble:
+            self.assemble()
+
+    @staticmethod
+    def bytes_needed(L: int, coarse_level: int = 1) -> int:
+        return lib().mg_hierarchy_bytes(L, coarse_level)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def assemble(self, stream=None):
+        check(lib().mg_hierarchy_assemble(self._h, _stream(stream)))
+
+    def close(self):
+        if self._h:
+            lib().mg_hierarchy_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def level_size(self, l: int) -> int:
+        return ((1 << l) + 1) ** 2
+
+    def bands(self, level: int, dtype=torch.float64):
+        import numpy as np
+        n = self.level_size(level)
+        out = np.zeros(9 * n, dtype=np.float64 if dtype == torch.float64 else np.float32)
+        check(lib().mg_get_bands(self._h, level, MG_F64 if dtype == torch.float64 else MG_F32,
+                                 out.ctypes.data_as(_vp)))
+        return out.reshape(9, n)
+
+    def coords(self, level: int):
+        import numpy as np
+        out = np.zeros(2 * self.level_size(level))
+        check(lib().mg_get_coords(self._h, level, out.ctypes.data_as(_vp)))
+        return out
+
+    def rhs_sinsin(self, b, stream=None):
+        check(lib().mg_rhs_sinsin(self._h, _ptr(b), _stream(stream)))
+
+    def rhs_uniform(self, seed: int, b, stream=None):
+        check(lib().mg_rhs_uniform(self._h, seed, _ptr(b), _stream(stream)))
+
+    def solve(self, b, x, opts: SolveOpts | None = None, stream=None, raise_on_error=True):
+        st = Stats()
+        rc = lib().mg_solve(self._h, _ptr(b), _ptr(x),
+                            ctypes.byref(opts) if opts is not None else None, _stream(stream),
+                            ctypes.byref(st))
+        if raise_on_error:
+            check(rc)
+        return st
+
+    def spmv(self, level, x, y, stream=None):
+        check(lib().mg_spmv(self._h, level, _dt(x), _ptr(x), _ptr(y), _stream(stream)))
+
+    def defect(self, level, b, x, d=None, norm=False, stream=None):
+        nv = _d()
+        check(lib().mg_defect(self._h, level, _dt(x), _ptr(b), _ptr(x), _ptr(d),
+                              ctypes.byref(nv) if norm else None, _stream(stream)))
+        return nv.value if norm else None
+
+    def smooth(self, level, b, x, sweeps=1, omega=0.7, stream=None):
+        check(lib().mg_smooth(self._h, level, _dt(x), _ptr(b), _ptr(x), sweeps, omega,
+                              _stream(stream)))
+
+    def jacobi(self, level, b, x, x_out, omega=0.7, stream=None):
+        check(lib().mg_jacobi(self._h, level, _dt(x), _ptr(b), _ptr(x), _ptr(x_out), omega,
+                              _stream(stream)))
+
+    def restrict(self, fine_level, d_f, b_c, stream=None):
+        check(lib().mg_restrict(self._h, fine_level, _dt(d_f), _ptr(d_f), _ptr(b_c),
+                                _stream(stream)))
+
+    def prolong(self, fine_level, x_c, x_f, stream=None):
+        check(lib().mg_prolong(self._h, fine_level, _dt(x_f), _ptr(x_c), _ptr(x_f),
+                               _stream(stream)))
+
+    def coarse_solve(self, b, x, stream=None):
+        check(lib().mg_coarse_solve(self._h, _dt(x), _ptr(b), _ptr(x), _stream(stream)))
+
+    def vcycle(self, level, b, x, nu_pre=2, nu_post=2, omega=0.7, stream=None):
+        check(lib().mg_vcycle(self._h, level, _dt(x), _ptr(b), _ptr(x), nu_pre, nu_post, omega,
+                              _stream(stream)))

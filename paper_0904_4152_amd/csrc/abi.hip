@@ -1,0 +1,467 @@
+// C ABI: error reporting, contexts with a device-memory budget, device
+// hierarchies (geometry, assembly) and the single-operator entry points.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "mg_internal.h"
+#include "solve.h"
+
+namespace mg {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+mg_status fail(mg_status s, const std::string& msg) {
+    g_last_error = msg;
+    return s;
+}
+
+int64_t vec_len(int64_t n) { return (n + 63) / 64 * 64; }
+
+int64_t band_stride(int64_t n) { return (n + 1023) / 1024 * 1024 + 64; }
+
+// Bytes of every device array of a hierarchy, in allocation order.
+static void hierarchy_arrays(int L, int Lc, std::vector<size_t>& sizes) {
+    const int64_t nL = ((int64_t(1) << L) + 1) * ((int64_t(1) << L) + 1);
+    sizes.push_back(2 * nL * sizeof(double));  // coords
+    for (int l = Lc; l <= L; ++l) {
+        const int64_t n = ((int64_t(1) << l) + 1) * ((int64_t(1) << l) + 1);
+        const int64_t bs = band_stride(n), vl = vec_len(n);
+        sizes.push_back(9 * bs * sizeof(double));
+        sizes.push_back(9 * bs * sizeof(float));
+        for (int v = 0; v < 3; ++v) sizes.push_back(vl * sizeof(double));
+        for (int v = 0; v < 3; ++v) sizes.push_back(vl * sizeof(float));
+    }
+    sizes.push_back(vec_len(nL) * sizeof(double));                    // d64
+    sizes.push_back((stencil_blocks(nL, 8) + 64) * sizeof(double));   // partials
+    sizes.push_back(64 * sizeof(double));                             // scal
+    const int mi = (1 << Lc) - 1;
+    sizes.push_back(std::max<size_t>(1, (size_t)mi * mi * mi * mi) * sizeof(double));  // chol
+    sizes.push_back(64);                                              // flag
+}
+
+static size_t round_alloc(size_t b) { return (b + 4095) / 4096 * 4096; }
+
+static bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+static mg_status check_level(const mg_hierarchy* h, int level) {
+    if (!h) return fail(MG_ERR_INVALID, "null hierarchy");
+    if (level < h->Lc || level > h->L)
+        return fail(MG_ERR_INVALID, "level " + std::to_string(level) + " outside [" +
+                                        std::to_string(h->Lc) + ", " + std::to_string(h->L) + "]");
+    if (!h->assembled) return fail(MG_ERR_INVALID, "hierarchy not assembled");
+    return MG_OK;
+}
+
+static mg_status set_device(const mg_hierarchy* h) {
+    MG_HIP(hipSetDevice(h->ctx->device));
+    return MG_OK;
+}
+
+}  // namespace mg
+
+using namespace mg;
+
+bool mg_context::reserve(size_t bytes) {
+    std::lock_guard<std::mutex> g(mu);
+    if (budget != 0 && in_use + bytes > budget) return false;
+    in_use += bytes;
+    high_water = std::max(high_water, in_use);
+    return true;
+}
+
+void mg_context::release(size_t bytes) {
+    std::lock_guard<std::mutex> g(mu);
+    in_use -= std::min(in_use, bytes);
+}
+
+extern "C" {
+
+void mg_default_opts(mg_solve_opts* o) {
+    if (!o) return;
+    o->nu_pre = 2;
+    o->nu_post = 2;
+    o->omega = 0.7;
+    o->rel_tol = 1e-8;
+    o->max_cycles = 100;
+    o->precision = MG_PREC_FP64;
+    o->inner_reduction = 1e-2;
+    o->inner_max_cycles = 8;
+    o->fixed_cycles = 0;
+    o->use_graph = 1;
+}
+
+const char* mg_last_error(void) { return g_last_error.c_str(); }
+
+const char* mg_status_string(mg_status s) {
+    switch (s) {
+        case MG_OK: return "MG_OK";
+        case MG_ERR_INVALID: return "MG_ERR_INVALID";
+        case MG_ERR_NOMEM: return "MG_ERR_NOMEM";
+        case MG_ERR_NOCONV: return "MG_ERR_NOCONV";
+        case MG_ERR_NUMERIC: return "MG_ERR_NUMERIC";
+        case MG_ERR_DEVICE: return "MG_ERR_DEVICE";
+        case MG_ERR_BUSY: return "MG_ERR_BUSY";
+    }
+    return "MG_ERR_UNKNOWN";
+}
+
+mg_status mg_context_create(int device, size_t budget, mg_context** out) {
+    if (!out) return fail(MG_ERR_INVALID, "null output pointer");
+    *out = nullptr;
+    int count = 0;
+    MG_HIP(hipGetDeviceCount(&count));
+    if (device < 0 || device >= count)
+        return fail(MG_ERR_INVALID, "device " + std::to_string(device) + " not present");
+    MG_HIP(hipSetDevice(device));
+    mg_context* c = new (std::nothrow) mg_context();
+    if (!c) return fail(MG_ERR_NOMEM, "host allocation failed");
+    c->device = device;
+    c->budget = budget;
+    *out = c;
+    return MG_OK;
+}
+
+mg_status mg_context_destroy(mg_context* ctx) {
+    if (!ctx) return fail(MG_ERR_INVALID, "null context");
+    delete ctx;
+    return MG_OK;
+}
+
+mg_status mg_context_memory(const mg_context* ctx, size_t* in_use, size_t* high_water) {
+    if (!ctx) return fail(MG_ERR_INVALID, "null context");
+    mg_context* c = const_cast<mg_context*>(ctx);
+    std::lock_guard<std::mutex> g(c->mu);
+    if (in_use) *in_use = c->in_use;
+    if (high_water) *high_water = c->high_water;
+    return MG_OK;
+}
+
+size_t mg_hierarchy_bytes(int L, int Lc) {
+    if (L < 1 || L > MG_MAX_LEVEL || Lc < 1 || Lc > std::min(L, MG_MAX_COARSE_LEVEL)) return 0;
+    std::vector<size_t> sizes;
+    hierarchy_arrays(L, Lc, sizes);
+    size_t total = 0;
+    for (size_t s : sizes) total += round_alloc(s);
+    return total;
+}
+
+static void free_arrays(mg_hierarchy* h) {
+    for (void* p : h->allocs) (void)hipFree(p);
+    h->allocs.clear();
+    if (h->host_scal) (void)hipHostFree(h->host_scal);
+    h->host_scal = nullptr;
+}
+
+mg_status mg_hierarchy_create(mg_context* ctx, int L, int Lc, double jitter, uint64_t seed,
+                              const double* host_xy, mg_hierarchy** out) {
+    if (!out) return fail(MG_ERR_INVALID, "null output pointer");
+    *out = nullptr;
+    if (!ctx) return fail(MG_ERR_INVALID, "null context");
+    if (L < 1 || L > MG_MAX_LEVEL)
+        return fail(MG_ERR_INVALID, "level L=" + std::to_string(L) + " outside [1, 14]");
+    if (Lc < 1 || Lc > std::min(L, MG_MAX_COARSE_LEVEL))
+        return fail(MG_ERR_INVALID, "coarse level " + std::to_string(Lc) + " outside [1, min(L, 3)]");
+    if (!(jitter >= 0.0 && jitter < 0.5))
+        return fail(MG_ERR_INVALID, "jitter must lie in [0, 0.5)");
+    MG_HIP(hipSetDevice(ctx->device));
+    std::vector<size_t> sizes;
+    hierarchy_arrays(L, Lc, sizes);
+    size_t total = 0;
+    for (size_t s : sizes) total += round_alloc(s);
+    if (!ctx->reserve(total))
+        return fail(MG_ERR_NOMEM, "hierarchy L=" + std::to_string(L) + " needs " +
+                                      std::to_string(total) + " bytes, over the context budget");
+    mg_hierarchy* h = new (std::nothrow) mg_hierarchy();
+    if (!h) {
+        ctx->release(total);
+        return fail(MG_ERR_NOMEM, "host allocation failed");
+    }
+    h->ctx = ctx;
+    h->L = L;
+    h->Lc = Lc;
+    h->charged = total;
+    std::vector<void*> ptrs;
+    for (size_t s : sizes) {
+        void* p = nullptr;
+        if (hipMalloc(&p, round_alloc(s)) != hipSuccess) {
+            (void)hipGetLastError();
+            for (void* q : ptrs) (void)hipFree(q);
+            ctx->release(total);
+            delete h;
+            return fail(MG_ERR_NOMEM, "hipMalloc failed for hierarchy L=" + std::to_string(L));
+        }
+        ptrs.push_back(p);
+    }
+    h->allocs = ptrs;
+    for (size_t a = 0; a < ptrs.size(); ++a) {
+        if (hipMemset(ptrs[a], 0, round_alloc(sizes[a])) != hipSuccess) {
+            free_arrays(h);
+            ctx->release(total);
+            delete h;
+            return fail(MG_ERR_DEVICE, "hipMemset failed");
+        }
+    }
+    size_t a = 0;
+    h->coords = (double*)ptrs[a++];
+    for (int l = Lc; l <= L; ++l) {
+        Level& lv = h->lv[l];
+        lv.l = l;
+        lv.N = (1 << l) + 1;
+        lv.n = (int64_t)lv.N * lv.N;
+        lv.bs = band_stride(lv.n);
+        lv.bands64 = (double*)ptrs[a++];
+        lv.bands32 = (float*)ptrs[a++];
+        lv.x64 = (double*)ptrs[a++];
+        lv.b64 = (double*)ptrs[a++];
+        lv.t64 = (double*)ptrs[a++];
+        lv.x32 = (float*)ptrs[a++];
+        lv.b32 = (float*)ptrs[a++];
+        lv.t32 = (float*)ptrs[a++];
+    }
+    h->d64 = (double*)ptrs[a++];
+    h->partials = (double*)ptrs[a++];
+    h->n_partials = stencil_blocks(h->lv[L].n, 8) + 64;
+    h->scal = (double*)ptrs[a++];
+    h->chol = (double*)ptrs[a++];
+    h->flag = (int*)ptrs[a++];
+    const int mi = (1 << Lc) - 1;
+    h->m = mi * mi;
+    if (hipHostMalloc((void**)&h->host_scal, 64 * sizeof(double), hipHostMallocDefault) !=
+        hipSuccess) {
+        h->host_scal = nullptr;
+        free_arrays(h);
+        ctx->release(total);
+        delete h;
+        return fail(MG_ERR_NOMEM, "pinned host allocation failed");
+    }
+    const int64_t nL = h->lv[L].n;
+    hipError_t e;
+    if (host_xy)
+        e = hipMemcpy(h->coords, host_xy, 2 * nL * sizeof(double), hipMemcpyHostToDevice);
+    else
+        e = launch_coords(h->coords, L, jitter, seed, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        free_arrays(h);
+        ctx->release(total);
+        delete h;
+        return fail(MG_ERR_DEVICE, std::string("geometry: ") + hipGetErrorString(e));
+    }
+    *out = h;
+    return MG_OK;
+}
+
+mg_status mg_hierarchy_assemble(mg_hierarchy* h, void* stream) {
+    if (!h) return fail(MG_ERR_INVALID, "null hierarchy");
+    if (mg_status s = set_device(h)) return s;
+    hipStream_t st = (hipStream_t)stream;
+    for (int l = h->Lc; l <= h->L; ++l) MG_HIP(launch_assemble(h->coords, h->L, h->lv[l], st));
+    MG_HIP(launch_chol_factor(h->lv[h->Lc], h->chol, h->flag, st));
+    int flag = 0;
+    MG_HIP(hipMemcpyAsync(&flag, h->flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    MG_HIP(hipStreamSynchronize(st));
+    if (flag) return fail(MG_ERR_NUMERIC, "coarse-grid block is not positive definite");
+    h->assembled = true;
+    return MG_OK;
+}
+
+mg_status mg_hierarchy_destroy(mg_hierarchy* h) {
+    if (!h) return fail(MG_ERR_INVALID, "null hierarchy");
+    (void)hipSetDevice(h->ctx->device);
+    (void)hipDeviceSynchronize();
+    destroy_graphs(h);
+    free_arrays(h);
+    h->ctx->release(h->charged);
+    delete h;
+    return MG_OK;
+}
+
+mg_status mg_hierarchy_info(const mg_hierarchy* h, int* L, int* Lc, int64_t* n) {
+    if (!h) return fail(MG_ERR_INVALID, "null hierarchy");
+    if (L) *L = h->L;
+    if (Lc) *Lc = h->Lc;
+    if (n) *n = h->lv[h->L].n;
+    return MG_OK;
+}
+
+mg_status mg_get_bands(const mg_hierarchy* h, int level, mg_dtype dtype, void* host_out) {
+    if (mg_status s = check_level(h, level)) return s;
+    if (!host_out) return fail(MG_ERR_INVALID, "null output");
+    if (mg_status s = set_device(h)) return s;
+    const Level& lv = h->lv[level];
+    const size_t es = dtype == MG_F64 ? 8 : 4;
+    const char* base = dtype == MG_F64 ? (const char*)lv.bands64 : (const char*)lv.bands32;
+    for (int k = 0; k < 9; ++k)
+        MG_HIP(hipMemcpy((char*)host_out + k * lv.n * es, base + k * lv.bs * es, lv.n * es,
+                         hipMemcpyDeviceToHost));
+    return MG_OK;
+}
+
+mg_status mg_get_coords(const mg_hierarchy* h, int level, double* host_out) {
+    if (!h) return fail(MG_ERR_INVALID, "null hierarchy");
+    if (level < h->Lc || level > h->L) return fail(MG_ERR_INVALID, "level out of range");
+    if (!host_out) return fail(MG_ERR_INVALID, "null output");
+    if (mg_status s = set_device(h)) return s;
+    const int N = (1 << level) + 1, Nf = (1 << h->L) + 1, sd = 1 << (h->L - level);
+    std::vector<double> all((size_t)2 * Nf * Nf);
+    MG_HIP(hipMemcpy(all.data(), h->coords, all.size() * sizeof(double), hipMemcpyDeviceToHost));
+    for (int j = 0; j < N; ++j)
+        for (int i = 0; i < N; ++i) {
+            const size_t pf = (size_t)(j * sd) * Nf + (size_t)(i * sd);
+            host_out[2 * ((size_t)j * N + i)] = all[2 * pf];
+            host_out[2 * ((size_t)j * N + i) + 1] = all[2 * pf + 1];
+        }
+    return MG_OK;
+}
+
+mg_status mg_rhs_sinsin(const mg_hierarchy* h, double* dev_b, void* stream) {
+    if (!h) return fail(MG_ERR_INVALID, "null hierarchy");
+    if (!dev_b) return fail(MG_ERR_INVALID, "null b");
+    if (mg_status s = set_device(h)) return s;
+    MG_HIP(launch_rhs_sinsin(h->coords, h->lv[h->L].N, dev_b, (hipStream_t)stream));
+    return MG_OK;
+}
+
+mg_status mg_rhs_uniform(const mg_hierarchy* h, uint64_t seed, double* dev_b, void* stream) {
+    if (!h) return fail(MG_ERR_INVALID, "null hierarchy");
+    if (!dev_b) return fail(MG_ERR_INVALID, "null b");
+    if (mg_status s = set_device(h)) return s;
+    MG_HIP(launch_rhs_uniform(h->lv[h->L].N, seed, dev_b, (hipStream_t)stream));
+    return MG_OK;
+}
+
+mg_status mg_spmv(const mg_hierarchy* h, int level, mg_dtype dtype, const void* x, void* y,
+                  void* stream) {
+    if (mg_status s = check_level(h, level)) return s;
+    if (!x || !y || !aligned16(x) || !aligned16(y))
+        return fail(MG_ERR_INVALID, "x and y must be non-null and 16-byte aligned");
+    if (x == y) return fail(MG_ERR_INVALID, "x and y must not alias");
+    if (mg_status s = set_device(h)) return s;
+    const Level& lv = h->lv[level];
+    hipStream_t st = (hipStream_t)stream;
+    if (dtype == MG_F64)
+        MG_HIP(launch_spmv<double>(lv, lv.bands64, (const double*)x, (double*)y, st));
+    else
+        MG_HIP(launch_spmv<float>(lv, lv.bands32, (const float*)x, (float*)y, st));
+    return MG_OK;
+}
+
+mg_status mg_defect(const mg_hierarchy* h, int level, mg_dtype dtype, const void* b,
+                    const void* x, void* d, double* host_norm, void* stream) {
+    if (mg_status s = check_level(h, level)) return s;
+    if (!b || !x || !aligned16(b) || !aligned16(x) || (d && !aligned16(d)))
+        return fail(MG_ERR_INVALID, "b, x, d must be 16-byte aligned device pointers");
+    if (!d && !host_norm) return fail(MG_ERR_INVALID, "nothing to compute (d and norm null)");
+    if (d && (d == x || d == b)) return fail(MG_ERR_INVALID, "d must not alias b or x");
+    if (mg_status s = set_device(h)) return s;
+    const Level& lv = h->lv[level];
+    hipStream_t st = (hipStream_t)stream;
+    mg_hierarchy* hm = const_cast<mg_hierarchy*>(h);
+    double* part = host_norm ? hm->partials : nullptr;
+    if (dtype == MG_F64)
+        MG_HIP(launch_defect<double>(lv, lv.bands64, (const double*)b, (const double*)x,
+                                     (double*)d, part, hm->scal, SC_USER, st));
+    else
+        MG_HIP(launch_defect<float>(lv, lv.bands32, (const float*)b, (const float*)x, (float*)d,
+                                    part, hm->scal, SC_USER, st));
+    if (host_norm) {
+        MG_HIP(hipMemcpyAsync(hm->host_scal + SC_USER, hm->scal + SC_USER, 2 * sizeof(double),
+                              hipMemcpyDeviceToHost, st));
+        MG_HIP(hipStreamSynchronize(st));
+        *host_norm = hm->host_scal[SC_USER + 1];
+    }
+    return MG_OK;
+}
+
+mg_status mg_smooth(const mg_hierarchy* h, int level, mg_dtype dtype, const void* b, void* x,
+                    int sweeps, double omega, void* stream) {
+    if (mg_status s = check_level(h, level)) return s;
+    if (!b || !x || !aligned16(b) || !aligned16(x) || b == x)
+        return fail(MG_ERR_INVALID, "b, x must be distinct 16-byte aligned device pointers");
+    if (sweeps < 0) return fail(MG_ERR_INVALID, "negative sweep count");
+    if (mg_status s = set_device(h)) return s;
+    const Level& lv = h->lv[level];
+    hipStream_t st = (hipStream_t)stream;
+    for (int s = 0; s < sweeps; ++s) {
+        if (dtype == MG_F64) {
+            MG_HIP(launch_jacobi<double>(lv, lv.bands64, (const double*)b, (const double*)x,
+                                         lv.t64, omega, st));
+            MG_HIP(launch_copy<double>(lv.t64, (double*)x, lv.n, st));
+        } else {
+            MG_HIP(launch_jacobi<float>(lv, lv.bands32, (const float*)b, (const float*)x,
+                                        lv.t32, (float)omega, st));
+            MG_HIP(launch_copy<float>(lv.t32, (float*)x, lv.n, st));
+        }
+    }
+    return MG_OK;
+}
+
+mg_status mg_jacobi(const mg_hierarchy* h, int level, mg_dtype dtype, const void* b,
+                    const void* x, void* x_out, double omega, void* stream) {
+    if (mg_status s = check_level(h, level)) return s;
+    if (!b || !x || !x_out || !aligned16(b) || !aligned16(x) || !aligned16(x_out))
+        return fail(MG_ERR_INVALID, "b, x, x_out must be 16-byte aligned device pointers");
+    if (x_out == x || x_out == b) return fail(MG_ERR_INVALID, "x_out must not alias x or b");
+    if (mg_status s = set_device(h)) return s;
+    const Level& lv = h->lv[level];
+    hipStream_t st = (hipStream_t)stream;
+    if (dtype == MG_F64)
+        MG_HIP(launch_jacobi<double>(lv, lv.bands64, (const double*)b, (const double*)x,
+                                     (double*)x_out, omega, st));
+    else
+        MG_HIP(launch_jacobi<float>(lv, lv.bands32, (const float*)b, (const float*)x,
+                                    (float*)x_out, (float)omega, st));
+    return MG_OK;
+}
+
+mg_status mg_restrict(const mg_hierarchy* h, int fine_level, mg_dtype dtype, const void* d_f,
+                      void* b_c, void* stream) {
+    if (mg_status s = check_level(h, fine_level)) return s;
+    if (fine_level <= h->Lc) return fail(MG_ERR_INVALID, "no coarser level below fine_level");
+    if (!d_f || !b_c) return fail(MG_ERR_INVALID, "null vector");
+    if (mg_status s = set_device(h)) return s;
+    const int Nf = h->lv[fine_level].N;
+    hipStream_t st = (hipStream_t)stream;
+    if (dtype == MG_F64)
+        MG_HIP(launch_restrict<double>(Nf, (const double*)d_f, (double*)b_c, st));
+    else
+        MG_HIP(launch_restrict<float>(Nf, (const float*)d_f, (float*)b_c, st));
+    return MG_OK;
+}
+
+mg_status mg_prolong(const mg_hierarchy* h, int fine_level, mg_dtype dtype, const void* x_c,
+                     void* x_f, void* stream) {
+    if (mg_status s = check_level(h, fine_level)) return s;
+    if (fine_level <= h->Lc) return fail(MG_ERR_INVALID, "no coarser level below fine_level");
+    if (!x_c || !x_f) return fail(MG_ERR_INVALID, "null vector");
+    if (mg_status s = set_device(h)) return s;
+    const int Nf = h->lv[fine_level].N;
+    hipStream_t st = (hipStream_t)stream;
+    if (dtype == MG_F64)
+        MG_HIP(launch_prolong<double>(Nf, (const double*)x_c, (double*)x_f, st));
+    else
+        MG_HIP(launch_prolong<float>(Nf, (const float*)x_c, (float*)x_f, st));
+    return MG_OK;
+}
+
+mg_status mg_coarse_solve(const mg_hierarchy* h, mg_dtype dtype, const void* b, void* x,
+                          void* stream) {
+    if (mg_status s = check_level(h, h ? h->Lc : 1)) return s;
+    if (!b || !x) return fail(MG_ERR_INVALID, "null vector");
+    if (mg_status s = set_device(h)) return s;
+    hipStream_t st = (hipStream_t)stream;
+    const int Nc = h->lv[h->Lc].N;
+    if (dtype == MG_F64)
+        MG_HIP(launch_coarse<double>(h->chol, h->m, Nc, (const double*)b, (double*)x, st));
+    else
+        MG_HIP(launch_coarse<float>(h->chol, h->m, Nc, (const float*)b, (float*)x, st));
+    return MG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,700 @@
+// gfx950 kernels of the Q1 multigrid Poisson hot path: grid and band
+// assembly, the 9-band product family (SpMV, defect with norm, damped
+// Jacobi), grid transfers, coarse direct solve and the mixed-precision
+// cast / update steps.
+//
+// All band-streaming kernels are HBM-bandwidth bound (about 0.2-0.4 flop per
+// byte), so they use no matrix cores: each thread owns 16 contiguous bytes of
+// every band (4 floats or 2 doubles), bands are read with non-temporal loads
+// (single use), the x halo of the three grid rows comes through L1/L2, and
+// workgroups are renumbered so that each XCD walks a contiguous part of the
+// grid (its L2 then sees the row reuse of x).
+#include <cmath>
+
+#include "mg_internal.h"
+
+namespace mg {
+
+namespace {
+
+constexpr int BLOCK = 256;
+
+// Hardware dispatches consecutive workgroups round-robin over the 8 XCDs.
+// Renumber so that XCD k processes the k-th contiguous eighth of the grid;
+// the launch grid is a multiple of 8 and surplus groups return at once.
+__device__ __forceinline__ int64_t xcd_block(int64_t nblk) {
+    const int64_t per = gridDim.x >> 3;
+    const int64_t b = blockIdx.x;
+    const int64_t lb = (b & 7) * per + (b >> 3);
+    return lb < nblk ? lb : -1;
+}
+
+inline unsigned grid8(int64_t nblk) { return (unsigned)((nblk + 7) / 8 * 8); }
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
+template <typename T>
+struct V16;
+template <>
+struct V16<float> {
+    typedef f32x4 type;
+    static constexpr int W = 4;
+};
+template <>
+struct V16<double> {
+    typedef f64x2 type;
+    static constexpr int W = 2;
+};
+
+// Deterministic block sum (wave shuffles, then waves in order); valid in
+// thread 0.  Every thread of the block must call it.
+__device__ __forceinline__ double block_sum(double v) {
+    __shared__ double ws[BLOCK / 64];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int w = 0; w < BLOCK / 64; ++w) s += ws[w];
+    }
+    return s;
+}
+
+enum { OP_SPMV = 0, OP_DEFECT = 1, OP_JACOBI = 2 };
+
+// One thread: W consecutive rows p0..p0+W-1 of the band product.  `fast`
+// blocks lie at least N+1 rows away from both ends of the vector, so the x
+// halo needs no bounds checks there.
+template <typename T, int OP, bool NORM, bool STORE>
+__global__ __launch_bounds__(BLOCK) void k_stencil(const T* __restrict__ bands, int64_t bs,
+                                                   int N, int64_t n, const T* __restrict__ x,
+                                                   const T* __restrict__ b,
+                                                   T* __restrict__ out, T omega,
+                                                   double* __restrict__ partials, int64_t nblk) {
+    constexpr int W = V16<T>::W;
+    typedef typename V16<T>::type VT;
+    const int64_t lb = xcd_block(nblk);
+    if (lb < 0) return;
+    const int64_t blo = lb * (int64_t)(BLOCK * W);
+    const int64_t p0 = blo + (int64_t)threadIdx.x * W;
+    const bool fast = (blo - N - 1 >= 0) && (blo + BLOCK * W + N + 1 <= n);
+    double sq = 0.0;
+    if (p0 < n) {
+        T xv[3][W + 2];
+        if (fast) {
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                const T* xp = x + p0 + (int64_t)(r - 1) * N - 1;
+#pragma unroll
+                for (int e = 0; e < W + 2; ++e) xv[r][e] = xp[e];
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+#pragma unroll
+                for (int e = 0; e < W + 2; ++e) {
+                    const int64_t q = p0 + (int64_t)(r - 1) * N - 1 + e;
+                    xv[r][e] = (q >= 0 && q < n) ? x[q] : T(0);
+                }
+            }
+        }
+        T bk[9][W];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            // band arrays are padded beyond n, so the vector load is in bounds
+            VT v = __builtin_nontemporal_load(reinterpret_cast<const VT*>(bands + k * bs + p0));
+            __builtin_memcpy(bk[k], &v, sizeof(VT));
+        }
+        T res[W];
+#pragma unroll
+        for (int v = 0; v < W; ++v) {
+            T acc = T(0);
+#pragma unroll
+            for (int k = 0; k < 9; ++k) acc = fma(bk[k][v], xv[k / 3][v + k % 3], acc);
+            res[v] = acc;
+        }
+        if (OP != OP_SPMV) {
+            T bb[W];
+            if (fast) {
+                VT v = *reinterpret_cast<const VT*>(b + p0);
+                __builtin_memcpy(bb, &v, sizeof(VT));
+            } else {
+#pragma unroll
+                for (int v = 0; v < W; ++v) bb[v] = (p0 + v < n) ? b[p0 + v] : T(0);
+            }
+#pragma unroll
+            for (int v = 0; v < W; ++v) {
+                if (OP == OP_DEFECT) {
+                    res[v] = bb[v] - res[v];
+                } else {
+                    res[v] = xv[1][v + 1] + omega * (bb[v] - res[v]) / bk[4][v];
+                }
+            }
+        }
+        if (NORM) {
+#pragma unroll
+            for (int v = 0; v < W; ++v)
+                if (p0 + v < n) sq += (double)res[v] * (double)res[v];
+        }
+        if (STORE) {
+            if (fast) {
+                VT v;
+                __builtin_memcpy(&v, res, sizeof(VT));
+                *reinterpret_cast<VT*>(out + p0) = v;
+            } else {
+#pragma unroll
+                for (int v = 0; v < W; ++v)
+                    if (p0 + v < n) out[p0 + v] = res[v];
+            }
+        }
+    }
+    if (NORM) {
+        const double s = block_sum(sq);
+        if (threadIdx.x == 0) partials[lb] = s;
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_reduce_final(const double* __restrict__ partials,
+                                                        int64_t np, double* __restrict__ scal,
+                                                        int slot) {
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < np; i += BLOCK) s += partials[i];
+    s = block_sum(s);
+    if (threadIdx.x == 0) {
+        scal[slot] = s;
+        scal[slot + 1] = sqrt(s);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_jacobi_zero(const T* __restrict__ diag,
+                                                       const T* __restrict__ b,
+                                                       T* __restrict__ xo, int64_t n, T omega) {
+    const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (p < n) xo[p] = omega * b[p] / diag[p];
+}
+
+// b_c(I,J) = sum over the 3x3 fine neighbourhood of (2I,2J) with weights
+// 1 (centre), 1/2 (edge), 1/4 (corner): the transpose of bilinear
+// interpolation; zero on the coarse boundary.
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_restrict(int Nf, const T* __restrict__ d,
+                                                    T* __restrict__ bc) {
+    const int Nc = (Nf >> 1) + 1;
+    const int I = blockIdx.x * BLOCK + threadIdx.x;
+    const int J = blockIdx.y;
+    if (I >= Nc) return;
+    T s = T(0);
+    if (I > 0 && J > 0 && I < Nc - 1 && J < Nc - 1) {
+        const T* c = d + (int64_t)(2 * J) * Nf + 2 * I;
+        const T* u = c - Nf;
+        const T* o = c + Nf;
+        const T corner = (u[-1] + u[1]) + (o[-1] + o[1]);
+        const T edge = (u[0] + o[0]) + (c[-1] + c[1]);
+        s = c[0] + T(0.5) * edge + T(0.25) * corner;
+    }
+    bc[(int64_t)J * Nc + I] = s;
+}
+
+// x_f(i,j) += bilinear interpolation of x_c at fine node (i,j).
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_prolong(int Nf, const T* __restrict__ xc,
+                                                   T* __restrict__ xf) {
+    const int Nc = (Nf >> 1) + 1;
+    const int i = blockIdx.x * BLOCK + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= Nf) return;
+    const int I = i >> 1, J = j >> 1;
+    const T* c = xc + (int64_t)J * Nc + I;
+    T v;
+    if (!(i & 1) && !(j & 1)) {
+        v = c[0];
+    } else if (!(j & 1)) {
+        v = T(0.5) * (c[0] + c[1]);
+    } else if (!(i & 1)) {
+        v = T(0.5) * (c[0] + c[Nc]);
+    } else {
+        v = T(0.25) * ((c[0] + c[1]) + (c[Nc] + c[Nc + 1]));
+    }
+    xf[(int64_t)j * Nf + i] += v;
+}
+
+// Coarsest level: boundary rows are identity rows, the interior block is
+// solved with its Cholesky factor (FP64 whatever T is).
+template <typename T>
+__global__ void k_coarse(const double* __restrict__ chol, int m, int Nc,
+                         const T* __restrict__ b, T* __restrict__ x) {
+    __shared__ double z[64];
+    const int mi = Nc - 2;
+    for (int p = threadIdx.x; p < Nc * Nc; p += blockDim.x) {
+        const int i = p % Nc, j = p / Nc;
+        if (i == 0 || j == 0 || i == Nc - 1 || j == Nc - 1) x[p] = b[p];
+    }
+    if (threadIdx.x == 0) {
+        for (int r = 0; r < m; ++r) {
+            const int i = 1 + r % mi, j = 1 + r / mi;
+            double s = (double)b[j * Nc + i];
+            for (int k = 0; k < r; ++k) s -= chol[r * m + k] * z[k];
+            z[r] = s / chol[r * m + r];
+        }
+        for (int r = m - 1; r >= 0; --r) {
+            double s = z[r];
+            for (int k = r + 1; k < m; ++k) s -= chol[k * m + r] * z[k];
+            z[r] = s / chol[r * m + r];
+        }
+        for (int r = 0; r < m; ++r) {
+            const int i = 1 + r % mi, j = 1 + r / mi;
+            x[j * Nc + i] = (T)z[r];
+        }
+    }
+}
+
+// Dense interior block of the coarsest operator and its Cholesky factor
+// (one thread; at most 49 unknowns).  flag = 1 if a pivot is not positive.
+__global__ void k_chol_factor(const double* __restrict__ bands, int64_t bs, int Nc,
+                              double* __restrict__ A, int* __restrict__ flag) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int mi = Nc - 2, m = mi * mi;
+    for (int r = 0; r < m * m; ++r) A[r] = 0.0;
+    for (int r = 0; r < m; ++r) {
+        const int i = 1 + r % mi, j = 1 + r / mi;
+        for (int k = 0; k < 9; ++k) {
+            const int ii = i + k % 3 - 1, jj = j + k / 3 - 1;
+            if (ii < 1 || jj < 1 || ii > Nc - 2 || jj > Nc - 2) continue;
+            A[r * m + (jj - 1) * mi + (ii - 1)] = bands[k * bs + (int64_t)j * Nc + i];
+        }
+    }
+    int bad = 0;
+    for (int c = 0; c < m; ++c) {
+        double d = A[c * m + c];
+        for (int k = 0; k < c; ++k) d -= A[c * m + k] * A[c * m + k];
+        if (!(d > 0.0)) {
+            bad = 1;
+            break;
+        }
+        d = sqrt(d);
+        A[c * m + c] = d;
+        for (int r = c + 1; r < m; ++r) {
+            double t = A[r * m + c];
+            for (int k = 0; k < c; ++k) t -= A[r * m + k] * A[c * m + k];
+            A[r * m + c] = t / d;
+        }
+    }
+    *flag = bad;
+}
+
+// ---------------------------------------------------------------- geometry
+
+__device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t k) {
+    uint64_t z = seed + (k + 1ull) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ double uniform01(uint64_t seed, uint64_t k) {
+    return (double)(splitmix64(seed, k) >> 11) * 0x1.0p-53;
+}
+
+// Finest-level coordinates: uniform grid, interior nodes moved by
+// (2u-1)*jitter*h in each direction.  Explicitly rounded operations keep
+// the result identical to a host evaluation of the same formula.
+__global__ __launch_bounds__(BLOCK) void k_coords(double* __restrict__ xy, int N, double jitter,
+                                                  uint64_t seed) {
+    const int i = blockIdx.x * BLOCK + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= N) return;
+    const int64_t p = (int64_t)j * N + i;
+    const double h = 1.0 / (double)(N - 1);
+    double x = __dmul_rn((double)i, h), y = __dmul_rn((double)j, h);
+    if (jitter != 0.0 && i > 0 && j > 0 && i < N - 1 && j < N - 1) {
+        const double ux = uniform01(seed, 2ull * (uint64_t)p);
+        const double uy = uniform01(seed, 2ull * (uint64_t)p + 1ull);
+        const double dx = __dmul_rn(__dmul_rn(__dadd_rn(2.0 * ux, -1.0), jitter), h);
+        const double dy = __dmul_rn(__dmul_rn(__dadd_rn(2.0 * uy, -1.0), jitter), h);
+        x = __dadd_rn(x, dx);
+        y = __dadd_rn(y, dy);
+    }
+    xy[2 * p] = x;
+    xy[2 * p + 1] = y;
+}
+
+// Bilinear map of one quadrilateral written as
+//   x(xi,eta) = ax0 + ax1 xi + ax2 eta + ax3 xi eta   (same for y),
+// corners counter-clockwise (-1,-1), (1,-1), (1,1), (-1,1).
+struct Quad {
+    double ax[4], ay[4];
+    __device__ void set(const double* cx, const double* cy) {
+        ax[0] = 0.25 * ((cx[0] + cx[1]) + (cx[2] + cx[3]));
+        ax[1] = 0.25 * ((cx[1] - cx[0]) + (cx[2] - cx[3]));
+        ax[2] = 0.25 * ((cx[2] - cx[1]) + (cx[3] - cx[0]));
+        ax[3] = 0.25 * ((cx[0] - cx[1]) + (cx[2] - cx[3]));
+        ay[0] = 0.25 * ((cy[0] + cy[1]) + (cy[2] + cy[3]));
+        ay[1] = 0.25 * ((cy[1] - cy[0]) + (cy[2] - cy[3]));
+        ay[2] = 0.25 * ((cy[2] - cy[1]) + (cy[3] - cy[0]));
+        ay[3] = 0.25 * ((cy[0] - cy[1]) + (cy[2] - cy[3]));
+    }
+};
+
+__device__ __constant__ double kSX[4] = {-1.0, 1.0, 1.0, -1.0};
+__device__ __constant__ double kSY[4] = {-1.0, -1.0, 1.0, 1.0};
+
+// Row `a` of the element stiffness matrix (2x2 Gauss):
+//   K[a][b] = sum_q (G_a G_b + H_a H_b) / det J_q
+// with G = det J * d(phi)/dx and H = det J * d(phi)/dy expressed through
+// the cofactors of J.  G and H are computed for all four corners with the
+// same instructions in every thread, so K[a][b] and K[b][a] agree bitwise.
+__device__ void element_row(const Quad& q, int a, double* Krow) {
+    const double g = 0.57735026918962576451;  // 1/sqrt(3)
+    for (int b = 0; b < 4; ++b) Krow[b] = 0.0;
+#pragma unroll
+    for (int qp = 0; qp < 4; ++qp) {
+        const double xi = (qp & 1) ? g : -g;
+        const double eta = (qp & 2) ? g : -g;
+        const double xx = q.ax[1] + q.ax[3] * eta, xe = q.ax[2] + q.ax[3] * xi;
+        const double yx = q.ay[1] + q.ay[3] * eta, ye = q.ay[2] + q.ay[3] * xi;
+        const double det = xx * ye - xe * yx;
+        double G[4], H[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const double dxi = 0.25 * kSX[c] * (1.0 + kSY[c] * eta);
+            const double deta = 0.25 * kSY[c] * (1.0 + kSX[c] * xi);
+            G[c] = ye * dxi - yx * deta;
+            H[c] = xx * deta - xe * dxi;
+        }
+        double Ga = G[0], Ha = H[0];
+#pragma unroll
+        for (int c = 1; c < 4; ++c)
+            if (c == a) {
+                Ga = G[c];
+                Ha = H[c];
+            }
+#pragma unroll
+        for (int b = 0; b < 4; ++b) Krow[b] += (Ga * G[b] + Ha * H[b]) / det;
+    }
+}
+
+__device__ __forceinline__ void level_xy(const double* __restrict__ xyf, int Nf, int s, int i,
+                                         int j, double* x, double* y) {
+    const int64_t pf = (int64_t)(j * s) * Nf + (int64_t)(i * s);
+    *x = xyf[2 * pf];
+    *y = xyf[2 * pf + 1];
+}
+
+// Node-centric assembly of one level: thread (i,j) visits the four elements
+// around its node in lexicographic order and accumulates its nine band
+// entries, then applies the Dirichlet treatment.  Writes FP64 bands and
+// their round-to-nearest FP32 copies.
+__global__ __launch_bounds__(BLOCK) void k_assemble(const double* __restrict__ xyf, int L, int l,
+                                                    double* __restrict__ b64,
+                                                    float* __restrict__ b32, int64_t bs) {
+    const int N = (1 << l) + 1, Nf = (1 << L) + 1, s = 1 << (L - l);
+    const int i = blockIdx.x * BLOCK + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= N) return;
+    const int64_t p = (int64_t)j * N + i;
+    double band[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) band[k] = 0.0;
+    const bool bnd = (i == 0 || j == 0 || i == N - 1 || j == N - 1);
+    if (bnd) {
+        band[4] = 1.0;
+    } else {
+        // element (ei,ej) = (i-1+ex, j-1+ey); this node is its corner a.
+        const int corner_of[4] = {2, 3, 1, 0};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int ex = e & 1, ey = e >> 1;
+            const int ei = i - 1 + ex, ej = j - 1 + ey;
+            double cx[4], cy[4];
+            level_xy(xyf, Nf, s, ei, ej, &cx[0], &cy[0]);
+            level_xy(xyf, Nf, s, ei + 1, ej, &cx[1], &cy[1]);
+            level_xy(xyf, Nf, s, ei + 1, ej + 1, &cx[2], &cy[2]);
+            level_xy(xyf, Nf, s, ei, ej + 1, &cx[3], &cy[3]);
+            Quad q;
+            q.set(cx, cy);
+            const int a = corner_of[e];
+            double Krow[4];
+            element_row(q, a, Krow);
+            // corner c sits at (ei + ox[c], ej + oy[c]); this node at (i, j)
+            const int ox[4] = {0, 1, 1, 0}, oy[4] = {0, 0, 1, 1};
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int di = ei + ox[c] - i, dj = ej + oy[c] - j;
+                band[(dj + 1) * 3 + (di + 1)] += Krow[c];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            const int ii = i + k % 3 - 1, jj = j + k / 3 - 1;
+            if (k != 4 && (ii == 0 || jj == 0 || ii == N - 1 || jj == N - 1)) band[k] = 0.0;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        b64[k * bs + p] = band[k];
+        b32[k * bs + p] = (float)band[k];
+    }
+}
+
+// Load vector of f = 2 pi^2 sin(pi x) sin(pi y), 3x3 Gauss per element,
+// node-centric over the four elements around each interior node.
+__global__ __launch_bounds__(BLOCK) void k_rhs_sinsin(const double* __restrict__ xy, int N,
+                                                      double* __restrict__ bout) {
+    const int i = blockIdx.x * BLOCK + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= N) return;
+    const int64_t p = (int64_t)j * N + i;
+    if (i == 0 || j == 0 || i == N - 1 || j == N - 1) {
+        bout[p] = 0.0;
+        return;
+    }
+    const double pi = 3.14159265358979323846;
+    const double gp[3] = {-0.77459666924148337704, 0.0, 0.77459666924148337704};
+    const double gw[3] = {5.0 / 9.0, 8.0 / 9.0, 5.0 / 9.0};
+    const int corner_of[4] = {2, 3, 1, 0};
+    double sum = 0.0;
+    for (int e = 0; e < 4; ++e) {
+        const int ei = i - 1 + (e & 1), ej = j - 1 + (e >> 1);
+        double cx[4], cy[4];
+        level_xy(xy, N, 1, ei, ej, &cx[0], &cy[0]);
+        level_xy(xy, N, 1, ei + 1, ej, &cx[1], &cy[1]);
+        level_xy(xy, N, 1, ei + 1, ej + 1, &cx[2], &cy[2]);
+        level_xy(xy, N, 1, ei, ej + 1, &cx[3], &cy[3]);
+        Quad q;
+        q.set(cx, cy);
+        const int a = corner_of[e];
+        for (int qj = 0; qj < 3; ++qj) {
+            for (int qi = 0; qi < 3; ++qi) {
+                const double xi = gp[qi], eta = gp[qj];
+                const double px = q.ax[0] + q.ax[1] * xi + q.ax[2] * eta + q.ax[3] * xi * eta;
+                const double py = q.ay[0] + q.ay[1] * xi + q.ay[2] * eta + q.ay[3] * xi * eta;
+                const double xx = q.ax[1] + q.ax[3] * eta, xe = q.ax[2] + q.ax[3] * xi;
+                const double yx = q.ay[1] + q.ay[3] * eta, ye = q.ay[2] + q.ay[3] * xi;
+                const double det = xx * ye - xe * yx;
+                const double phi = 0.25 * (1.0 + kSX[a] * xi) * (1.0 + kSY[a] * eta);
+                const double f = 2.0 * pi * pi * sin(pi * px) * sin(pi * py);
+                sum += gw[qi] * gw[qj] * det * f * phi;
+            }
+        }
+    }
+    bout[p] = sum;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_rhs_uniform(int N, uint64_t seed,
+                                                       double* __restrict__ bout) {
+    const int i = blockIdx.x * BLOCK + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= N) return;
+    const int64_t p = (int64_t)j * N + i;
+    double v = 0.0;
+    if (i > 0 && j > 0 && i < N - 1 && j < N - 1) v = 2.0 * uniform01(seed, (uint64_t)p) - 1.0;
+    bout[p] = v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_copy(const T* __restrict__ s, T* __restrict__ d,
+                                                int64_t n) {
+    const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (p < n) d[p] = s[p];
+}
+
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_sumsq(const T* __restrict__ v, int64_t n,
+                                                 double* __restrict__ partials, int64_t nblk) {
+    const int64_t lb = xcd_block(nblk);
+    if (lb < 0) return;
+    double s = 0.0;
+    const int64_t base = lb * (int64_t)(BLOCK * 4);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int64_t p = base + (int64_t)e * BLOCK + threadIdx.x;
+        if (p < n) s += (double)v[p] * (double)v[p];
+    }
+    s = block_sum(s);
+    if (threadIdx.x == 0) partials[lb] = s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_fill(T* __restrict__ v, int64_t n, T value) {
+    const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (p < n) v[p] = value;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_cast_scaled(const double* __restrict__ d,
+                                                       float* __restrict__ d32, int64_t n,
+                                                       const double* __restrict__ scal, int slot) {
+    const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (p >= n) return;
+    const double s = scal[slot + 1];
+    d32[p] = s > 0.0 ? (float)(d[p] / s) : 0.0f;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_update(double* __restrict__ x,
+                                                  const float* __restrict__ c, int64_t n,
+                                                  const double* __restrict__ scal, int slot) {
+    const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (p >= n) return;
+    x[p] += scal[slot + 1] * (double)c[p];
+}
+
+inline unsigned blocks1d(int64_t n) { return (unsigned)((n + BLOCK - 1) / BLOCK); }
+
+}  // namespace
+
+int64_t stencil_blocks(int64_t n, int elem_bytes) {
+    const int64_t per = (int64_t)BLOCK * (16 / elem_bytes);
+    return (n + per - 1) / per;
+}
+
+hipError_t launch_coords(double* xy, int L, double jitter, uint64_t seed, hipStream_t st) {
+    const int N = (1 << L) + 1;
+    hipLaunchKernelGGL(k_coords, dim3(blocks1d(N), N), dim3(BLOCK), 0, st, xy, N, jitter, seed);
+    return hipGetLastError();
+}
+
+hipError_t launch_assemble(const double* xy_fine, int L, const Level& lv, hipStream_t st) {
+    hipLaunchKernelGGL(k_assemble, dim3(blocks1d(lv.N), lv.N), dim3(BLOCK), 0, st, xy_fine, L,
+                       lv.l, lv.bands64, lv.bands32, lv.bs);
+    return hipGetLastError();
+}
+
+hipError_t launch_chol_factor(const Level& lc, double* chol, int* flag, hipStream_t st) {
+    hipLaunchKernelGGL(k_chol_factor, dim3(1), dim3(64), 0, st, lc.bands64, lc.bs, lc.N, chol,
+                       flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_rhs_sinsin(const double* xy, int N, double* b, hipStream_t st) {
+    hipLaunchKernelGGL(k_rhs_sinsin, dim3(blocks1d(N), N), dim3(BLOCK), 0, st, xy, N, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_rhs_uniform(int N, uint64_t seed, double* b, hipStream_t st) {
+    hipLaunchKernelGGL(k_rhs_uniform, dim3(blocks1d(N), N), dim3(BLOCK), 0, st, N, seed, b);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_spmv(const Level& lv, const T* bands, const T* x, T* y, hipStream_t st) {
+    const int64_t nb = stencil_blocks(lv.n, sizeof(T));
+    hipLaunchKernelGGL((k_stencil<T, OP_SPMV, false, true>), dim3(grid8(nb)), dim3(BLOCK), 0, st,
+                       bands, lv.bs, lv.N, lv.n, x, (const T*)nullptr, y, T(0),
+                       (double*)nullptr, nb);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_defect(const Level& lv, const T* bands, const T* b, const T* x, T* d,
+                         double* partials, double* scal, int slot, hipStream_t st) {
+    const int64_t nb = stencil_blocks(lv.n, sizeof(T));
+    const dim3 g(grid8(nb)), blk(BLOCK);
+    if (partials && d)
+        hipLaunchKernelGGL((k_stencil<T, OP_DEFECT, true, true>), g, blk, 0, st, bands, lv.bs,
+                           lv.N, lv.n, x, b, d, T(0), partials, nb);
+    else if (partials)
+        hipLaunchKernelGGL((k_stencil<T, OP_DEFECT, true, false>), g, blk, 0, st, bands, lv.bs,
+                           lv.N, lv.n, x, b, (T*)nullptr, T(0), partials, nb);
+    else
+        hipLaunchKernelGGL((k_stencil<T, OP_DEFECT, false, true>), g, blk, 0, st, bands, lv.bs,
+                           lv.N, lv.n, x, b, d, T(0), (double*)nullptr, nb);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !partials) return e;
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(BLOCK), 0, st, partials, nb, scal, slot);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_jacobi(const Level& lv, const T* bands, const T* b, const T* x, T* xo,
+                         T omega, hipStream_t st) {
+    const int64_t nb = stencil_blocks(lv.n, sizeof(T));
+    hipLaunchKernelGGL((k_stencil<T, OP_JACOBI, false, true>), dim3(grid8(nb)), dim3(BLOCK), 0,
+                       st, bands, lv.bs, lv.N, lv.n, x, b, xo, omega, (double*)nullptr, nb);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_jacobi_zero(const Level& lv, const T* bands, const T* b, T* xo, T omega,
+                              hipStream_t st) {
+    hipLaunchKernelGGL(k_jacobi_zero<T>, dim3(blocks1d(lv.n)), dim3(BLOCK), 0, st,
+                       bands + 4 * lv.bs, b, xo, lv.n, omega);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_restrict(int Nf, const T* d_f, T* b_c, hipStream_t st) {
+    const int Nc = (Nf >> 1) + 1;
+    hipLaunchKernelGGL(k_restrict<T>, dim3(blocks1d(Nc), Nc), dim3(BLOCK), 0, st, Nf, d_f, b_c);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_prolong(int Nf, const T* x_c, T* x_f, hipStream_t st) {
+    hipLaunchKernelGGL(k_prolong<T>, dim3(blocks1d(Nf), Nf), dim3(BLOCK), 0, st, Nf, x_c, x_f);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_coarse(const double* chol, int m, int Nc, const T* b, T* x, hipStream_t st) {
+    hipLaunchKernelGGL(k_coarse<T>, dim3(1), dim3(64), 0, st, chol, m, Nc, b, x);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_copy(const T* src, T* dst, int64_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_copy<T>, dim3(blocks1d(n)), dim3(BLOCK), 0, st, src, dst, n);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_norm(const T* v, int64_t n, double* partials, double* scal, int slot,
+                       hipStream_t st) {
+    const int64_t nb = (n + BLOCK * 4 - 1) / (BLOCK * 4);
+    hipLaunchKernelGGL(k_sumsq<T>, dim3(grid8(nb)), dim3(BLOCK), 0, st, v, n, partials, nb);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(BLOCK), 0, st, partials, nb, scal, slot);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fill(T* v, int64_t n, T value, hipStream_t st) {
+    hipLaunchKernelGGL(k_fill<T>, dim3(blocks1d(n)), dim3(BLOCK), 0, st, v, n, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_cast_scaled(const double* d64, float* d32, int64_t n, const double* scal,
+                              int slot, hipStream_t st) {
+    hipLaunchKernelGGL(k_cast_scaled, dim3(blocks1d(n)), dim3(BLOCK), 0, st, d64, d32, n, scal,
+                       slot);
+    return hipGetLastError();
+}
+
+hipError_t launch_update(double* x, const float* c32, int64_t n, const double* scal, int slot,
+                         hipStream_t st) {
+    hipLaunchKernelGGL(k_update, dim3(blocks1d(n)), dim3(BLOCK), 0, st, x, c32, n, scal, slot);
+    return hipGetLastError();
+}
+
+#define MG_INSTANTIATE(T)                                                                     \
+    template hipError_t launch_spmv<T>(const Level&, const T*, const T*, T*, hipStream_t);    \
+    template hipError_t launch_defect<T>(const Level&, const T*, const T*, const T*, T*,      \
+                                         double*, double*, int, hipStream_t);                 \
+    template hipError_t launch_jacobi<T>(const Level&, const T*, const T*, const T*, T*, T,   \
+                                         hipStream_t);                                        \
+    template hipError_t launch_jacobi_zero<T>(const Level&, const T*, const T*, T*, T,        \
+                                              hipStream_t);                                   \
+    template hipError_t launch_restrict<T>(int, const T*, T*, hipStream_t);                   \
+    template hipError_t launch_prolong<T>(int, const T*, T*, hipStream_t);                    \
+    template hipError_t launch_coarse<T>(const double*, int, int, const T*, T*, hipStream_t); \
+    template hipError_t launch_copy<T>(const T*, T*, int64_t, hipStream_t);                   \
+    template hipError_t launch_norm<T>(const T*, int64_t, double*, double*, int, hipStream_t); \
+    template hipError_t launch_fill<T>(T*, int64_t, T, hipStream_t);
+
+MG_INSTANTIATE(float)
+MG_INSTANTIATE(double)
+
+}  // namespace mg

@@ -1,0 +1,136 @@
+// Internal declarations of the multigrid library: device-resident hierarchy
+// layout and the kernel launchers shared by the C ABI, the solvers, the
+// batched path and the server.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "mgfem.h"
+
+namespace mg {
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string& msg);
+mg_status fail(mg_status s, const std::string& msg);
+
+#define MG_HIP(call)                                                                  \
+    do {                                                                              \
+        hipError_t e_ = (call);                                                       \
+        if (e_ != hipSuccess)                                                         \
+            return ::mg::fail(MG_ERR_DEVICE, std::string(#call) + ": " +              \
+                                                 hipGetErrorString(e_));              \
+    } while (0)
+
+// ---------------------------------------------------------------- layout
+// Band arrays of one level live in one allocation: band k starts at
+// k * band_stride elements.  The stride is n rounded up to 64 elements plus a
+// per-level skew of 64 elements times an odd factor, so that the nine
+// streams of a band product do not start on the same HBM channel.
+int64_t band_stride(int64_t n);
+// Vectors are padded to a multiple of 64 elements (the tail stays zero).
+int64_t vec_len(int64_t n);
+
+struct Level {
+    int l = 0;
+    int N = 0;
+    int64_t n = 0;
+    int64_t bs = 0;           // band stride (elements)
+    double* bands64 = nullptr;
+    float* bands32 = nullptr;
+    double *x64 = nullptr, *b64 = nullptr, *t64 = nullptr;
+    float *x32 = nullptr, *b32 = nullptr, *t32 = nullptr;
+};
+
+}  // namespace mg
+
+struct mg_context {
+    int device = 0;
+    size_t budget = 0;      // 0: unlimited
+    size_t in_use = 0;
+    size_t high_water = 0;
+    std::mutex mu;
+    // Charge `bytes` against the budget; false if it does not fit.
+    bool reserve(size_t bytes);
+    void release(size_t bytes);
+};
+
+struct GraphCache;  // defined in solve.hip
+
+struct mg_hierarchy {
+    mg_context* ctx = nullptr;
+    int L = 0, Lc = 1;
+    size_t charged = 0;
+    std::vector<void*> allocs;
+    mg::Level lv[MG_MAX_LEVEL + 1];
+    double* coords = nullptr;      // finest coordinates, 2n
+    double* d64 = nullptr;         // finest FP64 defect (mixed solver)
+    double* partials = nullptr;    // per-block partial sums of the reductions
+    int64_t n_partials = 0;
+    double* scal = nullptr;        // device scalars (norms), 64 doubles
+    double* host_scal = nullptr;   // pinned mirror of scal
+    double* chol = nullptr;        // m x m Cholesky factor of the coarse interior block
+    int m = 0;
+    int* flag = nullptr;           // device status flag of the coarse factorisation
+    bool assembled = false;
+    GraphCache* graphs = nullptr;
+};
+
+namespace mg {
+
+// Scalar slots in hierarchy::scal (sum of squares at s, norm at s+1).
+enum : int { SC_B = 0, SC_R64 = 2, SC_R32 = 4, SC_D32 = 6, SC_USER = 8 };
+
+// ---------------------------------------------------------------- kernels
+// All launchers enqueue on `st` and return the HIP launch error.
+hipError_t launch_coords(double* xy, int L, double jitter, uint64_t seed, hipStream_t st);
+hipError_t launch_assemble(const double* xy_fine, int L, const Level& lv, hipStream_t st);
+hipError_t launch_chol_factor(const Level& lc, double* chol, int* flag, hipStream_t st);
+hipError_t launch_rhs_sinsin(const double* xy, int N, double* b, hipStream_t st);
+hipError_t launch_rhs_uniform(int N, uint64_t seed, double* b, hipStream_t st);
+
+// Stencil family on one level.
+template <typename T>
+hipError_t launch_spmv(const Level& lv, const T* bands, const T* x, T* y, hipStream_t st);
+// d = b - A x (d may be null); if partials != null also writes per-block
+// sums of d^2 and reduces them into scal[slot] (sum) and scal[slot+1] (norm).
+template <typename T>
+hipError_t launch_defect(const Level& lv, const T* bands, const T* b, const T* x, T* d,
+                         double* partials, double* scal, int slot, hipStream_t st);
+template <typename T>
+hipError_t launch_jacobi(const Level& lv, const T* bands, const T* b, const T* x, T* xo,
+                         T omega, hipStream_t st);
+// Jacobi sweep from a zero initial guess: xo = omega b / diag.
+template <typename T>
+hipError_t launch_jacobi_zero(const Level& lv, const T* bands, const T* b, T* xo, T omega,
+                              hipStream_t st);
+template <typename T>
+hipError_t launch_restrict(int Nf, const T* d_f, T* b_c, hipStream_t st);
+template <typename T>
+hipError_t launch_prolong(int Nf, const T* x_c, T* x_f, hipStream_t st);
+template <typename T>
+hipError_t launch_coarse(const double* chol, int m, int Nc, const T* b, T* x, hipStream_t st);
+template <typename T>
+hipError_t launch_copy(const T* src, T* dst, int64_t n, hipStream_t st);
+// Sum of squares of v (accumulated in FP64) into scal[slot], norm into
+// scal[slot+1].
+template <typename T>
+hipError_t launch_norm(const T* v, int64_t n, double* partials, double* scal, int slot,
+                       hipStream_t st);
+template <typename T>
+hipError_t launch_fill(T* v, int64_t n, T value, hipStream_t st);
+// d32 = float(d64 / s) with s = scal[slot + 1] (0 if s == 0).
+hipError_t launch_cast_scaled(const double* d64, float* d32, int64_t n, const double* scal,
+                              int slot, hipStream_t st);
+// x += s * double(c32), s = scal[slot + 1].
+hipError_t launch_update(double* x, const float* c32, int64_t n, const double* scal, int slot,
+                         hipStream_t st);
+
+int64_t stencil_blocks(int64_t n, int elem_bytes);
+
+}  // namespace mg

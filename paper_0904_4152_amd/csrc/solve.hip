@@ -1,0 +1,358 @@
+// Multigrid drivers (Sec. 6.2): the V(nu_pre, nu_post) cycle with damped
+// Jacobi smoothing, the FP64 solver and the mixed-precision defect
+// correction with single-precision inner cycles.  Cycles are captured once
+// per hierarchy into HIP graphs and replayed, which removes the launch cost
+// of the coarse levels (tens of tiny kernels per cycle).
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "solve.h"
+
+struct GraphEntry {
+    int kind;  // 0: FP64 cycle + residual norm; 1: FP32 inner cycle + residual norm
+    int nu_pre, nu_post;
+    double omega;
+    bool x_zero;
+    hipGraphExec_t exec;
+    double bytes;
+};
+
+struct GraphCache {
+    hipStream_t st = nullptr;  // internal non-blocking stream (capture needs one)
+    bool capture_ok = true;
+    std::vector<GraphEntry> entries;
+};
+
+namespace mg {
+
+namespace {
+
+template <typename T>
+struct LV;
+template <>
+struct LV<double> {
+    static double* x(Level& l) { return l.x64; }
+    static double* b(Level& l) { return l.b64; }
+    static double* t(Level& l) { return l.t64; }
+    static const double* bands(const Level& l) { return l.bands64; }
+};
+template <>
+struct LV<float> {
+    static float* x(Level& l) { return l.x32; }
+    static float* b(Level& l) { return l.b32; }
+    static float* t(Level& l) { return l.t32; }
+    static const float* bands(const Level& l) { return l.bands32; }
+};
+
+#define MG_TRY(call)                         \
+    do {                                     \
+        hipError_t e_ = (call);              \
+        if (e_ != hipSuccess) return e_;     \
+    } while (0)
+
+}  // namespace
+
+// Byte model (algorithmic HBM traffic, s = sizeof(T)): band product family
+// 9 bands + x (+ b) (+ output); Jacobi from zero: diagonal + b + output;
+// restriction: fine defect + coarse rhs; prolongation: coarse x + fine x
+// read and written.
+template <typename T>
+hipError_t enqueue_vcycle(mg_hierarchy* h, int l, T* x, const T* b, bool x_zero, int nu_pre,
+                          int nu_post, double omega, Enq& q) {
+    Level& lv = h->lv[l];
+    const double s = sizeof(T), n = (double)lv.n;
+    const T om = (T)omega;
+    if (l == h->Lc) {
+        MG_TRY(launch_coarse<T>(h->chol, h->m, lv.N, b, x, q.st));
+        q.bytes += 2 * s * n;
+        return hipSuccess;
+    }
+    const T* bands = LV<T>::bands(lv);
+    T* cur = x;
+    T* oth = LV<T>::t(lv);
+    bool zero = x_zero;
+    if (zero && nu_pre == 0) {
+        MG_TRY(launch_fill<T>(cur, lv.n, T(0), q.st));
+        q.bytes += s * n;
+        zero = false;
+    }
+    for (int k = 0; k < nu_pre; ++k) {
+        if (zero) {
+            MG_TRY(launch_jacobi_zero<T>(lv, bands, b, oth, om, q.st));
+            q.bytes += 3 * s * n;
+            zero = false;
+        } else {
+            MG_TRY(launch_jacobi<T>(lv, bands, b, cur, oth, om, q.st));
+            q.bytes += 12 * s * n;
+        }
+        std::swap(cur, oth);
+    }
+    MG_TRY(launch_defect<T>(lv, bands, b, cur, oth, nullptr, nullptr, 0, q.st));
+    q.bytes += 12 * s * n;
+    Level& lc = h->lv[l - 1];
+    MG_TRY(launch_restrict<T>(lv.N, oth, LV<T>::b(lc), q.st));
+    q.bytes += s * (n + (double)lc.n);
+    MG_TRY(enqueue_vcycle<T>(h, l - 1, LV<T>::x(lc), LV<T>::b(lc), true, nu_pre, nu_post, omega,
+                             q));
+    MG_TRY(launch_prolong<T>(lv.N, LV<T>::x(lc), cur, q.st));
+    q.bytes += s * ((double)lc.n + 2 * n);
+    for (int k = 0; k < nu_post; ++k) {
+        MG_TRY(launch_jacobi<T>(lv, bands, b, cur, oth, om, q.st));
+        q.bytes += 12 * s * n;
+        std::swap(cur, oth);
+    }
+    if (cur != x) {
+        MG_TRY(launch_copy<T>(cur, x, lv.n, q.st));
+        q.bytes += 2 * s * n;
+    }
+    return hipSuccess;
+}
+
+template hipError_t enqueue_vcycle<double>(mg_hierarchy*, int, double*, const double*, bool, int,
+                                           int, double, Enq&);
+template hipError_t enqueue_vcycle<float>(mg_hierarchy*, int, float*, const float*, bool, int,
+                                          int, double, Enq&);
+
+// The unit replayed per iteration: FP64 cycle + FP64 residual norm (kind 0)
+// or FP32 inner cycle + FP32 residual norm (kind 1), on the finest level's
+// own vectors.
+static hipError_t enqueue_unit(mg_hierarchy* h, int kind, int nu_pre, int nu_post, double omega,
+                               bool x_zero, Enq& q) {
+    Level& F = h->lv[h->L];
+    const double n = (double)F.n;
+    if (kind == 0) {
+        MG_TRY(enqueue_vcycle<double>(h, h->L, F.x64, F.b64, false, nu_pre, nu_post, omega, q));
+        MG_TRY(launch_defect<double>(F, F.bands64, F.b64, F.x64, nullptr, h->partials, h->scal,
+                                     SC_R64, q.st));
+        q.bytes += 11 * 8 * n;
+    } else {
+        MG_TRY(enqueue_vcycle<float>(h, h->L, F.x32, F.b32, x_zero, nu_pre, nu_post, omega, q));
+        MG_TRY(launch_defect<float>(F, F.bands32, F.b32, F.x32, nullptr, h->partials, h->scal,
+                                    SC_R32, q.st));
+        q.bytes += 11 * 4 * n;
+    }
+    return hipSuccess;
+}
+
+static GraphCache* cache(mg_hierarchy* h) {
+    if (!h->graphs) h->graphs = new GraphCache();
+    return h->graphs;
+}
+
+void destroy_graphs(mg_hierarchy* h) {
+    if (!h->graphs) return;
+    for (auto& e : h->graphs->entries) (void)hipGraphExecDestroy(e.exec);
+    if (h->graphs->st) (void)hipStreamDestroy(h->graphs->st);
+    delete h->graphs;
+    h->graphs = nullptr;
+}
+
+// Run one unit, from a captured graph when allowed.
+static hipError_t run_unit(mg_hierarchy* h, int kind, const mg_solve_opts& o, bool x_zero,
+                           bool use_graph, Enq& q) {
+    GraphCache* gc = cache(h);
+    if (use_graph && gc->capture_ok) {
+        for (auto& e : gc->entries) {
+            if (e.kind == kind && e.nu_pre == o.nu_pre && e.nu_post == o.nu_post &&
+                e.omega == o.omega && e.x_zero == x_zero) {
+                q.bytes += e.bytes;
+                return hipGraphLaunch(e.exec, q.st);
+            }
+        }
+        Enq cq{q.st, 0.0};
+        hipError_t e = hipStreamBeginCapture(q.st, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            hipError_t ee = enqueue_unit(h, kind, o.nu_pre, o.nu_post, o.omega, x_zero, cq);
+            hipGraph_t g = nullptr;
+            e = hipStreamEndCapture(q.st, &g);
+            if (ee != hipSuccess) e = ee;
+            hipGraphExec_t ex = nullptr;
+            if (e == hipSuccess) e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+            if (g) (void)hipGraphDestroy(g);
+            if (e == hipSuccess) {
+                gc->entries.push_back({kind, o.nu_pre, o.nu_post, o.omega, x_zero, ex, cq.bytes});
+                q.bytes += cq.bytes;
+                return hipGraphLaunch(ex, q.st);
+            }
+        }
+        (void)hipGetLastError();
+        gc->capture_ok = false;  // fall back to direct launches for this hierarchy
+    }
+    return enqueue_unit(h, kind, o.nu_pre, o.nu_post, o.omega, x_zero, q);
+}
+
+static hipError_t read_scalar(mg_hierarchy* h, int slot, hipStream_t st, double* out) {
+    MG_TRY(hipMemcpyAsync(h->host_scal + slot, h->scal + slot, 2 * sizeof(double),
+                          hipMemcpyDeviceToHost, st));
+    MG_TRY(hipStreamSynchronize(st));
+    *out = h->host_scal[slot + 1];
+    return hipSuccess;
+}
+
+}  // namespace mg
+
+using namespace mg;
+
+#define MG_HIPS(call)                                                                         \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess) {                                                               \
+            st.status = MG_ERR_DEVICE;                                                        \
+            if (stats) *stats = st;                                                           \
+            return fail(MG_ERR_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_));   \
+        }                                                                                     \
+    } while (0)
+
+static mg_status validate_opts(const mg_solve_opts& o) {
+    if (o.nu_pre < 0 || o.nu_post < 0 || o.nu_pre + o.nu_post == 0 || o.nu_pre > 16 ||
+        o.nu_post > 16)
+        return fail(MG_ERR_INVALID, "smoothing steps must be in [0,16] and not both 0");
+    if (!(o.omega > 0.0 && o.omega < 2.0)) return fail(MG_ERR_INVALID, "omega must lie in (0,2)");
+    if (!(o.rel_tol >= 0.0) || o.max_cycles < 1)
+        return fail(MG_ERR_INVALID, "rel_tol must be >= 0 and max_cycles >= 1");
+    if (o.precision != MG_PREC_FP64 && o.precision != MG_PREC_MIXED)
+        return fail(MG_ERR_INVALID, "unknown precision");
+    if (o.precision == MG_PREC_MIXED &&
+        (!(o.inner_reduction >= 0.0 && o.inner_reduction < 1.0) || o.inner_max_cycles < 1))
+        return fail(MG_ERR_INVALID, "inner_reduction in [0,1) and inner_max_cycles >= 1 required");
+    if (o.fixed_cycles < 0) return fail(MG_ERR_INVALID, "fixed_cycles must be >= 0");
+    return MG_OK;
+}
+
+extern "C" mg_status mg_vcycle(mg_hierarchy* h, int level, mg_dtype dtype, const void* b,
+                               void* x, int nu_pre, int nu_post, double omega, void* stream) {
+    if (!h) return fail(MG_ERR_INVALID, "null hierarchy");
+    if (level < h->Lc || level > h->L) return fail(MG_ERR_INVALID, "level out of range");
+    if (!h->assembled) return fail(MG_ERR_INVALID, "hierarchy not assembled");
+    if (!b || !x || ((uintptr_t)b & 15) || ((uintptr_t)x & 15) || b == x)
+        return fail(MG_ERR_INVALID, "b, x must be distinct 16-byte aligned device pointers");
+    if (nu_pre < 0 || nu_post < 0 || nu_pre > 16 || nu_post > 16)
+        return fail(MG_ERR_INVALID, "smoothing steps out of range");
+    MG_HIP(hipSetDevice(h->ctx->device));
+    Enq q{(hipStream_t)stream, 0.0};
+    if (dtype == MG_F64)
+        MG_HIP(enqueue_vcycle<double>(h, level, (double*)x, (const double*)b, false, nu_pre,
+                                      nu_post, omega, q));
+    else
+        MG_HIP(enqueue_vcycle<float>(h, level, (float*)x, (const float*)b, false, nu_pre, nu_post,
+                                     omega, q));
+    return MG_OK;
+}
+
+extern "C" mg_status mg_solve(mg_hierarchy* h, const double* dev_b, double* dev_x,
+                              const mg_solve_opts* opts, void* stream, mg_stats* stats) {
+    const auto t0 = std::chrono::steady_clock::now();
+    mg_stats st{};
+    if (stats) *stats = st;
+    if (!h) return fail(MG_ERR_INVALID, "null hierarchy");
+    if (!h->assembled) return fail(MG_ERR_INVALID, "hierarchy not assembled");
+    if (!dev_b || !dev_x || dev_b == dev_x || ((uintptr_t)dev_b & 15) || ((uintptr_t)dev_x & 15))
+        return fail(MG_ERR_INVALID, "b, x must be distinct 16-byte aligned device pointers");
+    mg_solve_opts o;
+    if (opts)
+        o = *opts;
+    else
+        mg_default_opts(&o);
+    if (mg_status s = validate_opts(o)) return s;
+    MG_HIP(hipSetDevice(h->ctx->device));
+    GraphCache* gc = cache(h);
+    if (!gc->st) MG_HIP(hipStreamCreateWithFlags(&gc->st, hipStreamNonBlocking));
+    // Wait for the caller's producers of b and x, then work on the internal stream.
+    MG_HIPS(hipStreamSynchronize((hipStream_t)stream));
+    Enq q{gc->st, 0.0};
+    Level& F = h->lv[h->L];
+    const int64_t n = F.n;
+    const bool graphs = o.use_graph != 0;
+    MG_HIPS(launch_copy<double>(dev_b, F.b64, n, q.st));
+    MG_HIPS(launch_copy<double>(dev_x, F.x64, n, q.st));
+    MG_HIPS(launch_norm<double>(F.b64, n, h->partials, h->scal, SC_B, q.st));
+    q.bytes += 8.0 * 5 * n;
+    double bn = 0.0;
+    MG_HIPS(read_scalar(h, SC_B, q.st, &bn));
+    st.bnorm = bn;
+    mg_status result = MG_OK;
+    if (!std::isfinite(bn)) {
+        result = fail(MG_ERR_NUMERIC, "right-hand side contains NaN or Inf");
+    } else if (bn == 0.0) {
+        MG_HIPS(launch_fill<double>(F.x64, n, 0.0, q.st));
+    } else if (o.precision == MG_PREC_FP64) {
+        double r = 0.0;
+        MG_HIPS(launch_defect<double>(F, F.bands64, F.b64, F.x64, nullptr, h->partials, h->scal,
+                                      SC_R64, q.st));
+        q.bytes += 11.0 * 8 * n;
+        MG_HIPS(read_scalar(h, SC_R64, q.st, &r));
+        st.rel_res = r / bn;
+        for (int k = 1;; ++k) {
+            if (o.fixed_cycles > 0) {
+                if (k > o.fixed_cycles) break;
+            } else {
+                if (r <= o.rel_tol * bn) break;
+                if (k > o.max_cycles) {
+                    result = fail(MG_ERR_NOCONV, "no convergence within max_cycles");
+                    break;
+                }
+            }
+            MG_HIPS(run_unit(h, 0, o, false, graphs, q));
+            MG_HIPS(read_scalar(h, SC_R64, q.st, &r));
+            st.cycles = k;
+            st.rel_res = r / bn;
+            if (st.n_hist < MG_HIST) st.res_hist[st.n_hist++] = r / bn;
+            if (!std::isfinite(r) || r > 1e3 * bn) {
+                result = fail(MG_ERR_NUMERIC, "residual diverged or became NaN");
+                break;
+            }
+        }
+    } else {
+        for (int k = 1;; ++k) {
+            double s = 0.0;
+            MG_HIPS(launch_defect<double>(F, F.bands64, F.b64, F.x64, h->d64, h->partials,
+                                          h->scal, SC_R64, q.st));
+            q.bytes += 12.0 * 8 * n;
+            MG_HIPS(read_scalar(h, SC_R64, q.st, &s));
+            st.rel_res = s / bn;
+            if (k > 1 && st.n_hist < MG_HIST) st.res_hist[st.n_hist++] = s / bn;
+            if (!std::isfinite(s) || s > 1e3 * bn) {
+                result = fail(MG_ERR_NUMERIC, "residual diverged or became NaN");
+                break;
+            }
+            if (o.fixed_cycles > 0) {
+                if (k > o.fixed_cycles) break;
+            } else {
+                if (s <= o.rel_tol * bn) break;
+                if (k > o.max_cycles) {
+                    result = fail(MG_ERR_NOCONV, "no convergence within max_cycles");
+                    break;
+                }
+            }
+            if (s == 0.0) break;
+            MG_HIPS(launch_cast_scaled(h->d64, F.b32, n, h->scal, SC_R64, q.st));
+            MG_HIPS(launch_norm<float>(F.b32, n, h->partials, h->scal, SC_D32, q.st));
+            q.bytes += 16.0 * n;
+            double dn = 0.0;
+            MG_HIPS(read_scalar(h, SC_D32, q.st, &dn));
+            for (int it = 1; it <= o.inner_max_cycles; ++it) {
+                double r32 = 0.0;
+                MG_HIPS(run_unit(h, 1, o, it == 1, graphs, q));
+                MG_HIPS(read_scalar(h, SC_R32, q.st, &r32));
+                st.cycles++;
+                if (!std::isfinite(r32)) break;
+                if (r32 <= o.inner_reduction * dn) break;
+            }
+            MG_HIPS(launch_update(F.x64, F.x32, n, h->scal, SC_R64, q.st));
+            q.bytes += 20.0 * n;
+            st.outer_steps = k;
+        }
+    }
+    MG_HIPS(launch_copy<double>(F.x64, dev_x, n, q.st));
+    q.bytes += 16.0 * n;
+    MG_HIPS(hipStreamSynchronize(q.st));
+    st.status = result;
+    st.alg_bytes = q.bytes;
+    st.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (stats) *stats = st;
+    return result;
+}
