@@ -133,6 +133,14 @@ def main():
     }
     del x32, y32, b32, x64, y64
     if args.only_kernels:
+        # a plain device copy of known size (1 GiB read + 1 GiB written):
+        # the calibration reference for the HBM byte counters
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        t_copy = time_launches(lambda: dst.copy_(src), 5, torch)
+        out["calibration_copy"] = {"bytes_read": src.numel() * 4, "bytes_written": src.numel() * 4,
+                                   "us": t_copy * 1e6,
+                                   "GB_s": 2 * src.numel() * 4 / t_copy / 1e9}
         print(json.dumps(out))
         return
 
