@@ -81,10 +81,11 @@ typedef struct {
     int outer_steps;         /* mixed: FP64 defect-correction updates */
     double bnorm;            /* ||b||_2 */
     double rel_res;          /* ||b - A x||_2 / ||b||_2 at exit, evaluated in FP64 */
-    double seconds;          /* host wall time of the call */
+    double seconds;          /* host wall time of the call; server: submission to result */
     double alg_bytes;        /* algorithmic HBM bytes of the kernels launched */
     int n_hist;
     double res_hist[MG_HIST]; /* relative residual after each cycle / outer step */
+    double queue_seconds;     /* server: submission to admission */
 } mg_stats;
 
 /* Defaults: 2, 2, 0.7, 1e-8, 100, FP64, 1e-2, 8, 0, 1. */
@@ -149,6 +150,62 @@ mg_status mg_rhs_uniform(const mg_hierarchy* h, uint64_t seed, double* dev_b, vo
  * Not thread safe per hierarchy.  stats may be NULL. */
 mg_status mg_solve(mg_hierarchy* h, const double* dev_b, double* dev_x,
                    const mg_solve_opts* opts, void* stream, mg_stats* stats);
+
+/* ---- batched solve ---------------------------------------------------------
+ * Solve count independent problems A_p x_p = b_p (each with its own
+ * assembled hierarchy; levels may differ, the coarse level must agree) with
+ * the mixed-precision scheme of mg_solve, advancing all of them together:
+ * each V-cycle stage is one persistent launch over every problem that has
+ * that level, and each problem's outer/inner stop decisions are taken on the
+ * device.  A problem's arithmetic does not depend on the other problems in
+ * the batch (its result equals a batch of one bit for bit).  opts: NULL
+ * (defaults, mixed) or an array of count entries; precision must be
+ * MG_PREC_MIXED and nu_pre/nu_post must agree.  b[p], x[p]: device vectors
+ * of that problem's finest n; x is in/out.  stats: NULL or count entries.
+ * Synchronous.  Returns the first non-OK per-problem status, if any. */
+mg_status mg_solve_batch(mg_hierarchy* const* hs, const double* const* b, double* const* x,
+                         int count, const mg_solve_opts* opts, void* stream, mg_stats* stats);
+
+/* ---- serving ---------------------------------------------------------------
+ * A server owns a BatchEngine of `slots` slots, a scheduler thread and a pool
+ * of device-resident hierarchies of levels coarse_level..max_level charged
+ * against hbm_budget_bytes (and the context budget).  Requests are admitted
+ * in arrival order when a slot is free and their hierarchy fits the budget
+ * (idle hierarchies of other levels are evicted first); their problem is
+ * generated on the device (jittered grid from geom_seed, assembly, uniform
+ * right-hand side from rhs_seed, x0 = 0) and solved with the mixed scheme to
+ * rel_tol, advancing together with every other live request, one
+ * graph-replayed iteration at a time (continuous batching).  A request whose
+ * hierarchy cannot fit even on an idle server finishes with MG_ERR_NOMEM.
+ * opts (nullable): smoothing, omega and inner-loop options shared by all
+ * requests.  Thread safe. */
+typedef struct {
+    uint64_t completed;
+    size_t queued;
+    int live;
+    size_t queue_high_water;
+    size_t bytes;             /* hierarchies held (live + idle pool) */
+    size_t bytes_high_water;
+    double busy_seconds;      /* time spent in device iterations */
+} mg_server_info_t;
+
+mg_status mg_server_create(mg_context* ctx, int slots, size_t hbm_budget_bytes, int max_level,
+                           int coarse_level, const mg_solve_opts* opts, mg_server** out);
+/* Queue a request; never blocks on the device.  keep_x != 0 keeps the
+ * solution for collection.  MG_ERR_NOMEM if the level can never fit. */
+mg_status mg_server_submit(mg_server* s, int L, double rel_tol, double jitter,
+                           uint64_t geom_seed, uint64_t rhs_seed, int keep_x, uint64_t* ticket);
+/* MG_ERR_BUSY while the ticket is pending; otherwise the request's status,
+ * its stats (seconds = submission to result on the host) and, if kept and
+ * host_x is non-NULL, its solution (n doubles).  A ticket is collected once. */
+mg_status mg_server_poll(mg_server* s, uint64_t ticket, double* host_x, mg_stats* stats);
+/* Collect the oldest finished request, waiting up to timeout_s seconds;
+ * MG_ERR_BUSY if none finished in time. */
+mg_status mg_server_next(mg_server* s, double timeout_s, uint64_t* ticket, double* host_x,
+                         mg_stats* stats);
+mg_status mg_server_info(mg_server* s, mg_server_info_t* info);
+/* Finish every queued and running request, then free everything. */
+mg_status mg_server_destroy(mg_server* s);
 
 /* ---- single operators (asynchronous; for parity tests and benchmarks) -----
  * x, y, b, d: device vectors of the level's n elements in dtype. */

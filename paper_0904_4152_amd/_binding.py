@@ -32,10 +32,15 @@ class SolveOpts(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("status", _i), ("cycles", _i), ("outer_steps", _i), ("bnorm", _d),
                 ("rel_res", _d), ("seconds", _d), ("alg_bytes", _d), ("n_hist", _i),
-                ("res_hist", _d * MG_HIST)]
+                ("res_hist", _d * MG_HIST), ("queue_seconds", _d)]
 
     def hist(self):
         return [self.res_hist[k] for k in range(self.n_hist)]
+
+
+class ServerInfo(ctypes.Structure):
+    _fields_ = [("completed", _u64), ("queued", _sz), ("live", _i), ("queue_high_water", _sz),
+                ("bytes", _sz), ("bytes_high_water", _sz), ("busy_seconds", _d)]
 
 
 class MgError(RuntimeError):
@@ -69,6 +74,15 @@ _SIGS = {
     "mg_prolong": (_i, [_vp, _i, _i, _vp, _vp, _vp]),
     "mg_coarse_solve": (_i, [_vp, _i, _vp, _vp, _vp]),
     "mg_vcycle": (_i, [_vp, _i, _i, _vp, _vp, _i, _i, _d, _vp]),
+    "mg_server_create": (_i, [_vp, _i, _sz, _i, _i, ctypes.POINTER(SolveOpts),
+                              ctypes.POINTER(_vp)]),
+    "mg_server_submit": (_i, [_vp, _i, _d, _d, _u64, _u64, _i, ctypes.POINTER(_u64)]),
+    "mg_server_poll": (_i, [_vp, _u64, _vp, ctypes.POINTER(Stats)]),
+    "mg_server_next": (_i, [_vp, _d, ctypes.POINTER(_u64), _vp, ctypes.POINTER(Stats)]),
+    "mg_server_info": (_i, [_vp, ctypes.POINTER(ServerInfo)]),
+    "mg_server_destroy": (_i, [_vp]),
+    "mg_solve_batch": (_i, [ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp), _i,
+                            ctypes.POINTER(SolveOpts), _vp, ctypes.POINTER(Stats)]),
 }
 
 _lib = None
@@ -274,3 +288,78 @@ class Hierarchy:
     def vcycle(self, level, b, x, nu_pre=2, nu_post=2, omega=0.7, stream=None):
         check(lib().mg_vcycle(self._h, level, _dt(x), _ptr(b), _ptr(x), nu_pre, nu_post, omega,
                               _stream(stream)))
+
+
+def solve_batch(hierarchies, bs, xs, opts=None, stream=None, raise_on_error=True):
+    """mg_solve_batch over lists of Hierarchy objects and device tensors;
+    opts: None, one SolveOpts for all, or a list.  Returns the Stats list."""
+    n = len(hierarchies)
+    H = (_vp * n)(*[h.handle for h in hierarchies])
+    B = (_vp * n)(*[_ptr(t) for t in bs])
+    X = (_vp * n)(*[_ptr(t) for t in xs])
+    O = None
+    if opts is not None:
+        lst = opts if isinstance(opts, (list, tuple)) else [opts] * n
+        O = (SolveOpts * n)(*lst)
+    S = (Stats * n)()
+    rc = lib().mg_solve_batch(H, B, X, n, O, _stream(stream), S)
+    if raise_on_error:
+        check(rc)
+    return list(S)
+
+
+class Server:
+    """mg_server_*: continuous-batching solve service on one device."""
+
+    def __init__(self, ctx: Context, slots: int, budget_bytes: int, max_level: int,
+                 coarse_level: int = 1, opts: SolveOpts | None = None):
+        h = _vp()
+        check(lib().mg_server_create(ctx.handle, slots, budget_bytes, max_level, coarse_level,
+                                     ctypes.byref(opts) if opts is not None else None,
+                                     ctypes.byref(h)))
+        self._h = h
+        self.ctx = ctx
+
+    def submit(self, L, rel_tol, jitter, geom_seed, rhs_seed, keep_x=False) -> int:
+        t = _u64()
+        check(lib().mg_server_submit(self._h, L, rel_tol, jitter, geom_seed, rhs_seed,
+                                     int(keep_x), ctypes.byref(t)))
+        return t.value
+
+    def poll(self, ticket, n=None):
+        """(status, stats, x or None); status MG_ERR_BUSY while pending."""
+        import numpy as np
+        st = Stats()
+        x = np.zeros(n) if n else None
+        rc = lib().mg_server_poll(self._h, ticket, x.ctypes.data_as(_vp) if n else None,
+                                  ctypes.byref(st))
+        if rc not in (MG_OK, MG_ERR_BUSY, MG_ERR_NOCONV, MG_ERR_NUMERIC, MG_ERR_NOMEM):
+            check(rc)
+        return rc, st, x
+
+    def next(self, timeout=1.0):
+        """(ticket, status, stats) of the oldest finished request, or None."""
+        st = Stats()
+        t = _u64()
+        rc = lib().mg_server_next(self._h, timeout, ctypes.byref(t), None, ctypes.byref(st))
+        if rc == MG_ERR_BUSY:
+            return None
+        if rc not in (MG_OK, MG_ERR_NOCONV, MG_ERR_NUMERIC, MG_ERR_NOMEM):
+            check(rc)
+        return t.value, rc, st
+
+    def info(self) -> ServerInfo:
+        i = ServerInfo()
+        check(lib().mg_server_info(self._h, ctypes.byref(i)))
+        return i
+
+    def close(self):
+        if self._h:
+            check(lib().mg_server_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

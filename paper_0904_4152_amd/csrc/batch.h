@@ -1,0 +1,108 @@
+// Batched execution of many independent mixed-precision multigrid solves
+// (persistent stage kernels, per-problem state machine on the device, one
+// captured HIP graph per iteration).  Used by mg_solve_batch and the server.
+#pragma once
+
+#include <vector>
+
+#include "mg_internal.h"
+
+namespace mg {
+
+// Device view of one level of one problem.
+struct BLevel {
+    const double* bands64;
+    const float* bands32;
+    double* x64;
+    double* b64;
+    float* x32;
+    float* b32;
+    float* t32;
+    int64_t bs;
+    int64_t n;
+    int N;
+    int pad;
+};
+
+struct BProb {
+    BLevel lv[MG_MAX_LEVEL + 1];
+    double* d64;
+    double* partials;
+    const double* chol;
+    int m;
+    int L;
+    double omega;
+    double rel_tol;
+    double inner_reduction;
+    int inner_max;
+    int max_outer;
+    int fixed;
+    int pad;
+};
+
+enum : int {
+    BF_INIT = 1,
+    BF_OUTER = 2,
+    BF_CAST = 4,
+    BF_INNER = 8,
+    BF_UPDATE = 16,
+    BF_DONE = 32
+};
+
+struct BState {
+    int flags;
+    int first;
+    int outer;
+    int it;
+    int cycles;
+    int status;
+    int n_hist;
+    int pad;
+    double bn, s, dn, r32;
+    double hist[MG_HIST];
+};
+
+class BatchEngine {
+public:
+    // capacity problems of levels <= Lmax with common coarse level and
+    // smoothing counts.  Allocates device descriptors (not charged: a few MB).
+    mg_status init(int device, int capacity, int Lmax, int Lc, int nu_pre, int nu_post);
+    ~BatchEngine();
+
+    // Describe slot s (host side); takes effect at the next upload().
+    void set_slot(int s, mg_hierarchy* h, const mg_solve_opts& o);
+    void clear_slot(int s);
+    // Mark slot s to start a solve from its hierarchy's finest b64 / x64.
+    void start_slot(int s);
+    // Upload changed descriptors, work lists and started states.
+    mg_status upload();
+    // One iteration over all live slots (graph replay); synchronous.
+    mg_status step(int* active_left);
+    // Copy the device states to the host mirror; returns it.
+    mg_status read_states();
+    const BState& state(int s) const { return h_state_[s]; }
+    int capacity() const { return cap_; }
+    bool live(int s) const { return hp_[s].L > 0; }
+    hipStream_t stream() const { return st_; }
+    double bytes_per_step() const { return step_bytes_; }
+
+private:
+    hipError_t enqueue_iteration();
+    void build_lists();
+    int device_ = 0, cap_ = 0, Lmax_ = 0, Lc_ = 1, nu_pre_ = 2, nu_post_ = 2;
+    hipStream_t st_ = nullptr;
+    BProb* d_probs_ = nullptr;
+    BState* d_state_ = nullptr;
+    BState* h_state_ = nullptr;  // pinned
+    int* d_wl_ = nullptr;
+    int* d_active_ = nullptr;
+    int* h_active_ = nullptr;    // pinned
+    std::vector<BProb> hp_;
+    std::vector<int> h_wl_;
+    std::vector<char> started_;
+    bool probs_dirty_ = true;
+    hipGraphExec_t graph_ = nullptr;
+    double step_bytes_ = 0.0;
+};
+
+}  // namespace mg

@@ -1,0 +1,713 @@
+// Batched mixed-precision multigrid: many independent problems of different
+// levels advance together.  Every V-cycle stage (a sweep, a defect, a
+// transfer at one level) is one persistent launch over a work list of
+// (problem, tile) items covering every problem that has that level; the
+// problems are aligned at the coarse end, so one coarse-solve launch serves
+// them all.  Per-problem control (outer defect, cast, inner cycles, update,
+// stop tests of Sec. 6.2's mixed scheme) is a state machine advanced on the
+// device by tiny controller kernels, so one iteration is a fixed sequence of
+// launches: it is captured once into a HIP graph and replayed.  A problem's
+// arithmetic uses the same per-tile device functions and the same
+// reduction order as the single-problem solver, so its result does not
+// depend on the other problems in the batch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "batch.h"
+#include "device_ops.h"
+
+namespace mg {
+
+namespace {
+
+using dev::BLOCK;
+
+constexpr int NLISTS = 34;
+constexpr int WL_FINEST = 32;
+constexpr int WL_ALL = 33;
+inline int wl_level(int l) { return l; }
+inline int wl_restrict(int l) { return 16 + l; }
+
+constexpr int STAGE_GRID = 2048;
+constexpr int TILE = 1024;  // elements per work item (one FP32 stencil tile)
+
+enum { K_NORM = 0, K_S32 = 1, K_S64 = 2 };
+enum { F_BN = 0, F_S = 1, F_DN = 2, F_R32 = 3 };
+enum { PH_INIT = 0, PH_UPDATE = 1, PH_OUTER = 2, PH_CAST = 3, PH_INNER = 4 };
+
+// Work list: wl[0] = count, wl[1] = cap, prob[cap] at wl+2, tile prefix
+// start[cap+1] at wl+2+cap.  Item t belongs to the last k with start[k] <= t.
+__device__ __forceinline__ int wl_total(const int* wl) { return wl[2 + wl[1] + wl[0]]; }
+
+__device__ __forceinline__ void wl_item(const int* wl, int t, int* p, int* tile) {
+    const int count = wl[0], cap = wl[1];
+    const int* prob = wl + 2;
+    const int* start = wl + 2 + cap;
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (start[mid] <= t)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    *p = prob[lo];
+    *tile = t - start[lo];
+}
+
+__device__ __forceinline__ float* role32(const BLevel& lv, int r) { return r ? lv.t32 : lv.x32; }
+
+#define FOR_ITEMS(wl)                                              \
+    const int total_ = wl_total(wl);                               \
+    for (int t_ = blockIdx.x; t_ < total_; t_ += gridDim.x) {      \
+        int p, tile;                                               \
+        wl_item(wl, t_, &p, &tile);                                \
+        const BProb& P = probs[p];                                 \
+        const int flags = state[p].flags;
+
+#define END_ITEMS }
+
+// First pre-smoothing sweep at level l: from a zero iterate on every level
+// below the problem's finest and on the finest level at the first inner
+// cycle of an outer step; otherwise a full sweep src -> dst.
+__global__ __launch_bounds__(BLOCK) void kb_pre1(const BProb* __restrict__ probs,
+                                                 const BState* __restrict__ state,
+                                                 const int* __restrict__ wl, int l, int src,
+                                                 int dst, int mask) {
+    FOR_ITEMS(wl)
+    if (!(flags & mask)) continue;
+    const BLevel& lv = P.lv[l];
+    const float om = (float)P.omega;
+    const int64_t base = (int64_t)tile * TILE;
+    if (l < P.L || state[p].first) {
+        const float* diag = lv.bands32 + 4 * lv.bs;
+        float* xo = role32(lv, dst);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int64_t q = base + (int64_t)e * BLOCK + threadIdx.x;
+            if (q < lv.n) dev::jacobi_zero_elem(diag, (const float*)lv.b32, xo, q, om);
+        }
+    } else {
+        dev::stencil_tile<float, dev::OP_JACOBI, false, true>(lv.bands32, lv.bs, lv.N, lv.n,
+                                                              role32(lv, src), lv.b32,
+                                                              role32(lv, dst), om, base);
+    }
+    END_ITEMS
+}
+
+// Zero the iterate where the first sweep would start from zero (only used
+// when there is no pre-smoothing).
+__global__ __launch_bounds__(BLOCK) void kb_fill_cond(const BProb* __restrict__ probs,
+                                                      const BState* __restrict__ state,
+                                                      const int* __restrict__ wl, int l, int dst,
+                                                      int mask) {
+    FOR_ITEMS(wl)
+    if (!(flags & mask)) continue;
+    if (!(l < P.L || state[p].first)) continue;
+    const BLevel& lv = P.lv[l];
+    float* xo = role32(lv, dst);
+    const int64_t base = (int64_t)tile * TILE;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int64_t q = base + (int64_t)e * BLOCK + threadIdx.x;
+        if (q < lv.n) xo[q] = 0.0f;
+    }
+    END_ITEMS
+}
+
+template <int OP>
+__global__ __launch_bounds__(BLOCK) void kb_band(const BProb* __restrict__ probs,
+                                                 const BState* __restrict__ state,
+                                                 const int* __restrict__ wl, int l, int src,
+                                                 int dst, int mask) {
+    FOR_ITEMS(wl)
+    if (!(flags & mask)) continue;
+    const BLevel& lv = P.lv[l];
+    dev::stencil_tile<float, OP, false, true>(lv.bands32, lv.bs, lv.N, lv.n, role32(lv, src),
+                                              lv.b32, role32(lv, dst), (float)P.omega,
+                                              (int64_t)tile * TILE);
+    END_ITEMS
+}
+
+__global__ __launch_bounds__(BLOCK) void kb_restrict(const BProb* __restrict__ probs,
+                                                     const BState* __restrict__ state,
+                                                     const int* __restrict__ wl, int l, int src,
+                                                     int mask) {
+    FOR_ITEMS(wl)
+    if (!(flags & mask)) continue;
+    const BLevel& f = P.lv[l];
+    const BLevel& c = P.lv[l - 1];
+    const int64_t base = (int64_t)tile * TILE;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int64_t q = base + (int64_t)e * BLOCK + threadIdx.x;
+        if (q < c.n)
+            dev::restrict_elem<float>(f.N, role32(f, src), c.b32, (int)(q % c.N), (int)(q / c.N));
+    }
+    END_ITEMS
+}
+
+__global__ __launch_bounds__(BLOCK) void kb_prolong(const BProb* __restrict__ probs,
+                                                    const BState* __restrict__ state,
+                                                    const int* __restrict__ wl, int l, int dst,
+                                                    int mask) {
+    FOR_ITEMS(wl)
+    if (!(flags & mask)) continue;
+    const BLevel& f = P.lv[l];
+    const BLevel& c = P.lv[l - 1];
+    const int64_t base = (int64_t)tile * TILE;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int64_t q = base + (int64_t)e * BLOCK + threadIdx.x;
+        if (q < f.n)
+            dev::prolong_elem<float>(f.N, c.x32, role32(f, dst), (int)(q % f.N), (int)(q / f.N));
+    }
+    END_ITEMS
+}
+
+__global__ __launch_bounds__(BLOCK) void kb_copy(const BProb* __restrict__ probs,
+                                                 const BState* __restrict__ state,
+                                                 const int* __restrict__ wl, int l, int src,
+                                                 int dst, int mask) {
+    FOR_ITEMS(wl)
+    if (!(flags & mask)) continue;
+    const BLevel& lv = P.lv[l];
+    const float* s = role32(lv, src);
+    float* d = role32(lv, dst);
+    const int64_t base = (int64_t)tile * TILE;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int64_t q = base + (int64_t)e * BLOCK + threadIdx.x;
+        if (q < lv.n) d[q] = s[q];
+    }
+    END_ITEMS
+}
+
+// Coarsest level of every problem (one block per problem).
+__global__ __launch_bounds__(BLOCK) void kb_coarse(const BProb* __restrict__ probs,
+                                                   const BState* __restrict__ state,
+                                                   const int* __restrict__ wl, int Lc, int mask) {
+    FOR_ITEMS(wl)
+    if (!(flags & mask)) continue;
+    const BLevel& lv = P.lv[Lc];
+    dev::coarse_block<float>(P.chol, P.m, lv.N, lv.b32, lv.x32);
+    END_ITEMS
+}
+
+// FP32 residual norm of the inner iterate on the finest level (partials).
+__global__ __launch_bounds__(BLOCK) void kb_inner_norm(const BProb* __restrict__ probs,
+                                                       const BState* __restrict__ state,
+                                                       const int* __restrict__ wl, int mask) {
+    FOR_ITEMS(wl)
+    if (!(flags & mask)) continue;
+    const BLevel& lv = P.lv[P.L];
+    const double sq = dev::stencil_tile<float, dev::OP_DEFECT, true, false>(
+        lv.bands32, lv.bs, lv.N, lv.n, lv.x32, lv.b32, nullptr, 0.0f, (int64_t)tile * TILE);
+    const double s = dev::block_sum(sq);
+    if (threadIdx.x == 0) P.partials[tile] = s;
+    END_ITEMS
+}
+
+// FP64 defect d = b - A x on the finest level with norm partials: two FP64
+// stencil tiles (512 rows each) per work item.
+__global__ __launch_bounds__(BLOCK) void kb_outer_defect(const BProb* __restrict__ probs,
+                                                         const BState* __restrict__ state,
+                                                         const int* __restrict__ wl, int mask) {
+    FOR_ITEMS(wl)
+    if (!(flags & mask)) continue;
+    const BLevel& lv = P.lv[P.L];
+    for (int sub = 0; sub < 2; ++sub) {
+        const int64_t blo = (int64_t)(2 * tile + sub) * dev::tile_rows<double>();
+        const double sq = dev::stencil_tile<double, dev::OP_DEFECT, true, true>(
+            lv.bands64, lv.bs, lv.N, lv.n, lv.x64, lv.b64, P.d64, 0.0, blo);
+        const double s = dev::block_sum(sq);
+        if (threadIdx.x == 0) P.partials[2 * tile + sub] = s;
+    }
+    END_ITEMS
+}
+
+// Sum-of-squares partials of b64 (which = 0) or of the scaled FP32 defect
+// (which = 1) on the finest level.
+__global__ __launch_bounds__(BLOCK) void kb_sumsq(const BProb* __restrict__ probs,
+                                                  const BState* __restrict__ state,
+                                                  const int* __restrict__ wl, int which,
+                                                  int mask) {
+    FOR_ITEMS(wl)
+    if (!(flags & mask)) continue;
+    const BLevel& lv = P.lv[P.L];
+    const int64_t base = (int64_t)tile * dev::NORM_TILE;
+    const double sq = which == 0 ? dev::sumsq_tile<double>(lv.b64, lv.n, base)
+                                 : dev::sumsq_tile<float>(lv.b32, lv.n, base);
+    const double s = dev::block_sum(sq);
+    if (threadIdx.x == 0) P.partials[tile] = s;
+    END_ITEMS
+}
+
+// d32 = float(d64 / s), the scaled defect, into the finest FP32 rhs.
+__global__ __launch_bounds__(BLOCK) void kb_cast(const BProb* __restrict__ probs,
+                                                 const BState* __restrict__ state,
+                                                 const int* __restrict__ wl, int mask) {
+    FOR_ITEMS(wl)
+    if (!(flags & mask)) continue;
+    const BLevel& lv = P.lv[P.L];
+    const double s = state[p].s;
+    const int64_t base = (int64_t)tile * TILE;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int64_t q = base + (int64_t)e * BLOCK + threadIdx.x;
+        if (q < lv.n) lv.b32[q] = s > 0.0 ? (float)(P.d64[q] / s) : 0.0f;
+    }
+    END_ITEMS
+}
+
+// x64 += s * double(c32).
+__global__ __launch_bounds__(BLOCK) void kb_update(const BProb* __restrict__ probs,
+                                                   const BState* __restrict__ state,
+                                                   const int* __restrict__ wl, int mask) {
+    FOR_ITEMS(wl)
+    if (!(flags & mask)) continue;
+    const BLevel& lv = P.lv[P.L];
+    const double s = state[p].s;
+    const int64_t base = (int64_t)tile * TILE;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int64_t q = base + (int64_t)e * BLOCK + threadIdx.x;
+        if (q < lv.n) lv.x64[q] += s * (double)lv.x32[q];
+    }
+    END_ITEMS
+}
+
+// Norm of one problem from its partials (fixed order), into a state field.
+__global__ __launch_bounds__(BLOCK) void kb_finalize(const BProb* __restrict__ probs,
+                                                     BState* __restrict__ state,
+                                                     const int* __restrict__ wl, int kind,
+                                                     int field, int mask) {
+    FOR_ITEMS(wl)
+    if (!(flags & mask)) continue;
+    const int64_t n = P.lv[P.L].n;
+    const int64_t np = kind == K_S64 ? (n + dev::tile_rows<double>() - 1) / dev::tile_rows<double>()
+                                     : (n + TILE - 1) / TILE;
+    const double s = dev::reduce_partials(P.partials, np);
+    if (threadIdx.x == 0) {
+        const double r = sqrt(s);
+        BState& S = state[p];
+        if (field == F_BN)
+            S.bn = r;
+        else if (field == F_S)
+            S.s = r;
+        else if (field == F_DN)
+            S.dn = r;
+        else
+            S.r32 = r;
+    }
+    END_ITEMS
+}
+
+// Per-problem transitions of the mixed scheme (one block; thread per slot).
+__global__ __launch_bounds__(BLOCK) void kb_ctrl(const BProb* __restrict__ probs,
+                                                 BState* __restrict__ state, int cap, int phase,
+                                                 int* __restrict__ active) {
+    int live = 0;
+    for (int p = threadIdx.x; p < cap; p += BLOCK) {
+        const BProb& P = probs[p];
+        if (P.L == 0) continue;
+        BState& S = state[p];
+        const int f = S.flags;
+        if (phase == PH_INIT && (f & BF_INIT)) {
+            if (!isfinite(S.bn)) {
+                S.status = MG_ERR_NUMERIC;
+                S.flags = BF_DONE;
+            } else if (S.bn == 0.0) {
+                S.status = MG_OK;
+                S.flags = BF_DONE;
+            } else {
+                S.flags = BF_OUTER;
+            }
+        } else if (phase == PH_UPDATE && (f & BF_UPDATE)) {
+            S.outer += 1;
+            S.flags = BF_OUTER;
+        } else if (phase == PH_OUTER && (f & BF_OUTER)) {
+            const int k = S.outer + 1;
+            const double rel = S.s / S.bn;
+            if (k > 1 && S.n_hist < MG_HIST) S.hist[S.n_hist++] = rel;
+            int done = 0;
+            if (!isfinite(S.s) || S.s > 1e3 * S.bn) {
+                S.status = MG_ERR_NUMERIC;
+                done = 1;
+            } else if (P.fixed > 0) {
+                done = k > P.fixed;
+            } else if (S.s <= P.rel_tol * S.bn) {
+                done = 1;
+            } else if (k > P.max_outer) {
+                S.status = MG_ERR_NOCONV;
+                done = 1;
+            }
+            if (!done && S.s == 0.0) done = 1;
+            S.flags = done ? BF_DONE : BF_CAST;
+        } else if (phase == PH_CAST && (f & BF_CAST)) {
+            S.first = 1;
+            S.it = 0;
+            S.flags = BF_INNER;
+        } else if (phase == PH_INNER && (f & BF_INNER)) {
+            S.it += 1;
+            S.cycles += 1;
+            S.first = 0;
+            if (!isfinite(S.r32) || S.r32 <= P.inner_reduction * S.dn || S.it >= P.inner_max)
+                S.flags = BF_UPDATE;
+        }
+        if (!(S.flags & BF_DONE)) ++live;
+    }
+    if (phase == PH_INNER) {
+        const double tot = dev::block_sum((double)live);
+        if (threadIdx.x == 0) *active = (int)tot;
+    }
+}
+
+}  // namespace
+
+BatchEngine::~BatchEngine() {
+    if (graph_) (void)hipGraphExecDestroy(graph_);
+    if (st_) (void)hipStreamDestroy(st_);
+    if (d_probs_) (void)hipFree(d_probs_);
+    if (d_state_) (void)hipFree(d_state_);
+    if (d_wl_) (void)hipFree(d_wl_);
+    if (d_active_) (void)hipFree(d_active_);
+    if (h_state_) (void)hipHostFree(h_state_);
+    if (h_active_) (void)hipHostFree(h_active_);
+}
+
+mg_status BatchEngine::init(int device, int capacity, int Lmax, int Lc, int nu_pre,
+                            int nu_post) {
+    if (capacity < 1 || capacity > 65536) return fail(MG_ERR_INVALID, "batch capacity out of range");
+    device_ = device;
+    cap_ = capacity;
+    Lmax_ = Lmax;
+    Lc_ = Lc;
+    nu_pre_ = nu_pre;
+    nu_post_ = nu_post;
+    MG_HIP(hipSetDevice(device));
+    MG_HIP(hipStreamCreateWithFlags(&st_, hipStreamNonBlocking));
+    MG_HIP(hipMalloc(&d_probs_, sizeof(BProb) * cap_));
+    MG_HIP(hipMalloc(&d_state_, sizeof(BState) * cap_));
+    MG_HIP(hipMalloc(&d_wl_, sizeof(int) * NLISTS * (3 + 2 * cap_)));
+    MG_HIP(hipMalloc(&d_active_, 64));
+    MG_HIP(hipHostMalloc((void**)&h_state_, sizeof(BState) * cap_, hipHostMallocDefault));
+    MG_HIP(hipHostMalloc((void**)&h_active_, 64, hipHostMallocDefault));
+    hp_.assign(cap_, BProb{});
+    started_.assign(cap_, 0);
+    std::memset(h_state_, 0, sizeof(BState) * cap_);
+    for (int s = 0; s < cap_; ++s) h_state_[s].flags = BF_DONE;
+    MG_HIP(hipMemcpy(d_state_, h_state_, sizeof(BState) * cap_, hipMemcpyHostToDevice));
+    probs_dirty_ = true;
+    return MG_OK;
+}
+
+void BatchEngine::set_slot(int s, mg_hierarchy* h, const mg_solve_opts& o) {
+    BProb P{};
+    for (int l = h->Lc; l <= h->L; ++l) {
+        const Level& v = h->lv[l];
+        BLevel& b = P.lv[l];
+        b.bands64 = v.bands64;
+        b.bands32 = v.bands32;
+        b.x64 = v.x64;
+        b.b64 = v.b64;
+        b.x32 = v.x32;
+        b.b32 = v.b32;
+        b.t32 = v.t32;
+        b.bs = v.bs;
+        b.n = v.n;
+        b.N = v.N;
+    }
+    P.d64 = h->d64;
+    P.partials = h->partials;
+    P.chol = h->chol;
+    P.m = h->m;
+    P.L = h->L;
+    P.omega = o.omega;
+    P.rel_tol = o.rel_tol;
+    P.inner_reduction = o.inner_reduction;
+    P.inner_max = o.inner_max_cycles;
+    P.max_outer = o.max_cycles;
+    P.fixed = o.fixed_cycles;
+    hp_[s] = P;
+    probs_dirty_ = true;
+}
+
+void BatchEngine::clear_slot(int s) {
+    hp_[s] = BProb{};
+    started_[s] = 0;
+    probs_dirty_ = true;
+}
+
+void BatchEngine::start_slot(int s) { started_[s] = 1; }
+
+// Work lists of the current composition.
+void BatchEngine::build_lists() {
+    const int stride = 3 + 2 * cap_;
+    h_wl_.assign((size_t)NLISTS * stride, 0);
+    auto fill = [&](int id, auto eligible, auto tiles) {
+        int* w = h_wl_.data() + (size_t)id * stride;
+        int count = 0, acc = 0;
+        int* prob = w + 2;
+        int* start = w + 2 + cap_;
+        for (int s = 0; s < cap_; ++s) {
+            if (hp_[s].L == 0 || !eligible(hp_[s])) continue;
+            prob[count] = s;
+            start[count] = acc;
+            acc += tiles(hp_[s]);
+            ++count;
+        }
+        start[count] = acc;
+        w[0] = count;
+        w[1] = cap_;
+    };
+    auto ntiles = [](int64_t n) { return (int)((n + TILE - 1) / TILE); };
+    for (int l = Lc_ + 1; l <= Lmax_; ++l) {
+        fill(wl_level(l), [&](const BProb& P) { return P.L >= l; },
+             [&](const BProb& P) { return ntiles(P.lv[l].n); });
+        fill(wl_restrict(l), [&](const BProb& P) { return P.L >= l; },
+             [&](const BProb& P) { return ntiles(P.lv[l - 1].n); });
+    }
+    fill(WL_FINEST, [](const BProb&) { return true; },
+         [&](const BProb& P) { return ntiles(P.lv[P.L].n); });
+    fill(WL_ALL, [](const BProb&) { return true; }, [](const BProb&) { return 1; });
+}
+
+mg_status BatchEngine::upload() {
+    MG_HIP(hipSetDevice(device_));
+    if (probs_dirty_) {
+        build_lists();
+        MG_HIP(hipMemcpyAsync(d_probs_, hp_.data(), sizeof(BProb) * cap_, hipMemcpyHostToDevice,
+                              st_));
+        MG_HIP(hipMemcpyAsync(d_wl_, h_wl_.data(), sizeof(int) * h_wl_.size(),
+                              hipMemcpyHostToDevice, st_));
+        probs_dirty_ = false;
+    }
+    for (int s = 0; s < cap_; ++s) {
+        if (!started_[s]) continue;
+        BState& S = h_state_[s];
+        std::memset(&S, 0, sizeof(BState));
+        S.flags = BF_INIT;
+        MG_HIP(hipMemcpyAsync(d_state_ + s, &S, sizeof(BState), hipMemcpyHostToDevice, st_));
+        started_[s] = 0;
+    }
+    // the pinned mirror is reused by read_states: wait for the copies
+    MG_HIP(hipStreamSynchronize(st_));
+    return MG_OK;
+}
+
+hipError_t BatchEngine::enqueue_iteration() {
+    const int stride = 3 + 2 * cap_;
+    auto W = [&](int id) { return (const int*)(d_wl_ + (size_t)id * stride); };
+    const dim3 G(STAGE_GRID), B(BLOCK), G1(1);
+    const dim3 GA(std::min(cap_, 1024));
+    BProb* P = d_probs_;
+    BState* S = d_state_;
+#define LAUNCH(...)                                        \
+    do {                                                   \
+        hipLaunchKernelGGL(__VA_ARGS__);                   \
+        hipError_t e_ = hipGetLastError();                 \
+        if (e_ != hipSuccess) return e_;                   \
+    } while (0)
+    // new problems: ||b||
+    LAUNCH(kb_sumsq, G, B, 0, st_, P, S, W(WL_FINEST), 0, (int)BF_INIT);
+    LAUNCH(kb_finalize, GA, B, 0, st_, P, S, W(WL_ALL), (int)K_NORM, (int)F_BN, (int)BF_INIT);
+    LAUNCH(kb_ctrl, G1, B, 0, st_, P, S, cap_, (int)PH_INIT, d_active_);
+    // finished inner loops: x += s c
+    LAUNCH(kb_update, G, B, 0, st_, P, S, W(WL_FINEST), (int)BF_UPDATE);
+    LAUNCH(kb_ctrl, G1, B, 0, st_, P, S, cap_, (int)PH_UPDATE, d_active_);
+    // FP64 defect, norm and stop test
+    LAUNCH(kb_outer_defect, G, B, 0, st_, P, S, W(WL_FINEST), (int)BF_OUTER);
+    LAUNCH(kb_finalize, GA, B, 0, st_, P, S, W(WL_ALL), (int)K_S64, (int)F_S, (int)BF_OUTER);
+    LAUNCH(kb_ctrl, G1, B, 0, st_, P, S, cap_, (int)PH_OUTER, d_active_);
+    // scaled FP32 defect and its norm
+    LAUNCH(kb_cast, G, B, 0, st_, P, S, W(WL_FINEST), (int)BF_CAST);
+    LAUNCH(kb_sumsq, G, B, 0, st_, P, S, W(WL_FINEST), 1, (int)BF_CAST);
+    LAUNCH(kb_finalize, GA, B, 0, st_, P, S, W(WL_ALL), (int)K_NORM, (int)F_DN, (int)BF_CAST);
+    LAUNCH(kb_ctrl, G1, B, 0, st_, P, S, cap_, (int)PH_CAST, d_active_);
+    // one FP32 V-cycle for every problem in its inner loop (roles: 0 = x, 1 = t)
+    const int m = BF_INNER;
+    int cur = 0, oth = 1;
+    for (int l = Lmax_; l > Lc_; --l) {
+        cur = 0;
+        oth = 1;
+        if (nu_pre_ == 0) LAUNCH(kb_fill_cond, G, B, 0, st_, P, S, W(wl_level(l)), l, cur, m);
+        for (int k = 0; k < nu_pre_; ++k) {
+            if (k == 0)
+                LAUNCH(kb_pre1, G, B, 0, st_, P, S, W(wl_level(l)), l, cur, oth, m);
+            else
+                LAUNCH(kb_band<dev::OP_JACOBI>, G, B, 0, st_, P, S, W(wl_level(l)), l, cur, oth, m);
+            std::swap(cur, oth);
+        }
+        LAUNCH(kb_band<dev::OP_DEFECT>, G, B, 0, st_, P, S, W(wl_level(l)), l, cur, oth, m);
+        LAUNCH(kb_restrict, G, B, 0, st_, P, S, W(wl_restrict(l)), l, oth, m);
+    }
+    LAUNCH(kb_coarse, GA, B, 0, st_, P, S, W(WL_ALL), Lc_, m);
+    const int after_pre = nu_pre_ % 2;  // role holding the iterate after pre-smoothing
+    for (int l = Lc_ + 1; l <= Lmax_; ++l) {
+        cur = after_pre;
+        oth = 1 - cur;
+        LAUNCH(kb_prolong, G, B, 0, st_, P, S, W(wl_level(l)), l, cur, m);
+        for (int k = 0; k < nu_post_; ++k) {
+            LAUNCH(kb_band<dev::OP_JACOBI>, G, B, 0, st_, P, S, W(wl_level(l)), l, cur, oth, m);
+            std::swap(cur, oth);
+        }
+        if (cur != 0) LAUNCH(kb_copy, G, B, 0, st_, P, S, W(wl_level(l)), l, cur, 0, m);
+    }
+    // inner residual and stop test
+    LAUNCH(kb_inner_norm, G, B, 0, st_, P, S, W(WL_FINEST), m);
+    LAUNCH(kb_finalize, GA, B, 0, st_, P, S, W(WL_ALL), (int)K_S32, (int)F_R32, m);
+    LAUNCH(kb_ctrl, G1, B, 0, st_, P, S, cap_, (int)PH_INNER, d_active_);
+#undef LAUNCH
+    return hipSuccess;
+}
+
+mg_status BatchEngine::step(int* active_left) {
+    MG_HIP(hipSetDevice(device_));
+    if (!graph_) {
+        hipGraph_t g = nullptr;
+        MG_HIP(hipStreamBeginCapture(st_, hipStreamCaptureModeThreadLocal));
+        hipError_t e = enqueue_iteration();
+        hipError_t e2 = hipStreamEndCapture(st_, &g);
+        if (e == hipSuccess) e = e2;
+        if (e == hipSuccess) e = hipGraphInstantiate(&graph_, g, nullptr, nullptr, 0);
+        if (g) (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            graph_ = nullptr;
+            return fail(MG_ERR_DEVICE, std::string("batch graph capture: ") + hipGetErrorString(e));
+        }
+    }
+    MG_HIP(hipGraphLaunch(graph_, st_));
+    MG_HIP(hipMemcpyAsync(h_active_, d_active_, sizeof(int), hipMemcpyDeviceToHost, st_));
+    MG_HIP(hipStreamSynchronize(st_));
+    if (active_left) *active_left = h_active_[0];
+    return MG_OK;
+}
+
+mg_status BatchEngine::read_states() {
+    MG_HIP(hipSetDevice(device_));
+    MG_HIP(hipMemcpyAsync(h_state_, d_state_, sizeof(BState) * cap_, hipMemcpyDeviceToHost, st_));
+    MG_HIP(hipStreamSynchronize(st_));
+    return MG_OK;
+}
+
+}  // namespace mg
+
+// ---------------------------------------------------------------- C ABI
+
+namespace mg {
+
+// Algorithmic bytes of one FP32 V-cycle of a level-L problem (same byte
+// model as the single-problem driver; the finest first sweep counted full).
+double vcycle_bytes32(int L, int Lc, int nu_pre, int nu_post) {
+    auto n = [](int l) { return (double)(((int64_t(1) << l) + 1) * ((int64_t(1) << l) + 1)); };
+    double b = 8.0 * n(Lc);
+    for (int l = Lc + 1; l <= L; ++l) {
+        const double sweeps = (double)(nu_pre + nu_post) * 48.0 * n(l);
+        const double zero_saving = (l < L && nu_pre > 0) ? 36.0 * n(l) : 0.0;
+        b += sweeps - zero_saving + 48.0 * n(l) + 4.0 * (n(l) + n(l - 1)) +
+             4.0 * (n(l - 1) + 2.0 * n(l));
+    }
+    return b;
+}
+
+double mixed_solve_bytes(int L, int Lc, int nu_pre, int nu_post, const BState& S) {
+    const double n = (double)(((int64_t(1) << L) + 1) * ((int64_t(1) << L) + 1));
+    const int outer_defects = S.outer + 1;
+    return 8.0 * n + outer_defects * 96.0 * n + S.outer * (12.0 + 4.0 + 20.0) * n +
+           S.cycles * (vcycle_bytes32(L, Lc, nu_pre, nu_post) + 44.0 * n);
+}
+
+void fill_stats(const BState& S, int L, int Lc, int nu_pre, int nu_post, mg_stats* st) {
+    mg_stats o{};
+    o.status = (mg_status)S.status;
+    o.cycles = S.cycles;
+    o.outer_steps = S.outer;
+    o.bnorm = S.bn;
+    o.rel_res = S.bn > 0.0 ? S.s / S.bn : 0.0;
+    o.n_hist = S.n_hist;
+    for (int k = 0; k < S.n_hist && k < MG_HIST; ++k) o.res_hist[k] = S.hist[k];
+    o.alg_bytes = mixed_solve_bytes(L, Lc, nu_pre, nu_post, S);
+    *st = o;
+}
+
+}  // namespace mg
+
+using namespace mg;
+
+extern "C" mg_status mg_solve_batch(mg_hierarchy* const* hs, const double* const* b,
+                                    double* const* x, int count, const mg_solve_opts* opts,
+                                    void* stream, mg_stats* stats) {
+    if (!hs || !b || !x || count < 1) return fail(MG_ERR_INVALID, "empty or null batch");
+    mg_solve_opts def;
+    mg_default_opts(&def);
+    def.precision = MG_PREC_MIXED;
+    const mg_solve_opts& o0 = opts ? opts[0] : def;
+    int Lmax = 0;
+    for (int p = 0; p < count; ++p) {
+        const mg_hierarchy* h = hs[p];
+        const mg_solve_opts& o = opts ? opts[p] : def;
+        if (!h || !h->assembled) return fail(MG_ERR_INVALID, "null or unassembled hierarchy");
+        if (h->ctx->device != hs[0]->ctx->device || h->Lc != hs[0]->Lc)
+            return fail(MG_ERR_INVALID, "batch problems must share device and coarse level");
+        for (int q = 0; q < p; ++q)
+            if (hs[q] == h) return fail(MG_ERR_INVALID, "a hierarchy appears twice in the batch");
+        if (!b[p] || !x[p] || b[p] == x[p] || ((uintptr_t)b[p] & 15) || ((uintptr_t)x[p] & 15))
+            return fail(MG_ERR_INVALID, "b, x must be distinct 16-byte aligned device pointers");
+        if (o.precision != MG_PREC_MIXED)
+            return fail(MG_ERR_INVALID, "the batched solver runs the mixed-precision scheme");
+        if (o.nu_pre != o0.nu_pre || o.nu_post != o0.nu_post)
+            return fail(MG_ERR_INVALID, "smoothing counts must agree across the batch");
+        if (o.nu_pre < 0 || o.nu_post < 0 || o.nu_pre + o.nu_post == 0 || o.nu_pre > 16 ||
+            o.nu_post > 16 || !(o.omega > 0.0 && o.omega < 2.0) || !(o.rel_tol >= 0.0) ||
+            o.max_cycles < 1 || o.inner_max_cycles < 1 ||
+            !(o.inner_reduction >= 0.0 && o.inner_reduction < 1.0) || o.fixed_cycles < 0)
+            return fail(MG_ERR_INVALID, "invalid solver options");
+        Lmax = std::max(Lmax, h->L);
+    }
+    MG_HIP(hipSetDevice(hs[0]->ctx->device));
+    BatchEngine eng;
+    if (mg_status s = eng.init(hs[0]->ctx->device, count, Lmax, hs[0]->Lc, o0.nu_pre, o0.nu_post))
+        return s;
+    MG_HIP(hipStreamSynchronize((hipStream_t)stream));
+    int64_t iter_cap = 8;
+    for (int p = 0; p < count; ++p) {
+        mg_hierarchy* h = hs[p];
+        const Level& F = h->lv[h->L];
+        MG_HIP(launch_copy<double>(b[p], F.b64, F.n, eng.stream()));
+        MG_HIP(launch_copy<double>(x[p], F.x64, F.n, eng.stream()));
+        const mg_solve_opts& o = opts ? opts[p] : def;
+        eng.set_slot(p, h, o);
+        eng.start_slot(p);
+        const int outer = o.fixed_cycles > 0 ? o.fixed_cycles : o.max_cycles;
+        iter_cap = std::max<int64_t>(iter_cap, (int64_t)(outer + 1) * (o.inner_max_cycles + 1) + 4);
+    }
+    if (mg_status s = eng.upload()) return s;
+    int active = count;
+    for (int64_t it = 0; it < iter_cap && active > 0; ++it)
+        if (mg_status s = eng.step(&active)) return s;
+    if (mg_status s = eng.read_states()) return s;
+    mg_status worst = MG_OK;
+    for (int p = 0; p < count; ++p) {
+        mg_hierarchy* h = hs[p];
+        const Level& F = h->lv[h->L];
+        const BState& S = eng.state(p);
+        if (S.bn == 0.0 && S.status == MG_OK)
+            MG_HIP(launch_fill<double>(x[p], F.n, 0.0, eng.stream()));
+        else
+            MG_HIP(launch_copy<double>(F.x64, x[p], F.n, eng.stream()));
+        if (stats) fill_stats(S, h->L, h->Lc, o0.nu_pre, o0.nu_post, &stats[p]);
+        if (!(S.flags & BF_DONE)) {
+            if (stats) stats[p].status = MG_ERR_NOCONV;
+            worst = MG_ERR_NOCONV;
+        } else if (S.status != MG_OK && worst == MG_OK) {
+            worst = (mg_status)S.status;
+        }
+    }
+    MG_HIP(hipStreamSynchronize(eng.stream()));
+    if (worst != MG_OK) return fail(worst, "at least one problem of the batch did not converge");
+    return MG_OK;
+}

@@ -1,0 +1,244 @@
+// Device arithmetic of the hot path, per tile or per element.  The
+// single-problem kernels (kernels.hip) and the batched persistent kernels
+// (batch.hip) call exactly these functions with the same tiling, so a
+// problem's results do not depend on which other problems share a launch.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace mg {
+namespace dev {
+
+constexpr int BLOCK = 256;
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
+template <typename T>
+struct V16;
+template <>
+struct V16<float> {
+    typedef f32x4 type;
+    static constexpr int W = 4;
+};
+template <>
+struct V16<double> {
+    typedef f64x2 type;
+    static constexpr int W = 2;
+};
+
+// Rows per stencil tile: 16 bytes of every band per thread.
+template <typename T>
+constexpr int tile_rows() {
+    return BLOCK * V16<T>::W;
+}
+
+// Elements per reduction tile of a plain vector norm.
+constexpr int NORM_TILE = BLOCK * 4;
+
+// Deterministic block sum (wave shuffles, then the waves in order); the
+// result is valid in thread 0.  Every thread of the block must call it; it
+// may be called repeatedly in a loop.
+__device__ __forceinline__ double block_sum(double v) {
+    __shared__ double ws[BLOCK / 64];
+    __syncthreads();
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int w = 0; w < BLOCK / 64; ++w) s += ws[w];
+    }
+    return s;
+}
+
+enum { OP_SPMV = 0, OP_DEFECT = 1, OP_JACOBI = 2 };
+
+// One stencil tile: rows [blo, blo + tile_rows) of y = A x (SPMV),
+// d = b - A x (DEFECT) or x' = x + omega (b - A x) / a_pp (JACOBI).  Each
+// thread owns W consecutive rows.  Tiles at least N+1 rows away from both
+// ends of the vector read the x halo without bounds checks.  Returns the
+// thread's sum of squares of its outputs when NORM.
+template <typename T, int OP, bool NORM, bool STORE>
+__device__ __forceinline__ double stencil_tile(const T* __restrict__ bands, int64_t bs, int N,
+                                               int64_t n, const T* __restrict__ x,
+                                               const T* __restrict__ b, T* __restrict__ out,
+                                               T omega, int64_t blo) {
+    constexpr int W = V16<T>::W;
+    typedef typename V16<T>::type VT;
+    const int64_t p0 = blo + (int64_t)threadIdx.x * W;
+    const bool fast = (blo - N - 1 >= 0) && (blo + tile_rows<T>() + N + 1 <= n);
+    double sq = 0.0;
+    if (p0 >= n) return sq;
+    T xv[3][W + 2];
+    if (fast) {
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            const T* xp = x + p0 + (int64_t)(r - 1) * N - 1;
+#pragma unroll
+            for (int e = 0; e < W + 2; ++e) xv[r][e] = xp[e];
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+#pragma unroll
+            for (int e = 0; e < W + 2; ++e) {
+                const int64_t q = p0 + (int64_t)(r - 1) * N - 1 + e;
+                xv[r][e] = (q >= 0 && q < n) ? x[q] : T(0);
+            }
+        }
+    }
+    T bk[9][W];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        // band arrays are padded beyond n, so the vector load stays in bounds
+        VT v = __builtin_nontemporal_load(reinterpret_cast<const VT*>(bands + k * bs + p0));
+        __builtin_memcpy(bk[k], &v, sizeof(VT));
+    }
+    T res[W];
+#pragma unroll
+    for (int v = 0; v < W; ++v) {
+        T acc = T(0);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) acc = fma(bk[k][v], xv[k / 3][v + k % 3], acc);
+        res[v] = acc;
+    }
+    if (OP != OP_SPMV) {
+        T bb[W];
+        if (fast) {
+            VT v = *reinterpret_cast<const VT*>(b + p0);
+            __builtin_memcpy(bb, &v, sizeof(VT));
+        } else {
+#pragma unroll
+            for (int v = 0; v < W; ++v) bb[v] = (p0 + v < n) ? b[p0 + v] : T(0);
+        }
+#pragma unroll
+        for (int v = 0; v < W; ++v) {
+            if (OP == OP_DEFECT)
+                res[v] = bb[v] - res[v];
+            else
+                res[v] = xv[1][v + 1] + omega * (bb[v] - res[v]) / bk[4][v];
+        }
+    }
+    if (NORM) {
+#pragma unroll
+        for (int v = 0; v < W; ++v)
+            if (p0 + v < n) sq += (double)res[v] * (double)res[v];
+    }
+    if (STORE) {
+        if (fast) {
+            VT v;
+            __builtin_memcpy(&v, res, sizeof(VT));
+            *reinterpret_cast<VT*>(out + p0) = v;
+        } else {
+#pragma unroll
+            for (int v = 0; v < W; ++v)
+                if (p0 + v < n) out[p0 + v] = res[v];
+        }
+    }
+    return sq;
+}
+
+// Damped Jacobi sweep from a zero iterate: x' = omega b / a_pp.
+template <typename T>
+__device__ __forceinline__ void jacobi_zero_elem(const T* __restrict__ diag,
+                                                 const T* __restrict__ b, T* __restrict__ xo,
+                                                 int64_t p, T omega) {
+    xo[p] = omega * b[p] / diag[p];
+}
+
+// b_c(I,J) = P^T d_f: weights 1 (centre), 1/2 (edges), 1/4 (corners) over the
+// 3x3 fine neighbourhood of (2I, 2J); zero on the coarse boundary.
+template <typename T>
+__device__ __forceinline__ void restrict_elem(int Nf, const T* __restrict__ d,
+                                              T* __restrict__ bc, int I, int J) {
+    const int Nc = (Nf >> 1) + 1;
+    T s = T(0);
+    if (I > 0 && J > 0 && I < Nc - 1 && J < Nc - 1) {
+        const T* c = d + (int64_t)(2 * J) * Nf + 2 * I;
+        const T* u = c - Nf;
+        const T* o = c + Nf;
+        const T corner = (u[-1] + u[1]) + (o[-1] + o[1]);
+        const T edge = (u[0] + o[0]) + (c[-1] + c[1]);
+        s = c[0] + T(0.5) * edge + T(0.25) * corner;
+    }
+    bc[(int64_t)J * Nc + I] = s;
+}
+
+// x_f(i,j) += bilinear interpolation (index space) of x_c at fine node (i,j).
+template <typename T>
+__device__ __forceinline__ void prolong_elem(int Nf, const T* __restrict__ xc,
+                                             T* __restrict__ xf, int i, int j) {
+    const int Nc = (Nf >> 1) + 1;
+    const int I = i >> 1, J = j >> 1;
+    const T* c = xc + (int64_t)J * Nc + I;
+    T v;
+    if (!(i & 1) && !(j & 1))
+        v = c[0];
+    else if (!(j & 1))
+        v = T(0.5) * (c[0] + c[1]);
+    else if (!(i & 1))
+        v = T(0.5) * (c[0] + c[Nc]);
+    else
+        v = T(0.25) * ((c[0] + c[1]) + (c[Nc] + c[Nc + 1]));
+    xf[(int64_t)j * Nf + i] += v;
+}
+
+// Coarsest level, one block: boundary rows are identity rows; the interior
+// block is solved in FP64 with its Cholesky factor (at most 49 unknowns).
+template <typename T>
+__device__ __forceinline__ void coarse_block(const double* __restrict__ chol, int m, int Nc,
+                                             const T* __restrict__ b, T* __restrict__ x) {
+    __shared__ double z[64];
+    const int mi = Nc - 2;
+    __syncthreads();
+    for (int p = threadIdx.x; p < Nc * Nc; p += blockDim.x) {
+        const int i = p % Nc, j = p / Nc;
+        if (i == 0 || j == 0 || i == Nc - 1 || j == Nc - 1) x[p] = b[p];
+    }
+    if (threadIdx.x == 0) {
+        for (int r = 0; r < m; ++r) {
+            const int i = 1 + r % mi, j = 1 + r / mi;
+            double s = (double)b[j * Nc + i];
+            for (int k = 0; k < r; ++k) s -= chol[r * m + k] * z[k];
+            z[r] = s / chol[r * m + r];
+        }
+        for (int r = m - 1; r >= 0; --r) {
+            double s = z[r];
+            for (int k = r + 1; k < m; ++k) s -= chol[k * m + r] * z[k];
+            z[r] = s / chol[r * m + r];
+        }
+        for (int r = 0; r < m; ++r) {
+            const int i = 1 + r % mi, j = 1 + r / mi;
+            x[j * Nc + i] = (T)z[r];
+        }
+    }
+    __syncthreads();
+}
+
+// Sum of squares of one norm tile (elements base + e*BLOCK + tid, e < 4).
+template <typename T>
+__device__ __forceinline__ double sumsq_tile(const T* __restrict__ v, int64_t n, int64_t base) {
+    double s = 0.0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int64_t p = base + (int64_t)e * BLOCK + threadIdx.x;
+        if (p < n) s += (double)v[p] * (double)v[p];
+    }
+    return s;
+}
+
+// Fixed-order sum of np partials (one block); valid in thread 0.
+__device__ __forceinline__ double reduce_partials(const double* __restrict__ partials,
+                                                  int64_t np) {
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < np; i += BLOCK) s += partials[i];
+    return block_sum(s);
+}
+
+}  // namespace dev
+}  // namespace mg

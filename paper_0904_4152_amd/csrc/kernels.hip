@@ -11,13 +11,17 @@
 // grid (its L2 then sees the row reuse of x).
 #include <cmath>
 
+#include "device_ops.h"
 #include "mg_internal.h"
 
 namespace mg {
 
 namespace {
 
-constexpr int BLOCK = 256;
+using dev::BLOCK;
+using dev::OP_DEFECT;
+using dev::OP_JACOBI;
+using dev::OP_SPMV;
 
 // Hardware dispatches consecutive workgroups round-robin over the 8 XCDs.
 // Renumber so that XCD k processes the k-th contiguous eighth of the grid;
@@ -31,128 +35,19 @@ __device__ __forceinline__ int64_t xcd_block(int64_t nblk) {
 
 inline unsigned grid8(int64_t nblk) { return (unsigned)((nblk + 7) / 8 * 8); }
 
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef double f64x2 __attribute__((ext_vector_type(2)));
-
-template <typename T>
-struct V16;
-template <>
-struct V16<float> {
-    typedef f32x4 type;
-    static constexpr int W = 4;
-};
-template <>
-struct V16<double> {
-    typedef f64x2 type;
-    static constexpr int W = 2;
-};
-
-// Deterministic block sum (wave shuffles, then waves in order); valid in
-// thread 0.  Every thread of the block must call it.
-__device__ __forceinline__ double block_sum(double v) {
-    __shared__ double ws[BLOCK / 64];
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = v;
-    __syncthreads();
-    double s = 0.0;
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int w = 0; w < BLOCK / 64; ++w) s += ws[w];
-    }
-    return s;
-}
-
-enum { OP_SPMV = 0, OP_DEFECT = 1, OP_JACOBI = 2 };
-
-// One thread: W consecutive rows p0..p0+W-1 of the band product.  `fast`
-// blocks lie at least N+1 rows away from both ends of the vector, so the x
-// halo needs no bounds checks there.
+// One tile per workgroup of the band product family (see dev::stencil_tile).
 template <typename T, int OP, bool NORM, bool STORE>
 __global__ __launch_bounds__(BLOCK) void k_stencil(const T* __restrict__ bands, int64_t bs,
                                                    int N, int64_t n, const T* __restrict__ x,
                                                    const T* __restrict__ b,
                                                    T* __restrict__ out, T omega,
                                                    double* __restrict__ partials, int64_t nblk) {
-    constexpr int W = V16<T>::W;
-    typedef typename V16<T>::type VT;
     const int64_t lb = xcd_block(nblk);
     if (lb < 0) return;
-    const int64_t blo = lb * (int64_t)(BLOCK * W);
-    const int64_t p0 = blo + (int64_t)threadIdx.x * W;
-    const bool fast = (blo - N - 1 >= 0) && (blo + BLOCK * W + N + 1 <= n);
-    double sq = 0.0;
-    if (p0 < n) {
-        T xv[3][W + 2];
-        if (fast) {
-#pragma unroll
-            for (int r = 0; r < 3; ++r) {
-                const T* xp = x + p0 + (int64_t)(r - 1) * N - 1;
-#pragma unroll
-                for (int e = 0; e < W + 2; ++e) xv[r][e] = xp[e];
-            }
-        } else {
-#pragma unroll
-            for (int r = 0; r < 3; ++r) {
-#pragma unroll
-                for (int e = 0; e < W + 2; ++e) {
-                    const int64_t q = p0 + (int64_t)(r - 1) * N - 1 + e;
-                    xv[r][e] = (q >= 0 && q < n) ? x[q] : T(0);
-                }
-            }
-        }
-        T bk[9][W];
-#pragma unroll
-        for (int k = 0; k < 9; ++k) {
-            // band arrays are padded beyond n, so the vector load is in bounds
-            VT v = __builtin_nontemporal_load(reinterpret_cast<const VT*>(bands + k * bs + p0));
-            __builtin_memcpy(bk[k], &v, sizeof(VT));
-        }
-        T res[W];
-#pragma unroll
-        for (int v = 0; v < W; ++v) {
-            T acc = T(0);
-#pragma unroll
-            for (int k = 0; k < 9; ++k) acc = fma(bk[k][v], xv[k / 3][v + k % 3], acc);
-            res[v] = acc;
-        }
-        if (OP != OP_SPMV) {
-            T bb[W];
-            if (fast) {
-                VT v = *reinterpret_cast<const VT*>(b + p0);
-                __builtin_memcpy(bb, &v, sizeof(VT));
-            } else {
-#pragma unroll
-                for (int v = 0; v < W; ++v) bb[v] = (p0 + v < n) ? b[p0 + v] : T(0);
-            }
-#pragma unroll
-            for (int v = 0; v < W; ++v) {
-                if (OP == OP_DEFECT) {
-                    res[v] = bb[v] - res[v];
-                } else {
-                    res[v] = xv[1][v + 1] + omega * (bb[v] - res[v]) / bk[4][v];
-                }
-            }
-        }
-        if (NORM) {
-#pragma unroll
-            for (int v = 0; v < W; ++v)
-                if (p0 + v < n) sq += (double)res[v] * (double)res[v];
-        }
-        if (STORE) {
-            if (fast) {
-                VT v;
-                __builtin_memcpy(&v, res, sizeof(VT));
-                *reinterpret_cast<VT*>(out + p0) = v;
-            } else {
-#pragma unroll
-                for (int v = 0; v < W; ++v)
-                    if (p0 + v < n) out[p0 + v] = res[v];
-            }
-        }
-    }
+    const double sq = dev::stencil_tile<T, OP, NORM, STORE>(
+        bands, bs, N, n, x, b, out, omega, lb * (int64_t)dev::tile_rows<T>());
     if (NORM) {
-        const double s = block_sum(sq);
+        const double s = dev::block_sum(sq);
         if (threadIdx.x == 0) partials[lb] = s;
     }
 }
@@ -160,9 +55,7 @@ __global__ __launch_bounds__(BLOCK) void k_stencil(const T* __restrict__ bands, 
 __global__ __launch_bounds__(BLOCK) void k_reduce_final(const double* __restrict__ partials,
                                                         int64_t np, double* __restrict__ scal,
                                                         int slot) {
-    double s = 0.0;
-    for (int64_t i = threadIdx.x; i < np; i += BLOCK) s += partials[i];
-    s = block_sum(s);
+    const double s = dev::reduce_partials(partials, np);
     if (threadIdx.x == 0) {
         scal[slot] = s;
         scal[slot + 1] = sqrt(s);
@@ -174,82 +67,28 @@ __global__ __launch_bounds__(BLOCK) void k_jacobi_zero(const T* __restrict__ dia
                                                        const T* __restrict__ b,
                                                        T* __restrict__ xo, int64_t n, T omega) {
     const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    if (p < n) xo[p] = omega * b[p] / diag[p];
+    if (p < n) dev::jacobi_zero_elem(diag, b, xo, p, omega);
 }
 
-// b_c(I,J) = sum over the 3x3 fine neighbourhood of (2I,2J) with weights
-// 1 (centre), 1/2 (edge), 1/4 (corner): the transpose of bilinear
-// interpolation; zero on the coarse boundary.
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_restrict(int Nf, const T* __restrict__ d,
                                                     T* __restrict__ bc) {
     const int Nc = (Nf >> 1) + 1;
     const int I = blockIdx.x * BLOCK + threadIdx.x;
-    const int J = blockIdx.y;
-    if (I >= Nc) return;
-    T s = T(0);
-    if (I > 0 && J > 0 && I < Nc - 1 && J < Nc - 1) {
-        const T* c = d + (int64_t)(2 * J) * Nf + 2 * I;
-        const T* u = c - Nf;
-        const T* o = c + Nf;
-        const T corner = (u[-1] + u[1]) + (o[-1] + o[1]);
-        const T edge = (u[0] + o[0]) + (c[-1] + c[1]);
-        s = c[0] + T(0.5) * edge + T(0.25) * corner;
-    }
-    bc[(int64_t)J * Nc + I] = s;
+    if (I < Nc) dev::restrict_elem(Nf, d, bc, I, (int)blockIdx.y);
 }
 
-// x_f(i,j) += bilinear interpolation of x_c at fine node (i,j).
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_prolong(int Nf, const T* __restrict__ xc,
                                                    T* __restrict__ xf) {
-    const int Nc = (Nf >> 1) + 1;
     const int i = blockIdx.x * BLOCK + threadIdx.x;
-    const int j = blockIdx.y;
-    if (i >= Nf) return;
-    const int I = i >> 1, J = j >> 1;
-    const T* c = xc + (int64_t)J * Nc + I;
-    T v;
-    if (!(i & 1) && !(j & 1)) {
-        v = c[0];
-    } else if (!(j & 1)) {
-        v = T(0.5) * (c[0] + c[1]);
-    } else if (!(i & 1)) {
-        v = T(0.5) * (c[0] + c[Nc]);
-    } else {
-        v = T(0.25) * ((c[0] + c[1]) + (c[Nc] + c[Nc + 1]));
-    }
-    xf[(int64_t)j * Nf + i] += v;
+    if (i < Nf) dev::prolong_elem(Nf, xc, xf, i, (int)blockIdx.y);
 }
 
-// Coarsest level: boundary rows are identity rows, the interior block is
-// solved with its Cholesky factor (FP64 whatever T is).
 template <typename T>
 __global__ void k_coarse(const double* __restrict__ chol, int m, int Nc,
                          const T* __restrict__ b, T* __restrict__ x) {
-    __shared__ double z[64];
-    const int mi = Nc - 2;
-    for (int p = threadIdx.x; p < Nc * Nc; p += blockDim.x) {
-        const int i = p % Nc, j = p / Nc;
-        if (i == 0 || j == 0 || i == Nc - 1 || j == Nc - 1) x[p] = b[p];
-    }
-    if (threadIdx.x == 0) {
-        for (int r = 0; r < m; ++r) {
-            const int i = 1 + r % mi, j = 1 + r / mi;
-            double s = (double)b[j * Nc + i];
-            for (int k = 0; k < r; ++k) s -= chol[r * m + k] * z[k];
-            z[r] = s / chol[r * m + r];
-        }
-        for (int r = m - 1; r >= 0; --r) {
-            double s = z[r];
-            for (int k = r + 1; k < m; ++k) s -= chol[k * m + r] * z[k];
-            z[r] = s / chol[r * m + r];
-        }
-        for (int r = 0; r < m; ++r) {
-            const int i = 1 + r % mi, j = 1 + r / mi;
-            x[j * Nc + i] = (T)z[r];
-        }
-    }
+    dev::coarse_block(chol, m, Nc, b, x);
 }
 
 // Dense interior block of the coarsest operator and its Cholesky factor
@@ -507,14 +346,7 @@ __global__ __launch_bounds__(BLOCK) void k_sumsq(const T* __restrict__ v, int64_
                                                  double* __restrict__ partials, int64_t nblk) {
     const int64_t lb = xcd_block(nblk);
     if (lb < 0) return;
-    double s = 0.0;
-    const int64_t base = lb * (int64_t)(BLOCK * 4);
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        const int64_t p = base + (int64_t)e * BLOCK + threadIdx.x;
-        if (p < n) s += (double)v[p] * (double)v[p];
-    }
-    s = block_sum(s);
+    const double s = dev::block_sum(dev::sumsq_tile(v, n, lb * (int64_t)dev::NORM_TILE));
     if (threadIdx.x == 0) partials[lb] = s;
 }
 
@@ -549,6 +381,8 @@ int64_t stencil_blocks(int64_t n, int elem_bytes) {
     const int64_t per = (int64_t)BLOCK * (16 / elem_bytes);
     return (n + per - 1) / per;
 }
+
+int64_t norm_blocks(int64_t n) { return (n + dev::NORM_TILE - 1) / dev::NORM_TILE; }
 
 hipError_t launch_coords(double* xy, int L, double jitter, uint64_t seed, hipStream_t st) {
     const int N = (1 << L) + 1;
@@ -652,7 +486,7 @@ hipError_t launch_copy(const T* src, T* dst, int64_t n, hipStream_t st) {
 template <typename T>
 hipError_t launch_norm(const T* v, int64_t n, double* partials, double* scal, int slot,
                        hipStream_t st) {
-    const int64_t nb = (n + BLOCK * 4 - 1) / (BLOCK * 4);
+    const int64_t nb = norm_blocks(n);
     hipLaunchKernelGGL(k_sumsq<T>, dim3(grid8(nb)), dim3(BLOCK), 0, st, v, n, partials, nb);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -131,6 +131,8 @@ hipError_t launch_cast_scaled(const double* d64, float* d32, int64_t n, const do
 hipError_t launch_update(double* x, const float* c32, int64_t n, const double* scal, int slot,
                          hipStream_t st);
 
+// Workgroups (= tiles) of a band-product launch and of a vector-norm launch.
 int64_t stencil_blocks(int64_t n, int elem_bytes);
+int64_t norm_blocks(int64_t n);
 
 }  // namespace mg

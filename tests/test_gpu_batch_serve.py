@@ -1,0 +1,179 @@
+"""Batched solves and the serving loop on the device.
+
+A problem's arithmetic is the same whichever other problems share the
+launches (same per-tile device functions, per-problem reductions in a fixed
+order, stop decisions per problem), so its result must be bit-identical
+alone, in a batch, in the server's live mix and in the single-problem solver.
+Convergence is checked independently with the CPU oracle's operator.
+"""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def mg():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_0904_4152_amd as mg
+    mg.lib()
+    return mg
+
+
+@pytest.fixture(scope="module")
+def ctx(mg):
+    return mg.Context(0)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def make_problems(mg, ctx, levels, seed0=4100):
+    probs = []
+    amps = synth.batch_jitter(len(levels), 0.25, 4005)
+    for k, L in enumerate(levels):
+        h = mg.Hierarchy(ctx, int(L), jitter=float(amps[k]), seed=seed0 + k)
+        b = torch.empty(h.n, dtype=torch.float64, device="cuda")
+        h.rhs_uniform(4200 + k, b)
+        probs.append((h, b, float(amps[k]), seed0 + k))
+    return probs
+
+
+LEVELS = [5, 2, 8, 3, 7, 6, 4, 8, 1, 6]
+
+
+def test_batch_equals_single_solver_bitwise(mg, ctx):
+    probs = make_problems(mg, ctx, LEVELS)
+    opts = mg.default_opts(precision=mg.MG_PREC_MIXED, rel_tol=1e-8)
+    xs = [torch.zeros_like(b) for _, b, _, _ in probs]
+    stats = mg.solve_batch([p[0] for p in probs], [p[1] for p in probs], xs, opts)
+    for k, (h, b, _, _) in enumerate(probs):
+        x1 = torch.zeros_like(b)
+        s1 = h.solve(b, x1, opts)
+        assert stats[k].status == 0 and stats[k].rel_res <= 1e-8
+        assert (stats[k].cycles, stats[k].outer_steps) == (s1.cycles, s1.outer_steps)
+        np.testing.assert_array_equal(host(xs[k]), host(x1))
+        assert stats[k].rel_res == s1.rel_res
+
+
+def test_batch_alone_equals_in_the_mix(mg, ctx):
+    probs = make_problems(mg, ctx, LEVELS, seed0=900)
+    opts = mg.default_opts(precision=mg.MG_PREC_MIXED, rel_tol=1e-10)
+    xs = [torch.zeros_like(b) for _, b, _, _ in probs]
+    mg.solve_batch([p[0] for p in probs], [p[1] for p in probs], xs, opts)
+    for k in (0, 2, 8):
+        h, b, _, _ = probs[k]
+        x1 = torch.zeros_like(b)
+        st = mg.solve_batch([h], [b], [x1], opts)
+        np.testing.assert_array_equal(host(xs[k]), host(x1))
+        assert st[0].status == 0
+
+
+def test_batch_per_problem_tolerances_checked_by_oracle(mg, ctx, orc):
+    levels = [6, 7, 5, 8]
+    tols = [1e-6, 1e-8, 1e-10, 1e-8]
+    probs = make_problems(mg, ctx, levels, seed0=300)
+    opts = [mg.default_opts(precision=mg.MG_PREC_MIXED, rel_tol=t) for t in tols]
+    xs = [torch.zeros_like(b) for _, b, _, _ in probs]
+    stats = mg.solve_batch([p[0] for p in probs], [p[1] for p in probs], xs, opts)
+    for k, (h, b, a, gs) in enumerate(probs):
+        L = levels[k]
+        N = (1 << L) + 1
+        bands = orc.assemble(N, synth.coords(L, a, gs))
+        bh = host(b)
+        bref = synth.rhs_uniform(L, 4200 + k)
+        np.testing.assert_array_equal(bh, bref)  # device RHS generator = host generator
+        r = orc.norm2(orc.defect(N, bands, bh, host(xs[k]))) / orc.norm2(bh)
+        assert stats[k].status == 0
+        assert r <= 1.05 * tols[k], (k, r, tols[k])
+
+
+def test_batch_of_config_shape(mg, ctx):
+    """Levels drawn from {5..9} (seed 4004), jitter U[0, 0.25) per problem:
+    every problem reaches 1e-8."""
+    levels = synth.batch_levels(48, 5, 9, 4004)
+    probs = make_problems(mg, ctx, levels)
+    opts = mg.default_opts(precision=mg.MG_PREC_MIXED, rel_tol=1e-8)
+    xs = [torch.zeros_like(b) for _, b, _, _ in probs]
+    stats = mg.solve_batch([p[0] for p in probs], [p[1] for p in probs], xs, opts)
+    for s in stats:
+        assert s.status == 0 and s.rel_res <= 1e-8
+        assert 3 <= s.outer_steps <= 6
+
+
+def test_batch_errors(mg, ctx):
+    probs = make_problems(mg, ctx, [4, 5])
+    xs = [torch.zeros_like(b) for _, b, _, _ in probs]
+    with pytest.raises(mg.MgError) as e:
+        mg.solve_batch([p[0] for p in probs], [p[1] for p in probs], xs,
+                       mg.default_opts(precision=mg.MG_PREC_FP64))
+    assert e.value.status == mg.MG_ERR_INVALID
+    with pytest.raises(mg.MgError) as e:
+        mg.solve_batch([probs[0][0], probs[0][0]], [probs[0][1]] * 2, xs,
+                       mg.default_opts(precision=mg.MG_PREC_MIXED))
+    assert e.value.status == mg.MG_ERR_INVALID
+
+
+def test_server_result_same_alone_and_in_the_mix(mg, ctx):
+    """Requests that overlap on the device (more requests than slots, so they
+    are admitted as slots free up) give bit-identical results to the same
+    problem solved alone."""
+    srv = mg.Server(ctx, slots=4, budget_bytes=8 << 30, max_level=9)
+    reqs = []
+    rng = np.random.default_rng(5)
+    for r in range(10):
+        L = int(rng.integers(4, 10))
+        tol = [1e-6, 1e-8, 1e-10][r % 3]
+        a = float(rng.uniform(0, 0.25))
+        t = srv.submit(L, tol, a, 5100 + r, 5200 + r, keep_x=True)
+        reqs.append((t, L, tol, a, 5100 + r, 5200 + r))
+    results = {}
+    for t, L, *_ in reqs:
+        while True:
+            rc, st, x = srv.poll(t, n=((1 << L) + 1) ** 2)
+            if rc != mg.MG_ERR_BUSY:
+                break
+            import time
+            time.sleep(0.002)
+        results[t] = (rc, st, x)
+    info = srv.info()
+    srv.close()
+    assert info.completed == 10
+    for t, L, tol, a, gs, rs in reqs:
+        rc, st, x = results[t]
+        assert rc == 0 and st.rel_res <= tol
+        assert st.seconds >= st.queue_seconds >= 0.0
+        h = mg.Hierarchy(ctx, L, jitter=a, seed=gs)
+        b = torch.empty(h.n, dtype=torch.float64, device="cuda")
+        h.rhs_uniform(rs, b)
+        x1 = torch.zeros_like(b)
+        s1 = mg.solve_batch([h], [b], [x1], mg.default_opts(precision=mg.MG_PREC_MIXED,
+                                                            rel_tol=tol))
+        np.testing.assert_array_equal(x, host(x1))
+        assert (st.cycles, st.outer_steps) == (s1[0].cycles, s1[0].outer_steps)
+
+
+def test_server_budget_admission(mg, ctx):
+    one = mg.Hierarchy.bytes_needed(9)
+    srv = mg.Server(ctx, slots=8, budget_bytes=int(one * 1.5), max_level=9)
+    with pytest.raises(mg.MgError) as e:  # can never fit: rejected at submission
+        mg.Server(ctx, slots=1, budget_bytes=one // 2, max_level=9).submit(9, 1e-8, 0.1, 1, 2)
+    assert e.value.status == mg.MG_ERR_NOMEM
+    tickets = [srv.submit(9, 1e-8, 0.1, 10 + k, 20 + k) for k in range(4)]
+    got = []
+    while len(got) < 4:
+        r = srv.next(timeout=5.0)
+        assert r is not None
+        got.append(r)
+    info = srv.info()
+    srv.close()
+    assert sorted(t for t, _, _ in got) == sorted(tickets)
+    assert all(rc == 0 for _, rc, _ in got)
+    assert info.bytes_high_water <= int(one * 1.5)
