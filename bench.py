@@ -19,6 +19,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -35,6 +37,12 @@ def parse():
     ap.add_argument("--kernel-iters", type=int, default=50)
     ap.add_argument("--only-kernels", action="store_true",
                     help="time the band kernels only (for profiler runs)")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serve-rate", type=float, default=2000.0)
+    ap.add_argument("--serve-count", type=int, default=2000)
+    ap.add_argument("--serve-warmup", type=int, default=400)
+    ap.add_argument("--serve-slots", type=int, default=64)
     return ap.parse_args()
 
 
@@ -77,13 +85,123 @@ def time_launches(fn, iters, torch):
     return e0.elapsed_time(e1) * 1e-3 / iters
 
 
+def bench_batch(mg, ctx, synth, torch, dev, opts, count=256):
+    """256 independent mixed solves advanced together (one persistent launch
+    per V-cycle stage), against the same problems solved one after another."""
+    levels = synth.batch_levels(count, 5, 9, 4004)
+    amps = synth.batch_jitter(count, 0.25, 4005)
+    hs, bs, xs = [], [], []
+    for p in range(count):
+        h = mg.Hierarchy(ctx, int(levels[p]), jitter=float(amps[p]), seed=4100 + p)
+        b = torch.empty(h.n, dtype=torch.float64, device=dev)
+        h.rhs_uniform(4200 + p, b)
+        hs.append(h)
+        bs.append(b)
+        xs.append(torch.zeros_like(b))
+    mg.solve_batch(hs, bs, xs, opts)  # warm-up (graph capture)
+    reps = 3
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for x in xs:
+            x.zero_()
+        stats = mg.solve_batch(hs, bs, xs, opts)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    ok = all(s.status == 0 and s.rel_res <= opts.rel_tol for s in stats)
+    alg = sum(s.alg_bytes for s in stats)
+    t0 = time.perf_counter()
+    for h, b, x in zip(hs, bs, xs):
+        x.zero_()
+        h.solve(b, x, opts)
+    torch.cuda.synchronize()
+    dt_seq = time.perf_counter() - t0
+    rec = {"problems": count, "unknowns": int(sum(h.n for h in hs)),
+           "levels": {int(L): int((levels == L).sum()) for L in range(5, 10)},
+           "ms": dt * 1e3, "solves_s": count / dt, "all_reached_tol": ok,
+           "alg_GB_s": alg / dt / 1e9, "sequential_ms": dt_seq * 1e3,
+           "speedup_vs_sequential": dt_seq / dt,
+           "mean_outer": float(np.mean([s.outer_steps for s in stats])),
+           "mean_inner": float(np.mean([s.cycles for s in stats]))}
+    for h in hs:
+        h.close()
+    return rec
+
+
+def serve_once(mg, ctx, synth, rate, n_warm, n_meas, slots, budget):
+    import threading
+    srv = mg.Server(ctx, slots=slots, budget_bytes=budget, max_level=11,
+                    opts=mg.default_opts(precision=mg.MG_PREC_MIXED))
+    total = n_warm + n_meas
+    req = synth.serving_requests(total, rate, 5005)
+    lat = {}
+    failures = []
+
+    def collect():
+        got = 0
+        while got < total:
+            r = srv.next(timeout=30.0)
+            if r is None:
+                failures.append("timeout")
+                return
+            t, rc, st = r
+            if rc != 0:
+                failures.append(rc)
+            lat[t] = (st.seconds, st.queue_seconds, st.cycles, st.outer_steps)
+            got += 1
+
+    th = threading.Thread(target=collect)
+    th.start()
+    tickets = []
+    start = time.perf_counter()
+    t_first_meas = None
+    for r in range(total):
+        due = start + req["t"][r]
+        now = time.perf_counter()
+        if due > now:
+            time.sleep(due - now)
+        if r == n_warm:
+            t_first_meas = time.perf_counter()
+        tickets.append(srv.submit(int(req["L"][r]), float(req["tol"][r]),
+                                  float(req["jitter"][r]), int(req["geom_seed"][r]),
+                                  int(req["rhs_seed"][r])))
+    t_last_submit = time.perf_counter()
+    th.join()
+    t_end = time.perf_counter()
+    info = srv.info()
+    srv.close()
+    meas = [lat[t] for t in tickets[n_warm:] if t in lat]
+    ls = np.array([m[0] for m in meas]) * 1e3
+    qs = np.array([m[1] for m in meas]) * 1e3
+    dur = t_end - t_first_meas
+    return {"offered_req_s": rate,
+            "submitted_req_s": n_meas / max(t_last_submit - t_first_meas, 1e-9),
+            "achieved_solves_s": n_meas / dur, "requests": n_meas, "warmup": n_warm,
+            "slots": slots, "budget_GB": budget / 1e9,
+            "p50_ms": float(np.percentile(ls, 50)), "p90_ms": float(np.percentile(ls, 90)),
+            "p99_ms": float(np.percentile(ls, 99)), "mean_queue_ms": float(qs.mean()),
+            "mean_service_ms": float((ls - qs).mean()),
+            "hbm_high_water_GB": info.bytes_high_water / 1e9,
+            "queue_high_water": int(info.queue_high_water), "failures": len(failures)}
+
+
+def bench_serving(mg, ctx, synth, args):
+    budget = 200 * 10 ** 9
+    rec = {"headline": serve_once(mg, ctx, synth, args.serve_rate, args.serve_warmup,
+                                  args.serve_count, args.serve_slots, budget)}
+    sweep = []
+    for rate in (250, 500, 1000):
+        sweep.append(serve_once(mg, ctx, synth, rate, 100, 400, args.serve_slots, budget))
+    rec["sweep"] = sweep
+    return rec
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build measures one GPU only (each problem and each solve "
               "runs on a single MI355X); --gpus must be 1", file=sys.stderr)
         sys.exit(2)
-    import numpy as np
     import torch
 
     import paper_0904_4152_amd as mg
@@ -208,6 +326,14 @@ def main():
         out[name] = rec
         hh.close()
 
+    # ---------------- batched: 256 problems, L ~ U{5..9}, jitter U[0, 0.25) h
+    if not args.no_batch:
+        out["batch256"] = bench_batch(mg, ctx, synth, torch, dev, mixed)
+        torch.cuda.empty_cache()
+    # ---------------- serving: Poisson arrivals, P(L) ~ 1/L on 6..11
+    if not args.no_serving:
+        out["serving"] = bench_serving(mg, ctx, synth, args)
+
     # ---------------- oracle on the host CPU (bounded sample)
     cpu = None
     if not args.no_cpu_baseline:
@@ -247,6 +373,8 @@ def main():
                      "traffic": traffic_from_profiles("jacobi_fp32")},
         "cpu_baseline": cpu,
     }
+    if "serving" in out:
+        line["serving_p99_ms"] = out["serving"]["headline"]["p99_ms"]
     line.update(out)
     print(json.dumps(line))
 

@@ -98,3 +98,22 @@ def batch_levels(count: int, lo: int, hi: int, seed: int) -> np.ndarray:
 def batch_jitter(count: int, amax: float, seed: int) -> np.ndarray:
     """Per-problem jitter amplitudes drawn uniformly from [0, amax)."""
     return uniform(seed, np.arange(count, dtype=np.uint64)) * amax
+
+
+def serving_requests(count: int, rate: float, seed: int, lo: int = 6, hi: int = 11,
+                     tols=(1e-6, 1e-8, 1e-10), amax: float = 0.25):
+    """Open-loop request stream: exponential inter-arrival times at `rate`
+    per second (draws 4r), levels with P(L) proportional to 1/L on lo..hi
+    (draws 4r+1), tolerances uniform over `tols` (draws 4r+2), jitter
+    amplitudes uniform in [0, amax) (draws 4r+3); request r uses grid seed
+    5100 + r and right-hand-side seed 5200 + r."""
+    r = np.arange(count, dtype=np.uint64)
+    u = [uniform(seed, np.uint64(4) * r + np.uint64(c)) for c in range(4)]
+    gaps = -np.log1p(-u[0]) / rate
+    levels = np.arange(lo, hi + 1)
+    w = 1.0 / levels
+    cdf = np.cumsum(w) / w.sum()
+    L = levels[np.minimum(np.searchsorted(cdf, u[1], side="right"), len(levels) - 1)]
+    tol = np.asarray(tols)[np.minimum((u[2] * len(tols)).astype(np.int64), len(tols) - 1)]
+    return {"t": np.cumsum(gaps), "L": L.astype(np.int64), "tol": tol, "jitter": u[3] * amax,
+            "geom_seed": 5100 + r.astype(np.int64), "rhs_seed": 5200 + r.astype(np.int64)}
