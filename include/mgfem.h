@@ -239,9 +239,11 @@ mg_status mg_prolong(const mg_hierarchy* h, int fine_level, mg_dtype dtype, cons
 mg_status mg_coarse_solve(const mg_hierarchy* h, mg_dtype dtype, const void* b, void* x,
                           void* stream);
 /* One V(nu_pre, nu_post) cycle at `level` in place on x (levels below use the
- * hierarchy's own work vectors). */
+ * hierarchy's own work vectors).  fused != 0 (V(2,2) only) runs each level
+ * as two fused passes (two sweeps + defect + restriction; prolongation + two
+ * sweeps) with bit-identical results to the unfused sequence of kernels. */
 mg_status mg_vcycle(mg_hierarchy* h, int level, mg_dtype dtype, const void* b, void* x,
-                    int nu_pre, int nu_post, double omega, void* stream);
+                    int nu_pre, int nu_post, double omega, int fused, void* stream);
 
 #ifdef __cplusplus
 }

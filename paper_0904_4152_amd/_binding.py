@@ -73,7 +73,7 @@ _SIGS = {
     "mg_restrict": (_i, [_vp, _i, _i, _vp, _vp, _vp]),
     "mg_prolong": (_i, [_vp, _i, _i, _vp, _vp, _vp]),
     "mg_coarse_solve": (_i, [_vp, _i, _vp, _vp, _vp]),
-    "mg_vcycle": (_i, [_vp, _i, _i, _vp, _vp, _i, _i, _d, _vp]),
+    "mg_vcycle": (_i, [_vp, _i, _i, _vp, _vp, _i, _i, _d, _i, _vp]),
     "mg_server_create": (_i, [_vp, _i, _sz, _i, _i, ctypes.POINTER(SolveOpts),
                               ctypes.POINTER(_vp)]),
     "mg_server_submit": (_i, [_vp, _i, _d, _d, _u64, _u64, _i, ctypes.POINTER(_u64)]),
@@ -285,9 +285,11 @@ class Hierarchy:
     def coarse_solve(self, b, x, stream=None):
         check(lib().mg_coarse_solve(self._h, _dt(x), _ptr(b), _ptr(x), _stream(stream)))
 
-    def vcycle(self, level, b, x, nu_pre=2, nu_post=2, omega=0.7, stream=None):
+    def vcycle(self, level, b, x, nu_pre=2, nu_post=2, omega=0.7, fused=None, stream=None):
+        if fused is None:
+            fused = nu_pre == 2 and nu_post == 2
         check(lib().mg_vcycle(self._h, level, _dt(x), _ptr(b), _ptr(x), nu_pre, nu_post, omega,
-                              _stream(stream)))
+                              int(fused), _stream(stream)))
 
 
 def solve_batch(hierarchies, bs, xs, opts=None, stream=None, raise_on_error=True):

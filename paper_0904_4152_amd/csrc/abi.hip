@@ -25,6 +25,14 @@ int64_t vec_len(int64_t n) { return (n + 63) / 64 * 64; }
 
 int64_t band_stride(int64_t n) { return (n + 1023) / 1024 * 1024 + 64; }
 
+// Partial sums a reduction on the finest level of a level-L hierarchy can
+// produce: FP64 band-product tiles or fused tiles (at least 4 rows each).
+static int64_t max_partials(int L) {
+    const int64_t N = (int64_t(1) << L) + 1;
+    const int64_t fused = ((N + dev_fused_cols() - 1) / dev_fused_cols()) * ((N + 3) / 4);
+    return std::max(stencil_blocks(N * N, 8), fused);
+}
+
 // Bytes of every device array of a hierarchy, in allocation order.
 static void hierarchy_arrays(int L, int Lc, std::vector<size_t>& sizes) {
     const int64_t nL = ((int64_t(1) << L) + 1) * ((int64_t(1) << L) + 1);
@@ -38,7 +46,7 @@ static void hierarchy_arrays(int L, int Lc, std::vector<size_t>& sizes) {
         for (int v = 0; v < 3; ++v) sizes.push_back(vl * sizeof(float));
     }
     sizes.push_back(vec_len(nL) * sizeof(double));                    // d64
-    sizes.push_back((stencil_blocks(nL, 8) + 64) * sizeof(double));   // partials
+    sizes.push_back((max_partials(L) + 64) * sizeof(double));           // partials
     sizes.push_back(64 * sizeof(double));                             // scal
     const int mi = (1 << Lc) - 1;
     sizes.push_back(std::max<size_t>(1, (size_t)mi * mi * mi * mi) * sizeof(double));  // chol
@@ -226,7 +234,7 @@ mg_status mg_hierarchy_create(mg_context* ctx, int L, int Lc, double jitter, uin
     }
     h->d64 = (double*)ptrs[a++];
     h->partials = (double*)ptrs[a++];
-    h->n_partials = stencil_blocks(h->lv[L].n, 8) + 64;
+    h->n_partials = max_partials(L) + 64;
     h->scal = (double*)ptrs[a++];
     h->chol = (double*)ptrs[a++];
     h->flag = (int*)ptrs[a++];

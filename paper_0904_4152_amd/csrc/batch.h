@@ -21,7 +21,9 @@ struct BLevel {
     int64_t bs;
     int64_t n;
     int N;
-    int pad;
+    int rh;        // owned rows per fused tile
+    int nstrips;   // fused tiles: nstrips x nchunks
+    int nchunks;
 };
 
 struct BProb {

@@ -18,6 +18,7 @@
 
 #include "batch.h"
 #include "device_ops.h"
+#include "fused_ops.h"
 
 namespace mg {
 
@@ -25,11 +26,12 @@ namespace {
 
 using dev::BLOCK;
 
-constexpr int NLISTS = 34;
+constexpr int NLISTS = 50;
 constexpr int WL_FINEST = 32;
 constexpr int WL_ALL = 33;
 inline int wl_level(int l) { return l; }
 inline int wl_restrict(int l) { return 16 + l; }
+inline int wl_fused(int l) { return 34 + l; }
 
 constexpr int STAGE_GRID = 2048;
 constexpr int TILE = 1024;  // elements per work item (one FP32 stencil tile)
@@ -186,23 +188,94 @@ __global__ __launch_bounds__(BLOCK) void kb_copy(const BProb* __restrict__ probs
     END_ITEMS
 }
 
-// Coarsest level of every problem (one block per problem).
+// Coarse tail of every problem above the coarse level (one block each): the
+// sub-cycle over levels min(L - 1, TAIL_MAX) .. Lc.
+__global__ __launch_bounds__(BLOCK) void kb_tail(const BProb* __restrict__ probs,
+                                                 const BState* __restrict__ state,
+                                                 const int* __restrict__ wl, int Lc, int mask) {
+    FOR_ITEMS(wl)
+    if (!(flags & mask) || P.L <= Lc) continue;
+    dev::TailLevels<float> tl;
+    const int top = min(P.L - 1, dev::TAIL_MAX);
+    for (int l = Lc; l <= top; ++l) {
+        const BLevel& v = P.lv[l];
+        tl.lv[l] = dev::TailLevel<float>{v.bands32, v.x32, v.b32, v.t32, v.bs, v.n, v.N, 0};
+    }
+    tl.chol = P.chol;
+    tl.m = P.m;
+    tl.top = top;
+    tl.Lc = Lc;
+    dev::tail_cycle<float>(tl, (float)P.omega);
+    END_ITEMS
+}
+
+// Coarsest level (one block per problem); with only_level >= 0 only for the
+// problems whose finest level is only_level.
 __global__ __launch_bounds__(BLOCK) void kb_coarse(const BProb* __restrict__ probs,
                                                    const BState* __restrict__ state,
-                                                   const int* __restrict__ wl, int Lc, int mask) {
+                                                   const int* __restrict__ wl, int Lc, int mask,
+                                                   int only_level) {
     FOR_ITEMS(wl)
     if (!(flags & mask)) continue;
+    if (only_level >= 0 && P.L != only_level) continue;
     const BLevel& lv = P.lv[Lc];
     dev::coarse_block<float>(P.chol, P.m, lv.N, lv.b32, lv.x32);
     END_ITEMS
 }
 
-// FP32 residual norm of the inner iterate on the finest level (partials).
-__global__ __launch_bounds__(BLOCK) void kb_inner_norm(const BProb* __restrict__ probs,
-                                                       const BState* __restrict__ state,
-                                                       const int* __restrict__ wl, int mask) {
+// Fused pre-smoothing pass at level l (two sweeps, defect, restriction) for
+// the problems in their inner loop; iterate x -> t, coarse rhs at l-1.
+__global__ __launch_bounds__(dev::F_THREADS) void kb_fpre(const BProb* __restrict__ probs,
+                                                          const BState* __restrict__ state,
+                                                          const int* __restrict__ wl, int l,
+                                                          int mask) {
     FOR_ITEMS(wl)
     if (!(flags & mask)) continue;
+    const BLevel& lv = P.lv[l];
+    const int strip = tile % lv.nstrips, chunk = tile / lv.nstrips;
+    const float om = (float)P.omega;
+    if (l < P.L || state[p].first)
+        dev::pre_tile<float, true>(lv.bands32, lv.bs, lv.N, lv.x32, lv.b32, om, lv.t32,
+                                   P.lv[l - 1].b32, strip, chunk, lv.rh);
+    else
+        dev::pre_tile<float, false>(lv.bands32, lv.bs, lv.N, lv.x32, lv.b32, om, lv.t32,
+                                    P.lv[l - 1].b32, strip, chunk, lv.rh);
+    END_ITEMS
+}
+
+// Fused post-smoothing pass at level l (prolongation, two sweeps: t -> x);
+// on the problem's finest level also the residual-norm partials.
+__global__ __launch_bounds__(dev::F_THREADS) void kb_fpost(const BProb* __restrict__ probs,
+                                                           const BState* __restrict__ state,
+                                                           const int* __restrict__ wl, int l,
+                                                           int mask) {
+    FOR_ITEMS(wl)
+    if (!(flags & mask)) continue;
+    const BLevel& lv = P.lv[l];
+    const int strip = tile % lv.nstrips, chunk = tile / lv.nstrips;
+    const float om = (float)P.omega;
+    if (l == P.L) {
+        const double sq = dev::post_tile<float, true>(lv.bands32, lv.bs, lv.N, lv.t32,
+                                                      P.lv[l - 1].x32, lv.b32, om, lv.x32, strip,
+                                                      chunk, lv.rh);
+        const double s = dev::block_sum(sq);
+        if (threadIdx.x == 0) P.partials[tile] = s;
+    } else {
+        dev::post_tile<float, false>(lv.bands32, lv.bs, lv.N, lv.t32, P.lv[l - 1].x32, lv.b32, om,
+                                     lv.x32, strip, chunk, lv.rh);
+    }
+    END_ITEMS
+}
+
+// FP32 residual norm of the inner iterate on the finest level (partials);
+// with only_level >= 0 only for problems whose finest level is only_level.
+__global__ __launch_bounds__(BLOCK) void kb_inner_norm(const BProb* __restrict__ probs,
+                                                       const BState* __restrict__ state,
+                                                       const int* __restrict__ wl, int mask,
+                                                       int only_level) {
+    FOR_ITEMS(wl)
+    if (!(flags & mask)) continue;
+    if (only_level >= 0 && P.L != only_level) continue;
     const BLevel& lv = P.lv[P.L];
     const double sq = dev::stencil_tile<float, dev::OP_DEFECT, true, false>(
         lv.bands32, lv.bs, lv.N, lv.n, lv.x32, lv.b32, nullptr, 0.0f, (int64_t)tile * TILE);
@@ -284,12 +357,16 @@ __global__ __launch_bounds__(BLOCK) void kb_update(const BProb* __restrict__ pro
 __global__ __launch_bounds__(BLOCK) void kb_finalize(const BProb* __restrict__ probs,
                                                      BState* __restrict__ state,
                                                      const int* __restrict__ wl, int kind,
-                                                     int field, int mask) {
+                                                     int field, int mask, int fused_above) {
     FOR_ITEMS(wl)
     if (!(flags & mask)) continue;
-    const int64_t n = P.lv[P.L].n;
-    const int64_t np = kind == K_S64 ? (n + dev::tile_rows<double>() - 1) / dev::tile_rows<double>()
-                                     : (n + TILE - 1) / TILE;
+    const BLevel& F = P.lv[P.L];
+    const int64_t n = F.n;
+    int64_t np = kind == K_S64 ? (n + dev::tile_rows<double>() - 1) / dev::tile_rows<double>()
+                               : (n + TILE - 1) / TILE;
+    // the inner residual comes from the fused post pass above the coarse level
+    if (kind == K_S32 && fused_above >= 0 && P.L > fused_above)
+        np = (int64_t)F.nstrips * F.nchunks;
     const double s = dev::reduce_partials(P.partials, np);
     if (threadIdx.x == 0) {
         const double r = sqrt(s);
@@ -420,6 +497,10 @@ void BatchEngine::set_slot(int s, mg_hierarchy* h, const mg_solve_opts& o) {
         b.bs = v.bs;
         b.n = v.n;
         b.N = v.N;
+        const dev::FusedGeom g = dev::fused_geom(v.N, fused_rows(v.N));
+        b.rh = g.rh;
+        b.nstrips = g.nstrips;
+        b.nchunks = g.nchunks;
     }
     P.d64 = h->d64;
     P.partials = h->partials;
@@ -470,6 +551,11 @@ void BatchEngine::build_lists() {
              [&](const BProb& P) { return ntiles(P.lv[l].n); });
         fill(wl_restrict(l), [&](const BProb& P) { return P.L >= l; },
              [&](const BProb& P) { return ntiles(P.lv[l - 1].n); });
+        // fused passes run above the coarse tail: on levels > TAIL_MAX and on
+        // the problem's finest level
+        fill(wl_fused(l),
+             [&](const BProb& P) { return P.L >= l && (l > dev::TAIL_MAX || l == P.L); },
+             [&](const BProb& P) { return P.lv[l].nstrips * P.lv[l].nchunks; });
     }
     fill(WL_FINEST, [](const BProb&) { return true; },
          [&](const BProb& P) { return ntiles(P.lv[P.L].n); });
@@ -514,22 +600,38 @@ hipError_t BatchEngine::enqueue_iteration() {
     } while (0)
     // new problems: ||b||
     LAUNCH(kb_sumsq, G, B, 0, st_, P, S, W(WL_FINEST), 0, (int)BF_INIT);
-    LAUNCH(kb_finalize, GA, B, 0, st_, P, S, W(WL_ALL), (int)K_NORM, (int)F_BN, (int)BF_INIT);
+    LAUNCH(kb_finalize, GA, B, 0, st_, P, S, W(WL_ALL), (int)K_NORM, (int)F_BN, (int)BF_INIT, -1);
     LAUNCH(kb_ctrl, G1, B, 0, st_, P, S, cap_, (int)PH_INIT, d_active_);
     // finished inner loops: x += s c
     LAUNCH(kb_update, G, B, 0, st_, P, S, W(WL_FINEST), (int)BF_UPDATE);
     LAUNCH(kb_ctrl, G1, B, 0, st_, P, S, cap_, (int)PH_UPDATE, d_active_);
     // FP64 defect, norm and stop test
     LAUNCH(kb_outer_defect, G, B, 0, st_, P, S, W(WL_FINEST), (int)BF_OUTER);
-    LAUNCH(kb_finalize, GA, B, 0, st_, P, S, W(WL_ALL), (int)K_S64, (int)F_S, (int)BF_OUTER);
+    LAUNCH(kb_finalize, GA, B, 0, st_, P, S, W(WL_ALL), (int)K_S64, (int)F_S, (int)BF_OUTER, -1);
     LAUNCH(kb_ctrl, G1, B, 0, st_, P, S, cap_, (int)PH_OUTER, d_active_);
     // scaled FP32 defect and its norm
     LAUNCH(kb_cast, G, B, 0, st_, P, S, W(WL_FINEST), (int)BF_CAST);
     LAUNCH(kb_sumsq, G, B, 0, st_, P, S, W(WL_FINEST), 1, (int)BF_CAST);
-    LAUNCH(kb_finalize, GA, B, 0, st_, P, S, W(WL_ALL), (int)K_NORM, (int)F_DN, (int)BF_CAST);
+    LAUNCH(kb_finalize, GA, B, 0, st_, P, S, W(WL_ALL), (int)K_NORM, (int)F_DN, (int)BF_CAST, -1);
     LAUNCH(kb_ctrl, G1, B, 0, st_, P, S, cap_, (int)PH_CAST, d_active_);
-    // one FP32 V-cycle for every problem in its inner loop (roles: 0 = x, 1 = t)
+    // one FP32 V-cycle for every problem in its inner loop
     const int m = BF_INNER;
+    const bool fused = nu_pre_ == 2 && nu_post_ == 2;
+    if (fused) {
+        const dim3 GF(STAGE_GRID), BF(dev::F_THREADS);
+        for (int l = Lmax_; l > Lc_; --l)
+            LAUNCH(kb_fpre, GF, BF, 0, st_, P, S, W(wl_fused(l)), l, m);
+        LAUNCH(kb_tail, GA, B, 0, st_, P, S, W(WL_ALL), Lc_, m);
+        LAUNCH(kb_coarse, GA, B, 0, st_, P, S, W(WL_ALL), Lc_, m, Lc_);
+        for (int l = Lc_ + 1; l <= Lmax_; ++l)
+            LAUNCH(kb_fpost, GF, BF, 0, st_, P, S, W(wl_fused(l)), l, m);
+        // problems without a level above the coarse one: residual from a defect pass
+        LAUNCH(kb_inner_norm, G, B, 0, st_, P, S, W(WL_FINEST), m, Lc_);
+        LAUNCH(kb_finalize, GA, B, 0, st_, P, S, W(WL_ALL), (int)K_S32, (int)F_R32, m, Lc_);
+        LAUNCH(kb_ctrl, G1, B, 0, st_, P, S, cap_, (int)PH_INNER, d_active_);
+        return hipSuccess;
+    }
+    // roles of the unfused cycle: 0 = x, 1 = t
     int cur = 0, oth = 1;
     for (int l = Lmax_; l > Lc_; --l) {
         cur = 0;
@@ -545,7 +647,7 @@ hipError_t BatchEngine::enqueue_iteration() {
         LAUNCH(kb_band<dev::OP_DEFECT>, G, B, 0, st_, P, S, W(wl_level(l)), l, cur, oth, m);
         LAUNCH(kb_restrict, G, B, 0, st_, P, S, W(wl_restrict(l)), l, oth, m);
     }
-    LAUNCH(kb_coarse, GA, B, 0, st_, P, S, W(WL_ALL), Lc_, m);
+    LAUNCH(kb_coarse, GA, B, 0, st_, P, S, W(WL_ALL), Lc_, m, -1);
     const int after_pre = nu_pre_ % 2;  // role holding the iterate after pre-smoothing
     for (int l = Lc_ + 1; l <= Lmax_; ++l) {
         cur = after_pre;
@@ -558,8 +660,8 @@ hipError_t BatchEngine::enqueue_iteration() {
         if (cur != 0) LAUNCH(kb_copy, G, B, 0, st_, P, S, W(wl_level(l)), l, cur, 0, m);
     }
     // inner residual and stop test
-    LAUNCH(kb_inner_norm, G, B, 0, st_, P, S, W(WL_FINEST), m);
-    LAUNCH(kb_finalize, GA, B, 0, st_, P, S, W(WL_ALL), (int)K_S32, (int)F_R32, m);
+    LAUNCH(kb_inner_norm, G, B, 0, st_, P, S, W(WL_FINEST), m, -1);
+    LAUNCH(kb_finalize, GA, B, 0, st_, P, S, W(WL_ALL), (int)K_S32, (int)F_R32, m, -1);
     LAUNCH(kb_ctrl, G1, B, 0, st_, P, S, cap_, (int)PH_INNER, d_active_);
 #undef LAUNCH
     return hipSuccess;
@@ -605,6 +707,11 @@ namespace mg {
 double vcycle_bytes32(int L, int Lc, int nu_pre, int nu_post) {
     auto n = [](int l) { return (double)(((int64_t(1) << l) + 1) * ((int64_t(1) << l) + 1)); };
     double b = 8.0 * n(Lc);
+    if (nu_pre == 2 && nu_post == 2) {
+        for (int l = Lc + 1; l <= L; ++l)
+            b += (l < L ? 11.0 : 12.0) * 4.0 * n(l) + 12.0 * 4.0 * n(l) + 8.0 * n(l - 1);
+        return b;
+    }
     for (int l = Lc + 1; l <= L; ++l) {
         const double sweeps = (double)(nu_pre + nu_post) * 48.0 * n(l);
         const double zero_saving = (l < L && nu_pre > 0) ? 36.0 * n(l) : 0.0;
@@ -617,8 +724,9 @@ double vcycle_bytes32(int L, int Lc, int nu_pre, int nu_post) {
 double mixed_solve_bytes(int L, int Lc, int nu_pre, int nu_post, const BState& S) {
     const double n = (double)(((int64_t(1) << L) + 1) * ((int64_t(1) << L) + 1));
     const int outer_defects = S.outer + 1;
+    const double norm_pass = (nu_pre == 2 && nu_post == 2 && L > Lc) ? 0.0 : 44.0 * n;
     return 8.0 * n + outer_defects * 96.0 * n + S.outer * (12.0 + 4.0 + 20.0) * n +
-           S.cycles * (vcycle_bytes32(L, Lc, nu_pre, nu_post) + 44.0 * n);
+           S.cycles * (vcycle_bytes32(L, Lc, nu_pre, nu_post) + norm_pass);
 }
 
 void fill_stats(const BState& S, int L, int Lc, int nu_pre, int nu_post, mg_stats* st) {

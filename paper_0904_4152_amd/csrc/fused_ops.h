@@ -1,0 +1,356 @@
+// Fused smoothing passes of the V(2,2) cycle.  One workgroup owns a strip
+// of grid columns and a chunk of grid rows and marches down the rows; each
+// row of bands, x and b is read from HBM once and kept (bands in a register
+// ring of three rows, iterates in LDS rings of three rows) while every
+// fused step that needs it runs:
+//   pre  : two damped Jacobi sweeps (the first possibly from a zero
+//          iterate), the defect of the result and its restriction P^T d to
+//          the next coarser level;
+//   post : prolongation and correction x + P x_c, two damped Jacobi sweeps,
+//          and optionally the sum of squares of the final defect.
+// Each node's arithmetic is the one of the unfused kernels (same operands,
+// same operation order), so fused and unfused cycles give identical bits.
+// Strips overlap by F_HALO columns and chunks by F_HALO rows; the overlap is
+// recomputed and only owned nodes are written.
+//
+// Rows of x and of bands are loaded two steps ahead of their use, so that
+// enough bytes are in flight per wavefront to cover HBM latency.
+// Row bookkeeping of one step: the x row jx enters; the first sweep runs at
+// row jx-1, the second at jx-2, the defect (pre) or norm (post) at jx-3 and
+// the restriction (pre) at jx-4.  A row j lives in ring slot j mod 3; the
+// loop is unrolled by three so every slot index is a compile-time constant.
+#pragma once
+
+#include "device_ops.h"
+
+namespace mg {
+namespace dev {
+
+constexpr int F_THREADS = 256;                // one grid column per thread
+constexpr int F_HALO = 4;                     // columns / rows recomputed per side
+constexpr int F_CW = F_THREADS - 2 * F_HALO;  // owned columns per strip (even)
+
+struct FusedGeom {
+    int nstrips, nchunks, rh;  // rh: owned rows per chunk (even)
+};
+
+__host__ __device__ inline FusedGeom fused_geom(int N, int rh) {
+    FusedGeom g;
+    g.rh = rh;
+    g.nstrips = (N + F_CW - 1) / F_CW;
+    g.nchunks = (N + rh - 1) / rh;
+    return g;
+}
+
+__device__ __forceinline__ bool in_range(int v, int lo, int hi) { return v >= lo && v < hi; }
+
+// The 9-term band product at one node from the rows j-1, j, j+1 of an
+// iterate held in LDS, around LDS column t: the fma chain of stencil_tile.
+template <typename T>
+__device__ __forceinline__ T band_row_product(const T (&bk)[9], const T* __restrict__ rm,
+                                              const T* __restrict__ rc,
+                                              const T* __restrict__ rp, int t) {
+    const T* rows[3] = {rm, rc, rp};
+    T acc = T(0);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) acc = fma(bk[k], rows[k / 3][t + k % 3 - 1], acc);
+    return acc;
+}
+
+// Bands and b of node (col, j); zeros outside the grid or when !need.
+template <typename T>
+__device__ __forceinline__ void load_band_row(const T* __restrict__ bands, int64_t bs, int N,
+                                              int j, int col, bool need, T (&bk)[9], T& bb,
+                                              const T* __restrict__ b) {
+    if (need && j >= 0 && j < N && col >= 0 && col < N) {
+        const int64_t p = (int64_t)j * N + col;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) bk[k] = __builtin_nontemporal_load(bands + k * bs + p);
+        bb = b[p];
+    } else {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) bk[k] = T(0);
+        bb = T(0);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void copy9(T (&d)[9], const T (&s)[9]) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) d[k] = s[k];
+}
+
+// Pre-smoothing tile (strip, chunk) on a level with N nodes per side:
+// x2 = J(J(x)) on owned nodes and bc = P^T (b - A x2) on the owned coarse
+// nodes (coarse boundary 0).  With XZERO the first sweep starts from a zero
+// iterate and x is not read.
+template <typename T, bool XZERO>
+__device__ void pre_tile(const T* __restrict__ bands, int64_t bs, int N, const T* __restrict__ x,
+                         const T* __restrict__ b, T omega, T* __restrict__ x2out,
+                         T* __restrict__ bc, int strip, int chunk, int rh) {
+    __shared__ T X[3][F_THREADS + 2], A[3][F_THREADS + 2], B[3][F_THREADS + 2],
+        D[3][F_THREADS + 2];
+    const int t = threadIdx.x + 1;  // LDS column; 0 and F_THREADS+1 are guards
+    const int c0 = strip * F_CW, c1 = min(c0 + F_CW, N);
+    const int r0 = chunk * rh, r1 = min(r0 + rh, N);
+    const int col = c0 - F_HALO + (int)threadIdx.x;
+    const bool cval = col >= 0 && col < N;
+    // column / row ranges where each step is needed
+    const bool c_op1 = cval && in_range(col, c0 - 3, c1 + 3);
+    const bool c_op2 = cval && in_range(col, c0 - 2, c1 + 2);
+    const bool c_op3 = cval && in_range(col, c0 - 1, c1 + 1);
+    const bool c_own = in_range(col, c0, c1);
+    const int Nc = (N >> 1) + 1;
+    if (threadIdx.x < 2) {
+        const int g = threadIdx.x ? F_THREADS + 1 : 0;
+#pragma unroll
+        for (int s = 0; s < 3; ++s) X[s][g] = A[s][g] = B[s][g] = D[s][g] = T(0);
+    }
+    T bk[3][9], bb[3];
+    // prefetch buffers: bands / b and x of row r in slot r mod 3, loaded two
+    // steps before their use (no buffer is read before its load is 2 steps old)
+    T pfb[3][9], pfbb[3], pfx[3];
+    const int jstart = r0 - F_HALO - ((((r0 - F_HALO) % 3) + 3) % 3);  // multiple of 3
+    const int jend = r1 + 4;
+    auto xload = [&](int j) -> T {
+        return (!XZERO && in_range(j, 0, N) && cval) ? x[(int64_t)j * N + col] : T(0);
+    };
+    auto need1 = [&](int j) { return c_op1 && in_range(j, r0 - 3, r1 + 3); };
+    pfx[0] = xload(jstart);
+    pfx[1] = xload(jstart + 1);
+    load_band_row(bands, bs, N, jstart - 1, col, need1(jstart - 1), pfb[2], pfbb[2], b);
+    load_band_row(bands, bs, N, jstart, col, need1(jstart), pfb[0], pfbb[0], b);
+#pragma unroll 1
+    for (int jb = jstart; jb < jend; jb += 3) {
+#pragma unroll
+        for (int ph = 0; ph < 3; ++ph) {
+            const int jx = jb + ph;  // slot ph
+            const int j1 = jx - 1, j2 = jx - 2, j3 = jx - 3, jr = jx - 4;
+            constexpr int dummy = 0;
+            (void)dummy;
+            const int s1 = (ph + 2) % 3, s2 = (ph + 1) % 3, s3 = ph;
+            // 1. x row jx into its slot; bands of row j1 into the register ring;
+            //    prefetch the next x row and the next band row
+            if (!XZERO) X[ph][t] = pfx[ph];
+            pfx[(ph + 2) % 3] = xload(jx + 2);
+            copy9(bk[s1], pfb[(ph + 2) % 3]);
+            bb[s1] = pfbb[(ph + 2) % 3];
+            load_band_row(bands, bs, N, jx + 1, col, need1(jx + 1), pfb[(ph + 1) % 3],
+                          pfbb[(ph + 1) % 3], b);
+            __syncthreads();
+            // 2. first sweep at row j1
+            {
+                T v = T(0);
+                if (c_op1 && in_range(j1, r0 - 3, r1 + 3) && in_range(j1, 0, N)) {
+                    if (XZERO) {
+                        v = omega * bb[s1] / bk[s1][4];
+                    } else {
+                        const T acc = band_row_product(bk[s1], X[(ph + 1) % 3], X[(ph + 2) % 3],
+                                                       X[ph], t);
+                        v = X[(ph + 2) % 3][t] + omega * (bb[s1] - acc) / bk[s1][4];
+                    }
+                }
+                A[s1][t] = v;
+            }
+            __syncthreads();
+            // 3. second sweep at row j2 (written on owned nodes)
+            {
+                T v = T(0);
+                if (c_op2 && in_range(j2, r0 - 2, r1 + 2) && in_range(j2, 0, N)) {
+                    const T acc = band_row_product(bk[s2], A[(s2 + 2) % 3], A[s2], A[s1], t);
+                    v = A[s2][t] + omega * (bb[s2] - acc) / bk[s2][4];
+                    if (c_own && in_range(j2, r0, r1)) x2out[(int64_t)j2 * N + col] = v;
+                }
+                B[s2][t] = v;
+            }
+            __syncthreads();
+            // 4. defect at row j3
+            {
+                T v = T(0);
+                if (c_op3 && in_range(j3, r0 - 1, r1 + 1) && in_range(j3, 0, N)) {
+                    const T acc = band_row_product(bk[s3], B[(s3 + 2) % 3], B[s3], B[s2], t);
+                    v = bb[s3] - acc;
+                }
+                D[s3][t] = v;
+            }
+            __syncthreads();
+            // 5. restriction of defect rows jr-1, jr, jr+1 to coarse row jr/2
+            if (in_range(jr, r0, r1) && !(jr & 1) && c_own && !(col & 1)) {
+                const int I = col >> 1, J = jr >> 1;
+                T s = T(0);
+                if (I > 0 && J > 0 && I < Nc - 1 && J < Nc - 1) {
+                    const T* u = D[(ph + 1) % 3];  // row jr - 1
+                    const T* c = D[(ph + 2) % 3];  // row jr
+                    const T* o = D[ph];            // row jr + 1
+                    const T corner = (u[t - 1] + u[t + 1]) + (o[t - 1] + o[t + 1]);
+                    const T edge = (u[t] + o[t]) + (c[t - 1] + c[t + 1]);
+                    s = c[t] + T(0.5) * edge + T(0.25) * corner;
+                }
+                bc[(int64_t)J * Nc + I] = s;
+            }
+        }
+    }
+}
+
+// Interpolated coarse correction (P x_c) at fine node (i, j): the value
+// prolong_elem adds.
+template <typename T>
+__device__ __forceinline__ T prolong_value(int Nf, const T* __restrict__ xc, int i, int j) {
+    const int Nc = (Nf >> 1) + 1;
+    const T* c = xc + (int64_t)(j >> 1) * Nc + (i >> 1);
+    if (!(i & 1) && !(j & 1)) return c[0];
+    if (!(j & 1)) return T(0.5) * (c[0] + c[1]);
+    if (!(i & 1)) return T(0.5) * (c[0] + c[Nc]);
+    return T(0.25) * ((c[0] + c[1]) + (c[Nc] + c[Nc + 1]));
+}
+
+// Post-smoothing tile: x_out = J(J(x + P x_c)) on owned nodes; with NORM
+// also the thread's sum of squares of b - A x_out over its owned nodes.
+template <typename T, bool NORM>
+__device__ double post_tile(const T* __restrict__ bands, int64_t bs, int N,
+                            const T* __restrict__ x, const T* __restrict__ xc,
+                            const T* __restrict__ b, T omega, T* __restrict__ xout, int strip,
+                            int chunk, int rh) {
+    __shared__ T X[3][F_THREADS + 2], A[3][F_THREADS + 2], B[3][F_THREADS + 2];
+    constexpr int H = NORM ? 3 : 2;  // halo the last step needs
+    const int t = threadIdx.x + 1;
+    const int c0 = strip * F_CW, c1 = min(c0 + F_CW, N);
+    const int r0 = chunk * rh, r1 = min(r0 + rh, N);
+    const int col = c0 - F_HALO + (int)threadIdx.x;
+    const bool cval = col >= 0 && col < N;
+    const bool c_x = cval && in_range(col, c0 - H, c1 + H);
+    const bool c_op1 = cval && in_range(col, c0 - (H - 1), c1 + (H - 1));
+    const bool c_op2 = cval && in_range(col, c0 - (H - 2), c1 + (H - 2));
+    const bool c_own = in_range(col, c0, c1);
+    if (threadIdx.x < 2) {
+        const int g = threadIdx.x ? F_THREADS + 1 : 0;
+#pragma unroll
+        for (int s = 0; s < 3; ++s) X[s][g] = A[s][g] = B[s][g] = T(0);
+    }
+    T bk[3][9], bb[3];
+    T pfb[3][9], pfbb[3], pfx[3];  // prefetch buffers as in pre_tile
+    double sq = 0.0;
+    const int jstart = r0 - F_HALO - ((((r0 - F_HALO) % 3) + 3) % 3);
+    const int jend = r1 + 3;
+    auto xrow = [&](int j) -> T {
+        if (!c_x || !in_range(j, r0 - H, r1 + H) || !in_range(j, 0, N)) return T(0);
+        return x[(int64_t)j * N + col] + prolong_value(N, xc, col, j);
+    };
+    auto need1 = [&](int j) { return c_op1 && in_range(j, r0 - (H - 1), r1 + (H - 1)); };
+    pfx[0] = xrow(jstart);
+    pfx[1] = xrow(jstart + 1);
+    load_band_row(bands, bs, N, jstart - 1, col, need1(jstart - 1), pfb[2], pfbb[2], b);
+    load_band_row(bands, bs, N, jstart, col, need1(jstart), pfb[0], pfbb[0], b);
+#pragma unroll 1
+    for (int jb = jstart; jb < jend; jb += 3) {
+#pragma unroll
+        for (int ph = 0; ph < 3; ++ph) {
+            const int jx = jb + ph;
+            const int j1 = jx - 1, j2 = jx - 2, j3 = jx - 3;
+            const int s1 = (ph + 2) % 3, s2 = (ph + 1) % 3, s3 = ph;
+            X[ph][t] = pfx[ph];
+            pfx[(ph + 2) % 3] = xrow(jx + 2);
+            copy9(bk[s1], pfb[(ph + 2) % 3]);
+            bb[s1] = pfbb[(ph + 2) % 3];
+            load_band_row(bands, bs, N, jx + 1, col, need1(jx + 1), pfb[(ph + 1) % 3],
+                          pfbb[(ph + 1) % 3], b);
+            __syncthreads();
+            {
+                T v = T(0);
+                if (c_op1 && in_range(j1, r0 - (H - 1), r1 + (H - 1)) && in_range(j1, 0, N)) {
+                    const T acc = band_row_product(bk[s1], X[(ph + 1) % 3], X[(ph + 2) % 3],
+                                                   X[ph], t);
+                    v = X[(ph + 2) % 3][t] + omega * (bb[s1] - acc) / bk[s1][4];
+                }
+                A[s1][t] = v;
+            }
+            __syncthreads();
+            {
+                T v = T(0);
+                if (c_op2 && in_range(j2, r0 - (H - 2), r1 + (H - 2)) && in_range(j2, 0, N)) {
+                    const T acc = band_row_product(bk[s2], A[(s2 + 2) % 3], A[s2], A[s1], t);
+                    v = A[s2][t] + omega * (bb[s2] - acc) / bk[s2][4];
+                    if (c_own && in_range(j2, r0, r1)) xout[(int64_t)j2 * N + col] = v;
+                }
+                B[s2][t] = v;
+            }
+            __syncthreads();
+            if (NORM && c_own && in_range(j3, r0, r1)) {
+                const T acc = band_row_product(bk[s3], B[(s3 + 2) % 3], B[s3], B[s2], t);
+                const T d = bb[s3] - acc;
+                sq += (double)d * (double)d;
+            }
+        }
+    }
+    return sq;
+}
+
+// ---------------------------------------------------------------- coarse tail
+// Levels at and below TAIL_MAX hold at most 65 x 65 nodes and sit in L2: one
+// workgroup runs the whole V(2,2) sub-cycle over them (workgroup barriers
+// between the steps instead of kernel launches), with the per-node
+// arithmetic of the separate kernels.
+constexpr int TAIL_MAX = 5;
+
+template <typename T>
+struct TailLevel {
+    const T* bands;
+    T* x;
+    T* b;
+    T* t;
+    int64_t bs;
+    int64_t n;
+    int N;
+    int pad;
+};
+
+template <typename T>
+struct TailLevels {
+    TailLevel<T> lv[TAIL_MAX + 1];  // index = level
+    const double* chol;
+    int m;
+    int top;  // highest level of the tail; entered with a zero iterate
+    int Lc;
+};
+
+// x_top = V(top, 0, b_top) over levels top..Lc (one workgroup of BLOCK threads).
+template <typename T>
+__device__ void tail_cycle(const TailLevels<T>& tl, T omega) {
+    for (int l = tl.top; l > tl.Lc; --l) {
+        const TailLevel<T>& v = tl.lv[l];
+        const T* diag = v.bands + 4 * v.bs;
+        for (int64_t p = threadIdx.x; p < v.n; p += BLOCK) jacobi_zero_elem(diag, v.b, v.t, p, omega);
+        __syncthreads();
+        for (int64_t blo = 0; blo < v.n; blo += tile_rows<T>())
+            stencil_tile<T, OP_JACOBI, false, true>(v.bands, v.bs, v.N, v.n, v.t, v.b, v.x, omega,
+                                                    blo);
+        __syncthreads();
+        for (int64_t blo = 0; blo < v.n; blo += tile_rows<T>())
+            stencil_tile<T, OP_DEFECT, false, true>(v.bands, v.bs, v.N, v.n, v.x, v.b, v.t, omega,
+                                                    blo);
+        __syncthreads();
+        const TailLevel<T>& c = tl.lv[l - 1];
+        for (int64_t q = threadIdx.x; q < c.n; q += BLOCK)
+            restrict_elem<T>(v.N, v.t, c.b, (int)(q % c.N), (int)(q / c.N));
+        __syncthreads();
+    }
+    coarse_block<T>(tl.chol, tl.m, tl.lv[tl.Lc].N, tl.lv[tl.Lc].b, tl.lv[tl.Lc].x);
+    for (int l = tl.Lc + 1; l <= tl.top; ++l) {
+        const TailLevel<T>& v = tl.lv[l];
+        const TailLevel<T>& c = tl.lv[l - 1];
+        for (int64_t p = threadIdx.x; p < v.n; p += BLOCK)
+            prolong_elem<T>(v.N, c.x, v.x, (int)(p % v.N), (int)(p / v.N));
+        __syncthreads();
+        for (int64_t blo = 0; blo < v.n; blo += tile_rows<T>())
+            stencil_tile<T, OP_JACOBI, false, true>(v.bands, v.bs, v.N, v.n, v.x, v.b, v.t, omega,
+                                                    blo);
+        __syncthreads();
+        for (int64_t blo = 0; blo < v.n; blo += tile_rows<T>())
+            stencil_tile<T, OP_JACOBI, false, true>(v.bands, v.bs, v.N, v.n, v.t, v.b, v.x, omega,
+                                                    blo);
+        __syncthreads();
+    }
+}
+
+}  // namespace dev
+}  // namespace mg

@@ -9,9 +9,13 @@
 // (single use), the x halo of the three grid rows comes through L1/L2, and
 // workgroups are renumbered so that each XCD walks a contiguous part of the
 // grid (its L2 then sees the row reuse of x).
+#include <algorithm>
 #include <cmath>
+#include <cstdlib>
+#include <type_traits>
 
 #include "device_ops.h"
+#include "fused_ops.h"
 #include "mg_internal.h"
 
 namespace mg {
@@ -89,6 +93,45 @@ template <typename T>
 __global__ void k_coarse(const double* __restrict__ chol, int m, int Nc,
                          const T* __restrict__ b, T* __restrict__ x) {
     dev::coarse_block(chol, m, Nc, b, x);
+}
+
+// Fused pre-smoothing pass: one (strip, chunk) tile per workgroup.
+template <typename T, bool XZERO>
+__global__ __launch_bounds__(dev::F_THREADS) void k_pre(const T* __restrict__ bands, int64_t bs,
+                                                        int N, const T* __restrict__ x,
+                                                        const T* __restrict__ b, T omega,
+                                                        T* __restrict__ x2out,
+                                                        T* __restrict__ bc, int nstrips,
+                                                        int nchunks, int rh) {
+    const int64_t lb = xcd_block((int64_t)nstrips * nchunks);
+    if (lb < 0) return;
+    dev::pre_tile<T, XZERO>(bands, bs, N, x, b, omega, x2out, bc, (int)(lb % nstrips),
+                            (int)(lb / nstrips), rh);
+}
+
+// Fused post-smoothing pass; with NORM one partial sum of squares per tile.
+template <typename T, bool NORM>
+__global__ __launch_bounds__(dev::F_THREADS) void k_post(const T* __restrict__ bands, int64_t bs,
+                                                         int N, const T* __restrict__ x,
+                                                         const T* __restrict__ xc,
+                                                         const T* __restrict__ b, T omega,
+                                                         T* __restrict__ xout,
+                                                         double* __restrict__ partials,
+                                                         int nstrips, int nchunks, int rh) {
+    const int64_t lb = xcd_block((int64_t)nstrips * nchunks);
+    if (lb < 0) return;
+    const double sq = dev::post_tile<T, NORM>(bands, bs, N, x, xc, b, omega, xout,
+                                              (int)(lb % nstrips), (int)(lb / nstrips), rh);
+    if (NORM) {
+        const double s = dev::block_sum(sq);
+        if (threadIdx.x == 0) partials[lb] = s;
+    }
+}
+
+// Coarse tail: the V(2,2) sub-cycle over levels top..Lc in one workgroup.
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_tail(dev::TailLevels<T> tl, T omega) {
+    dev::tail_cycle<T>(tl, omega);
 }
 
 // Dense interior block of the coarsest operator and its Cholesky factor
@@ -458,6 +501,93 @@ hipError_t launch_jacobi_zero(const Level& lv, const T* bands, const T* b, T* xo
     return hipGetLastError();
 }
 
+// Owned rows per fused tile: the largest power of two from rhmax (64) down
+// to 4 that still gives at least `target` tiles (so that small levels keep
+// the device busy and their marching pipelines short).
+int fused_rows(int N) {
+    static const int target = [] {
+        const char* e = getenv("MG_FUSED_TILES");
+        return e ? std::max(1, atoi(e)) : 1024;
+    }();
+    static const int rhmax = [] {
+        const char* e = getenv("MG_FUSED_RHMAX");
+        const int v = e ? atoi(e) : 64;
+        return (v >= 8 && v % 2 == 0) ? v : 64;
+    }();
+    const int nstrips = (N + dev::F_CW - 1) / dev::F_CW;
+    int rh = rhmax;
+    while (rh > 4 && (int64_t)nstrips * ((N + rh - 1) / rh) < target) rh /= 2;
+    return rh;
+}
+
+int dev_fused_cols() { return dev::F_CW; }
+
+int64_t fused_tiles(int N) {
+    const dev::FusedGeom g = dev::fused_geom(N, fused_rows(N));
+    return (int64_t)g.nstrips * g.nchunks;
+}
+
+template <typename T>
+hipError_t launch_pre(const Level& lv, const T* bands, const T* x, bool x_zero, const T* b,
+                      T omega, T* x2out, T* bc, hipStream_t st) {
+    const dev::FusedGeom g = dev::fused_geom(lv.N, fused_rows(lv.N));
+    const int64_t nt = (int64_t)g.nstrips * g.nchunks;
+    if (x_zero)
+        hipLaunchKernelGGL((k_pre<T, true>), dim3(grid8(nt)), dim3(dev::F_THREADS), 0, st, bands,
+                           lv.bs, lv.N, x, b, omega, x2out, bc, g.nstrips, g.nchunks, g.rh);
+    else
+        hipLaunchKernelGGL((k_pre<T, false>), dim3(grid8(nt)), dim3(dev::F_THREADS), 0, st,
+                           bands, lv.bs, lv.N, x, b, omega, x2out, bc, g.nstrips, g.nchunks,
+                           g.rh);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_post(const Level& lv, const T* bands, const T* x, const T* xc, const T* b,
+                       T omega, T* xout, double* partials, double* scal, int slot,
+                       hipStream_t st) {
+    const dev::FusedGeom g = dev::fused_geom(lv.N, fused_rows(lv.N));
+    const int64_t nt = (int64_t)g.nstrips * g.nchunks;
+    if (partials) {
+        hipLaunchKernelGGL((k_post<T, true>), dim3(grid8(nt)), dim3(dev::F_THREADS), 0, st,
+                           bands, lv.bs, lv.N, x, xc, b, omega, xout, partials, g.nstrips,
+                           g.nchunks, g.rh);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(BLOCK), 0, st, partials, nt, scal, slot);
+    } else {
+        hipLaunchKernelGGL((k_post<T, false>), dim3(grid8(nt)), dim3(dev::F_THREADS), 0, st,
+                           bands, lv.bs, lv.N, x, xc, b, omega, xout, (double*)nullptr,
+                           g.nstrips, g.nchunks, g.rh);
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_tail(const Level* lv, int top, int Lc, const double* chol, int m, T omega,
+                       hipStream_t st) {
+    dev::TailLevels<T> tl{};
+    for (int l = Lc; l <= top; ++l) {
+        dev::TailLevel<T>& d = tl.lv[l];
+        const Level& v = lv[l];
+        d.bands = std::is_same<T, float>::value ? (const T*)v.bands32 : (const T*)v.bands64;
+        d.x = std::is_same<T, float>::value ? (T*)v.x32 : (T*)v.x64;
+        d.b = std::is_same<T, float>::value ? (T*)v.b32 : (T*)v.b64;
+        d.t = std::is_same<T, float>::value ? (T*)v.t32 : (T*)v.t64;
+        d.bs = v.bs;
+        d.n = v.n;
+        d.N = v.N;
+    }
+    tl.chol = chol;
+    tl.m = m;
+    tl.top = top;
+    tl.Lc = Lc;
+    hipLaunchKernelGGL(k_tail<T>, dim3(1), dim3(BLOCK), 0, st, tl, omega);
+    return hipGetLastError();
+}
+
+int tail_max_level() { return dev::TAIL_MAX; }
+
 template <typename T>
 hipError_t launch_restrict(int Nf, const T* d_f, T* b_c, hipStream_t st) {
     const int Nc = (Nf >> 1) + 1;
@@ -526,7 +656,12 @@ hipError_t launch_update(double* x, const float* c32, int64_t n, const double* s
     template hipError_t launch_coarse<T>(const double*, int, int, const T*, T*, hipStream_t); \
     template hipError_t launch_copy<T>(const T*, T*, int64_t, hipStream_t);                   \
     template hipError_t launch_norm<T>(const T*, int64_t, double*, double*, int, hipStream_t); \
-    template hipError_t launch_fill<T>(T*, int64_t, T, hipStream_t);
+    template hipError_t launch_fill<T>(T*, int64_t, T, hipStream_t);                          \
+    template hipError_t launch_pre<T>(const Level&, const T*, const T*, bool, const T*, T, T*,  \
+                                      T*, hipStream_t);                                         \
+    template hipError_t launch_post<T>(const Level&, const T*, const T*, const T*, const T*, T, \
+                                       T*, double*, double*, int, hipStream_t);               \
+    template hipError_t launch_tail<T>(const Level*, int, int, const double*, int, T, hipStream_t);
 
 MG_INSTANTIATE(float)
 MG_INSTANTIATE(double)

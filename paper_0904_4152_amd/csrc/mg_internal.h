@@ -131,6 +131,28 @@ hipError_t launch_cast_scaled(const double* d64, float* d32, int64_t n, const do
 hipError_t launch_update(double* x, const float* c32, int64_t n, const double* scal, int slot,
                          hipStream_t st);
 
+// Fused smoothing passes of a V(2,2) level (see fused_ops.h): pre = two
+// sweeps (x_zero: the first from a zero iterate) + defect + restriction into
+// bc; post = prolongation/correction + two sweeps, and with partials the
+// residual norm reduced into scal[slot], scal[slot + 1].
+template <typename T>
+hipError_t launch_pre(const Level& lv, const T* bands, const T* x, bool x_zero, const T* b,
+                      T omega, T* x2out, T* bc, hipStream_t st);
+template <typename T>
+hipError_t launch_post(const Level& lv, const T* bands, const T* x, const T* xc, const T* b,
+                       T omega, T* xout, double* partials, double* scal, int slot,
+                       hipStream_t st);
+// The V(2,2) sub-cycle over levels top..Lc (top <= tail_max_level(), entered
+// with a zero iterate on level top) in one workgroup.  lv is indexed by level.
+template <typename T>
+hipError_t launch_tail(const Level* lv, int top, int Lc, const double* chol, int m, T omega,
+                       hipStream_t st);
+int tail_max_level();
+// Owned rows per fused tile for a level of N nodes per side, and tiles per pass.
+int fused_rows(int N);
+int64_t fused_tiles(int N);
+int dev_fused_cols();  // owned columns per fused strip
+
 // Workgroups (= tiles) of a band-product launch and of a vector-norm launch.
 int64_t stencil_blocks(int64_t n, int elem_bytes);
 int64_t norm_blocks(int64_t n);

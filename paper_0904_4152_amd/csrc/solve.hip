@@ -117,6 +117,50 @@ template hipError_t enqueue_vcycle<double>(mg_hierarchy*, int, double*, const do
 template hipError_t enqueue_vcycle<float>(mg_hierarchy*, int, float*, const float*, bool, int,
                                           int, double, Enq&);
 
+// V(2,2) cycle from the fused passes: per level one pre pass (two sweeps,
+// defect, restriction: x -> t, b_c) and one post pass (prolongation, two
+// sweeps: t + P x_c -> x).  With partials the top-level post pass also
+// reduces ||b - A x|| into scal[slot], scal[slot + 1].  Byte model: bands
+// (9 s), iterate in (s, not when from zero), b (s) and iterate out (s) per
+// node and pass, plus the coarse vector (s per coarse node).
+template <typename T>
+hipError_t enqueue_vcycle_fused(mg_hierarchy* h, int l, T* x, const T* b, bool x_zero,
+                                double omega, Enq& q, double* partials, double* scal, int slot) {
+    Level& lv = h->lv[l];
+    const double s = sizeof(T), n = (double)lv.n;
+    const T om = (T)omega;
+    const T* bands = LV<T>::bands(lv);
+    if (l == h->Lc) {
+        MG_TRY(launch_coarse<T>(h->chol, h->m, lv.N, b, x, q.st));
+        q.bytes += 2 * s * n;
+        if (partials) {
+            MG_TRY(launch_defect<T>(lv, bands, b, x, nullptr, partials, scal, slot, q.st));
+            q.bytes += 11 * s * n;
+        }
+        return hipSuccess;
+    }
+    Level& lc = h->lv[l - 1];
+    T* t = LV<T>::t(lv);
+    MG_TRY(launch_pre<T>(lv, bands, x, x_zero, b, om, t, LV<T>::b(lc), q.st));
+    q.bytes += (x_zero ? 11 : 12) * s * n + s * (double)lc.n;
+    if (l - 1 <= tail_max_level()) {
+        // every coarser level in one workgroup; same bytes as the unfused cycle there
+        MG_TRY(launch_tail<T>(h->lv, l - 1, h->Lc, h->chol, h->m, om, q.st));
+        for (int k = h->Lc + 1; k < l; ++k) q.bytes += 84.0 * s * (double)h->lv[k].n;
+    } else {
+        MG_TRY(enqueue_vcycle_fused<T>(h, l - 1, LV<T>::x(lc), LV<T>::b(lc), true, omega, q,
+                                       nullptr, nullptr, 0));
+    }
+    MG_TRY(launch_post<T>(lv, bands, t, LV<T>::x(lc), b, om, x, partials, scal, slot, q.st));
+    q.bytes += 12 * s * n + s * (double)lc.n;
+    return hipSuccess;
+}
+
+template hipError_t enqueue_vcycle_fused<double>(mg_hierarchy*, int, double*, const double*, bool,
+                                                 double, Enq&, double*, double*, int);
+template hipError_t enqueue_vcycle_fused<float>(mg_hierarchy*, int, float*, const float*, bool,
+                                                double, Enq&, double*, double*, int);
+
 // The unit replayed per iteration: FP64 cycle + FP64 residual norm (kind 0)
 // or FP32 inner cycle + FP32 residual norm (kind 1), on the finest level's
 // own vectors.
@@ -124,6 +168,13 @@ static hipError_t enqueue_unit(mg_hierarchy* h, int kind, int nu_pre, int nu_pos
                                bool x_zero, Enq& q) {
     Level& F = h->lv[h->L];
     const double n = (double)F.n;
+    if (nu_pre == 2 && nu_post == 2) {
+        if (kind == 0)
+            return enqueue_vcycle_fused<double>(h, h->L, F.x64, F.b64, false, omega, q,
+                                                h->partials, h->scal, SC_R64);
+        return enqueue_vcycle_fused<float>(h, h->L, F.x32, F.b32, x_zero, omega, q, h->partials,
+                                           h->scal, SC_R32);
+    }
     if (kind == 0) {
         MG_TRY(enqueue_vcycle<double>(h, h->L, F.x64, F.b64, false, nu_pre, nu_post, omega, q));
         MG_TRY(launch_defect<double>(F, F.bands64, F.b64, F.x64, nullptr, h->partials, h->scal,
@@ -224,7 +275,8 @@ static mg_status validate_opts(const mg_solve_opts& o) {
 }
 
 extern "C" mg_status mg_vcycle(mg_hierarchy* h, int level, mg_dtype dtype, const void* b,
-                               void* x, int nu_pre, int nu_post, double omega, void* stream) {
+                               void* x, int nu_pre, int nu_post, double omega, int fused,
+                               void* stream) {
     if (!h) return fail(MG_ERR_INVALID, "null hierarchy");
     if (level < h->Lc || level > h->L) return fail(MG_ERR_INVALID, "level out of range");
     if (!h->assembled) return fail(MG_ERR_INVALID, "hierarchy not assembled");
@@ -234,7 +286,15 @@ extern "C" mg_status mg_vcycle(mg_hierarchy* h, int level, mg_dtype dtype, const
         return fail(MG_ERR_INVALID, "smoothing steps out of range");
     MG_HIP(hipSetDevice(h->ctx->device));
     Enq q{(hipStream_t)stream, 0.0};
-    if (dtype == MG_F64)
+    if (fused && (nu_pre != 2 || nu_post != 2))
+        return fail(MG_ERR_INVALID, "the fused cycle is V(2,2)");
+    if (fused && dtype == MG_F64)
+        MG_HIP(enqueue_vcycle_fused<double>(h, level, (double*)x, (const double*)b, false, omega, q,
+                                            nullptr, nullptr, 0));
+    else if (fused)
+        MG_HIP(enqueue_vcycle_fused<float>(h, level, (float*)x, (const float*)b, false, omega, q,
+                                           nullptr, nullptr, 0));
+    else if (dtype == MG_F64)
         MG_HIP(enqueue_vcycle<double>(h, level, (double*)x, (const double*)b, false, nu_pre,
                                       nu_post, omega, q));
     else
