@@ -234,6 +234,13 @@ def main():
     t_spmv32 = time_launches(lambda: h.spmv(L, x32, y32), it, torch)
     t_spmv64 = time_launches(lambda: h.spmv(L, x64, y64), it, torch)
     t_jac32 = time_launches(lambda: h.jacobi(L, b32, x32, y32, 0.7), it, torch)
+    # the fused passes of the FP32 cycle on the finest level (the solve's
+    # dominant kernels): pre = 2 sweeps + defect + restriction, post =
+    # prolongation + 2 sweeps + residual norm
+    Nc = ((1 << (L - 1)) + 1) ** 2
+    bc32 = torch.zeros(Nc, dtype=torch.float32, device=dev)
+    t_pre32 = time_launches(lambda: h.pre_smooth(L, b32, x32, y32, bc32), it, torch)
+    t_post32 = time_launches(lambda: h.post_smooth(L, b32, x32, bc32, y32), it, torch)
     bytes_spmv32 = 11 * 4 * n
     bytes_spmv64 = 11 * 8 * n
     bytes_jac32 = 12 * 4 * n
@@ -248,7 +255,16 @@ def main():
         "jacobi_fp32": {"us": t_jac32 * 1e6, "alg_bytes": bytes_jac32,
                         "GB_s": gbs(bytes_jac32, t_jac32),
                         "frac_hbm_peak": gbs(bytes_jac32, t_jac32) / PEAK_HBM_GBS},
+        # pre: 9 bands + x + b read, x2 written (4 B each), coarse rhs written
+        "fused_pre_fp32": {"us": t_pre32 * 1e6, "alg_bytes": 12 * 4 * n + 4 * Nc,
+                           "GB_s": gbs(12 * 4 * n + 4 * Nc, t_pre32),
+                           "frac_hbm_peak": gbs(12 * 4 * n + 4 * Nc, t_pre32) / PEAK_HBM_GBS},
+        # post: 9 bands + x + b read, x written, coarse correction read
+        "fused_post_fp32": {"us": t_post32 * 1e6, "alg_bytes": 12 * 4 * n + 4 * Nc,
+                            "GB_s": gbs(12 * 4 * n + 4 * Nc, t_post32),
+                            "frac_hbm_peak": gbs(12 * 4 * n + 4 * Nc, t_post32) / PEAK_HBM_GBS},
     }
+    del bc32
     del x32, y32, b32, x64, y64
     if args.only_kernels:
         # a plain device copy of known size (1 GiB read + 1 GiB written):

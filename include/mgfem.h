@@ -227,6 +227,21 @@ mg_status mg_smooth(const mg_hierarchy* h, int level, mg_dtype dtype, const void
  * or b. */
 mg_status mg_jacobi(const mg_hierarchy* h, int level, mg_dtype dtype, const void* b,
                     const void* x, void* x_out, double omega, void* stream);
+/* Fused pre-smoothing pass of a V(2,2) level (one kernel launch; Sec. 6.2):
+ * x2 = two damped Jacobi sweeps starting from x (x_zero != 0: from a zero
+ * iterate, x is not read) and b_c = P^T (b - A x2) on level-1 with the
+ * coarse boundary set to 0.  level > coarse level; x2 must not alias x or b;
+ * b_c has the n of level-1. */
+mg_status mg_pre_smooth(const mg_hierarchy* h, int level, mg_dtype dtype, const void* b,
+                        const void* x, int x_zero, double omega, void* x2, void* b_c,
+                        void* stream);
+/* Fused post-smoothing pass (one kernel launch): x_out = two damped Jacobi
+ * sweeps starting from x + P x_c; if host_norm is non-NULL also
+ * ||b - A x_out||_2 (FP64 accumulation; makes the call synchronous).
+ * x_out must not alias x, x_c or b. */
+mg_status mg_post_smooth(const mg_hierarchy* h, int level, mg_dtype dtype, const void* b,
+                         const void* x, const void* x_c, double omega, void* x_out,
+                         double* host_norm, void* stream);
 /* b_c = P^T d_f with the coarse boundary set to 0; P is bilinear
  * interpolation in index space (weights 1, 1/2, 1/4). */
 mg_status mg_restrict(const mg_hierarchy* h, int fine_level, mg_dtype dtype, const void* d_f,

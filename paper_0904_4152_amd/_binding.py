@@ -70,6 +70,8 @@ _SIGS = {
     "mg_defect": (_i, [_vp, _i, _i, _vp, _vp, _vp, ctypes.POINTER(_d), _vp]),
     "mg_smooth": (_i, [_vp, _i, _i, _vp, _vp, _i, _d, _vp]),
     "mg_jacobi": (_i, [_vp, _i, _i, _vp, _vp, _vp, _d, _vp]),
+    "mg_pre_smooth": (_i, [_vp, _i, _i, _vp, _vp, _i, _d, _vp, _vp, _vp]),
+    "mg_post_smooth": (_i, [_vp, _i, _i, _vp, _vp, _vp, _d, _vp, ctypes.POINTER(_d), _vp]),
     "mg_restrict": (_i, [_vp, _i, _i, _vp, _vp, _vp]),
     "mg_prolong": (_i, [_vp, _i, _i, _vp, _vp, _vp]),
     "mg_coarse_solve": (_i, [_vp, _i, _vp, _vp, _vp]),
@@ -273,6 +275,17 @@ class Hierarchy:
     def jacobi(self, level, b, x, x_out, omega=0.7, stream=None):
         check(lib().mg_jacobi(self._h, level, _dt(x), _ptr(b), _ptr(x), _ptr(x_out), omega,
                               _stream(stream)))
+
+    def pre_smooth(self, level, b, x, x2, b_c, x_zero=False, omega=0.7, stream=None):
+        check(lib().mg_pre_smooth(self._h, level, _dt(b), _ptr(b), _ptr(x), int(x_zero), omega,
+                                  _ptr(x2), _ptr(b_c), _stream(stream)))
+
+    def post_smooth(self, level, b, x, x_c, x_out, omega=0.7, norm=False, stream=None):
+        nv = _d()
+        check(lib().mg_post_smooth(self._h, level, _dt(b), _ptr(b), _ptr(x), _ptr(x_c), omega,
+                                   _ptr(x_out), ctypes.byref(nv) if norm else None,
+                                   _stream(stream)))
+        return nv.value if norm else None
 
     def restrict(self, fine_level, d_f, b_c, stream=None):
         check(lib().mg_restrict(self._h, fine_level, _dt(d_f), _ptr(d_f), _ptr(b_c),

@@ -26,10 +26,10 @@ int64_t vec_len(int64_t n) { return (n + 63) / 64 * 64; }
 int64_t band_stride(int64_t n) { return (n + 1023) / 1024 * 1024 + 64; }
 
 // Partial sums a reduction on the finest level of a level-L hierarchy can
-// produce: FP64 band-product tiles or fused tiles (at least 4 rows each).
+// produce: FP64 band-product tiles, or one per (fused strip, grid row).
 static int64_t max_partials(int L) {
     const int64_t N = (int64_t(1) << L) + 1;
-    const int64_t fused = ((N + dev_fused_cols() - 1) / dev_fused_cols()) * ((N + 3) / 4);
+    const int64_t fused = ((N + dev_fused_cols() - 1) / dev_fused_cols()) * N;
     return std::max(stencil_blocks(N * N, 8), fused);
 }
 
@@ -425,6 +425,57 @@ mg_status mg_jacobi(const mg_hierarchy* h, int level, mg_dtype dtype, const void
     else
         MG_HIP(launch_jacobi<float>(lv, lv.bands32, (const float*)b, (const float*)x,
                                     (float*)x_out, (float)omega, st));
+    return MG_OK;
+}
+
+mg_status mg_pre_smooth(const mg_hierarchy* h, int level, mg_dtype dtype, const void* b,
+                        const void* x, int x_zero, double omega, void* x2, void* b_c,
+                        void* stream) {
+    if (mg_status s = check_level(h, level)) return s;
+    if (level <= h->Lc) return fail(MG_ERR_INVALID, "no coarser level below level");
+    if (!b || !x2 || !b_c || (!x_zero && !x))
+        return fail(MG_ERR_INVALID, "null vector");
+    if (x2 == b || (!x_zero && x2 == x) || b_c == x2)
+        return fail(MG_ERR_INVALID, "x2 must not alias x, b or b_c");
+    if (mg_status s = set_device(h)) return s;
+    const Level& lv = h->lv[level];
+    hipStream_t st = (hipStream_t)stream;
+    if (dtype == MG_F64)
+        MG_HIP(launch_pre<double>(lv, lv.bands64, (const double*)x, x_zero != 0, (const double*)b,
+                                  omega, (double*)x2, (double*)b_c, st));
+    else
+        MG_HIP(launch_pre<float>(lv, lv.bands32, (const float*)x, x_zero != 0, (const float*)b,
+                                 (float)omega, (float*)x2, (float*)b_c, st));
+    return MG_OK;
+}
+
+mg_status mg_post_smooth(const mg_hierarchy* h, int level, mg_dtype dtype, const void* b,
+                         const void* x, const void* x_c, double omega, void* x_out,
+                         double* host_norm, void* stream) {
+    if (mg_status s = check_level(h, level)) return s;
+    if (level <= h->Lc) return fail(MG_ERR_INVALID, "no coarser level below level");
+    if (!b || !x || !x_c || !x_out) return fail(MG_ERR_INVALID, "null vector");
+    if (x_out == x || x_out == x_c || x_out == b)
+        return fail(MG_ERR_INVALID, "x_out must not alias x, x_c or b");
+    if (mg_status s = set_device(h)) return s;
+    const Level& lv = h->lv[level];
+    hipStream_t st = (hipStream_t)stream;
+    mg_hierarchy* hm = const_cast<mg_hierarchy*>(h);
+    double* part = host_norm ? hm->partials : nullptr;
+    if (dtype == MG_F64)
+        MG_HIP(launch_post<double>(lv, lv.bands64, (const double*)x, (const double*)x_c,
+                                   (const double*)b, omega, (double*)x_out, part, hm->scal, SC_USER,
+                                   st));
+    else
+        MG_HIP(launch_post<float>(lv, lv.bands32, (const float*)x, (const float*)x_c,
+                                  (const float*)b, (float)omega, (float*)x_out, part, hm->scal,
+                                  SC_USER, st));
+    if (host_norm) {
+        MG_HIP(hipMemcpyAsync(hm->host_scal + SC_USER, hm->scal + SC_USER, 2 * sizeof(double),
+                              hipMemcpyDeviceToHost, st));
+        MG_HIP(hipStreamSynchronize(st));
+        *host_norm = hm->host_scal[SC_USER + 1];
+    }
     return MG_OK;
 }
 

@@ -254,16 +254,12 @@ __global__ __launch_bounds__(dev::F_THREADS) void kb_fpost(const BProb* __restri
     const BLevel& lv = P.lv[l];
     const int strip = tile % lv.nstrips, chunk = tile / lv.nstrips;
     const float om = (float)P.omega;
-    if (l == P.L) {
-        const double sq = dev::post_tile<float, true>(lv.bands32, lv.bs, lv.N, lv.t32,
-                                                      P.lv[l - 1].x32, lv.b32, om, lv.x32, strip,
-                                                      chunk, lv.rh);
-        const double s = dev::block_sum(sq);
-        if (threadIdx.x == 0) P.partials[tile] = s;
-    } else {
+    if (l == P.L)
+        dev::post_tile<float, true>(lv.bands32, lv.bs, lv.N, lv.t32, P.lv[l - 1].x32, lv.b32, om,
+                                    lv.x32, P.partials, strip, chunk, lv.rh);
+    else
         dev::post_tile<float, false>(lv.bands32, lv.bs, lv.N, lv.t32, P.lv[l - 1].x32, lv.b32, om,
-                                     lv.x32, strip, chunk, lv.rh);
-    }
+                                     lv.x32, nullptr, strip, chunk, lv.rh);
     END_ITEMS
 }
 
@@ -366,7 +362,7 @@ __global__ __launch_bounds__(BLOCK) void kb_finalize(const BProb* __restrict__ p
                                : (n + TILE - 1) / TILE;
     // the inner residual comes from the fused post pass above the coarse level
     if (kind == K_S32 && fused_above >= 0 && P.L > fused_above)
-        np = (int64_t)F.nstrips * F.nchunks;
+        np = (int64_t)F.nstrips * F.N;  // per (strip, row) partials of the fused post pass
     const double s = dev::reduce_partials(P.partials, np);
     if (threadIdx.x == 0) {
         const double r = sqrt(s);
@@ -497,7 +493,7 @@ void BatchEngine::set_slot(int s, mg_hierarchy* h, const mg_solve_opts& o) {
         b.bs = v.bs;
         b.n = v.n;
         b.N = v.N;
-        const dev::FusedGeom g = dev::fused_geom(v.N, fused_rows(v.N));
+        const dev::FusedGeom g = dev::fused_geom(v.N, batch_fused_rows(v.N));
         b.rh = g.rh;
         b.nstrips = g.nstrips;
         b.nchunks = g.nchunks;

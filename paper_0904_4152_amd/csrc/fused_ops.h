@@ -17,8 +17,9 @@
 // enough bytes are in flight per wavefront to cover HBM latency.
 // Row bookkeeping of one step: the x row jx enters; the first sweep runs at
 // row jx-1, the second at jx-2, the defect (pre) or norm (post) at jx-3 and
-// the restriction (pre) at jx-4.  A row j lives in ring slot j mod 3; the
-// loop is unrolled by three so every slot index is a compile-time constant.
+// the restriction (pre) at jx-4.  An iterate row j lives in LDS slot j mod 3
+// and a band row in register slot j mod 6; the loop is unrolled by six so
+// every slot index is a compile-time constant.
 #pragma once
 
 #include "device_ops.h"
@@ -57,16 +58,57 @@ __device__ __forceinline__ T band_row_product(const T (&bk)[9], const T* __restr
     return acc;
 }
 
-// Bands and b of node (col, j); zeros outside the grid or when !need.
+// Raw buffer resources: one per band array, for b and for x.  A load
+// whose byte offset falls outside [0, bytes) returns zero, so rows above and
+// below the grid need no checks (negative offsets wrap to huge unsigned ones).
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+constexpr int RSRC_WORD3 = 0x00020000;  // raw (untyped) buffer access on CDNA
+constexpr int AUX_NT = 2;               // non-temporal: bands are read once
+
+__device__ __forceinline__ rsrc_t make_rsrc(const void* base, int64_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0,
+                                             (int)(uint32_t)bytes, RSRC_WORD3);
+}
+
+template <typename T, int AUX>
+struct BufLoad;
+template <int AUX>
+struct BufLoad<float, AUX> {
+    static __device__ __forceinline__ float get(rsrc_t r, uint32_t off) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, AUX));
+    }
+};
+template <int AUX>
+struct BufLoad<double, AUX> {
+    static __device__ __forceinline__ double get(rsrc_t r, uint32_t off) {
+        return __builtin_bit_cast(double,
+                                  __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, AUX));
+    }
+};
+template <typename T, int AUX = 0>
+__device__ __forceinline__ T bload(rsrc_t r, uint32_t off) {
+    return BufLoad<T, AUX>::get(r, off);
+}
+
 template <typename T>
-__device__ __forceinline__ void load_band_row(const T* __restrict__ bands, int64_t bs, int N,
-                                              int j, int col, bool need, T (&bk)[9], T& bb,
-                                              const T* __restrict__ b) {
-    if (need && j >= 0 && j < N && col >= 0 && col < N) {
-        const int64_t p = (int64_t)j * N + col;
+struct RowRsrc {
+    rsrc_t band[9];
+    rsrc_t b;
+    __device__ RowRsrc(const T* bands, int64_t bs, const T* bb, int64_t n) {
 #pragma unroll
-        for (int k = 0; k < 9; ++k) bk[k] = __builtin_nontemporal_load(bands + k * bs + p);
-        bb = b[p];
+        for (int k = 0; k < 9; ++k) band[k] = make_rsrc(bands + k * bs, n * (int64_t)sizeof(T));
+        b = make_rsrc(bb, n * (int64_t)sizeof(T));
+    }
+};
+
+// Bands and b of one node at byte offset off; zeros when !need.
+template <typename T>
+__device__ __forceinline__ void load_row(const RowRsrc<T>& R, uint32_t off, bool need,
+                                         T (&bk)[9], T& bb) {
+    if (need) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) bk[k] = bload<T, AUX_NT>(R.band[k], off);
+        bb = bload<T>(R.b, off);
     } else {
 #pragma unroll
         for (int k = 0; k < 9; ++k) bk[k] = T(0);
@@ -74,16 +116,16 @@ __device__ __forceinline__ void load_band_row(const T* __restrict__ bands, int64
     }
 }
 
-template <typename T>
-__device__ __forceinline__ void copy9(T (&d)[9], const T (&s)[9]) {
-#pragma unroll
-    for (int k = 0; k < 9; ++k) d[k] = s[k];
+__device__ __forceinline__ uint32_t node_off(int j, int N, int col, int size) {
+    return (uint32_t)(j * N + col) * (uint32_t)size;
 }
 
 // Pre-smoothing tile (strip, chunk) on a level with N nodes per side:
 // x2 = J(J(x)) on owned nodes and bc = P^T (b - A x2) on the owned coarse
 // nodes (coarse boundary 0).  With XZERO the first sweep starts from a zero
-// iterate and x is not read.
+// iterate and x is not read.  Band rows live in a ring of six register slots
+// (row r in slot r mod 6; the loop is unrolled by six) so that the load of a
+// row lands in its slot two steps before its first use.
 template <typename T, bool XZERO>
 __device__ void pre_tile(const T* __restrict__ bands, int64_t bs, int N, const T* __restrict__ x,
                          const T* __restrict__ b, T omega, T* __restrict__ x2out,
@@ -101,77 +143,74 @@ __device__ void pre_tile(const T* __restrict__ bands, int64_t bs, int N, const T
     const bool c_op3 = cval && in_range(col, c0 - 1, c1 + 1);
     const bool c_own = in_range(col, c0, c1);
     const int Nc = (N >> 1) + 1;
+    const int64_t n = (int64_t)N * N;
+    const RowRsrc<T> R(bands, bs, b, n);
+    const rsrc_t Rx = make_rsrc(x, n * (int64_t)sizeof(T));
     if (threadIdx.x < 2) {
         const int g = threadIdx.x ? F_THREADS + 1 : 0;
 #pragma unroll
         for (int s = 0; s < 3; ++s) X[s][g] = A[s][g] = B[s][g] = D[s][g] = T(0);
     }
-    T bk[3][9], bb[3];
-    // prefetch buffers: bands / b and x of row r in slot r mod 3, loaded two
-    // steps before their use (no buffer is read before its load is 2 steps old)
-    T pfb[3][9], pfbb[3], pfx[3];
-    const int jstart = r0 - F_HALO - ((((r0 - F_HALO) % 3) + 3) % 3);  // multiple of 3
+    T bk[6][9], bb[6];  // band rows, slot r mod 6
+    T pfx[3];           // x rows, slot r mod 3
+    const int jstart = r0 - F_HALO - ((((r0 - F_HALO) % 6) + 6) % 6);  // multiple of 6
     const int jend = r1 + 4;
     auto xload = [&](int j) -> T {
-        return (!XZERO && in_range(j, 0, N) && cval) ? x[(int64_t)j * N + col] : T(0);
+        return (!XZERO && cval) ? bload<T>(Rx, node_off(j, N, col, sizeof(T))) : T(0);
     };
     auto need1 = [&](int j) { return c_op1 && in_range(j, r0 - 3, r1 + 3); };
     pfx[0] = xload(jstart);
     pfx[1] = xload(jstart + 1);
-    load_band_row(bands, bs, N, jstart - 1, col, need1(jstart - 1), pfb[2], pfbb[2], b);
-    load_band_row(bands, bs, N, jstart, col, need1(jstart), pfb[0], pfbb[0], b);
+    load_row(R, node_off(jstart - 1, N, col, sizeof(T)), need1(jstart - 1), bk[5], bb[5]);
+    load_row(R, node_off(jstart, N, col, sizeof(T)), need1(jstart), bk[0], bb[0]);
 #pragma unroll 1
-    for (int jb = jstart; jb < jend; jb += 3) {
+    for (int jb = jstart; jb < jend; jb += 6) {
 #pragma unroll
-        for (int ph = 0; ph < 3; ++ph) {
-            const int jx = jb + ph;  // slot ph
+        for (int ph = 0; ph < 6; ++ph) {
+            const int jx = jb + ph;  // x row entering: LDS slot x3
+            const int x3 = ph % 3;
             const int j1 = jx - 1, j2 = jx - 2, j3 = jx - 3, jr = jx - 4;
-            constexpr int dummy = 0;
-            (void)dummy;
-            const int s1 = (ph + 2) % 3, s2 = (ph + 1) % 3, s3 = ph;
-            // 1. x row jx into its slot; bands of row j1 into the register ring;
-            //    prefetch the next x row and the next band row
-            if (!XZERO) X[ph][t] = pfx[ph];
-            pfx[(ph + 2) % 3] = xload(jx + 2);
-            copy9(bk[s1], pfb[(ph + 2) % 3]);
-            bb[s1] = pfbb[(ph + 2) % 3];
-            load_band_row(bands, bs, N, jx + 1, col, need1(jx + 1), pfb[(ph + 1) % 3],
-                          pfbb[(ph + 1) % 3], b);
+            const int b1 = (ph + 5) % 6, b2 = (ph + 4) % 6, b3 = (ph + 3) % 6;
+            const int l1 = (x3 + 2) % 3, l2 = (x3 + 1) % 3;  // LDS slots of rows jx-1, jx-2
+            // 1. x row jx into LDS; prefetch x row jx+2 and the bands of row jx+1
+            if (!XZERO) X[x3][t] = pfx[x3];
+            pfx[(x3 + 2) % 3] = xload(jx + 2);
+            load_row(R, node_off(jx + 1, N, col, sizeof(T)), need1(jx + 1), bk[(ph + 1) % 6],
+                     bb[(ph + 1) % 6]);
             __syncthreads();
             // 2. first sweep at row j1
             {
                 T v = T(0);
                 if (c_op1 && in_range(j1, r0 - 3, r1 + 3) && in_range(j1, 0, N)) {
                     if (XZERO) {
-                        v = omega * bb[s1] / bk[s1][4];
+                        v = omega * bb[b1] / bk[b1][4];
                     } else {
-                        const T acc = band_row_product(bk[s1], X[(ph + 1) % 3], X[(ph + 2) % 3],
-                                                       X[ph], t);
-                        v = X[(ph + 2) % 3][t] + omega * (bb[s1] - acc) / bk[s1][4];
+                        const T acc = band_row_product(bk[b1], X[l2], X[l1], X[x3], t);
+                        v = X[l1][t] + omega * (bb[b1] - acc) / bk[b1][4];
                     }
                 }
-                A[s1][t] = v;
+                A[l1][t] = v;
             }
             __syncthreads();
             // 3. second sweep at row j2 (written on owned nodes)
             {
                 T v = T(0);
                 if (c_op2 && in_range(j2, r0 - 2, r1 + 2) && in_range(j2, 0, N)) {
-                    const T acc = band_row_product(bk[s2], A[(s2 + 2) % 3], A[s2], A[s1], t);
-                    v = A[s2][t] + omega * (bb[s2] - acc) / bk[s2][4];
+                    const T acc = band_row_product(bk[b2], A[x3], A[l2], A[l1], t);
+                    v = A[l2][t] + omega * (bb[b2] - acc) / bk[b2][4];
                     if (c_own && in_range(j2, r0, r1)) x2out[(int64_t)j2 * N + col] = v;
                 }
-                B[s2][t] = v;
+                B[l2][t] = v;
             }
             __syncthreads();
             // 4. defect at row j3
             {
                 T v = T(0);
                 if (c_op3 && in_range(j3, r0 - 1, r1 + 1) && in_range(j3, 0, N)) {
-                    const T acc = band_row_product(bk[s3], B[(s3 + 2) % 3], B[s3], B[s2], t);
-                    v = bb[s3] - acc;
+                    const T acc = band_row_product(bk[b3], B[l1], B[x3], B[l2], t);
+                    v = bb[b3] - acc;
                 }
-                D[s3][t] = v;
+                D[x3][t] = v;
             }
             __syncthreads();
             // 5. restriction of defect rows jr-1, jr, jr+1 to coarse row jr/2
@@ -179,9 +218,9 @@ __device__ void pre_tile(const T* __restrict__ bands, int64_t bs, int N, const T
                 const int I = col >> 1, J = jr >> 1;
                 T s = T(0);
                 if (I > 0 && J > 0 && I < Nc - 1 && J < Nc - 1) {
-                    const T* u = D[(ph + 1) % 3];  // row jr - 1
-                    const T* c = D[(ph + 2) % 3];  // row jr
-                    const T* o = D[ph];            // row jr + 1
+                    const T* u = D[l2];  // row jr - 1
+                    const T* c = D[l1];  // row jr
+                    const T* o = D[x3];  // row jr + 1
                     const T corner = (u[t - 1] + u[t + 1]) + (o[t - 1] + o[t + 1]);
                     const T edge = (u[t] + o[t]) + (c[t - 1] + c[t + 1]);
                     s = c[t] + T(0.5) * edge + T(0.25) * corner;
@@ -204,13 +243,16 @@ __device__ __forceinline__ T prolong_value(int Nf, const T* __restrict__ xc, int
     return T(0.25) * ((c[0] + c[1]) + (c[Nc] + c[Nc + 1]));
 }
 
-// Post-smoothing tile: x_out = J(J(x + P x_c)) on owned nodes; with NORM
-// also the thread's sum of squares of b - A x_out over its owned nodes.
+// Post-smoothing tile: x_out = J(J(x + P x_c)) on owned nodes.  With NORM
+// also rowpart[strip * N + j] = sum of (b - A x_out)^2 over the strip's owned
+// columns of row j, for the tile's owned rows: the partial sums do not
+// depend on how rows are split into chunks.  Same row pipeline and register
+// ring as pre_tile.
 template <typename T, bool NORM>
-__device__ double post_tile(const T* __restrict__ bands, int64_t bs, int N,
-                            const T* __restrict__ x, const T* __restrict__ xc,
-                            const T* __restrict__ b, T omega, T* __restrict__ xout, int strip,
-                            int chunk, int rh) {
+__device__ void post_tile(const T* __restrict__ bands, int64_t bs, int N, const T* __restrict__ x,
+                          const T* __restrict__ xc, const T* __restrict__ b, T omega,
+                          T* __restrict__ xout, double* __restrict__ rowpart, int strip, int chunk,
+                          int rh) {
     __shared__ T X[3][F_THREADS + 2], A[3][F_THREADS + 2], B[3][F_THREADS + 2];
     constexpr int H = NORM ? 3 : 2;  // halo the last step needs
     const int t = threadIdx.x + 1;
@@ -222,67 +264,72 @@ __device__ double post_tile(const T* __restrict__ bands, int64_t bs, int N,
     const bool c_op1 = cval && in_range(col, c0 - (H - 1), c1 + (H - 1));
     const bool c_op2 = cval && in_range(col, c0 - (H - 2), c1 + (H - 2));
     const bool c_own = in_range(col, c0, c1);
+    const int64_t n = (int64_t)N * N;
+    const RowRsrc<T> R(bands, bs, b, n);
+    const rsrc_t Rx = make_rsrc(x, n * (int64_t)sizeof(T));
     if (threadIdx.x < 2) {
         const int g = threadIdx.x ? F_THREADS + 1 : 0;
 #pragma unroll
         for (int s = 0; s < 3; ++s) X[s][g] = A[s][g] = B[s][g] = T(0);
     }
-    T bk[3][9], bb[3];
-    T pfb[3][9], pfbb[3], pfx[3];  // prefetch buffers as in pre_tile
-    double sq = 0.0;
-    const int jstart = r0 - F_HALO - ((((r0 - F_HALO) % 3) + 3) % 3);
+    T bk[6][9], bb[6];
+    T pfx[3];
+    const int jstart = r0 - F_HALO - ((((r0 - F_HALO) % 6) + 6) % 6);
     const int jend = r1 + 3;
     auto xrow = [&](int j) -> T {
         if (!c_x || !in_range(j, r0 - H, r1 + H) || !in_range(j, 0, N)) return T(0);
-        return x[(int64_t)j * N + col] + prolong_value(N, xc, col, j);
+        return bload<T>(Rx, node_off(j, N, col, sizeof(T))) + prolong_value(N, xc, col, j);
     };
     auto need1 = [&](int j) { return c_op1 && in_range(j, r0 - (H - 1), r1 + (H - 1)); };
     pfx[0] = xrow(jstart);
     pfx[1] = xrow(jstart + 1);
-    load_band_row(bands, bs, N, jstart - 1, col, need1(jstart - 1), pfb[2], pfbb[2], b);
-    load_band_row(bands, bs, N, jstart, col, need1(jstart), pfb[0], pfbb[0], b);
+    load_row(R, node_off(jstart - 1, N, col, sizeof(T)), need1(jstart - 1), bk[5], bb[5]);
+    load_row(R, node_off(jstart, N, col, sizeof(T)), need1(jstart), bk[0], bb[0]);
 #pragma unroll 1
-    for (int jb = jstart; jb < jend; jb += 3) {
+    for (int jb = jstart; jb < jend; jb += 6) {
 #pragma unroll
-        for (int ph = 0; ph < 3; ++ph) {
+        for (int ph = 0; ph < 6; ++ph) {
             const int jx = jb + ph;
+            const int x3 = ph % 3;
             const int j1 = jx - 1, j2 = jx - 2, j3 = jx - 3;
-            const int s1 = (ph + 2) % 3, s2 = (ph + 1) % 3, s3 = ph;
-            X[ph][t] = pfx[ph];
-            pfx[(ph + 2) % 3] = xrow(jx + 2);
-            copy9(bk[s1], pfb[(ph + 2) % 3]);
-            bb[s1] = pfbb[(ph + 2) % 3];
-            load_band_row(bands, bs, N, jx + 1, col, need1(jx + 1), pfb[(ph + 1) % 3],
-                          pfbb[(ph + 1) % 3], b);
+            const int b1 = (ph + 5) % 6, b2 = (ph + 4) % 6, b3 = (ph + 3) % 6;
+            const int l1 = (x3 + 2) % 3, l2 = (x3 + 1) % 3;
+            X[x3][t] = pfx[x3];
+            pfx[(x3 + 2) % 3] = xrow(jx + 2);
+            load_row(R, node_off(jx + 1, N, col, sizeof(T)), need1(jx + 1), bk[(ph + 1) % 6],
+                     bb[(ph + 1) % 6]);
             __syncthreads();
             {
                 T v = T(0);
                 if (c_op1 && in_range(j1, r0 - (H - 1), r1 + (H - 1)) && in_range(j1, 0, N)) {
-                    const T acc = band_row_product(bk[s1], X[(ph + 1) % 3], X[(ph + 2) % 3],
-                                                   X[ph], t);
-                    v = X[(ph + 2) % 3][t] + omega * (bb[s1] - acc) / bk[s1][4];
+                    const T acc = band_row_product(bk[b1], X[l2], X[l1], X[x3], t);
+                    v = X[l1][t] + omega * (bb[b1] - acc) / bk[b1][4];
                 }
-                A[s1][t] = v;
+                A[l1][t] = v;
             }
             __syncthreads();
             {
                 T v = T(0);
                 if (c_op2 && in_range(j2, r0 - (H - 2), r1 + (H - 2)) && in_range(j2, 0, N)) {
-                    const T acc = band_row_product(bk[s2], A[(s2 + 2) % 3], A[s2], A[s1], t);
-                    v = A[s2][t] + omega * (bb[s2] - acc) / bk[s2][4];
+                    const T acc = band_row_product(bk[b2], A[x3], A[l2], A[l1], t);
+                    v = A[l2][t] + omega * (bb[b2] - acc) / bk[b2][4];
                     if (c_own && in_range(j2, r0, r1)) xout[(int64_t)j2 * N + col] = v;
                 }
-                B[s2][t] = v;
+                B[l2][t] = v;
             }
             __syncthreads();
-            if (NORM && c_own && in_range(j3, r0, r1)) {
-                const T acc = band_row_product(bk[s3], B[(s3 + 2) % 3], B[s3], B[s2], t);
-                const T d = bb[s3] - acc;
-                sq += (double)d * (double)d;
+            if (NORM && in_range(j3, r0, r1)) {
+                double dd = 0.0;
+                if (c_own) {
+                    const T acc = band_row_product(bk[b3], B[l1], B[x3], B[l2], t);
+                    const T d = bb[b3] - acc;
+                    dd = (double)d * (double)d;
+                }
+                const double srow = block_sum(dd);
+                if (threadIdx.x == 0) rowpart[(int64_t)strip * N + j3] = srow;
             }
         }
     }
-    return sq;
 }
 
 // ---------------------------------------------------------------- coarse tail

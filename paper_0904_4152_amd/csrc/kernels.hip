@@ -109,7 +109,8 @@ __global__ __launch_bounds__(dev::F_THREADS) void k_pre(const T* __restrict__ ba
                             (int)(lb / nstrips), rh);
 }
 
-// Fused post-smoothing pass; with NORM one partial sum of squares per tile.
+// Fused post-smoothing pass; with NORM one partial sum of squares per
+// (strip, grid row) in partials.
 template <typename T, bool NORM>
 __global__ __launch_bounds__(dev::F_THREADS) void k_post(const T* __restrict__ bands, int64_t bs,
                                                          int N, const T* __restrict__ x,
@@ -120,12 +121,8 @@ __global__ __launch_bounds__(dev::F_THREADS) void k_post(const T* __restrict__ b
                                                          int nstrips, int nchunks, int rh) {
     const int64_t lb = xcd_block((int64_t)nstrips * nchunks);
     if (lb < 0) return;
-    const double sq = dev::post_tile<T, NORM>(bands, bs, N, x, xc, b, omega, xout,
-                                              (int)(lb % nstrips), (int)(lb / nstrips), rh);
-    if (NORM) {
-        const double s = dev::block_sum(sq);
-        if (threadIdx.x == 0) partials[lb] = s;
-    }
+    dev::post_tile<T, NORM>(bands, bs, N, x, xc, b, omega, xout, partials, (int)(lb % nstrips),
+                            (int)(lb / nstrips), rh);
 }
 
 // Coarse tail: the V(2,2) sub-cycle over levels top..Lc in one workgroup.
@@ -522,6 +519,18 @@ int fused_rows(int N) {
 
 int dev_fused_cols() { return dev::F_CW; }
 
+// Owned rows per fused tile in the batched engine, where many problems fill
+// the device: longer chunks waste less on the recomputed halo rows.
+int batch_fused_rows(int N) {
+    static const int rh = [] {
+        const char* e = getenv("MG_BATCH_RH");
+        const int v = e ? atoi(e) : 32;
+        return (v >= 4 && v % 2 == 0) ? v : 32;
+    }();
+    (void)N;
+    return rh;
+}
+
 int64_t fused_tiles(int N) {
     const dev::FusedGeom g = dev::fused_geom(N, fused_rows(N));
     return (int64_t)g.nstrips * g.nchunks;
@@ -554,7 +563,8 @@ hipError_t launch_post(const Level& lv, const T* bands, const T* x, const T* xc,
                            g.nchunks, g.rh);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(BLOCK), 0, st, partials, nt, scal, slot);
+        hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(BLOCK), 0, st, partials,
+                           (int64_t)g.nstrips * lv.N, scal, slot);
     } else {
         hipLaunchKernelGGL((k_post<T, false>), dim3(grid8(nt)), dim3(dev::F_THREADS), 0, st,
                            bands, lv.bs, lv.N, x, xc, b, omega, xout, (double*)nullptr,

@@ -152,6 +152,7 @@ int tail_max_level();
 int fused_rows(int N);
 int64_t fused_tiles(int N);
 int dev_fused_cols();  // owned columns per fused strip
+int batch_fused_rows(int N);
 
 // Workgroups (= tiles) of a band-product launch and of a vector-norm launch.
 int64_t stencil_blocks(int64_t n, int elem_bytes);

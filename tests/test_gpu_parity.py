@@ -421,3 +421,45 @@ def test_fused_cycle_equals_unfused_bitwise(mg, ctx, L, a, dtype):
     st_f = h.solve(b.double(), torch.zeros(n, dtype=torch.float64, device="cuda"),
                    mg.default_opts(precision=mg.MG_PREC_MIXED, fixed_cycles=2))
     assert st_f.status == 0
+
+
+@pytest.mark.parametrize("L,a", [(2, 0.0), (6, 0.2), (10, 0.2)])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_fused_passes_match_oracle(mg, ctx, orc, L, a, dtype):
+    """Pre pass = two damped Jacobi sweeps, defect, restriction with boundary
+    filter; post pass = prolongation/correction and two sweeps (+ residual
+    norm); each against the oracle's operators on the device bands."""
+    h = mg.Hierarchy(ctx, L, jitter=a, seed=60 + L)
+    N, Nc = (1 << L) + 1, (1 << (L - 1)) + 1
+    np_dt = np.float64 if dtype == torch.float64 else np.float32
+    u = U64 if dtype == torch.float64 else U32
+    bands = h.bands(L, dtype).astype(np.float64)
+    rng = np.random.default_rng(L + 7)
+    x = rng.standard_normal(N * N).astype(np_dt).astype(np.float64)
+    b = rng.standard_normal(N * N).astype(np_dt).astype(np.float64)
+    om = float(np_dt(0.7))
+    # pre pass against oracle operators (FP64 evaluation of the same inputs)
+    x2 = torch.empty(N * N, dtype=dtype, device="cuda")
+    bc = torch.empty(Nc * Nc, dtype=dtype, device="cuda")
+    h.pre_smooth(L, dev(b, dtype), dev(x, dtype), x2, bc, omega=om)
+    x1 = orc.jacobi(N, bands, b, x, om)
+    x2r = orc.jacobi(N, bands, b, x1, om)
+    scale = np.max(np.abs(x2r)) + np.max(np.abs(b))
+    assert_within(host(x2), x2r, 64 * u * scale, "pre x2")
+    bcr = orc.restrict(N, orc.defect(N, bands, b, host(x2)), filter=True)
+    sc = orc.restrict(N, np.abs(b) + abs_band_product(N, bands, host(x2)), filter=True)
+    assert_within(host(bc), bcr, 16 * u * sc, "pre restriction")
+    # from a zero iterate
+    h.pre_smooth(L, dev(b, dtype), dev(x, dtype), x2, bc, x_zero=True, omega=om)
+    x2z = orc.jacobi(N, bands, b, orc.jacobi(N, bands, b, np.zeros(N * N), om), om)
+    assert_within(host(x2), x2z, 64 * u * (np.max(np.abs(x2z)) + np.max(np.abs(b))), "pre zero")
+    # post pass
+    xc = rng.standard_normal(Nc * Nc).astype(np_dt).astype(np.float64)
+    xc[~synth.interior_mask(L - 1)] = 0.0
+    xo = torch.empty(N * N, dtype=dtype, device="cuda")
+    nrm = h.post_smooth(L, dev(b, dtype), dev(x, dtype), dev(xc, dtype), xo, omega=om, norm=True)
+    xp = orc.prolong_add(N, xc, x)
+    xr = orc.jacobi(N, bands, b, orc.jacobi(N, bands, b, xp, om), om)
+    assert_within(host(xo), xr, 64 * u * (np.max(np.abs(xr)) + np.max(np.abs(b))), "post")
+    dref = orc.norm2(orc.defect(N, bands, b, host(xo)))
+    assert abs(nrm - dref) <= 64 * u * (orc.norm2(b) + orc.norm2(abs_band_product(N, bands, host(xo))))
