@@ -7,6 +7,7 @@
 #include <new>
 #include <string>
 
+#include "device_ops.h"
 #include "mg_internal.h"
 #include "solve.h"
 
@@ -26,11 +27,17 @@ int64_t vec_len(int64_t n) { return (n + 63) / 64 * 64; }
 int64_t band_stride(int64_t n) { return (n + 1023) / 1024 * 1024 + 64; }
 
 // Partial sums a reduction on the finest level of a level-L hierarchy can
-// produce: FP64 band-product tiles, or one per (fused strip, grid row).
+// produce: FP64 band-product tiles, or the fused post pass's per-row ones.
 static int64_t max_partials(int L) {
     const int64_t N = (int64_t(1) << L) + 1;
-    const int64_t fused = ((N + dev_fused_cols() - 1) / dev_fused_cols()) * N;
+    const int64_t fused = fused_max_norm_parts(N);
     return std::max(stencil_blocks(N * N, 8), fused);
+}
+
+// The partials buffer: partials, padding to 64, then the segment sums of a
+// two-stage reduction.
+static int64_t partials_len(int L) {
+    return (max_partials(L) + 63) / 64 * 64 + dev::RED_MAX_SEGS + 64;
 }
 
 // Bytes of every device array of a hierarchy, in allocation order.
@@ -46,7 +53,7 @@ static void hierarchy_arrays(int L, int Lc, std::vector<size_t>& sizes) {
         for (int v = 0; v < 3; ++v) sizes.push_back(vl * sizeof(float));
     }
     sizes.push_back(vec_len(nL) * sizeof(double));                    // d64
-    sizes.push_back((max_partials(L) + 64) * sizeof(double));           // partials
+    sizes.push_back(partials_len(L) * sizeof(double));                  // partials
     sizes.push_back(64 * sizeof(double));                             // scal
     const int mi = (1 << Lc) - 1;
     sizes.push_back(std::max<size_t>(1, (size_t)mi * mi * mi * mi) * sizeof(double));  // chol
@@ -234,7 +241,7 @@ mg_status mg_hierarchy_create(mg_context* ctx, int L, int Lc, double jitter, uin
     }
     h->d64 = (double*)ptrs[a++];
     h->partials = (double*)ptrs[a++];
-    h->n_partials = max_partials(L) + 64;
+    h->n_partials = partials_len(L);
     h->scal = (double*)ptrs[a++];
     h->chol = (double*)ptrs[a++];
     h->flag = (int*)ptrs[a++];

@@ -22,6 +22,8 @@ struct BLevel {
     int64_t n;
     int N;
     int rh;        // owned rows per fused tile
+    int cw;        // owned columns per fused strip
+    int bt;        // threads per fused workgroup
     int nstrips;   // fused tiles: nstrips x nchunks
     int nchunks;
 };
@@ -104,6 +106,10 @@ private:
     std::vector<char> started_;
     bool probs_dirty_ = true;
     hipGraphExec_t graph_ = nullptr;
+    // Optional launches present in the captured graph: bit l for the fused
+    // passes at level l, bit 0 for the residual of problems with no level
+    // above the coarse one.  The set only grows (a new bit recaptures).
+    uint32_t launch_mask_ = 0;
     double step_bytes_ = 0.0;
 };
 

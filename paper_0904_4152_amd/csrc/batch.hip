@@ -15,6 +15,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
+#include <new>
 
 #include "batch.h"
 #include "device_ops.h"
@@ -26,9 +28,10 @@ namespace {
 
 using dev::BLOCK;
 
-constexpr int NLISTS = 50;
+constexpr int NLISTS = 51;
 constexpr int WL_FINEST = 32;
 constexpr int WL_ALL = 33;
+constexpr int WL_FINEST_COARSE = 50;  // finest tiles of problems with L = Lc
 inline int wl_level(int l) { return l; }
 inline int wl_restrict(int l) { return 16 + l; }
 inline int wl_fused(int l) { return 34 + l; }
@@ -225,41 +228,41 @@ __global__ __launch_bounds__(BLOCK) void kb_coarse(const BProb* __restrict__ pro
 
 // Fused pre-smoothing pass at level l (two sweeps, defect, restriction) for
 // the problems in their inner loop; iterate x -> t, coarse rhs at l-1.
-__global__ __launch_bounds__(dev::F_THREADS) void kb_fpre(const BProb* __restrict__ probs,
-                                                          const BState* __restrict__ state,
-                                                          const int* __restrict__ wl, int l,
-                                                          int mask) {
+template <int BT>
+__global__ __launch_bounds__(BT) void kb_fpre(const BProb* __restrict__ probs,
+                                              const BState* __restrict__ state,
+                                              const int* __restrict__ wl, int l, int mask) {
     FOR_ITEMS(wl)
     if (!(flags & mask)) continue;
     const BLevel& lv = P.lv[l];
     const int strip = tile % lv.nstrips, chunk = tile / lv.nstrips;
     const float om = (float)P.omega;
     if (l < P.L || state[p].first)
-        dev::pre_tile<float, true>(lv.bands32, lv.bs, lv.N, lv.x32, lv.b32, om, lv.t32,
-                                   P.lv[l - 1].b32, strip, chunk, lv.rh);
+        dev::pre_tile<float, true, BT>(lv.bands32, lv.bs, lv.N, lv.x32, lv.b32, om, lv.t32,
+                                       P.lv[l - 1].b32, strip, chunk, lv.rh, lv.cw);
     else
-        dev::pre_tile<float, false>(lv.bands32, lv.bs, lv.N, lv.x32, lv.b32, om, lv.t32,
-                                    P.lv[l - 1].b32, strip, chunk, lv.rh);
+        dev::pre_tile<float, false, BT>(lv.bands32, lv.bs, lv.N, lv.x32, lv.b32, om, lv.t32,
+                                        P.lv[l - 1].b32, strip, chunk, lv.rh, lv.cw);
     END_ITEMS
 }
 
 // Fused post-smoothing pass at level l (prolongation, two sweeps: t -> x);
 // on the problem's finest level also the residual-norm partials.
-__global__ __launch_bounds__(dev::F_THREADS) void kb_fpost(const BProb* __restrict__ probs,
-                                                           const BState* __restrict__ state,
-                                                           const int* __restrict__ wl, int l,
-                                                           int mask) {
+template <int BT>
+__global__ __launch_bounds__(BT) void kb_fpost(const BProb* __restrict__ probs,
+                                               const BState* __restrict__ state,
+                                               const int* __restrict__ wl, int l, int mask) {
     FOR_ITEMS(wl)
     if (!(flags & mask)) continue;
     const BLevel& lv = P.lv[l];
     const int strip = tile % lv.nstrips, chunk = tile / lv.nstrips;
     const float om = (float)P.omega;
     if (l == P.L)
-        dev::post_tile<float, true>(lv.bands32, lv.bs, lv.N, lv.t32, P.lv[l - 1].x32, lv.b32, om,
-                                    lv.x32, P.partials, strip, chunk, lv.rh);
+        dev::post_tile<float, true, BT>(lv.bands32, lv.bs, lv.N, lv.t32, P.lv[l - 1].x32, lv.b32,
+                                        om, lv.x32, P.partials, strip, chunk, lv.rh, lv.cw);
     else
-        dev::post_tile<float, false>(lv.bands32, lv.bs, lv.N, lv.t32, P.lv[l - 1].x32, lv.b32, om,
-                                     lv.x32, nullptr, strip, chunk, lv.rh);
+        dev::post_tile<float, false, BT>(lv.bands32, lv.bs, lv.N, lv.t32, P.lv[l - 1].x32,
+                                         lv.b32, om, lv.x32, nullptr, strip, chunk, lv.rh, lv.cw);
     END_ITEMS
 }
 
@@ -362,7 +365,7 @@ __global__ __launch_bounds__(BLOCK) void kb_finalize(const BProb* __restrict__ p
                                : (n + TILE - 1) / TILE;
     // the inner residual comes from the fused post pass above the coarse level
     if (kind == K_S32 && fused_above >= 0 && P.L > fused_above)
-        np = (int64_t)F.nstrips * F.N;  // per (strip, row) partials of the fused post pass
+        np = (int64_t)F.nstrips * (F.bt / 64) * F.N;  // per-row partials of the fused post pass
     const double s = dev::reduce_partials(P.partials, np);
     if (threadIdx.x == 0) {
         const double r = sqrt(s);
@@ -493,8 +496,10 @@ void BatchEngine::set_slot(int s, mg_hierarchy* h, const mg_solve_opts& o) {
         b.bs = v.bs;
         b.n = v.n;
         b.N = v.N;
-        const dev::FusedGeom g = dev::fused_geom(v.N, batch_fused_rows(v.N));
+        const dev::FusedGeom g = batch_geom(v.N);
         b.rh = g.rh;
+        b.cw = g.cw;
+        b.bt = g.bt;
         b.nstrips = g.nstrips;
         b.nchunks = g.nchunks;
     }
@@ -555,7 +560,19 @@ void BatchEngine::build_lists() {
     }
     fill(WL_FINEST, [](const BProb&) { return true; },
          [&](const BProb& P) { return ntiles(P.lv[P.L].n); });
+    fill(WL_FINEST_COARSE, [&](const BProb& P) { return P.L == Lc_; },
+         [&](const BProb& P) { return ntiles(P.lv[P.L].n); });
     fill(WL_ALL, [](const BProb&) { return true; }, [](const BProb&) { return 1; });
+    // optional launches this composition needs; a new one invalidates the graph
+    uint32_t need = 0;
+    for (int l = Lc_ + 1; l <= Lmax_; ++l)
+        if (h_wl_[(size_t)wl_fused(l) * stride] > 0) need |= 1u << l;
+    if (h_wl_[(size_t)WL_FINEST_COARSE * stride] > 0) need |= 1u;
+    if (need & ~launch_mask_) {
+        launch_mask_ |= need;
+        if (graph_) (void)hipGraphExecDestroy(graph_);
+        graph_ = nullptr;
+    }
 }
 
 mg_status BatchEngine::upload() {
@@ -614,15 +631,27 @@ hipError_t BatchEngine::enqueue_iteration() {
     const int m = BF_INNER;
     const bool fused = nu_pre_ == 2 && nu_post_ == 2;
     if (fused) {
-        const dim3 GF(STAGE_GRID), BF(dev::F_THREADS);
+#define FUSED(KERNEL, l)                                                                  \
+    {                                                                                     \
+        const int bt = fused_bt((1 << (l)) + 1);                                          \
+        const dim3 GF(STAGE_GRID * (dev::F_MAX_THREADS / bt)), BF(bt);                    \
+        switch (bt) {                                                                     \
+            case 64: LAUNCH(KERNEL<64>, GF, BF, 0, st_, P, S, W(wl_fused(l)), l, m); break;   \
+            case 128: LAUNCH(KERNEL<128>, GF, BF, 0, st_, P, S, W(wl_fused(l)), l, m); break; \
+            case 192: LAUNCH(KERNEL<192>, GF, BF, 0, st_, P, S, W(wl_fused(l)), l, m); break; \
+            default: LAUNCH(KERNEL<256>, GF, BF, 0, st_, P, S, W(wl_fused(l)), l, m); break;  \
+        }                                                                                 \
+    }
         for (int l = Lmax_; l > Lc_; --l)
-            LAUNCH(kb_fpre, GF, BF, 0, st_, P, S, W(wl_fused(l)), l, m);
+            if (launch_mask_ & (1u << l)) FUSED(kb_fpre, l)
         LAUNCH(kb_tail, GA, B, 0, st_, P, S, W(WL_ALL), Lc_, m);
         LAUNCH(kb_coarse, GA, B, 0, st_, P, S, W(WL_ALL), Lc_, m, Lc_);
         for (int l = Lc_ + 1; l <= Lmax_; ++l)
-            LAUNCH(kb_fpost, GF, BF, 0, st_, P, S, W(wl_fused(l)), l, m);
+            if (launch_mask_ & (1u << l)) FUSED(kb_fpost, l)
+#undef FUSED
         // problems without a level above the coarse one: residual from a defect pass
-        LAUNCH(kb_inner_norm, G, B, 0, st_, P, S, W(WL_FINEST), m, Lc_);
+        if (launch_mask_ & 1u)
+            LAUNCH(kb_inner_norm, G, B, 0, st_, P, S, W(WL_FINEST_COARSE), m, Lc_);
         LAUNCH(kb_finalize, GA, B, 0, st_, P, S, W(WL_ALL), (int)K_S32, (int)F_R32, m, Lc_);
         LAUNCH(kb_ctrl, G1, B, 0, st_, P, S, cap_, (int)PH_INNER, d_active_);
         return hipSuccess;
@@ -742,6 +771,54 @@ void fill_stats(const BState& S, int L, int Lc, int nu_pre, int nu_post, mg_stat
 
 using namespace mg;
 
+namespace {
+
+// Idle batch engines kept between mg_solve_batch calls, so that repeated
+// batches reuse the device descriptors, work-list buffers and the captured
+// iteration graph.  An engine serves one call at a time; it is taken out of
+// the pool for the call.  The pool lives until the process ends (device
+// memory of a few MB per engine; never destroyed during static teardown).
+struct EnginePool {
+    struct Entry {
+        int device, Lmax, Lc, nu_pre, nu_post;
+        BatchEngine* eng;
+    };
+    std::mutex mu;
+    std::vector<Entry> idle;  // oldest first
+    static constexpr size_t MAX_IDLE = 4;
+
+    BatchEngine* take(int device, int count, int Lmax, int Lc, int nu_pre, int nu_post) {
+        std::lock_guard<std::mutex> g(mu);
+        int best = -1;
+        for (int i = 0; i < (int)idle.size(); ++i) {
+            const Entry& e = idle[i];
+            if (e.device == device && e.Lmax == Lmax && e.Lc == Lc && e.nu_pre == nu_pre &&
+                e.nu_post == nu_post && e.eng->capacity() >= count &&
+                (best < 0 || e.eng->capacity() < idle[best].eng->capacity()))
+                best = i;
+        }
+        if (best < 0) return nullptr;
+        BatchEngine* eng = idle[best].eng;
+        idle.erase(idle.begin() + best);
+        return eng;
+    }
+    void give(int device, int Lmax, int Lc, int nu_pre, int nu_post, BatchEngine* eng) {
+        std::lock_guard<std::mutex> g(mu);
+        idle.push_back({device, Lmax, Lc, nu_pre, nu_post, eng});
+        if (idle.size() > MAX_IDLE) {
+            delete idle.front().eng;
+            idle.erase(idle.begin());
+        }
+    }
+};
+
+EnginePool& engine_pool() {
+    static EnginePool* pool = new EnginePool();
+    return *pool;
+}
+
+}  // namespace
+
 extern "C" mg_status mg_solve_batch(mg_hierarchy* const* hs, const double* const* b,
                                     double* const* x, int count, const mg_solve_opts* opts,
                                     void* stream, mg_stats* stats) {
@@ -772,11 +849,34 @@ extern "C" mg_status mg_solve_batch(mg_hierarchy* const* hs, const double* const
             return fail(MG_ERR_INVALID, "invalid solver options");
         Lmax = std::max(Lmax, h->L);
     }
-    MG_HIP(hipSetDevice(hs[0]->ctx->device));
-    BatchEngine eng;
-    if (mg_status s = eng.init(hs[0]->ctx->device, count, Lmax, hs[0]->Lc, o0.nu_pre, o0.nu_post))
-        return s;
+    const int device = hs[0]->ctx->device, Lc = hs[0]->Lc;
+    MG_HIP(hipSetDevice(device));
     MG_HIP(hipStreamSynchronize((hipStream_t)stream));
+    EnginePool& pool = engine_pool();
+    BatchEngine* taken = pool.take(device, count, Lmax, Lc, o0.nu_pre, o0.nu_post);
+    if (!taken) {
+        taken = new (std::nothrow) BatchEngine();
+        if (!taken) return fail(MG_ERR_NOMEM, "host allocation failed");
+        if (mg_status s = taken->init(device, count, Lmax, Lc, o0.nu_pre, o0.nu_post)) {
+            delete taken;
+            return s;
+        }
+    }
+    // back to the pool on every exit path, unless the device failed under it
+    struct Return {
+        EnginePool& pool;
+        BatchEngine* eng;
+        int device, Lmax, Lc, nu_pre, nu_post;
+        bool ok = false;
+        ~Return() {
+            if (ok)
+                pool.give(device, Lmax, Lc, nu_pre, nu_post, eng);
+            else
+                delete eng;
+        }
+    } ret{pool, taken, device, Lmax, Lc, o0.nu_pre, o0.nu_post};
+    BatchEngine& eng = *taken;
+    for (int s = count; s < eng.capacity(); ++s) eng.clear_slot(s);
     int64_t iter_cap = 8;
     for (int p = 0; p < count; ++p) {
         mg_hierarchy* h = hs[p];
@@ -812,6 +912,7 @@ extern "C" mg_status mg_solve_batch(mg_hierarchy* const* hs, const double* const
         }
     }
     MG_HIP(hipStreamSynchronize(eng.stream()));
+    ret.ok = true;
     if (worst != MG_OK) return fail(worst, "at least one problem of the batch did not converge");
     return MG_OK;
 }

@@ -41,8 +41,9 @@ constexpr int NORM_TILE = BLOCK * 4;
 // Deterministic block sum (wave shuffles, then the waves in order); the
 // result is valid in thread 0.  Every thread of the block must call it; it
 // may be called repeatedly in a loop.
+template <int NT = BLOCK>
 __device__ __forceinline__ double block_sum(double v) {
-    __shared__ double ws[BLOCK / 64];
+    __shared__ double ws[NT / 64];
     __syncthreads();
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -51,7 +52,7 @@ __device__ __forceinline__ double block_sum(double v) {
     double s = 0.0;
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int w = 0; w < BLOCK / 64; ++w) s += ws[w];
+        for (int w = 0; w < NT / 64; ++w) s += ws[w];
     }
     return s;
 }
@@ -232,12 +233,32 @@ __device__ __forceinline__ double sumsq_tile(const T* __restrict__ v, int64_t n,
     return s;
 }
 
-// Fixed-order sum of np partials (one block); valid in thread 0.
+constexpr int64_t RED_SEG = 8192;  // partials per first-stage segment
+constexpr int RED_MAX_SEGS = 1024;  // so at most 8M partials
+
+// Thread-strided sum of p[lo, hi) then block_sum; valid in thread 0.
+__device__ __forceinline__ double strided_sum(const double* __restrict__ p, int64_t lo,
+                                              int64_t hi) {
+    double s = 0.0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += BLOCK) s += p[i];
+    return block_sum(s);
+}
+
+// Fixed-order sum of np partials (one block); valid in thread 0.  Up to
+// RED_SEG partials take one strided pass; more are summed in segments of
+// RED_SEG whose sums are then summed the same way, which a grid of segment
+// blocks followed by one final block reproduces bit for bit.
 __device__ __forceinline__ double reduce_partials(const double* __restrict__ partials,
                                                   int64_t np) {
-    double s = 0.0;
-    for (int64_t i = threadIdx.x; i < np; i += BLOCK) s += partials[i];
-    return block_sum(s);
+    if (np <= RED_SEG) return strided_sum(partials, 0, np);
+    __shared__ double segs[RED_MAX_SEGS];
+    const int64_t ns = (np + RED_SEG - 1) / RED_SEG;
+    for (int64_t sg = 0; sg < ns; ++sg) {
+        const double v = strided_sum(partials, sg * RED_SEG, min(np, (sg + 1) * RED_SEG));
+        if (threadIdx.x == 0) segs[sg] = v;
+    }
+    __syncthreads();
+    return strided_sum(segs, 0, ns);
 }
 
 }  // namespace dev

@@ -27,18 +27,27 @@
 namespace mg {
 namespace dev {
 
-constexpr int F_THREADS = 256;                // one grid column per thread
-constexpr int F_HALO = 4;                     // columns / rows recomputed per side
-constexpr int F_CW = F_THREADS - 2 * F_HALO;  // owned columns per strip (even)
+constexpr int F_HALO = 4;           // columns / rows recomputed per side
+constexpr int F_MIN_THREADS = 64;   // workgroup widths: 64, 128, 192 or 256 threads,
+constexpr int F_MAX_THREADS = 256;  // one grid column per thread
 
 struct FusedGeom {
-    int nstrips, nchunks, rh;  // rh: owned rows per chunk (even)
+    int bt;       // threads per workgroup
+    int cw;       // owned columns per strip (even, at most bt - 2 F_HALO)
+    int nstrips;  // strips of cw columns (the last one may be narrower)
+    int nchunks;  // chunks of rh rows
+    int rh;       // owned rows per chunk (even)
 };
 
-__host__ __device__ inline FusedGeom fused_geom(int N, int rh) {
+// Strips of equal width (rounded up to even) as few as bt threads allow.
+__host__ __device__ inline FusedGeom fused_geom(int N, int bt, int rh) {
     FusedGeom g;
+    g.bt = bt;
     g.rh = rh;
-    g.nstrips = (N + F_CW - 1) / F_CW;
+    const int cmax = bt - 2 * F_HALO;
+    g.nstrips = (N + cmax - 1) / cmax;
+    g.cw = (N + g.nstrips - 1) / g.nstrips;
+    g.cw += g.cw & 1;
     g.nchunks = (N + rh - 1) / rh;
     return g;
 }
@@ -126,14 +135,13 @@ __device__ __forceinline__ uint32_t node_off(int j, int N, int col, int size) {
 // iterate and x is not read.  Band rows live in a ring of six register slots
 // (row r in slot r mod 6; the loop is unrolled by six) so that the load of a
 // row lands in its slot two steps before its first use.
-template <typename T, bool XZERO>
+template <typename T, bool XZERO, int BT>
 __device__ void pre_tile(const T* __restrict__ bands, int64_t bs, int N, const T* __restrict__ x,
                          const T* __restrict__ b, T omega, T* __restrict__ x2out,
-                         T* __restrict__ bc, int strip, int chunk, int rh) {
-    __shared__ T X[3][F_THREADS + 2], A[3][F_THREADS + 2], B[3][F_THREADS + 2],
-        D[3][F_THREADS + 2];
-    const int t = threadIdx.x + 1;  // LDS column; 0 and F_THREADS+1 are guards
-    const int c0 = strip * F_CW, c1 = min(c0 + F_CW, N);
+                         T* __restrict__ bc, int strip, int chunk, int rh, int cw) {
+    __shared__ T X[3][BT + 2], A[3][BT + 2], B[3][BT + 2], D[3][BT + 2];
+    const int t = threadIdx.x + 1;  // LDS column; 0 and BT+1 are guards
+    const int c0 = strip * cw, c1 = min(c0 + cw, N);
     const int r0 = chunk * rh, r1 = min(r0 + rh, N);
     const int col = c0 - F_HALO + (int)threadIdx.x;
     const bool cval = col >= 0 && col < N;
@@ -147,7 +155,7 @@ __device__ void pre_tile(const T* __restrict__ bands, int64_t bs, int N, const T
     const RowRsrc<T> R(bands, bs, b, n);
     const rsrc_t Rx = make_rsrc(x, n * (int64_t)sizeof(T));
     if (threadIdx.x < 2) {
-        const int g = threadIdx.x ? F_THREADS + 1 : 0;
+        const int g = threadIdx.x ? BT + 1 : 0;
 #pragma unroll
         for (int s = 0; s < 3; ++s) X[s][g] = A[s][g] = B[s][g] = D[s][g] = T(0);
     }
@@ -243,20 +251,34 @@ __device__ __forceinline__ T prolong_value(int Nf, const T* __restrict__ xc, int
     return T(0.25) * ((c[0] + c[1]) + (c[Nc] + c[Nc + 1]));
 }
 
+// Partial sums of squares a fused post pass with NORM writes: one per
+// (strip, wavefront, grid row).
+__host__ __device__ inline int64_t fused_norm_parts(const FusedGeom& g, int N) {
+    return (int64_t)g.nstrips * (g.bt / 64) * N;
+}
+
+// Sum over the 64 lanes of a wavefront (butterfly, fixed order).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
 // Post-smoothing tile: x_out = J(J(x + P x_c)) on owned nodes.  With NORM
-// also rowpart[strip * N + j] = sum of (b - A x_out)^2 over the strip's owned
-// columns of row j, for the tile's owned rows: the partial sums do not
-// depend on how rows are split into chunks.  Same row pipeline and register
-// ring as pre_tile.
-template <typename T, bool NORM>
+// also rowpart[(strip * (BT / 64) + w) * N + j] = sum of (b - A x_out)^2 over
+// the owned columns of row j that wavefront w holds, for the tile's owned
+// rows: the partial sums do not depend on how rows are split into chunks,
+// and need no workgroup barrier.  Same row pipeline and register ring as
+// pre_tile.
+template <typename T, bool NORM, int BT>
 __device__ void post_tile(const T* __restrict__ bands, int64_t bs, int N, const T* __restrict__ x,
                           const T* __restrict__ xc, const T* __restrict__ b, T omega,
                           T* __restrict__ xout, double* __restrict__ rowpart, int strip, int chunk,
-                          int rh) {
-    __shared__ T X[3][F_THREADS + 2], A[3][F_THREADS + 2], B[3][F_THREADS + 2];
+                          int rh, int cw) {
+    __shared__ T X[3][BT + 2], A[3][BT + 2], B[3][BT + 2];
     constexpr int H = NORM ? 3 : 2;  // halo the last step needs
     const int t = threadIdx.x + 1;
-    const int c0 = strip * F_CW, c1 = min(c0 + F_CW, N);
+    const int c0 = strip * cw, c1 = min(c0 + cw, N);
     const int r0 = chunk * rh, r1 = min(r0 + rh, N);
     const int col = c0 - F_HALO + (int)threadIdx.x;
     const bool cval = col >= 0 && col < N;
@@ -268,7 +290,7 @@ __device__ void post_tile(const T* __restrict__ bands, int64_t bs, int N, const 
     const RowRsrc<T> R(bands, bs, b, n);
     const rsrc_t Rx = make_rsrc(x, n * (int64_t)sizeof(T));
     if (threadIdx.x < 2) {
-        const int g = threadIdx.x ? F_THREADS + 1 : 0;
+        const int g = threadIdx.x ? BT + 1 : 0;
 #pragma unroll
         for (int s = 0; s < 3; ++s) X[s][g] = A[s][g] = B[s][g] = T(0);
     }
@@ -325,8 +347,9 @@ __device__ void post_tile(const T* __restrict__ bands, int64_t bs, int N, const 
                     const T d = bb[b3] - acc;
                     dd = (double)d * (double)d;
                 }
-                const double srow = block_sum(dd);
-                if (threadIdx.x == 0) rowpart[(int64_t)strip * N + j3] = srow;
+                dd = wave_sum(dd);
+                if ((threadIdx.x & 63) == 0)
+                    rowpart[((int64_t)strip * (BT / 64) + (threadIdx.x >> 6)) * N + j3] = dd;
             }
         }
     }

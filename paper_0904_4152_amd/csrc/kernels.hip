@@ -89,40 +89,64 @@ __global__ __launch_bounds__(BLOCK) void k_prolong(int Nf, const T* __restrict__
     if (i < Nf) dev::prolong_elem(Nf, xc, xf, i, (int)blockIdx.y);
 }
 
+// First stage of a segmented reduction: one block per RED_SEG partials.
+__global__ __launch_bounds__(BLOCK) void k_reduce_segs(const double* __restrict__ partials,
+                                                       int64_t np, double* __restrict__ segs) {
+    const int64_t sg = blockIdx.x;
+    const double v = dev::strided_sum(partials, sg * dev::RED_SEG,
+                                      std::min<int64_t>(np, (sg + 1) * dev::RED_SEG));
+    if (threadIdx.x == 0) segs[sg] = v;
+}
+
+// scal[slot] = sum of the np partials (the order of dev::reduce_partials),
+// scal[slot + 1] = its square root.  Segment sums go right after the
+// partials, which the partials buffer leaves room for.
+hipError_t launch_reduce(double* partials, int64_t np, double* scal, int slot, hipStream_t st) {
+    if (np <= dev::RED_SEG) {
+        hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(BLOCK), 0, st, partials, np, scal, slot);
+        return hipGetLastError();
+    }
+    const int64_t ns = (np + dev::RED_SEG - 1) / dev::RED_SEG;
+    if (ns > dev::RED_MAX_SEGS) return hipErrorInvalidValue;
+    double* segs = partials + (np + 63) / 64 * 64;
+    hipLaunchKernelGGL(k_reduce_segs, dim3(ns), dim3(BLOCK), 0, st, partials, np, segs);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(BLOCK), 0, st, segs, ns, scal, slot);
+    return hipGetLastError();
+}
+
 template <typename T>
 __global__ void k_coarse(const double* __restrict__ chol, int m, int Nc,
                          const T* __restrict__ b, T* __restrict__ x) {
     dev::coarse_block(chol, m, Nc, b, x);
 }
 
-// Fused pre-smoothing pass: one (strip, chunk) tile per workgroup.
-template <typename T, bool XZERO>
-__global__ __launch_bounds__(dev::F_THREADS) void k_pre(const T* __restrict__ bands, int64_t bs,
-                                                        int N, const T* __restrict__ x,
-                                                        const T* __restrict__ b, T omega,
-                                                        T* __restrict__ x2out,
-                                                        T* __restrict__ bc, int nstrips,
-                                                        int nchunks, int rh) {
-    const int64_t lb = xcd_block((int64_t)nstrips * nchunks);
+// Fused pre-smoothing pass: one (strip, chunk) tile per workgroup of BT
+// threads.
+template <typename T, bool XZERO, int BT>
+__global__ __launch_bounds__(BT) void k_pre(const T* __restrict__ bands, int64_t bs, int N,
+                                            const T* __restrict__ x, const T* __restrict__ b,
+                                            T omega, T* __restrict__ x2out, T* __restrict__ bc,
+                                            dev::FusedGeom g) {
+    const int64_t lb = xcd_block((int64_t)g.nstrips * g.nchunks);
     if (lb < 0) return;
-    dev::pre_tile<T, XZERO>(bands, bs, N, x, b, omega, x2out, bc, (int)(lb % nstrips),
-                            (int)(lb / nstrips), rh);
+    dev::pre_tile<T, XZERO, BT>(bands, bs, N, x, b, omega, x2out, bc, (int)(lb % g.nstrips),
+                                (int)(lb / g.nstrips), g.rh, g.cw);
 }
 
 // Fused post-smoothing pass; with NORM one partial sum of squares per
-// (strip, grid row) in partials.
-template <typename T, bool NORM>
-__global__ __launch_bounds__(dev::F_THREADS) void k_post(const T* __restrict__ bands, int64_t bs,
-                                                         int N, const T* __restrict__ x,
-                                                         const T* __restrict__ xc,
-                                                         const T* __restrict__ b, T omega,
-                                                         T* __restrict__ xout,
-                                                         double* __restrict__ partials,
-                                                         int nstrips, int nchunks, int rh) {
-    const int64_t lb = xcd_block((int64_t)nstrips * nchunks);
+// (strip, wavefront, grid row) in partials.
+template <typename T, bool NORM, int BT>
+__global__ __launch_bounds__(BT) void k_post(const T* __restrict__ bands, int64_t bs, int N,
+                                             const T* __restrict__ x, const T* __restrict__ xc,
+                                             const T* __restrict__ b, T omega,
+                                             T* __restrict__ xout, double* __restrict__ partials,
+                                             dev::FusedGeom g) {
+    const int64_t lb = xcd_block((int64_t)g.nstrips * g.nchunks);
     if (lb < 0) return;
-    dev::post_tile<T, NORM>(bands, bs, N, x, xc, b, omega, xout, partials, (int)(lb % nstrips),
-                            (int)(lb / nstrips), rh);
+    dev::post_tile<T, NORM, BT>(bands, bs, N, x, xc, b, omega, xout, partials,
+                                (int)(lb % g.nstrips), (int)(lb / g.nstrips), g.rh, g.cw);
 }
 
 // Coarse tail: the V(2,2) sub-cycle over levels top..Lc in one workgroup.
@@ -477,8 +501,7 @@ hipError_t launch_defect(const Level& lv, const T* bands, const T* b, const T* x
                            lv.N, lv.n, x, b, d, T(0), (double*)nullptr, nb);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !partials) return e;
-    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(BLOCK), 0, st, partials, nb, scal, slot);
-    return hipGetLastError();
+    return launch_reduce(partials, nb, scal, slot, st);
 }
 
 template <typename T>
@@ -498,56 +521,92 @@ hipError_t launch_jacobi_zero(const Level& lv, const T* bands, const T* b, T* xo
     return hipGetLastError();
 }
 
-// Owned rows per fused tile: the largest power of two from rhmax (64) down
-// to 4 that still gives at least `target` tiles (so that small levels keep
-// the device busy and their marching pipelines short).
-int fused_rows(int N) {
-    static const int target = [] {
-        const char* e = getenv("MG_FUSED_TILES");
-        return e ? std::max(1, atoi(e)) : 1024;
-    }();
-    static const int rhmax = [] {
-        const char* e = getenv("MG_FUSED_RHMAX");
-        const int v = e ? atoi(e) : 64;
-        return (v >= 8 && v % 2 == 0) ? v : 64;
-    }();
-    const int nstrips = (N + dev::F_CW - 1) / dev::F_CW;
-    int rh = rhmax;
-    while (rh > 4 && (int64_t)nstrips * ((N + rh - 1) / rh) < target) rh /= 2;
-    return rh;
+static int env_int(const char* name, int dflt) {
+    const char* e = getenv(name);
+    return e ? atoi(e) : dflt;
 }
 
-int dev_fused_cols() { return dev::F_CW; }
+// Workgroup width of the fused passes on a level with N nodes per side: the
+// width that covers a row with the fewest threads, ties to the wider one.
+// MG_FUSED_BT (64, 128, 192 or 256) forces one width for every level.
+int fused_bt(int N) {
+    static const int forced = env_int("MG_FUSED_BT", 0);
+    if (forced == 64 || forced == 128 || forced == 192 || forced == 256) return forced;
+    int best = dev::F_MAX_THREADS;
+    int64_t best_threads = INT64_MAX;
+    for (int bt = dev::F_MAX_THREADS; bt >= dev::F_MIN_THREADS; bt -= 64) {
+        const int64_t th = (int64_t)dev::fused_geom(N, bt, 2).nstrips * bt;
+        if (th < best_threads) {
+            best_threads = th;
+            best = bt;
+        }
+    }
+    return best;
+}
 
-// Owned rows per fused tile in the batched engine, where many problems fill
-// the device: longer chunks waste less on the recomputed halo rows.
-int batch_fused_rows(int N) {
-    static const int rh = [] {
-        const char* e = getenv("MG_BATCH_RH");
-        const int v = e ? atoi(e) : 32;
-        return (v >= 4 && v % 2 == 0) ? v : 32;
+int64_t fused_max_norm_parts(int N) {
+    int64_t m = 0;
+    for (int bt = dev::F_MIN_THREADS; bt <= dev::F_MAX_THREADS; bt += 64)
+        m = std::max(m, dev::fused_norm_parts(dev::fused_geom(N, bt, 2), N));
+    return m;
+}
+
+// Tiles of a single-problem fused pass: owned rows per chunk are the largest
+// power of two from rhmax (64) down to 4 that still gives at least `target`
+// tiles (so that small levels keep the device busy and their marching
+// pipelines short).
+dev::FusedGeom single_geom(int N) {
+    static const int target = std::max(1, env_int("MG_FUSED_TILES", 1024));
+    static const int rhmax = [] {
+        const int v = env_int("MG_FUSED_RHMAX", 64);
+        return (v >= 8 && v % 2 == 0) ? v : 64;
     }();
-    (void)N;
-    return rh;
+    const int bt = fused_bt(N);
+    const int nstrips = dev::fused_geom(N, bt, 2).nstrips;
+    int rh = rhmax;
+    while (rh > 4 && (int64_t)nstrips * ((N + rh - 1) / rh) < target) rh /= 2;
+    return dev::fused_geom(N, bt, rh);
+}
+
+// Tiles of the batched engine, where many problems fill the device: chunks
+// of 32 rows waste little on the recomputed halo rows; grids of at most 65
+// rows take shorter chunks, which shortens their marching pipelines.  Same
+// strips as a single solve, so residual norms sum the same partials.
+// MG_BATCH_RH forces one chunk height.
+dev::FusedGeom batch_geom(int N) {
+    static const int forced = env_int("MG_BATCH_RH", 0);
+    int rh = N <= 33 ? 8 : N <= 65 ? 16 : 32;
+    if (forced >= 4 && forced % 2 == 0) rh = forced;
+    return dev::fused_geom(N, fused_bt(N), rh);
 }
 
 int64_t fused_tiles(int N) {
-    const dev::FusedGeom g = dev::fused_geom(N, fused_rows(N));
+    const dev::FusedGeom g = single_geom(N);
     return (int64_t)g.nstrips * g.nchunks;
 }
+
+#define MG_FUSED_BT_SWITCH(bt, LAUNCH) \
+    switch (bt) {                      \
+        case 64: LAUNCH(64); break;    \
+        case 128: LAUNCH(128); break;  \
+        case 192: LAUNCH(192); break;  \
+        default: LAUNCH(256); break;   \
+    }
 
 template <typename T>
 hipError_t launch_pre(const Level& lv, const T* bands, const T* x, bool x_zero, const T* b,
                       T omega, T* x2out, T* bc, hipStream_t st) {
-    const dev::FusedGeom g = dev::fused_geom(lv.N, fused_rows(lv.N));
-    const int64_t nt = (int64_t)g.nstrips * g.nchunks;
-    if (x_zero)
-        hipLaunchKernelGGL((k_pre<T, true>), dim3(grid8(nt)), dim3(dev::F_THREADS), 0, st, bands,
-                           lv.bs, lv.N, x, b, omega, x2out, bc, g.nstrips, g.nchunks, g.rh);
-    else
-        hipLaunchKernelGGL((k_pre<T, false>), dim3(grid8(nt)), dim3(dev::F_THREADS), 0, st,
-                           bands, lv.bs, lv.N, x, b, omega, x2out, bc, g.nstrips, g.nchunks,
-                           g.rh);
+    const dev::FusedGeom g = single_geom(lv.N);
+    const dim3 grid(grid8((int64_t)g.nstrips * g.nchunks)), block(g.bt);
+#define PRE(BT)                                                                               \
+    if (x_zero)                                                                               \
+        hipLaunchKernelGGL((k_pre<T, true, BT>), grid, block, 0, st, bands, lv.bs, lv.N, x, b, \
+                           omega, x2out, bc, g);                                              \
+    else                                                                                      \
+        hipLaunchKernelGGL((k_pre<T, false, BT>), grid, block, 0, st, bands, lv.bs, lv.N, x,   \
+                           b, omega, x2out, bc, g);
+    MG_FUSED_BT_SWITCH(g.bt, PRE)
+#undef PRE
     return hipGetLastError();
 }
 
@@ -555,22 +614,20 @@ template <typename T>
 hipError_t launch_post(const Level& lv, const T* bands, const T* x, const T* xc, const T* b,
                        T omega, T* xout, double* partials, double* scal, int slot,
                        hipStream_t st) {
-    const dev::FusedGeom g = dev::fused_geom(lv.N, fused_rows(lv.N));
-    const int64_t nt = (int64_t)g.nstrips * g.nchunks;
-    if (partials) {
-        hipLaunchKernelGGL((k_post<T, true>), dim3(grid8(nt)), dim3(dev::F_THREADS), 0, st,
-                           bands, lv.bs, lv.N, x, xc, b, omega, xout, partials, g.nstrips,
-                           g.nchunks, g.rh);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(BLOCK), 0, st, partials,
-                           (int64_t)g.nstrips * lv.N, scal, slot);
-    } else {
-        hipLaunchKernelGGL((k_post<T, false>), dim3(grid8(nt)), dim3(dev::F_THREADS), 0, st,
-                           bands, lv.bs, lv.N, x, xc, b, omega, xout, (double*)nullptr,
-                           g.nstrips, g.nchunks, g.rh);
-    }
-    return hipGetLastError();
+    const dev::FusedGeom g = single_geom(lv.N);
+    const dim3 grid(grid8((int64_t)g.nstrips * g.nchunks)), block(g.bt);
+#define POST(BT)                                                                             \
+    if (partials)                                                                            \
+        hipLaunchKernelGGL((k_post<T, true, BT>), grid, block, 0, st, bands, lv.bs, lv.N, x, \
+                           xc, b, omega, xout, partials, g);                                 \
+    else                                                                                     \
+        hipLaunchKernelGGL((k_post<T, false, BT>), grid, block, 0, st, bands, lv.bs, lv.N,   \
+                           x, xc, b, omega, xout, (double*)nullptr, g);
+    MG_FUSED_BT_SWITCH(g.bt, POST)
+#undef POST
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !partials) return e;
+    return launch_reduce(partials, dev::fused_norm_parts(g, lv.N), scal, slot, st);
 }
 
 template <typename T>
@@ -630,8 +687,7 @@ hipError_t launch_norm(const T* v, int64_t n, double* partials, double* scal, in
     hipLaunchKernelGGL(k_sumsq<T>, dim3(grid8(nb)), dim3(BLOCK), 0, st, v, n, partials, nb);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(BLOCK), 0, st, partials, nb, scal, slot);
-    return hipGetLastError();
+    return launch_reduce(partials, nb, scal, slot, st);
 }
 
 template <typename T>

@@ -148,11 +148,17 @@ template <typename T>
 hipError_t launch_tail(const Level* lv, int top, int Lc, const double* chol, int m, T omega,
                        hipStream_t st);
 int tail_max_level();
-// Owned rows per fused tile for a level of N nodes per side, and tiles per pass.
-int fused_rows(int N);
+// Tiling of the fused passes on a level of N nodes per side: workgroup
+// width, geometry of a single-problem pass and of the batched engine, tiles
+// per single-problem pass, and the most residual partials any width gives.
+namespace dev {
+struct FusedGeom;
+}
+int fused_bt(int N);
+dev::FusedGeom single_geom(int N);
+dev::FusedGeom batch_geom(int N);
 int64_t fused_tiles(int N);
-int dev_fused_cols();  // owned columns per fused strip
-int batch_fused_rows(int N);
+int64_t fused_max_norm_parts(int N);
 
 // Workgroups (= tiles) of a band-product launch and of a vector-norm launch.
 int64_t stencil_blocks(int64_t n, int elem_bytes);
