@@ -381,15 +381,13 @@ mg_status mg_defect(const mg_hierarchy* h, int level, mg_dtype dtype, const void
     double* part = host_norm ? hm->partials : nullptr;
     if (dtype == MG_F64)
         MG_HIP(launch_defect<double>(lv, lv.bands64, (const double*)b, (const double*)x,
-                                     (double*)d, part, hm->scal, SC_USER, st));
+                                     (double*)d, part, hm->scal, SC_USER, hm->host_scal, st));
     else
         MG_HIP(launch_defect<float>(lv, lv.bands32, (const float*)b, (const float*)x, (float*)d,
-                                    part, hm->scal, SC_USER, st));
+                                    part, hm->scal, SC_USER, hm->host_scal, st));
     if (host_norm) {
-        MG_HIP(hipMemcpyAsync(hm->host_scal + SC_USER, hm->scal + SC_USER, 2 * sizeof(double),
-                              hipMemcpyDeviceToHost, st));
         MG_HIP(hipStreamSynchronize(st));
-        *host_norm = hm->host_scal[SC_USER + 1];
+        *host_norm = ((const volatile double*)hm->host_scal)[SC_USER + 1];
     }
     return MG_OK;
 }
@@ -472,16 +470,14 @@ mg_status mg_post_smooth(const mg_hierarchy* h, int level, mg_dtype dtype, const
     if (dtype == MG_F64)
         MG_HIP(launch_post<double>(lv, lv.bands64, (const double*)x, (const double*)x_c,
                                    (const double*)b, omega, (double*)x_out, part, hm->scal, SC_USER,
-                                   st));
+                                   hm->host_scal, st));
     else
         MG_HIP(launch_post<float>(lv, lv.bands32, (const float*)x, (const float*)x_c,
                                   (const float*)b, (float)omega, (float*)x_out, part, hm->scal,
-                                  SC_USER, st));
+                                  SC_USER, hm->host_scal, st));
     if (host_norm) {
-        MG_HIP(hipMemcpyAsync(hm->host_scal + SC_USER, hm->scal + SC_USER, 2 * sizeof(double),
-                              hipMemcpyDeviceToHost, st));
         MG_HIP(hipStreamSynchronize(st));
-        *host_norm = hm->host_scal[SC_USER + 1];
+        *host_norm = ((const volatile double*)hm->host_scal)[SC_USER + 1];
     }
     return MG_OK;
 }

@@ -66,6 +66,8 @@ struct BState {
     double hist[MG_HIST];
 };
 
+constexpr int ITER_RING = 4;  // iterations whose counts the pinned ring holds
+
 class BatchEngine {
 public:
     // capacity problems of levels <= Lmax with common coarse level and
@@ -82,6 +84,9 @@ public:
     mg_status upload();
     // One iteration over all live slots (graph replay); synchronous.
     mg_status step(int* active_left);
+    // Iterations until every slot is done (at most iter_cap), keeping the
+    // next needed iteration queued while the host waits; synchronous.
+    mg_status run(int64_t iter_cap, int64_t* iterations);
     // Copy the device states to the host mirror; returns it.
     mg_status read_states();
     const BState& state(int s) const { return h_state_[s]; }
@@ -93,14 +98,19 @@ public:
 private:
     hipError_t enqueue_iteration();
     void build_lists();
+    mg_status ensure_graph();
+    mg_status launch();
+    mg_status wait(int64_t k, int* live, int* sure);
     int device_ = 0, cap_ = 0, Lmax_ = 0, Lc_ = 1, nu_pre_ = 2, nu_post_ = 2;
     hipStream_t st_ = nullptr;
     BProb* d_probs_ = nullptr;
     BState* d_state_ = nullptr;
     BState* h_state_ = nullptr;  // pinned
     int* d_wl_ = nullptr;
-    int* d_active_ = nullptr;
-    int* h_active_ = nullptr;    // pinned
+    int* d_iter_ = nullptr;   // iterations run (device counter)
+    int* h_ring_ = nullptr;   // pinned: per iteration, live and sure counts
+    hipEvent_t ev_[ITER_RING] = {};  // end of the iterations in flight
+    int64_t launched_ = 0;    // iterations launched (equals the device counter)
     std::vector<BProb> hp_;
     std::vector<int> h_wl_;
     std::vector<char> started_;

@@ -365,7 +365,8 @@ __global__ __launch_bounds__(BLOCK) void kb_finalize(const BProb* __restrict__ p
                                : (n + TILE - 1) / TILE;
     // the inner residual comes from the fused post pass above the coarse level
     if (kind == K_S32 && fused_above >= 0 && P.L > fused_above)
-        np = (int64_t)F.nstrips * (F.bt / 64) * F.N;  // per-row partials of the fused post pass
+        np = (int64_t)F.nstrips * (F.bt / 64) *
+             ((F.N + dev::F_NORM_ROWS - 1) / dev::F_NORM_ROWS);  // fused post pass partials
     const double s = dev::reduce_partials(P.partials, np);
     if (threadIdx.x == 0) {
         const double r = sqrt(s);
@@ -383,10 +384,15 @@ __global__ __launch_bounds__(BLOCK) void kb_finalize(const BProb* __restrict__ p
 }
 
 // Per-problem transitions of the mixed scheme (one block; thread per slot).
+// At the end of an iteration (PH_INNER) also reports to the host, in slot
+// k mod ITER_RING of the pinned ring (k = iterations so far): the problems
+// not done, and those still in their inner loop, which cannot finish in the
+// next iteration (a problem finishes only at an outer step).
 __global__ __launch_bounds__(BLOCK) void kb_ctrl(const BProb* __restrict__ probs,
                                                  BState* __restrict__ state, int cap, int phase,
-                                                 int* __restrict__ active) {
-    int live = 0;
+                                                 int* __restrict__ iter,
+                                                 int* __restrict__ ring) {
+    int live = 0, sure = 0;
     for (int p = threadIdx.x; p < cap; p += BLOCK) {
         const BProb& P = probs[p];
         if (P.L == 0) continue;
@@ -435,10 +441,18 @@ __global__ __launch_bounds__(BLOCK) void kb_ctrl(const BProb* __restrict__ probs
                 S.flags = BF_UPDATE;
         }
         if (!(S.flags & BF_DONE)) ++live;
+        if (S.flags == BF_INNER) ++sure;
     }
     if (phase == PH_INNER) {
         const double tot = dev::block_sum((double)live);
-        if (threadIdx.x == 0) *active = (int)tot;
+        const double tsure = dev::block_sum((double)sure);
+        if (threadIdx.x == 0) {
+            const int k = *iter;
+            *iter = k + 1;
+            ring[(k % ITER_RING) * 2] = (int)tot;
+            ring[(k % ITER_RING) * 2 + 1] = (int)tsure;
+            __threadfence_system();
+        }
     }
 }
 
@@ -450,9 +464,11 @@ BatchEngine::~BatchEngine() {
     if (d_probs_) (void)hipFree(d_probs_);
     if (d_state_) (void)hipFree(d_state_);
     if (d_wl_) (void)hipFree(d_wl_);
-    if (d_active_) (void)hipFree(d_active_);
+    for (hipEvent_t e : ev_)
+        if (e) (void)hipEventDestroy(e);
+    if (d_iter_) (void)hipFree(d_iter_);
     if (h_state_) (void)hipHostFree(h_state_);
-    if (h_active_) (void)hipHostFree(h_active_);
+    if (h_ring_) (void)hipHostFree(h_ring_);
 }
 
 mg_status BatchEngine::init(int device, int capacity, int Lmax, int Lc, int nu_pre,
@@ -469,9 +485,13 @@ mg_status BatchEngine::init(int device, int capacity, int Lmax, int Lc, int nu_p
     MG_HIP(hipMalloc(&d_probs_, sizeof(BProb) * cap_));
     MG_HIP(hipMalloc(&d_state_, sizeof(BState) * cap_));
     MG_HIP(hipMalloc(&d_wl_, sizeof(int) * NLISTS * (3 + 2 * cap_)));
-    MG_HIP(hipMalloc(&d_active_, 64));
+    MG_HIP(hipMalloc(&d_iter_, 64));
+    MG_HIP(hipMemset(d_iter_, 0, 64));
+    launched_ = 0;
+    for (hipEvent_t& e : ev_) MG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     MG_HIP(hipHostMalloc((void**)&h_state_, sizeof(BState) * cap_, hipHostMallocDefault));
-    MG_HIP(hipHostMalloc((void**)&h_active_, 64, hipHostMallocDefault));
+    MG_HIP(hipHostMalloc((void**)&h_ring_, sizeof(int) * 2 * ITER_RING, hipHostMallocDefault));
+    std::memset(h_ring_, 0, sizeof(int) * 2 * ITER_RING);
     hp_.assign(cap_, BProb{});
     started_.assign(cap_, 0);
     std::memset(h_state_, 0, sizeof(BState) * cap_);
@@ -496,7 +516,8 @@ void BatchEngine::set_slot(int s, mg_hierarchy* h, const mg_solve_opts& o) {
         b.bs = v.bs;
         b.n = v.n;
         b.N = v.N;
-        const dev::FusedGeom g = batch_geom(v.N);
+        // chunk height: set by build_lists from the composition
+        const dev::FusedGeom g = dev::fused_geom(v.N, fused_bt(v.N), 4);
         b.rh = g.rh;
         b.cw = g.cw;
         b.bt = g.bt;
@@ -547,6 +568,24 @@ void BatchEngine::build_lists() {
         w[1] = cap_;
     };
     auto ntiles = [](int64_t n) { return (int)((n + TILE - 1) / TILE); };
+    auto fused_here = [](const BProb& P, int l) {
+        return P.L >= l && (l > dev::TAIL_MAX || l == P.L);
+    };
+    // chunk heights of the fused passes for this composition: every problem
+    // at a level shares one (the solves do not depend on it)
+    for (int l = Lc_ + 1; l <= Lmax_; ++l) {
+        int64_t count = 0;
+        for (int s = 0; s < cap_; ++s)
+            if (hp_[s].L > 0 && fused_here(hp_[s], l)) ++count;
+        if (count == 0) continue;
+        const int N = (1 << l) + 1, bt = fused_bt(N);
+        const dev::FusedGeom g = dev::fused_geom(N, bt, fused_rh(N, bt, count));
+        for (int s = 0; s < cap_; ++s) {
+            if (hp_[s].L == 0 || !fused_here(hp_[s], l)) continue;
+            hp_[s].lv[l].rh = g.rh;
+            hp_[s].lv[l].nchunks = g.nchunks;
+        }
+    }
     for (int l = Lc_ + 1; l <= Lmax_; ++l) {
         fill(wl_level(l), [&](const BProb& P) { return P.L >= l; },
              [&](const BProb& P) { return ntiles(P.lv[l].n); });
@@ -554,8 +593,7 @@ void BatchEngine::build_lists() {
              [&](const BProb& P) { return ntiles(P.lv[l - 1].n); });
         // fused passes run above the coarse tail: on levels > TAIL_MAX and on
         // the problem's finest level
-        fill(wl_fused(l),
-             [&](const BProb& P) { return P.L >= l && (l > dev::TAIL_MAX || l == P.L); },
+        fill(wl_fused(l), [&](const BProb& P) { return fused_here(P, l); },
              [&](const BProb& P) { return P.lv[l].nstrips * P.lv[l].nchunks; });
     }
     fill(WL_FINEST, [](const BProb&) { return true; },
@@ -614,19 +652,19 @@ hipError_t BatchEngine::enqueue_iteration() {
     // new problems: ||b||
     LAUNCH(kb_sumsq, G, B, 0, st_, P, S, W(WL_FINEST), 0, (int)BF_INIT);
     LAUNCH(kb_finalize, GA, B, 0, st_, P, S, W(WL_ALL), (int)K_NORM, (int)F_BN, (int)BF_INIT, -1);
-    LAUNCH(kb_ctrl, G1, B, 0, st_, P, S, cap_, (int)PH_INIT, d_active_);
+    LAUNCH(kb_ctrl, G1, B, 0, st_, P, S, cap_, (int)PH_INIT, d_iter_, h_ring_);
     // finished inner loops: x += s c
     LAUNCH(kb_update, G, B, 0, st_, P, S, W(WL_FINEST), (int)BF_UPDATE);
-    LAUNCH(kb_ctrl, G1, B, 0, st_, P, S, cap_, (int)PH_UPDATE, d_active_);
+    LAUNCH(kb_ctrl, G1, B, 0, st_, P, S, cap_, (int)PH_UPDATE, d_iter_, h_ring_);
     // FP64 defect, norm and stop test
     LAUNCH(kb_outer_defect, G, B, 0, st_, P, S, W(WL_FINEST), (int)BF_OUTER);
     LAUNCH(kb_finalize, GA, B, 0, st_, P, S, W(WL_ALL), (int)K_S64, (int)F_S, (int)BF_OUTER, -1);
-    LAUNCH(kb_ctrl, G1, B, 0, st_, P, S, cap_, (int)PH_OUTER, d_active_);
+    LAUNCH(kb_ctrl, G1, B, 0, st_, P, S, cap_, (int)PH_OUTER, d_iter_, h_ring_);
     // scaled FP32 defect and its norm
     LAUNCH(kb_cast, G, B, 0, st_, P, S, W(WL_FINEST), (int)BF_CAST);
     LAUNCH(kb_sumsq, G, B, 0, st_, P, S, W(WL_FINEST), 1, (int)BF_CAST);
     LAUNCH(kb_finalize, GA, B, 0, st_, P, S, W(WL_ALL), (int)K_NORM, (int)F_DN, (int)BF_CAST, -1);
-    LAUNCH(kb_ctrl, G1, B, 0, st_, P, S, cap_, (int)PH_CAST, d_active_);
+    LAUNCH(kb_ctrl, G1, B, 0, st_, P, S, cap_, (int)PH_CAST, d_iter_, h_ring_);
     // one FP32 V-cycle for every problem in its inner loop
     const int m = BF_INNER;
     const bool fused = nu_pre_ == 2 && nu_post_ == 2;
@@ -653,7 +691,7 @@ hipError_t BatchEngine::enqueue_iteration() {
         if (launch_mask_ & 1u)
             LAUNCH(kb_inner_norm, G, B, 0, st_, P, S, W(WL_FINEST_COARSE), m, Lc_);
         LAUNCH(kb_finalize, GA, B, 0, st_, P, S, W(WL_ALL), (int)K_S32, (int)F_R32, m, Lc_);
-        LAUNCH(kb_ctrl, G1, B, 0, st_, P, S, cap_, (int)PH_INNER, d_active_);
+        LAUNCH(kb_ctrl, G1, B, 0, st_, P, S, cap_, (int)PH_INNER, d_iter_, h_ring_);
         return hipSuccess;
     }
     // roles of the unfused cycle: 0 = x, 1 = t
@@ -687,13 +725,12 @@ hipError_t BatchEngine::enqueue_iteration() {
     // inner residual and stop test
     LAUNCH(kb_inner_norm, G, B, 0, st_, P, S, W(WL_FINEST), m, -1);
     LAUNCH(kb_finalize, GA, B, 0, st_, P, S, W(WL_ALL), (int)K_S32, (int)F_R32, m, -1);
-    LAUNCH(kb_ctrl, G1, B, 0, st_, P, S, cap_, (int)PH_INNER, d_active_);
+    LAUNCH(kb_ctrl, G1, B, 0, st_, P, S, cap_, (int)PH_INNER, d_iter_, h_ring_);
 #undef LAUNCH
     return hipSuccess;
 }
 
-mg_status BatchEngine::step(int* active_left) {
-    MG_HIP(hipSetDevice(device_));
+mg_status BatchEngine::ensure_graph() {
     if (!graph_) {
         hipGraph_t g = nullptr;
         MG_HIP(hipStreamBeginCapture(st_, hipStreamCaptureModeThreadLocal));
@@ -707,10 +744,60 @@ mg_status BatchEngine::step(int* active_left) {
             return fail(MG_ERR_DEVICE, std::string("batch graph capture: ") + hipGetErrorString(e));
         }
     }
+    return MG_OK;
+}
+
+mg_status BatchEngine::launch() {
     MG_HIP(hipGraphLaunch(graph_, st_));
-    MG_HIP(hipMemcpyAsync(h_active_, d_active_, sizeof(int), hipMemcpyDeviceToHost, st_));
-    MG_HIP(hipStreamSynchronize(st_));
-    if (active_left) *active_left = h_active_[0];
+    MG_HIP(hipEventRecord(ev_[launched_ % ITER_RING], st_));
+    ++launched_;
+    return MG_OK;
+}
+
+// Wait for iteration k; its counts of live and of certainly-continuing problems.
+mg_status BatchEngine::wait(int64_t k, int* live, int* sure) {
+    MG_HIP(hipEventSynchronize(ev_[k % ITER_RING]));
+    const volatile int* r = h_ring_ + (k % ITER_RING) * 2;
+    *live = r[0];
+    *sure = r[1];
+    return MG_OK;
+}
+
+mg_status BatchEngine::step(int* active_left) {
+    MG_HIP(hipSetDevice(device_));
+    if (mg_status s = ensure_graph()) return s;
+    const int64_t k = launched_;
+    if (mg_status s = launch()) return s;
+    int live = 0, sure = 0;
+    if (mg_status s = wait(k, &live, &sure)) return s;
+    if (active_left) *active_left = live;
+    return MG_OK;
+}
+
+// Iterations until no problem is live (at most iter_cap).  While the last
+// finished iteration shows a problem still in its inner loop, the next but
+// one iteration is certainly needed and is queued before the host waits, so
+// the device does not idle between iterations; at outer steps the host
+// waits for the decision.  No iteration is queued that is not needed.
+mg_status BatchEngine::run(int64_t iter_cap, int64_t* iterations) {
+    MG_HIP(hipSetDevice(device_));
+    if (mg_status s = ensure_graph()) return s;
+    const int64_t first = launched_;
+    int64_t next = first;  // next iteration to wait for
+    if (iter_cap > 0)
+        if (mg_status s = launch()) return s;
+    while (next < launched_) {
+        int live = 0, sure = 0;
+        if (mg_status s = wait(next, &live, &sure)) return s;
+        ++next;
+        if (live == 0) break;
+        const bool room = launched_ - first < iter_cap;
+        if (room && launched_ == next)
+            if (mg_status s = launch()) return s;  // nothing queued: go on
+        if (room && launched_ == next + 1 && sure > 0)
+            if (mg_status s = launch()) return s;  // needed after the queued one
+    }
+    if (iterations) *iterations = next - first;
     return MG_OK;
 }
 
@@ -890,9 +977,7 @@ extern "C" mg_status mg_solve_batch(mg_hierarchy* const* hs, const double* const
         iter_cap = std::max<int64_t>(iter_cap, (int64_t)(outer + 1) * (o.inner_max_cycles + 1) + 4);
     }
     if (mg_status s = eng.upload()) return s;
-    int active = count;
-    for (int64_t it = 0; it < iter_cap && active > 0; ++it)
-        if (mg_status s = eng.step(&active)) return s;
+    if (mg_status s = eng.run(iter_cap, nullptr)) return s;
     if (mg_status s = eng.read_states()) return s;
     mg_status worst = MG_OK;
     for (int p = 0; p < count; ++p) {

@@ -251,10 +251,14 @@ __device__ __forceinline__ T prolong_value(int Nf, const T* __restrict__ xc, int
     return T(0.25) * ((c[0] + c[1]) + (c[Nc] + c[Nc + 1]));
 }
 
+// Grid rows per residual partial of a fused post pass; chunk heights are
+// multiples of it, so no group of rows straddles two tiles.
+constexpr int F_NORM_ROWS = 4;
+
 // Partial sums of squares a fused post pass with NORM writes: one per
-// (strip, wavefront, grid row).
+// (strip, wavefront, group of F_NORM_ROWS grid rows).
 __host__ __device__ inline int64_t fused_norm_parts(const FusedGeom& g, int N) {
-    return (int64_t)g.nstrips * (g.bt / 64) * N;
+    return (int64_t)g.nstrips * (g.bt / 64) * ((N + F_NORM_ROWS - 1) / F_NORM_ROWS);
 }
 
 // Sum over the 64 lanes of a wavefront (butterfly, fixed order).
@@ -265,11 +269,12 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // Post-smoothing tile: x_out = J(J(x + P x_c)) on owned nodes.  With NORM
-// also rowpart[(strip * (BT / 64) + w) * N + j] = sum of (b - A x_out)^2 over
-// the owned columns of row j that wavefront w holds, for the tile's owned
-// rows: the partial sums do not depend on how rows are split into chunks,
-// and need no workgroup barrier.  Same row pipeline and register ring as
-// pre_tile.
+// also rowpart[(strip * (BT / 64) + w) * NG + G] = sum of (b - A x_out)^2
+// over the owned columns that wavefront w holds in the rows of group G (rows
+// 4G .. 4G+3; NG groups), each lane adding its rows in order before the
+// wavefront sum: the partial sums do not depend on how rows are split into
+// chunks, and need no workgroup barrier.  Same row pipeline and register
+// ring as pre_tile.
 template <typename T, bool NORM, int BT>
 __device__ void post_tile(const T* __restrict__ bands, int64_t bs, int N, const T* __restrict__ x,
                           const T* __restrict__ xc, const T* __restrict__ b, T omega,
@@ -296,6 +301,8 @@ __device__ void post_tile(const T* __restrict__ bands, int64_t bs, int N, const 
     }
     T bk[6][9], bb[6];
     T pfx[3];
+    double nacc = 0.0;  // this lane's part of the current row group
+    const int ng = (N + F_NORM_ROWS - 1) / F_NORM_ROWS;
     const int jstart = r0 - F_HALO - ((((r0 - F_HALO) % 6) + 6) % 6);
     const int jend = r1 + 3;
     auto xrow = [&](int j) -> T {
@@ -341,15 +348,18 @@ __device__ void post_tile(const T* __restrict__ bands, int64_t bs, int N, const 
             }
             __syncthreads();
             if (NORM && in_range(j3, r0, r1)) {
-                double dd = 0.0;
                 if (c_own) {
                     const T acc = band_row_product(bk[b3], B[l1], B[x3], B[l2], t);
                     const T d = bb[b3] - acc;
-                    dd = (double)d * (double)d;
+                    nacc += (double)d * (double)d;
                 }
-                dd = wave_sum(dd);
-                if ((threadIdx.x & 63) == 0)
-                    rowpart[((int64_t)strip * (BT / 64) + (threadIdx.x >> 6)) * N + j3] = dd;
+                if ((j3 % F_NORM_ROWS) == F_NORM_ROWS - 1 || j3 == r1 - 1) {
+                    const double w = wave_sum(nacc);
+                    if ((threadIdx.x & 63) == 0)
+                        rowpart[((int64_t)strip * (BT / 64) + (threadIdx.x >> 6)) * ng +
+                                j3 / F_NORM_ROWS] = w;
+                    nacc = 0.0;
+                }
             }
         }
     }

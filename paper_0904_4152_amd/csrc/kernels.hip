@@ -58,11 +58,16 @@ __global__ __launch_bounds__(BLOCK) void k_stencil(const T* __restrict__ bands, 
 
 __global__ __launch_bounds__(BLOCK) void k_reduce_final(const double* __restrict__ partials,
                                                         int64_t np, double* __restrict__ scal,
-                                                        int slot) {
+                                                        int slot, double* __restrict__ host) {
     const double s = dev::reduce_partials(partials, np);
     if (threadIdx.x == 0) {
         scal[slot] = s;
         scal[slot + 1] = sqrt(s);
+        if (host) {
+            host[slot] = s;
+            host[slot + 1] = sqrt(s);
+            __threadfence_system();
+        }
     }
 }
 
@@ -99,11 +104,13 @@ __global__ __launch_bounds__(BLOCK) void k_reduce_segs(const double* __restrict_
 }
 
 // scal[slot] = sum of the np partials (the order of dev::reduce_partials),
-// scal[slot + 1] = its square root.  Segment sums go right after the
+// scal[slot + 1] = its square root; the same into host[slot..] if not null.  Segment sums go right after the
 // partials, which the partials buffer leaves room for.
-hipError_t launch_reduce(double* partials, int64_t np, double* scal, int slot, hipStream_t st) {
+hipError_t launch_reduce(double* partials, int64_t np, double* scal, int slot, double* host,
+                         hipStream_t st) {
     if (np <= dev::RED_SEG) {
-        hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(BLOCK), 0, st, partials, np, scal, slot);
+        hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(BLOCK), 0, st, partials, np, scal, slot,
+                           host);
         return hipGetLastError();
     }
     const int64_t ns = (np + dev::RED_SEG - 1) / dev::RED_SEG;
@@ -112,7 +119,7 @@ hipError_t launch_reduce(double* partials, int64_t np, double* scal, int slot, h
     hipLaunchKernelGGL(k_reduce_segs, dim3(ns), dim3(BLOCK), 0, st, partials, np, segs);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(BLOCK), 0, st, segs, ns, scal, slot);
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(BLOCK), 0, st, segs, ns, scal, slot, host);
     return hipGetLastError();
 }
 
@@ -487,7 +494,7 @@ hipError_t launch_spmv(const Level& lv, const T* bands, const T* x, T* y, hipStr
 
 template <typename T>
 hipError_t launch_defect(const Level& lv, const T* bands, const T* b, const T* x, T* d,
-                         double* partials, double* scal, int slot, hipStream_t st) {
+                         double* partials, double* scal, int slot, double* host, hipStream_t st) {
     const int64_t nb = stencil_blocks(lv.n, sizeof(T));
     const dim3 g(grid8(nb)), blk(BLOCK);
     if (partials && d)
@@ -501,7 +508,7 @@ hipError_t launch_defect(const Level& lv, const T* bands, const T* b, const T* x
                            lv.N, lv.n, x, b, d, T(0), (double*)nullptr, nb);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !partials) return e;
-    return launch_reduce(partials, nb, scal, slot, st);
+    return launch_reduce(partials, nb, scal, slot, host, st);
 }
 
 template <typename T>
@@ -551,33 +558,24 @@ int64_t fused_max_norm_parts(int N) {
     return m;
 }
 
-// Tiles of a single-problem fused pass: owned rows per chunk are the largest
-// power of two from rhmax (64) down to 4 that still gives at least `target`
-// tiles (so that small levels keep the device busy and their marching
-// pipelines short).
-dev::FusedGeom single_geom(int N) {
-    static const int target = std::max(1, env_int("MG_FUSED_TILES", 1024));
-    static const int rhmax = [] {
-        const int v = env_int("MG_FUSED_RHMAX", 64);
-        return (v >= 8 && v % 2 == 0) ? v : 64;
-    }();
-    const int bt = fused_bt(N);
-    const int nstrips = dev::fused_geom(N, bt, 2).nstrips;
-    int rh = rhmax;
-    while (rh > 4 && (int64_t)nstrips * ((N + rh - 1) / rh) < target) rh /= 2;
-    return dev::fused_geom(N, bt, rh);
+// Owned rows per chunk of a fused pass over `count` problems on a level with
+// N nodes per side: the longest chunk (a power of two from 64 down to 4)
+// that still gives at least MG_FUSED_WAVES (default 3500, about 14 per
+// compute unit) wavefronts, so that levels with little work keep the device
+// busy and their marching pipelines short, and levels with much work waste
+// little on the recomputed halo rows.  Chunk heights are multiples of
+// F_NORM_ROWS.
+int fused_rh(int N, int bt, int64_t count) {
+    static const int64_t target = std::max(1, env_int("MG_FUSED_WAVES", 3500));
+    const int64_t per_chunk = count * dev::fused_geom(N, bt, 4).nstrips * (bt / 64);
+    int rh = 64;
+    while (rh > 4 && per_chunk * ((N + rh - 1) / rh) < target) rh /= 2;
+    return rh;
 }
 
-// Tiles of the batched engine, where many problems fill the device: chunks
-// of 32 rows waste little on the recomputed halo rows; grids of at most 65
-// rows take shorter chunks, which shortens their marching pipelines.  Same
-// strips as a single solve, so residual norms sum the same partials.
-// MG_BATCH_RH forces one chunk height.
-dev::FusedGeom batch_geom(int N) {
-    static const int forced = env_int("MG_BATCH_RH", 0);
-    int rh = N <= 33 ? 8 : N <= 65 ? 16 : 32;
-    if (forced >= 4 && forced % 2 == 0) rh = forced;
-    return dev::fused_geom(N, fused_bt(N), rh);
+dev::FusedGeom single_geom(int N) {
+    const int bt = fused_bt(N);
+    return dev::fused_geom(N, bt, fused_rh(N, bt, 1));
 }
 
 int64_t fused_tiles(int N) {
@@ -612,7 +610,7 @@ hipError_t launch_pre(const Level& lv, const T* bands, const T* x, bool x_zero, 
 
 template <typename T>
 hipError_t launch_post(const Level& lv, const T* bands, const T* x, const T* xc, const T* b,
-                       T omega, T* xout, double* partials, double* scal, int slot,
+                       T omega, T* xout, double* partials, double* scal, int slot, double* host,
                        hipStream_t st) {
     const dev::FusedGeom g = single_geom(lv.N);
     const dim3 grid(grid8((int64_t)g.nstrips * g.nchunks)), block(g.bt);
@@ -627,7 +625,7 @@ hipError_t launch_post(const Level& lv, const T* bands, const T* x, const T* xc,
 #undef POST
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !partials) return e;
-    return launch_reduce(partials, dev::fused_norm_parts(g, lv.N), scal, slot, st);
+    return launch_reduce(partials, dev::fused_norm_parts(g, lv.N), scal, slot, host, st);
 }
 
 template <typename T>
@@ -682,12 +680,12 @@ hipError_t launch_copy(const T* src, T* dst, int64_t n, hipStream_t st) {
 
 template <typename T>
 hipError_t launch_norm(const T* v, int64_t n, double* partials, double* scal, int slot,
-                       hipStream_t st) {
+                       double* host, hipStream_t st) {
     const int64_t nb = norm_blocks(n);
     hipLaunchKernelGGL(k_sumsq<T>, dim3(grid8(nb)), dim3(BLOCK), 0, st, v, n, partials, nb);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return launch_reduce(partials, nb, scal, slot, st);
+    return launch_reduce(partials, nb, scal, slot, host, st);
 }
 
 template <typename T>
@@ -712,7 +710,7 @@ hipError_t launch_update(double* x, const float* c32, int64_t n, const double* s
 #define MG_INSTANTIATE(T)                                                                     \
     template hipError_t launch_spmv<T>(const Level&, const T*, const T*, T*, hipStream_t);    \
     template hipError_t launch_defect<T>(const Level&, const T*, const T*, const T*, T*,      \
-                                         double*, double*, int, hipStream_t);                 \
+                                         double*, double*, int, double*, hipStream_t);        \
     template hipError_t launch_jacobi<T>(const Level&, const T*, const T*, const T*, T*, T,   \
                                          hipStream_t);                                        \
     template hipError_t launch_jacobi_zero<T>(const Level&, const T*, const T*, T*, T,        \
@@ -721,12 +719,13 @@ hipError_t launch_update(double* x, const float* c32, int64_t n, const double* s
     template hipError_t launch_prolong<T>(int, const T*, T*, hipStream_t);                    \
     template hipError_t launch_coarse<T>(const double*, int, int, const T*, T*, hipStream_t); \
     template hipError_t launch_copy<T>(const T*, T*, int64_t, hipStream_t);                   \
-    template hipError_t launch_norm<T>(const T*, int64_t, double*, double*, int, hipStream_t); \
+    template hipError_t launch_norm<T>(const T*, int64_t, double*, double*, int, double*,     \
+                                       hipStream_t);                                          \
     template hipError_t launch_fill<T>(T*, int64_t, T, hipStream_t);                          \
     template hipError_t launch_pre<T>(const Level&, const T*, const T*, bool, const T*, T, T*,  \
                                       T*, hipStream_t);                                         \
     template hipError_t launch_post<T>(const Level&, const T*, const T*, const T*, const T*, T, \
-                                       T*, double*, double*, int, hipStream_t);               \
+                                       T*, double*, double*, int, double*, hipStream_t);      \
     template hipError_t launch_tail<T>(const Level*, int, int, const double*, int, T, hipStream_t);
 
 MG_INSTANTIATE(float)

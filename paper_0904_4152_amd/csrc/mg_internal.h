@@ -97,11 +97,14 @@ hipError_t launch_rhs_uniform(int N, uint64_t seed, double* b, hipStream_t st);
 // Stencil family on one level.
 template <typename T>
 hipError_t launch_spmv(const Level& lv, const T* bands, const T* x, T* y, hipStream_t st);
+// Reductions land in scal[slot] (sum of squares) and scal[slot+1] (norm) in
+// device memory and, when host is not null, also in host[slot], host[slot+1]
+// (pinned memory, for the host to read once the stream has synchronized).
 // d = b - A x (d may be null); if partials != null also writes per-block
-// sums of d^2 and reduces them into scal[slot] (sum) and scal[slot+1] (norm).
+// sums of d^2 and reduces them.
 template <typename T>
 hipError_t launch_defect(const Level& lv, const T* bands, const T* b, const T* x, T* d,
-                         double* partials, double* scal, int slot, hipStream_t st);
+                         double* partials, double* scal, int slot, double* host, hipStream_t st);
 template <typename T>
 hipError_t launch_jacobi(const Level& lv, const T* bands, const T* b, const T* x, T* xo,
                          T omega, hipStream_t st);
@@ -121,7 +124,7 @@ hipError_t launch_copy(const T* src, T* dst, int64_t n, hipStream_t st);
 // scal[slot+1].
 template <typename T>
 hipError_t launch_norm(const T* v, int64_t n, double* partials, double* scal, int slot,
-                       hipStream_t st);
+                       double* host, hipStream_t st);
 template <typename T>
 hipError_t launch_fill(T* v, int64_t n, T value, hipStream_t st);
 // d32 = float(d64 / s) with s = scal[slot + 1] (0 if s == 0).
@@ -140,7 +143,7 @@ hipError_t launch_pre(const Level& lv, const T* bands, const T* x, bool x_zero, 
                       T omega, T* x2out, T* bc, hipStream_t st);
 template <typename T>
 hipError_t launch_post(const Level& lv, const T* bands, const T* x, const T* xc, const T* b,
-                       T omega, T* xout, double* partials, double* scal, int slot,
+                       T omega, T* xout, double* partials, double* scal, int slot, double* host,
                        hipStream_t st);
 // The V(2,2) sub-cycle over levels top..Lc (top <= tail_max_level(), entered
 // with a zero iterate on level top) in one workgroup.  lv is indexed by level.
@@ -149,14 +152,15 @@ hipError_t launch_tail(const Level* lv, int top, int Lc, const double* chol, int
                        hipStream_t st);
 int tail_max_level();
 // Tiling of the fused passes on a level of N nodes per side: workgroup
-// width, geometry of a single-problem pass and of the batched engine, tiles
-// per single-problem pass, and the most residual partials any width gives.
+// width, chunk height for a pass over `count` problems, geometry of a
+// single-problem pass, tiles per single-problem pass, and the most residual
+// partials any width gives.
 namespace dev {
 struct FusedGeom;
 }
 int fused_bt(int N);
+int fused_rh(int N, int bt, int64_t count);
 dev::FusedGeom single_geom(int N);
-dev::FusedGeom batch_geom(int N);
 int64_t fused_tiles(int N);
 int64_t fused_max_norm_parts(int N);
 

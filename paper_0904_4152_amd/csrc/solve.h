@@ -21,10 +21,12 @@ hipError_t enqueue_vcycle(mg_hierarchy* h, int l, T* x, const T* b, bool x_zero,
                           int nu_post, double omega, Enq& q);
 
 // The same cycle for V(2,2) from the fused smoothing passes; with partials
-// the top-level pass also reduces the residual norm into scal[slot].
+// the top-level pass also reduces the residual norm into scal[slot] (and
+// into host[slot] when host is not null).
 template <typename T>
 hipError_t enqueue_vcycle_fused(mg_hierarchy* h, int l, T* x, const T* b, bool x_zero,
-                                double omega, Enq& q, double* partials, double* scal, int slot);
+                                double omega, Enq& q, double* partials, double* scal, int slot,
+                                double* host);
 
 void destroy_graphs(mg_hierarchy* h);
 

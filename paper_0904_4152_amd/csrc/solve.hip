@@ -91,7 +91,7 @@ hipError_t enqueue_vcycle(mg_hierarchy* h, int l, T* x, const T* b, bool x_zero,
         }
         std::swap(cur, oth);
     }
-    MG_TRY(launch_defect<T>(lv, bands, b, cur, oth, nullptr, nullptr, 0, q.st));
+    MG_TRY(launch_defect<T>(lv, bands, b, cur, oth, nullptr, nullptr, 0, nullptr, q.st));
     q.bytes += 12 * s * n;
     Level& lc = h->lv[l - 1];
     MG_TRY(launch_restrict<T>(lv.N, oth, LV<T>::b(lc), q.st));
@@ -120,12 +120,13 @@ template hipError_t enqueue_vcycle<float>(mg_hierarchy*, int, float*, const floa
 // V(2,2) cycle from the fused passes: per level one pre pass (two sweeps,
 // defect, restriction: x -> t, b_c) and one post pass (prolongation, two
 // sweeps: t + P x_c -> x).  With partials the top-level post pass also
-// reduces ||b - A x|| into scal[slot], scal[slot + 1].  Byte model: bands
+// reduces ||b - A x|| into scal[slot], scal[slot + 1] (and host[slot..]).  Byte model: bands
 // (9 s), iterate in (s, not when from zero), b (s) and iterate out (s) per
 // node and pass, plus the coarse vector (s per coarse node).
 template <typename T>
 hipError_t enqueue_vcycle_fused(mg_hierarchy* h, int l, T* x, const T* b, bool x_zero,
-                                double omega, Enq& q, double* partials, double* scal, int slot) {
+                                double omega, Enq& q, double* partials, double* scal, int slot,
+                                double* host) {
     Level& lv = h->lv[l];
     const double s = sizeof(T), n = (double)lv.n;
     const T om = (T)omega;
@@ -134,7 +135,7 @@ hipError_t enqueue_vcycle_fused(mg_hierarchy* h, int l, T* x, const T* b, bool x
         MG_TRY(launch_coarse<T>(h->chol, h->m, lv.N, b, x, q.st));
         q.bytes += 2 * s * n;
         if (partials) {
-            MG_TRY(launch_defect<T>(lv, bands, b, x, nullptr, partials, scal, slot, q.st));
+            MG_TRY(launch_defect<T>(lv, bands, b, x, nullptr, partials, scal, slot, host, q.st));
             q.bytes += 11 * s * n;
         }
         return hipSuccess;
@@ -149,17 +150,18 @@ hipError_t enqueue_vcycle_fused(mg_hierarchy* h, int l, T* x, const T* b, bool x
         for (int k = h->Lc + 1; k < l; ++k) q.bytes += 84.0 * s * (double)h->lv[k].n;
     } else {
         MG_TRY(enqueue_vcycle_fused<T>(h, l - 1, LV<T>::x(lc), LV<T>::b(lc), true, omega, q,
-                                       nullptr, nullptr, 0));
+                                       nullptr, nullptr, 0, nullptr));
     }
-    MG_TRY(launch_post<T>(lv, bands, t, LV<T>::x(lc), b, om, x, partials, scal, slot, q.st));
+    MG_TRY(launch_post<T>(lv, bands, t, LV<T>::x(lc), b, om, x, partials, scal, slot, host,
+                          q.st));
     q.bytes += 12 * s * n + s * (double)lc.n;
     return hipSuccess;
 }
 
 template hipError_t enqueue_vcycle_fused<double>(mg_hierarchy*, int, double*, const double*, bool,
-                                                 double, Enq&, double*, double*, int);
+                                                 double, Enq&, double*, double*, int, double*);
 template hipError_t enqueue_vcycle_fused<float>(mg_hierarchy*, int, float*, const float*, bool,
-                                                double, Enq&, double*, double*, int);
+                                                double, Enq&, double*, double*, int, double*);
 
 // The unit replayed per iteration: FP64 cycle + FP64 residual norm (kind 0)
 // or FP32 inner cycle + FP32 residual norm (kind 1), on the finest level's
@@ -171,19 +173,19 @@ static hipError_t enqueue_unit(mg_hierarchy* h, int kind, int nu_pre, int nu_pos
     if (nu_pre == 2 && nu_post == 2) {
         if (kind == 0)
             return enqueue_vcycle_fused<double>(h, h->L, F.x64, F.b64, false, omega, q,
-                                                h->partials, h->scal, SC_R64);
+                                                h->partials, h->scal, SC_R64, h->host_scal);
         return enqueue_vcycle_fused<float>(h, h->L, F.x32, F.b32, x_zero, omega, q, h->partials,
-                                           h->scal, SC_R32);
+                                           h->scal, SC_R32, h->host_scal);
     }
     if (kind == 0) {
         MG_TRY(enqueue_vcycle<double>(h, h->L, F.x64, F.b64, false, nu_pre, nu_post, omega, q));
         MG_TRY(launch_defect<double>(F, F.bands64, F.b64, F.x64, nullptr, h->partials, h->scal,
-                                     SC_R64, q.st));
+                                     SC_R64, h->host_scal, q.st));
         q.bytes += 11 * 8 * n;
     } else {
         MG_TRY(enqueue_vcycle<float>(h, h->L, F.x32, F.b32, x_zero, nu_pre, nu_post, omega, q));
         MG_TRY(launch_defect<float>(F, F.bands32, F.b32, F.x32, nullptr, h->partials, h->scal,
-                                    SC_R32, q.st));
+                                    SC_R32, h->host_scal, q.st));
         q.bytes += 11 * 4 * n;
     }
     return hipSuccess;
@@ -236,11 +238,11 @@ static hipError_t run_unit(mg_hierarchy* h, int kind, const mg_solve_opts& o, bo
     return enqueue_unit(h, kind, o.nu_pre, o.nu_post, o.omega, x_zero, q);
 }
 
+// The norm a reduction enqueued on st left in the pinned mirror (every
+// reduction the drivers read back writes it there directly: no copy).
 static hipError_t read_scalar(mg_hierarchy* h, int slot, hipStream_t st, double* out) {
-    MG_TRY(hipMemcpyAsync(h->host_scal + slot, h->scal + slot, 2 * sizeof(double),
-                          hipMemcpyDeviceToHost, st));
     MG_TRY(hipStreamSynchronize(st));
-    *out = h->host_scal[slot + 1];
+    *out = ((const volatile double*)h->host_scal)[slot + 1];
     return hipSuccess;
 }
 
@@ -290,10 +292,10 @@ extern "C" mg_status mg_vcycle(mg_hierarchy* h, int level, mg_dtype dtype, const
         return fail(MG_ERR_INVALID, "the fused cycle is V(2,2)");
     if (fused && dtype == MG_F64)
         MG_HIP(enqueue_vcycle_fused<double>(h, level, (double*)x, (const double*)b, false, omega, q,
-                                            nullptr, nullptr, 0));
+                                            nullptr, nullptr, 0, nullptr));
     else if (fused)
         MG_HIP(enqueue_vcycle_fused<float>(h, level, (float*)x, (const float*)b, false, omega, q,
-                                           nullptr, nullptr, 0));
+                                           nullptr, nullptr, 0, nullptr));
     else if (dtype == MG_F64)
         MG_HIP(enqueue_vcycle<double>(h, level, (double*)x, (const double*)b, false, nu_pre,
                                       nu_post, omega, q));
@@ -329,7 +331,7 @@ extern "C" mg_status mg_solve(mg_hierarchy* h, const double* dev_b, double* dev_
     const bool graphs = o.use_graph != 0;
     MG_HIPS(launch_copy<double>(dev_b, F.b64, n, q.st));
     MG_HIPS(launch_copy<double>(dev_x, F.x64, n, q.st));
-    MG_HIPS(launch_norm<double>(F.b64, n, h->partials, h->scal, SC_B, q.st));
+    MG_HIPS(launch_norm<double>(F.b64, n, h->partials, h->scal, SC_B, h->host_scal, q.st));
     q.bytes += 8.0 * 5 * n;
     double bn = 0.0;
     MG_HIPS(read_scalar(h, SC_B, q.st, &bn));
@@ -342,7 +344,7 @@ extern "C" mg_status mg_solve(mg_hierarchy* h, const double* dev_b, double* dev_
     } else if (o.precision == MG_PREC_FP64) {
         double r = 0.0;
         MG_HIPS(launch_defect<double>(F, F.bands64, F.b64, F.x64, nullptr, h->partials, h->scal,
-                                      SC_R64, q.st));
+                                      SC_R64, h->host_scal, q.st));
         q.bytes += 11.0 * 8 * n;
         MG_HIPS(read_scalar(h, SC_R64, q.st, &r));
         st.rel_res = r / bn;
@@ -370,7 +372,7 @@ extern "C" mg_status mg_solve(mg_hierarchy* h, const double* dev_b, double* dev_
         for (int k = 1;; ++k) {
             double s = 0.0;
             MG_HIPS(launch_defect<double>(F, F.bands64, F.b64, F.x64, h->d64, h->partials,
-                                          h->scal, SC_R64, q.st));
+                                          h->scal, SC_R64, h->host_scal, q.st));
             q.bytes += 12.0 * 8 * n;
             MG_HIPS(read_scalar(h, SC_R64, q.st, &s));
             st.rel_res = s / bn;
@@ -390,7 +392,8 @@ extern "C" mg_status mg_solve(mg_hierarchy* h, const double* dev_b, double* dev_
             }
             if (s == 0.0) break;
             MG_HIPS(launch_cast_scaled(h->d64, F.b32, n, h->scal, SC_R64, q.st));
-            MG_HIPS(launch_norm<float>(F.b32, n, h->partials, h->scal, SC_D32, q.st));
+            MG_HIPS(launch_norm<float>(F.b32, n, h->partials, h->scal, SC_D32, h->host_scal,
+                                       q.st));
             q.bytes += 16.0 * n;
             double dn = 0.0;
             MG_HIPS(read_scalar(h, SC_D32, q.st, &dn));
