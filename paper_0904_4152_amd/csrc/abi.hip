@@ -261,7 +261,7 @@ mg_status mg_hierarchy_create(mg_context* ctx, int L, int Lc, double jitter, uin
         e = hipMemcpy(h->coords, host_xy, 2 * nL * sizeof(double), hipMemcpyHostToDevice);
     else
         e = launch_coords(h->coords, L, jitter, seed, nullptr);
-    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);  // null stream only: others keep running
     if (e != hipSuccess) {
         free_arrays(h);
         ctx->release(total);
@@ -276,7 +276,7 @@ mg_status mg_hierarchy_assemble(mg_hierarchy* h, void* stream) {
     if (!h) return fail(MG_ERR_INVALID, "null hierarchy");
     if (mg_status s = set_device(h)) return s;
     hipStream_t st = (hipStream_t)stream;
-    for (int l = h->Lc; l <= h->L; ++l) MG_HIP(launch_assemble(h->coords, h->L, h->lv[l], st));
+    MG_HIP(launch_assemble(h->coords, h->lv, h->Lc, h->L, st));
     MG_HIP(launch_chol_factor(h->lv[h->Lc], h->chol, h->flag, st));
     int flag = 0;
     MG_HIP(hipMemcpyAsync(&flag, h->flag, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -347,7 +347,7 @@ mg_status mg_rhs_uniform(const mg_hierarchy* h, uint64_t seed, double* dev_b, vo
     if (!h) return fail(MG_ERR_INVALID, "null hierarchy");
     if (!dev_b) return fail(MG_ERR_INVALID, "null b");
     if (mg_status s = set_device(h)) return s;
-    MG_HIP(launch_rhs_uniform(h->lv[h->L].N, seed, dev_b, (hipStream_t)stream));
+    MG_HIP(launch_rhs_uniform(h->lv[h->L].N, seed, dev_b, nullptr, (hipStream_t)stream));
     return MG_OK;
 }
 

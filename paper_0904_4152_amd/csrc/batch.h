@@ -80,8 +80,25 @@ public:
     void clear_slot(int s);
     // Mark slot s to start a solve from its hierarchy's finest b64 / x64.
     void start_slot(int s);
-    // Upload changed descriptors, work lists and started states.
+    // Upload changed descriptors, work lists and started states; synchronous.
     mg_status upload();
+    // The same, stream-ordered (later launches see it; it waits for the work
+    // enqueued on setup_stream() so far).
+    mg_status upload_async();
+    // Asynchronous stepping: launch one iteration; wait for iteration k and
+    // read its report (live and certainly-continuing problems, and every
+    // slot's flags as of its end, valid until iteration k + ITER_RING is
+    // launched).
+    mg_status launch_iteration();
+    mg_status wait_iteration(int64_t k, int* live, int* sure, const int** flags);
+    int64_t launched() const { return launched_; }
+    // Device-to-host copies unordered with the iterations, for data of
+    // finished problems only.
+    mg_status fetch(const void* dev, void* host, size_t bytes);
+    mg_status fetch_state(int s, BState* out);
+    // Stream for building new problems (assembly); upload_async orders the
+    // iterations after it.
+    hipStream_t setup_stream() const { return setup_st_; }
     // One iteration over all live slots (graph replay); synchronous.
     mg_status step(int* active_left);
     // Iterations until every slot is done (at most iter_cap), keeping the
@@ -111,6 +128,14 @@ private:
     int* h_ring_ = nullptr;   // pinned: per iteration, live and sure counts
     hipEvent_t ev_[ITER_RING] = {};  // end of the iterations in flight
     int64_t launched_ = 0;    // iterations launched (equals the device counter)
+    hipStream_t setup_st_ = nullptr, read_st_ = nullptr;
+    hipEvent_t ev_setup_ = nullptr;
+    hipEvent_t ev_upload_[2] = {};   // staging area b free again
+    int ubuf_ = 0;
+    BProb* h_probs_stage_[2] = {};   // pinned staging of descriptors,
+    int* h_wl_stage_[2] = {};        // work lists
+    BState* h_start_stage_[2] = {};  // and started states
+    BState* h_fetch_ = nullptr;      // pinned, one state
     std::vector<BProb> hp_;
     std::vector<int> h_wl_;
     std::vector<char> started_;

@@ -193,7 +193,7 @@ __global__ __launch_bounds__(BLOCK) void kb_copy(const BProb* __restrict__ probs
 
 // Coarse tail of every problem above the coarse level (one block each): the
 // sub-cycle over levels min(L - 1, TAIL_MAX) .. Lc.
-__global__ __launch_bounds__(BLOCK) void kb_tail(const BProb* __restrict__ probs,
+__global__ __launch_bounds__(dev::TAIL_THREADS) void kb_tail(const BProb* __restrict__ probs,
                                                  const BState* __restrict__ state,
                                                  const int* __restrict__ wl, int Lc, int mask) {
     FOR_ITEMS(wl)
@@ -384,18 +384,24 @@ __global__ __launch_bounds__(BLOCK) void kb_finalize(const BProb* __restrict__ p
 }
 
 // Per-problem transitions of the mixed scheme (one block; thread per slot).
-// At the end of an iteration (PH_INNER) also reports to the host, in slot
-// k mod ITER_RING of the pinned ring (k = iterations so far): the problems
-// not done, and those still in their inner loop, which cannot finish in the
-// next iteration (a problem finishes only at an outer step).
+// At the end of an iteration (PH_INNER) also reports to the host, in entry
+// k mod ITER_RING of the pinned ring (k = iterations so far; entries of
+// 2 + cap ints): the problems not done, those still in their inner loop,
+// which cannot finish in the next iteration (a problem finishes only at an
+// outer step), and every slot's flags (0 for an empty slot).
 __global__ __launch_bounds__(BLOCK) void kb_ctrl(const BProb* __restrict__ probs,
                                                  BState* __restrict__ state, int cap, int phase,
                                                  int* __restrict__ iter,
                                                  int* __restrict__ ring) {
     int live = 0, sure = 0;
+    int* entry = nullptr;
+    if (phase == PH_INNER) entry = ring + (int64_t)(*iter % ITER_RING) * (2 + cap);
     for (int p = threadIdx.x; p < cap; p += BLOCK) {
         const BProb& P = probs[p];
-        if (P.L == 0) continue;
+        if (P.L == 0) {
+            if (entry) entry[2 + p] = 0;
+            continue;
+        }
         BState& S = state[p];
         const int f = S.flags;
         if (phase == PH_INIT && (f & BF_INIT)) {
@@ -442,15 +448,16 @@ __global__ __launch_bounds__(BLOCK) void kb_ctrl(const BProb* __restrict__ probs
         }
         if (!(S.flags & BF_DONE)) ++live;
         if (S.flags == BF_INNER) ++sure;
+        if (entry) entry[2 + p] = S.flags;
     }
     if (phase == PH_INNER) {
+        __threadfence_system();
         const double tot = dev::block_sum((double)live);
         const double tsure = dev::block_sum((double)sure);
         if (threadIdx.x == 0) {
-            const int k = *iter;
-            *iter = k + 1;
-            ring[(k % ITER_RING) * 2] = (int)tot;
-            ring[(k % ITER_RING) * 2 + 1] = (int)tsure;
+            *iter = *iter + 1;
+            entry[0] = (int)tot;
+            entry[1] = (int)tsure;
             __threadfence_system();
         }
     }
@@ -464,11 +471,22 @@ BatchEngine::~BatchEngine() {
     if (d_probs_) (void)hipFree(d_probs_);
     if (d_state_) (void)hipFree(d_state_);
     if (d_wl_) (void)hipFree(d_wl_);
+    if (setup_st_) (void)hipStreamDestroy(setup_st_);
+    if (read_st_) (void)hipStreamDestroy(read_st_);
     for (hipEvent_t e : ev_)
         if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : ev_upload_)
+        if (e) (void)hipEventDestroy(e);
+    if (ev_setup_) (void)hipEventDestroy(ev_setup_);
     if (d_iter_) (void)hipFree(d_iter_);
     if (h_state_) (void)hipHostFree(h_state_);
     if (h_ring_) (void)hipHostFree(h_ring_);
+    for (int b = 0; b < 2; ++b) {
+        if (h_probs_stage_[b]) (void)hipHostFree(h_probs_stage_[b]);
+        if (h_wl_stage_[b]) (void)hipHostFree(h_wl_stage_[b]);
+        if (h_start_stage_[b]) (void)hipHostFree(h_start_stage_[b]);
+    }
+    if (h_fetch_) (void)hipHostFree(h_fetch_);
 }
 
 mg_status BatchEngine::init(int device, int capacity, int Lmax, int Lc, int nu_pre,
@@ -482,6 +500,19 @@ mg_status BatchEngine::init(int device, int capacity, int Lmax, int Lc, int nu_p
     nu_post_ = nu_post;
     MG_HIP(hipSetDevice(device));
     MG_HIP(hipStreamCreateWithFlags(&st_, hipStreamNonBlocking));
+    MG_HIP(hipStreamCreateWithFlags(&setup_st_, hipStreamNonBlocking));
+    MG_HIP(hipStreamCreateWithFlags(&read_st_, hipStreamNonBlocking));
+    MG_HIP(hipEventCreateWithFlags(&ev_setup_, hipEventDisableTiming));
+    for (hipEvent_t& e : ev_upload_) MG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    const size_t wl_ints = (size_t)NLISTS * (3 + 2 * cap_);
+    for (int b = 0; b < 2; ++b) {
+        MG_HIP(hipHostMalloc((void**)&h_probs_stage_[b], sizeof(BProb) * cap_,
+                             hipHostMallocDefault));
+        MG_HIP(hipHostMalloc((void**)&h_wl_stage_[b], sizeof(int) * wl_ints, hipHostMallocDefault));
+        MG_HIP(hipHostMalloc((void**)&h_start_stage_[b], sizeof(BState) * cap_,
+                             hipHostMallocDefault));
+    }
+    MG_HIP(hipHostMalloc((void**)&h_fetch_, sizeof(BState), hipHostMallocDefault));
     MG_HIP(hipMalloc(&d_probs_, sizeof(BProb) * cap_));
     MG_HIP(hipMalloc(&d_state_, sizeof(BState) * cap_));
     MG_HIP(hipMalloc(&d_wl_, sizeof(int) * NLISTS * (3 + 2 * cap_)));
@@ -490,8 +521,9 @@ mg_status BatchEngine::init(int device, int capacity, int Lmax, int Lc, int nu_p
     launched_ = 0;
     for (hipEvent_t& e : ev_) MG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     MG_HIP(hipHostMalloc((void**)&h_state_, sizeof(BState) * cap_, hipHostMallocDefault));
-    MG_HIP(hipHostMalloc((void**)&h_ring_, sizeof(int) * 2 * ITER_RING, hipHostMallocDefault));
-    std::memset(h_ring_, 0, sizeof(int) * 2 * ITER_RING);
+    const size_t ring_ints = (size_t)ITER_RING * (2 + cap_);
+    MG_HIP(hipHostMalloc((void**)&h_ring_, sizeof(int) * ring_ints, hipHostMallocDefault));
+    std::memset(h_ring_, 0, sizeof(int) * ring_ints);
     hp_.assign(cap_, BProb{});
     started_.assign(cap_, 0);
     std::memset(h_state_, 0, sizeof(BState) * cap_);
@@ -613,26 +645,69 @@ void BatchEngine::build_lists() {
     }
 }
 
-mg_status BatchEngine::upload() {
+// Stream-ordered: launches after this call see the new descriptors, lists
+// and started states, and wait for the work enqueued on setup_stream() so
+// far.  Host data goes through one of two pinned staging areas, each reused
+// only after its previous copies have completed.
+mg_status BatchEngine::upload_async() {
     MG_HIP(hipSetDevice(device_));
+    MG_HIP(hipEventRecord(ev_setup_, setup_st_));
+    MG_HIP(hipStreamWaitEvent(st_, ev_setup_, 0));
+    const int b = ubuf_;
+    ubuf_ ^= 1;
+    MG_HIP(hipEventSynchronize(ev_upload_[b]));
     if (probs_dirty_) {
         build_lists();
-        MG_HIP(hipMemcpyAsync(d_probs_, hp_.data(), sizeof(BProb) * cap_, hipMemcpyHostToDevice,
-                              st_));
-        MG_HIP(hipMemcpyAsync(d_wl_, h_wl_.data(), sizeof(int) * h_wl_.size(),
+        std::memcpy(h_probs_stage_[b], hp_.data(), sizeof(BProb) * cap_);
+        std::memcpy(h_wl_stage_[b], h_wl_.data(), sizeof(int) * h_wl_.size());
+        MG_HIP(hipMemcpyAsync(d_probs_, h_probs_stage_[b], sizeof(BProb) * cap_,
+                              hipMemcpyHostToDevice, st_));
+        MG_HIP(hipMemcpyAsync(d_wl_, h_wl_stage_[b], sizeof(int) * h_wl_.size(),
                               hipMemcpyHostToDevice, st_));
         probs_dirty_ = false;
     }
     for (int s = 0; s < cap_; ++s) {
         if (!started_[s]) continue;
-        BState& S = h_state_[s];
+        BState& S = h_start_stage_[b][s];
         std::memset(&S, 0, sizeof(BState));
         S.flags = BF_INIT;
         MG_HIP(hipMemcpyAsync(d_state_ + s, &S, sizeof(BState), hipMemcpyHostToDevice, st_));
         started_[s] = 0;
     }
-    // the pinned mirror is reused by read_states: wait for the copies
+    MG_HIP(hipEventRecord(ev_upload_[b], st_));
+    return MG_OK;
+}
+
+mg_status BatchEngine::upload() {
+    if (mg_status s = upload_async()) return s;
     MG_HIP(hipStreamSynchronize(st_));
+    return MG_OK;
+}
+
+mg_status BatchEngine::launch_iteration() {
+    MG_HIP(hipSetDevice(device_));
+    if (mg_status s = ensure_graph()) return s;
+    return launch();
+}
+
+mg_status BatchEngine::wait_iteration(int64_t k, int* live, int* sure, const int** flags) {
+    if (mg_status s = wait(k, live, sure)) return s;
+    if (flags) *flags = h_ring_ + (k % ITER_RING) * (2 + cap_) + 2;
+    return MG_OK;
+}
+
+// Device-to-host copy on the read stream, unordered with the iterations:
+// only for data no queued iteration writes (the state and iterate of a
+// finished problem).
+mg_status BatchEngine::fetch(const void* dev, void* host, size_t bytes) {
+    MG_HIP(hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, read_st_));
+    MG_HIP(hipStreamSynchronize(read_st_));
+    return MG_OK;
+}
+
+mg_status BatchEngine::fetch_state(int s, BState* out) {
+    if (mg_status e = fetch(d_state_ + s, h_fetch_, sizeof(BState))) return e;
+    *out = *h_fetch_;
     return MG_OK;
 }
 
@@ -682,7 +757,7 @@ hipError_t BatchEngine::enqueue_iteration() {
     }
         for (int l = Lmax_; l > Lc_; --l)
             if (launch_mask_ & (1u << l)) FUSED(kb_fpre, l)
-        LAUNCH(kb_tail, GA, B, 0, st_, P, S, W(WL_ALL), Lc_, m);
+        LAUNCH(kb_tail, GA, dim3(dev::TAIL_THREADS), 0, st_, P, S, W(WL_ALL), Lc_, m);
         LAUNCH(kb_coarse, GA, B, 0, st_, P, S, W(WL_ALL), Lc_, m, Lc_);
         for (int l = Lc_ + 1; l <= Lmax_; ++l)
             if (launch_mask_ & (1u << l)) FUSED(kb_fpost, l)
@@ -757,7 +832,7 @@ mg_status BatchEngine::launch() {
 // Wait for iteration k; its counts of live and of certainly-continuing problems.
 mg_status BatchEngine::wait(int64_t k, int* live, int* sure) {
     MG_HIP(hipEventSynchronize(ev_[k % ITER_RING]));
-    const volatile int* r = h_ring_ + (k % ITER_RING) * 2;
+    const volatile int* r = h_ring_ + (k % ITER_RING) * (2 + cap_);
     *live = r[0];
     *sure = r[1];
     return MG_OK;

@@ -366,11 +366,15 @@ __device__ void post_tile(const T* __restrict__ bands, int64_t bs, int N, const 
 }
 
 // ---------------------------------------------------------------- coarse tail
-// Levels at and below TAIL_MAX hold at most 65 x 65 nodes and sit in L2: one
-// workgroup runs the whole V(2,2) sub-cycle over them (workgroup barriers
-// between the steps instead of kernel launches), with the per-node
-// arithmetic of the separate kernels.
+// Levels at and below TAIL_MAX hold at most 33 x 33 nodes: one workgroup
+// runs the whole V(2,2) sub-cycle over them, with workgroup barriers
+// between the steps instead of kernel launches.  The bands of these levels
+// and every work vector live in LDS for the whole sub-cycle (one load of the
+// bands and of b at the top level, one store of x at the top level), so the
+// chain of dependent steps runs at LDS latency.  Per-node arithmetic is the
+// one of the separate kernels: same results, bit for bit.
 constexpr int TAIL_MAX = 5;
+constexpr int TAIL_THREADS = 1024;  // about one node of the 33 x 33 level per thread
 
 template <typename T>
 struct TailLevel {
@@ -393,43 +397,109 @@ struct TailLevels {
     int Lc;
 };
 
-// x_top = V(top, 0, b_top) over levels top..Lc (one workgroup of BLOCK threads).
+// LDS image of level l: 9 bands (band-major, stride n), then x with N+1
+// zeros on either side, b, and t with N+1 zeros on either side (the zeros
+// stand for the neighbours outside the grid of the band products).
+__host__ __device__ constexpr int tail_level_elems(int l) {
+    return 12 * ((1 << l) + 1) * ((1 << l) + 1) + 4 * ((1 << l) + 2);
+}
+__host__ __device__ constexpr int tail_lds_elems() {
+    int e = 0;
+    for (int l = 1; l <= TAIL_MAX; ++l) e += tail_level_elems(l);
+    return e;
+}
+
+template <typename T>
+struct TailLds {
+    T* bands;
+    T* x;
+    T* b;
+    T* t;
+    int N, n;
+    __device__ TailLds(T* lds, int Lc, int l) {
+        int off = 0;
+        for (int m = Lc; m < l; ++m) off += tail_level_elems(m);
+        N = (1 << l) + 1;
+        n = N * N;
+        const int pad = N + 1;
+        bands = lds + off;
+        x = bands + 9 * n + pad;
+        b = x + n + pad;
+        t = b + n + pad;
+    }
+};
+
+// Band product at node p of an LDS level: the fma chain of stencil_tile.
+template <typename T>
+__device__ __forceinline__ T tail_product(const TailLds<T>& v, const T* __restrict__ x, int p) {
+    T acc = T(0);
+#pragma unroll
+    for (int k = 0; k < 9; ++k)
+        acc = fma(v.bands[k * v.n + p], x[p + (k / 3 - 1) * v.N + (k % 3 - 1)], acc);
+    return acc;
+}
+
+// Damped Jacobi sweep xo = x + omega (b - A x) / a_pp on an LDS level.
+template <typename T>
+__device__ __forceinline__ void tail_jacobi(const TailLds<T>& v, const T* x, T* xo, T omega) {
+    for (int p = threadIdx.x; p < v.n; p += TAIL_THREADS) {
+        const T acc = tail_product(v, x, p);
+        xo[p] = x[p] + omega * (v.b[p] - acc) / v.bands[4 * v.n + p];
+    }
+}
+
+// x_top = V(top, 0, b_top) over levels top..Lc (one workgroup of TAIL_THREADS
+// threads).
 template <typename T>
 __device__ void tail_cycle(const TailLevels<T>& tl, T omega) {
+    __shared__ T lds[tail_lds_elems()];
+    for (int l = tl.Lc; l <= tl.top; ++l) {
+        const TailLds<T> v(lds, tl.Lc, l);
+        const TailLevel<T>& g = tl.lv[l];
+        for (int e = threadIdx.x; e < 9 * v.n; e += TAIL_THREADS) {
+            const int k = e / v.n, p = e - k * v.n;
+            v.bands[e] = g.bands[k * g.bs + p];
+        }
+        for (int e = threadIdx.x; e < v.N + 1; e += TAIL_THREADS) {
+            v.x[-v.N - 1 + e] = v.x[v.n + e] = T(0);
+            v.t[-v.N - 1 + e] = v.t[v.n + e] = T(0);
+        }
+    }
+    {
+        const TailLds<T> v(lds, tl.Lc, tl.top);
+        for (int p = threadIdx.x; p < v.n; p += TAIL_THREADS) v.b[p] = tl.lv[tl.top].b[p];
+    }
+    __syncthreads();
     for (int l = tl.top; l > tl.Lc; --l) {
-        const TailLevel<T>& v = tl.lv[l];
-        const T* diag = v.bands + 4 * v.bs;
-        for (int64_t p = threadIdx.x; p < v.n; p += BLOCK) jacobi_zero_elem(diag, v.b, v.t, p, omega);
+        const TailLds<T> v(lds, tl.Lc, l);
+        for (int p = threadIdx.x; p < v.n; p += TAIL_THREADS)
+            jacobi_zero_elem(v.bands + 4 * v.n, v.b, v.t, p, omega);
         __syncthreads();
-        for (int64_t blo = 0; blo < v.n; blo += tile_rows<T>())
-            stencil_tile<T, OP_JACOBI, false, true>(v.bands, v.bs, v.N, v.n, v.t, v.b, v.x, omega,
-                                                    blo);
+        tail_jacobi(v, v.t, v.x, omega);
         __syncthreads();
-        for (int64_t blo = 0; blo < v.n; blo += tile_rows<T>())
-            stencil_tile<T, OP_DEFECT, false, true>(v.bands, v.bs, v.N, v.n, v.x, v.b, v.t, omega,
-                                                    blo);
+        for (int p = threadIdx.x; p < v.n; p += TAIL_THREADS) v.t[p] = v.b[p] - tail_product(v, v.x, p);
         __syncthreads();
-        const TailLevel<T>& c = tl.lv[l - 1];
-        for (int64_t q = threadIdx.x; q < c.n; q += BLOCK)
-            restrict_elem<T>(v.N, v.t, c.b, (int)(q % c.N), (int)(q / c.N));
+        const TailLds<T> c(lds, tl.Lc, l - 1);
+        for (int q = threadIdx.x; q < c.n; q += TAIL_THREADS)
+            restrict_elem<T>(v.N, v.t, c.b, q % c.N, q / c.N);
         __syncthreads();
     }
-    coarse_block<T>(tl.chol, tl.m, tl.lv[tl.Lc].N, tl.lv[tl.Lc].b, tl.lv[tl.Lc].x);
+    {
+        const TailLds<T> c(lds, tl.Lc, tl.Lc);
+        coarse_block<T>(tl.chol, tl.m, c.N, c.b, c.x);
+    }
     for (int l = tl.Lc + 1; l <= tl.top; ++l) {
-        const TailLevel<T>& v = tl.lv[l];
-        const TailLevel<T>& c = tl.lv[l - 1];
-        for (int64_t p = threadIdx.x; p < v.n; p += BLOCK)
-            prolong_elem<T>(v.N, c.x, v.x, (int)(p % v.N), (int)(p / v.N));
+        const TailLds<T> v(lds, tl.Lc, l);
+        const TailLds<T> c(lds, tl.Lc, l - 1);
+        for (int p = threadIdx.x; p < v.n; p += TAIL_THREADS) prolong_elem<T>(v.N, c.x, v.x, p % v.N, p / v.N);
         __syncthreads();
-        for (int64_t blo = 0; blo < v.n; blo += tile_rows<T>())
-            stencil_tile<T, OP_JACOBI, false, true>(v.bands, v.bs, v.N, v.n, v.x, v.b, v.t, omega,
-                                                    blo);
+        tail_jacobi(v, v.x, v.t, omega);
         __syncthreads();
-        for (int64_t blo = 0; blo < v.n; blo += tile_rows<T>())
-            stencil_tile<T, OP_JACOBI, false, true>(v.bands, v.bs, v.N, v.n, v.t, v.b, v.x, omega,
-                                                    blo);
+        tail_jacobi(v, v.t, v.x, omega);
         __syncthreads();
     }
+    const TailLds<T> v(lds, tl.Lc, tl.top);
+    for (int p = threadIdx.x; p < v.n; p += TAIL_THREADS) tl.lv[tl.top].x[p] = v.x[p];
 }
 
 }  // namespace dev

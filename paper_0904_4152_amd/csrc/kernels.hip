@@ -158,7 +158,7 @@ __global__ __launch_bounds__(BT) void k_post(const T* __restrict__ bands, int64_
 
 // Coarse tail: the V(2,2) sub-cycle over levels top..Lc in one workgroup.
 template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_tail(dev::TailLevels<T> tl, T omega) {
+__global__ __launch_bounds__(dev::TAIL_THREADS) void k_tail(dev::TailLevels<T> tl, T omega) {
     dev::tail_cycle<T>(tl, omega);
 }
 
@@ -252,14 +252,17 @@ struct Quad {
 __device__ __constant__ double kSX[4] = {-1.0, 1.0, 1.0, -1.0};
 __device__ __constant__ double kSY[4] = {-1.0, -1.0, 1.0, 1.0};
 
-// Row `a` of the element stiffness matrix (2x2 Gauss):
+// Element stiffness matrix (2x2 Gauss):
 //   K[a][b] = sum_q (G_a G_b + H_a H_b) / det J_q
 // with G = det J * d(phi)/dx and H = det J * d(phi)/dy expressed through
-// the cofactors of J.  G and H are computed for all four corners with the
-// same instructions in every thread, so K[a][b] and K[b][a] agree bitwise.
-__device__ void element_row(const Quad& q, int a, double* Krow) {
+// the cofactors of J.  Each entry with b >= a is computed once and mirrored,
+// so K is symmetric bit for bit.
+__device__ void element_matrix(const Quad& q, double (&K)[4][4]) {
     const double g = 0.57735026918962576451;  // 1/sqrt(3)
-    for (int b = 0; b < 4; ++b) Krow[b] = 0.0;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) K[a][b] = 0.0;
 #pragma unroll
     for (int qp = 0; qp < 4; ++qp) {
         const double xi = (qp & 1) ? g : -g;
@@ -275,16 +278,15 @@ __device__ void element_row(const Quad& q, int a, double* Krow) {
             G[c] = ye * dxi - yx * deta;
             H[c] = xx * deta - xe * dxi;
         }
-        double Ga = G[0], Ha = H[0];
 #pragma unroll
-        for (int c = 1; c < 4; ++c)
-            if (c == a) {
-                Ga = G[c];
-                Ha = H[c];
-            }
+        for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) Krow[b] += (Ga * G[b] + Ha * H[b]) / det;
+            for (int b = a; b < 4; ++b) K[a][b] += (G[a] * G[b] + H[a] * H[b]) / det;
     }
+#pragma unroll
+    for (int a = 1; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < a; ++b) K[a][b] = K[b][a];
 }
 
 __device__ __forceinline__ void level_xy(const double* __restrict__ xyf, int Nf, int s, int i,
@@ -294,17 +296,52 @@ __device__ __forceinline__ void level_xy(const double* __restrict__ xyf, int Nf,
     *y = xyf[2 * pf + 1];
 }
 
-// Node-centric assembly of one level: thread (i,j) visits the four elements
-// around its node in lexicographic order and accumulates its nine band
-// entries, then applies the Dirichlet treatment.  Writes FP64 bands and
-// their round-to-nearest FP32 copies.
-__global__ __launch_bounds__(BLOCK) void k_assemble(const double* __restrict__ xyf, int L, int l,
-                                                    double* __restrict__ b64,
-                                                    float* __restrict__ b32, int64_t bs) {
-    const int N = (1 << l) + 1, Nf = (1 << L) + 1, s = 1 << (L - l);
-    const int i = blockIdx.x * BLOCK + threadIdx.x;
-    const int j = blockIdx.y;
-    if (i >= N) return;
+// All levels Lc..L of a hierarchy in one launch.  A workgroup assembles a
+// tile of AT x AT nodes of one level: it first computes the stiffness
+// matrices of the (AT+1)^2 elements touching the tile into LDS, then each
+// thread sums the entries of its node's nine bands over the four elements
+// around the node in lexicographic order and applies the Dirichlet
+// treatment.  Writes FP64 bands and their round-to-nearest FP32 copies.
+// Level l owns the workgroups [first[l], first[l + 1]).
+constexpr int AT = 16;
+static_assert(AT * AT == BLOCK, "one thread per tile node");
+
+struct AssembleLevels {
+    double* b64[MG_MAX_LEVEL + 1];
+    float* b32[MG_MAX_LEVEL + 1];
+    int64_t bs[MG_MAX_LEVEL + 1];
+    int64_t first[MG_MAX_LEVEL + 2];
+    int Lc, L;
+};
+
+__global__ __launch_bounds__(BLOCK) void k_assemble(const double* __restrict__ xyf,
+                                                    AssembleLevels a) {
+    __shared__ double Ke[(AT + 1) * (AT + 1)][16];
+    const int64_t blk = blockIdx.x;
+    int l = a.Lc;
+    while (l < a.L && blk >= a.first[l + 1]) ++l;
+    const int N = (1 << l) + 1, Nf = (1 << a.L) + 1, s = 1 << (a.L - l);
+    const int tiles_x = (N + AT - 1) / AT;
+    const int64_t local = blk - a.first[l];
+    const int i0 = (int)(local % tiles_x) * AT, j0 = (int)(local / tiles_x) * AT;
+    for (int e = threadIdx.x; e < (AT + 1) * (AT + 1); e += BLOCK) {
+        const int ei = i0 - 1 + e % (AT + 1), ej = j0 - 1 + e / (AT + 1);
+        if (ei < 0 || ej < 0 || ei >= N - 1 || ej >= N - 1) continue;
+        double cx[4], cy[4];
+        level_xy(xyf, Nf, s, ei, ej, &cx[0], &cy[0]);
+        level_xy(xyf, Nf, s, ei + 1, ej, &cx[1], &cy[1]);
+        level_xy(xyf, Nf, s, ei + 1, ej + 1, &cx[2], &cy[2]);
+        level_xy(xyf, Nf, s, ei, ej + 1, &cx[3], &cy[3]);
+        Quad q;
+        q.set(cx, cy);
+        double K[4][4];
+        element_matrix(q, K);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) Ke[e][r] = K[r / 4][r % 4];
+    }
+    __syncthreads();
+    const int i = i0 + (int)threadIdx.x % AT, j = j0 + (int)threadIdx.x / AT;
+    if (i >= N || j >= N) return;
     const int64_t p = (int64_t)j * N + i;
     double band[9];
 #pragma unroll
@@ -313,28 +350,20 @@ __global__ __launch_bounds__(BLOCK) void k_assemble(const double* __restrict__ x
     if (bnd) {
         band[4] = 1.0;
     } else {
-        // element (ei,ej) = (i-1+ex, j-1+ey); this node is its corner a.
+        // element (ei,ej) = (i-1+ex, j-1+ey); this node is its corner c_node.
         const int corner_of[4] = {2, 3, 1, 0};
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const int ex = e & 1, ey = e >> 1;
             const int ei = i - 1 + ex, ej = j - 1 + ey;
-            double cx[4], cy[4];
-            level_xy(xyf, Nf, s, ei, ej, &cx[0], &cy[0]);
-            level_xy(xyf, Nf, s, ei + 1, ej, &cx[1], &cy[1]);
-            level_xy(xyf, Nf, s, ei + 1, ej + 1, &cx[2], &cy[2]);
-            level_xy(xyf, Nf, s, ei, ej + 1, &cx[3], &cy[3]);
-            Quad q;
-            q.set(cx, cy);
-            const int a = corner_of[e];
-            double Krow[4];
-            element_row(q, a, Krow);
+            const double* K = Ke[(ej - j0 + 1) * (AT + 1) + (ei - i0 + 1)];
+            const int c_node = corner_of[e];
             // corner c sits at (ei + ox[c], ej + oy[c]); this node at (i, j)
             const int ox[4] = {0, 1, 1, 0}, oy[4] = {0, 0, 1, 1};
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 const int di = ei + ox[c] - i, dj = ej + oy[c] - j;
-                band[(dj + 1) * 3 + (di + 1)] += Krow[c];
+                band[(dj + 1) * 3 + (di + 1)] += K[c_node * 4 + c];
             }
         }
 #pragma unroll
@@ -343,6 +372,9 @@ __global__ __launch_bounds__(BLOCK) void k_assemble(const double* __restrict__ x
             if (k != 4 && (ii == 0 || jj == 0 || ii == N - 1 || jj == N - 1)) band[k] = 0.0;
         }
     }
+    double* b64 = a.b64[l];
+    float* b32 = a.b32[l];
+    const int64_t bs = a.bs[l];
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
         b64[k * bs + p] = band[k];
@@ -394,8 +426,10 @@ __global__ __launch_bounds__(BLOCK) void k_rhs_sinsin(const double* __restrict__
     bout[p] = sum;
 }
 
+// Seeded uniform right-hand side; with x0 also a zero initial iterate.
 __global__ __launch_bounds__(BLOCK) void k_rhs_uniform(int N, uint64_t seed,
-                                                       double* __restrict__ bout) {
+                                                       double* __restrict__ bout,
+                                                       double* __restrict__ x0) {
     const int i = blockIdx.x * BLOCK + threadIdx.x;
     const int j = blockIdx.y;
     if (i >= N) return;
@@ -403,6 +437,7 @@ __global__ __launch_bounds__(BLOCK) void k_rhs_uniform(int N, uint64_t seed,
     double v = 0.0;
     if (i > 0 && j > 0 && i < N - 1 && j < N - 1) v = 2.0 * uniform01(seed, (uint64_t)p) - 1.0;
     bout[p] = v;
+    if (x0) x0[p] = 0.0;
 }
 
 template <typename T>
@@ -461,9 +496,21 @@ hipError_t launch_coords(double* xy, int L, double jitter, uint64_t seed, hipStr
     return hipGetLastError();
 }
 
-hipError_t launch_assemble(const double* xy_fine, int L, const Level& lv, hipStream_t st) {
-    hipLaunchKernelGGL(k_assemble, dim3(blocks1d(lv.N), lv.N), dim3(BLOCK), 0, st, xy_fine, L,
-                       lv.l, lv.bands64, lv.bands32, lv.bs);
+hipError_t launch_assemble(const double* xy_fine, const Level* lv, int Lc, int L, hipStream_t st) {
+    AssembleLevels a{};
+    a.Lc = Lc;
+    a.L = L;
+    int64_t nb = 0;
+    for (int l = Lc; l <= L; ++l) {
+        const int64_t N = (int64_t(1) << l) + 1, t = (N + AT - 1) / AT;
+        a.b64[l] = lv[l].bands64;
+        a.b32[l] = lv[l].bands32;
+        a.bs[l] = lv[l].bs;
+        a.first[l] = nb;
+        nb += t * t;
+    }
+    a.first[L + 1] = nb;
+    hipLaunchKernelGGL(k_assemble, dim3((unsigned)nb), dim3(BLOCK), 0, st, xy_fine, a);
     return hipGetLastError();
 }
 
@@ -478,8 +525,8 @@ hipError_t launch_rhs_sinsin(const double* xy, int N, double* b, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_rhs_uniform(int N, uint64_t seed, double* b, hipStream_t st) {
-    hipLaunchKernelGGL(k_rhs_uniform, dim3(blocks1d(N), N), dim3(BLOCK), 0, st, N, seed, b);
+hipError_t launch_rhs_uniform(int N, uint64_t seed, double* b, double* x0, hipStream_t st) {
+    hipLaunchKernelGGL(k_rhs_uniform, dim3(blocks1d(N), N), dim3(BLOCK), 0, st, N, seed, b, x0);
     return hipGetLastError();
 }
 
@@ -647,7 +694,7 @@ hipError_t launch_tail(const Level* lv, int top, int Lc, const double* chol, int
     tl.m = m;
     tl.top = top;
     tl.Lc = Lc;
-    hipLaunchKernelGGL(k_tail<T>, dim3(1), dim3(BLOCK), 0, st, tl, omega);
+    hipLaunchKernelGGL(k_tail<T>, dim3(1), dim3(dev::TAIL_THREADS), 0, st, tl, omega);
     return hipGetLastError();
 }
 

@@ -89,10 +89,12 @@ enum : int { SC_B = 0, SC_R64 = 2, SC_R32 = 4, SC_D32 = 6, SC_USER = 8 };
 // ---------------------------------------------------------------- kernels
 // All launchers enqueue on `st` and return the HIP launch error.
 hipError_t launch_coords(double* xy, int L, double jitter, uint64_t seed, hipStream_t st);
-hipError_t launch_assemble(const double* xy_fine, int L, const Level& lv, hipStream_t st);
+// Bands of levels Lc..L (lv indexed by level) from the finest coordinates.
+hipError_t launch_assemble(const double* xy_fine, const Level* lv, int Lc, int L, hipStream_t st);
 hipError_t launch_chol_factor(const Level& lc, double* chol, int* flag, hipStream_t st);
 hipError_t launch_rhs_sinsin(const double* xy, int N, double* b, hipStream_t st);
-hipError_t launch_rhs_uniform(int N, uint64_t seed, double* b, hipStream_t st);
+// Seeded uniform right-hand side; x0 (nullable) set to zero alongside.
+hipError_t launch_rhs_uniform(int N, uint64_t seed, double* b, double* x0, hipStream_t st);
 
 // Stencil family on one level.
 template <typename T>

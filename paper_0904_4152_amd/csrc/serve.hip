@@ -5,7 +5,9 @@
 // uniform right-hand side) in a resident hierarchy of its level, and
 // advances all live requests together one graph-replayed iteration at a
 // time.  Requests that arrive while others run join at the next iteration
-// (continuous batching); finished ones leave their slot at once.
+// (continuous batching); finished ones leave their slot at once.  The
+// device always has the next iteration queued while the scheduler handles
+// the report of the previous one, so host work does not idle the GPU.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -75,12 +77,15 @@ struct mg_server {
     std::vector<mg_hierarchy*> slot_h;
     std::multimap<int, mg_hierarchy*> pool;      // idle hierarchies by level
     std::deque<mg_hierarchy*> pool_lru;
+    std::vector<int64_t> slot_first;             // first iteration that sees the slot's problem
     int live = 0;
+    bool dirty = false;                          // slots changed since the last upload
     uint64_t completed = 0;
     size_t queue_high = 0;
     double busy_seconds = 0.0;
 
     void run();
+    bool complete(int s);
     mg_hierarchy* take_hierarchy(int L);
     void release_hierarchy(mg_hierarchy* h);
     bool admit_one(int slot, const Request& r);
@@ -137,13 +142,12 @@ void mg_server::release_hierarchy(mg_hierarchy* h) {
 bool mg_server::admit_one(int slot, const Request& r) {
     mg_hierarchy* h = take_hierarchy(r.L);
     if (!h) return false;
-    hipStream_t st = eng.stream();
+    hipStream_t st = eng.setup_stream();
     hipError_t e = launch_coords(h->coords, r.L, r.jitter, r.geom_seed, st);
-    for (int l = Lc; l <= r.L && e == hipSuccess; ++l) e = launch_assemble(h->coords, r.L, h->lv[l], st);
+    if (e == hipSuccess) e = launch_assemble(h->coords, h->lv, Lc, r.L, st);
     if (e == hipSuccess) e = launch_chol_factor(h->lv[Lc], h->chol, h->flag, st);
     const Level& F = h->lv[r.L];
-    if (e == hipSuccess) e = launch_rhs_uniform(F.N, r.rhs_seed, F.b64, st);
-    if (e == hipSuccess) e = launch_fill<double>(F.x64, F.n, 0.0, st);
+    if (e == hipSuccess) e = launch_rhs_uniform(F.N, r.rhs_seed, F.b64, F.x64, st);
     if (e != hipSuccess) {
         release_hierarchy(h);
         set_fatal(MG_ERR_DEVICE, std::string("admission: ") + hipGetErrorString(e));
@@ -157,19 +161,52 @@ bool mg_server::admit_one(int slot, const Request& r) {
     slot_req[slot] = r;
     slot_req[slot].t_admit = Clock::now();
     slot_h[slot] = h;
+    slot_first[slot] = eng.launched();  // the upload precedes the next launch
     ++live;
+    dirty = true;
+    return true;
+}
+
+// Deliver the finished problem of slot s and free the slot.
+bool mg_server::complete(int s) {
+    mg_hierarchy* h = slot_h[s];
+    const Request& r = slot_req[s];
+    Result res;
+    BState S;
+    if (eng.fetch_state(s, &S) != MG_OK) return false;
+    fill_stats(S, h->L, Lc, opts.nu_pre, opts.nu_post, &res.stats);
+    if (r.keep_x) {
+        res.x.resize(h->lv[h->L].n);
+        if (eng.fetch(h->lv[h->L].x64, res.x.data(), res.x.size() * sizeof(double)) != MG_OK)
+            return false;
+    }
+    const auto now = Clock::now();
+    res.stats.seconds = secs(r.t_submit, now);
+    res.stats.queue_seconds = secs(r.t_submit, r.t_admit);
+    eng.clear_slot(s);
+    release_hierarchy(h);
+    slot_h[s] = nullptr;
+    --live;
+    dirty = true;
+    std::lock_guard<std::mutex> g(mu);
+    pending.erase(r.ticket);
+    done.emplace(r.ticket, std::move(res));
+    done_order.push_back(r.ticket);
+    ++completed;
+    cv_done.notify_all();
     return true;
 }
 
 void mg_server::run() {
     (void)hipSetDevice(ctx->device);
+    int64_t next = eng.launched();  // oldest iteration not yet reported
+    Clock::time_point t_busy{};
     for (;;) {
-        bool changed = false;
         {
             std::unique_lock<std::mutex> g(mu);
-            if (live == 0)
-                cv_work.wait(g, [&] { return stop || !queue.empty(); });
-            if (stop && queue.empty() && live == 0) return;
+            const bool idle = live == 0 && next == eng.launched();
+            if (idle) cv_work.wait(g, [&] { return stop || !queue.empty(); });
+            if (stop && queue.empty() && live == 0 && next == eng.launched()) return;
             // admit in arrival order while a slot and memory are available
             while (!queue.empty()) {
                 int slot = -1;
@@ -185,7 +222,7 @@ void mg_server::run() {
                 g.lock();
                 if (!ok) {
                     if (fatal != MG_OK) return;
-                    if (live == 0) {
+                    if (live == 0 && next == eng.launched()) {
                         // cannot fit even alone: fail the request cleanly
                         queue.pop_front();
                         pending.erase(r.ticket);
@@ -200,57 +237,39 @@ void mg_server::run() {
                     break;  // wait for running requests to free memory
                 }
                 queue.pop_front();
-                changed = true;
             }
         }
-        if (live == 0) continue;
-        if (changed && eng.upload() != MG_OK) {
+        if (dirty) {
+            if (eng.upload_async() != MG_OK) {
+                set_fatal(MG_ERR_DEVICE, mg_last_error());
+                return;
+            }
+            dirty = false;
+        }
+        // keep two iterations in flight while problems are live
+        if (live > 0 && eng.launched() - next < 2) {
+            if (next == eng.launched()) t_busy = Clock::now();
+            if (eng.launch_iteration() != MG_OK) {
+                set_fatal(MG_ERR_DEVICE, mg_last_error());
+                return;
+            }
+            if (eng.launched() - next < 2) continue;  // queue the second one first
+        }
+        if (next == eng.launched()) continue;
+        int nlive = 0, sure = 0;
+        const int* flags = nullptr;
+        if (eng.wait_iteration(next, &nlive, &sure, &flags) != MG_OK) {
             set_fatal(MG_ERR_DEVICE, mg_last_error());
             return;
         }
-        const auto t0 = Clock::now();
-        int active = 0;
-        if (eng.step(&active) != MG_OK) {
-            set_fatal(MG_ERR_DEVICE, mg_last_error());
-            return;
-        }
-        busy_seconds += secs(t0, Clock::now());
-        if (active >= live) continue;
-        if (eng.read_states() != MG_OK) {
-            set_fatal(MG_ERR_DEVICE, mg_last_error());
-            return;
-        }
+        const int64_t k = next++;
+        if (next == eng.launched()) busy_seconds += secs(t_busy, Clock::now());
         for (int s = 0; s < eng.capacity(); ++s) {
-            if (!slot_h[s] || !(eng.state(s).flags & BF_DONE)) continue;
-            mg_hierarchy* h = slot_h[s];
-            const Request& r = slot_req[s];
-            Result res;
-            fill_stats(eng.state(s), h->L, Lc, opts.nu_pre, opts.nu_post, &res.stats);
-            if (r.keep_x) {
-                res.x.resize(h->lv[h->L].n);
-                if (hipMemcpy(res.x.data(), h->lv[h->L].x64, res.x.size() * sizeof(double),
-                              hipMemcpyDeviceToHost) != hipSuccess) {
-                    set_fatal(MG_ERR_DEVICE, "result copy failed");
-                    return;
-                }
+            if (!slot_h[s] || slot_first[s] > k || !(flags[s] & BF_DONE)) continue;
+            if (!complete(s)) {
+                set_fatal(MG_ERR_DEVICE, "result copy failed");
+                return;
             }
-            const auto now = Clock::now();
-            res.stats.seconds = secs(r.t_submit, now);
-            res.stats.queue_seconds = secs(r.t_submit, r.t_admit);
-            eng.clear_slot(s);
-            release_hierarchy(h);
-            slot_h[s] = nullptr;
-            --live;
-            std::lock_guard<std::mutex> g(mu);
-            pending.erase(r.ticket);
-            done.emplace(r.ticket, std::move(res));
-            done_order.push_back(r.ticket);
-            ++completed;
-            cv_done.notify_all();
-        }
-        if (eng.upload() != MG_OK) {
-            set_fatal(MG_ERR_DEVICE, mg_last_error());
-            return;
         }
     }
 }
@@ -285,6 +304,7 @@ mg_status mg_server_create(mg_context* ctx, int slots, size_t budget, int max_le
     }
     s->slot_req.resize(slots);
     s->slot_h.assign(slots, nullptr);
+    s->slot_first.assign(slots, 0);
     s->worker = std::thread([s] { s->run(); });
     *out = s;
     return MG_OK;
