@@ -110,19 +110,20 @@ struct RowRsrc {
     }
 };
 
-// Bands and b of one node at byte offset off; zeros when !need.
+// Byte offset past every buffer: a load from it returns zero.
+constexpr uint32_t OFF_NONE = 0x80000000u;
+
+// Bands and b of one node at byte offset off; zeros when !need.  The loads
+// are issued on every lane (an unneeded lane reads past the buffer), so no
+// branch separates a load from its later use and the compiler's wait
+// counting stays exact across the loop.
 template <typename T>
 __device__ __forceinline__ void load_row(const RowRsrc<T>& R, uint32_t off, bool need,
                                          T (&bk)[9], T& bb) {
-    if (need) {
+    const uint32_t o = need ? off : OFF_NONE;
 #pragma unroll
-        for (int k = 0; k < 9; ++k) bk[k] = bload<T, AUX_NT>(R.band[k], off);
-        bb = bload<T>(R.b, off);
-    } else {
-#pragma unroll
-        for (int k = 0; k < 9; ++k) bk[k] = T(0);
-        bb = T(0);
-    }
+    for (int k = 0; k < 9; ++k) bk[k] = bload<T, AUX_NT>(R.band[k], o);
+    bb = bload<T>(R.b, o);
 }
 
 __device__ __forceinline__ uint32_t node_off(int j, int N, int col, int size) {
@@ -164,7 +165,8 @@ __device__ void pre_tile(const T* __restrict__ bands, int64_t bs, int N, const T
     const int jstart = r0 - F_HALO - ((((r0 - F_HALO) % 6) + 6) % 6);  // multiple of 6
     const int jend = r1 + 4;
     auto xload = [&](int j) -> T {
-        return (!XZERO && cval) ? bload<T>(Rx, node_off(j, N, col, sizeof(T))) : T(0);
+        if (XZERO) return T(0);
+        return bload<T>(Rx, cval ? node_off(j, N, col, sizeof(T)) : OFF_NONE);
     };
     auto need1 = [&](int j) { return c_op1 && in_range(j, r0 - 3, r1 + 3); };
     pfx[0] = xload(jstart);
@@ -239,18 +241,6 @@ __device__ void pre_tile(const T* __restrict__ bands, int64_t bs, int N, const T
     }
 }
 
-// Interpolated coarse correction (P x_c) at fine node (i, j): the value
-// prolong_elem adds.
-template <typename T>
-__device__ __forceinline__ T prolong_value(int Nf, const T* __restrict__ xc, int i, int j) {
-    const int Nc = (Nf >> 1) + 1;
-    const T* c = xc + (int64_t)(j >> 1) * Nc + (i >> 1);
-    if (!(i & 1) && !(j & 1)) return c[0];
-    if (!(j & 1)) return T(0.5) * (c[0] + c[1]);
-    if (!(i & 1)) return T(0.5) * (c[0] + c[Nc]);
-    return T(0.25) * ((c[0] + c[1]) + (c[Nc] + c[Nc + 1]));
-}
-
 // Grid rows per residual partial of a fused post pass; chunk heights are
 // multiples of it, so no group of rows straddles two tiles.
 constexpr int F_NORM_ROWS = 4;
@@ -300,18 +290,45 @@ __device__ void post_tile(const T* __restrict__ bands, int64_t bs, int N, const 
         for (int s = 0; s < 3; ++s) X[s][g] = A[s][g] = B[s][g] = T(0);
     }
     T bk[6][9], bb[6];
-    T pfx[3];
+    // x and the four coarse values around each x row in flight (slot r mod 3)
+    T pfx[3], pc0[3], pc1[3], pc2[3], pc3[3];
     double nacc = 0.0;  // this lane's part of the current row group
     const int ng = (N + F_NORM_ROWS - 1) / F_NORM_ROWS;
     const int jstart = r0 - F_HALO - ((((r0 - F_HALO) % 6) + 6) % 6);
     const int jend = r1 + 3;
-    auto xrow = [&](int j) -> T {
-        if (!c_x || !in_range(j, r0 - H, r1 + H) || !in_range(j, 0, N)) return T(0);
-        return bload<T>(Rx, node_off(j, N, col, sizeof(T))) + prolong_value(N, xc, col, j);
+    // x row j plus its coarse correction P x_c (the arithmetic of
+    // prolong_elem): the x value and the four coarse values around the node
+    // are loaded two steps ahead and combined when the row enters
+    const int Nc = (N >> 1) + 1;
+    const rsrc_t Rc = make_rsrc(xc, (int64_t)Nc * Nc * (int64_t)sizeof(T));
+    auto x_use = [&](int j) { return c_x && in_range(j, r0 - H, r1 + H) && in_range(j, 0, N); };
+    auto xrow_load = [&](int j, T& xv, T& c0, T& c1, T& c2, T& c3) {
+        const bool use = x_use(j);
+        const uint32_t ox = use ? node_off(j, N, col, sizeof(T)) : OFF_NONE;
+        const uint32_t oc =
+            use ? (uint32_t)((j >> 1) * Nc + (col >> 1)) * (uint32_t)sizeof(T) : OFF_NONE;
+        xv = bload<T>(Rx, ox);
+        c0 = bload<T>(Rc, oc);
+        c1 = bload<T>(Rc, oc + (uint32_t)sizeof(T));
+        c2 = bload<T>(Rc, oc + (uint32_t)(Nc * sizeof(T)));
+        c3 = bload<T>(Rc, oc + (uint32_t)((Nc + 1) * sizeof(T)));
+    };
+    auto xrow_value = [&](int j, T xv, T c0, T c1, T c2, T c3) -> T {
+        if (!x_use(j)) return T(0);
+        T v;
+        if (!(col & 1) && !(j & 1))
+            v = c0;
+        else if (!(j & 1))
+            v = T(0.5) * (c0 + c1);
+        else if (!(col & 1))
+            v = T(0.5) * (c0 + c2);
+        else
+            v = T(0.25) * ((c0 + c1) + (c2 + c3));
+        return xv + v;
     };
     auto need1 = [&](int j) { return c_op1 && in_range(j, r0 - (H - 1), r1 + (H - 1)); };
-    pfx[0] = xrow(jstart);
-    pfx[1] = xrow(jstart + 1);
+    xrow_load(jstart, pfx[0], pc0[0], pc1[0], pc2[0], pc3[0]);
+    xrow_load(jstart + 1, pfx[1], pc0[1], pc1[1], pc2[1], pc3[1]);
     load_row(R, node_off(jstart - 1, N, col, sizeof(T)), need1(jstart - 1), bk[5], bb[5]);
     load_row(R, node_off(jstart, N, col, sizeof(T)), need1(jstart), bk[0], bb[0]);
 #pragma unroll 1
@@ -323,8 +340,11 @@ __device__ void post_tile(const T* __restrict__ bands, int64_t bs, int N, const 
             const int j1 = jx - 1, j2 = jx - 2, j3 = jx - 3;
             const int b1 = (ph + 5) % 6, b2 = (ph + 4) % 6, b3 = (ph + 3) % 6;
             const int l1 = (x3 + 2) % 3, l2 = (x3 + 1) % 3;
-            X[x3][t] = pfx[x3];
-            pfx[(x3 + 2) % 3] = xrow(jx + 2);
+            X[x3][t] = xrow_value(jx, pfx[x3], pc0[x3], pc1[x3], pc2[x3], pc3[x3]);
+            {
+                const int x5 = (x3 + 2) % 3;
+                xrow_load(jx + 2, pfx[x5], pc0[x5], pc1[x5], pc2[x5], pc3[x5]);
+            }
             load_row(R, node_off(jx + 1, N, col, sizeof(T)), need1(jx + 1), bk[(ph + 1) % 6],
                      bb[(ph + 1) % 6]);
             __syncthreads();
