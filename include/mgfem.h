@@ -162,7 +162,13 @@ mg_status mg_solve(mg_hierarchy* h, const double* dev_b, double* dev_x,
  * (defaults, mixed) or an array of count entries; precision must be
  * MG_PREC_MIXED and nu_pre/nu_post must agree.  b[p], x[p]: device vectors
  * of that problem's finest n; x is in/out.  stats: NULL or count entries.
- * Synchronous.  Returns the first non-OK per-problem status, if any. */
+ * Synchronous.  Returns the first non-OK per-problem status, if any.
+ * The batch machinery (device descriptors of the problems, work lists and
+ * the captured iteration graph; a few MB of device memory outside any
+ * context budget) is kept after the call and reused by later calls with the
+ * same device, largest level, coarse level and smoothing counts; at most
+ * four idle sets are kept, until the process ends.  Concurrent calls use
+ * separate sets; one hierarchy must not be in two concurrent calls. */
 mg_status mg_solve_batch(mg_hierarchy* const* hs, const double* const* b, double* const* x,
                          int count, const mg_solve_opts* opts, void* stream, mg_stats* stats);
 
@@ -186,7 +192,7 @@ typedef struct {
     size_t queue_high_water;
     size_t bytes;             /* hierarchies held (live + idle pool) */
     size_t bytes_high_water;
-    double busy_seconds;      /* time spent in device iterations */
+    double busy_seconds;      /* time with at least one iteration on the device */
 } mg_server_info_t;
 
 mg_status mg_server_create(mg_context* ctx, int slots, size_t hbm_budget_bytes, int max_level,
