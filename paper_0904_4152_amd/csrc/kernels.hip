@@ -297,14 +297,16 @@ __device__ __forceinline__ void level_xy(const double* __restrict__ xyf, int Nf,
 }
 
 // All levels Lc..L of a hierarchy in one launch.  A workgroup assembles a
-// tile of AT x AT nodes of one level: it first computes the stiffness
-// matrices of the (AT+1)^2 elements touching the tile into LDS, then each
-// thread sums the entries of its node's nine bands over the four elements
-// around the node in lexicographic order and applies the Dirichlet
-// treatment.  Writes FP64 bands and their round-to-nearest FP32 copies.
-// Level l owns the workgroups [first[l], first[l + 1]).
-constexpr int AT = 16;
-static_assert(AT * AT == BLOCK, "one thread per tile node");
+// tile of ATX x ATY nodes of one level: it first computes the stiffness
+// matrices of the (ATX+1) x (ATY+1) elements touching the tile into LDS (one
+// element per thread), then each of the first ATX*ATY threads sums the
+// entries of its node's nine bands over the four elements around the node
+// in lexicographic order and applies the Dirichlet treatment.  Writes FP64
+// bands and their round-to-nearest FP32 copies; a tile row is 63
+// consecutive nodes, so the band writes are long contiguous runs.  Level l
+// owns the workgroups [first[l], first[l + 1]).
+constexpr int ATX = 63, ATY = 3;
+static_assert((ATX + 1) * (ATY + 1) == BLOCK, "one thread per element of a tile");
 
 struct AssembleLevels {
     double* b64[MG_MAX_LEVEL + 1];
@@ -316,31 +318,34 @@ struct AssembleLevels {
 
 __global__ __launch_bounds__(BLOCK) void k_assemble(const double* __restrict__ xyf,
                                                     AssembleLevels a) {
-    __shared__ double Ke[(AT + 1) * (AT + 1)][16];
+    __shared__ double Ke[(ATX + 1) * (ATY + 1)][16];
     const int64_t blk = blockIdx.x;
     int l = a.Lc;
     while (l < a.L && blk >= a.first[l + 1]) ++l;
     const int N = (1 << l) + 1, Nf = (1 << a.L) + 1, s = 1 << (a.L - l);
-    const int tiles_x = (N + AT - 1) / AT;
+    const int tiles_x = (N + ATX - 1) / ATX;
     const int64_t local = blk - a.first[l];
-    const int i0 = (int)(local % tiles_x) * AT, j0 = (int)(local / tiles_x) * AT;
-    for (int e = threadIdx.x; e < (AT + 1) * (AT + 1); e += BLOCK) {
-        const int ei = i0 - 1 + e % (AT + 1), ej = j0 - 1 + e / (AT + 1);
-        if (ei < 0 || ej < 0 || ei >= N - 1 || ej >= N - 1) continue;
-        double cx[4], cy[4];
-        level_xy(xyf, Nf, s, ei, ej, &cx[0], &cy[0]);
-        level_xy(xyf, Nf, s, ei + 1, ej, &cx[1], &cy[1]);
-        level_xy(xyf, Nf, s, ei + 1, ej + 1, &cx[2], &cy[2]);
-        level_xy(xyf, Nf, s, ei, ej + 1, &cx[3], &cy[3]);
-        Quad q;
-        q.set(cx, cy);
-        double K[4][4];
-        element_matrix(q, K);
+    const int i0 = (int)(local % tiles_x) * ATX, j0 = (int)(local / tiles_x) * ATY;
+    {
+        const int e = threadIdx.x;
+        const int ei = i0 - 1 + e % (ATX + 1), ej = j0 - 1 + e / (ATX + 1);
+        if (ei >= 0 && ej >= 0 && ei < N - 1 && ej < N - 1) {
+            double cx[4], cy[4];
+            level_xy(xyf, Nf, s, ei, ej, &cx[0], &cy[0]);
+            level_xy(xyf, Nf, s, ei + 1, ej, &cx[1], &cy[1]);
+            level_xy(xyf, Nf, s, ei + 1, ej + 1, &cx[2], &cy[2]);
+            level_xy(xyf, Nf, s, ei, ej + 1, &cx[3], &cy[3]);
+            Quad q;
+            q.set(cx, cy);
+            double K[4][4];
+            element_matrix(q, K);
 #pragma unroll
-        for (int r = 0; r < 16; ++r) Ke[e][r] = K[r / 4][r % 4];
+            for (int r = 0; r < 16; ++r) Ke[e][r] = K[r / 4][r % 4];
+        }
     }
     __syncthreads();
-    const int i = i0 + (int)threadIdx.x % AT, j = j0 + (int)threadIdx.x / AT;
+    if ((int)threadIdx.x >= ATX * ATY) return;
+    const int i = i0 + (int)threadIdx.x % ATX, j = j0 + (int)threadIdx.x / ATX;
     if (i >= N || j >= N) return;
     const int64_t p = (int64_t)j * N + i;
     double band[9];
@@ -356,7 +361,7 @@ __global__ __launch_bounds__(BLOCK) void k_assemble(const double* __restrict__ x
         for (int e = 0; e < 4; ++e) {
             const int ex = e & 1, ey = e >> 1;
             const int ei = i - 1 + ex, ej = j - 1 + ey;
-            const double* K = Ke[(ej - j0 + 1) * (AT + 1) + (ei - i0 + 1)];
+            const double* K = Ke[(ej - j0 + 1) * (ATX + 1) + (ei - i0 + 1)];
             const int c_node = corner_of[e];
             // corner c sits at (ei + ox[c], ej + oy[c]); this node at (i, j)
             const int ox[4] = {0, 1, 1, 0}, oy[4] = {0, 0, 1, 1};
@@ -502,12 +507,12 @@ hipError_t launch_assemble(const double* xy_fine, const Level* lv, int Lc, int L
     a.L = L;
     int64_t nb = 0;
     for (int l = Lc; l <= L; ++l) {
-        const int64_t N = (int64_t(1) << l) + 1, t = (N + AT - 1) / AT;
+        const int64_t N = (int64_t(1) << l) + 1;
         a.b64[l] = lv[l].bands64;
         a.b32[l] = lv[l].bands32;
         a.bs[l] = lv[l].bs;
         a.first[l] = nb;
-        nb += t * t;
+        nb += ((N + ATX - 1) / ATX) * ((N + ATY - 1) / ATY);
     }
     a.first[L + 1] = nb;
     hipLaunchKernelGGL(k_assemble, dim3((unsigned)nb), dim3(BLOCK), 0, st, xy_fine, a);

@@ -76,6 +76,32 @@ def test_batch_alone_equals_in_the_mix(mg, ctx):
         assert st[0].status == 0
 
 
+def test_batch_composition_changes_tiling_not_bits(mg, ctx):
+    # The fused passes pick each level's chunk height from how many problems
+    # share the level, and the batch machinery is reused between calls; a
+    # problem's result must not change with either.  Problem 0 (L = 9) is
+    # solved among 40, among 10 and alone (chunk heights 32, 8 and 4 rows at
+    # L = 9), in calls of shrinking size, and by the single-problem solver.
+    crowd = make_problems(mg, ctx, [9] * 40, seed0=3000)
+    opts = mg.default_opts(precision=mg.MG_PREC_MIXED, rel_tol=1e-8)
+    h0, b0 = crowd[0][0], crowd[0][1]
+    results = []
+    for group in (crowd, crowd[:10], crowd[:1]):
+        xs = [torch.zeros_like(p[1]) for p in group]
+        st = mg.solve_batch([p[0] for p in group], [p[1] for p in group], xs, opts)
+        assert all(s.status == 0 and s.rel_res <= 1e-8 for s in st)
+        results.append((host(xs[0]), st[0].cycles, st[0].rel_res))
+    for x, cyc, rel in results[1:]:
+        np.testing.assert_array_equal(x, results[0][0])
+        assert (cyc, rel) == results[0][1:]
+    x1 = torch.zeros_like(b0)
+    s1 = h0.solve(b0, x1, opts)
+    np.testing.assert_array_equal(host(x1), results[0][0])
+    assert s1.cycles == results[0][1]
+    for h, _, _, _ in crowd:
+        h.close()
+
+
 def test_batch_per_problem_tolerances_checked_by_oracle(mg, ctx, orc):
     levels = [6, 7, 5, 8]
     tols = [1e-6, 1e-8, 1e-10, 1e-8]
