@@ -255,8 +255,9 @@ __device__ __constant__ double kSY[4] = {-1.0, -1.0, 1.0, 1.0};
 // Element stiffness matrix (2x2 Gauss):
 //   K[a][b] = sum_q (G_a G_b + H_a H_b) / det J_q
 // with G = det J * d(phi)/dx and H = det J * d(phi)/dy expressed through
-// the cofactors of J.  Each entry with b >= a is computed once and mirrored,
-// so K is symmetric bit for bit.
+// the cofactors of J (one reciprocal of det J per quadrature point).  Each
+// entry with b >= a is computed once and mirrored, so K is symmetric bit
+// for bit.
 __device__ void element_matrix(const Quad& q, double (&K)[4][4]) {
     const double g = 0.57735026918962576451;  // 1/sqrt(3)
 #pragma unroll
@@ -270,6 +271,7 @@ __device__ void element_matrix(const Quad& q, double (&K)[4][4]) {
         const double xx = q.ax[1] + q.ax[3] * eta, xe = q.ax[2] + q.ax[3] * xi;
         const double yx = q.ay[1] + q.ay[3] * eta, ye = q.ay[2] + q.ay[3] * xi;
         const double det = xx * ye - xe * yx;
+        const double inv = 1.0 / det;
         double G[4], H[4];
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
@@ -281,7 +283,7 @@ __device__ void element_matrix(const Quad& q, double (&K)[4][4]) {
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
-            for (int b = a; b < 4; ++b) K[a][b] += (G[a] * G[b] + H[a] * H[b]) / det;
+            for (int b = a; b < 4; ++b) K[a][b] += (G[a] * G[b] + H[a] * H[b]) * inv;
     }
 #pragma unroll
     for (int a = 1; a < 4; ++a)
