@@ -65,7 +65,13 @@ __device__ __forceinline__ void wl_item(const int* wl, int t, int* p, int* tile)
 
 __device__ __forceinline__ float* role32(const BLevel& lv, int r) { return r ? lv.t32 : lv.x32; }
 
+// Work items of list wl for the problems whose flags meet `mask`.  The
+// whole launch returns at once when no problem has any of those flags:
+// state[cap] holds the union of every live problem's flags, written by the
+// control kernel after each phase (and set to all bits when new problems
+// are uploaded).
 #define FOR_ITEMS(wl)                                              \
+    if (!(state[wl[1]].flags & mask)) return;                      \
     const int total_ = wl_total(wl);                               \
     for (int t_ = blockIdx.x; t_ < total_; t_ += gridDim.x) {      \
         int p, tile;                                               \
@@ -393,7 +399,7 @@ __global__ __launch_bounds__(BLOCK) void kb_ctrl(const BProb* __restrict__ probs
                                                  BState* __restrict__ state, int cap, int phase,
                                                  int* __restrict__ iter,
                                                  int* __restrict__ ring) {
-    int live = 0, sure = 0;
+    int live = 0, sure = 0, present = 0;
     int* entry = nullptr;
     if (phase == PH_INNER) entry = ring + (int64_t)(*iter % ITER_RING) * (2 + cap);
     for (int p = threadIdx.x; p < cap; p += BLOCK) {
@@ -448,7 +454,21 @@ __global__ __launch_bounds__(BLOCK) void kb_ctrl(const BProb* __restrict__ probs
         }
         if (!(S.flags & BF_DONE)) ++live;
         if (S.flags == BF_INNER) ++sure;
+        present |= S.flags;
         if (entry) entry[2 + p] = S.flags;
+    }
+    {
+        __shared__ int wor[BLOCK / 64];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) present |= __shfl_xor(present, o, 64);
+        if ((threadIdx.x & 63) == 0) wor[threadIdx.x >> 6] = present;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int v = 0;
+#pragma unroll
+            for (int w = 0; w < BLOCK / 64; ++w) v |= wor[w];
+            state[cap].flags = v;
+        }
     }
     if (phase == PH_INNER) {
         __threadfence_system();
@@ -509,12 +529,12 @@ mg_status BatchEngine::init(int device, int capacity, int Lmax, int Lc, int nu_p
         MG_HIP(hipHostMalloc((void**)&h_probs_stage_[b], sizeof(BProb) * cap_,
                              hipHostMallocDefault));
         MG_HIP(hipHostMalloc((void**)&h_wl_stage_[b], sizeof(int) * wl_ints, hipHostMallocDefault));
-        MG_HIP(hipHostMalloc((void**)&h_start_stage_[b], sizeof(BState) * cap_,
+        MG_HIP(hipHostMalloc((void**)&h_start_stage_[b], sizeof(BState) * (cap_ + 1),
                              hipHostMallocDefault));
     }
     MG_HIP(hipHostMalloc((void**)&h_fetch_, sizeof(BState), hipHostMallocDefault));
     MG_HIP(hipMalloc(&d_probs_, sizeof(BProb) * cap_));
-    MG_HIP(hipMalloc(&d_state_, sizeof(BState) * cap_));
+    MG_HIP(hipMalloc(&d_state_, sizeof(BState) * (cap_ + 1)));  // + flags union
     MG_HIP(hipMalloc(&d_wl_, sizeof(int) * NLISTS * (3 + 2 * cap_)));
     MG_HIP(hipMalloc(&d_iter_, 64));
     MG_HIP(hipMemset(d_iter_, 0, 64));
@@ -529,6 +549,11 @@ mg_status BatchEngine::init(int device, int capacity, int Lmax, int Lc, int nu_p
     std::memset(h_state_, 0, sizeof(BState) * cap_);
     for (int s = 0; s < cap_; ++s) h_state_[s].flags = BF_DONE;
     MG_HIP(hipMemcpy(d_state_, h_state_, sizeof(BState) * cap_, hipMemcpyHostToDevice));
+    {
+        BState all{};
+        all.flags = -1;
+        MG_HIP(hipMemcpy(d_state_ + cap_, &all, sizeof(BState), hipMemcpyHostToDevice));
+    }
     probs_dirty_ = true;
     return MG_OK;
 }
@@ -666,6 +691,7 @@ mg_status BatchEngine::upload_async() {
                               hipMemcpyHostToDevice, st_));
         probs_dirty_ = false;
     }
+    bool any_started = false;
     for (int s = 0; s < cap_; ++s) {
         if (!started_[s]) continue;
         BState& S = h_start_stage_[b][s];
@@ -673,6 +699,14 @@ mg_status BatchEngine::upload_async() {
         S.flags = BF_INIT;
         MG_HIP(hipMemcpyAsync(d_state_ + s, &S, sizeof(BState), hipMemcpyHostToDevice, st_));
         started_[s] = 0;
+        any_started = true;
+    }
+    if (any_started) {
+        // the union of flags now includes BF_INIT: mark every flag present
+        BState& A = h_start_stage_[b][cap_];
+        std::memset(&A, 0, sizeof(BState));
+        A.flags = -1;
+        MG_HIP(hipMemcpyAsync(d_state_ + cap_, &A, sizeof(BState), hipMemcpyHostToDevice, st_));
     }
     MG_HIP(hipEventRecord(ev_upload_[b], st_));
     return MG_OK;
