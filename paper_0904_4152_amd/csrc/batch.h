@@ -106,6 +106,10 @@ public:
     mg_status run(int64_t iter_cap, int64_t* iterations);
     // Copy the device states to the host mirror; returns it.
     mg_status read_states();
+    // One launch copying the callers' b and x of slots 0..count-1 into the
+    // problems' finest vectors (out = false; after upload), or the
+    // solutions back into x (out = true: x = 0 for a zero right-hand side).
+    mg_status io(const double* const* b, double* const* x, int count, bool out);
     const BState& state(int s) const { return h_state_[s]; }
     int capacity() const { return cap_; }
     bool live(int s) const { return hp_[s].L > 0; }
@@ -136,6 +140,8 @@ private:
     int* h_wl_stage_[2] = {};        // work lists
     BState* h_start_stage_[2] = {};  // and started states
     BState* h_fetch_ = nullptr;      // pinned, one state
+    double** d_io_ = nullptr;        // callers' b and x of every slot
+    double** h_io_ = nullptr;        // pinned staging of d_io_
     std::vector<BProb> hp_;
     std::vector<int> h_wl_;
     std::vector<char> started_;

@@ -358,6 +358,37 @@ __global__ __launch_bounds__(BLOCK) void kb_update(const BProb* __restrict__ pro
     END_ITEMS
 }
 
+// Copies between the callers' vectors and every listed problem's finest
+// vectors, one launch for the whole batch: out == 0: b64 <- b_p, x64 <- x_p;
+// out != 0: x_p <- x64 (zero for a zero right-hand side).  io[p] and
+// io[cap + p] hold problem p's caller b and x.
+__global__ __launch_bounds__(BLOCK) void kb_io(const BProb* __restrict__ probs,
+                                               const BState* __restrict__ state,
+                                               const int* __restrict__ wl,
+                                               double* const* __restrict__ io, int out) {
+    const int total = wl_total(wl), cap = wl[1];
+    for (int t = blockIdx.x; t < total; t += gridDim.x) {
+        int p, tile;
+        wl_item(wl, t, &p, &tile);
+        const BLevel& lv = probs[p].lv[probs[p].L];
+        const double* bu = io[p];
+        double* xu = io[cap + p];
+        const bool zero = state[p].bn == 0.0 && state[p].status == MG_OK;
+        const int64_t base = (int64_t)tile * TILE;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int64_t q = base + (int64_t)e * BLOCK + threadIdx.x;
+            if (q >= lv.n) continue;
+            if (!out) {
+                lv.b64[q] = bu[q];
+                lv.x64[q] = xu[q];
+            } else {
+                xu[q] = zero ? 0.0 : lv.x64[q];
+            }
+        }
+    }
+}
+
 // Norm of one problem from its partials (fixed order), into a state field.
 __global__ __launch_bounds__(BLOCK) void kb_finalize(const BProb* __restrict__ probs,
                                                      BState* __restrict__ state,
@@ -499,6 +530,8 @@ BatchEngine::~BatchEngine() {
         if (e) (void)hipEventDestroy(e);
     if (ev_setup_) (void)hipEventDestroy(ev_setup_);
     if (d_iter_) (void)hipFree(d_iter_);
+    if (d_io_) (void)hipFree(d_io_);
+    if (h_io_) (void)hipHostFree(h_io_);
     if (h_state_) (void)hipHostFree(h_state_);
     if (h_ring_) (void)hipHostFree(h_ring_);
     for (int b = 0; b < 2; ++b) {
@@ -533,6 +566,8 @@ mg_status BatchEngine::init(int device, int capacity, int Lmax, int Lc, int nu_p
                              hipHostMallocDefault));
     }
     MG_HIP(hipHostMalloc((void**)&h_fetch_, sizeof(BState), hipHostMallocDefault));
+    MG_HIP(hipMalloc(&d_io_, sizeof(double*) * 2 * cap_));
+    MG_HIP(hipHostMalloc((void**)&h_io_, sizeof(double*) * 2 * cap_, hipHostMallocDefault));
     MG_HIP(hipMalloc(&d_probs_, sizeof(BProb) * cap_));
     MG_HIP(hipMalloc(&d_state_, sizeof(BState) * (cap_ + 1)));  // + flags union
     MG_HIP(hipMalloc(&d_wl_, sizeof(int) * NLISTS * (3 + 2 * cap_)));
@@ -910,6 +945,25 @@ mg_status BatchEngine::run(int64_t iter_cap, int64_t* iterations) {
     return MG_OK;
 }
 
+mg_status BatchEngine::io(const double* const* b, double* const* x, int count, bool out) {
+    MG_HIP(hipSetDevice(device_));
+    if (!out) {
+        // previous copies from the staging area have completed: read_states
+        // synchronised the stream after the last call
+        for (int p = 0; p < cap_; ++p) {
+            h_io_[p] = p < count ? const_cast<double*>(b[p]) : nullptr;
+            h_io_[cap_ + p] = p < count ? x[p] : nullptr;
+        }
+        MG_HIP(hipMemcpyAsync(d_io_, h_io_, sizeof(double*) * 2 * cap_, hipMemcpyHostToDevice,
+                              st_));
+    }
+    const int stride = 3 + 2 * cap_;
+    hipLaunchKernelGGL(kb_io, dim3(STAGE_GRID), dim3(BLOCK), 0, st_, d_probs_, d_state_,
+                       (const int*)(d_wl_ + (size_t)WL_FINEST * stride), d_io_, (int)out);
+    MG_HIP(hipGetLastError());
+    return MG_OK;
+}
+
 mg_status BatchEngine::read_states() {
     MG_HIP(hipSetDevice(device_));
     MG_HIP(hipMemcpyAsync(h_state_, d_state_, sizeof(BState) * cap_, hipMemcpyDeviceToHost, st_));
@@ -1076,9 +1130,6 @@ extern "C" mg_status mg_solve_batch(mg_hierarchy* const* hs, const double* const
     int64_t iter_cap = 8;
     for (int p = 0; p < count; ++p) {
         mg_hierarchy* h = hs[p];
-        const Level& F = h->lv[h->L];
-        MG_HIP(launch_copy<double>(b[p], F.b64, F.n, eng.stream()));
-        MG_HIP(launch_copy<double>(x[p], F.x64, F.n, eng.stream()));
         const mg_solve_opts& o = opts ? opts[p] : def;
         eng.set_slot(p, h, o);
         eng.start_slot(p);
@@ -1086,17 +1137,14 @@ extern "C" mg_status mg_solve_batch(mg_hierarchy* const* hs, const double* const
         iter_cap = std::max<int64_t>(iter_cap, (int64_t)(outer + 1) * (o.inner_max_cycles + 1) + 4);
     }
     if (mg_status s = eng.upload()) return s;
+    if (mg_status s = eng.io(b, x, count, false)) return s;
     if (mg_status s = eng.run(iter_cap, nullptr)) return s;
+    if (mg_status s = eng.io(b, x, count, true)) return s;
     if (mg_status s = eng.read_states()) return s;
     mg_status worst = MG_OK;
     for (int p = 0; p < count; ++p) {
         mg_hierarchy* h = hs[p];
-        const Level& F = h->lv[h->L];
         const BState& S = eng.state(p);
-        if (S.bn == 0.0 && S.status == MG_OK)
-            MG_HIP(launch_fill<double>(x[p], F.n, 0.0, eng.stream()));
-        else
-            MG_HIP(launch_copy<double>(F.x64, x[p], F.n, eng.stream()));
         if (stats) fill_stats(S, h->L, h->Lc, o0.nu_pre, o0.nu_post, &stats[p]);
         if (!(S.flags & BF_DONE)) {
             if (stats) stats[p].status = MG_ERR_NOCONV;
