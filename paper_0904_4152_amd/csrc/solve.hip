@@ -238,11 +238,34 @@ static hipError_t run_unit(mg_hierarchy* h, int kind, const mg_solve_opts& o, bo
     return enqueue_unit(h, kind, o.nu_pre, o.nu_post, o.omega, x_zero, q);
 }
 
-// The norm a reduction enqueued on st left in the pinned mirror (every
-// reduction the drivers read back writes it there directly: no copy).
+// Host read-back of reduced norms.  Every reduction the drivers read writes
+// its result straight into the hierarchy's pinned mirror (no copy).  Before
+// the producing work is enqueued the host arms the slot with a value no
+// norm takes; it then spins on the mirror, which returns as soon as the
+// final reduction kernel has stored the norm, without the wake-up latency
+// of a blocking stream synchronisation.  After 50 ms of spinning it falls
+// back to synchronising the stream (which also reports device errors).
+constexpr double kArmed = -1.0;
+
+static void arm_scalar(mg_hierarchy* h, int slot) {
+    ((volatile double*)h->host_scal)[slot + 1] = kArmed;
+}
+
 static hipError_t read_scalar(mg_hierarchy* h, int slot, hipStream_t st, double* out) {
+    const volatile double* v = (const volatile double*)h->host_scal + slot + 1;
+    const auto t0 = std::chrono::steady_clock::now();
+    for (unsigned i = 1;; ++i) {
+        const double x = *v;
+        if (!(x == kArmed)) {
+            *out = x;
+            return hipSuccess;
+        }
+        if ((i & 4095u) == 0 &&
+            std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(50))
+            break;
+    }
     MG_TRY(hipStreamSynchronize(st));
-    *out = ((const volatile double*)h->host_scal)[slot + 1];
+    *out = *v;
     return hipSuccess;
 }
 
@@ -331,6 +354,7 @@ extern "C" mg_status mg_solve(mg_hierarchy* h, const double* dev_b, double* dev_
     const bool graphs = o.use_graph != 0;
     MG_HIPS(launch_copy<double>(dev_b, F.b64, n, q.st));
     MG_HIPS(launch_copy<double>(dev_x, F.x64, n, q.st));
+    arm_scalar(h, SC_B);
     MG_HIPS(launch_norm<double>(F.b64, n, h->partials, h->scal, SC_B, h->host_scal, q.st));
     q.bytes += 8.0 * 5 * n;
     double bn = 0.0;
@@ -343,6 +367,7 @@ extern "C" mg_status mg_solve(mg_hierarchy* h, const double* dev_b, double* dev_
         MG_HIPS(launch_fill<double>(F.x64, n, 0.0, q.st));
     } else if (o.precision == MG_PREC_FP64) {
         double r = 0.0;
+        arm_scalar(h, SC_R64);
         MG_HIPS(launch_defect<double>(F, F.bands64, F.b64, F.x64, nullptr, h->partials, h->scal,
                                       SC_R64, h->host_scal, q.st));
         q.bytes += 11.0 * 8 * n;
@@ -358,6 +383,7 @@ extern "C" mg_status mg_solve(mg_hierarchy* h, const double* dev_b, double* dev_
                     break;
                 }
             }
+            arm_scalar(h, SC_R64);
             MG_HIPS(run_unit(h, 0, o, false, graphs, q));
             MG_HIPS(read_scalar(h, SC_R64, q.st, &r));
             st.cycles = k;
@@ -371,6 +397,7 @@ extern "C" mg_status mg_solve(mg_hierarchy* h, const double* dev_b, double* dev_
     } else {
         for (int k = 1;; ++k) {
             double s = 0.0;
+            arm_scalar(h, SC_R64);
             MG_HIPS(launch_defect<double>(F, F.bands64, F.b64, F.x64, h->d64, h->partials,
                                           h->scal, SC_R64, h->host_scal, q.st));
             q.bytes += 12.0 * 8 * n;
@@ -391,15 +418,18 @@ extern "C" mg_status mg_solve(mg_hierarchy* h, const double* dev_b, double* dev_
                 }
             }
             if (s == 0.0) break;
+            arm_scalar(h, SC_D32);
             MG_HIPS(launch_cast_scaled(h->d64, F.b32, n, h->scal, SC_R64, q.st));
             MG_HIPS(launch_norm<float>(F.b32, n, h->partials, h->scal, SC_D32, h->host_scal,
                                        q.st));
             q.bytes += 16.0 * n;
+            // ||d32|| is first needed after the first inner cycle: read it then
             double dn = 0.0;
-            MG_HIPS(read_scalar(h, SC_D32, q.st, &dn));
             for (int it = 1; it <= o.inner_max_cycles; ++it) {
                 double r32 = 0.0;
+                arm_scalar(h, SC_R32);
                 MG_HIPS(run_unit(h, 1, o, it == 1, graphs, q));
+                if (it == 1) MG_HIPS(read_scalar(h, SC_D32, q.st, &dn));
                 MG_HIPS(read_scalar(h, SC_R32, q.st, &r32));
                 st.cycles++;
                 if (!std::isfinite(r32)) break;
