@@ -74,6 +74,14 @@ def lib():
         L.or_prolong_add_f32.argtypes = [ctypes.c_int, _fp, _fp]
         L.or_hier_create.argtypes = [ctypes.c_int, ctypes.c_int, _dp]
         L.or_hier_create.restype = ctypes.c_void_p
+        L.or_hier_create_bc.argtypes = [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int]
+        L.or_hier_create_bc.restype = ctypes.c_void_p
+        L.or_assemble_bc.argtypes = [ctypes.c_int, _dp, ctypes.c_int, _dp]
+        L.or_load_vector_bc.argtypes = [ctypes.c_int, _dp, ctypes.c_int, ctypes.c_int, _dp]
+        L.or_l2_error.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_int]
+        L.or_l2_error.restype = ctypes.c_double
+        L.or_restrict_bc.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_int]
+        L.or_restrict_f32_bc.argtypes = [ctypes.c_int, _fp, _fp, ctypes.c_int]
         L.or_hier_destroy.argtypes = [ctypes.c_void_p]
         L.or_hier_N.argtypes = [ctypes.c_void_p, ctypes.c_int]
         L.or_hier_bands.argtypes = [ctypes.c_void_p, ctypes.c_int]
@@ -112,23 +120,39 @@ def element_stiffness(xq, yq) -> np.ndarray:
     return K.reshape(4, 4)
 
 
-def assemble(N: int, xy: np.ndarray, dirichlet: bool = True) -> np.ndarray:
+ALL_DIRICHLET = 15  # Dirichlet side bits: 1 x = 0, 2 x = 1, 4 y = 0, 8 y = 1
+
+
+def assemble(N: int, xy: np.ndarray, dirichlet: bool = True, dmask: int | None = None):
+    """Bands of the stiffness matrix; Dirichlet treatment on the sides in
+    ``dmask`` (default: every side if ``dirichlet``, none otherwise)."""
     xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1)
     bands = np.zeros(9 * N * N)
-    lib().or_assemble(N, _d(xy), int(dirichlet), _d(bands))
+    if dmask is None:
+        dmask = ALL_DIRICHLET if dirichlet else 0
+    lib().or_assemble_bc(N, _d(xy), int(dmask), _d(bands))
     return bands.reshape(9, N * N)
 
 
-def load_vector(N: int, xy: np.ndarray, fn: int = 0, dirichlet: bool = True) -> np.ndarray:
+def load_vector(N: int, xy: np.ndarray, fn: int = 0, dirichlet: bool = True,
+                dmask: int | None = None) -> np.ndarray:
     xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1)
     b = np.zeros(N * N)
-    lib().or_load_vector(N, _d(xy), fn, int(dirichlet), _d(b))
+    if dmask is None:
+        dmask = ALL_DIRICHLET if dirichlet else 0
+    lib().or_load_vector_bc(N, _d(xy), fn, int(dmask), _d(b))
     return b
 
 
 def l2_error_sinsin(N: int, xy: np.ndarray, u: np.ndarray) -> float:
     xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1)
     return lib().or_l2_error_sinsin(N, _d(xy), _d(np.ascontiguousarray(u)))
+
+
+def l2_error(N: int, xy: np.ndarray, u: np.ndarray, fn: int) -> float:
+    """L2 error against the exact solution of manufactured load ``fn``."""
+    xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1)
+    return lib().or_l2_error(N, _d(xy), _d(np.ascontiguousarray(u)), fn)
 
 
 def spmv(N, bands, x):
@@ -149,10 +173,12 @@ def jacobi(N, bands, b, x, omega=0.7):
     return y
 
 
-def restrict(Nf, d_f, filter=True):
+def restrict(Nf, d_f, filter=True, dmask: int | None = None):
     Nc = (Nf - 1) // 2 + 1
     bc = np.zeros(Nc * Nc)
-    lib().or_restrict(Nf, _d(d_f), _d(bc), int(filter))
+    if dmask is None:
+        dmask = ALL_DIRICHLET if filter else 0
+    lib().or_restrict_bc(Nf, _d(d_f), _d(bc), int(dmask))
     return bc
 
 
@@ -186,10 +212,10 @@ def jacobi_f32(N, bands32, b32, x32, omega=0.7):
     return y
 
 
-def restrict_f32(Nf, d_f32):
+def restrict_f32(Nf, d_f32, dmask: int = ALL_DIRICHLET):
     Nc = (Nf - 1) // 2 + 1
     bc = np.zeros(Nc * Nc, dtype=np.float32)
-    lib().or_restrict_f32(Nf, _f(d_f32), _f(bc))
+    lib().or_restrict_f32_bc(Nf, _f(d_f32), _f(bc), int(dmask))
     return bc
 
 
@@ -202,12 +228,13 @@ def prolong_add_f32(Nf, x_c32, x_f32):
 class Hierarchy:
     """Oracle multigrid hierarchy on the finest coordinates ``xy`` (2*n)."""
 
-    def __init__(self, L: int, xy: np.ndarray, Lc: int = 1):
-        self.L, self.Lc = L, Lc
+    def __init__(self, L: int, xy: np.ndarray, Lc: int = 1, dmask: int = ALL_DIRICHLET):
+        self.L, self.Lc, self.dmask = L, Lc, dmask
         self._xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1)
-        self._h = lib().or_hier_create(L, Lc, _d(self._xy))
+        self._h = lib().or_hier_create_bc(L, Lc, _d(self._xy), int(dmask))
         if not self._h:
-            raise ValueError("oracle hierarchy creation failed (L=%d, Lc=%d)" % (L, Lc))
+            raise ValueError("oracle hierarchy creation failed (L=%d, Lc=%d, dmask=%d)"
+                             % (L, Lc, dmask))
 
     def close(self):
         if self._h:

@@ -22,6 +22,16 @@ static int is_boundary(int N, int i, int j) {
     return i == 0 || j == 0 || i == N - 1 || j == N - 1;
 }
 
+/* Node (i,j) lies on a Dirichlet side: bit 1 x = 0 (i = 0), bit 2 x = 1
+ * (i = N-1), bit 4 y = 0 (j = 0), bit 8 y = 1 (j = N-1).  The rest of the
+ * boundary carries the natural homogeneous Neumann condition (Sec. 2.1:
+ * Dirichlet and Neumann parts of the boundary): its rows are the assembled
+ * ones. */
+static int is_dirichlet(int N, int i, int j, int dmask) {
+    return (i == 0 && (dmask & 1)) || (i == N - 1 && (dmask & 2)) || (j == 0 && (dmask & 4)) ||
+           (j == N - 1 && (dmask & 8));
+}
+
 /* Reference square [-1,1]^2, corners counter-clockwise. */
 static const double XI_A[4] = {-1.0, 1.0, 1.0, -1.0};
 static const double ETA_A[4] = {-1.0, -1.0, 1.0, 1.0};
@@ -117,6 +127,10 @@ static void element_nodes(int N, const double* xy, int i, int j, int* nodes, dou
  * even on a simple grid).  Elements are visited lexicographically, j outer,
  * so A[p][q] and A[q][p] receive the same terms in the same order. */
 void or_assemble(int N, const double* xy, int dirichlet, double* bands) {
+    or_assemble_bc(N, xy, dirichlet ? OR_ALL_DIRICHLET : 0, bands);
+}
+
+void or_assemble_bc(int N, const double* xy, int dmask, double* bands) {
     size_t n = (size_t)N * N;
     memset(bands, 0, 9 * n * sizeof(double));
     for (int j = 0; j < N - 1; ++j) {
@@ -136,17 +150,17 @@ void or_assemble(int N, const double* xy, int dirichlet, double* bands) {
             }
         }
     }
-    if (!dirichlet) return;
+    if (!dmask) return;
     for (int j = 0; j < N; ++j) {
         for (int i = 0; i < N; ++i) {
             size_t p = (size_t)j * N + i;
-            if (is_boundary(N, i, j)) {
+            if (is_dirichlet(N, i, j, dmask)) {
                 for (int k = 0; k < 9; ++k) bands[(size_t)k * n + p] = 0.0;
                 bands[4 * n + p] = 1.0;
             } else {
                 for (int k = 0; k < 9; ++k) {
                     if (k == 4) continue;
-                    if (is_boundary(N, i + band_di(k), j + band_dj(k)))
+                    if (is_dirichlet(N, i + band_di(k), j + band_dj(k), dmask))
                         bands[(size_t)k * n + p] = 0.0;
                 }
             }
@@ -156,10 +170,23 @@ void or_assemble(int N, const double* xy, int dirichlet, double* bands) {
 
 static double rhs_f(int fn, double x, double y) {
     if (fn == 1) return 1.0;
+    if (fn == 2) return 2.0 * OR_PI * OR_PI * cos(OR_PI * x) * sin(OR_PI * y);
+    if (fn == 3) return 0.5 * OR_PI * OR_PI * sin(0.5 * OR_PI * x) * sin(0.5 * OR_PI * y);
     return 2.0 * OR_PI * OR_PI * sin(OR_PI * x) * sin(OR_PI * y);
 }
 
+/* The exact solutions of the manufactured problems: -Laplace(u) = rhs_f. */
+static double exact_u(int fn, double x, double y) {
+    if (fn == 2) return cos(OR_PI * x) * sin(OR_PI * y);
+    if (fn == 3) return sin(0.5 * OR_PI * x) * sin(0.5 * OR_PI * y);
+    return sin(OR_PI * x) * sin(OR_PI * y);
+}
+
 void or_load_vector(int N, const double* xy, int fn, int dirichlet, double* b) {
+    or_load_vector_bc(N, xy, fn, dirichlet ? OR_ALL_DIRICHLET : 0, b);
+}
+
+void or_load_vector_bc(int N, const double* xy, int fn, int dmask, double* b) {
     size_t n = (size_t)N * N;
     double pts[5], wts[5];
     gauss_rule(3, pts, wts);
@@ -179,14 +206,18 @@ void or_load_vector(int N, const double* xy, int fn, int dirichlet, double* b) {
             }
         }
     }
-    if (!dirichlet) return;
     for (int j = 0; j < N; ++j)
         for (int i = 0; i < N; ++i)
-            if (is_boundary(N, i, j)) b[(size_t)j * N + i] = 0.0;
+            if (is_dirichlet(N, i, j, dmask)) b[(size_t)j * N + i] = 0.0;
 }
 
 /* Integral L2 norm of u - u_h (Sec. 6.2.1), u = sin(pi x) sin(pi y). */
 double or_l2_error_sinsin(int N, const double* xy, const double* u) {
+    return or_l2_error(N, xy, u, 0);
+}
+
+/* The same for the exact solution of manufactured problem fn. */
+double or_l2_error(int N, const double* xy, const double* u, int fn) {
     double pts[5], wts[5], sum = 0.0;
     gauss_rule(5, pts, wts);
     for (int j = 0; j < N - 1; ++j) {
@@ -200,7 +231,7 @@ double or_l2_error_sinsin(int N, const double* xy, const double* u) {
                     map_point(xq, yq, pts[qi], pts[qj], &px, &py, &det, NULL, NULL);
                     double uh = 0.0;
                     for (int a = 0; a < 4; ++a) uh += u[nodes[a]] * phi_ref(a, pts[qi], pts[qj]);
-                    double e = sin(OR_PI * px) * sin(OR_PI * py) - uh;
+                    double e = exact_u(fn, px, py) - uh;
                     sum += wts[qi] * wts[qj] * det * e * e;
                 }
             }
@@ -253,6 +284,11 @@ static double w1d(int f, int c) {
 /* b_c[I,J] = sum_{fine (f,g)} P[(f,g),(I,J)] d_f[f,g]  (P^T), terms outside
  * the fine grid absent; then the coarse boundary is zeroed. */
 void or_restrict(int Nf, const double* d_f, double* b_c, int filter) {
+    or_restrict_bc(Nf, d_f, b_c, filter ? OR_ALL_DIRICHLET : 0);
+}
+
+/* The same with the coarse Dirichlet nodes of the sides in dmask zeroed. */
+void or_restrict_bc(int Nf, const double* d_f, double* b_c, int dmask) {
     int Nc = (Nf - 1) / 2 + 1;
     for (int J = 0; J < Nc; ++J) {
         for (int I = 0; I < Nc; ++I) {
@@ -263,7 +299,7 @@ void or_restrict(int Nf, const double* d_f, double* b_c, int filter) {
                     s += w1d(f, I) * w1d(g, J) * d_f[(size_t)g * Nf + f];
                 }
             }
-            if (filter && is_boundary(Nc, I, J)) s = 0.0;
+            if (is_dirichlet(Nc, I, J, dmask)) s = 0.0;
             b_c[(size_t)J * Nc + I] = s;
         }
     }
@@ -348,14 +384,20 @@ void or_jacobi_f32(int N, const float* bands, const float* b, const float* x, fl
 }
 
 void or_restrict_f32(int Nf, const float* d_f, float* b_c) {
+    or_restrict_f32_bc(Nf, d_f, b_c, OR_ALL_DIRICHLET);
+}
+
+void or_restrict_f32_bc(int Nf, const float* d_f, float* b_c, int dmask) {
     int Nc = (Nf - 1) / 2 + 1;
     for (int J = 0; J < Nc; ++J) {
         for (int I = 0; I < Nc; ++I) {
             float s = 0.0f;
-            if (!is_boundary(Nc, I, J)) {
+            if (!is_dirichlet(Nc, I, J, dmask)) {
                 for (int g = 2 * J - 1; g <= 2 * J + 1; ++g)
-                    for (int f = 2 * I - 1; f <= 2 * I + 1; ++f)
+                    for (int f = 2 * I - 1; f <= 2 * I + 1; ++f) {
+                        if (f < 0 || g < 0 || f >= Nf || g >= Nf) continue;
                         s += (float)(w1d(f, I) * w1d(g, J)) * d_f[(size_t)g * Nf + f];
+                    }
             }
             b_c[(size_t)J * Nc + I] = s;
         }
@@ -388,16 +430,24 @@ struct or_hier {
     float* bands32[OR_MAXL + 1];
     double *x[OR_MAXL + 1], *b[OR_MAXL + 1], *t[OR_MAXL + 1];
     float *x32[OR_MAXL + 1], *b32[OR_MAXL + 1], *t32[OR_MAXL + 1];
-    int m;          /* interior unknowns at Lc */
-    double* chol;   /* m x m lower Cholesky factor of the interior block */
+    int dmask;      /* Dirichlet sides */
+    int m;          /* unknowns at Lc: the nodes not on a Dirichlet side */
+    int* cnode;     /* m node indices of the unknowns, in index order */
+    double* chol;   /* m x m lower Cholesky factor of their block */
     double* cwork;  /* m */
 };
 
 or_hier* or_hier_create(int L, int Lc, const double* xy_fine) {
-    if (L < 1 || L > OR_MAXL || Lc < 1 || Lc > L) return NULL;
+    return or_hier_create_bc(L, Lc, xy_fine, OR_ALL_DIRICHLET);
+}
+
+or_hier* or_hier_create_bc(int L, int Lc, const double* xy_fine, int dmask) {
+    if (L < 1 || L > OR_MAXL || Lc < 1 || Lc > L || dmask <= 0 || dmask > OR_ALL_DIRICHLET)
+        return NULL;
     or_hier* h = (or_hier*)calloc(1, sizeof(or_hier));
     h->L = L;
     h->Lc = Lc;
+    h->dmask = dmask;
     int Nf = (1 << L) + 1;
     for (int l = Lc; l <= L; ++l) {
         int N = (1 << l) + 1, s = 1 << (L - l);
@@ -411,7 +461,7 @@ or_hier* or_hier_create(int L, int Lc, const double* xy_fine) {
                 h->xy[l][2 * ((size_t)j * N + i) + 1] = xy_fine[2 * pf + 1];
             }
         h->bands[l] = (double*)malloc(9 * n * sizeof(double));
-        or_assemble(N, h->xy[l], 1, h->bands[l]);
+        or_assemble_bc(N, h->xy[l], dmask, h->bands[l]);
         h->bands32[l] = (float*)malloc(9 * n * sizeof(float));
         for (size_t q = 0; q < 9 * n; ++q) h->bands32[l][q] = (float)h->bands[l][q];
         h->x[l] = (double*)calloc(n, sizeof(double));
@@ -424,21 +474,32 @@ or_hier* or_hier_create(int L, int Lc, const double* xy_fine) {
     /* Coarse-grid direct solver (replaces the paper's unpreconditioned CG
      * of Sec. 6.2 by an exact dense factorisation of the interior block). */
     int Nc = h->N[Lc];
-    int mi = Nc - 2;
-    h->m = mi * mi;
+    size_t nc = (size_t)Nc * Nc;
+    int* col = (int*)malloc(nc * sizeof(int));  /* node -> unknown, or -1 */
+    h->cnode = (int*)malloc(nc * sizeof(int));
+    h->m = 0;
+    for (int j = 0; j < Nc; ++j)
+        for (int i = 0; i < Nc; ++i) {
+            size_t p = (size_t)j * Nc + i;
+            col[p] = -1;
+            if (!is_dirichlet(Nc, i, j, dmask)) {
+                col[p] = h->m;
+                h->cnode[h->m++] = (int)p;
+            }
+        }
     h->chol = (double*)calloc((size_t)h->m * h->m, sizeof(double));
     h->cwork = (double*)calloc((size_t)h->m, sizeof(double));
-    size_t nc = (size_t)Nc * Nc;
     for (int r = 0; r < h->m; ++r) {
-        int i = 1 + r % mi, j = 1 + r / mi;
-        size_t p = (size_t)j * Nc + i;
+        int p = h->cnode[r], i = p % Nc, j = p / Nc;
         for (int k = 0; k < 9; ++k) {
             int ii = i + band_di(k), jj = j + band_dj(k);
-            if (is_boundary(Nc, ii, jj)) continue;
-            int c = (jj - 1) * mi + (ii - 1);
+            if (ii < 0 || jj < 0 || ii >= Nc || jj >= Nc) continue;
+            int c = col[jj * Nc + ii];
+            if (c < 0) continue;
             h->chol[(size_t)r * h->m + c] = h->bands[Lc][(size_t)k * nc + p];
         }
     }
+    free(col);
     if (or_cholesky(h->m, h->chol) != 0) {
         or_hier_destroy(h);
         return NULL;
@@ -455,6 +516,7 @@ void or_hier_destroy(or_hier* h) {
     }
     free(h->chol);
     free(h->cwork);
+    free(h->cnode);
     free(h);
 }
 
@@ -462,22 +524,16 @@ int or_hier_N(const or_hier* h, int l) { return h->N[l]; }
 const double* or_hier_bands(const or_hier* h, int l) { return h->bands[l]; }
 const double* or_hier_coords(const or_hier* h, int l) { return h->xy[l]; }
 
-/* Direct solve at the coarsest level: interior by Cholesky, boundary rows
- * are identity rows. */
+/* Direct solve at the coarsest level: the unknowns by Cholesky, Dirichlet
+ * rows are identity rows. */
 static void coarse_solve(or_hier* h, double* x, const double* b) {
-    int Nc = h->N[h->Lc], mi = Nc - 2;
+    int Nc = h->N[h->Lc];
     for (int j = 0; j < Nc; ++j)
         for (int i = 0; i < Nc; ++i)
-            if (is_boundary(Nc, i, j)) x[(size_t)j * Nc + i] = b[(size_t)j * Nc + i];
-    for (int r = 0; r < h->m; ++r) {
-        int i = 1 + r % mi, j = 1 + r / mi;
-        h->cwork[r] = b[(size_t)j * Nc + i];
-    }
+            if (is_dirichlet(Nc, i, j, h->dmask)) x[(size_t)j * Nc + i] = b[(size_t)j * Nc + i];
+    for (int r = 0; r < h->m; ++r) h->cwork[r] = b[h->cnode[r]];
     or_cholesky_solve(h->m, h->chol, h->cwork);
-    for (int r = 0; r < h->m; ++r) {
-        int i = 1 + r % mi, j = 1 + r / mi;
-        x[(size_t)j * Nc + i] = h->cwork[r];
-    }
+    for (int r = 0; r < h->m; ++r) x[h->cnode[r]] = h->cwork[r];
 }
 
 /* V(nu_pre, nu_post) cycle (Sec. 6.2): smooth, restrict the defect, recurse
@@ -495,7 +551,7 @@ int or_vcycle(or_hier* h, int l, double* x, const double* b, const or_opts* o) {
         memcpy(x, t, n * sizeof(double));
     }
     or_defect(N, h->bands[l], b, x, t);
-    or_restrict(N, t, h->b[l - 1], 1);
+    or_restrict_bc(N, t, h->b[l - 1], h->dmask);
     size_t nc = (size_t)h->N[l - 1] * h->N[l - 1];
     memset(h->x[l - 1], 0, nc * sizeof(double));
     or_vcycle(h, l - 1, h->x[l - 1], h->b[l - 1], o);
@@ -568,7 +624,7 @@ static void vcycle32(or_hier* h, int l, float* x, const float* b, const or_opts*
     }
     or_spmv_f32(N, h->bands32[l], x, t);
     for (size_t p = 0; p < n; ++p) t[p] = b[p] - t[p];
-    or_restrict_f32(N, t, h->b32[l - 1]);
+    or_restrict_f32_bc(N, t, h->b32[l - 1], h->dmask);
     size_t nc = (size_t)h->N[l - 1] * h->N[l - 1];
     memset(h->x32[l - 1], 0, nc * sizeof(float));
     vcycle32(h, l - 1, h->x32[l - 1], h->b32[l - 1], o);

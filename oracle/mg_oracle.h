@@ -17,8 +17,11 @@
  *   N = 2^L + 1 nodes per side, n = N*N, node (i,j) has index p = j*N + i.
  *   Band k (k = 0..8) stores A[p, p + off_k] at index p, with
  *   off_k = (k/3 - 1)*N + (k%3 - 1); band-major storage bands[k*n + p].
- *   Homogeneous Dirichlet on the whole boundary: boundary rows and columns
- *   are zeroed and the diagonal set to 1.
+ *   Homogeneous Dirichlet on the sides in a mask dmask (bit 1: x = 0,
+ *   bit 2: x = 1, bit 4: y = 0, bit 8: y = 1; 15 = the whole boundary, the
+ *   default): their rows and columns are zeroed and the diagonal set to 1.
+ *   The other sides carry the natural homogeneous Neumann condition (their
+ *   rows are the assembled ones).
  *   Coarse levels are rediscretised on the fine coordinates sampled every
  *   2^(L-l) nodes; restriction is the transpose of bilinear index-space
  *   prolongation followed by zeroing the coarse boundary.
@@ -39,13 +42,23 @@ void or_element_stiffness(const double* xq, const double* yq, double* K);
  * coordinates xy (2*n, interleaved).  dirichlet != 0 applies the boundary
  * treatment described above.  bands: 9*n doubles. */
 void or_assemble(int N, const double* xy, int dirichlet, double* bands);
+/* The same with Dirichlet treatment on the sides in dmask only. */
+#define OR_ALL_DIRICHLET 15
+void or_assemble_bc(int N, const double* xy, int dmask, double* bands);
 
 /* Load vector b_p = sum_e int_e f phi_p (3x3 Gauss).  fn 0: f = 2 pi^2
  * sin(pi x) sin(pi y); fn 1: f = 1.  dirichlet != 0 zeroes boundary nodes. */
 void or_load_vector(int N, const double* xy, int fn, int dirichlet, double* b);
+/* fn 2: f = 2 pi^2 cos(pi x) sin(pi y) (solution cos(pi x) sin(pi y), Neumann
+ * on x = 0, 1); fn 3: f = pi^2/2 sin(pi x/2) sin(pi y/2) (solution
+ * sin(pi x/2) sin(pi y/2), Neumann on x = 1 and y = 1).  Zero on the
+ * Dirichlet sides in dmask. */
+void or_load_vector_bc(int N, const double* xy, int fn, int dmask, double* b);
 
 /* L2 error ||u - u_h|| against u = sin(pi x) sin(pi y), 5x5 Gauss. */
 double or_l2_error_sinsin(int N, const double* xy, const double* u);
+/* The same against the exact solution of load fn (0, 2 or 3 above). */
+double or_l2_error(int N, const double* xy, const double* u, int fn);
 
 /* Band operations (FP64). */
 void or_spmv(int N, const double* bands, const double* x, double* y);
@@ -54,6 +67,8 @@ void or_jacobi(int N, const double* bands, const double* b, const double* x,
                double* x_out, double omega);
 /* Restriction: b_c = P^T d_f, then (filter != 0) zero on the coarse boundary. */
 void or_restrict(int Nf, const double* d_f, double* b_c, int filter);
+/* The same, zeroing the coarse nodes on the Dirichlet sides in dmask. */
+void or_restrict_bc(int Nf, const double* d_f, double* b_c, int dmask);
 /* Prolongation with correction: x_f += P x_c. */
 void or_prolong_add(int Nf, const double* x_c, double* x_f);
 double or_norm2(size_t n, const double* v);
@@ -68,6 +83,7 @@ void or_spmv_f32(int N, const float* bands, const float* x, float* y);
 void or_jacobi_f32(int N, const float* bands, const float* b, const float* x,
                    float* x_out, float omega);
 void or_restrict_f32(int Nf, const float* d_f, float* b_c);
+void or_restrict_f32_bc(int Nf, const float* d_f, float* b_c, int dmask);
 void or_prolong_add_f32(int Nf, const float* x_c, float* x_f);
 
 /* ---- hierarchy and solvers ---- */
@@ -94,6 +110,9 @@ typedef struct {
 } or_stats;
 
 or_hier* or_hier_create(int L, int Lc, const double* xy_fine);
+/* The same with Dirichlet sides dmask (1..15; at least one side, else the
+ * operator is singular). */
+or_hier* or_hier_create_bc(int L, int Lc, const double* xy_fine, int dmask);
 void or_hier_destroy(or_hier* h);
 int or_hier_N(const or_hier* h, int l);
 const double* or_hier_bands(const or_hier* h, int l);
