@@ -17,8 +17,12 @@
  *   - band k = 0..8 holds A[p][p + off_k] at index p, off_k =
  *     (k/3 - 1)*N + (k%3 - 1), i.e. offsets -N-1, -N, -N+1, -1, 0, 1, N-1,
  *     N, N+1;
- *   - homogeneous Dirichlet conditions on the whole boundary: boundary rows
- *     and columns are zero except a unit diagonal;
+ *   - homogeneous boundary conditions, Dirichlet on a chosen set of sides
+ *     (every side unless the hierarchy was made by mg_hierarchy_create_bc)
+ *     and the natural (free) Neumann condition on the others (Sec. 2.1:
+ *     mixed Dirichlet and Neumann conditions): rows and columns of
+ *     Dirichlet nodes are zero except a unit diagonal, and their right-hand
+ *     side entries must be zero;
  *   - every vector argument named dev_* or documented as "device" is a
  *     contiguous, unpadded device buffer of n elements in index order p,
  *     owned by the caller; the library never keeps such a pointer after the
@@ -58,6 +62,12 @@ typedef struct mg_server mg_server;
 
 #define MG_MAX_LEVEL 14
 #define MG_MAX_COARSE_LEVEL 3
+/* Side bits of dirichlet_sides: x = 0, x = 1, y = 0, y = 1. */
+#define MG_SIDE_X0 1
+#define MG_SIDE_X1 2
+#define MG_SIDE_Y0 4
+#define MG_SIDE_Y1 8
+#define MG_ALL_DIRICHLET 15
 #define MG_HIST 128
 
 /* Solver options (Sec. 6.2: V cycle, two damped Jacobi pre- and
@@ -116,11 +126,24 @@ mg_status mg_context_memory(const mg_context* ctx, size_t* in_use, size_t* high_
  * allocating anything when the hierarchy does not fit the budget. */
 mg_status mg_hierarchy_create(mg_context* ctx, int L, int coarse_level, double jitter,
                               uint64_t geom_seed, const double* host_xy, mg_hierarchy** out);
+/* The same with Dirichlet conditions only on the sides set in
+ * dirichlet_sides (MG_SIDE_* bits, 1..15; Sec. 2.1 mixed conditions, Sec.
+ * 6.2.2 free Neumann and geometric Dirichlet sides) and the natural Neumann
+ * condition on the rest.  A node on a Dirichlet side is a Dirichlet node,
+ * corners included.  Every level and the coarse solve use the same sides;
+ * the coarse solve factorises the block of the coarsest level's nodes off
+ * the Dirichlet sides.  MG_ERR_INVALID for 0 (the pure Neumann problem is
+ * singular) or a value above 15.  mg_hierarchy_create(...) is
+ * mg_hierarchy_create_bc(..., MG_ALL_DIRICHLET, out). */
+mg_status mg_hierarchy_create_bc(mg_context* ctx, int L, int coarse_level, double jitter,
+                                 uint64_t geom_seed, const double* host_xy, int dirichlet_sides,
+                                 mg_hierarchy** out);
 /* Device bytes mg_hierarchy_create would charge for (L, coarse_level). */
 size_t mg_hierarchy_bytes(int L, int coarse_level);
 /* Assemble all levels (Sec. 2.1: the matrix is assembled fully): 2x2 Gauss
  * element matrices on the isoparametric bilinear map, Dirichlet treatment,
- * FP32 copy, and the Cholesky factor of the coarsest interior block.
+ * FP32 copy, and the Cholesky factor of the coarsest level's block of
+ * non-Dirichlet nodes.
  * Synchronous.  MG_ERR_NUMERIC if the coarse block is not positive definite
  * (a tangled grid). */
 mg_status mg_hierarchy_assemble(mg_hierarchy* h, void* stream);
@@ -135,8 +158,10 @@ mg_status mg_get_coords(const mg_hierarchy* h, int level, double* host_out);
 /* Right-hand sides on the finest level (asynchronous on stream):
  * mg_rhs_sinsin: load vector of f = 2 pi^2 sin(pi x) sin(pi y) (3x3 Gauss),
  * whose exact solution is u = sin(pi x) sin(pi y) (Sec. 6.2.1 accuracy test
- * with an analytically known solution); mg_rhs_uniform: b_p = 2u - 1 with u
- * the SplitMix64 draw p of seed, at interior nodes.  Boundary entries 0. */
+ * with an analytically known solution), boundary entries 0; only for a
+ * hierarchy with every side Dirichlet (MG_ERR_INVALID otherwise);
+ * mg_rhs_uniform: b_p = 2u - 1 with u the SplitMix64 draw p of seed, at
+ * nodes off the Dirichlet sides, 0 on them. */
 mg_status mg_rhs_sinsin(const mg_hierarchy* h, double* dev_b, void* stream);
 mg_status mg_rhs_uniform(const mg_hierarchy* h, uint64_t seed, double* dev_b, void* stream);
 

@@ -14,6 +14,9 @@ MG_OK, MG_ERR_INVALID, MG_ERR_NOMEM, MG_ERR_NOCONV, MG_ERR_NUMERIC, MG_ERR_DEVIC
 MG_PREC_FP64, MG_PREC_MIXED = 0, 1
 MG_F64, MG_F32 = 0, 1
 MG_HIST = 128
+# Side bits of dirichlet_sides: x = 0, x = 1, y = 0, y = 1.
+SIDE_X0, SIDE_X1, SIDE_Y0, SIDE_Y1 = 1, 2, 4, 8
+ALL_DIRICHLET = 15
 
 _vp = ctypes.c_void_p
 _i = ctypes.c_int
@@ -57,6 +60,7 @@ _SIGS = {
     "mg_context_destroy": (_i, [_vp]),
     "mg_context_memory": (_i, [_vp, ctypes.POINTER(_sz), ctypes.POINTER(_sz)]),
     "mg_hierarchy_create": (_i, [_vp, _i, _i, _d, _u64, _vp, ctypes.POINTER(_vp)]),
+    "mg_hierarchy_create_bc": (_i, [_vp, _i, _i, _d, _u64, _vp, _i, ctypes.POINTER(_vp)]),
     "mg_hierarchy_bytes": (_sz, [_i, _i]),
     "mg_hierarchy_assemble": (_i, [_vp, _vp]),
     "mg_hierarchy_destroy": (_i, [_vp]),
@@ -187,16 +191,18 @@ class Hierarchy:
     """Device hierarchy; methods call the C ABI with tensor pointers."""
 
     def __init__(self, ctx: Context, L: int, coarse_level: int = 1, jitter: float = 0.0,
-                 seed: int = 0, xy=None, assemble: bool = True):
+                 seed: int = 0, xy=None, assemble: bool = True,
+                 dirichlet_sides: int = ALL_DIRICHLET):
         h = _vp()
         xy_ptr = None
         if xy is not None:
             import numpy as np
             self._xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1)
             xy_ptr = self._xy.ctypes.data_as(_vp)
-        check(lib().mg_hierarchy_create(ctx.handle, L, coarse_level, jitter, seed, xy_ptr,
-                                        ctypes.byref(h)))
+        check(lib().mg_hierarchy_create_bc(ctx.handle, L, coarse_level, jitter, seed, xy_ptr,
+                                           dirichlet_sides, ctypes.byref(h)))
         self._h = h
+        self.dirichlet_sides = dirichlet_sides
         self.ctx = ctx
         self.L = L
         self.Lc = coarse_level

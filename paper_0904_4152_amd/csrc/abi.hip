@@ -55,8 +55,8 @@ static void hierarchy_arrays(int L, int Lc, std::vector<size_t>& sizes) {
     sizes.push_back(vec_len(nL) * sizeof(double));                    // d64
     sizes.push_back(partials_len(L) * sizeof(double));                  // partials
     sizes.push_back(64 * sizeof(double));                             // scal
-    const int mi = (1 << Lc) - 1;
-    sizes.push_back(std::max<size_t>(1, (size_t)mi * mi * mi * mi) * sizeof(double));  // chol
+    const size_t nc = ((size_t(1) << Lc) + 1) * ((size_t(1) << Lc) + 1);
+    sizes.push_back(nc * nc * sizeof(double));                         // chol (m <= nc)
     sizes.push_back(64);                                              // flag
 }
 
@@ -175,9 +175,17 @@ static void free_arrays(mg_hierarchy* h) {
 
 mg_status mg_hierarchy_create(mg_context* ctx, int L, int Lc, double jitter, uint64_t seed,
                               const double* host_xy, mg_hierarchy** out) {
+    return mg_hierarchy_create_bc(ctx, L, Lc, jitter, seed, host_xy, MG_ALL_DIRICHLET, out);
+}
+
+mg_status mg_hierarchy_create_bc(mg_context* ctx, int L, int Lc, double jitter, uint64_t seed,
+                                 const double* host_xy, int dirichlet_sides, mg_hierarchy** out) {
     if (!out) return fail(MG_ERR_INVALID, "null output pointer");
     *out = nullptr;
     if (!ctx) return fail(MG_ERR_INVALID, "null context");
+    if (dirichlet_sides < 1 || dirichlet_sides > MG_ALL_DIRICHLET)
+        return fail(MG_ERR_INVALID, "dirichlet_sides=" + std::to_string(dirichlet_sides) +
+                                        " outside [1, 15]: at least one side must be Dirichlet");
     if (L < 1 || L > MG_MAX_LEVEL)
         return fail(MG_ERR_INVALID, "level L=" + std::to_string(L) + " outside [1, 14]");
     if (Lc < 1 || Lc > std::min(L, MG_MAX_COARSE_LEVEL))
@@ -200,6 +208,7 @@ mg_status mg_hierarchy_create(mg_context* ctx, int L, int Lc, double jitter, uin
     h->ctx = ctx;
     h->L = L;
     h->Lc = Lc;
+    h->dmask = dirichlet_sides;
     h->charged = total;
     std::vector<void*> ptrs;
     for (size_t s : sizes) {
@@ -245,8 +254,12 @@ mg_status mg_hierarchy_create(mg_context* ctx, int L, int Lc, double jitter, uin
     h->scal = (double*)ptrs[a++];
     h->chol = (double*)ptrs[a++];
     h->flag = (int*)ptrs[a++];
-    const int mi = (1 << Lc) - 1;
-    h->m = mi * mi;
+    {
+        const int Nc = (1 << Lc) + 1;
+        h->m = 0;
+        for (int j = 0; j < Nc; ++j)
+            for (int i = 0; i < Nc; ++i) h->m += dev::is_dirichlet(Nc, i, j, h->dmask) ? 0 : 1;
+    }
     if (hipHostMalloc((void**)&h->host_scal, 64 * sizeof(double), hipHostMallocDefault) !=
         hipSuccess) {
         h->host_scal = nullptr;
@@ -276,8 +289,8 @@ mg_status mg_hierarchy_assemble(mg_hierarchy* h, void* stream) {
     if (!h) return fail(MG_ERR_INVALID, "null hierarchy");
     if (mg_status s = set_device(h)) return s;
     hipStream_t st = (hipStream_t)stream;
-    MG_HIP(launch_assemble(h->coords, h->lv, h->Lc, h->L, st));
-    MG_HIP(launch_chol_factor(h->lv[h->Lc], h->chol, h->flag, st));
+    MG_HIP(launch_assemble(h->coords, h->lv, h->Lc, h->L, h->dmask, st));
+    MG_HIP(launch_chol_factor(h->lv[h->Lc], h->dmask, h->chol, h->flag, st));
     int flag = 0;
     MG_HIP(hipMemcpyAsync(&flag, h->flag, sizeof(int), hipMemcpyDeviceToHost, st));
     MG_HIP(hipStreamSynchronize(st));
@@ -338,6 +351,8 @@ mg_status mg_get_coords(const mg_hierarchy* h, int level, double* host_out) {
 mg_status mg_rhs_sinsin(const mg_hierarchy* h, double* dev_b, void* stream) {
     if (!h) return fail(MG_ERR_INVALID, "null hierarchy");
     if (!dev_b) return fail(MG_ERR_INVALID, "null b");
+    if (h->dmask != MG_ALL_DIRICHLET)
+        return fail(MG_ERR_INVALID, "the sin-sin load vector needs Dirichlet conditions on every side");
     if (mg_status s = set_device(h)) return s;
     MG_HIP(launch_rhs_sinsin(h->coords, h->lv[h->L].N, dev_b, (hipStream_t)stream));
     return MG_OK;
@@ -347,7 +362,7 @@ mg_status mg_rhs_uniform(const mg_hierarchy* h, uint64_t seed, double* dev_b, vo
     if (!h) return fail(MG_ERR_INVALID, "null hierarchy");
     if (!dev_b) return fail(MG_ERR_INVALID, "null b");
     if (mg_status s = set_device(h)) return s;
-    MG_HIP(launch_rhs_uniform(h->lv[h->L].N, seed, dev_b, nullptr, (hipStream_t)stream));
+    MG_HIP(launch_rhs_uniform(h->lv[h->L].N, seed, h->dmask, dev_b, nullptr, (hipStream_t)stream));
     return MG_OK;
 }
 
@@ -447,10 +462,10 @@ mg_status mg_pre_smooth(const mg_hierarchy* h, int level, mg_dtype dtype, const 
     hipStream_t st = (hipStream_t)stream;
     if (dtype == MG_F64)
         MG_HIP(launch_pre<double>(lv, lv.bands64, (const double*)x, x_zero != 0, (const double*)b,
-                                  omega, (double*)x2, (double*)b_c, st));
+                                  omega, (double*)x2, (double*)b_c, h->dmask, st));
     else
         MG_HIP(launch_pre<float>(lv, lv.bands32, (const float*)x, x_zero != 0, (const float*)b,
-                                 (float)omega, (float*)x2, (float*)b_c, st));
+                                 (float)omega, (float*)x2, (float*)b_c, h->dmask, st));
     return MG_OK;
 }
 
@@ -491,9 +506,9 @@ mg_status mg_restrict(const mg_hierarchy* h, int fine_level, mg_dtype dtype, con
     const int Nf = h->lv[fine_level].N;
     hipStream_t st = (hipStream_t)stream;
     if (dtype == MG_F64)
-        MG_HIP(launch_restrict<double>(Nf, (const double*)d_f, (double*)b_c, st));
+        MG_HIP(launch_restrict<double>(Nf, (const double*)d_f, (double*)b_c, h->dmask, st));
     else
-        MG_HIP(launch_restrict<float>(Nf, (const float*)d_f, (float*)b_c, st));
+        MG_HIP(launch_restrict<float>(Nf, (const float*)d_f, (float*)b_c, h->dmask, st));
     return MG_OK;
 }
 
@@ -520,9 +535,10 @@ mg_status mg_coarse_solve(const mg_hierarchy* h, mg_dtype dtype, const void* b, 
     hipStream_t st = (hipStream_t)stream;
     const int Nc = h->lv[h->Lc].N;
     if (dtype == MG_F64)
-        MG_HIP(launch_coarse<double>(h->chol, h->m, Nc, (const double*)b, (double*)x, st));
+        MG_HIP(launch_coarse<double>(h->chol, h->m, Nc, (const double*)b, (double*)x, h->dmask,
+                                              st));
     else
-        MG_HIP(launch_coarse<float>(h->chol, h->m, Nc, (const float*)b, (float*)x, st));
+        MG_HIP(launch_coarse<float>(h->chol, h->m, Nc, (const float*)b, (float*)x, h->dmask, st));
     return MG_OK;
 }
 

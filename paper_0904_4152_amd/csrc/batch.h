@@ -41,7 +41,7 @@ struct BProb {
     int inner_max;
     int max_outer;
     int fixed;
-    int pad;
+    int dmask;  // Dirichlet sides
 };
 
 enum : int {

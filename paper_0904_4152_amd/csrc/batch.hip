@@ -156,7 +156,8 @@ __global__ __launch_bounds__(BLOCK) void kb_restrict(const BProb* __restrict__ p
     for (int e = 0; e < 4; ++e) {
         const int64_t q = base + (int64_t)e * BLOCK + threadIdx.x;
         if (q < c.n)
-            dev::restrict_elem<float>(f.N, role32(f, src), c.b32, (int)(q % c.N), (int)(q / c.N));
+            dev::restrict_elem<float>(f.N, role32(f, src), c.b32, (int)(q % c.N), (int)(q / c.N),
+                                      P.dmask);
     }
     END_ITEMS
 }
@@ -214,6 +215,7 @@ __global__ __launch_bounds__(dev::TAIL_THREADS) void kb_tail(const BProb* __rest
     tl.m = P.m;
     tl.top = top;
     tl.Lc = Lc;
+    tl.dmask = P.dmask;
     dev::tail_cycle<float>(tl, (float)P.omega);
     END_ITEMS
 }
@@ -228,7 +230,7 @@ __global__ __launch_bounds__(BLOCK) void kb_coarse(const BProb* __restrict__ pro
     if (!(flags & mask)) continue;
     if (only_level >= 0 && P.L != only_level) continue;
     const BLevel& lv = P.lv[Lc];
-    dev::coarse_block<float>(P.chol, P.m, lv.N, lv.b32, lv.x32);
+    dev::coarse_block<float>(P.chol, P.m, lv.N, lv.b32, lv.x32, P.dmask);
     END_ITEMS
 }
 
@@ -245,10 +247,10 @@ __global__ __launch_bounds__(BT) void kb_fpre(const BProb* __restrict__ probs,
     const float om = (float)P.omega;
     if (l < P.L || state[p].first)
         dev::pre_tile<float, true, BT>(lv.bands32, lv.bs, lv.N, lv.x32, lv.b32, om, lv.t32,
-                                       P.lv[l - 1].b32, strip, chunk, lv.rh, lv.cw);
+                                       P.lv[l - 1].b32, P.dmask, strip, chunk, lv.rh, lv.cw);
     else
         dev::pre_tile<float, false, BT>(lv.bands32, lv.bs, lv.N, lv.x32, lv.b32, om, lv.t32,
-                                        P.lv[l - 1].b32, strip, chunk, lv.rh, lv.cw);
+                                        P.lv[l - 1].b32, P.dmask, strip, chunk, lv.rh, lv.cw);
     END_ITEMS
 }
 
@@ -620,6 +622,7 @@ void BatchEngine::set_slot(int s, mg_hierarchy* h, const mg_solve_opts& o) {
     P.partials = h->partials;
     P.chol = h->chol;
     P.m = h->m;
+    P.dmask = h->dmask;
     P.L = h->L;
     P.omega = o.omega;
     P.rel_tol = o.rel_tol;

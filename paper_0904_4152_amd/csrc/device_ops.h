@@ -152,20 +152,34 @@ __device__ __forceinline__ void jacobi_zero_elem(const T* __restrict__ diag,
     xo[p] = omega * b[p] / diag[p];
 }
 
+// Dirichlet sides (bit 1: x = 0, bit 2: x = 1, bit 4: y = 0, bit 8: y = 1);
+// the other sides carry the natural homogeneous Neumann condition.
+constexpr int ALL_DIRICHLET = 15;
+
+// Evaluated without short-circuits, so callers get straight-line selects.
+__host__ __device__ __forceinline__ bool is_dirichlet(int N, int i, int j, int dmask) {
+    const unsigned side = (unsigned)(i == 0) | (unsigned)(i == N - 1) << 1 |
+                          (unsigned)(j == 0) << 2 | (unsigned)(j == N - 1) << 3;
+    return (side & (unsigned)dmask) != 0;
+}
+
 // b_c(I,J) = P^T d_f: weights 1 (centre), 1/2 (edges), 1/4 (corners) over the
-// 3x3 fine neighbourhood of (2I, 2J); zero on the coarse boundary.
+// 3x3 fine neighbourhood of (2I, 2J), terms outside the grid absent (zero);
+// zero at coarse Dirichlet nodes.
 template <typename T>
 __device__ __forceinline__ void restrict_elem(int Nf, const T* __restrict__ d,
-                                              T* __restrict__ bc, int I, int J) {
+                                              T* __restrict__ bc, int I, int J, int dmask) {
     const int Nc = (Nf >> 1) + 1;
     T s = T(0);
-    if (I > 0 && J > 0 && I < Nc - 1 && J < Nc - 1) {
-        const T* c = d + (int64_t)(2 * J) * Nf + 2 * I;
-        const T* u = c - Nf;
-        const T* o = c + Nf;
-        const T corner = (u[-1] + u[1]) + (o[-1] + o[1]);
-        const T edge = (u[0] + o[0]) + (c[-1] + c[1]);
-        s = c[0] + T(0.5) * edge + T(0.25) * corner;
+    if (!is_dirichlet(Nc, I, J, dmask)) {
+        const int i = 2 * I, j = 2 * J;
+        auto at = [&](int di, int dj) -> T {
+            const int ii = i + di, jj = j + dj;
+            return (ii >= 0 && ii < Nf && jj >= 0 && jj < Nf) ? d[(int64_t)jj * Nf + ii] : T(0);
+        };
+        const T corner = (at(-1, -1) + at(1, -1)) + (at(-1, 1) + at(1, 1));
+        const T edge = (at(0, -1) + at(0, 1)) + (at(-1, 0) + at(1, 0));
+        s = at(0, 0) + T(0.5) * edge + T(0.25) * corner;
     }
     bc[(int64_t)J * Nc + I] = s;
 }
@@ -189,22 +203,29 @@ __device__ __forceinline__ void prolong_elem(int Nf, const T* __restrict__ xc,
     xf[(int64_t)j * Nf + i] += v;
 }
 
-// Coarsest level, one block: boundary rows are identity rows; the interior
-// block is solved in FP64 with its Cholesky factor (at most 49 unknowns).
+// Unknowns of the coarsest level: the nodes off the Dirichlet sides, in
+// index order (at most 81: a 9 x 9 grid).
+constexpr int COARSE_MAX_UNKNOWNS = 81;
+
+// Coarsest level, one block: Dirichlet rows are identity rows; the other
+// nodes are solved in FP64 with the Cholesky factor of their block.
 template <typename T>
 __device__ __forceinline__ void coarse_block(const double* __restrict__ chol, int m, int Nc,
-                                             const T* __restrict__ b, T* __restrict__ x) {
-    __shared__ double z[64];
-    const int mi = Nc - 2;
+                                             const T* __restrict__ b, T* __restrict__ x,
+                                             int dmask) {
+    __shared__ double z[COARSE_MAX_UNKNOWNS];
+    __shared__ int node[COARSE_MAX_UNKNOWNS];
     __syncthreads();
     for (int p = threadIdx.x; p < Nc * Nc; p += blockDim.x) {
         const int i = p % Nc, j = p / Nc;
-        if (i == 0 || j == 0 || i == Nc - 1 || j == Nc - 1) x[p] = b[p];
+        if (is_dirichlet(Nc, i, j, dmask)) x[p] = b[p];
     }
     if (threadIdx.x == 0) {
+        int r = 0;
+        for (int p = 0; p < Nc * Nc; ++p)
+            if (!is_dirichlet(Nc, p % Nc, p / Nc, dmask)) node[r++] = p;
         for (int r = 0; r < m; ++r) {
-            const int i = 1 + r % mi, j = 1 + r / mi;
-            double s = (double)b[j * Nc + i];
+            double s = (double)b[node[r]];
             for (int k = 0; k < r; ++k) s -= chol[r * m + k] * z[k];
             z[r] = s / chol[r * m + r];
         }
@@ -213,10 +234,7 @@ __device__ __forceinline__ void coarse_block(const double* __restrict__ chol, in
             for (int k = r + 1; k < m; ++k) s -= chol[k * m + r] * z[k];
             z[r] = s / chol[r * m + r];
         }
-        for (int r = 0; r < m; ++r) {
-            const int i = 1 + r % mi, j = 1 + r / mi;
-            x[j * Nc + i] = (T)z[r];
-        }
+        for (int r = 0; r < m; ++r) x[node[r]] = (T)z[r];
     }
     __syncthreads();
 }

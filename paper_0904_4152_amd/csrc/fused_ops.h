@@ -132,14 +132,14 @@ __device__ __forceinline__ uint32_t node_off(int j, int N, int col, int size) {
 
 // Pre-smoothing tile (strip, chunk) on a level with N nodes per side:
 // x2 = J(J(x)) on owned nodes and bc = P^T (b - A x2) on the owned coarse
-// nodes (coarse boundary 0).  With XZERO the first sweep starts from a zero
+// nodes (0 at coarse nodes on the Dirichlet sides of dmask).  With XZERO the first sweep starts from a zero
 // iterate and x is not read.  Band rows live in a ring of six register slots
 // (row r in slot r mod 6; the loop is unrolled by six) so that the load of a
 // row lands in its slot two steps before its first use.
 template <typename T, bool XZERO, int BT>
 __device__ void pre_tile(const T* __restrict__ bands, int64_t bs, int N, const T* __restrict__ x,
                          const T* __restrict__ b, T omega, T* __restrict__ x2out,
-                         T* __restrict__ bc, int strip, int chunk, int rh, int cw) {
+                         T* __restrict__ bc, int dmask, int strip, int chunk, int rh, int cw) {
     __shared__ T X[3][BT + 2], A[3][BT + 2], B[3][BT + 2], D[3][BT + 2];
     const int t = threadIdx.x + 1;  // LDS column; 0 and BT+1 are guards
     const int c0 = strip * cw, c1 = min(c0 + cw, N);
@@ -227,7 +227,8 @@ __device__ void pre_tile(const T* __restrict__ bands, int64_t bs, int N, const T
             if (in_range(jr, r0, r1) && !(jr & 1) && c_own && !(col & 1)) {
                 const int I = col >> 1, J = jr >> 1;
                 T s = T(0);
-                if (I > 0 && J > 0 && I < Nc - 1 && J < Nc - 1) {
+                // defect columns and rows outside the grid are zero in LDS
+                if (!is_dirichlet(Nc, I, J, dmask)) {
                     const T* u = D[l2];  // row jr - 1
                     const T* c = D[l1];  // row jr
                     const T* o = D[x3];  // row jr + 1
@@ -415,6 +416,7 @@ struct TailLevels {
     int m;
     int top;  // highest level of the tail; entered with a zero iterate
     int Lc;
+    int dmask;  // Dirichlet sides
 };
 
 // LDS image of level l: 9 bands (band-major, stride n), then x with N+1
@@ -501,12 +503,12 @@ __device__ void tail_cycle(const TailLevels<T>& tl, T omega) {
         __syncthreads();
         const TailLds<T> c(lds, tl.Lc, l - 1);
         for (int q = threadIdx.x; q < c.n; q += TAIL_THREADS)
-            restrict_elem<T>(v.N, v.t, c.b, q % c.N, q / c.N);
+            restrict_elem<T>(v.N, v.t, c.b, q % c.N, q / c.N, tl.dmask);
         __syncthreads();
     }
     {
         const TailLds<T> c(lds, tl.Lc, tl.Lc);
-        coarse_block<T>(tl.chol, tl.m, c.N, c.b, c.x);
+        coarse_block<T>(tl.chol, tl.m, c.N, c.b, c.x, tl.dmask);
     }
     for (int l = tl.Lc + 1; l <= tl.top; ++l) {
         const TailLds<T> v(lds, tl.Lc, l);

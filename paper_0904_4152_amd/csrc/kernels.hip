@@ -81,10 +81,10 @@ __global__ __launch_bounds__(BLOCK) void k_jacobi_zero(const T* __restrict__ dia
 
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_restrict(int Nf, const T* __restrict__ d,
-                                                    T* __restrict__ bc) {
+                                                    T* __restrict__ bc, int dmask) {
     const int Nc = (Nf >> 1) + 1;
     const int I = blockIdx.x * BLOCK + threadIdx.x;
-    if (I < Nc) dev::restrict_elem(Nf, d, bc, I, (int)blockIdx.y);
+    if (I < Nc) dev::restrict_elem(Nf, d, bc, I, (int)blockIdx.y, dmask);
 }
 
 template <typename T>
@@ -125,8 +125,8 @@ hipError_t launch_reduce(double* partials, int64_t np, double* scal, int slot, d
 
 template <typename T>
 __global__ void k_coarse(const double* __restrict__ chol, int m, int Nc,
-                         const T* __restrict__ b, T* __restrict__ x) {
-    dev::coarse_block(chol, m, Nc, b, x);
+                         const T* __restrict__ b, T* __restrict__ x, int dmask) {
+    dev::coarse_block(chol, m, Nc, b, x, dmask);
 }
 
 // Fused pre-smoothing pass: one (strip, chunk) tile per workgroup of BT
@@ -135,15 +135,15 @@ template <typename T, bool XZERO, int BT>
 __global__ __launch_bounds__(BT) void k_pre(const T* __restrict__ bands, int64_t bs, int N,
                                             const T* __restrict__ x, const T* __restrict__ b,
                                             T omega, T* __restrict__ x2out, T* __restrict__ bc,
-                                            dev::FusedGeom g) {
+                                            int dmask, dev::FusedGeom g) {
     const int64_t lb = xcd_block((int64_t)g.nstrips * g.nchunks);
     if (lb < 0) return;
-    dev::pre_tile<T, XZERO, BT>(bands, bs, N, x, b, omega, x2out, bc, (int)(lb % g.nstrips),
-                                (int)(lb / g.nstrips), g.rh, g.cw);
+    dev::pre_tile<T, XZERO, BT>(bands, bs, N, x, b, omega, x2out, bc, dmask,
+                                (int)(lb % g.nstrips), (int)(lb / g.nstrips), g.rh, g.cw);
 }
 
 // Fused post-smoothing pass; with NORM one partial sum of squares per
-// (strip, wavefront, grid row) in partials.
+// (strip, wavefront, group of F_NORM_ROWS grid rows) in partials.
 template <typename T, bool NORM, int BT>
 __global__ __launch_bounds__(BT) void k_post(const T* __restrict__ bands, int64_t bs, int N,
                                              const T* __restrict__ x, const T* __restrict__ xc,
@@ -162,19 +162,26 @@ __global__ __launch_bounds__(dev::TAIL_THREADS) void k_tail(dev::TailLevels<T> t
     dev::tail_cycle<T>(tl, omega);
 }
 
-// Dense interior block of the coarsest operator and its Cholesky factor
-// (one thread; at most 49 unknowns).  flag = 1 if a pivot is not positive.
-__global__ void k_chol_factor(const double* __restrict__ bands, int64_t bs, int Nc,
+// Dense block of the coarsest operator over its unknowns (the nodes off the
+// Dirichlet sides, in index order) and its Cholesky factor (one thread; at
+// most 72 unknowns).  flag = 1 if a pivot is not positive.
+__global__ void k_chol_factor(const double* __restrict__ bands, int64_t bs, int Nc, int dmask,
                               double* __restrict__ A, int* __restrict__ flag) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const int mi = Nc - 2, m = mi * mi;
+    int idx[dev::COARSE_MAX_UNKNOWNS];
+    int m = 0;
+    for (int p = 0; p < Nc * Nc; ++p)
+        idx[p] = dev::is_dirichlet(Nc, p % Nc, p / Nc, dmask) ? -1 : m++;
     for (int r = 0; r < m * m; ++r) A[r] = 0.0;
-    for (int r = 0; r < m; ++r) {
-        const int i = 1 + r % mi, j = 1 + r / mi;
+    for (int p = 0; p < Nc * Nc; ++p) {
+        const int r = idx[p];
+        if (r < 0) continue;
+        const int i = p % Nc, j = p / Nc;
         for (int k = 0; k < 9; ++k) {
             const int ii = i + k % 3 - 1, jj = j + k / 3 - 1;
-            if (ii < 1 || jj < 1 || ii > Nc - 2 || jj > Nc - 2) continue;
-            A[r * m + (jj - 1) * mi + (ii - 1)] = bands[k * bs + (int64_t)j * Nc + i];
+            if (ii < 0 || jj < 0 || ii > Nc - 1 || jj > Nc - 1) continue;
+            const int c = idx[jj * Nc + ii];
+            if (c >= 0) A[r * m + c] = bands[k * bs + p];
         }
     }
     int bad = 0;
@@ -316,6 +323,7 @@ struct AssembleLevels {
     int64_t bs[MG_MAX_LEVEL + 1];
     int64_t first[MG_MAX_LEVEL + 2];
     int Lc, L;
+    int dmask;  // Dirichlet sides
 };
 
 __global__ __launch_bounds__(BLOCK) void k_assemble(const double* __restrict__ xyf,
@@ -353,16 +361,17 @@ __global__ __launch_bounds__(BLOCK) void k_assemble(const double* __restrict__ x
     double band[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) band[k] = 0.0;
-    const bool bnd = (i == 0 || j == 0 || i == N - 1 || j == N - 1);
-    if (bnd) {
+    if (dev::is_dirichlet(N, i, j, a.dmask)) {
         band[4] = 1.0;
     } else {
         // element (ei,ej) = (i-1+ex, j-1+ey); this node is its corner c_node.
+        // Elements outside the grid (nodes on a Neumann side) are absent.
         const int corner_of[4] = {2, 3, 1, 0};
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const int ex = e & 1, ey = e >> 1;
             const int ei = i - 1 + ex, ej = j - 1 + ey;
+            if (ei < 0 || ej < 0 || ei > N - 2 || ej > N - 2) continue;
             const double* K = Ke[(ej - j0 + 1) * (ATX + 1) + (ei - i0 + 1)];
             const int c_node = corner_of[e];
             // corner c sits at (ei + ox[c], ej + oy[c]); this node at (i, j)
@@ -373,10 +382,13 @@ __global__ __launch_bounds__(BLOCK) void k_assemble(const double* __restrict__ x
                 band[(dj + 1) * 3 + (di + 1)] += K[c_node * 4 + c];
             }
         }
+        // couplings to Dirichlet nodes move to the right-hand side (zero
+        // data); a select per band, with no divergent branch around it
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
             const int ii = i + k % 3 - 1, jj = j + k / 3 - 1;
-            if (k != 4 && (ii == 0 || jj == 0 || ii == N - 1 || jj == N - 1)) band[k] = 0.0;
+            const bool drop = k != 4 && dev::is_dirichlet(N, ii, jj, a.dmask);
+            band[k] = drop ? 0.0 : band[k];
         }
     }
     double* b64 = a.b64[l];
@@ -433,8 +445,9 @@ __global__ __launch_bounds__(BLOCK) void k_rhs_sinsin(const double* __restrict__
     bout[p] = sum;
 }
 
-// Seeded uniform right-hand side; with x0 also a zero initial iterate.
-__global__ __launch_bounds__(BLOCK) void k_rhs_uniform(int N, uint64_t seed,
+// Seeded uniform right-hand side (zero on the Dirichlet sides); with x0 also
+// a zero initial iterate.
+__global__ __launch_bounds__(BLOCK) void k_rhs_uniform(int N, uint64_t seed, int dmask,
                                                        double* __restrict__ bout,
                                                        double* __restrict__ x0) {
     const int i = blockIdx.x * BLOCK + threadIdx.x;
@@ -442,7 +455,7 @@ __global__ __launch_bounds__(BLOCK) void k_rhs_uniform(int N, uint64_t seed,
     if (i >= N) return;
     const int64_t p = (int64_t)j * N + i;
     double v = 0.0;
-    if (i > 0 && j > 0 && i < N - 1 && j < N - 1) v = 2.0 * uniform01(seed, (uint64_t)p) - 1.0;
+    if (!dev::is_dirichlet(N, i, j, dmask)) v = 2.0 * uniform01(seed, (uint64_t)p) - 1.0;
     bout[p] = v;
     if (x0) x0[p] = 0.0;
 }
@@ -503,10 +516,12 @@ hipError_t launch_coords(double* xy, int L, double jitter, uint64_t seed, hipStr
     return hipGetLastError();
 }
 
-hipError_t launch_assemble(const double* xy_fine, const Level* lv, int Lc, int L, hipStream_t st) {
+hipError_t launch_assemble(const double* xy_fine, const Level* lv, int Lc, int L, int dmask,
+                           hipStream_t st) {
     AssembleLevels a{};
     a.Lc = Lc;
     a.L = L;
+    a.dmask = dmask;
     int64_t nb = 0;
     for (int l = Lc; l <= L; ++l) {
         const int64_t N = (int64_t(1) << l) + 1;
@@ -521,9 +536,10 @@ hipError_t launch_assemble(const double* xy_fine, const Level* lv, int Lc, int L
     return hipGetLastError();
 }
 
-hipError_t launch_chol_factor(const Level& lc, double* chol, int* flag, hipStream_t st) {
-    hipLaunchKernelGGL(k_chol_factor, dim3(1), dim3(64), 0, st, lc.bands64, lc.bs, lc.N, chol,
-                       flag);
+hipError_t launch_chol_factor(const Level& lc, int dmask, double* chol, int* flag,
+                              hipStream_t st) {
+    hipLaunchKernelGGL(k_chol_factor, dim3(1), dim3(64), 0, st, lc.bands64, lc.bs, lc.N, dmask,
+                       chol, flag);
     return hipGetLastError();
 }
 
@@ -532,8 +548,10 @@ hipError_t launch_rhs_sinsin(const double* xy, int N, double* b, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_rhs_uniform(int N, uint64_t seed, double* b, double* x0, hipStream_t st) {
-    hipLaunchKernelGGL(k_rhs_uniform, dim3(blocks1d(N), N), dim3(BLOCK), 0, st, N, seed, b, x0);
+hipError_t launch_rhs_uniform(int N, uint64_t seed, int dmask, double* b, double* x0,
+                              hipStream_t st) {
+    hipLaunchKernelGGL(k_rhs_uniform, dim3(blocks1d(N), N), dim3(BLOCK), 0, st, N, seed, dmask,
+                       b, x0);
     return hipGetLastError();
 }
 
@@ -647,16 +665,16 @@ int64_t fused_tiles(int N) {
 
 template <typename T>
 hipError_t launch_pre(const Level& lv, const T* bands, const T* x, bool x_zero, const T* b,
-                      T omega, T* x2out, T* bc, hipStream_t st) {
+                      T omega, T* x2out, T* bc, int dmask, hipStream_t st) {
     const dev::FusedGeom g = single_geom(lv.N);
     const dim3 grid(grid8((int64_t)g.nstrips * g.nchunks)), block(g.bt);
 #define PRE(BT)                                                                               \
     if (x_zero)                                                                               \
         hipLaunchKernelGGL((k_pre<T, true, BT>), grid, block, 0, st, bands, lv.bs, lv.N, x, b, \
-                           omega, x2out, bc, g);                                              \
+                           omega, x2out, bc, dmask, g);                                       \
     else                                                                                      \
         hipLaunchKernelGGL((k_pre<T, false, BT>), grid, block, 0, st, bands, lv.bs, lv.N, x,   \
-                           b, omega, x2out, bc, g);
+                           b, omega, x2out, bc, dmask, g);
     MG_FUSED_BT_SWITCH(g.bt, PRE)
 #undef PRE
     return hipGetLastError();
@@ -683,8 +701,8 @@ hipError_t launch_post(const Level& lv, const T* bands, const T* x, const T* xc,
 }
 
 template <typename T>
-hipError_t launch_tail(const Level* lv, int top, int Lc, const double* chol, int m, T omega,
-                       hipStream_t st) {
+hipError_t launch_tail(const Level* lv, int top, int Lc, const double* chol, int m, int dmask,
+                       T omega, hipStream_t st) {
     dev::TailLevels<T> tl{};
     for (int l = Lc; l <= top; ++l) {
         dev::TailLevel<T>& d = tl.lv[l];
@@ -701,6 +719,7 @@ hipError_t launch_tail(const Level* lv, int top, int Lc, const double* chol, int
     tl.m = m;
     tl.top = top;
     tl.Lc = Lc;
+    tl.dmask = dmask;
     hipLaunchKernelGGL(k_tail<T>, dim3(1), dim3(dev::TAIL_THREADS), 0, st, tl, omega);
     return hipGetLastError();
 }
@@ -708,9 +727,10 @@ hipError_t launch_tail(const Level* lv, int top, int Lc, const double* chol, int
 int tail_max_level() { return dev::TAIL_MAX; }
 
 template <typename T>
-hipError_t launch_restrict(int Nf, const T* d_f, T* b_c, hipStream_t st) {
+hipError_t launch_restrict(int Nf, const T* d_f, T* b_c, int dmask, hipStream_t st) {
     const int Nc = (Nf >> 1) + 1;
-    hipLaunchKernelGGL(k_restrict<T>, dim3(blocks1d(Nc), Nc), dim3(BLOCK), 0, st, Nf, d_f, b_c);
+    hipLaunchKernelGGL(k_restrict<T>, dim3(blocks1d(Nc), Nc), dim3(BLOCK), 0, st, Nf, d_f, b_c,
+                       dmask);
     return hipGetLastError();
 }
 
@@ -721,8 +741,9 @@ hipError_t launch_prolong(int Nf, const T* x_c, T* x_f, hipStream_t st) {
 }
 
 template <typename T>
-hipError_t launch_coarse(const double* chol, int m, int Nc, const T* b, T* x, hipStream_t st) {
-    hipLaunchKernelGGL(k_coarse<T>, dim3(1), dim3(64), 0, st, chol, m, Nc, b, x);
+hipError_t launch_coarse(const double* chol, int m, int Nc, const T* b, T* x, int dmask,
+                         hipStream_t st) {
+    hipLaunchKernelGGL(k_coarse<T>, dim3(1), dim3(64), 0, st, chol, m, Nc, b, x, dmask);
     return hipGetLastError();
 }
 
@@ -769,18 +790,20 @@ hipError_t launch_update(double* x, const float* c32, int64_t n, const double* s
                                          hipStream_t);                                        \
     template hipError_t launch_jacobi_zero<T>(const Level&, const T*, const T*, T*, T,        \
                                               hipStream_t);                                   \
-    template hipError_t launch_restrict<T>(int, const T*, T*, hipStream_t);                   \
+    template hipError_t launch_restrict<T>(int, const T*, T*, int, hipStream_t);              \
     template hipError_t launch_prolong<T>(int, const T*, T*, hipStream_t);                    \
-    template hipError_t launch_coarse<T>(const double*, int, int, const T*, T*, hipStream_t); \
+    template hipError_t launch_coarse<T>(const double*, int, int, const T*, T*, int,          \
+                                         hipStream_t);                                        \
     template hipError_t launch_copy<T>(const T*, T*, int64_t, hipStream_t);                   \
     template hipError_t launch_norm<T>(const T*, int64_t, double*, double*, int, double*,     \
                                        hipStream_t);                                          \
     template hipError_t launch_fill<T>(T*, int64_t, T, hipStream_t);                          \
     template hipError_t launch_pre<T>(const Level&, const T*, const T*, bool, const T*, T, T*,  \
-                                      T*, hipStream_t);                                         \
+                                      T*, int, hipStream_t);                                    \
     template hipError_t launch_post<T>(const Level&, const T*, const T*, const T*, const T*, T, \
                                        T*, double*, double*, int, double*, hipStream_t);      \
-    template hipError_t launch_tail<T>(const Level*, int, int, const double*, int, T, hipStream_t);
+    template hipError_t launch_tail<T>(const Level*, int, int, const double*, int, int, T,     \
+                                       hipStream_t);
 
 MG_INSTANTIATE(float)
 MG_INSTANTIATE(double)

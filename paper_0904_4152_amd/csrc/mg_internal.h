@@ -65,6 +65,7 @@ struct GraphCache;  // defined in solve.hip
 struct mg_hierarchy {
     mg_context* ctx = nullptr;
     int L = 0, Lc = 1;
+    int dmask = 15;                // Dirichlet sides (bits 1: x=0, 2: x=1, 4: y=0, 8: y=1)
     size_t charged = 0;
     std::vector<void*> allocs;
     mg::Level lv[MG_MAX_LEVEL + 1];
@@ -74,8 +75,8 @@ struct mg_hierarchy {
     int64_t n_partials = 0;
     double* scal = nullptr;        // device scalars (norms), 64 doubles
     double* host_scal = nullptr;   // pinned mirror of scal
-    double* chol = nullptr;        // m x m Cholesky factor of the coarse interior block
-    int m = 0;
+    double* chol = nullptr;        // m x m Cholesky factor of the coarse unknowns' block
+    int m = 0;                     // coarse unknowns (nodes off the Dirichlet sides)
     int* flag = nullptr;           // device status flag of the coarse factorisation
     bool assembled = false;
     GraphCache* graphs = nullptr;
@@ -89,12 +90,16 @@ enum : int { SC_B = 0, SC_R64 = 2, SC_R32 = 4, SC_D32 = 6, SC_USER = 8 };
 // ---------------------------------------------------------------- kernels
 // All launchers enqueue on `st` and return the HIP launch error.
 hipError_t launch_coords(double* xy, int L, double jitter, uint64_t seed, hipStream_t st);
+// dmask below: the Dirichlet sides of the problem (bits as in mg_hierarchy).
 // Bands of levels Lc..L (lv indexed by level) from the finest coordinates.
-hipError_t launch_assemble(const double* xy_fine, const Level* lv, int Lc, int L, hipStream_t st);
-hipError_t launch_chol_factor(const Level& lc, double* chol, int* flag, hipStream_t st);
+hipError_t launch_assemble(const double* xy_fine, const Level* lv, int Lc, int L, int dmask,
+                           hipStream_t st);
+hipError_t launch_chol_factor(const Level& lc, int dmask, double* chol, int* flag,
+                              hipStream_t st);
 hipError_t launch_rhs_sinsin(const double* xy, int N, double* b, hipStream_t st);
 // Seeded uniform right-hand side; x0 (nullable) set to zero alongside.
-hipError_t launch_rhs_uniform(int N, uint64_t seed, double* b, double* x0, hipStream_t st);
+hipError_t launch_rhs_uniform(int N, uint64_t seed, int dmask, double* b, double* x0,
+                              hipStream_t st);
 
 // Stencil family on one level.
 template <typename T>
@@ -115,11 +120,12 @@ template <typename T>
 hipError_t launch_jacobi_zero(const Level& lv, const T* bands, const T* b, T* xo, T omega,
                               hipStream_t st);
 template <typename T>
-hipError_t launch_restrict(int Nf, const T* d_f, T* b_c, hipStream_t st);
+hipError_t launch_restrict(int Nf, const T* d_f, T* b_c, int dmask, hipStream_t st);
 template <typename T>
 hipError_t launch_prolong(int Nf, const T* x_c, T* x_f, hipStream_t st);
 template <typename T>
-hipError_t launch_coarse(const double* chol, int m, int Nc, const T* b, T* x, hipStream_t st);
+hipError_t launch_coarse(const double* chol, int m, int Nc, const T* b, T* x, int dmask,
+                         hipStream_t st);
 template <typename T>
 hipError_t launch_copy(const T* src, T* dst, int64_t n, hipStream_t st);
 // Sum of squares of v (accumulated in FP64) into scal[slot], norm into
@@ -142,7 +148,7 @@ hipError_t launch_update(double* x, const float* c32, int64_t n, const double* s
 // residual norm reduced into scal[slot], scal[slot + 1].
 template <typename T>
 hipError_t launch_pre(const Level& lv, const T* bands, const T* x, bool x_zero, const T* b,
-                      T omega, T* x2out, T* bc, hipStream_t st);
+                      T omega, T* x2out, T* bc, int dmask, hipStream_t st);
 template <typename T>
 hipError_t launch_post(const Level& lv, const T* bands, const T* x, const T* xc, const T* b,
                        T omega, T* xout, double* partials, double* scal, int slot, double* host,
@@ -150,8 +156,8 @@ hipError_t launch_post(const Level& lv, const T* bands, const T* x, const T* xc,
 // The V(2,2) sub-cycle over levels top..Lc (top <= tail_max_level(), entered
 // with a zero iterate on level top) in one workgroup.  lv is indexed by level.
 template <typename T>
-hipError_t launch_tail(const Level* lv, int top, int Lc, const double* chol, int m, T omega,
-                       hipStream_t st);
+hipError_t launch_tail(const Level* lv, int top, int Lc, const double* chol, int m, int dmask,
+                       T omega, hipStream_t st);
 int tail_max_level();
 // Tiling of the fused passes on a level of N nodes per side: workgroup
 // width, chunk height for a pass over `count` problems, geometry of a

@@ -12,8 +12,9 @@ Workload recipes (the paper's synthetic Poisson problems, Sec. 2.1 / 6.2):
   * grid: N = 2^L + 1 nodes per side, node (i, j) at (i h + dx, j h + dy),
     h = 1/(N-1); boundary nodes are not moved; interior nodes move by
     dx = (2u - 1) a h, dy likewise, with u drawn at k = 2p (x) and 2p + 1 (y);
-  * uniform right-hand side: b_p = 2u - 1 (k = p) on interior nodes, 0 on the
-    boundary -- the load vector itself, not f at the nodes;
+  * uniform right-hand side: b_p = 2u - 1 (k = p) on nodes off the
+    Dirichlet sides (all interior nodes when every side is Dirichlet), 0 on
+    them -- the load vector itself, not f at the nodes;
   * Gaussian right-hand side: Box-Muller on (u at k = 2p, u at k = 2p + 1).
 """
 from __future__ import annotations
@@ -72,11 +73,22 @@ def interior_mask(L: int) -> np.ndarray:
     return (ii > 0) & (jj > 0) & (ii < N - 1) & (jj < N - 1)
 
 
-def rhs_uniform(L: int, seed: int) -> np.ndarray:
-    """b_p = 2u - 1 on interior nodes, 0 on the boundary."""
+def free_mask(L: int, dirichlet_sides: int = 15) -> np.ndarray:
+    """Nodes off the Dirichlet sides (bits 1: x = 0, 2: x = 1, 4: y = 0,
+    8: y = 1); with every side Dirichlet, the interior nodes."""
+    N = grid_size(L)
+    ii = np.tile(np.arange(N), N)
+    jj = np.repeat(np.arange(N), N)
+    on = (((ii == 0) & bool(dirichlet_sides & 1)) | ((ii == N - 1) & bool(dirichlet_sides & 2)) |
+          ((jj == 0) & bool(dirichlet_sides & 4)) | ((jj == N - 1) & bool(dirichlet_sides & 8)))
+    return ~on
+
+
+def rhs_uniform(L: int, seed: int, dirichlet_sides: int = 15) -> np.ndarray:
+    """b_p = 2u - 1 off the Dirichlet sides, 0 on them."""
     N = grid_size(L)
     u = uniform(seed, np.arange(N * N, dtype=np.uint64))
-    return np.where(interior_mask(L), 2.0 * u - 1.0, 0.0)
+    return np.where(free_mask(L, dirichlet_sides), 2.0 * u - 1.0, 0.0)
 
 
 def rhs_gaussian(L: int, seed: int) -> np.ndarray:

@@ -182,7 +182,9 @@ def test_restrict_prolong(mg, ctx, orc, L, dtype):
     h.restrict(L, dev(d, dtype), bc)
     ref = orc.restrict(Nf, d, filter=True)
     sc = orc.restrict(Nf, np.abs(d), filter=True)
-    assert_within(host(bc), ref, 4 * u * sc, "restrict")
+    # nine weighted terms (weights powers of two) summed in different orders
+    # on the two sides: each within gamma_8 of the exact sum, so 16 u apart
+    assert_within(host(bc), ref, 16 * u * sc, "restrict")
     xfd = dev(xf, dtype)
     h.prolong(L, dev(xc, dtype), xfd)
     ref = orc.prolong_add(Nf, xc, xf)
