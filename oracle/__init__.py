@@ -36,7 +36,9 @@ class OrOpts(ctypes.Structure):
     _fields_ = [("nu_pre", ctypes.c_int), ("nu_post", ctypes.c_int),
                 ("omega", ctypes.c_double), ("rel_tol", ctypes.c_double),
                 ("max_cycles", ctypes.c_int), ("fixed_cycles", ctypes.c_int),
-                ("inner_reduction", ctypes.c_double), ("inner_max_cycles", ctypes.c_int)]
+                ("inner_reduction", ctypes.c_double), ("inner_max_cycles", ctypes.c_int),
+                ("coarse_cg", ctypes.c_int), ("coarse_tol", ctypes.c_double),
+                ("coarse_max_iter", ctypes.c_int)]
 
 
 class OrStats(ctypes.Structure):
@@ -93,6 +95,12 @@ def lib():
                                     ctypes.POINTER(OrStats)]
         L.or_solve_mixed_emulated.argtypes = [ctypes.c_void_p, _dp, _dp,
                                               ctypes.POINTER(OrOpts), ctypes.POINTER(OrStats)]
+        L.or_dot.argtypes = [ctypes.c_size_t, _dp, _dp]
+        L.or_dot.restype = ctypes.c_double
+        L.or_cg.argtypes = [ctypes.c_int, _dp, _dp, _dp, ctypes.c_double, ctypes.c_int]
+        L.or_cg.restype = ctypes.c_int
+        L.or_solve_pcg.argtypes = [ctypes.c_void_p, _dp, _dp, ctypes.POINTER(OrOpts),
+                                   ctypes.c_int, ctypes.POINTER(OrStats)]
     return _lib
 
 
@@ -107,9 +115,10 @@ def _f(a: np.ndarray):
 
 
 def opts(nu_pre=2, nu_post=2, omega=0.7, rel_tol=1e-8, max_cycles=100, fixed_cycles=0,
-         inner_reduction=1e-2, inner_max_cycles=8) -> OrOpts:
+         inner_reduction=1e-2, inner_max_cycles=8, coarse_cg=False, coarse_tol=1e-10,
+         coarse_max_iter=200) -> OrOpts:
     return OrOpts(nu_pre, nu_post, omega, rel_tol, max_cycles, fixed_cycles,
-                  inner_reduction, inner_max_cycles)
+                  inner_reduction, inner_max_cycles, int(coarse_cg), coarse_tol, coarse_max_iter)
 
 
 def element_stiffness(xq, yq) -> np.ndarray:
@@ -271,6 +280,15 @@ class Hierarchy:
                             ctypes.byref(o or opts()), ctypes.byref(st))
         return x, st
 
+    def solve_pcg(self, b, x0=None, o: OrOpts | None = None, precond32: bool = False):
+        """CG preconditioned by one V-cycle (FP64, or FP32 with precond32)."""
+        n = self.N(self.L) ** 2
+        x = np.zeros(n) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
+        st = OrStats()
+        lib().or_solve_pcg(self._h, _d(np.ascontiguousarray(b)), _d(x),
+                           ctypes.byref(o or opts()), int(precond32), ctypes.byref(st))
+        return x, st
+
     def solve_mixed_emulated(self, b, x0=None, o: OrOpts | None = None):
         n = self.N(self.L) ** 2
         x = np.zeros(n) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
@@ -278,6 +296,14 @@ class Hierarchy:
         lib().or_solve_mixed_emulated(self._h, _d(np.ascontiguousarray(b)), _d(x),
                                       ctypes.byref(o or opts()), ctypes.byref(st))
         return x, st
+
+
+def cg(N, bands, b, x0=None, tol=1e-10, max_iter=200):
+    """Unpreconditioned CG on one level's banded system; returns (x, steps)."""
+    x = np.zeros(N * N) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
+    k = lib().or_cg(N, _d(np.ascontiguousarray(bands, dtype=np.float64).reshape(-1)),
+                    _d(np.ascontiguousarray(b, dtype=np.float64)), _d(x), tol, max_iter)
+    return x, k
 
 
 def hist(st: OrStats):

@@ -358,6 +358,44 @@ void or_cholesky_solve(int m, const double* Lf, double* b) {
     }
 }
 
+double or_dot(size_t n, const double* u, const double* v) {
+    double s = 0.0;
+    for (size_t p = 0; p < n; ++p) s += u[p] * v[p];
+    return s;
+}
+
+/* Unpreconditioned conjugate gradients (Hestenes and Stiefel), the coarse
+ * grid solver of Sec. 6.2, on the full banded system of one level: from the
+ * iterate in x, r = b - A x, p = r; each step q = A p, alpha = (r.r)/(p.q),
+ * x += alpha p, r -= alpha q, beta = (r'.r')/(r.r), p = r' + beta p.  Stops
+ * before a step once ||r|| <= tol ||b|| or after max_iter steps.  Dirichlet
+ * rows (identity, zero right-hand side) stay at zero from a zero start.
+ * Returns the number of steps taken. */
+int or_cg(int N, const double* bands, const double* b, double* x, double tol, int max_iter) {
+    size_t n = (size_t)N * N;
+    double* r = (double*)malloc(n * sizeof(double));
+    double* p = (double*)malloc(n * sizeof(double));
+    double* q = (double*)malloc(n * sizeof(double));
+    or_defect(N, bands, b, x, r);
+    memcpy(p, r, n * sizeof(double));
+    double rr = or_dot(n, r, r);
+    double stop = tol * or_norm2(n, b);
+    int k = 0;
+    while (k < max_iter && sqrt(rr) > stop) {
+        or_spmv(N, bands, p, q);
+        double alpha = rr / or_dot(n, p, q);
+        for (size_t i = 0; i < n; ++i) x[i] += alpha * p[i];
+        for (size_t i = 0; i < n; ++i) r[i] -= alpha * q[i];
+        double rr_new = or_dot(n, r, r);
+        double beta = rr_new / rr;
+        for (size_t i = 0; i < n; ++i) p[i] = r[i] + beta * p[i];
+        rr = rr_new;
+        ++k;
+    }
+    free(r); free(p); free(q);
+    return k;
+}
+
 /* ---- single precision band operations (emulated FP32 inner cycles) ---- */
 void or_spmv_f32(int N, const float* bands, const float* x, float* y) {
     size_t n = (size_t)N * N;
@@ -524,10 +562,16 @@ int or_hier_N(const or_hier* h, int l) { return h->N[l]; }
 const double* or_hier_bands(const or_hier* h, int l) { return h->bands[l]; }
 const double* or_hier_coords(const or_hier* h, int l) { return h->xy[l]; }
 
-/* Direct solve at the coarsest level: the unknowns by Cholesky, Dirichlet
- * rows are identity rows. */
-static void coarse_solve(or_hier* h, double* x, const double* b) {
+/* Solve at the coarsest level: with o->coarse_cg by CG from a zero iterate
+ * (Sec. 6.2), else directly: the unknowns by Cholesky, Dirichlet rows are
+ * identity rows. */
+static void coarse_solve(or_hier* h, double* x, const double* b, const or_opts* o) {
     int Nc = h->N[h->Lc];
+    if (o->coarse_cg) {
+        memset(x, 0, (size_t)Nc * Nc * sizeof(double));
+        or_cg(Nc, h->bands[h->Lc], b, x, o->coarse_tol, o->coarse_max_iter);
+        return;
+    }
     for (int j = 0; j < Nc; ++j)
         for (int i = 0; i < Nc; ++i)
             if (is_dirichlet(Nc, i, j, h->dmask)) x[(size_t)j * Nc + i] = b[(size_t)j * Nc + i];
@@ -542,7 +586,7 @@ int or_vcycle(or_hier* h, int l, double* x, const double* b, const or_opts* o) {
     int N = h->N[l];
     size_t n = (size_t)N * N;
     if (l == h->Lc) {
-        coarse_solve(h, x, b);
+        coarse_solve(h, x, b, o);
         return 0;
     }
     double* t = h->t[l];
@@ -612,7 +656,7 @@ static void vcycle32(or_hier* h, int l, float* x, const float* b, const or_opts*
         double* bd = h->b[l];
         double* xd = h->x[l];
         for (size_t p = 0; p < n; ++p) bd[p] = (double)b[p];
-        coarse_solve(h, xd, bd);
+        coarse_solve(h, xd, bd, o);
         for (size_t p = 0; p < n; ++p) x[p] = (float)xd[p];
         return;
     }
@@ -686,5 +730,84 @@ int or_solve_mixed_emulated(or_hier* h, const double* b, double* x, const or_opt
         st->outer_steps = k;
     }
     free(d); free(d32); free(c32); free(r32);
+    return st->status;
+}
+
+/* z = M r with M one V-cycle from a zero iterate: in FP64, or with
+ * precond32 in single precision on r / ||r|| scaled back (the FP32 cycle of
+ * the mixed scheme used as a preconditioner). */
+static void precondition(or_hier* h, const double* r, double* z, const or_opts* o, int precond32,
+                         float* r32, float* z32) {
+    int N = h->N[h->L];
+    size_t n = (size_t)N * N;
+    if (!precond32) {
+        memset(z, 0, n * sizeof(double));
+        or_vcycle(h, h->L, z, r, o);
+        return;
+    }
+    double s = or_norm2(n, r);
+    if (s == 0.0) {
+        memset(z, 0, n * sizeof(double));
+        return;
+    }
+    for (size_t p = 0; p < n; ++p) r32[p] = (float)(r[p] / s);
+    memset(z32, 0, n * sizeof(float));
+    vcycle32(h, h->L, z32, r32, o);
+    for (size_t p = 0; p < n; ++p) z[p] = s * (double)z32[p];
+}
+
+/* Conjugate gradients preconditioned by one multigrid cycle (Sec. 4.1: a
+ * solver plugged into another as its preconditioner; the cycle of Sec. 6.2).  From
+ * x: r = b - A x, z = M r, p = z; each step q = A p,
+ * alpha = (r.z)/(p.q), x += alpha p, r -= alpha q, stop once
+ * ||r|| <= rel_tol ||b|| (r updated by the recurrence), z' = M r',
+ * beta = (r'.z')/(r.z), p = z' + beta p.  stats: cycles = steps (one
+ * preconditioner cycle each), res_hist the recurrence residual after each
+ * step, rel_res the true residual at exit. */
+int or_solve_pcg(or_hier* h, const double* b, double* x, const or_opts* o, int precond32,
+                 or_stats* st) {
+    int N = h->N[h->L];
+    size_t n = (size_t)N * N;
+    memset(st, 0, sizeof(*st));
+    double bn = or_norm2(n, b);
+    st->bnorm = bn;
+    if (bn == 0.0) {
+        memset(x, 0, n * sizeof(double));
+        return 0;
+    }
+    double* r = (double*)malloc(n * sizeof(double));
+    double* z = (double*)malloc(n * sizeof(double));
+    double* p = (double*)malloc(n * sizeof(double));
+    double* q = (double*)malloc(n * sizeof(double));
+    float* r32 = (float*)malloc(n * sizeof(float));
+    float* z32 = (float*)malloc(n * sizeof(float));
+    or_defect(N, h->bands[h->L], b, x, r);
+    double rn = or_norm2(n, r);
+    precondition(h, r, z, o, precond32, r32, z32);
+    memcpy(p, z, n * sizeof(double));
+    double rz = or_dot(n, r, z);
+    for (int k = 1;; ++k) {
+        if (o->fixed_cycles > 0) {
+            if (k > o->fixed_cycles) break;
+        } else {
+            if (rn <= o->rel_tol * bn) break;
+            if (k > o->max_cycles) { st->status = 3; break; }
+        }
+        or_spmv(N, h->bands[h->L], p, q);
+        double alpha = rz / or_dot(n, p, q);
+        for (size_t i = 0; i < n; ++i) x[i] += alpha * p[i];
+        for (size_t i = 0; i < n; ++i) r[i] -= alpha * q[i];
+        rn = or_norm2(n, r);
+        st->cycles = k;
+        if (st->n_hist < 256) st->res_hist[st->n_hist++] = rn / bn;
+        if (!(rn == rn) || rn > 1e3 * bn) { st->status = 4; break; }
+        precondition(h, r, z, o, precond32, r32, z32);
+        double rz_new = or_dot(n, r, z);
+        double beta = rz_new / rz;
+        for (size_t i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
+        rz = rz_new;
+    }
+    st->rel_res = residual_norm(h, b, x) / bn;
+    free(r); free(z); free(p); free(q); free(r32); free(z32);
     return st->status;
 }

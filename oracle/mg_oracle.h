@@ -77,6 +77,11 @@ double or_norm2(size_t n, const double* v);
  * pivot is not positive. */
 int or_cholesky(int m, double* A);
 void or_cholesky_solve(int m, const double* Lf, double* b);
+double or_dot(size_t n, const double* u, const double* v);
+/* Unpreconditioned CG on one level's banded system, from the iterate in x,
+ * until ||b - A x|| <= tol ||b|| (recurrence residual) or max_iter steps;
+ * returns the steps taken. */
+int or_cg(int N, const double* bands, const double* b, double* x, double tol, int max_iter);
 
 /* Single-precision band operations used by the emulated mixed solver. */
 void or_spmv_f32(int N, const float* bands, const float* x, float* y);
@@ -97,6 +102,9 @@ typedef struct {
     int fixed_cycles;      /* > 0: run exactly this many (no stop test) */
     double inner_reduction;
     int inner_max_cycles;
+    int coarse_cg;         /* 1: coarsest level by CG from zero (Sec. 6.2); 0: Cholesky */
+    double coarse_tol;     /* CG: stop once ||r|| <= coarse_tol ||b|| */
+    int coarse_max_iter;   /* CG: at most this many steps */
 } or_opts;
 
 typedef struct {
@@ -122,6 +130,10 @@ int or_vcycle(or_hier* h, int l, double* x, const double* b, const or_opts* o);
 int or_solve_fp64(or_hier* h, const double* b, double* x, const or_opts* o, or_stats* st);
 int or_solve_mixed_emulated(or_hier* h, const double* b, double* x, const or_opts* o,
                             or_stats* st);
+/* CG preconditioned by one V-cycle from zero (FP64, or FP32 on the scaled
+ * residual with precond32). */
+int or_solve_pcg(or_hier* h, const double* b, double* x, const or_opts* o, int precond32,
+                 or_stats* st);
 
 #ifdef __cplusplus
 }

@@ -535,3 +535,120 @@ def test_mixed_bc_vcycle_contraction(orc, dmask):
     rates = [hist[k + 1] / hist[k] for k in range(len(hist) - 1)]
     assert st.status == 0
     assert max(rates) < 0.2, rates
+
+
+# ---------------------------------------------------------------- conjugate gradients
+
+
+def _scipy_cg_iterates(A, b, steps, M=None):
+    """Iterates of scipy's own CG (an independent implementation of the same
+    recurrences), one per step, from x0 = 0 with the stopping test off."""
+    from scipy.sparse.linalg import cg
+    out = []
+    cg(A, b, x0=np.zeros_like(b), rtol=0.0, atol=0.0, maxiter=steps, M=M,
+       callback=lambda xk: out.append(np.array(xk, copy=True)))
+    return out
+
+
+@pytest.mark.parametrize("L,a,dmask", [(3, 0.0, 15), (4, 0.2, 15), (4, 0.2, 5)])
+def test_cg_iterates_match_scipy_cg(orc, L, a, dmask):
+    N = synth.grid_size(L)
+    h = orc.Hierarchy(L, synth.coords(L, a, seed=8), dmask=dmask)
+    bands = h.bands(L)
+    b = synth.rhs_uniform(L, 12, dmask)
+    A = bands_to_csr(N, bands)
+    ref = _scipy_cg_iterates(A, b, 6)
+    for k in range(1, 7):
+        x, steps = orc.cg(N, bands, b, tol=0.0, max_iter=k)
+        assert steps == k
+        assert np.linalg.norm(x - ref[k - 1]) <= 1e-12 * np.linalg.norm(ref[k - 1])
+
+
+@pytest.mark.parametrize("L,dmask", [(2, 15), (3, 15), (3, 12), (4, 1)])
+def test_cg_solves_to_tolerance_and_stops_there(orc, L, dmask):
+    N = synth.grid_size(L)
+    h = orc.Hierarchy(L, synth.coords(L, 0.2, seed=4), dmask=dmask)
+    bands = h.bands(L)
+    b = synth.rhs_uniform(L, 3, dmask)
+    A = bands_to_csr(N, bands).toarray()
+    xd = np.linalg.solve(A, b)
+    x, steps = orc.cg(N, bands, b, tol=1e-13, max_iter=1000)
+    assert np.linalg.norm(x - xd) <= 1e-11 * np.linalg.norm(xd)
+    # the stop test: the step before the last had not yet reached the bound
+    assert np.linalg.norm(b - A @ x) <= 1.01e-13 * np.linalg.norm(b)
+    xp, _ = orc.cg(N, bands, b, tol=0.0, max_iter=steps - 1)
+    assert np.linalg.norm(b - A @ xp) > 1e-13 * np.linalg.norm(b) * 0.99
+    # Dirichlet nodes keep their zero start
+    D = dirichlet_nodes(N, dmask)
+    assert np.all(x[D] == 0.0)
+    # zero right-hand side: no step
+    z, k0 = orc.cg(N, bands, np.zeros(N * N), tol=1e-10, max_iter=50)
+    assert k0 == 0 and not z.any()
+
+
+def test_cg_residuals_orthogonal_and_energy_error_decreasing(orc):
+    L = 4
+    N = synth.grid_size(L)
+    h = orc.Hierarchy(L, synth.coords(L, 0.25, seed=19))
+    bands = h.bands(L)
+    b = synth.rhs_uniform(L, 20)
+    A = bands_to_csr(N, bands).toarray()
+    xd = np.linalg.solve(A, b)
+    rs, errs = [], []
+    for k in range(0, 8):
+        x, _ = orc.cg(N, bands, b, tol=0.0, max_iter=k)
+        rs.append(b - A @ x)
+        e = x - xd
+        errs.append(np.sqrt(e @ A @ e))
+    for i in range(len(rs)):
+        for j in range(i):
+            assert abs(rs[i] @ rs[j]) <= 1e-10 * np.linalg.norm(rs[i]) * np.linalg.norm(rs[j])
+    assert all(errs[k + 1] < errs[k] for k in range(len(errs) - 1))
+
+
+@pytest.mark.parametrize("Lc", [1, 2, 3, 4])
+def test_cg_coarse_solver_matches_cholesky_cycle(orc, Lc):
+    L = 6
+    h = orc.Hierarchy(L, synth.coords(L, 0.2, seed=2), Lc=Lc)
+    b = synth.rhs_uniform(L, 5)
+    x0 = np.zeros(b.size)
+    xc = h.vcycle(L, x0, b, orc.opts())
+    xg = h.vcycle(L, x0, b, orc.opts(coarse_cg=True, coarse_tol=1e-14, coarse_max_iter=1000))
+    assert np.linalg.norm(xg - xc) <= 1e-12 * np.linalg.norm(xc)
+    # a loose coarse tolerance still converges, in about as many cycles
+    _, s0 = h.solve_fp64(b, o=orc.opts())
+    _, s1 = h.solve_fp64(b, o=orc.opts(coarse_cg=True, coarse_tol=1e-3))
+    assert s1.status == 0 and abs(s1.cycles - s0.cycles) <= 1
+
+
+@pytest.mark.parametrize("L,a,dmask", [(4, 0.2, 15), (5, 0.25, 12)])
+def test_pcg_iterates_match_scipy_pcg_with_the_cycle_as_preconditioner(orc, L, a, dmask):
+    from scipy.sparse.linalg import LinearOperator
+    N = synth.grid_size(L)
+    h = orc.Hierarchy(L, synth.coords(L, a, seed=3), dmask=dmask)
+    b = synth.rhs_uniform(L, 4, dmask)
+    A = bands_to_csr(N, h.bands(L))
+    n = N * N
+    M = LinearOperator((n, n), dtype=np.float64,
+                       matvec=lambda r: h.vcycle(L, np.zeros(n), np.ravel(r).astype(np.float64)))
+    ref = _scipy_cg_iterates(A, b, 4, M=M)
+    for k in range(1, 5):
+        x, st = h.solve_pcg(b, o=orc.opts(fixed_cycles=k))
+        assert st.cycles == k
+        assert np.linalg.norm(x - ref[k - 1]) <= 1e-12 * np.linalg.norm(ref[k - 1])
+        assert abs(st.rel_res - np.linalg.norm(b - A @ x) / np.linalg.norm(b)) <= 1e-12
+
+
+@pytest.mark.parametrize("precond32", [False, True])
+def test_pcg_reaches_tolerance_with_fewer_steps_than_cycles(orc, precond32):
+    for L in (6, 8):
+        h = orc.Hierarchy(L, synth.coords(L, 0.2, seed=1002))
+        b = synth.rhs_uniform(L, 2002)
+        xm, sm = h.solve_fp64(b, o=orc.opts(rel_tol=1e-10))
+        xp, sp_ = h.solve_pcg(b, o=orc.opts(rel_tol=1e-10), precond32=precond32)
+        assert sp_.status == 0 and sp_.rel_res <= 1.01e-10
+        assert sp_.cycles < sm.cycles
+        assert np.linalg.norm(xp - xm) <= 1e-8 * np.linalg.norm(xm)
+        # residual history falls monotonically by at least 5x per step
+        hist = [1.0] + orc.hist(sp_)
+        assert all(hist[k + 1] < 0.2 * hist[k] for k in range(len(hist) - 1)), hist
