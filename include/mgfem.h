@@ -61,13 +61,17 @@ typedef struct mg_hierarchy mg_hierarchy;
 typedef struct mg_server mg_server;
 
 #define MG_MAX_LEVEL 14
-#define MG_MAX_COARSE_LEVEL 3
+#define MG_MAX_COARSE_LEVEL 4
 /* Side bits of dirichlet_sides: x = 0, x = 1, y = 0, y = 1. */
 #define MG_SIDE_X0 1
 #define MG_SIDE_X1 2
 #define MG_SIDE_Y0 4
 #define MG_SIDE_Y1 8
 #define MG_ALL_DIRICHLET 15
+/* Solvers of the coarsest level (mg_hierarchy_set_coarse_solver). */
+#define MG_COARSE_CHOLESKY 0
+#define MG_COARSE_CG 1
+#define MG_COARSE_CG_MAX_ITER 10000
 #define MG_HIST 128
 
 /* Solver options (Sec. 6.2: V cycle, two damped Jacobi pre- and
@@ -122,7 +126,7 @@ mg_status mg_context_memory(const mg_context* ctx, size_t* in_use, size_t* high_
  * dx = (2u-1)*jitter*h, dy = (2u'-1)*jitter*h with u, u' the SplitMix64
  * draws 2p and 2p+1 of geom_seed, generated on the device.  Coarse levels
  * use the finest coordinates sampled every 2^(L-l) nodes.
- * 1 <= coarse_level <= min(L, 3); L <= 14.  Returns MG_ERR_NOMEM without
+ * 1 <= coarse_level <= min(L, 4); L <= 14.  Returns MG_ERR_NOMEM without
  * allocating anything when the hierarchy does not fit the budget. */
 mg_status mg_hierarchy_create(mg_context* ctx, int L, int coarse_level, double jitter,
                               uint64_t geom_seed, const double* host_xy, mg_hierarchy** out);
@@ -147,6 +151,20 @@ size_t mg_hierarchy_bytes(int L, int coarse_level);
  * Synchronous.  MG_ERR_NUMERIC if the coarse block is not positive definite
  * (a tangled grid). */
 mg_status mg_hierarchy_assemble(mg_hierarchy* h, void* stream);
+/* How every later cycle of h solves its coarsest level, in FP64 (also the
+ * coarse solve of the single-precision cycles):
+ *   MG_COARSE_CHOLESKY (the default): the Cholesky factor of the block of
+ *     the nodes off the Dirichlet sides, made by mg_hierarchy_assemble
+ *     (single-threaded substitutions: fast up to coarse level 2 or 3);
+ *   MG_COARSE_CG: unpreconditioned conjugate gradients from a zero iterate
+ *     (Sec. 6.2 uses CG for the coarse grid problems), stopping before a step
+ *     once ||r|| <= tol ||b|| (r by the recurrence) or after max_iter steps
+ *     (1..MG_COARSE_CG_MAX_ITER; tol in [0, 1)).  Its dot products have one
+ *     fixed summation order, so every path gives the same bits.
+ * tol and max_iter are ignored for MG_COARSE_CHOLESKY.  Synchronises the
+ * device and drops the hierarchy's captured cycles.  Not thread safe per
+ * hierarchy. */
+mg_status mg_hierarchy_set_coarse_solver(mg_hierarchy* h, int solver, double tol, int max_iter);
 mg_status mg_hierarchy_destroy(mg_hierarchy* h);
 mg_status mg_hierarchy_info(const mg_hierarchy* h, int* L, int* coarse_level, int64_t* n_finest);
 /* Copy the 9*n band values of one level to host memory, band-major

@@ -17,6 +17,7 @@ MG_HIST = 128
 # Side bits of dirichlet_sides: x = 0, x = 1, y = 0, y = 1.
 SIDE_X0, SIDE_X1, SIDE_Y0, SIDE_Y1 = 1, 2, 4, 8
 ALL_DIRICHLET = 15
+MG_COARSE_CHOLESKY, MG_COARSE_CG = 0, 1
 
 _vp = ctypes.c_void_p
 _i = ctypes.c_int
@@ -62,6 +63,7 @@ _SIGS = {
     "mg_hierarchy_create": (_i, [_vp, _i, _i, _d, _u64, _vp, ctypes.POINTER(_vp)]),
     "mg_hierarchy_create_bc": (_i, [_vp, _i, _i, _d, _u64, _vp, _i, ctypes.POINTER(_vp)]),
     "mg_hierarchy_bytes": (_sz, [_i, _i]),
+    "mg_hierarchy_set_coarse_solver": (_i, [_vp, _i, _d, _i]),
     "mg_hierarchy_assemble": (_i, [_vp, _vp]),
     "mg_hierarchy_destroy": (_i, [_vp]),
     "mg_hierarchy_info": (_i, [_vp, ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i64)]),
@@ -221,6 +223,9 @@ class Hierarchy:
 
     def assemble(self, stream=None):
         check(lib().mg_hierarchy_assemble(self._h, _stream(stream)))
+
+    def set_coarse_solver(self, solver: int, tol: float = 1e-10, max_iter: int = 200):
+        check(lib().mg_hierarchy_set_coarse_solver(self._h, solver, tol, max_iter))
 
     def close(self):
         if self._h:

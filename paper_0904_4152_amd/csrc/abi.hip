@@ -78,6 +78,21 @@ static mg_status set_device(const mg_hierarchy* h) {
     return MG_OK;
 }
 
+static_assert(MG_MAX_COARSE_LEVEL == dev::COARSE_MAX_LEVEL, "coarse level bound");
+
+dev::CoarseSolver coarse_solver(const mg_hierarchy* h) {
+    dev::CoarseSolver cs{};
+    cs.chol = h->chol;
+    cs.bands = h->lv[h->Lc].bands64;
+    cs.bs = h->lv[h->Lc].bs;
+    cs.m = h->m;
+    cs.dmask = h->dmask;
+    cs.cg = h->coarse_cg;
+    cs.max_iter = h->coarse_max_iter;
+    cs.tol = h->coarse_tol;
+    return cs;
+}
+
 }  // namespace mg
 
 using namespace mg;
@@ -189,7 +204,7 @@ mg_status mg_hierarchy_create_bc(mg_context* ctx, int L, int Lc, double jitter, 
     if (L < 1 || L > MG_MAX_LEVEL)
         return fail(MG_ERR_INVALID, "level L=" + std::to_string(L) + " outside [1, 14]");
     if (Lc < 1 || Lc > std::min(L, MG_MAX_COARSE_LEVEL))
-        return fail(MG_ERR_INVALID, "coarse level " + std::to_string(Lc) + " outside [1, min(L, 3)]");
+        return fail(MG_ERR_INVALID, "coarse level " + std::to_string(Lc) + " outside [1, min(L, 4)]");
     if (!(jitter >= 0.0 && jitter < 0.5))
         return fail(MG_ERR_INVALID, "jitter must lie in [0, 0.5)");
     MG_HIP(hipSetDevice(ctx->device));
@@ -296,6 +311,29 @@ mg_status mg_hierarchy_assemble(mg_hierarchy* h, void* stream) {
     MG_HIP(hipStreamSynchronize(st));
     if (flag) return fail(MG_ERR_NUMERIC, "coarse-grid block is not positive definite");
     h->assembled = true;
+    return MG_OK;
+}
+
+mg_status mg_hierarchy_set_coarse_solver(mg_hierarchy* h, int solver, double tol, int max_iter) {
+    if (!h) return fail(MG_ERR_INVALID, "null hierarchy");
+    if (solver != MG_COARSE_CHOLESKY && solver != MG_COARSE_CG)
+        return fail(MG_ERR_INVALID, "unknown coarse solver " + std::to_string(solver));
+    if (solver == MG_COARSE_CG) {
+        if (!(tol >= 0.0 && tol < 1.0))
+            return fail(MG_ERR_INVALID, "coarse CG tolerance must lie in [0, 1)");
+        if (max_iter < 1 || max_iter > MG_COARSE_CG_MAX_ITER)
+            return fail(MG_ERR_INVALID, "coarse CG step limit outside [1, " +
+                                            std::to_string(MG_COARSE_CG_MAX_ITER) + "]");
+    }
+    if (mg_status s = set_device(h)) return s;
+    // captured cycles hold the old solver in their kernel arguments
+    MG_HIP(hipDeviceSynchronize());
+    destroy_graphs(h);
+    h->coarse_cg = solver == MG_COARSE_CG;
+    if (h->coarse_cg) {
+        h->coarse_tol = tol;
+        h->coarse_max_iter = max_iter;
+    }
     return MG_OK;
 }
 
@@ -535,10 +573,9 @@ mg_status mg_coarse_solve(const mg_hierarchy* h, mg_dtype dtype, const void* b, 
     hipStream_t st = (hipStream_t)stream;
     const int Nc = h->lv[h->Lc].N;
     if (dtype == MG_F64)
-        MG_HIP(launch_coarse<double>(h->chol, h->m, Nc, (const double*)b, (double*)x, h->dmask,
-                                              st));
+        MG_HIP(launch_coarse<double>(coarse_solver(h), Nc, (const double*)b, (double*)x, st));
     else
-        MG_HIP(launch_coarse<float>(h->chol, h->m, Nc, (const float*)b, (float*)x, h->dmask, st));
+        MG_HIP(launch_coarse<float>(coarse_solver(h), Nc, (const float*)b, (float*)x, st));
     return MG_OK;
 }
 

@@ -32,8 +32,7 @@ struct BProb {
     BLevel lv[MG_MAX_LEVEL + 1];
     double* d64;
     double* partials;
-    const double* chol;
-    int m;
+    dev::CoarseSolver cs;  // coarsest solve
     int L;
     double omega;
     double rel_tol;

@@ -211,11 +211,9 @@ __global__ __launch_bounds__(dev::TAIL_THREADS) void kb_tail(const BProb* __rest
         const BLevel& v = P.lv[l];
         tl.lv[l] = dev::TailLevel<float>{v.bands32, v.x32, v.b32, v.t32, v.bs, v.n, v.N, 0};
     }
-    tl.chol = P.chol;
-    tl.m = P.m;
+    tl.cs = P.cs;
     tl.top = top;
     tl.Lc = Lc;
-    tl.dmask = P.dmask;
     dev::tail_cycle<float>(tl, (float)P.omega);
     END_ITEMS
 }
@@ -230,7 +228,7 @@ __global__ __launch_bounds__(BLOCK) void kb_coarse(const BProb* __restrict__ pro
     if (!(flags & mask)) continue;
     if (only_level >= 0 && P.L != only_level) continue;
     const BLevel& lv = P.lv[Lc];
-    dev::coarse_block<float>(P.chol, P.m, lv.N, lv.b32, lv.x32, P.dmask);
+    dev::coarse_block<float>(P.cs, lv.N, lv.b32, lv.x32);
     END_ITEMS
 }
 
@@ -620,8 +618,7 @@ void BatchEngine::set_slot(int s, mg_hierarchy* h, const mg_solve_opts& o) {
     }
     P.d64 = h->d64;
     P.partials = h->partials;
-    P.chol = h->chol;
-    P.m = h->m;
+    P.cs = coarse_solver(h);
     P.dmask = h->dmask;
     P.L = h->L;
     P.omega = o.omega;

@@ -203,39 +203,133 @@ __device__ __forceinline__ void prolong_elem(int Nf, const T* __restrict__ xc,
     xf[(int64_t)j * Nf + i] += v;
 }
 
-// Unknowns of the coarsest level: the nodes off the Dirichlet sides, in
-// index order (at most 81: a 9 x 9 grid).
-constexpr int COARSE_MAX_UNKNOWNS = 81;
+// Coarsest level: at most 17 x 17 nodes (level 4).
+constexpr int COARSE_MAX_LEVEL = 4;
+constexpr int COARSE_MAX_N = (1 << COARSE_MAX_LEVEL) + 1;
+constexpr int COARSE_MAX_UNKNOWNS = COARSE_MAX_N * COARSE_MAX_N;
+// LDS doubles of a coarse solve: CG keeps x, r, q and p (p with N+1 zeros on
+// either side for the band product); Cholesky needs m values and m indices.
+constexpr int COARSE_LDS = 4 * COARSE_MAX_UNKNOWNS + 2 * (COARSE_MAX_N + 1);
+static_assert(COARSE_LDS >= COARSE_MAX_UNKNOWNS + (COARSE_MAX_UNKNOWNS + 1) / 2,
+              "Cholesky scratch fits");
 
-// Coarsest level, one block: Dirichlet rows are identity rows; the other
-// nodes are solved in FP64 with the Cholesky factor of their block.
+// How the coarsest level is solved (always in FP64).
+struct CoarseSolver {
+    const double* chol;    // m x m Cholesky factor of the unknowns' block
+    const double* bands;   // FP64 bands of the coarsest level (stride bs)
+    int64_t bs;
+    int m;                 // unknowns: the nodes off the Dirichlet sides
+    int dmask;             // Dirichlet sides
+    int cg;                // 1: conjugate gradients; 0: Cholesky
+    int max_iter;          // CG step limit
+    double tol;            // CG: stop once ||r|| <= tol ||b||
+};
+
+// Dirichlet rows are identity rows; the other nodes are solved with the
+// Cholesky factor of their block (thread 0; forward and back substitution).
 template <typename T>
-__device__ __forceinline__ void coarse_block(const double* __restrict__ chol, int m, int Nc,
-                                             const T* __restrict__ b, T* __restrict__ x,
-                                             int dmask) {
-    __shared__ double z[COARSE_MAX_UNKNOWNS];
-    __shared__ int node[COARSE_MAX_UNKNOWNS];
-    __syncthreads();
-    for (int p = threadIdx.x; p < Nc * Nc; p += blockDim.x) {
-        const int i = p % Nc, j = p / Nc;
-        if (is_dirichlet(Nc, i, j, dmask)) x[p] = b[p];
-    }
+__device__ __forceinline__ void coarse_cholesky(const CoarseSolver& cs, int Nc,
+                                                const T* __restrict__ b, T* __restrict__ x,
+                                                double* __restrict__ w) {
+    double* z = w;
+    int* node = reinterpret_cast<int*>(w + COARSE_MAX_UNKNOWNS);
+    const int m = cs.m;
+    for (int p = threadIdx.x; p < Nc * Nc; p += blockDim.x)
+        if (is_dirichlet(Nc, p % Nc, p / Nc, cs.dmask)) x[p] = b[p];
     if (threadIdx.x == 0) {
         int r = 0;
         for (int p = 0; p < Nc * Nc; ++p)
-            if (!is_dirichlet(Nc, p % Nc, p / Nc, dmask)) node[r++] = p;
+            if (!is_dirichlet(Nc, p % Nc, p / Nc, cs.dmask)) node[r++] = p;
         for (int r = 0; r < m; ++r) {
             double s = (double)b[node[r]];
-            for (int k = 0; k < r; ++k) s -= chol[r * m + k] * z[k];
-            z[r] = s / chol[r * m + r];
+            for (int k = 0; k < r; ++k) s -= cs.chol[r * m + k] * z[k];
+            z[r] = s / cs.chol[r * m + r];
         }
         for (int r = m - 1; r >= 0; --r) {
             double s = z[r];
-            for (int k = r + 1; k < m; ++k) s -= chol[k * m + r] * z[k];
-            z[r] = s / chol[r * m + r];
+            for (int k = r + 1; k < m; ++k) s -= cs.chol[k * m + r] * z[k];
+            z[r] = s / cs.chol[r * m + r];
         }
         for (int r = 0; r < m; ++r) x[node[r]] = (T)z[r];
     }
+}
+
+// u . v over n nodes in one fixed order for any workgroup size: lane l of
+// wavefront 0 sums the nodes p = l mod 64 in index order, then the lanes
+// combine in a fixed butterfly and lane 0's total is broadcast through
+// *slot.  Every thread of the workgroup must call it.
+__device__ __forceinline__ double cg_dot(const double* __restrict__ u,
+                                         const double* __restrict__ v, int n, double* slot) {
+    if (threadIdx.x < 64) {
+        double s = 0.0;
+        for (int p = threadIdx.x; p < n; p += 64) s += u[p] * v[p];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+        if (threadIdx.x == 0) *slot = s;
+    }
+    __syncthreads();
+    return *slot;
+}
+
+// Unpreconditioned conjugate gradients (Hestenes and Stiefel) on the
+// coarsest level from a zero iterate, in FP64: q = A p, alpha = (r.r)/(p.q),
+// x += alpha p, r -= alpha q, beta = (r'.r')/(r.r), p = r' + beta p; stops
+// before a step once ||r|| <= tol ||b|| or after max_iter steps.  Dirichlet
+// rows keep their zero start (identity rows, zero right-hand side).  The
+// results do not depend on the workgroup size.
+template <typename T>
+__device__ __forceinline__ void coarse_cg(const CoarseSolver& cs, int N, const T* __restrict__ b,
+                                          T* __restrict__ x, double* __restrict__ w) {
+    __shared__ double red[2];
+    const int n = N * N;
+    double* xs = w;
+    double* r = xs + n;
+    double* q = r + n;
+    double* p = q + n + (N + 1);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const double bi = (double)b[i];
+        xs[i] = 0.0;
+        r[i] = bi;
+        p[i] = bi;
+    }
+    for (int e = threadIdx.x; e < N + 1; e += blockDim.x) p[-N - 1 + e] = p[n + e] = 0.0;
+    __syncthreads();
+    double rr = cg_dot(r, r, n, &red[0]);
+    const double stop = cs.tol * sqrt(rr);
+    for (int k = 0; k < cs.max_iter && sqrt(rr) > stop; ++k) {
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            double acc = 0.0;
+#pragma unroll
+            for (int kb = 0; kb < 9; ++kb)
+                acc = fma(cs.bands[kb * cs.bs + i], p[i + (kb / 3 - 1) * N + (kb % 3 - 1)], acc);
+            q[i] = acc;
+        }
+        __syncthreads();
+        const double alpha = rr / cg_dot(p, q, n, &red[1]);
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            xs[i] += alpha * p[i];
+            r[i] -= alpha * q[i];
+        }
+        __syncthreads();
+        const double rr_new = cg_dot(r, r, n, &red[0]);
+        const double beta = rr_new / rr;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = r[i] + beta * p[i];
+        __syncthreads();
+        rr = rr_new;
+    }
+    for (int i = threadIdx.x; i < n; i += blockDim.x) x[i] = (T)xs[i];
+}
+
+// The coarsest solve by the configured method, one workgroup; x complete
+// for every thread on return.
+template <typename T>
+__device__ __forceinline__ void coarse_block(const CoarseSolver& cs, int Nc, const T* b, T* x) {
+    __shared__ double w[COARSE_LDS];
+    __syncthreads();
+    if (cs.cg)
+        coarse_cg<T>(cs, Nc, b, x, w);
+    else
+        coarse_cholesky<T>(cs, Nc, b, x, w);
     __syncthreads();
 }
 

@@ -412,11 +412,9 @@ struct TailLevel {
 template <typename T>
 struct TailLevels {
     TailLevel<T> lv[TAIL_MAX + 1];  // index = level
-    const double* chol;
-    int m;
+    CoarseSolver cs;                // coarsest solve; cs.dmask: the Dirichlet sides
     int top;  // highest level of the tail; entered with a zero iterate
     int Lc;
-    int dmask;  // Dirichlet sides
 };
 
 // LDS image of level l: 9 bands (band-major, stride n), then x with N+1
@@ -503,12 +501,12 @@ __device__ void tail_cycle(const TailLevels<T>& tl, T omega) {
         __syncthreads();
         const TailLds<T> c(lds, tl.Lc, l - 1);
         for (int q = threadIdx.x; q < c.n; q += TAIL_THREADS)
-            restrict_elem<T>(v.N, v.t, c.b, q % c.N, q / c.N, tl.dmask);
+            restrict_elem<T>(v.N, v.t, c.b, q % c.N, q / c.N, tl.cs.dmask);
         __syncthreads();
     }
     {
         const TailLds<T> c(lds, tl.Lc, tl.Lc);
-        coarse_block<T>(tl.chol, tl.m, c.N, c.b, c.x, tl.dmask);
+        coarse_block<T>(tl.cs, c.N, c.b, c.x);
     }
     for (int l = tl.Lc + 1; l <= tl.top; ++l) {
         const TailLds<T> v(lds, tl.Lc, l);

@@ -124,9 +124,9 @@ hipError_t launch_reduce(double* partials, int64_t np, double* scal, int slot, d
 }
 
 template <typename T>
-__global__ void k_coarse(const double* __restrict__ chol, int m, int Nc,
-                         const T* __restrict__ b, T* __restrict__ x, int dmask) {
-    dev::coarse_block(chol, m, Nc, b, x, dmask);
+__global__ void k_coarse(dev::CoarseSolver cs, int Nc, const T* __restrict__ b,
+                         T* __restrict__ x) {
+    dev::coarse_block<T>(cs, Nc, b, x);
 }
 
 // Fused pre-smoothing pass: one (strip, chunk) tile per workgroup of BT
@@ -701,8 +701,8 @@ hipError_t launch_post(const Level& lv, const T* bands, const T* x, const T* xc,
 }
 
 template <typename T>
-hipError_t launch_tail(const Level* lv, int top, int Lc, const double* chol, int m, int dmask,
-                       T omega, hipStream_t st) {
+hipError_t launch_tail(const Level* lv, int top, int Lc, const dev::CoarseSolver& cs, T omega,
+                       hipStream_t st) {
     dev::TailLevels<T> tl{};
     for (int l = Lc; l <= top; ++l) {
         dev::TailLevel<T>& d = tl.lv[l];
@@ -715,11 +715,9 @@ hipError_t launch_tail(const Level* lv, int top, int Lc, const double* chol, int
         d.n = v.n;
         d.N = v.N;
     }
-    tl.chol = chol;
-    tl.m = m;
+    tl.cs = cs;
     tl.top = top;
     tl.Lc = Lc;
-    tl.dmask = dmask;
     hipLaunchKernelGGL(k_tail<T>, dim3(1), dim3(dev::TAIL_THREADS), 0, st, tl, omega);
     return hipGetLastError();
 }
@@ -741,9 +739,8 @@ hipError_t launch_prolong(int Nf, const T* x_c, T* x_f, hipStream_t st) {
 }
 
 template <typename T>
-hipError_t launch_coarse(const double* chol, int m, int Nc, const T* b, T* x, int dmask,
-                         hipStream_t st) {
-    hipLaunchKernelGGL(k_coarse<T>, dim3(1), dim3(64), 0, st, chol, m, Nc, b, x, dmask);
+hipError_t launch_coarse(const dev::CoarseSolver& cs, int Nc, const T* b, T* x, hipStream_t st) {
+    hipLaunchKernelGGL(k_coarse<T>, dim3(1), dim3(64), 0, st, cs, Nc, b, x);
     return hipGetLastError();
 }
 
@@ -792,7 +789,7 @@ hipError_t launch_update(double* x, const float* c32, int64_t n, const double* s
                                               hipStream_t);                                   \
     template hipError_t launch_restrict<T>(int, const T*, T*, int, hipStream_t);              \
     template hipError_t launch_prolong<T>(int, const T*, T*, hipStream_t);                    \
-    template hipError_t launch_coarse<T>(const double*, int, int, const T*, T*, int,          \
+    template hipError_t launch_coarse<T>(const dev::CoarseSolver&, int, const T*, T*,         \
                                          hipStream_t);                                        \
     template hipError_t launch_copy<T>(const T*, T*, int64_t, hipStream_t);                   \
     template hipError_t launch_norm<T>(const T*, int64_t, double*, double*, int, double*,     \
@@ -802,7 +799,7 @@ hipError_t launch_update(double* x, const float* c32, int64_t n, const double* s
                                       T*, int, hipStream_t);                                    \
     template hipError_t launch_post<T>(const Level&, const T*, const T*, const T*, const T*, T, \
                                        T*, double*, double*, int, double*, hipStream_t);      \
-    template hipError_t launch_tail<T>(const Level*, int, int, const double*, int, int, T,     \
+    template hipError_t launch_tail<T>(const Level*, int, int, const dev::CoarseSolver&, T,    \
                                        hipStream_t);
 
 MG_INSTANTIATE(float)

@@ -11,6 +11,7 @@
 #include <string>
 #include <vector>
 
+#include "device_ops.h"
 #include "mgfem.h"
 
 namespace mg {
@@ -77,6 +78,9 @@ struct mg_hierarchy {
     double* host_scal = nullptr;   // pinned mirror of scal
     double* chol = nullptr;        // m x m Cholesky factor of the coarse unknowns' block
     int m = 0;                     // coarse unknowns (nodes off the Dirichlet sides)
+    int coarse_cg = 0;             // coarsest solve: 1 conjugate gradients, 0 Cholesky
+    double coarse_tol = 1e-10;     // CG stop: ||r|| <= coarse_tol ||b||
+    int coarse_max_iter = 200;     // CG step limit
     int* flag = nullptr;           // device status flag of the coarse factorisation
     bool assembled = false;
     GraphCache* graphs = nullptr;
@@ -86,6 +90,9 @@ namespace mg {
 
 // Scalar slots in hierarchy::scal (sum of squares at s, norm at s+1).
 enum : int { SC_B = 0, SC_R64 = 2, SC_R32 = 4, SC_D32 = 6, SC_USER = 8 };
+
+// How the hierarchy's coarsest level is solved.
+dev::CoarseSolver coarse_solver(const mg_hierarchy* h);
 
 // ---------------------------------------------------------------- kernels
 // All launchers enqueue on `st` and return the HIP launch error.
@@ -124,8 +131,7 @@ hipError_t launch_restrict(int Nf, const T* d_f, T* b_c, int dmask, hipStream_t 
 template <typename T>
 hipError_t launch_prolong(int Nf, const T* x_c, T* x_f, hipStream_t st);
 template <typename T>
-hipError_t launch_coarse(const double* chol, int m, int Nc, const T* b, T* x, int dmask,
-                         hipStream_t st);
+hipError_t launch_coarse(const dev::CoarseSolver& cs, int Nc, const T* b, T* x, hipStream_t st);
 template <typename T>
 hipError_t launch_copy(const T* src, T* dst, int64_t n, hipStream_t st);
 // Sum of squares of v (accumulated in FP64) into scal[slot], norm into
@@ -156,8 +162,8 @@ hipError_t launch_post(const Level& lv, const T* bands, const T* x, const T* xc,
 // The V(2,2) sub-cycle over levels top..Lc (top <= tail_max_level(), entered
 // with a zero iterate on level top) in one workgroup.  lv is indexed by level.
 template <typename T>
-hipError_t launch_tail(const Level* lv, int top, int Lc, const double* chol, int m, int dmask,
-                       T omega, hipStream_t st);
+hipError_t launch_tail(const Level* lv, int top, int Lc, const dev::CoarseSolver& cs, T omega,
+                       hipStream_t st);
 int tail_max_level();
 // Tiling of the fused passes on a level of N nodes per side: workgroup
 // width, chunk height for a pass over `count` problems, geometry of a
@@ -165,7 +171,7 @@ int tail_max_level();
 // partials any width gives.
 namespace dev {
 struct FusedGeom;
-}
+}  // namespace dev
 int fused_bt(int N);
 int fused_rh(int N, int bt, int64_t count);
 dev::FusedGeom single_geom(int N);

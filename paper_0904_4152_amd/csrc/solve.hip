@@ -67,7 +67,7 @@ hipError_t enqueue_vcycle(mg_hierarchy* h, int l, T* x, const T* b, bool x_zero,
     const double s = sizeof(T), n = (double)lv.n;
     const T om = (T)omega;
     if (l == h->Lc) {
-        MG_TRY(launch_coarse<T>(h->chol, h->m, lv.N, b, x, h->dmask, q.st));
+        MG_TRY(launch_coarse<T>(coarse_solver(h), lv.N, b, x, q.st));
         q.bytes += 2 * s * n;
         return hipSuccess;
     }
@@ -132,7 +132,7 @@ hipError_t enqueue_vcycle_fused(mg_hierarchy* h, int l, T* x, const T* b, bool x
     const T om = (T)omega;
     const T* bands = LV<T>::bands(lv);
     if (l == h->Lc) {
-        MG_TRY(launch_coarse<T>(h->chol, h->m, lv.N, b, x, h->dmask, q.st));
+        MG_TRY(launch_coarse<T>(coarse_solver(h), lv.N, b, x, q.st));
         q.bytes += 2 * s * n;
         if (partials) {
             MG_TRY(launch_defect<T>(lv, bands, b, x, nullptr, partials, scal, slot, host, q.st));
@@ -146,7 +146,7 @@ hipError_t enqueue_vcycle_fused(mg_hierarchy* h, int l, T* x, const T* b, bool x
     q.bytes += (x_zero ? 11 : 12) * s * n + s * (double)lc.n;
     if (l - 1 <= tail_max_level()) {
         // every coarser level in one workgroup; same bytes as the unfused cycle there
-        MG_TRY(launch_tail<T>(h->lv, l - 1, h->Lc, h->chol, h->m, h->dmask, om, q.st));
+        MG_TRY(launch_tail<T>(h->lv, l - 1, h->Lc, coarse_solver(h), om, q.st));
         for (int k = h->Lc + 1; k < l; ++k) q.bytes += 84.0 * s * (double)h->lv[k].n;
     } else {
         MG_TRY(enqueue_vcycle_fused<T>(h, l - 1, LV<T>::x(lc), LV<T>::b(lc), true, omega, q,
