@@ -87,6 +87,7 @@ typedef struct {
     int inner_max_cycles;    /* mixed: cap on FP32 cycles per outer step (8) */
     int fixed_cycles;        /* > 0: run exactly this many cycles / outer steps */
     int use_graph;           /* 1: replay captured HIP graphs for the cycles (1) */
+    int krylov;              /* 1: CG preconditioned by one V-cycle (0) */
 } mg_solve_opts;
 
 typedef struct {
@@ -102,7 +103,7 @@ typedef struct {
     double queue_seconds;     /* server: submission to admission */
 } mg_stats;
 
-/* Defaults: 2, 2, 0.7, 1e-8, 100, FP64, 1e-2, 8, 0, 1. */
+/* Defaults: 2, 2, 0.7, 1e-8, 100, FP64, 1e-2, 8, 0, 1, 0. */
 void mg_default_opts(mg_solve_opts* opts);
 const char* mg_last_error(void);
 const char* mg_status_string(mg_status s);
@@ -189,8 +190,16 @@ mg_status mg_rhs_uniform(const mg_hierarchy* h, uint64_t seed, double* dev_b, vo
  * FP64 defect d = b - A x and norm s, d32 = float(d / s), FP32 V-cycles on
  * A32 c = d32 from c = 0 until the FP32 residual drops by inner_reduction
  * (at most inner_max_cycles), x += s * double(c); the coarsest solve is
- * always FP64.  Returns after the result is in dev_x (synchronises stream).
- * Not thread safe per hierarchy.  stats may be NULL. */
+ * always FP64.
+ * krylov = 1: conjugate gradients preconditioned by one V(nu_pre, nu_post)
+ * cycle from a zero iterate (Sec. 4.1: a solver plugged into another as its
+ * preconditioner), in FP64; the cycle is FP64, or with MG_PREC_MIXED an FP32
+ * cycle on r / ||r|| scaled back by ||r||.  Stops once the recurrence
+ * residual ||r|| <= rel_tol ||b||; stats.cycles counts CG steps (one cycle
+ * each), res_hist the recurrence residuals, rel_res the true residual at
+ * exit; inner_reduction and inner_max_cycles are unused.
+ * Returns after the result is in dev_x (synchronises stream).  Not thread
+ * safe per hierarchy.  stats may be NULL. */
 mg_status mg_solve(mg_hierarchy* h, const double* dev_b, double* dev_x,
                    const mg_solve_opts* opts, void* stream, mg_stats* stats);
 
@@ -203,7 +212,7 @@ mg_status mg_solve(mg_hierarchy* h, const double* dev_b, double* dev_x,
  * device.  A problem's arithmetic does not depend on the other problems in
  * the batch (its result equals a batch of one bit for bit).  opts: NULL
  * (defaults, mixed) or an array of count entries; precision must be
- * MG_PREC_MIXED and nu_pre/nu_post must agree.  b[p], x[p]: device vectors
+ * MG_PREC_MIXED, krylov 0, and nu_pre/nu_post must agree.  b[p], x[p]: device vectors
  * of that problem's finest n; x is in/out.  stats: NULL or count entries.
  * Synchronous.  Returns the first non-OK per-problem status, if any.
  * The batch machinery (device descriptors of the problems, work lists and
@@ -227,7 +236,8 @@ mg_status mg_solve_batch(mg_hierarchy* const* hs, const double* const* b, double
  * graph-replayed iteration at a time (continuous batching).  A request whose
  * hierarchy cannot fit even on an idle server finishes with MG_ERR_NOMEM.
  * opts (nullable): smoothing, omega and inner-loop options shared by all
- * requests.  Thread safe. */
+ * requests (precision and krylov are forced to MG_PREC_MIXED and 0).
+ * Thread safe. */
 typedef struct {
     uint64_t completed;
     size_t queued;

@@ -30,7 +30,8 @@ _i64 = ctypes.c_int64
 class SolveOpts(ctypes.Structure):
     _fields_ = [("nu_pre", _i), ("nu_post", _i), ("omega", _d), ("rel_tol", _d),
                 ("max_cycles", _i), ("precision", _i), ("inner_reduction", _d),
-                ("inner_max_cycles", _i), ("fixed_cycles", _i), ("use_graph", _i)]
+                ("inner_max_cycles", _i), ("fixed_cycles", _i), ("use_graph", _i),
+                ("krylov", _i)]
 
 
 class Stats(ctypes.Structure):

@@ -50,7 +50,10 @@ static void hierarchy_arrays(int L, int Lc, std::vector<size_t>& sizes) {
         sizes.push_back(9 * bs * sizeof(double));
         sizes.push_back(9 * bs * sizeof(float));
         for (int v = 0; v < 3; ++v) sizes.push_back(vl * sizeof(double));
-        for (int v = 0; v < 3; ++v) sizes.push_back(vl * sizeof(float));
+        // x32 and b32 back to back: together one FP64 vector (the Krylov
+        // solver's z / q, which is never live with them)
+        sizes.push_back(2 * vl * sizeof(float));
+        sizes.push_back(vl * sizeof(float));
     }
     sizes.push_back(vec_len(nL) * sizeof(double));                    // d64
     sizes.push_back(partials_len(L) * sizeof(double));                  // partials
@@ -124,6 +127,7 @@ void mg_default_opts(mg_solve_opts* o) {
     o->inner_max_cycles = 8;
     o->fixed_cycles = 0;
     o->use_graph = 1;
+    o->krylov = 0;
 }
 
 const char* mg_last_error(void) { return g_last_error.c_str(); }
@@ -260,7 +264,7 @@ mg_status mg_hierarchy_create_bc(mg_context* ctx, int L, int Lc, double jitter, 
         lv.b64 = (double*)ptrs[a++];
         lv.t64 = (double*)ptrs[a++];
         lv.x32 = (float*)ptrs[a++];
-        lv.b32 = (float*)ptrs[a++];
+        lv.b32 = lv.x32 + vec_len(lv.n);
         lv.t32 = (float*)ptrs[a++];
     }
     h->d64 = (double*)ptrs[a++];

@@ -1090,6 +1090,8 @@ extern "C" mg_status mg_solve_batch(mg_hierarchy* const* hs, const double* const
             return fail(MG_ERR_INVALID, "b, x must be distinct 16-byte aligned device pointers");
         if (o.precision != MG_PREC_MIXED)
             return fail(MG_ERR_INVALID, "the batched solver runs the mixed-precision scheme");
+        if (o.krylov)
+            return fail(MG_ERR_INVALID, "the batched solver runs multigrid defect correction");
         if (o.nu_pre != o0.nu_pre || o.nu_post != o0.nu_post)
             return fail(MG_ERR_INVALID, "smoothing counts must agree across the batch");
         if (o.nu_pre < 0 || o.nu_post < 0 || o.nu_pre + o.nu_post == 0 || o.nu_pre > 16 ||

@@ -499,6 +499,87 @@ __global__ __launch_bounds__(BLOCK) void k_update(double* __restrict__ x,
     x[p] += scal[slot + 1] * (double)c[p];
 }
 
+// ---------------------------------------------------------------- Krylov
+// Vector kernels of the preconditioned CG solver.  A preconditioned vector
+// z is FP64, or an FP32 cycle result c with z = s double(c), s =
+// scal[zslot + 1] (zslot >= 0).
+template <typename TZ>
+__device__ __forceinline__ double z_value(const TZ* __restrict__ z, int64_t p, double s) {
+    return s * (double)z[p];
+}
+template <>
+__device__ __forceinline__ double z_value<double>(const double* __restrict__ z, int64_t p,
+                                                  double) {
+    return z[p];
+}
+
+// Partial sums of u . z per norm tile.
+template <typename TZ>
+__global__ __launch_bounds__(BLOCK) void k_dot(const double* __restrict__ u,
+                                               const TZ* __restrict__ z, int64_t n,
+                                               const double* __restrict__ scal, int zslot,
+                                               double* __restrict__ partials, int64_t nblk) {
+    const int64_t lb = xcd_block(nblk);
+    if (lb < 0) return;
+    const double s = zslot >= 0 ? scal[zslot + 1] : 1.0;
+    double acc = 0.0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int64_t p = lb * (int64_t)dev::NORM_TILE + (int64_t)e * BLOCK + threadIdx.x;
+        if (p < n) acc += u[p] * z_value(z, p, s);
+    }
+    const double t = dev::block_sum(acc);
+    if (threadIdx.x == 0) partials[lb] = t;
+}
+
+// p = z + beta p, beta = scal[s_new] / scal[s_old] (0 for the first
+// direction, where scal[s_old] is +inf).
+template <typename TZ>
+__global__ __launch_bounds__(BLOCK) void k_pcg_dir(double* __restrict__ pv,
+                                                   const TZ* __restrict__ z, int64_t n,
+                                                   const double* __restrict__ scal, int zslot,
+                                                   int s_new, int s_old) {
+    const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (p >= n) return;
+    const double s = zslot >= 0 ? scal[zslot + 1] : 1.0;
+    const double beta = scal[s_new] / scal[s_old];
+    pv[p] = z_value(z, p, s) + beta * pv[p];
+}
+
+// alpha = scal[s_num] / scal[s_den]; x += alpha p; r -= alpha q; partial
+// sums of the new r^2 per norm tile.
+__global__ __launch_bounds__(BLOCK) void k_pcg_step(double* __restrict__ x, double* __restrict__ r,
+                                                    const double* __restrict__ pv,
+                                                    const double* __restrict__ q, int64_t n,
+                                                    const double* __restrict__ scal, int s_num,
+                                                    int s_den, double* __restrict__ partials,
+                                                    int64_t nblk) {
+    const int64_t lb = xcd_block(nblk);
+    if (lb < 0) return;
+    const double alpha = scal[s_num] / scal[s_den];
+    double acc = 0.0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int64_t p = lb * (int64_t)dev::NORM_TILE + (int64_t)e * BLOCK + threadIdx.x;
+        if (p < n) {
+            x[p] += alpha * pv[p];
+            const double rn = r[p] - alpha * q[p];
+            r[p] = rn;
+            acc += rn * rn;
+        }
+    }
+    const double t = dev::block_sum(acc);
+    if (threadIdx.x == 0) partials[lb] = t;
+}
+
+// scal[to], scal[to + 1] = scal[from], scal[from + 1] (one thread).
+__global__ void k_scalar_copy(double* __restrict__ scal, int from, int to) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        scal[to] = scal[from];
+        scal[to + 1] = scal[from + 1];
+    }
+}
+
 inline unsigned blocks1d(int64_t n) { return (unsigned)((n + BLOCK - 1) / BLOCK); }
 
 }  // namespace
@@ -776,6 +857,49 @@ hipError_t launch_cast_scaled(const double* d64, float* d32, int64_t n, const do
 hipError_t launch_update(double* x, const float* c32, int64_t n, const double* scal, int slot,
                          hipStream_t st) {
     hipLaunchKernelGGL(k_update, dim3(blocks1d(n)), dim3(BLOCK), 0, st, x, c32, n, scal, slot);
+    return hipGetLastError();
+}
+
+template <typename TZ>
+hipError_t launch_dot(const double* u, const TZ* z, int64_t n, const double* zscal, int zslot,
+                      double* partials, double* scal, int slot, hipStream_t st) {
+    const int64_t nb = norm_blocks(n);
+    hipLaunchKernelGGL(k_dot<TZ>, dim3(grid8(nb)), dim3(BLOCK), 0, st, u, z, n, zscal, zslot,
+                       partials, nb);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_reduce(partials, nb, scal, slot, nullptr, st);
+}
+template hipError_t launch_dot<double>(const double*, const double*, int64_t, const double*, int,
+                                       double*, double*, int, hipStream_t);
+template hipError_t launch_dot<float>(const double*, const float*, int64_t, const double*, int,
+                                      double*, double*, int, hipStream_t);
+
+template <typename TZ>
+hipError_t launch_pcg_dir(double* p, const TZ* z, int64_t n, const double* scal, int zslot,
+                          int s_new, int s_old, hipStream_t st) {
+    hipLaunchKernelGGL(k_pcg_dir<TZ>, dim3(blocks1d(n)), dim3(BLOCK), 0, st, p, z, n, scal, zslot,
+                       s_new, s_old);
+    return hipGetLastError();
+}
+template hipError_t launch_pcg_dir<double>(double*, const double*, int64_t, const double*, int,
+                                           int, int, hipStream_t);
+template hipError_t launch_pcg_dir<float>(double*, const float*, int64_t, const double*, int,
+                                          int, int, hipStream_t);
+
+hipError_t launch_pcg_step(double* x, double* r, const double* p, const double* q, int64_t n,
+                           double* scal, int s_num, int s_den, double* partials, int slot,
+                           double* host, hipStream_t st) {
+    const int64_t nb = norm_blocks(n);
+    hipLaunchKernelGGL(k_pcg_step, dim3(grid8(nb)), dim3(BLOCK), 0, st, x, r, p, q, n, scal,
+                       s_num, s_den, partials, nb);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_reduce(partials, nb, scal, slot, host, st);
+}
+
+hipError_t launch_scalar_copy(double* scal, int from, int to, hipStream_t st) {
+    hipLaunchKernelGGL(k_scalar_copy, dim3(1), dim3(64), 0, st, scal, from, to);
     return hipGetLastError();
 }
 

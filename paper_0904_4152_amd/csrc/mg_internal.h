@@ -89,7 +89,18 @@ struct mg_hierarchy {
 namespace mg {
 
 // Scalar slots in hierarchy::scal (sum of squares at s, norm at s+1).
-enum : int { SC_B = 0, SC_R64 = 2, SC_R32 = 4, SC_D32 = 6, SC_USER = 8 };
+enum : int {
+    SC_B = 0,
+    SC_R64 = 2,
+    SC_R32 = 4,
+    SC_D32 = 6,
+    SC_USER = 8,
+    // preconditioned CG: p.q, r.z (current and previous), ||r||
+    SC_PQ = 10,
+    SC_RZ = 12,
+    SC_RZ_OLD = 14,
+    SC_RR = 16
+};
 
 // How the hierarchy's coarsest level is solved.
 dev::CoarseSolver coarse_solver(const mg_hierarchy* h);
@@ -147,6 +158,22 @@ hipError_t launch_cast_scaled(const double* d64, float* d32, int64_t n, const do
 // x += s * double(c32), s = scal[slot + 1].
 hipError_t launch_update(double* x, const float* c32, int64_t n, const double* scal, int slot,
                          hipStream_t st);
+
+// Preconditioned CG vector operations.  z is FP64, or FP32 scaled by
+// zscal[zslot + 1] (zslot >= 0).  u . z into scal[slot]; p = z + beta p with
+// beta = scal[s_new] / scal[s_old]; alpha = scal[s_num] / scal[s_den],
+// x += alpha p, r -= alpha q and ||r||^2 into scal[slot] (norm at slot + 1,
+// mirrored to host when not null); scal[to..to+1] = scal[from..from+1].
+template <typename TZ>
+hipError_t launch_dot(const double* u, const TZ* z, int64_t n, const double* zscal, int zslot,
+                      double* partials, double* scal, int slot, hipStream_t st);
+template <typename TZ>
+hipError_t launch_pcg_dir(double* p, const TZ* z, int64_t n, const double* scal, int zslot,
+                          int s_new, int s_old, hipStream_t st);
+hipError_t launch_pcg_step(double* x, double* r, const double* p, const double* q, int64_t n,
+                           double* scal, int s_num, int s_den, double* partials, int slot,
+                           double* host, hipStream_t st);
+hipError_t launch_scalar_copy(double* scal, int from, int to, hipStream_t st);
 
 // Fused smoothing passes of a V(2,2) level (see fused_ops.h): pre = two
 // sweeps (x_zero: the first from a zero iterate) + defect + restriction into

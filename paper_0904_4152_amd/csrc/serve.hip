@@ -297,6 +297,7 @@ mg_status mg_server_create(mg_context* ctx, int slots, size_t budget, int max_le
     else
         mg_default_opts(&s->opts);
     s->opts.precision = MG_PREC_MIXED;
+    s->opts.krylov = 0;
     if (mg_status st = s->eng.init(ctx->device, slots, max_level, coarse_level, s->opts.nu_pre,
                                    s->opts.nu_post)) {
         delete s;

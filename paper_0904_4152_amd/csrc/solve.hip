@@ -13,7 +13,8 @@
 #include "solve.h"
 
 struct GraphEntry {
-    int kind;  // 0: FP64 cycle + residual norm; 1: FP32 inner cycle + residual norm
+    int kind;  // 0: FP64 cycle + residual norm; 1: FP32 inner cycle + residual norm;
+               // 2, 3: preconditioned CG step with an FP64 / FP32 cycle
     int nu_pre, nu_post;
     double omega;
     bool x_zero;
@@ -163,13 +164,61 @@ template hipError_t enqueue_vcycle_fused<double>(mg_hierarchy*, int, double*, co
 template hipError_t enqueue_vcycle_fused<float>(mg_hierarchy*, int, float*, const float*, bool,
                                                 double, Enq&, double*, double*, int, double*);
 
+// One step of CG preconditioned by one V-cycle from zero (Sec. 4.1: a
+// solver as another's preconditioner; the cycle of Sec. 6.2), on the finest
+// level's vectors: x in x64, r in d64, p in b64 (the right-hand side copy is
+// not needed once r0 is formed), and z / q sharing the FP32 pair x32|b32
+// (never live together, nor with the FP32 cycle's own use of the pair):
+//   z = M r (kind 2: FP64 cycle; kind 3: FP32 cycle on r / ||r||, z =
+//   ||r|| c32); rz = r.z; p = z + (rz / rz_old) p; rz_old = rz; q = A p;
+//   alpha = rz / p.q; x += alpha p; r -= alpha q; ||r|| to the host mirror.
+// Before the first step scal[SC_RZ_OLD] is +inf, so the first p is z.
+static hipError_t enqueue_pcg_step(mg_hierarchy* h, bool mixed, int nu_pre, int nu_post,
+                                   double omega, Enq& q) {
+    Level& F = h->lv[h->L];
+    const int64_t n = F.n;
+    const double dn = (double)n;
+    double* r = h->d64;
+    double* p = F.b64;
+    double* zq = reinterpret_cast<double*>(F.x32);
+    const bool fused = nu_pre == 2 && nu_post == 2;
+    if (!mixed) {
+        if (fused)
+            MG_TRY(enqueue_vcycle_fused<double>(h, h->L, zq, r, true, omega, q, nullptr, nullptr,
+                                                0, nullptr));
+        else
+            MG_TRY(enqueue_vcycle<double>(h, h->L, zq, r, true, nu_pre, nu_post, omega, q));
+        MG_TRY(launch_dot<double>(r, zq, n, h->scal, -1, h->partials, h->scal, SC_RZ, q.st));
+        MG_TRY(launch_pcg_dir<double>(p, zq, n, h->scal, -1, SC_RZ, SC_RZ_OLD, q.st));
+        q.bytes += (16.0 + 24.0) * dn;
+    } else {
+        MG_TRY(launch_cast_scaled(r, F.b32, n, h->scal, SC_RR, q.st));
+        if (fused)
+            MG_TRY(enqueue_vcycle_fused<float>(h, h->L, F.x32, F.b32, true, omega, q, nullptr,
+                                               nullptr, 0, nullptr));
+        else
+            MG_TRY(enqueue_vcycle<float>(h, h->L, F.x32, F.b32, true, nu_pre, nu_post, omega, q));
+        MG_TRY(launch_dot<float>(r, F.x32, n, h->scal, SC_RR, h->partials, h->scal, SC_RZ, q.st));
+        MG_TRY(launch_pcg_dir<float>(p, F.x32, n, h->scal, SC_RR, SC_RZ, SC_RZ_OLD, q.st));
+        q.bytes += (12.0 + 12.0 + 20.0) * dn;
+    }
+    MG_TRY(launch_scalar_copy(h->scal, SC_RZ, SC_RZ_OLD, q.st));
+    MG_TRY(launch_spmv<double>(F, F.bands64, p, zq, q.st));
+    MG_TRY(launch_dot<double>(p, zq, n, h->scal, -1, h->partials, h->scal, SC_PQ, q.st));
+    MG_TRY(launch_pcg_step(F.x64, r, p, zq, n, h->scal, SC_RZ, SC_PQ, h->partials, SC_RR,
+                           h->host_scal, q.st));
+    q.bytes += (88.0 + 16.0 + 48.0) * dn;
+    return hipSuccess;
+}
+
 // The unit replayed per iteration: FP64 cycle + FP64 residual norm (kind 0)
 // or FP32 inner cycle + FP32 residual norm (kind 1), on the finest level's
-// own vectors.
+// own vectors, or a preconditioned CG step (kinds 2, 3).
 static hipError_t enqueue_unit(mg_hierarchy* h, int kind, int nu_pre, int nu_post, double omega,
                                bool x_zero, Enq& q) {
     Level& F = h->lv[h->L];
     const double n = (double)F.n;
+    if (kind >= 2) return enqueue_pcg_step(h, kind == 3, nu_pre, nu_post, omega, q);
     if (nu_pre == 2 && nu_post == 2) {
         if (kind == 0)
             return enqueue_vcycle_fused<double>(h, h->L, F.x64, F.b64, false, omega, q,
@@ -296,6 +345,7 @@ static mg_status validate_opts(const mg_solve_opts& o) {
         (!(o.inner_reduction >= 0.0 && o.inner_reduction < 1.0) || o.inner_max_cycles < 1))
         return fail(MG_ERR_INVALID, "inner_reduction in [0,1) and inner_max_cycles >= 1 required");
     if (o.fixed_cycles < 0) return fail(MG_ERR_INVALID, "fixed_cycles must be >= 0");
+    if (o.krylov != 0 && o.krylov != 1) return fail(MG_ERR_INVALID, "krylov must be 0 or 1");
     return MG_OK;
 }
 
@@ -365,6 +415,45 @@ extern "C" mg_status mg_solve(mg_hierarchy* h, const double* dev_b, double* dev_
         result = fail(MG_ERR_NUMERIC, "right-hand side contains NaN or Inf");
     } else if (bn == 0.0) {
         MG_HIPS(launch_fill<double>(F.x64, n, 0.0, q.st));
+    } else if (o.krylov) {
+        // r0 = b - A x0 and its norm; the first direction is z (beta = 0)
+        double r = 0.0;
+        arm_scalar(h, SC_RR);
+        MG_HIPS(launch_defect<double>(F, F.bands64, F.b64, F.x64, h->d64, h->partials, h->scal,
+                                      SC_RR, h->host_scal, q.st));
+        MG_HIPS(launch_fill<double>(h->scal + SC_RZ_OLD, 1, INFINITY, q.st));
+        q.bytes += 12.0 * 8 * n;
+        MG_HIPS(read_scalar(h, SC_RR, q.st, &r));
+        st.rel_res = r / bn;
+        const int kind = o.precision == MG_PREC_FP64 ? 2 : 3;
+        for (int k = 1;; ++k) {
+            if (o.fixed_cycles > 0) {
+                if (k > o.fixed_cycles) break;
+            } else {
+                if (r <= o.rel_tol * bn) break;
+                if (k > o.max_cycles) {
+                    result = fail(MG_ERR_NOCONV, "no convergence within max_cycles");
+                    break;
+                }
+            }
+            arm_scalar(h, SC_RR);
+            MG_HIPS(run_unit(h, kind, o, false, graphs, q));
+            MG_HIPS(read_scalar(h, SC_RR, q.st, &r));
+            st.cycles = k;
+            if (st.n_hist < MG_HIST) st.res_hist[st.n_hist++] = r / bn;
+            if (!std::isfinite(r) || r > 1e3 * bn) {
+                result = fail(MG_ERR_NUMERIC, "residual diverged or became NaN");
+                break;
+            }
+        }
+        // the true residual at exit, from the caller's b (the copy holds p)
+        double rt = 0.0;
+        arm_scalar(h, SC_R64);
+        MG_HIPS(launch_defect<double>(F, F.bands64, dev_b, F.x64, nullptr, h->partials, h->scal,
+                                      SC_R64, h->host_scal, q.st));
+        q.bytes += 11.0 * 8 * n;
+        MG_HIPS(read_scalar(h, SC_R64, q.st, &rt));
+        st.rel_res = rt / bn;
     } else if (o.precision == MG_PREC_FP64) {
         double r = 0.0;
         arm_scalar(h, SC_R64);
