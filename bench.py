@@ -320,7 +320,30 @@ def main():
                  "alg_GB_s": st_f.alg_bytes / t_fp64 / 1e9},
         "mixed_speedup_vs_fp64": t_fp64 / t_mixed,
     }
+
+    def timed(hh, o, reps=3):
+        st = solve(hh, b, x, o)  # warm the graphs
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            st = solve(hh, b, x, o)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        return {"ms": dt * 1e3, "steps": st.cycles, "outer_steps": st.outer_steps,
+                "rel_res": st.rel_res, "alg_GB_s": st.alg_bytes / dt / 1e9}
+
+    # CG preconditioned by one cycle (FP64 cycle; FP32 cycle on r / ||r||)
+    out["L12"]["pcg_fp64"] = timed(h, mg.default_opts(precision=mg.MG_PREC_FP64, rel_tol=1e-8,
+                                                      krylov=1))
+    out["L12"]["pcg_mixed"] = timed(h, mg.default_opts(precision=mg.MG_PREC_MIXED,
+                                                       rel_tol=1e-8, krylov=1))
     h.close()
+    torch.cuda.empty_cache()
+    # coarse grid on level 4 (17 x 17) solved by CG, as in the paper's setup
+    h4 = mg.Hierarchy(ctx, L, coarse_level=4, jitter=jit, seed=gseed)
+    h4.set_coarse_solver(mg.MG_COARSE_CG, tol=1e-10, max_iter=200)
+    out["L12"]["mixed_cg_coarse_L4"] = timed(h4, mixed)
+    h4.close()
     del b, x
     torch.cuda.empty_cache()
 
