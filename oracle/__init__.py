@@ -95,6 +95,7 @@ def lib():
                                     ctypes.POINTER(OrStats)]
         L.or_solve_mixed_emulated.argtypes = [ctypes.c_void_p, _dp, _dp,
                                               ctypes.POINTER(OrOpts), ctypes.POINTER(OrStats)]
+        L.or_axpy.argtypes = [ctypes.c_size_t, ctypes.c_double, _dp, _dp]
         L.or_dot.argtypes = [ctypes.c_size_t, _dp, _dp]
         L.or_dot.restype = ctypes.c_double
         L.or_cg.argtypes = [ctypes.c_int, _dp, _dp, _dp, ctypes.c_double, ctypes.c_int]
@@ -304,6 +305,25 @@ def cg(N, bands, b, x0=None, tol=1e-10, max_iter=200):
     k = lib().or_cg(N, _d(np.ascontiguousarray(bands, dtype=np.float64).reshape(-1)),
                     _d(np.ascontiguousarray(b, dtype=np.float64)), _d(x), tol, max_iter)
     return x, k
+
+
+def axpy(alpha, x, y):
+    """y = alpha x + y (Sec. 6.1).  FP64 inputs: FP64 arithmetic in index
+    order.  FP32 inputs: alpha rounded to FP32, then alpha x + y evaluated
+    in FP64 (the product is exact there) and rounded once to FP32."""
+    if np.asarray(x).dtype == np.float32:
+        a32 = float(np.float32(alpha))
+        return (a32 * x.astype(np.float64) + y.astype(np.float64)).astype(np.float32)
+    out = np.array(y, dtype=np.float64, copy=True)
+    lib().or_axpy(out.size, float(alpha), _d(np.ascontiguousarray(x, dtype=np.float64)), _d(out))
+    return out
+
+
+def dot(x, y) -> float:
+    """x . y in FP64, summed in index order (FP32 inputs widened exactly)."""
+    xd = np.ascontiguousarray(x, dtype=np.float64)
+    yd = np.ascontiguousarray(y, dtype=np.float64)
+    return lib().or_dot(xd.size, _d(xd), _d(yd))
 
 
 def hist(st: OrStats):

@@ -358,6 +358,11 @@ void or_cholesky_solve(int m, const double* Lf, double* b) {
     }
 }
 
+/* y = alpha x + y (Sec. 6.1 axpy), in index order. */
+void or_axpy(size_t n, double alpha, const double* x, double* y) {
+    for (size_t p = 0; p < n; ++p) y[p] = alpha * x[p] + y[p];
+}
+
 double or_dot(size_t n, const double* u, const double* v) {
     double s = 0.0;
     for (size_t p = 0; p < n; ++p) s += u[p] * v[p];

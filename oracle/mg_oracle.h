@@ -78,6 +78,8 @@ double or_norm2(size_t n, const double* v);
 int or_cholesky(int m, double* A);
 void or_cholesky_solve(int m, const double* Lf, double* b);
 double or_dot(size_t n, const double* u, const double* v);
+/* BLAS level 1 of Sec. 6.1: y = alpha x + y; u . v and ||v|| sum in index order. */
+void or_axpy(size_t n, double alpha, const double* x, double* y);
 /* Unpreconditioned CG on one level's banded system, from the iterate in x,
  * until ||b - A x|| <= tol ||b|| (recurrence residual) or max_iter steps;
  * returns the steps taken. */

@@ -652,3 +652,38 @@ def test_pcg_reaches_tolerance_with_fewer_steps_than_cycles(orc, precond32):
         # residual history falls monotonically by at least 5x per step
         hist = [1.0] + orc.hist(sp_)
         assert all(hist[k + 1] < 0.2 * hist[k] for k in range(len(hist) - 1)), hist
+
+
+# ---------------------------------------------------------------- BLAS level 1
+
+
+def test_blas1_closed_forms(orc):
+    n = 1000
+    i = np.arange(1, n + 1, dtype=np.float64)
+    assert orc.dot(i, i) == n * (n + 1) * (2 * n + 1) / 6
+    assert orc.dot(i, np.ones(n)) == n * (n + 1) / 2
+    assert orc.norm2(np.full(n, 3.0)) == 3.0 * np.sqrt(n)
+    y = orc.axpy(2.0, i, np.ones(n))
+    np.testing.assert_array_equal(y, 2 * i + 1)
+    np.testing.assert_array_equal(orc.axpy(0.0, i, i), i)
+    y32 = orc.axpy(-1.0, i.astype(np.float32), i.astype(np.float32))
+    assert y32.dtype == np.float32 and not y32.any()
+
+
+def test_blas1_dot_against_exactly_rounded_sum(orc):
+    import math
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal(4097)
+    y = rng.standard_normal(4097)
+    exact = math.fsum(float(a) * float(b) for a, b in zip(x, y))
+    s = orc.dot(x, y)
+    # recursive summation: |error| <= gamma_n sum |x y| (products exact in fsum
+    # up to their own rounding, u each)
+    bound = (x.size + 1) * 2.0 ** -53 * float(np.sum(np.abs(x * y)))
+    assert abs(s - exact) <= bound
+    # FP32 axpy: the correctly rounded image of the FP64 value
+    x32 = x.astype(np.float32)
+    y32 = y.astype(np.float32)
+    r = orc.axpy(0.3, x32, y32)
+    ref = np.float32(0.3).astype(np.float64) * x32.astype(np.float64) + y32.astype(np.float64)
+    assert np.all(np.abs(r.astype(np.float64) - ref) <= 2.0 ** -24 * np.abs(ref))
