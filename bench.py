@@ -87,6 +87,38 @@ def time_launches(fn, iters, torch):
     return e0.elapsed_time(e1) * 1e-3 / iters
 
 
+def bench_blas1(ctx, torch, dev, sizes=None):
+    """BLAS level 1 (Sec. 6.1) over lengths from cache-resident to HBM-sized:
+    axpy (asynchronous, HIP-event timed per launch; 3 streams, 2 flops per
+    element) and dot / norm2 (synchronous calls, host wall time including the
+    result's return; 2 / 1 streams)."""
+    sizes = sizes or [1 << k for k in range(10, 29, 2)]
+    rows = []
+    for n in sizes:
+        rec = {"n": n}
+        for name, dt, es in (("saxpy", torch.float32, 4), ("daxpy", torch.float64, 8)):
+            x = torch.ones(n, dtype=dt, device=dev)
+            y = torch.ones(n, dtype=dt, device=dev)
+            iters = max(10, min(2000, (1 << 26) // n))
+            t = time_launches(lambda: ctx.axpy(1e-3, x, y), iters, torch)
+            rec[name] = {"us": t * 1e6, "GB_s": 3 * es * n / t / 1e9,
+                         "MFLOP_s": 2 * n / t / 1e6}
+            if name == "saxpy":
+                reps = max(5, min(200, (1 << 24) // n))
+                for op, fn, streams in (("sdot", lambda: ctx.dot(x, y), 2),
+                                        ("snrm2", lambda: ctx.norm2(x), 1)):
+                    fn()
+                    t0 = time.perf_counter()
+                    for _ in range(reps):
+                        fn()
+                    t = (time.perf_counter() - t0) / reps
+                    rec[op] = {"us": t * 1e6, "GB_s": streams * es * n / t / 1e9}
+            del x, y
+        rows.append(rec)
+    torch.cuda.empty_cache()
+    return rows
+
+
 def bench_batch(mg, ctx, synth, torch, dev, opts, count=256):
     """256 independent mixed solves advanced together (one persistent launch
     per V-cycle stage), against the same problems solved one after another."""
@@ -273,6 +305,8 @@ def main():
     del bc32
     del x32, y32, b32, x64, y64
     if args.only_kernels:
+        # saxpy at 2^28 elements (1 GiB per vector): the BLAS-1 reference rate
+        out["blas1"] = bench_blas1(ctx, torch, dev, sizes=[1 << 28])
         # a plain device copy of known size (1 GiB read + 1 GiB written):
         # the calibration reference for the HBM byte counters
         src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
@@ -370,6 +404,9 @@ def main():
                           "outer_steps": s.outer_steps, "rel_res": s.rel_res}
         out[name] = rec
         hh.close()
+
+    # ---------------- BLAS level 1 over lengths 2^10 .. 2^28
+    out["blas1"] = bench_blas1(ctx, torch, dev)
 
     # ---------------- batched: 256 problems, L ~ U{5..9}, jitter U[0, 0.25) h
     if not args.no_batch:

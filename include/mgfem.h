@@ -266,6 +266,28 @@ mg_status mg_server_info(mg_server* s, mg_server_info_t* info);
 /* Finish every queued and running request, then free everything. */
 mg_status mg_server_destroy(mg_server* s);
 
+/* ---- BLAS level 1 (Sec. 6.1: axpy and the other vector-vector operations,
+ * bound by memory bandwidth, as the basic architecture comparison) ----------
+ * x, y: device vectors of n elements of dtype on ctx's device, 16-byte
+ * aligned (may be NULL when n = 0), 0 <= n <= MG_BLAS_MAX_N.
+ * mg_axpy: y = alpha x + y, one fused multiply-add per element (FP32:
+ *   alpha rounded to FP32 first); x and y must not alias; asynchronous.
+ * mg_dot: x . y, mg_norm2: ||x||_2; products and sums in FP64 in one fixed
+ *   order (each thread over its elements in index order, then a fixed tree
+ *   over the workgroup, then the tiles in the library's two-stage order), so
+ *   a result depends only on the data.  Synchronous: waits for stream and
+ *   writes *host_out.  They keep a reduction scratch in the context of about
+ *   8 bytes per 1024 FP64 / 2048 FP32 elements plus 8 KiB, grown when a
+ *   longer vector needs more and charged to the context budget
+ *   (MG_ERR_NOMEM when it does not fit); calls on one context serialise. */
+#define MG_BLAS_MAX_N ((int64_t)1 << 33)
+mg_status mg_axpy(mg_context* ctx, mg_dtype dtype, int64_t n, double alpha, const void* x, void* y,
+                  void* stream);
+mg_status mg_dot(mg_context* ctx, mg_dtype dtype, int64_t n, const void* x, const void* y,
+                 double* host_out, void* stream);
+mg_status mg_norm2(mg_context* ctx, mg_dtype dtype, int64_t n, const void* x, double* host_out,
+                   void* stream);
+
 /* ---- single operators (asynchronous; for parity tests and benchmarks) -----
  * x, y, b, d: device vectors of the level's n elements in dtype. */
 /* y = A x (Sec. 4.1/4.2 banded matrix-vector product). */

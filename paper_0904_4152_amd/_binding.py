@@ -90,6 +90,9 @@ _SIGS = {
     "mg_server_next": (_i, [_vp, _d, ctypes.POINTER(_u64), _vp, ctypes.POINTER(Stats)]),
     "mg_server_info": (_i, [_vp, ctypes.POINTER(ServerInfo)]),
     "mg_server_destroy": (_i, [_vp]),
+    "mg_axpy": (_i, [_vp, _i, _i64, _d, _vp, _vp, _vp]),
+    "mg_dot": (_i, [_vp, _i, _i64, _vp, _vp, ctypes.POINTER(_d), _vp]),
+    "mg_norm2": (_i, [_vp, _i, _i64, _vp, ctypes.POINTER(_d), _vp]),
     "mg_solve_batch": (_i, [ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp), _i,
                             ctypes.POINTER(SolveOpts), _vp, ctypes.POINTER(Stats)]),
 }
@@ -177,6 +180,27 @@ class Context:
         a, b = _sz(), _sz()
         check(lib().mg_context_memory(self._h, ctypes.byref(a), ctypes.byref(b)))
         return a.value, b.value
+
+    def axpy(self, alpha: float, x, y, stream=None):
+        """y = alpha x + y on device vectors of equal length (BLAS level 1)."""
+        if x.numel() != y.numel() or x.dtype != y.dtype:
+            raise ValueError("x and y must have the same length and dtype")
+        check(lib().mg_axpy(self._h, _dt(x), x.numel(), alpha, _ptr(x), _ptr(y),
+                            _stream(stream)))
+
+    def dot(self, x, y, stream=None) -> float:
+        if x.numel() != y.numel() or x.dtype != y.dtype:
+            raise ValueError("x and y must have the same length and dtype")
+        out = _d()
+        check(lib().mg_dot(self._h, _dt(x), x.numel(), _ptr(x), _ptr(y), ctypes.byref(out),
+                           _stream(stream)))
+        return out.value
+
+    def norm2(self, x, stream=None) -> float:
+        out = _d()
+        check(lib().mg_norm2(self._h, _dt(x), x.numel(), _ptr(x), ctypes.byref(out),
+                             _stream(stream)))
+        return out.value
 
     def close(self):
         if self._h:

@@ -163,6 +163,12 @@ mg_status mg_context_create(int device, size_t budget, mg_context** out) {
 
 mg_status mg_context_destroy(mg_context* ctx) {
     if (!ctx) return fail(MG_ERR_INVALID, "null context");
+    if (ctx->blas_scratch || ctx->blas_host) {
+        (void)hipSetDevice(ctx->device);
+        (void)hipDeviceSynchronize();
+        if (ctx->blas_scratch) (void)hipFree(ctx->blas_scratch);
+        if (ctx->blas_host) (void)hipHostFree(ctx->blas_host);
+    }
     delete ctx;
     return MG_OK;
 }

@@ -103,25 +103,6 @@ __global__ __launch_bounds__(BLOCK) void k_reduce_segs(const double* __restrict_
     if (threadIdx.x == 0) segs[sg] = v;
 }
 
-// scal[slot] = sum of the np partials (the order of dev::reduce_partials),
-// scal[slot + 1] = its square root; the same into host[slot..] if not null.  Segment sums go right after the
-// partials, which the partials buffer leaves room for.
-hipError_t launch_reduce(double* partials, int64_t np, double* scal, int slot, double* host,
-                         hipStream_t st) {
-    if (np <= dev::RED_SEG) {
-        hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(BLOCK), 0, st, partials, np, scal, slot,
-                           host);
-        return hipGetLastError();
-    }
-    const int64_t ns = (np + dev::RED_SEG - 1) / dev::RED_SEG;
-    if (ns > dev::RED_MAX_SEGS) return hipErrorInvalidValue;
-    double* segs = partials + (np + 63) / 64 * 64;
-    hipLaunchKernelGGL(k_reduce_segs, dim3(ns), dim3(BLOCK), 0, st, partials, np, segs);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(BLOCK), 0, st, segs, ns, scal, slot, host);
-    return hipGetLastError();
-}
 
 template <typename T>
 __global__ void k_coarse(dev::CoarseSolver cs, int Nc, const T* __restrict__ b,
@@ -583,6 +564,26 @@ __global__ void k_scalar_copy(double* __restrict__ scal, int from, int to) {
 inline unsigned blocks1d(int64_t n) { return (unsigned)((n + BLOCK - 1) / BLOCK); }
 
 }  // namespace
+
+// scal[slot] = sum of the np partials (the order of dev::reduce_partials),
+// scal[slot + 1] = its square root; the same into host[slot..] if not null.  Segment sums go right after the
+// partials, which the partials buffer leaves room for.
+hipError_t launch_reduce(double* partials, int64_t np, double* scal, int slot, double* host,
+                         hipStream_t st) {
+    if (np <= dev::RED_SEG) {
+        hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(BLOCK), 0, st, partials, np, scal, slot,
+                           host);
+        return hipGetLastError();
+    }
+    const int64_t ns = (np + dev::RED_SEG - 1) / dev::RED_SEG;
+    if (ns > dev::RED_MAX_SEGS) return hipErrorInvalidValue;
+    double* segs = partials + (np + 63) / 64 * 64;
+    hipLaunchKernelGGL(k_reduce_segs, dim3(ns), dim3(BLOCK), 0, st, partials, np, segs);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(BLOCK), 0, st, segs, ns, scal, slot, host);
+    return hipGetLastError();
+}
 
 int64_t stencil_blocks(int64_t n, int elem_bytes) {
     const int64_t per = (int64_t)BLOCK * (16 / elem_bytes);

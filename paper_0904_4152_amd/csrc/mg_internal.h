@@ -56,6 +56,11 @@ struct mg_context {
     size_t in_use = 0;
     size_t high_water = 0;
     std::mutex mu;
+    // reduction scratch of the BLAS level-1 calls (grown on demand, charged)
+    std::mutex blas_mu;
+    double* blas_scratch = nullptr;
+    size_t blas_bytes = 0;
+    double* blas_host = nullptr;  // pinned result mirror
     // Charge `bytes` against the budget; false if it does not fit.
     bool reserve(size_t bytes);
     void release(size_t bytes);
@@ -157,6 +162,13 @@ hipError_t launch_cast_scaled(const double* d64, float* d32, int64_t n, const do
                               int slot, hipStream_t st);
 // x += s * double(c32), s = scal[slot + 1].
 hipError_t launch_update(double* x, const float* c32, int64_t n, const double* scal, int slot,
+                         hipStream_t st);
+
+// Deterministic sum of np partials (dev::reduce_partials' order; one
+// block, or segment blocks and a final block beyond dev::RED_SEG partials,
+// whose sums go right after the partials, padded to 64): scal[slot] = sum,
+// scal[slot + 1] = sqrt(sum), mirrored into host[slot..] when not null.
+hipError_t launch_reduce(double* partials, int64_t np, double* scal, int slot, double* host,
                          hipStream_t st);
 
 // Preconditioned CG vector operations.  z is FP64, or FP32 scaled by
