@@ -96,6 +96,9 @@ def lib():
         L.or_solve_mixed_emulated.argtypes = [ctypes.c_void_p, _dp, _dp,
                                               ctypes.POINTER(OrOpts), ctypes.POINTER(OrStats)]
         L.or_axpy.argtypes = [ctypes.c_size_t, ctypes.c_double, _dp, _dp]
+        L.or_band4_combine.argtypes = [ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(_dp),
+                                       ctypes.c_size_t, ctypes.POINTER(ctypes.c_int),
+                                       ctypes.POINTER(_dp), _dp, _dp, _dp]
         L.or_dot.argtypes = [ctypes.c_size_t, _dp, _dp]
         L.or_dot.restype = ctypes.c_double
         L.or_cg.argtypes = [ctypes.c_int, _dp, _dp, _dp, ctypes.c_double, ctypes.c_int]
@@ -316,6 +319,23 @@ def axpy(alpha, x, y):
         return (a32 * x.astype(np.float64) + y.astype(np.float64)).astype(np.float32)
     out = np.array(y, dtype=np.float64, copy=True)
     lib().or_axpy(out.size, float(alpha), _d(np.ascontiguousarray(x, dtype=np.float64)), _d(out))
+    return out
+
+
+def band4_combine(bands, offsets, vs, u, s=None):
+    """u + sum_i M_i v_i (+ s) for four-band M_i: bands[i] has shape (4, n),
+    offsets[i] four ints, vs[i] a vector of n (Sec. 2.2 prediction step)."""
+    n = len(u)
+    m = len(bands)
+    bs_ = [np.ascontiguousarray(b, dtype=np.float64).reshape(-1) for b in bands]
+    vs_ = [np.ascontiguousarray(v, dtype=np.float64) for v in vs]
+    off = (ctypes.c_int * (4 * m))(*[int(o) for row in offsets for o in row])
+    bp = (_dp * m)(*[_d(b) for b in bs_])
+    vp = (_dp * m)(*[_d(v) for v in vs_])
+    ud = np.ascontiguousarray(u, dtype=np.float64)
+    sd = None if s is None else np.ascontiguousarray(s, dtype=np.float64)
+    out = np.zeros(n)
+    lib().or_band4_combine(n, m, bp, n, off, vp, _d(ud), None if sd is None else _d(sd), _d(out))
     return out
 
 

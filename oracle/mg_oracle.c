@@ -358,6 +358,24 @@ void or_cholesky_solve(int m, const double* Lf, double* b) {
     }
 }
 
+/* u_new = u + sum_i M_i v_i (+ s) with four-band M_i (Sec. 2.2 prediction
+ * step): band k of term i holds M_i[p][p + off[4i+k]] at bands[i][k*bs + p];
+ * neighbours outside [0, n) are absent. */
+void or_band4_combine(size_t n, int m, const double* const* bands, size_t bs, const int* off,
+                      const double* const* v, const double* u, const double* s, double* out) {
+    for (size_t p = 0; p < n; ++p) {
+        double acc = u[p];
+        for (int i = 0; i < m; ++i)
+            for (int k = 0; k < 4; ++k) {
+                long long q = (long long)p + off[4 * i + k];
+                if (q < 0 || q >= (long long)n) continue;
+                acc += bands[i][(size_t)k * bs + p] * v[i][q];
+            }
+        if (s) acc += s[p];
+        out[p] = acc;
+    }
+}
+
 /* y = alpha x + y (Sec. 6.1 axpy), in index order. */
 void or_axpy(size_t n, double alpha, const double* x, double* y) {
     for (size_t p = 0; p < n; ++p) y[p] = alpha * x[p] + y[p];

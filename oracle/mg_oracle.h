@@ -80,6 +80,9 @@ void or_cholesky_solve(int m, const double* Lf, double* b);
 double or_dot(size_t n, const double* u, const double* v);
 /* BLAS level 1 of Sec. 6.1: y = alpha x + y; u . v and ||v|| sum in index order. */
 void or_axpy(size_t n, double alpha, const double* x, double* y);
+/* Sec. 2.2 prediction step: out = u + sum_i M_i v_i (+ s), four bands each. */
+void or_band4_combine(size_t n, int m, const double* const* bands, size_t bs, const int* off,
+                      const double* const* v, const double* u, const double* s, double* out);
 /* Unpreconditioned CG on one level's banded system, from the iterate in x,
  * until ||b - A x|| <= tol ||b|| (recurrence residual) or max_iter steps;
  * returns the steps taken. */

@@ -687,3 +687,64 @@ def test_blas1_dot_against_exactly_rounded_sum(orc):
     r = orc.axpy(0.3, x32, y32)
     ref = np.float32(0.3).astype(np.float64) * x32.astype(np.float64) + y32.astype(np.float64)
     assert np.all(np.abs(r.astype(np.float64) - ref) <= 2.0 ** -24 * np.abs(ref))
+
+
+# ---------------------------------------------------------------- four-band combination
+
+
+def _band4_csr(n, band, offs):
+    """scipy matrix of one four-band term, built from the band definition."""
+    rows, cols, vals = [], [], []
+    p = np.arange(n)
+    for k, o in enumerate(offs):
+        ok = (p + o >= 0) & (p + o < n)
+        rows.append(p[ok])
+        cols.append(p[ok] + o)
+        vals.append(band[k][ok])
+    return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                         shape=(n, n))
+
+
+def test_band4_matches_scipy_products(orc):
+    N = 37
+    n = N * N
+    rng = np.random.default_rng(4)
+    offsets = [(-2, -1, 1, 2), (-2 * N, -N, N, 2 * N), (-1, 0, 1, N), (-N - 1, -N + 1, N - 1, N + 1)]
+    bands = [rng.standard_normal((4, n)) for _ in offsets]
+    vs = [rng.standard_normal(n) for _ in offsets]
+    u = rng.standard_normal(n)
+    s = rng.standard_normal(n)
+    ref = u + s
+    for b, o, v in zip(bands, offsets, vs):
+        ref = ref + _band4_csr(n, b, o) @ v
+    got = orc.band4_combine(bands, offsets, vs, u, s)
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-12)
+    # fewer terms, no source
+    got2 = orc.band4_combine(bands[:1], offsets[:1], vs[:1], u)
+    np.testing.assert_allclose(got2, u + _band4_csr(n, bands[0], offsets[0]) @ vs[0], atol=1e-13)
+
+
+def test_band4_central_differences_of_linear_functions_are_exact(orc):
+    # d/dx and d/dy by central differences (the second-order space
+    # discretisation of the shallow-water scheme) of f = 3x - 2y on a grid of
+    # spacing 1: 3 and -2 at every interior node
+    N = 20
+    n = N * N
+    i = np.tile(np.arange(N), N).astype(np.float64)
+    j = np.repeat(np.arange(N), N).astype(np.float64)
+    f = 3 * i - 2 * j
+    dx = np.zeros((4, n))
+    dx[0], dx[1] = -0.5, 0.5      # offsets -1, +1
+    dy = np.zeros((4, n))
+    dy[2], dy[3] = -0.5, 0.5      # offsets -N, +N
+    zero = np.zeros(n)
+    gx = orc.band4_combine([dx], [(-1, 1, -N, N)], [f], zero)
+    gy = orc.band4_combine([dy], [(-1, 1, -N, N)], [f], zero)
+    inner = (i > 0) & (i < N - 1) & (j > 0) & (j < N - 1)
+    assert np.all(gx[inner] == 3.0) and np.all(gy[inner] == -2.0)
+    # a pure shift: v moved by one, the last entry has no neighbour
+    sh = np.zeros((4, 5))
+    sh[0] = 1.0
+    v = np.arange(1.0, 6.0)
+    np.testing.assert_array_equal(orc.band4_combine([sh], [(1, 2, 3, 4)], [v], np.zeros(5)),
+                                  [2.0, 3.0, 4.0, 5.0, 0.0])
