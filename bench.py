@@ -119,6 +119,29 @@ def bench_blas1(ctx, torch, dev, sizes=None):
     return rows
 
 
+def bench_band4(ctx, torch, dev, N=4096, iters=50):
+    """The shallow-water prediction step (Sec. 2.2) as one fused pass on an
+    N x N grid in FP32: u_new = u + M1 v + M2 w + M3 u + M4 u + s with four
+    four-band matrices (x and y second-order differences and their mixed
+    stencils).  Algorithmic bytes per node: 16 band values, the distinct
+    vectors v, w, u and s read once and u_new written (84 B)."""
+    n = N * N
+    g = torch.Generator(device=dev).manual_seed(5)
+    bands = [torch.rand((4, n), generator=g, device=dev, dtype=torch.float32) for _ in range(4)]
+    v, w, u, s = (torch.rand(n, generator=g, device=dev, dtype=torch.float32) for _ in range(4))
+    out = torch.empty_like(u)
+    offs = [(-2, -1, 1, 2), (-2 * N, -N, N, 2 * N), (-1, 1, -N, N),
+            (-N - 1, -N + 1, N - 1, N + 1)]
+    t = time_launches(lambda: ctx.band4_combine(bands, offs, [v, w, u, u], u, out, s=s), iters,
+                      torch)
+    alg = 84 * n
+    res = {"N": N, "n": n, "us": t * 1e6, "alg_bytes": alg, "GB_s": alg / t / 1e9,
+           "frac_hbm_peak": alg / t / 1e9 / PEAK_HBM_GBS}
+    del bands, v, w, u, s, out
+    torch.cuda.empty_cache()
+    return res
+
+
 def bench_batch(mg, ctx, synth, torch, dev, opts, count=256):
     """256 independent mixed solves advanced together (one persistent launch
     per V-cycle stage), against the same problems solved one after another."""
@@ -307,6 +330,7 @@ def main():
     if args.only_kernels:
         # saxpy at 2^28 elements (1 GiB per vector): the BLAS-1 reference rate
         out["blas1"] = bench_blas1(ctx, torch, dev, sizes=[1 << 28])
+        out["swe_band4"] = bench_band4(ctx, torch, dev)
         # a plain device copy of known size (1 GiB read + 1 GiB written):
         # the calibration reference for the HBM byte counters
         src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
@@ -407,6 +431,8 @@ def main():
 
     # ---------------- BLAS level 1 over lengths 2^10 .. 2^28
     out["blas1"] = bench_blas1(ctx, torch, dev)
+    # ---------------- shallow-water prediction step (four-band combination)
+    out["swe_band4"] = bench_band4(ctx, torch, dev)
 
     # ---------------- batched: 256 problems, L ~ U{5..9}, jitter U[0, 0.25) h
     if not args.no_batch:

@@ -288,6 +288,22 @@ mg_status mg_dot(mg_context* ctx, mg_dtype dtype, int64_t n, const void* x, cons
 mg_status mg_norm2(mg_context* ctx, mg_dtype dtype, int64_t n, const void* x, double* host_out,
                    void* stream);
 
+/* ---- four-band combination (Sec. 2.2: the shallow-water prediction step,
+ * u_new = u + M1 v + M2 w + M3 u + M4 u + S(u), with four-band matrices) ----
+ * u_new[p] = u[p] + sum_{i<m} sum_{k<4} band_i,k[p] v_i[p + offsets[4i+k]]
+ *            (+ s[p] when s is not NULL),  p = 0..n-1,
+ * where band k of term i is bands[i][k * band_stride + p] (band_stride >= n)
+ * and neighbours outside [0, n) count as zero.  1 <= m <= 4; every offset in
+ * (-n, n); v_i may repeat and may be u; u_new must not alias any input.
+ * The terms are added after u in (i, k) order, each as one fused
+ * multiply-add, the source last.  All pointers are device memory of dtype
+ * on ctx's device (bands, offsets and v are host arrays of m pointers / 4m
+ * ints).  Asynchronous on stream. */
+mg_status mg_band4_combine(mg_context* ctx, mg_dtype dtype, int64_t n, int m,
+                           const void* const* bands, int64_t band_stride, const int* offsets,
+                           const void* const* v, const void* u, const void* s, void* u_new,
+                           void* stream);
+
 /* ---- single operators (asynchronous; for parity tests and benchmarks) -----
  * x, y, b, d: device vectors of the level's n elements in dtype. */
 /* y = A x (Sec. 4.1/4.2 banded matrix-vector product). */

@@ -93,6 +93,8 @@ _SIGS = {
     "mg_axpy": (_i, [_vp, _i, _i64, _d, _vp, _vp, _vp]),
     "mg_dot": (_i, [_vp, _i, _i64, _vp, _vp, ctypes.POINTER(_d), _vp]),
     "mg_norm2": (_i, [_vp, _i, _i64, _vp, ctypes.POINTER(_d), _vp]),
+    "mg_band4_combine": (_i, [_vp, _i, _i64, _i, ctypes.POINTER(_vp), _i64, ctypes.POINTER(_i),
+                              ctypes.POINTER(_vp), _vp, _vp, _vp, _vp]),
     "mg_solve_batch": (_i, [ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp), _i,
                             ctypes.POINTER(SolveOpts), _vp, ctypes.POINTER(Stats)]),
 }
@@ -195,6 +197,22 @@ class Context:
         check(lib().mg_dot(self._h, _dt(x), x.numel(), _ptr(x), _ptr(y), ctypes.byref(out),
                            _stream(stream)))
         return out.value
+
+    def band4_combine(self, bands, offsets, vs, u, u_new, s=None, stream=None):
+        """u_new = u + sum_i M_i v_i (+ s): bands[i] a device tensor of shape
+        (4, n) or (4, stride), offsets[i] four ints, vs[i] device vectors."""
+        m = len(bands)
+        n = u.numel()
+        stride = bands[0].shape[-1]
+        for b in bands:
+            if b.dim() != 2 or b.shape[0] != 4 or b.shape[1] != stride or not b.is_contiguous():
+                raise ValueError("bands must be contiguous (4, stride) tensors of one stride")
+        bp = (_vp * m)(*[b.data_ptr() for b in bands])
+        vp = (_vp * m)(*[v.data_ptr() for v in vs])
+        off = (_i * (4 * m))(*[int(o) for row in offsets for o in row])
+        check(lib().mg_band4_combine(self._h, _dt(u), n, m, bp, stride, off, vp, _ptr(u),
+                                     _ptr(s) if s is not None else None, _ptr(u_new),
+                                     _stream(stream)))
 
     def norm2(self, x, stream=None) -> float:
         out = _d()

@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmgfem.so")
-SOURCES = ["kernels.hip", "abi.hip", "solve.hip", "batch.hip", "serve.hip", "blas1.hip"]
+SOURCES = ["kernels.hip", "abi.hip", "solve.hip", "batch.hip", "serve.hip", "blas1.hip",
+           "band4.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
