@@ -17,9 +17,12 @@
 // enough bytes are in flight per wavefront to cover HBM latency.
 // Row bookkeeping of one step: the x row jx enters; the first sweep runs at
 // row jx-1, the second at jx-2, the defect (pre) or norm (post) at jx-3 and
-// the restriction (pre) at jx-4.  An iterate row j lives in LDS slot j mod 3
-// and a band row in register slot j mod 6; the loop is unrolled by six so
-// every slot index is a compile-time constant.
+// the restriction (pre) at jx-4.  With j0 the first row of the march, an
+// iterate row j lives in LDS slot (j - j0) mod 3 and a band row in register
+// slot (j - j0) mod 6; the loop is unrolled by six so every slot index is a
+// compile-time constant.  The march starts at the first row that is needed
+// and runs whole blocks of six steps past the last one (the extra steps
+// compute nothing that is kept).
 #pragma once
 
 #include "device_ops.h"
@@ -132,10 +135,10 @@ __device__ __forceinline__ uint32_t node_off(int j, int N, int col, int size) {
 
 // Pre-smoothing tile (strip, chunk) on a level with N nodes per side:
 // x2 = J(J(x)) on owned nodes and bc = P^T (b - A x2) on the owned coarse
-// nodes (0 at coarse nodes on the Dirichlet sides of dmask).  With XZERO the first sweep starts from a zero
-// iterate and x is not read.  Band rows live in a ring of six register slots
-// (row r in slot r mod 6; the loop is unrolled by six) so that the load of a
-// row lands in its slot two steps before its first use.
+// nodes (0 at coarse nodes on the Dirichlet sides of dmask).  With XZERO the
+// first sweep starts from a zero iterate and x is not read.  Band rows live
+// in a ring of six register slots (the loop is unrolled by six) so that the
+// load of a row lands in its slot two steps before its first use.
 template <typename T, bool XZERO, int BT>
 __device__ void pre_tile(const T* __restrict__ bands, int64_t bs, int N, const T* __restrict__ x,
                          const T* __restrict__ b, T omega, T* __restrict__ x2out,
@@ -162,7 +165,9 @@ __device__ void pre_tile(const T* __restrict__ bands, int64_t bs, int N, const T
     }
     T bk[6][9], bb[6];  // band rows, slot r mod 6
     T pfx[3];           // x rows, slot r mod 3
-    const int jstart = r0 - F_HALO - ((((r0 - F_HALO) % 6) + 6) % 6);  // multiple of 6
+    // the first x row any sweep needs enters first; the last restriction
+    // row leaves last
+    const int jstart = r0 - F_HALO;
     const int jend = r1 + 4;
     auto xload = [&](int j) -> T {
         if (XZERO) return T(0);
@@ -295,8 +300,10 @@ __device__ void post_tile(const T* __restrict__ bands, int64_t bs, int N, const 
     T pfx[3], pc0[3], pc1[3], pc2[3], pc3[3];
     double nacc = 0.0;  // this lane's part of the current row group
     const int ng = (N + F_NORM_ROWS - 1) / F_NORM_ROWS;
-    const int jstart = r0 - F_HALO - ((((r0 - F_HALO) % 6) + 6) % 6);
-    const int jend = r1 + 3;
+    // first x row needed .. last row of the last step (the norm, or the
+    // second sweep)
+    const int jstart = r0 - H;
+    const int jend = r1 + (NORM ? 3 : 2);
     // x row j plus its coarse correction P x_c (the arithmetic of
     // prolong_elem): the x value and the four coarse values around the node
     // are loaded two steps ahead and combined when the row enters
@@ -365,9 +372,9 @@ __device__ void post_tile(const T* __restrict__ bands, int64_t bs, int N, const 
                     v = A[l2][t] + omega * (bb[b2] - acc) / bk[b2][4];
                     if (c_own && in_range(j2, r0, r1)) xout[(int64_t)j2 * N + col] = v;
                 }
-                B[l2][t] = v;
+                if (NORM) B[l2][t] = v;
             }
-            __syncthreads();
+            if (NORM) __syncthreads();
             if (NORM && in_range(j3, r0, r1)) {
                 if (c_own) {
                     const T acc = band_row_product(bk[b3], B[l1], B[x3], B[l2], t);
