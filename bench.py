@@ -155,7 +155,23 @@ def bench_batch(mg, ctx, synth, torch, dev, opts, count=256):
         hs.append(h)
         bs.append(b)
         xs.append(torch.zeros_like(b))
+    # tile heights picked by the autotuner for this composition (no result
+    # bit depends on them); the rule's choice is timed as well, for reference
+    mg.batch_clear_tiles()
     mg.solve_batch(hs, bs, xs, opts)  # warm-up (graph capture)
+    t_rule = []
+    for _ in range(3):
+        for x in xs:
+            x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mg.solve_batch(hs, bs, xs, opts)
+        torch.cuda.synchronize()
+        t_rule.append(time.perf_counter() - t0)
+    t0 = time.perf_counter()
+    tiles = mg.batch_autotune(hs, opts, reps=10)
+    t_tune = time.perf_counter() - t0
+    mg.solve_batch(hs, bs, xs, opts)  # warm-up with the tuned tiles
     reps = 5
     dts = []
     for _ in range(reps):
@@ -183,7 +199,9 @@ def bench_batch(mg, ctx, synth, torch, dev, opts, count=256):
            "alg_GB_s": alg / dt / 1e9, "sequential_ms": dt_seq * 1e3,
            "speedup_vs_sequential": dt_seq / dt,
            "mean_outer": float(np.mean([s.outer_steps for s in stats])),
-           "mean_inner": float(np.mean([s.cycles for s in stats]))}
+           "mean_inner": float(np.mean([s.cycles for s in stats])),
+           "autotune": {"seconds": t_tune, "tiles": tiles,
+                        "rule_tiles_ms": float(np.median(t_rule)) * 1e3}}
     for h in hs:
         h.close()
     return rec

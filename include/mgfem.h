@@ -224,6 +224,37 @@ mg_status mg_solve(mg_hierarchy* h, const double* dev_b, double* dev_x,
 mg_status mg_solve_batch(mg_hierarchy* const* hs, const double* const* b, double* const* x,
                          int count, const mg_solve_opts* opts, void* stream, mg_stats* stats);
 
+/* ---- batched tiles: autotuner ----------------------------------------------
+ * The fused passes of the batched solver (and of the server) process each
+ * level in tiles of a strip of columns by a number of grid rows.  The rows
+ * per tile come from a process-wide table filled by this autotuner, keyed by
+ * level and by the number of problems at that level rounded down to a power
+ * of two; levels without an entry use the rule "largest height in 4..64 that
+ * still gives about 3500 wavefronts".  The wavefronts per grid row stay
+ * with the rule that covers a row with the fewest threads: the residual
+ * norm's summation order depends on them, and a batched result must equal
+ * the single solve bit for bit.  Tile heights change no result bit.
+ * mg_batch_autotune: for the composition of these problems (options as for
+ * mg_solve_batch; NULL: defaults), times the fused pre- and post-smoothing
+ * passes of every level with 4, 8, 16, 32 and 64 rows per tile (reps pairs
+ * each, on the problems' FP32 work vectors, which no later solve reads before
+ * writing), stores the fastest in the table and writes up to out_cap chosen
+ * rows to out (*n_out = rows chosen).  Synchronous; thread safe with respect
+ * to other batches on separate hierarchies.  Only V(2,2) cycles have tiles.
+ * mg_batch_set_tile: installs one entry (e.g. read back from a file);
+ * tile_rows a power of two in [4, 256].  mg_batch_clear_tiles: empties the
+ * table. */
+typedef struct {
+    int level;
+    int problems;     /* problems at this level in the tuned composition */
+    int tile_rows;    /* chosen rows per tile */
+    double us;        /* one pre + post pass pair at that height, microseconds */
+} mg_tile_choice;
+mg_status mg_batch_autotune(mg_hierarchy* const* hs, int count, const mg_solve_opts* opts,
+                            int reps, mg_tile_choice* out, int out_cap, int* n_out);
+mg_status mg_batch_set_tile(int level, int problems, int tile_rows);
+mg_status mg_batch_clear_tiles(void);
+
 /* ---- serving ---------------------------------------------------------------
  * A server owns a BatchEngine of `slots` slots, a scheduler thread and a pool
  * of device-resident hierarchies of levels coarse_level..max_level charged

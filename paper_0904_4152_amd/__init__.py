@@ -13,5 +13,6 @@ from ._binding import (  # noqa: F401
     MG_ERR_BUSY, MG_PREC_FP64, MG_PREC_MIXED, MG_F64, MG_F32, SIDE_X0, SIDE_X1, SIDE_Y0, SIDE_Y1,
     ALL_DIRICHLET, MG_COARSE_CHOLESKY, MG_COARSE_CG, MgError, SolveOpts, Stats,
     lib, library_path, default_opts, Context, Hierarchy, check, solve_batch, Server,
+    TileChoice, batch_autotune, batch_set_tiles, batch_clear_tiles, save_tiles, load_tiles,
     ServerInfo,
 )

@@ -34,6 +34,10 @@ class SolveOpts(ctypes.Structure):
                 ("krylov", _i)]
 
 
+class TileChoice(ctypes.Structure):
+    _fields_ = [("level", _i), ("problems", _i), ("tile_rows", _i), ("us", _d)]
+
+
 class Stats(ctypes.Structure):
     _fields_ = [("status", _i), ("cycles", _i), ("outer_steps", _i), ("bnorm", _d),
                 ("rel_res", _d), ("seconds", _d), ("alg_bytes", _d), ("n_hist", _i),
@@ -95,6 +99,10 @@ _SIGS = {
     "mg_norm2": (_i, [_vp, _i, _i64, _vp, ctypes.POINTER(_d), _vp]),
     "mg_band4_combine": (_i, [_vp, _i, _i64, _i, ctypes.POINTER(_vp), _i64, ctypes.POINTER(_i),
                               ctypes.POINTER(_vp), _vp, _vp, _vp, _vp]),
+    "mg_batch_autotune": (_i, [ctypes.POINTER(_vp), _i, ctypes.POINTER(SolveOpts), _i,
+                               ctypes.POINTER(TileChoice), _i, ctypes.POINTER(_i)]),
+    "mg_batch_set_tile": (_i, [_i, _i, _i]),
+    "mg_batch_clear_tiles": (_i, []),
     "mg_solve_batch": (_i, [ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp), _i,
                             ctypes.POINTER(SolveOpts), _vp, ctypes.POINTER(Stats)]),
 }
@@ -357,6 +365,44 @@ class Hierarchy:
             fused = nu_pre == 2 and nu_post == 2
         check(lib().mg_vcycle(self._h, level, _dt(x), _ptr(b), _ptr(x), nu_pre, nu_post, omega,
                               int(fused), _stream(stream)))
+
+
+def batch_autotune(hierarchies, opts=None, reps=10):
+    """Tune the batched solver's tile heights for this composition; returns the
+    chosen rows as dicts (level, problems, tile_rows, us)."""
+    n = len(hierarchies)
+    hs = (_vp * n)(*[h.handle for h in hierarchies])
+    out = (TileChoice * 16)()
+    got = _i()
+    check(lib().mg_batch_autotune(hs, n, ctypes.byref(opts) if opts is not None else None, reps,
+                                  out, 16, ctypes.byref(got)))
+    return [{"level": out[i].level, "problems": out[i].problems,
+             "tile_rows": out[i].tile_rows, "us": out[i].us} for i in range(min(got.value, 16))]
+
+
+def batch_set_tiles(rows):
+    """Install tile choices (the rows batch_autotune returns, e.g. from JSON)."""
+    for r in rows:
+        check(lib().mg_batch_set_tile(int(r["level"]), int(r["problems"]), int(r["tile_rows"])))
+
+
+def batch_clear_tiles():
+    check(lib().mg_batch_clear_tiles())
+
+
+def save_tiles(rows, path):
+    import json
+    with open(path, "w") as f:
+        json.dump({"tiles": rows}, f, indent=1)
+
+
+def load_tiles(path):
+    """Read a tile file written by save_tiles and install it."""
+    import json
+    with open(path) as f:
+        rows = json.load(f)["tiles"]
+    batch_set_tiles(rows)
+    return rows
 
 
 def solve_batch(hierarchies, bs, xs, opts=None, stream=None, raise_on_error=True):

@@ -109,6 +109,11 @@ public:
     // problems' finest vectors (out = false; after upload), or the
     // solutions back into x (out = true: x = 0 for a zero right-hand side).
     mg_status io(const double* const* b, double* const* x, int count, bool out);
+    // Autotuner: for every level the fused passes run on in the current
+    // composition (after upload), time the pre and post passes with each
+    // tile height, keep the fastest in the process-wide tile table and
+    // report it.  Uses only the FP32 work vectors (scratch); synchronous.
+    mg_status tune(int reps, std::vector<mg_tile_choice>* out);
     const BState& state(int s) const { return h_state_[s]; }
     int capacity() const { return cap_; }
     bool live(int s) const { return hp_[s].L > 0; }
@@ -117,6 +122,8 @@ public:
 
 private:
     hipError_t enqueue_iteration();
+    hipError_t launch_fused(int l, bool pre, int mask);
+    int problems_at(int l) const;
     void build_lists();
     mg_status ensure_graph();
     mg_status launch();
@@ -151,6 +158,14 @@ private:
     // above the coarse one.  The set only grows (a new bit recaptures).
     uint32_t launch_mask_ = 0;
     double step_bytes_ = 0.0;
+    int rh_override_[MG_MAX_LEVEL + 1] = {};  // tile heights under trial (0: none)
 };
+
+// Process-wide table of tuned tile heights of the batched fused passes,
+// keyed by level and by the number of problems at that level (rounded down
+// to a power of two); 0 when the level has no entry.
+int tile_table_get(int level, int64_t problems);
+void tile_table_set(int level, int64_t problems, int rows);
+void tile_table_clear();
 
 }  // namespace mg

@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <new>
 
@@ -639,6 +640,51 @@ void BatchEngine::clear_slot(int s) {
 
 void BatchEngine::start_slot(int s) { started_[s] = 1; }
 
+namespace {
+struct TileTable {
+    std::mutex mu;
+    std::map<std::pair<int, int>, int> rows;  // (level, log2 problems) -> tile rows
+};
+TileTable& tile_table() {
+    static TileTable* t = new TileTable();
+    return *t;
+}
+int log2_floor(int64_t v) {
+    int k = 0;
+    while (v > 1) {
+        v >>= 1;
+        ++k;
+    }
+    return k;
+}
+}  // namespace
+
+int tile_table_get(int level, int64_t problems) {
+    TileTable& t = tile_table();
+    std::lock_guard<std::mutex> g(t.mu);
+    auto it = t.rows.find({level, log2_floor(problems)});
+    return it == t.rows.end() ? 0 : it->second;
+}
+
+void tile_table_set(int level, int64_t problems, int rows) {
+    TileTable& t = tile_table();
+    std::lock_guard<std::mutex> g(t.mu);
+    t.rows[{level, log2_floor(problems)}] = rows;
+}
+
+void tile_table_clear() {
+    TileTable& t = tile_table();
+    std::lock_guard<std::mutex> g(t.mu);
+    t.rows.clear();
+}
+
+int BatchEngine::problems_at(int l) const {
+    int count = 0;
+    for (int s = 0; s < cap_; ++s)
+        if (hp_[s].L >= l && (l > dev::TAIL_MAX || l == hp_[s].L)) ++count;
+    return count;
+}
+
 // Work lists of the current composition.
 void BatchEngine::build_lists() {
     const int stride = 3 + 2 * cap_;
@@ -664,14 +710,18 @@ void BatchEngine::build_lists() {
         return P.L >= l && (l > dev::TAIL_MAX || l == P.L);
     };
     // chunk heights of the fused passes for this composition: every problem
-    // at a level shares one (the solves do not depend on it)
+    // at a level shares one (the solves do not depend on it): a height under
+    // trial by the autotuner, else the tuned one, else the wavefront rule
     for (int l = Lc_ + 1; l <= Lmax_; ++l) {
         int64_t count = 0;
         for (int s = 0; s < cap_; ++s)
             if (hp_[s].L > 0 && fused_here(hp_[s], l)) ++count;
         if (count == 0) continue;
         const int N = (1 << l) + 1, bt = fused_bt(N);
-        const dev::FusedGeom g = dev::fused_geom(N, bt, fused_rh(N, bt, count));
+        int rh = rh_override_[l];
+        if (!rh) rh = tile_table_get(l, count);
+        if (!rh) rh = fused_rh(N, bt, count);
+        const dev::FusedGeom g = dev::fused_geom(N, bt, rh);
         for (int s = 0; s < cap_; ++s) {
             if (hp_[s].L == 0 || !fused_here(hp_[s], l)) continue;
             hp_[s].lv[l].rh = g.rh;
@@ -778,6 +828,81 @@ mg_status BatchEngine::fetch_state(int s, BState* out) {
     if (mg_status e = fetch(d_state_ + s, h_fetch_, sizeof(BState))) return e;
     *out = *h_fetch_;
     return MG_OK;
+}
+
+// One fused pass (pre or post) at level l over the problems whose flags meet
+// mask, as in an iteration.
+hipError_t BatchEngine::launch_fused(int l, bool pre, int mask) {
+    const int stride = 3 + 2 * cap_;
+    const int* wl = d_wl_ + (size_t)wl_fused(l) * stride;
+    const int bt = fused_bt((1 << l) + 1);
+    const dim3 GF(STAGE_GRID * (dev::F_MAX_THREADS / bt)), BF(bt);
+#define ONE(BT)                                                                              \
+    if (pre)                                                                                 \
+        hipLaunchKernelGGL(kb_fpre<BT>, GF, BF, 0, st_, d_probs_, d_state_, wl, l, mask);   \
+    else                                                                                     \
+        hipLaunchKernelGGL(kb_fpost<BT>, GF, BF, 0, st_, d_probs_, d_state_, wl, l, mask);
+    switch (bt) {
+        case 64: ONE(64) break;
+        case 128: ONE(128) break;
+        case 192: ONE(192) break;
+        default: ONE(256) break;
+    }
+#undef ONE
+    return hipGetLastError();
+}
+
+mg_status BatchEngine::tune(int reps, std::vector<mg_tile_choice>* out) {
+    static const int kRows[] = {4, 8, 16, 32, 64};
+    MG_HIP(hipSetDevice(device_));
+    if (mg_status s = upload()) return s;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    MG_HIP(hipEventCreate(&e0));
+    MG_HIP(hipEventCreate(&e1));
+    struct Ev {
+        hipEvent_t a, b;
+        ~Ev() {
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+        }
+    } ev{e0, e1};
+    if (!(nu_pre_ == 2 && nu_post_ == 2)) return MG_OK;  // only the fused cycle has tiles
+    for (int l = Lc_ + 1; l <= Lmax_; ++l) {
+        const int count = problems_at(l);
+        if (count == 0) continue;
+        int best = 0;
+        float best_ms = 0.0f;
+        for (int rh : kRows) {
+            rh_override_[l] = rh;
+            probs_dirty_ = true;
+            if (mg_status s = upload()) {
+                rh_override_[l] = 0;
+                return s;
+            }
+            for (int w = 0; w < 2; ++w) {  // warm-up
+                MG_HIP(launch_fused(l, true, BF_INIT));
+                MG_HIP(launch_fused(l, false, BF_INIT));
+            }
+            MG_HIP(hipEventRecord(e0, st_));
+            for (int r = 0; r < reps; ++r) {
+                MG_HIP(launch_fused(l, true, BF_INIT));
+                MG_HIP(launch_fused(l, false, BF_INIT));
+            }
+            MG_HIP(hipEventRecord(e1, st_));
+            MG_HIP(hipEventSynchronize(e1));
+            float ms = 0.0f;
+            MG_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (!best || ms < best_ms) {
+                best = rh;
+                best_ms = ms;
+            }
+        }
+        rh_override_[l] = 0;
+        tile_table_set(l, count, best);
+        if (out) out->push_back({l, count, best, 1e3 * best_ms / reps});
+    }
+    probs_dirty_ = true;
+    return upload();
 }
 
 hipError_t BatchEngine::enqueue_iteration() {
@@ -1158,5 +1283,73 @@ extern "C" mg_status mg_solve_batch(mg_hierarchy* const* hs, const double* const
     MG_HIP(hipStreamSynchronize(eng.stream()));
     ret.ok = true;
     if (worst != MG_OK) return fail(worst, "at least one problem of the batch did not converge");
+    return MG_OK;
+}
+
+extern "C" mg_status mg_batch_autotune(mg_hierarchy* const* hs, int count,
+                                       const mg_solve_opts* opts, int reps, mg_tile_choice* out,
+                                       int out_cap, int* n_out) {
+    if (n_out) *n_out = 0;
+    if (!hs || count < 1) return fail(MG_ERR_INVALID, "empty or null batch");
+    if (reps < 1 || reps > 1000) return fail(MG_ERR_INVALID, "reps must lie in [1, 1000]");
+    if (out_cap < 0 || (out_cap > 0 && !out)) return fail(MG_ERR_INVALID, "bad output array");
+    mg_solve_opts o;
+    mg_default_opts(&o);
+    o.precision = MG_PREC_MIXED;
+    if (opts) o = *opts;
+    int Lmax = 0;
+    for (int p = 0; p < count; ++p) {
+        const mg_hierarchy* h = hs[p];
+        if (!h || !h->assembled) return fail(MG_ERR_INVALID, "null or unassembled hierarchy");
+        if (h->ctx->device != hs[0]->ctx->device || h->Lc != hs[0]->Lc)
+            return fail(MG_ERR_INVALID, "batch problems must share device and coarse level");
+        for (int q = 0; q < p; ++q)
+            if (hs[q] == h) return fail(MG_ERR_INVALID, "a hierarchy appears twice in the batch");
+        Lmax = std::max(Lmax, h->L);
+    }
+    if (o.nu_pre < 0 || o.nu_post < 0 || o.nu_pre + o.nu_post == 0 || o.nu_pre > 16 ||
+        o.nu_post > 16 || !(o.omega > 0.0 && o.omega < 2.0))
+        return fail(MG_ERR_INVALID, "invalid solver options");
+    const int device = hs[0]->ctx->device, Lc = hs[0]->Lc;
+    MG_HIP(hipSetDevice(device));
+    EnginePool& pool = engine_pool();
+    BatchEngine* eng = pool.take(device, count, Lmax, Lc, o.nu_pre, o.nu_post);
+    if (!eng) {
+        eng = new (std::nothrow) BatchEngine();
+        if (!eng) return fail(MG_ERR_NOMEM, "host allocation failed");
+        if (mg_status s = eng->init(device, count, Lmax, Lc, o.nu_pre, o.nu_post)) {
+            delete eng;
+            return s;
+        }
+    }
+    for (int s = count; s < eng->capacity(); ++s) eng->clear_slot(s);
+    for (int p = 0; p < count; ++p) {
+        eng->set_slot(p, hs[p], o);
+        eng->start_slot(p);
+    }
+    std::vector<mg_tile_choice> rows;
+    const mg_status st = eng->tune(reps, &rows);
+    if (st != MG_OK) {
+        delete eng;
+        return st;
+    }
+    pool.give(device, Lmax, Lc, o.nu_pre, o.nu_post, eng);
+    const int n = std::min<int>(out_cap, (int)rows.size());
+    for (int i = 0; i < n; ++i) out[i] = rows[i];
+    if (n_out) *n_out = (int)rows.size();
+    return MG_OK;
+}
+
+extern "C" mg_status mg_batch_set_tile(int level, int problems, int tile_rows) {
+    if (level < 2 || level > MG_MAX_LEVEL) return fail(MG_ERR_INVALID, "level outside [2, 14]");
+    if (problems < 1) return fail(MG_ERR_INVALID, "problems must be >= 1");
+    if (tile_rows < 4 || tile_rows > 256 || (tile_rows & (tile_rows - 1)))
+        return fail(MG_ERR_INVALID, "tile_rows must be a power of two in [4, 256]");
+    tile_table_set(level, problems, tile_rows);
+    return MG_OK;
+}
+
+extern "C" mg_status mg_batch_clear_tiles(void) {
+    tile_table_clear();
     return MG_OK;
 }

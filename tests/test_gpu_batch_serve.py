@@ -203,3 +203,47 @@ def test_server_budget_admission(mg, ctx):
     assert sorted(t for t, _, _ in got) == sorted(tickets)
     assert all(rc == 0 for _, rc, _ in got)
     assert info.bytes_high_water <= int(one * 1.5)
+
+
+def test_autotuned_tiles_change_no_bit(mg, ctx, tmp_path):
+    """The autotuner picks a tile height per level of this composition; the
+    batch solved with the tuned table, with a forced odd choice and with the
+    rule's choice gives the same bits, and the table round-trips through a
+    file."""
+    probs = make_problems(mg, ctx, [9, 8, 7, 6, 5, 9, 8, 7] * 3, seed0=5000)
+    opts = mg.default_opts(precision=mg.MG_PREC_MIXED, rel_tol=1e-8)
+    hs, bs_ = [p[0] for p in probs], [p[1] for p in probs]
+
+    def run():
+        xs = [torch.zeros_like(b) for b in bs_]
+        st = mg.solve_batch(hs, bs_, xs, opts)
+        assert all(s.status == 0 and s.rel_res <= 1e-8 for s in st)
+        return [host(x) for x in xs], [(s.cycles, s.outer_steps, s.rel_res) for s in st]
+
+    mg.batch_clear_tiles()
+    ref_x, ref_s = run()
+    rows = mg.batch_autotune(hs, opts, reps=3)
+    assert sorted(r["level"] for r in rows) == [5, 6, 7, 8, 9]
+    for r in rows:
+        assert r["tile_rows"] in (4, 8, 16, 32, 64) and r["us"] > 0.0
+    # problems per level: levels above the coarse tail (5) run for every
+    # problem that has them, level 5 only as a finest level
+    by_level = {r["level"]: r["problems"] for r in rows}
+    assert by_level == {9: 6, 8: 12, 7: 18, 6: 21, 5: 3}
+    x1, s1 = run()
+    path = str(tmp_path / "tiles.json")
+    mg.save_tiles(rows, path)
+    mg.batch_clear_tiles()
+    assert mg.load_tiles(path) == rows
+    x2, s2 = run()
+    mg.batch_set_tiles([{"level": 9, "problems": 6, "tile_rows": 128}])  # not a tuner candidate
+    x3, s3 = run()
+    for xs, ss in ((x1, s1), (x2, s2), (x3, s3)):
+        assert ss == ref_s
+        for a, b in zip(xs, ref_x):
+            np.testing.assert_array_equal(a, b)
+    with pytest.raises(mg.MgError):
+        mg.batch_set_tiles([{"level": 9, "problems": 6, "tile_rows": 12}])
+    mg.batch_clear_tiles()
+    for h, _, _, _ in probs:
+        h.close()
