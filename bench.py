@@ -42,8 +42,8 @@ def parse():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-rate", type=float, default=2000.0)
-    ap.add_argument("--serve-count", type=int, default=10000)
-    ap.add_argument("--serve-warmup", type=int, default=1000)
+    ap.add_argument("--serve-count", type=int, default=20000)
+    ap.add_argument("--serve-warmup", type=int, default=2000)
     ap.add_argument("--serve-slots", type=int, default=64)
     return ap.parse_args()
 
