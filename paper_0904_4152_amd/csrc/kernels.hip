@@ -148,8 +148,8 @@ __global__ __launch_bounds__(dev::TAIL_THREADS) void k_tail(dev::TailLevels<T> t
 // most 72 unknowns).  flag = 1 if a pivot is not positive.
 __global__ void k_chol_factor(const double* __restrict__ bands, int64_t bs, int Nc, int dmask,
                               double* __restrict__ A, int* __restrict__ flag) {
+    __shared__ int idx[dev::COARSE_MAX_UNKNOWNS];  // node -> unknown (LDS: no scratch)
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    int idx[dev::COARSE_MAX_UNKNOWNS];
     int m = 0;
     for (int p = 0; p < Nc * Nc; ++p)
         idx[p] = dev::is_dirichlet(Nc, p % Nc, p / Nc, dmask) ? -1 : m++;
@@ -200,11 +200,8 @@ __device__ __forceinline__ double uniform01(uint64_t seed, uint64_t k) {
 // Finest-level coordinates: uniform grid, interior nodes moved by
 // (2u-1)*jitter*h in each direction.  Explicitly rounded operations keep
 // the result identical to a host evaluation of the same formula.
-__global__ __launch_bounds__(BLOCK) void k_coords(double* __restrict__ xy, int N, double jitter,
-                                                  uint64_t seed) {
-    const int i = blockIdx.x * BLOCK + threadIdx.x;
-    const int j = blockIdx.y;
-    if (i >= N) return;
+__device__ __forceinline__ void coords_node(double* __restrict__ xy, int N, double jitter,
+                                            uint64_t seed, int i, int j) {
     const int64_t p = (int64_t)j * N + i;
     const double h = 1.0 / (double)(N - 1);
     double x = __dmul_rn((double)i, h), y = __dmul_rn((double)j, h);
@@ -218,6 +215,12 @@ __global__ __launch_bounds__(BLOCK) void k_coords(double* __restrict__ xy, int N
     }
     xy[2 * p] = x;
     xy[2 * p + 1] = y;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_coords(double* __restrict__ xy, int N, double jitter,
+                                                  uint64_t seed) {
+    const int i = blockIdx.x * BLOCK + threadIdx.x;
+    if (i < N) coords_node(xy, N, jitter, seed, i, (int)blockIdx.y);
 }
 
 // Bilinear map of one quadrilateral written as
@@ -428,17 +431,33 @@ __global__ __launch_bounds__(BLOCK) void k_rhs_sinsin(const double* __restrict__
 
 // Seeded uniform right-hand side (zero on the Dirichlet sides); with x0 also
 // a zero initial iterate.
-__global__ __launch_bounds__(BLOCK) void k_rhs_uniform(int N, uint64_t seed, int dmask,
-                                                       double* __restrict__ bout,
-                                                       double* __restrict__ x0) {
-    const int i = blockIdx.x * BLOCK + threadIdx.x;
-    const int j = blockIdx.y;
-    if (i >= N) return;
+__device__ __forceinline__ void rhs_uniform_node(int N, uint64_t seed, int dmask,
+                                                 double* __restrict__ bout,
+                                                 double* __restrict__ x0, int i, int j) {
     const int64_t p = (int64_t)j * N + i;
     double v = 0.0;
     if (!dev::is_dirichlet(N, i, j, dmask)) v = 2.0 * uniform01(seed, (uint64_t)p) - 1.0;
     bout[p] = v;
     if (x0) x0[p] = 0.0;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_rhs_uniform(int N, uint64_t seed, int dmask,
+                                                       double* __restrict__ bout,
+                                                       double* __restrict__ x0) {
+    const int i = blockIdx.x * BLOCK + threadIdx.x;
+    if (i < N) rhs_uniform_node(N, seed, dmask, bout, x0, i, (int)blockIdx.y);
+}
+
+// Both of the above in one launch (a served request's problem set-up).
+__global__ __launch_bounds__(BLOCK) void k_coords_rhs(double* __restrict__ xy, int N,
+                                                      double jitter, uint64_t gseed,
+                                                      uint64_t rseed, int dmask,
+                                                      double* __restrict__ bout,
+                                                      double* __restrict__ x0) {
+    const int i = blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= N) return;
+    coords_node(xy, N, jitter, gseed, i, (int)blockIdx.y);
+    rhs_uniform_node(N, rseed, dmask, bout, x0, i, (int)blockIdx.y);
 }
 
 template <typename T>
@@ -595,6 +614,15 @@ int64_t norm_blocks(int64_t n) { return (n + dev::NORM_TILE - 1) / dev::NORM_TIL
 hipError_t launch_coords(double* xy, int L, double jitter, uint64_t seed, hipStream_t st) {
     const int N = (1 << L) + 1;
     hipLaunchKernelGGL(k_coords, dim3(blocks1d(N), N), dim3(BLOCK), 0, st, xy, N, jitter, seed);
+    return hipGetLastError();
+}
+
+hipError_t launch_coords_rhs(double* xy, int L, double jitter, uint64_t geom_seed,
+                             uint64_t rhs_seed, int dmask, double* b, double* x0,
+                             hipStream_t st) {
+    const int N = (1 << L) + 1;
+    hipLaunchKernelGGL(k_coords_rhs, dim3(blocks1d(N), N), dim3(BLOCK), 0, st, xy, N, jitter,
+                       geom_seed, rhs_seed, dmask, b, x0);
     return hipGetLastError();
 }
 

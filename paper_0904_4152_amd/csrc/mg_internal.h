@@ -113,6 +113,11 @@ dev::CoarseSolver coarse_solver(const mg_hierarchy* h);
 // ---------------------------------------------------------------- kernels
 // All launchers enqueue on `st` and return the HIP launch error.
 hipError_t launch_coords(double* xy, int L, double jitter, uint64_t seed, hipStream_t st);
+// Coordinates and the seeded uniform right-hand side with x0 = 0 (one launch;
+// the same values as launch_coords + launch_rhs_uniform).
+hipError_t launch_coords_rhs(double* xy, int L, double jitter, uint64_t geom_seed,
+                             uint64_t rhs_seed, int dmask, double* b, double* x0,
+                             hipStream_t st);
 // dmask below: the Dirichlet sides of the problem (bits as in mg_hierarchy).
 // Bands of levels Lc..L (lv indexed by level) from the finest coordinates.
 hipError_t launch_assemble(const double* xy_fine, const Level* lv, int Lc, int L, int dmask,

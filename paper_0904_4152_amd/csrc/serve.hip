@@ -143,11 +143,11 @@ bool mg_server::admit_one(int slot, const Request& r) {
     mg_hierarchy* h = take_hierarchy(r.L);
     if (!h) return false;
     hipStream_t st = eng.setup_stream();
-    hipError_t e = launch_coords(h->coords, r.L, r.jitter, r.geom_seed, st);
+    const Level& F = h->lv[r.L];
+    hipError_t e = launch_coords_rhs(h->coords, r.L, r.jitter, r.geom_seed, r.rhs_seed, h->dmask,
+                                     F.b64, F.x64, st);
     if (e == hipSuccess) e = launch_assemble(h->coords, h->lv, Lc, r.L, h->dmask, st);
     if (e == hipSuccess) e = launch_chol_factor(h->lv[Lc], h->dmask, h->chol, h->flag, st);
-    const Level& F = h->lv[r.L];
-    if (e == hipSuccess) e = launch_rhs_uniform(F.N, r.rhs_seed, h->dmask, F.b64, F.x64, st);
     if (e != hipSuccess) {
         release_hierarchy(h);
         set_fatal(MG_ERR_DEVICE, std::string("admission: ") + hipGetErrorString(e));
