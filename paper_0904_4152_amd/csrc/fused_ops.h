@@ -129,6 +129,55 @@ __device__ __forceinline__ void load_row(const RowRsrc<T>& R, uint32_t off, bool
     bb = bload<T>(R.b, o);
 }
 
+// The diagonal and upper bands (4..8) and b of one node; the lower bands
+// are rebuilt from the neighbours' upper bands (see LowerBands).
+template <typename T>
+__device__ __forceinline__ void load_upper(const RowRsrc<T>& R, uint32_t off, bool need,
+                                           T (&bk)[9], T& bb) {
+    const uint32_t o = need ? off : OFF_NONE;
+#pragma unroll
+    for (int k = 4; k < 9; ++k) bk[k] = bload<T, AUX_NT>(R.band[k], o);
+    bb = bload<T>(R.b, o);
+}
+
+// The assembled matrix is symmetric bit for bit (each entry and its mirror
+// sum the same element terms in the same order), so the lower bands of a
+// row are upper bands of its neighbours:
+//   A[p][p-1]   = band 5 at p-1      (same row, left column)
+//   A[p][p-N-1] = band 8 at p-N-1    (previous row, left column)
+//   A[p][p-N]   = band 7 at p-N      (previous row, same column)
+//   A[p][p-N+1] = band 6 at p-N+1    (previous row, right column).
+// A tile reads 5 of the 9 band streams; bands 5, 6 and 8 of each row pass
+// through LDS to the neighbouring columns (6 and 8 kept for two rows), band
+// 7 of the previous row is still in the thread's register ring.  Columns
+// and rows outside the grid read as zero, as the stored lower bands are.
+template <typename T, int BT>
+struct LowerBands {
+    T* u5;  // band 5 of the row being completed
+    T* u6;  // band 6 of two consecutive rows (slot = relative row parity)
+    T* u8;  // band 8, likewise
+    __device__ void init() {
+        if (threadIdx.x < 2) {
+            const int g = threadIdx.x ? BT + 1 : 0;
+            u5[g] = u6[g] = u6[(BT + 2) + g] = u8[g] = u8[(BT + 2) + g] = T(0);
+        }
+    }
+    // Before a barrier: publish the upper bands of row r (slot par).
+    __device__ __forceinline__ void publish(const T (&bk)[9], int par, int t) {
+        u5[t] = bk[5];
+        u6[par * (BT + 2) + t] = bk[6];
+        u8[par * (BT + 2) + t] = bk[8];
+    }
+    // After it: complete row r from its own and row r-1's published bands
+    // (row r-1 in slot prev, its band 7 in bkp).
+    __device__ __forceinline__ void complete(T (&bk)[9], const T (&bkp)[9], int prev, int t) {
+        bk[0] = u8[prev * (BT + 2) + t - 1];
+        bk[1] = bkp[7];
+        bk[2] = u6[prev * (BT + 2) + t + 1];
+        bk[3] = u5[t - 1];
+    }
+};
+
 __device__ __forceinline__ uint32_t node_off(int j, int N, int col, int size) {
     return (uint32_t)(j * N + col) * (uint32_t)size;
 }
@@ -144,6 +193,8 @@ __device__ void pre_tile(const T* __restrict__ bands, int64_t bs, int N, const T
                          const T* __restrict__ b, T omega, T* __restrict__ x2out,
                          T* __restrict__ bc, int dmask, int strip, int chunk, int rh, int cw) {
     __shared__ T X[3][BT + 2], A[3][BT + 2], B[3][BT + 2], D[3][BT + 2];
+    __shared__ T U5[BT + 2], U6[2][BT + 2], U8[2][BT + 2];
+    LowerBands<T, BT> lower{U5, &U6[0][0], &U8[0][0]};
     const int t = threadIdx.x + 1;  // LDS column; 0 and BT+1 are guards
     const int c0 = strip * cw, c1 = min(c0 + cw, N);
     const int r0 = chunk * rh, r1 = min(r0 + rh, N);
@@ -163,8 +214,9 @@ __device__ void pre_tile(const T* __restrict__ bands, int64_t bs, int N, const T
 #pragma unroll
         for (int s = 0; s < 3; ++s) X[s][g] = A[s][g] = B[s][g] = D[s][g] = T(0);
     }
-    T bk[6][9], bb[6];  // band rows, slot r mod 6
-    T pfx[3];           // x rows, slot r mod 3
+    lower.init();
+    T bk[6][9], bb[6];  // band rows, slot (r - jstart) mod 6
+    T pfx[3];           // x rows, slot (r - jstart) mod 3
     // the first x row any sweep needs enters first; the last restriction
     // row leaves last
     const int jstart = r0 - F_HALO;
@@ -173,11 +225,14 @@ __device__ void pre_tile(const T* __restrict__ bands, int64_t bs, int N, const T
         if (XZERO) return T(0);
         return bload<T>(Rx, cval ? node_off(j, N, col, sizeof(T)) : OFF_NONE);
     };
-    auto need1 = [&](int j) { return c_op1 && in_range(j, r0 - 3, r1 + 3); };
+    // upper bands and b: the rows the first sweep needs and the one above
+    // (its lower bands come from there), on every column of the tile (the
+    // halo columns' bands complete their neighbours' rows)
+    auto needb = [&](int j) { return cval && in_range(j, r0 - 4, r1 + 3); };
     pfx[0] = xload(jstart);
     pfx[1] = xload(jstart + 1);
-    load_row(R, node_off(jstart - 1, N, col, sizeof(T)), need1(jstart - 1), bk[5], bb[5]);
-    load_row(R, node_off(jstart, N, col, sizeof(T)), need1(jstart), bk[0], bb[0]);
+    load_upper(R, node_off(jstart - 1, N, col, sizeof(T)), needb(jstart - 1), bk[5], bb[5]);
+    load_upper(R, node_off(jstart, N, col, sizeof(T)), needb(jstart), bk[0], bb[0]);
 #pragma unroll 1
     for (int jb = jstart; jb < jend; jb += 6) {
 #pragma unroll
@@ -187,12 +242,15 @@ __device__ void pre_tile(const T* __restrict__ bands, int64_t bs, int N, const T
             const int j1 = jx - 1, j2 = jx - 2, j3 = jx - 3, jr = jx - 4;
             const int b1 = (ph + 5) % 6, b2 = (ph + 4) % 6, b3 = (ph + 3) % 6;
             const int l1 = (x3 + 2) % 3, l2 = (x3 + 1) % 3;  // LDS slots of rows jx-1, jx-2
-            // 1. x row jx into LDS; prefetch x row jx+2 and the bands of row jx+1
+            // 1. x row jx and the upper bands of row jx-1 into LDS; prefetch x
+            // row jx+2 and the bands of row jx+1
             if (!XZERO) X[x3][t] = pfx[x3];
+            lower.publish(bk[b1], (ph + 1) & 1, t);
             pfx[(x3 + 2) % 3] = xload(jx + 2);
-            load_row(R, node_off(jx + 1, N, col, sizeof(T)), need1(jx + 1), bk[(ph + 1) % 6],
-                     bb[(ph + 1) % 6]);
+            load_upper(R, node_off(jx + 1, N, col, sizeof(T)), needb(jx + 1), bk[(ph + 1) % 6],
+                       bb[(ph + 1) % 6]);
             __syncthreads();
+            lower.complete(bk[b1], bk[b2], ph & 1, t);
             // 2. first sweep at row j1
             {
                 T v = T(0);
@@ -277,6 +335,8 @@ __device__ void post_tile(const T* __restrict__ bands, int64_t bs, int N, const 
                           T* __restrict__ xout, double* __restrict__ rowpart, int strip, int chunk,
                           int rh, int cw) {
     __shared__ T X[3][BT + 2], A[3][BT + 2], B[3][BT + 2];
+    __shared__ T U5[BT + 2], U6[2][BT + 2], U8[2][BT + 2];
+    LowerBands<T, BT> lower{U5, &U6[0][0], &U8[0][0]};
     constexpr int H = NORM ? 3 : 2;  // halo the last step needs
     const int t = threadIdx.x + 1;
     const int c0 = strip * cw, c1 = min(c0 + cw, N);
@@ -295,6 +355,7 @@ __device__ void post_tile(const T* __restrict__ bands, int64_t bs, int N, const 
 #pragma unroll
         for (int s = 0; s < 3; ++s) X[s][g] = A[s][g] = B[s][g] = T(0);
     }
+    lower.init();
     T bk[6][9], bb[6];
     // x and the four coarse values around each x row in flight (slot r mod 3)
     T pfx[3], pc0[3], pc1[3], pc2[3], pc3[3];
@@ -334,11 +395,13 @@ __device__ void post_tile(const T* __restrict__ bands, int64_t bs, int N, const 
             v = T(0.25) * ((c0 + c1) + (c2 + c3));
         return xv + v;
     };
-    auto need1 = [&](int j) { return c_op1 && in_range(j, r0 - (H - 1), r1 + (H - 1)); };
+    // upper bands and b: the first sweep's rows and the one above, on every
+    // column of the tile (see pre_tile)
+    auto needb = [&](int j) { return cval && in_range(j, r0 - H, r1 + (H - 1)); };
     xrow_load(jstart, pfx[0], pc0[0], pc1[0], pc2[0], pc3[0]);
     xrow_load(jstart + 1, pfx[1], pc0[1], pc1[1], pc2[1], pc3[1]);
-    load_row(R, node_off(jstart - 1, N, col, sizeof(T)), need1(jstart - 1), bk[5], bb[5]);
-    load_row(R, node_off(jstart, N, col, sizeof(T)), need1(jstart), bk[0], bb[0]);
+    load_upper(R, node_off(jstart - 1, N, col, sizeof(T)), needb(jstart - 1), bk[5], bb[5]);
+    load_upper(R, node_off(jstart, N, col, sizeof(T)), needb(jstart), bk[0], bb[0]);
 #pragma unroll 1
     for (int jb = jstart; jb < jend; jb += 6) {
 #pragma unroll
@@ -349,13 +412,15 @@ __device__ void post_tile(const T* __restrict__ bands, int64_t bs, int N, const 
             const int b1 = (ph + 5) % 6, b2 = (ph + 4) % 6, b3 = (ph + 3) % 6;
             const int l1 = (x3 + 2) % 3, l2 = (x3 + 1) % 3;
             X[x3][t] = xrow_value(jx, pfx[x3], pc0[x3], pc1[x3], pc2[x3], pc3[x3]);
+            lower.publish(bk[b1], (ph + 1) & 1, t);
             {
                 const int x5 = (x3 + 2) % 3;
                 xrow_load(jx + 2, pfx[x5], pc0[x5], pc1[x5], pc2[x5], pc3[x5]);
             }
-            load_row(R, node_off(jx + 1, N, col, sizeof(T)), need1(jx + 1), bk[(ph + 1) % 6],
-                     bb[(ph + 1) % 6]);
+            load_upper(R, node_off(jx + 1, N, col, sizeof(T)), needb(jx + 1), bk[(ph + 1) % 6],
+                       bb[(ph + 1) % 6]);
             __syncthreads();
+            lower.complete(bk[b1], bk[b2], ph & 1, t);
             {
                 T v = T(0);
                 if (c_op1 && in_range(j1, r0 - (H - 1), r1 + (H - 1)) && in_range(j1, 0, N)) {
