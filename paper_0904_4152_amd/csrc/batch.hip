@@ -283,7 +283,7 @@ __global__ __launch_bounds__(BLOCK) void kb_inner_norm(const BProb* __restrict__
     if (!(flags & mask)) continue;
     if (only_level >= 0 && P.L != only_level) continue;
     const BLevel& lv = P.lv[P.L];
-    const double sq = dev::stencil_tile<float, dev::OP_DEFECT, true, false>(
+    const double sq = dev::stencil_tile<float, dev::OP_DEFECT, true, false, true>(
         lv.bands32, lv.bs, lv.N, lv.n, lv.x32, lv.b32, nullptr, 0.0f, (int64_t)tile * TILE);
     const double s = dev::block_sum(sq);
     if (threadIdx.x == 0) P.partials[tile] = s;
@@ -300,7 +300,7 @@ __global__ __launch_bounds__(BLOCK) void kb_outer_defect(const BProb* __restrict
     const BLevel& lv = P.lv[P.L];
     for (int sub = 0; sub < 2; ++sub) {
         const int64_t blo = (int64_t)(2 * tile + sub) * dev::tile_rows<double>();
-        const double sq = dev::stencil_tile<double, dev::OP_DEFECT, true, true>(
+        const double sq = dev::stencil_tile<double, dev::OP_DEFECT, true, true, true>(
             lv.bands64, lv.bs, lv.N, lv.n, lv.x64, lv.b64, P.d64, 0.0, blo);
         const double s = dev::block_sum(sq);
         if (threadIdx.x == 0) P.partials[2 * tile + sub] = s;

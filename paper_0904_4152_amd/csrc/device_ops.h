@@ -64,7 +64,14 @@ enum { OP_SPMV = 0, OP_DEFECT = 1, OP_JACOBI = 2 };
 // thread owns W consecutive rows.  Tiles at least N+1 rows away from both
 // ends of the vector read the x halo without bounds checks.  Returns the
 // thread's sum of squares of its outputs when NORM.
-template <typename T, int OP, bool NORM, bool STORE>
+//
+// SYM: the matrix is symmetric bit for bit, so the lower bands at p are
+// read as upper bands of the neighbours (band 8 at p-N-1, 7 at p-N, 6 at
+// p-N+1, 5 at p-1; zero before the first row, as stored).  Those rows were
+// streamed by the tiles just before (same XCD), so the shifted reads are
+// served by the cache and HBM sees 5 band streams instead of 9.  Same
+// values, same results.
+template <typename T, int OP, bool NORM, bool STORE, bool SYM = false>
 __device__ __forceinline__ double stencil_tile(const T* __restrict__ bands, int64_t bs, int N,
                                                int64_t n, const T* __restrict__ x,
                                                const T* __restrict__ b, T* __restrict__ out,
@@ -95,10 +102,23 @@ __device__ __forceinline__ double stencil_tile(const T* __restrict__ bands, int6
     }
     T bk[9][W];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) {
-        // band arrays are padded beyond n, so the vector load stays in bounds
-        VT v = __builtin_nontemporal_load(reinterpret_cast<const VT*>(bands + k * bs + p0));
+    for (int k = SYM ? 4 : 0; k < 9; ++k) {
+        // band arrays are padded beyond n, so the vector load stays in bounds;
+        // with SYM the bands read again by later tiles stay cacheable
+        const VT* src = reinterpret_cast<const VT*>(bands + k * bs + p0);
+        VT v = (!SYM || k == 4) ? __builtin_nontemporal_load(src) : *src;
         __builtin_memcpy(bk[k], &v, sizeof(VT));
+    }
+    if (SYM) {
+        const int64_t sh[4] = {-(int64_t)N - 1, -(int64_t)N, -(int64_t)N + 1, -1};
+        const int up[4] = {8, 7, 6, 5};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const T* src = bands + up[k] * bs + p0 + sh[k];
+#pragma unroll
+            for (int v = 0; v < W; ++v)
+                bk[k][v] = (fast || p0 + v + sh[k] >= 0) ? src[v] : T(0);
+        }
     }
     T res[W];
 #pragma unroll

@@ -1,7 +1,7 @@
 // Fused smoothing passes of the V(2,2) cycle.  One workgroup owns a strip
 // of grid columns and a chunk of grid rows and marches down the rows; each
 // row of bands, x and b is read from HBM once and kept (bands in a register
-// ring of three rows, iterates in LDS rings of three rows) while every
+// ring of six rows, iterates in LDS rings of three rows) while every
 // fused step that needs it runs:
 //   pre  : two damped Jacobi sweeps (the first possibly from a zero
 //          iterate), the defect of the result and its restriction P^T d to
@@ -13,19 +13,23 @@
 // Strips overlap by F_HALO columns and chunks by F_HALO rows; the overlap is
 // recomputed and only owned nodes are written.
 //
-// Rows of x and of bands are loaded two steps ahead of their use, so that
-// enough bytes are in flight per wavefront to cover HBM latency.
-// Row bookkeeping of one step: the x row jx enters; the first sweep runs at
-// row jx-1, the second at jx-2, the defect (pre) or norm (post) at jx-3 and
-// the restriction (pre) at jx-4.  With j0 the first row of the march, an
-// iterate row j lives in LDS slot (j - j0) mod 3 and a band row in register
-// slot (j - j0) mod 6; the loop is unrolled by six so every slot index is a
-// compile-time constant.  The march starts at the first row that is needed
-// and runs whole blocks of six steps past the last one (the extra steps
-// compute nothing that is kept).
+// Rows of x and of bands are loaded two to three steps ahead of their use,
+// so that enough bytes are in flight per wavefront to cover HBM latency.
+// Row bookkeeping of one step of the pre pass: the x row jx enters; after a
+// first barrier the first sweep runs at row jx-1 and the defect at jx-4,
+// after a second barrier the second sweep at jx-2 and the restriction at
+// jx-5.  The post pass runs the first sweep at jx-1, the second at jx-2 and
+// the norm at jx-3, a barrier before each.  With j0 the first row of the
+// march, an iterate row j lives
+// in LDS slot (j - j0) mod 3 and a band row in register slot (j - j0) mod 6;
+// the loop is unrolled by six so every slot index is a compile-time
+// constant.  The march starts at the first row that is needed and runs
+// whole blocks of six steps past the last one (the extra steps compute
+// nothing that is kept).
 #pragma once
 
 #include "device_ops.h"
+#include "mgfem.h"
 
 namespace mg {
 namespace dev {
@@ -56,6 +60,11 @@ __host__ __device__ inline FusedGeom fused_geom(int N, int bt, int rh) {
 }
 
 __device__ __forceinline__ bool in_range(int v, int lo, int hi) { return v >= lo && v < hi; }
+
+// v in [lo, hi) for lo <= hi, with one compare.
+__device__ __forceinline__ bool in_win(int v, int lo, int hi) {
+    return (unsigned)(v - lo) < (unsigned)(hi - lo);
+}
 
 // The 9-term band product at one node from the rows j-1, j, j+1 of an
 // iterate held in LDS, around LDS column t: the fma chain of stencil_tile.
@@ -113,8 +122,14 @@ struct RowRsrc {
     }
 };
 
-// Byte offset past every buffer: a load from it returns zero.
-constexpr uint32_t OFF_NONE = 0x80000000u;
+// Byte offset past every buffer: a load from it returns zero.  The largest
+// buffer (an FP64 vector at the finest admitted level, 16385^2 x 8 B) is
+// just over 2 GiB, so the offset sits at 3 GiB, with room below 2^32 for the
+// small strides added to it.
+constexpr uint32_t OFF_NONE = 0xC0000000u;
+static_assert((uint64_t)((1 << MG_MAX_LEVEL) + 1) * ((1 << MG_MAX_LEVEL) + 1) * sizeof(double) <
+                  (uint64_t)OFF_NONE,
+              "out-of-range offset inside a buffer");
 
 // Bands and b of one node at byte offset off; zeros when !need.  The loads
 // are issued on every lane (an unneeded lane reads past the buffer), so no
@@ -186,8 +201,18 @@ __device__ __forceinline__ uint32_t node_off(int j, int N, int col, int size) {
 // x2 = J(J(x)) on owned nodes and bc = P^T (b - A x2) on the owned coarse
 // nodes (0 at coarse nodes on the Dirichlet sides of dmask).  With XZERO the
 // first sweep starts from a zero iterate and x is not read.  Band rows live
-// in a ring of six register slots (the loop is unrolled by six) so that the
-// load of a row lands in its slot two steps before its first use.
+// in a ring of six register slots (the loop is unrolled by six): the load of
+// row jx+2 goes out in step jx as soon as the defect has freed its slot, two
+// and a half steps before the row is first used; x rows go out three steps
+// ahead.
+//
+// One step (x row jx entering) runs in two barrier-separated phases: phase A
+// takes the first sweep at row jx-1 (from the x rows written before the
+// first barrier) and the defect at row jx-4 (from second-sweep rows of
+// earlier steps); phase B takes the second sweep at row jx-2 (from the
+// first-sweep row of phase A) and the restriction at row jx-5 (from the
+// defect row of phase A).  Every LDS row ring has three slots: a slot is
+// rewritten only in a window that no reader of its old row shares.
 template <typename T, bool XZERO, int BT>
 __device__ void pre_tile(const T* __restrict__ bands, int64_t bs, int N, const T* __restrict__ x,
                          const T* __restrict__ b, T omega, T* __restrict__ x2out,
@@ -200,11 +225,16 @@ __device__ void pre_tile(const T* __restrict__ bands, int64_t bs, int N, const T
     const int r0 = chunk * rh, r1 = min(r0 + rh, N);
     const int col = c0 - F_HALO + (int)threadIdx.x;
     const bool cval = col >= 0 && col < N;
-    // column / row ranges where each step is needed
+    // column / row ranges where each step is needed (rows clipped to the
+    // grid: rows outside it hold zeros)
     const bool c_op1 = cval && in_range(col, c0 - 3, c1 + 3);
     const bool c_op2 = cval && in_range(col, c0 - 2, c1 + 2);
     const bool c_op3 = cval && in_range(col, c0 - 1, c1 + 1);
     const bool c_own = in_range(col, c0, c1);
+    const bool c_coarse = c_own && !(col & 1);
+    const int lo1 = max(r0 - 3, 0), hi1 = min(r1 + 3, N);
+    const int lo2 = max(r0 - 2, 0), hi2 = min(r1 + 2, N);
+    const int lo3 = max(r0 - 1, 0), hi3 = min(r1 + 1, N);
     const int Nc = (N >> 1) + 1;
     const int64_t n = (int64_t)N * N;
     const RowRsrc<T> R(bands, bs, b, n);
@@ -215,91 +245,89 @@ __device__ void pre_tile(const T* __restrict__ bands, int64_t bs, int N, const T
         for (int s = 0; s < 3; ++s) X[s][g] = A[s][g] = B[s][g] = D[s][g] = T(0);
     }
     lower.init();
-    T bk[6][9], bb[6];  // band rows, slot (r - jstart) mod 6
-    T pfx[3];           // x rows, slot (r - jstart) mod 3
-    // the first x row any sweep needs enters first; the last restriction
-    // row leaves last
-    const int jstart = r0 - F_HALO;
-    const int jend = r1 + 4;
+    T bk[6][9], bb[6];  // band rows, slot (r - js) mod 6
+    T pfx[3];           // x rows, slot (r - js) mod 3 (LDS rows likewise)
+    // The first x row any sweep needs (r0 - F_HALO) enters LDS before the
+    // loop, whose first step brings in the next; the last restriction row
+    // leaves last.
+    const int js = r0 - F_HALO + 1;
+    const int jend = r1 + 5;
     auto xload = [&](int j) -> T {
         if (XZERO) return T(0);
-        return bload<T>(Rx, cval ? node_off(j, N, col, sizeof(T)) : OFF_NONE);
+        return bload<T>(Rx, cval && j < r1 + 4 ? node_off(j, N, col, sizeof(T)) : OFF_NONE);
     };
     // upper bands and b: the rows the first sweep needs and the one above
     // (its lower bands come from there), on every column of the tile (the
     // halo columns' bands complete their neighbours' rows)
     auto needb = [&](int j) { return cval && in_range(j, r0 - 4, r1 + 3); };
-    pfx[0] = xload(jstart);
-    pfx[1] = xload(jstart + 1);
-    load_upper(R, node_off(jstart - 1, N, col, sizeof(T)), needb(jstart - 1), bk[5], bb[5]);
-    load_upper(R, node_off(jstart, N, col, sizeof(T)), needb(jstart), bk[0], bb[0]);
+    if (!XZERO) X[2][t] = xload(js - 1);  // slot of row js - 1
+    pfx[0] = xload(js);
+    pfx[1] = xload(js + 1);
+    pfx[2] = xload(js + 2);
+    load_upper(R, node_off(js - 1, N, col, sizeof(T)), needb(js - 1), bk[5], bb[5]);
+    load_upper(R, node_off(js, N, col, sizeof(T)), needb(js), bk[0], bb[0]);
+    load_upper(R, node_off(js + 1, N, col, sizeof(T)), needb(js + 1), bk[1], bb[1]);
 #pragma unroll 1
-    for (int jb = jstart; jb < jend; jb += 6) {
+    for (int jb = js; jb < jend; jb += 6) {
 #pragma unroll
         for (int ph = 0; ph < 6; ++ph) {
             const int jx = jb + ph;  // x row entering: LDS slot x3
             const int x3 = ph % 3;
-            const int j1 = jx - 1, j2 = jx - 2, j3 = jx - 3, jr = jx - 4;
-            const int b1 = (ph + 5) % 6, b2 = (ph + 4) % 6, b3 = (ph + 3) % 6;
-            const int l1 = (x3 + 2) % 3, l2 = (x3 + 1) % 3;  // LDS slots of rows jx-1, jx-2
-            // 1. x row jx and the upper bands of row jx-1 into LDS; prefetch x
-            // row jx+2 and the bands of row jx+1
+            const int j1 = jx - 1, j2 = jx - 2, jd = jx - 4, jr = jx - 5;
+            const int b1 = (ph + 5) % 6, b2 = (ph + 4) % 6, bd = (ph + 2) % 6;
+            // LDS slots: x3 holds rows jx, jx-3, jx-6; l1 rows jx-1, jx-4;
+            // l2 rows jx-2, jx-5
+            const int l1 = (x3 + 2) % 3, l2 = (x3 + 1) % 3;
+            // x row jx and the upper bands of row jx-1 into LDS; prefetch x
+            // row jx+3 into the register just freed
             if (!XZERO) X[x3][t] = pfx[x3];
             lower.publish(bk[b1], (ph + 1) & 1, t);
-            pfx[(x3 + 2) % 3] = xload(jx + 2);
-            load_upper(R, node_off(jx + 1, N, col, sizeof(T)), needb(jx + 1), bk[(ph + 1) % 6],
-                       bb[(ph + 1) % 6]);
+            pfx[x3] = xload(jx + 3);
             __syncthreads();
+            // ---- phase A
             lower.complete(bk[b1], bk[b2], ph & 1, t);
-            // 2. first sweep at row j1
+            // Every lane computes each step (lanes and rows outside a step's
+            // window select zero), so the steps run without divergent
+            // branches.
+            // first sweep at row j1
             {
-                T v = T(0);
-                if (c_op1 && in_range(j1, r0 - 3, r1 + 3) && in_range(j1, 0, N)) {
-                    if (XZERO) {
-                        v = omega * bb[b1] / bk[b1][4];
-                    } else {
-                        const T acc = band_row_product(bk[b1], X[l2], X[l1], X[x3], t);
-                        v = X[l1][t] + omega * (bb[b1] - acc) / bk[b1][4];
-                    }
+                T v;
+                if (XZERO) {
+                    v = omega * bb[b1] / bk[b1][4];
+                } else {
+                    const T acc = band_row_product(bk[b1], X[l2], X[l1], X[x3], t);
+                    v = X[l1][t] + omega * (bb[b1] - acc) / bk[b1][4];
                 }
-                A[l1][t] = v;
+                A[l1][t] = (c_op1 & in_win(j1, lo1, hi1)) ? v : T(0);
             }
-            __syncthreads();
-            // 3. second sweep at row j2 (written on owned nodes)
+            // defect at row jd from second-sweep rows jd-1, jd, jd+1
             {
-                T v = T(0);
-                if (c_op2 && in_range(j2, r0 - 2, r1 + 2) && in_range(j2, 0, N)) {
-                    const T acc = band_row_product(bk[b2], A[x3], A[l2], A[l1], t);
-                    v = A[l2][t] + omega * (bb[b2] - acc) / bk[b2][4];
-                    if (c_own && in_range(j2, r0, r1)) x2out[(int64_t)j2 * N + col] = v;
-                }
+                const T acc = band_row_product(bk[bd], B[l2], B[l1], B[x3], t);
+                D[l1][t] = (c_op3 & in_win(jd, lo3, hi3)) ? bb[bd] - acc : T(0);
+            }
+            // the bands of row jx+2 into the slot row jd no longer needs
+            load_upper(R, node_off(jx + 2, N, col, sizeof(T)), needb(jx + 2), bk[bd], bb[bd]);
+            __syncthreads();
+            // ---- phase B
+            // second sweep at row j2 (written on owned nodes)
+            {
+                const T acc = band_row_product(bk[b2], A[x3], A[l2], A[l1], t);
+                T v = A[l2][t] + omega * (bb[b2] - acc) / bk[b2][4];
+                v = (c_op2 & in_win(j2, lo2, hi2)) ? v : T(0);
+                if (in_win(j2, r0, r1) && c_own) x2out[(int64_t)j2 * N + col] = v;
                 B[l2][t] = v;
             }
-            __syncthreads();
-            // 4. defect at row j3
-            {
-                T v = T(0);
-                if (c_op3 && in_range(j3, r0 - 1, r1 + 1) && in_range(j3, 0, N)) {
-                    const T acc = band_row_product(bk[b3], B[l1], B[x3], B[l2], t);
-                    v = bb[b3] - acc;
-                }
-                D[x3][t] = v;
-            }
-            __syncthreads();
-            // 5. restriction of defect rows jr-1, jr, jr+1 to coarse row jr/2
-            if (in_range(jr, r0, r1) && !(jr & 1) && c_own && !(col & 1)) {
+            // restriction of defect rows jr-1, jr, jr+1 to coarse row jr/2
+            if (in_win(jr, r0, r1) && !(jr & 1)) {
                 const int I = col >> 1, J = jr >> 1;
-                T s = T(0);
                 // defect columns and rows outside the grid are zero in LDS
-                if (!is_dirichlet(Nc, I, J, dmask)) {
-                    const T* u = D[l2];  // row jr - 1
-                    const T* c = D[l1];  // row jr
-                    const T* o = D[x3];  // row jr + 1
-                    const T corner = (u[t - 1] + u[t + 1]) + (o[t - 1] + o[t + 1]);
-                    const T edge = (u[t] + o[t]) + (c[t - 1] + c[t + 1]);
-                    s = c[t] + T(0.5) * edge + T(0.25) * corner;
-                }
-                bc[(int64_t)J * Nc + I] = s;
+                const T* u = D[x3];  // row jr - 1
+                const T* c = D[l2];  // row jr
+                const T* o = D[l1];  // row jr + 1
+                const T corner = (u[t - 1] + u[t + 1]) + (o[t - 1] + o[t + 1]);
+                const T edge = (u[t] + o[t]) + (c[t - 1] + c[t + 1]);
+                const T s = c[t] + T(0.5) * edge + T(0.25) * corner;
+                if (c_coarse) bc[(int64_t)J * Nc + I] = is_dirichlet(Nc, I, J, dmask) ? T(0) : s;
             }
         }
     }
@@ -327,8 +355,9 @@ __device__ __forceinline__ double wave_sum(double v) {
 // over the owned columns that wavefront w holds in the rows of group G (rows
 // 4G .. 4G+3; NG groups), each lane adding its rows in order before the
 // wavefront sum: the partial sums do not depend on how rows are split into
-// chunks, and need no workgroup barrier.  Same row pipeline and register
-// ring as pre_tile.
+// chunks, and need no workgroup barrier.  Same register ring as pre_tile;
+// a barrier before each of the first sweep (row jx-1), the second (row
+// jx-2) and the norm (row jx-3).
 template <typename T, bool NORM, int BT>
 __device__ void post_tile(const T* __restrict__ bands, int64_t bs, int N, const T* __restrict__ x,
                           const T* __restrict__ xc, const T* __restrict__ b, T omega,
@@ -347,6 +376,8 @@ __device__ void post_tile(const T* __restrict__ bands, int64_t bs, int N, const 
     const bool c_op1 = cval && in_range(col, c0 - (H - 1), c1 + (H - 1));
     const bool c_op2 = cval && in_range(col, c0 - (H - 2), c1 + (H - 2));
     const bool c_own = in_range(col, c0, c1);
+    const int lo1 = max(r0 - (H - 1), 0), hi1 = min(r1 + (H - 1), N);
+    const int lo2 = max(r0 - (H - 2), 0), hi2 = min(r1 + (H - 2), N);
     const int64_t n = (int64_t)N * N;
     const RowRsrc<T> R(bands, bs, b, n);
     const rsrc_t Rx = make_rsrc(x, n * (int64_t)sizeof(T));
@@ -367,7 +398,7 @@ __device__ void post_tile(const T* __restrict__ bands, int64_t bs, int N, const 
     const int jend = r1 + (NORM ? 3 : 2);
     // x row j plus its coarse correction P x_c (the arithmetic of
     // prolong_elem): the x value and the four coarse values around the node
-    // are loaded two steps ahead and combined when the row enters
+    // are loaded ahead and combined when the row enters
     const int Nc = (N >> 1) + 1;
     const rsrc_t Rc = make_rsrc(xc, (int64_t)Nc * Nc * (int64_t)sizeof(T));
     auto x_use = [&](int j) { return c_x && in_range(j, r0 - H, r1 + H) && in_range(j, 0, N); };
@@ -382,26 +413,27 @@ __device__ void post_tile(const T* __restrict__ bands, int64_t bs, int N, const 
         c2 = bload<T>(Rc, oc + (uint32_t)(Nc * sizeof(T)));
         c3 = bload<T>(Rc, oc + (uint32_t)((Nc + 1) * sizeof(T)));
     };
+    const bool c_even = !(col & 1);
     auto xrow_value = [&](int j, T xv, T c0, T c1, T c2, T c3) -> T {
-        if (!x_use(j)) return T(0);
-        T v;
-        if (!(col & 1) && !(j & 1))
-            v = c0;
-        else if (!(j & 1))
-            v = T(0.5) * (c0 + c1);
-        else if (!(col & 1))
-            v = T(0.5) * (c0 + c2);
-        else
-            v = T(0.25) * ((c0 + c1) + (c2 + c3));
-        return xv + v;
+        // every case is evaluated and one selected (no divergent branch)
+        const T v_row = c_even ? c0 : T(0.5) * (c0 + c1);  // even grid row
+        const T v_odd = c_even ? T(0.5) * (c0 + c2) : T(0.25) * ((c0 + c1) + (c2 + c3));
+        const T v = (j & 1) ? v_odd : v_row;
+        return x_use(j) ? xv + v : T(0);
     };
     // upper bands and b: the first sweep's rows and the one above, on every
     // column of the tile (see pre_tile)
     auto needb = [&](int j) { return cval && in_range(j, r0 - H, r1 + (H - 1)); };
+    // Without NORM no step reads row jx-3 and the register ring has room to
+    // load bands and x one row further ahead (three rows in flight).
+    constexpr int AHEAD = NORM ? 2 : 3;
     xrow_load(jstart, pfx[0], pc0[0], pc1[0], pc2[0], pc3[0]);
     xrow_load(jstart + 1, pfx[1], pc0[1], pc1[1], pc2[1], pc3[1]);
+    if (AHEAD == 3) xrow_load(jstart + 2, pfx[2], pc0[2], pc1[2], pc2[2], pc3[2]);
     load_upper(R, node_off(jstart - 1, N, col, sizeof(T)), needb(jstart - 1), bk[5], bb[5]);
     load_upper(R, node_off(jstart, N, col, sizeof(T)), needb(jstart), bk[0], bb[0]);
+    if (AHEAD == 3)
+        load_upper(R, node_off(jstart + 1, N, col, sizeof(T)), needb(jstart + 1), bk[1], bb[1]);
 #pragma unroll 1
     for (int jb = jstart; jb < jend; jb += 6) {
 #pragma unroll
@@ -414,37 +446,36 @@ __device__ void post_tile(const T* __restrict__ bands, int64_t bs, int N, const 
             X[x3][t] = xrow_value(jx, pfx[x3], pc0[x3], pc1[x3], pc2[x3], pc3[x3]);
             lower.publish(bk[b1], (ph + 1) & 1, t);
             {
-                const int x5 = (x3 + 2) % 3;
-                xrow_load(jx + 2, pfx[x5], pc0[x5], pc1[x5], pc2[x5], pc3[x5]);
+                // x row jx+AHEAD into its slot (the one just written to LDS
+                // when three rows are in flight)
+                const int xs = (x3 + AHEAD) % 3;
+                xrow_load(jx + AHEAD, pfx[xs], pc0[xs], pc1[xs], pc2[xs], pc3[xs]);
             }
-            load_upper(R, node_off(jx + 1, N, col, sizeof(T)), needb(jx + 1), bk[(ph + 1) % 6],
-                       bb[(ph + 1) % 6]);
+            load_upper(R, node_off(jx + AHEAD - 1, N, col, sizeof(T)), needb(jx + AHEAD - 1),
+                       bk[(ph + AHEAD - 1) % 6], bb[(ph + AHEAD - 1) % 6]);
             __syncthreads();
             lower.complete(bk[b1], bk[b2], ph & 1, t);
+            // every lane computes each sweep (lanes and rows outside the
+            // sweep's window select zero): no divergent branches
             {
-                T v = T(0);
-                if (c_op1 && in_range(j1, r0 - (H - 1), r1 + (H - 1)) && in_range(j1, 0, N)) {
-                    const T acc = band_row_product(bk[b1], X[l2], X[l1], X[x3], t);
-                    v = X[l1][t] + omega * (bb[b1] - acc) / bk[b1][4];
-                }
-                A[l1][t] = v;
+                const T acc = band_row_product(bk[b1], X[l2], X[l1], X[x3], t);
+                const T v = X[l1][t] + omega * (bb[b1] - acc) / bk[b1][4];
+                A[l1][t] = (c_op1 & in_win(j1, lo1, hi1)) ? v : T(0);
             }
             __syncthreads();
             {
-                T v = T(0);
-                if (c_op2 && in_range(j2, r0 - (H - 2), r1 + (H - 2)) && in_range(j2, 0, N)) {
-                    const T acc = band_row_product(bk[b2], A[x3], A[l2], A[l1], t);
-                    v = A[l2][t] + omega * (bb[b2] - acc) / bk[b2][4];
-                    if (c_own && in_range(j2, r0, r1)) xout[(int64_t)j2 * N + col] = v;
-                }
+                const T acc = band_row_product(bk[b2], A[x3], A[l2], A[l1], t);
+                T v = A[l2][t] + omega * (bb[b2] - acc) / bk[b2][4];
+                v = (c_op2 & in_win(j2, lo2, hi2)) ? v : T(0);
+                if (in_win(j2, r0, r1) && c_own) xout[(int64_t)j2 * N + col] = v;
                 if (NORM) B[l2][t] = v;
             }
             if (NORM) __syncthreads();
-            if (NORM && in_range(j3, r0, r1)) {
-                if (c_own) {
+            if (NORM && in_win(j3, r0, r1)) {
+                {
                     const T acc = band_row_product(bk[b3], B[l1], B[x3], B[l2], t);
                     const T d = bb[b3] - acc;
-                    nacc += (double)d * (double)d;
+                    nacc += c_own ? (double)d * (double)d : 0.0;
                 }
                 if ((j3 % F_NORM_ROWS) == F_NORM_ROWS - 1 || j3 == r1 - 1) {
                     const double w = wave_sum(nacc);

@@ -40,7 +40,7 @@ __device__ __forceinline__ int64_t xcd_block(int64_t nblk) {
 inline unsigned grid8(int64_t nblk) { return (unsigned)((nblk + 7) / 8 * 8); }
 
 // One tile per workgroup of the band product family (see dev::stencil_tile).
-template <typename T, int OP, bool NORM, bool STORE>
+template <typename T, int OP, bool NORM, bool STORE, bool SYM = false>
 __global__ __launch_bounds__(BLOCK) void k_stencil(const T* __restrict__ bands, int64_t bs,
                                                    int N, int64_t n, const T* __restrict__ x,
                                                    const T* __restrict__ b,
@@ -48,7 +48,7 @@ __global__ __launch_bounds__(BLOCK) void k_stencil(const T* __restrict__ bands, 
                                                    double* __restrict__ partials, int64_t nblk) {
     const int64_t lb = xcd_block(nblk);
     if (lb < 0) return;
-    const double sq = dev::stencil_tile<T, OP, NORM, STORE>(
+    const double sq = dev::stencil_tile<T, OP, NORM, STORE, SYM>(
         bands, bs, N, n, x, b, out, omega, lb * (int64_t)dev::tile_rows<T>());
     if (NORM) {
         const double s = dev::block_sum(sq);
@@ -666,11 +666,17 @@ hipError_t launch_rhs_uniform(int N, uint64_t seed, int dmask, double* b, double
 }
 
 template <typename T>
-hipError_t launch_spmv(const Level& lv, const T* bands, const T* x, T* y, hipStream_t st) {
+hipError_t launch_spmv(const Level& lv, const T* bands, const T* x, T* y, hipStream_t st,
+                       bool sym) {
     const int64_t nb = stencil_blocks(lv.n, sizeof(T));
-    hipLaunchKernelGGL((k_stencil<T, OP_SPMV, false, true>), dim3(grid8(nb)), dim3(BLOCK), 0, st,
-                       bands, lv.bs, lv.N, lv.n, x, (const T*)nullptr, y, T(0),
-                       (double*)nullptr, nb);
+    if (sym)
+        hipLaunchKernelGGL((k_stencil<T, OP_SPMV, false, true, true>), dim3(grid8(nb)),
+                           dim3(BLOCK), 0, st, bands, lv.bs, lv.N, lv.n, x, (const T*)nullptr, y,
+                           T(0), (double*)nullptr, nb);
+    else
+        hipLaunchKernelGGL((k_stencil<T, OP_SPMV, false, true>), dim3(grid8(nb)), dim3(BLOCK), 0,
+                           st, bands, lv.bs, lv.N, lv.n, x, (const T*)nullptr, y, T(0),
+                           (double*)nullptr, nb);
     return hipGetLastError();
 }
 
@@ -680,14 +686,14 @@ hipError_t launch_defect(const Level& lv, const T* bands, const T* b, const T* x
     const int64_t nb = stencil_blocks(lv.n, sizeof(T));
     const dim3 g(grid8(nb)), blk(BLOCK);
     if (partials && d)
-        hipLaunchKernelGGL((k_stencil<T, OP_DEFECT, true, true>), g, blk, 0, st, bands, lv.bs,
-                           lv.N, lv.n, x, b, d, T(0), partials, nb);
+        hipLaunchKernelGGL((k_stencil<T, OP_DEFECT, true, true, true>), g, blk, 0, st, bands,
+                           lv.bs, lv.N, lv.n, x, b, d, T(0), partials, nb);
     else if (partials)
-        hipLaunchKernelGGL((k_stencil<T, OP_DEFECT, true, false>), g, blk, 0, st, bands, lv.bs,
-                           lv.N, lv.n, x, b, (T*)nullptr, T(0), partials, nb);
+        hipLaunchKernelGGL((k_stencil<T, OP_DEFECT, true, false, true>), g, blk, 0, st, bands,
+                           lv.bs, lv.N, lv.n, x, b, (T*)nullptr, T(0), partials, nb);
     else
-        hipLaunchKernelGGL((k_stencil<T, OP_DEFECT, false, true>), g, blk, 0, st, bands, lv.bs,
-                           lv.N, lv.n, x, b, d, T(0), (double*)nullptr, nb);
+        hipLaunchKernelGGL((k_stencil<T, OP_DEFECT, false, true, true>), g, blk, 0, st, bands,
+                           lv.bs, lv.N, lv.n, x, b, d, T(0), (double*)nullptr, nb);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !partials) return e;
     return launch_reduce(partials, nb, scal, slot, host, st);
@@ -933,7 +939,7 @@ hipError_t launch_scalar_copy(double* scal, int from, int to, hipStream_t st) {
 }
 
 #define MG_INSTANTIATE(T)                                                                     \
-    template hipError_t launch_spmv<T>(const Level&, const T*, const T*, T*, hipStream_t);    \
+    template hipError_t launch_spmv<T>(const Level&, const T*, const T*, T*, hipStream_t, bool); \
     template hipError_t launch_defect<T>(const Level&, const T*, const T*, const T*, T*,      \
                                          double*, double*, int, double*, hipStream_t);        \
     template hipError_t launch_jacobi<T>(const Level&, const T*, const T*, const T*, T*, T,   \

@@ -131,7 +131,10 @@ hipError_t launch_rhs_uniform(int N, uint64_t seed, int dmask, double* b, double
 
 // Stencil family on one level.
 template <typename T>
-hipError_t launch_spmv(const Level& lv, const T* bands, const T* x, T* y, hipStream_t st);
+// sym: read the lower bands as shifted upper bands (same values for the
+// assembled, symmetric matrices; five band streams from HBM instead of nine).
+hipError_t launch_spmv(const Level& lv, const T* bands, const T* x, T* y, hipStream_t st,
+                       bool sym = false);
 // Reductions land in scal[slot] (sum of squares) and scal[slot+1] (norm) in
 // device memory and, when host is not null, also in host[slot], host[slot+1]
 // (pinned memory, for the host to read once the stream has synchronized).

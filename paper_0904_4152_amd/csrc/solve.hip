@@ -203,7 +203,7 @@ static hipError_t enqueue_pcg_step(mg_hierarchy* h, bool mixed, int nu_pre, int 
         q.bytes += (12.0 + 12.0 + 20.0) * dn;
     }
     MG_TRY(launch_scalar_copy(h->scal, SC_RZ, SC_RZ_OLD, q.st));
-    MG_TRY(launch_spmv<double>(F, F.bands64, p, zq, q.st));
+    MG_TRY(launch_spmv<double>(F, F.bands64, p, zq, q.st, true));
     MG_TRY(launch_dot<double>(p, zq, n, h->scal, -1, h->partials, h->scal, SC_PQ, q.st));
     MG_TRY(launch_pcg_step(F.x64, r, p, zq, n, h->scal, SC_RZ, SC_PQ, h->partials, SC_RR,
                            h->host_scal, q.st));

@@ -1,5 +1,6 @@
 """The largest problem the boundary accepts, L = 14 (16385 x 16385 =
-268,468,225 unknowns, about 58 GB of hierarchy), solved in mixed precision.
+268,468,225 unknowns, about 58 GB of hierarchy), solved in mixed precision,
+and the FP64 fused passes at that size (vectors over 2 GiB).
 
 Too large for the oracle to solve, so the checks use properties that hold at
 any size, on a random sample of nodes: each sampled row of the device
@@ -115,4 +116,44 @@ def test_level_14_mixed_solve(mg, orc):
     assert np.all(np.abs(r) <= rnorm)
     est = np.sqrt(np.mean(r * r) * h.n)
     assert rnorm / 3 <= est <= 3 * rnorm, (est, rnorm)
+    h.close()
+
+
+def test_level_14_fp64_fused_passes_equal_separate_kernels(mg):
+    """FP64 vectors at L = 14 hold 2,147,745,800 bytes, past 2^31: the fused
+    passes' zero-returning loads (halo columns outside the grid, rows outside
+    a tile's window) must still fall outside every buffer.  The pre pass
+    equals two sweeps, the defect and the restriction, and the post pass the
+    prolongation and two sweeps, bit for bit, as at small sizes."""
+    ctx = mg.Context(0)
+    h = mg.Hierarchy(ctx, L, jitter=A_JIT, seed=GSEED)
+    n, nc = h.n, ((1 << (L - 1)) + 1) ** 2
+    assert n * 8 > 2 ** 31
+    g = torch.Generator(device="cuda")
+    g.manual_seed(1414)
+    b = torch.randn(n, dtype=torch.float64, device="cuda", generator=g)
+    x = torch.randn(n, dtype=torch.float64, device="cuda", generator=g)
+    xc = torch.randn(nc, dtype=torch.float64, device="cuda", generator=g)
+    out = torch.empty_like(x)
+    bc = torch.empty_like(xc)
+    h.pre_smooth(L, b, x, out, bc)
+    t1 = torch.empty_like(x)
+    t2 = torch.empty_like(x)
+    h.jacobi(L, b, x, t1, 0.7)
+    h.jacobi(L, b, t1, t2, 0.7)
+    assert torch.equal(out, t2)
+    h.defect(L, b, t2, t1)
+    bc2 = torch.empty_like(bc)
+    h.restrict(L, t1, bc2)
+    assert torch.equal(bc, bc2)
+    nrm = h.post_smooth(L, b, x, xc, out, norm=True)
+    t1.copy_(x)
+    h.prolong(L, xc, t1)
+    h.jacobi(L, b, t1, t2, 0.7)
+    h.jacobi(L, b, t2, t1, 0.7)
+    assert torch.equal(out, t1)
+    # the norm sums in another order: rounding-level agreement
+    ref = h.defect(L, b, t1, t2, norm=True)
+    assert abs(nrm - ref) <= 1e-12 * ref
+    del b, x, xc, out, bc, t1, t2, bc2
     h.close()
