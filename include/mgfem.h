@@ -198,7 +198,9 @@ mg_status mg_rhs_uniform(const mg_hierarchy* h, uint64_t seed, double* dev_b, vo
  * residual ||r|| <= rel_tol ||b||; stats.cycles counts CG steps (one cycle
  * each), res_hist the recurrence residuals, rel_res the true residual at
  * exit; inner_reduction and inner_max_cycles are unused.
- * Returns after the result is in dev_x (synchronises stream).  Not thread
+ * Returns after the result is in dev_x (synchronises stream).  The mixed
+ * solver updates dev_x in place as it goes (the others write it at the
+ * end), so dev_x holds the last iterate also after an error.  Not thread
  * safe per hierarchy.  stats may be NULL. */
 mg_status mg_solve(mg_hierarchy* h, const double* dev_b, double* dev_x,
                    const mg_solve_opts* opts, void* stream, mg_stats* stats);

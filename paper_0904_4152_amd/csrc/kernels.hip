@@ -491,6 +491,33 @@ __global__ __launch_bounds__(BLOCK) void k_cast_scaled(const double* __restrict_
     d32[p] = s > 0.0 ? (float)(d[p] / s) : 0.0f;
 }
 
+// k_cast_scaled and the norm partials of its output in one pass: per norm
+// tile, the elements and summation order of k_sumsq (same partials, bit for
+// bit).
+__global__ __launch_bounds__(BLOCK) void k_cast_scaled_sumsq(const double* __restrict__ d,
+                                                             float* __restrict__ d32, int64_t n,
+                                                             const double* __restrict__ scal,
+                                                             int slot,
+                                                             double* __restrict__ partials,
+                                                             int64_t nblk) {
+    const int64_t lb = xcd_block(nblk);
+    if (lb < 0) return;
+    const double s = scal[slot + 1];
+    const int64_t base = lb * (int64_t)dev::NORM_TILE;
+    double acc = 0.0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int64_t p = base + (int64_t)e * BLOCK + threadIdx.x;
+        if (p < n) {
+            const float v = s > 0.0 ? (float)(d[p] / s) : 0.0f;
+            d32[p] = v;
+            acc += (double)v * (double)v;
+        }
+    }
+    const double t = dev::block_sum(acc);
+    if (threadIdx.x == 0) partials[lb] = t;
+}
+
 __global__ __launch_bounds__(BLOCK) void k_update(double* __restrict__ x,
                                                   const float* __restrict__ c, int64_t n,
                                                   const double* __restrict__ scal, int slot) {
@@ -887,6 +914,17 @@ hipError_t launch_cast_scaled(const double* d64, float* d32, int64_t n, const do
     hipLaunchKernelGGL(k_cast_scaled, dim3(blocks1d(n)), dim3(BLOCK), 0, st, d64, d32, n, scal,
                        slot);
     return hipGetLastError();
+}
+
+hipError_t launch_cast_scaled_norm(const double* d64, float* d32, int64_t n, const double* scal,
+                                   int slot, double* partials, double* out_scal, int out_slot,
+                                   double* host, hipStream_t st) {
+    const int64_t nb = norm_blocks(n);
+    hipLaunchKernelGGL(k_cast_scaled_sumsq, dim3(grid8(nb)), dim3(BLOCK), 0, st, d64, d32, n, scal,
+                       slot, partials, nb);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_reduce(partials, nb, out_scal, out_slot, host, st);
 }
 
 hipError_t launch_update(double* x, const float* c32, int64_t n, const double* scal, int slot,

@@ -168,6 +168,11 @@ hipError_t launch_fill(T* v, int64_t n, T value, hipStream_t st);
 // d32 = float(d64 / s) with s = scal[slot + 1] (0 if s == 0).
 hipError_t launch_cast_scaled(const double* d64, float* d32, int64_t n, const double* scal,
                               int slot, hipStream_t st);
+// The same, followed by launch_norm of d32 into out_scal[out_slot] (same
+// partials and sum, in one pass over the vectors).
+hipError_t launch_cast_scaled_norm(const double* d64, float* d32, int64_t n, const double* scal,
+                                   int slot, double* partials, double* out_scal, int out_slot,
+                                   double* host, hipStream_t st);
 // x += s * double(c32), s = scal[slot + 1].
 hipError_t launch_update(double* x, const float* c32, int64_t n, const double* scal, int slot,
                          hipStream_t st);

@@ -402,11 +402,21 @@ extern "C" mg_status mg_solve(mg_hierarchy* h, const double* dev_b, double* dev_
     Level& F = h->lv[h->L];
     const int64_t n = F.n;
     const bool graphs = o.use_graph != 0;
-    MG_HIPS(launch_copy<double>(dev_b, F.b64, n, q.st));
-    MG_HIPS(launch_copy<double>(dev_x, F.x64, n, q.st));
+    // The mixed-precision loop touches the FP64 vectors only in directly
+    // launched kernels (defect, update), so it reads the caller's b and
+    // updates the caller's x in place; the other solvers' captured graphs
+    // work on the hierarchy's own copies.
+    const bool direct = !o.krylov && o.precision == MG_PREC_MIXED;
+    const double* B64 = direct ? dev_b : F.b64;
+    double* X64 = direct ? dev_x : F.x64;
+    if (!direct) {
+        MG_HIPS(launch_copy<double>(dev_b, F.b64, n, q.st));
+        MG_HIPS(launch_copy<double>(dev_x, F.x64, n, q.st));
+        q.bytes += 8.0 * 4 * n;
+    }
     arm_scalar(h, SC_B);
-    MG_HIPS(launch_norm<double>(F.b64, n, h->partials, h->scal, SC_B, h->host_scal, q.st));
-    q.bytes += 8.0 * 5 * n;
+    MG_HIPS(launch_norm<double>(B64, n, h->partials, h->scal, SC_B, h->host_scal, q.st));
+    q.bytes += 8.0 * n;
     double bn = 0.0;
     MG_HIPS(read_scalar(h, SC_B, q.st, &bn));
     st.bnorm = bn;
@@ -414,7 +424,7 @@ extern "C" mg_status mg_solve(mg_hierarchy* h, const double* dev_b, double* dev_
     if (!std::isfinite(bn)) {
         result = fail(MG_ERR_NUMERIC, "right-hand side contains NaN or Inf");
     } else if (bn == 0.0) {
-        MG_HIPS(launch_fill<double>(F.x64, n, 0.0, q.st));
+        MG_HIPS(launch_fill<double>(X64, n, 0.0, q.st));
     } else if (o.krylov) {
         // r0 = b - A x0 and its norm; the first direction is z (beta = 0)
         double r = 0.0;
@@ -487,8 +497,8 @@ extern "C" mg_status mg_solve(mg_hierarchy* h, const double* dev_b, double* dev_
         for (int k = 1;; ++k) {
             double s = 0.0;
             arm_scalar(h, SC_R64);
-            MG_HIPS(launch_defect<double>(F, F.bands64, F.b64, F.x64, h->d64, h->partials,
-                                          h->scal, SC_R64, h->host_scal, q.st));
+            MG_HIPS(launch_defect<double>(F, F.bands64, B64, X64, h->d64, h->partials, h->scal,
+                                          SC_R64, h->host_scal, q.st));
             q.bytes += 12.0 * 8 * n;
             MG_HIPS(read_scalar(h, SC_R64, q.st, &s));
             st.rel_res = s / bn;
@@ -508,10 +518,9 @@ extern "C" mg_status mg_solve(mg_hierarchy* h, const double* dev_b, double* dev_
             }
             if (s == 0.0) break;
             arm_scalar(h, SC_D32);
-            MG_HIPS(launch_cast_scaled(h->d64, F.b32, n, h->scal, SC_R64, q.st));
-            MG_HIPS(launch_norm<float>(F.b32, n, h->partials, h->scal, SC_D32, h->host_scal,
-                                       q.st));
-            q.bytes += 16.0 * n;
+            MG_HIPS(launch_cast_scaled_norm(h->d64, F.b32, n, h->scal, SC_R64, h->partials,
+                                            h->scal, SC_D32, h->host_scal, q.st));
+            q.bytes += 12.0 * n;
             // ||d32|| is first needed after the first inner cycle: read it then
             double dn = 0.0;
             for (int it = 1; it <= o.inner_max_cycles; ++it) {
@@ -524,13 +533,15 @@ extern "C" mg_status mg_solve(mg_hierarchy* h, const double* dev_b, double* dev_
                 if (!std::isfinite(r32)) break;
                 if (r32 <= o.inner_reduction * dn) break;
             }
-            MG_HIPS(launch_update(F.x64, F.x32, n, h->scal, SC_R64, q.st));
+            MG_HIPS(launch_update(X64, F.x32, n, h->scal, SC_R64, q.st));
             q.bytes += 20.0 * n;
             st.outer_steps = k;
         }
     }
-    MG_HIPS(launch_copy<double>(F.x64, dev_x, n, q.st));
-    q.bytes += 16.0 * n;
+    if (!direct) {
+        MG_HIPS(launch_copy<double>(F.x64, dev_x, n, q.st));
+        q.bytes += 16.0 * n;
+    }
     MG_HIPS(hipStreamSynchronize(q.st));
     st.status = result;
     st.alg_bytes = q.bytes;
