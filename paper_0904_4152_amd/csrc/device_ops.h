@@ -260,14 +260,18 @@ __device__ __forceinline__ void coarse_cholesky(const CoarseSolver& cs, int Nc,
         int r = 0;
         for (int p = 0; p < Nc * Nc; ++p)
             if (!is_dirichlet(Nc, p % Nc, p / Nc, cs.dmask)) node[r++] = p;
+        // the factor is banded (unknowns in node order: nothing more than
+        // Nc + 1 off the diagonal), so the sums run over the band only; the
+        // terms left out are exact zeros
+        const int bw = Nc + 1;
         for (int r = 0; r < m; ++r) {
             double s = (double)b[node[r]];
-            for (int k = 0; k < r; ++k) s -= cs.chol[r * m + k] * z[k];
+            for (int k = max(0, r - bw); k < r; ++k) s -= cs.chol[r * m + k] * z[k];
             z[r] = s / cs.chol[r * m + r];
         }
         for (int r = m - 1; r >= 0; --r) {
             double s = z[r];
-            for (int k = r + 1; k < m; ++k) s -= cs.chol[k * m + r] * z[k];
+            for (int k = r + 1; k < min(m, r + bw + 1); ++k) s -= cs.chol[k * m + r] * z[k];
             z[r] = s / cs.chol[r * m + r];
         }
         for (int r = 0; r < m; ++r) x[node[r]] = (T)z[r];

@@ -146,15 +146,33 @@ __global__ __launch_bounds__(dev::TAIL_THREADS) void k_tail(dev::TailLevels<T> t
 // Dense block of the coarsest operator over its unknowns (the nodes off the
 // Dirichlet sides, in index order) and its Cholesky factor (one thread; at
 // most 72 unknowns).  flag = 1 if a pivot is not positive.
-__global__ void k_chol_factor(const double* __restrict__ bands, int64_t bs, int Nc, int dmask,
-                              double* __restrict__ A, int* __restrict__ flag) {
+// Dense Cholesky factor (lower triangle, row-major m x m) of the coarsest
+// level's operator restricted to its unknowns, by one wavefront.  Unknowns
+// are numbered in node order, so the matrix, and with it the factor, is
+// banded: entries more than bw = Nc + 1 below the diagonal are zero and
+// stay zero.  Column by column: lane 0 forms the pivot, then the lanes form
+// the band's rows below it, each row's sum in increasing k as a plain dense
+// factorisation would (the terms skipped below the band are exact zeros).
+__global__ __launch_bounds__(64) void k_chol_factor(const double* __restrict__ bands, int64_t bs,
+                                                    int Nc, int dmask, double* __restrict__ A,
+                                                    int* __restrict__ flag) {
     __shared__ int idx[dev::COARSE_MAX_UNKNOWNS];  // node -> unknown (LDS: no scratch)
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    int m = 0;
-    for (int p = 0; p < Nc * Nc; ++p)
-        idx[p] = dev::is_dirichlet(Nc, p % Nc, p / Nc, dmask) ? -1 : m++;
-    for (int r = 0; r < m * m; ++r) A[r] = 0.0;
-    for (int p = 0; p < Nc * Nc; ++p) {
+    __shared__ int m_s, bad_s;
+    __shared__ double piv_s;
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        int m = 0;
+        for (int p = 0; p < Nc * Nc; ++p)
+            idx[p] = dev::is_dirichlet(Nc, p % Nc, p / Nc, dmask) ? -1 : m++;
+        m_s = m;
+        bad_s = 0;
+    }
+    __syncthreads();
+    const int m = m_s;
+    const int bw = Nc + 1;
+    for (int r = tid; r < m * m; r += 64) A[r] = 0.0;
+    __syncthreads();
+    for (int p = tid; p < Nc * Nc; p += 64) {
         const int r = idx[p];
         if (r < 0) continue;
         const int i = p % Nc, j = p / Nc;
@@ -165,23 +183,30 @@ __global__ void k_chol_factor(const double* __restrict__ bands, int64_t bs, int 
             if (c >= 0) A[r * m + c] = bands[k * bs + p];
         }
     }
-    int bad = 0;
+    __syncthreads();
     for (int c = 0; c < m; ++c) {
-        double d = A[c * m + c];
-        for (int k = 0; k < c; ++k) d -= A[c * m + k] * A[c * m + k];
-        if (!(d > 0.0)) {
-            bad = 1;
-            break;
+        if (tid == 0) {
+            double d = A[c * m + c];
+            for (int k = max(0, c - bw); k < c; ++k) d -= A[c * m + k] * A[c * m + k];
+            if (!(d > 0.0)) {
+                bad_s = 1;
+            } else {
+                d = sqrt(d);
+                A[c * m + c] = d;
+                piv_s = d;
+            }
         }
-        d = sqrt(d);
-        A[c * m + c] = d;
-        for (int r = c + 1; r < m; ++r) {
+        __syncthreads();
+        if (bad_s) break;
+        const double d = piv_s;
+        for (int r = c + 1 + tid; r < m && r <= c + bw; r += 64) {
             double t = A[r * m + c];
-            for (int k = 0; k < c; ++k) t -= A[r * m + k] * A[c * m + k];
+            for (int k = max(0, r - bw); k < c; ++k) t -= A[r * m + k] * A[c * m + k];
             A[r * m + c] = t / d;
         }
+        __syncthreads();
     }
-    *flag = bad;
+    if (tid == 0) *flag = bad_s;
 }
 
 // ---------------------------------------------------------------- geometry
