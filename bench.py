@@ -395,6 +395,7 @@ def main():
     torch.cuda.synchronize()
     t_mixed = (time.perf_counter() - t0) / args.steps
     st_m = stats[-1]
+    x_mixed = x.cpu().numpy()
 
     st_f = solve(h, b, x, fp64)  # warm the FP64 graphs
     t0 = time.perf_counter()
@@ -403,6 +404,7 @@ def main():
         st_f = solve(h, b, x, fp64)
     torch.cuda.synchronize()
     t_fp64 = (time.perf_counter() - t0) / nf
+    x_fp64 = x.cpu().numpy()
     out["L12"] = {
         "n": n, "setup_s": t_setup,
         "mixed": {"ms": t_mixed * 1e3, "outer_steps": st_m.outer_steps,
@@ -440,6 +442,7 @@ def main():
     torch.cuda.empty_cache()
 
     # ---------------- L = 10 (FP64 vs mixed) and L = 6 (sin sin, FP64)
+    small_x = {}
     for name, (LL, a, gs, kind, reps) in {"L10": (10, 0.2, 1002, "uniform", 5),
                                           "L6": (6, 0.0, 0, "sinsin", 20)}.items():
         hh = mg.Hierarchy(ctx, LL, jitter=a, seed=gs)
@@ -460,6 +463,7 @@ def main():
             dt = (time.perf_counter() - t0) / reps
             rec[pname] = {"ms": dt * 1e3, "solves_s": 1.0 / dt, "cycles": s.cycles,
                           "outer_steps": s.outer_steps, "rel_res": s.rel_res}
+            small_x[(name, pname)] = xx.cpu().numpy()
         out[name] = rec
         hh.close()
 
@@ -484,12 +488,37 @@ def main():
         bh = synth.rhs_gaussian(L, rseed)
         oh = oracle.Hierarchy(L, xy)
         t0 = time.perf_counter()
-        _, ost = oh.solve_fp64(bh, o=oracle.opts(rel_tol=1e-8))
+        xo, ost = oh.solve_fp64(bh, o=oracle.opts(rel_tol=1e-8))
         dt = time.perf_counter() - t0
         cpu = {"value": 1.0 / dt, "unit": "solves/s", "cores": 1, "kind": "oracle",
                "sample": "one plain FP64 V(2,2) solve to 1e-8 of the same L=12 problem "
                          "(%d cycles, %.1f s, assembly excluded), single thread" % (ost.cycles, dt)}
         oh.close()
+        # each GPU result against the oracle's FP64 solution of the same problem
+        # (inputs from the host generators and the oracle's own load vector)
+        def vs_oracle(xo_, ost_, xf, xm):
+            xn = float(np.linalg.norm(xo_))
+            return {"oracle_cycles": ost_.cycles,
+                    "fp64_rel_solution_diff": float(np.linalg.norm(xf - xo_)) / xn,
+                    "mixed_rel_solution_diff": float(np.linalg.norm(xm - xo_)) / xn}
+
+        out["L12"]["vs_oracle"] = vs_oracle(xo, ost, x_fp64, x_mixed)
+        for name, LL, a, gs in (("L10", 10, 0.2, 1002), ("L6", 6, 0.0, 0)):
+            xy_s = synth.coords(LL, a, gs)
+            Ns = (1 << LL) + 1
+            b_s = (synth.rhs_uniform(LL, 2002) if name == "L10"
+                   else oracle.load_vector(Ns, xy_s, fn=0))
+            oh_s = oracle.Hierarchy(LL, xy_s)
+            xo_s, ost_s = oh_s.solve_fp64(b_s, o=oracle.opts(rel_tol=1e-8))
+            oh_s.close()
+            out[name]["vs_oracle"] = vs_oracle(xo_s, ost_s, small_x[(name, "fp64")],
+                                               small_x[(name, "mixed")])
+        try:
+            model = next(ln.split(":", 1)[1].strip() for ln in open("/proc/cpuinfo")
+                         if ln.startswith("model name"))
+        except (OSError, StopIteration):
+            model = "unknown"
+        cpu["host"] = {"nproc": os.cpu_count(), "cpu_model": model}
 
     roof_achieved = out["band_kernels"]["fused_pre_fp32"]["GB_s"]
     line = {
