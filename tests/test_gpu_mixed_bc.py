@@ -120,7 +120,7 @@ def test_restrict(mg, ctx, orc, mask, L, dtype):
 
 
 @pytest.mark.parametrize("mask", MASKS)
-@pytest.mark.parametrize("Lc", [1, 2, 3])
+@pytest.mark.parametrize("Lc", [1, 2, 3, 4])
 def test_coarse_direct_solve(mg, ctx, orc, mask, Lc):
     L = max(Lc, 4)
     h = mg.Hierarchy(ctx, L, coarse_level=Lc, jitter=0.2, seed=5, dirichlet_sides=mask)

@@ -192,7 +192,7 @@ def test_restrict_prolong(mg, ctx, orc, L, dtype):
     assert_within(host(xfd), ref, 4 * u * sc, "prolong")
 
 
-@pytest.mark.parametrize("Lc", [1, 2, 3])
+@pytest.mark.parametrize("Lc", [1, 2, 3, 4])
 def test_coarse_direct_solve(mg, ctx, orc, Lc):
     L = max(Lc, 4)
     h = mg.Hierarchy(ctx, L, coarse_level=Lc, jitter=0.2, seed=5)
