@@ -372,11 +372,23 @@ __device__ __forceinline__ double sumsq_tile(const T* __restrict__ v, int64_t n,
 constexpr int64_t RED_SEG = 8192;  // partials per first-stage segment
 constexpr int RED_MAX_SEGS = 1024;  // so at most 8M partials
 
-// Thread-strided sum of p[lo, hi) then block_sum; valid in thread 0.
+// Thread-strided sum of p[lo, hi) then block_sum; valid in thread 0.  Each
+// thread adds its elements in index order; eight loads are in flight at a
+// time, so a long sum costs a few memory latencies rather than one per
+// element.
 __device__ __forceinline__ double strided_sum(const double* __restrict__ p, int64_t lo,
                                               int64_t hi) {
+    constexpr int U = 8;
     double s = 0.0;
-    for (int64_t i = lo + threadIdx.x; i < hi; i += BLOCK) s += p[i];
+    int64_t i = lo + threadIdx.x;
+    for (; i + (int64_t)(U - 1) * BLOCK < hi; i += (int64_t)U * BLOCK) {
+        double v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = p[i + (int64_t)u * BLOCK];
+#pragma unroll
+        for (int u = 0; u < U; ++u) s += v[u];
+    }
+    for (; i < hi; i += BLOCK) s += p[i];
     return block_sum(s);
 }
 
