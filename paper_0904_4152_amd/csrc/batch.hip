@@ -334,10 +334,16 @@ __global__ __launch_bounds__(BLOCK) void kb_cast(const BProb* __restrict__ probs
     const BLevel& lv = P.lv[P.L];
     const double s = state[p].s;
     const int64_t base = (int64_t)tile * TILE;
+    double dv[4];  // loads first; lanes past n read element 0 and store nothing
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
         const int64_t q = base + (int64_t)e * BLOCK + threadIdx.x;
-        if (q < lv.n) lv.b32[q] = s > 0.0 ? (float)(P.d64[q] / s) : 0.0f;
+        dv[e] = P.d64[q < lv.n ? q : 0];
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int64_t q = base + (int64_t)e * BLOCK + threadIdx.x;
+        if (q < lv.n) lv.b32[q] = s > 0.0 ? (float)(dv[e] / s) : 0.0f;
     }
     END_ITEMS
 }
@@ -351,10 +357,19 @@ __global__ __launch_bounds__(BLOCK) void kb_update(const BProb* __restrict__ pro
     const BLevel& lv = P.lv[P.L];
     const double s = state[p].s;
     const int64_t base = (int64_t)tile * TILE;
+    double xv[4];  // loads first; lanes past n read element 0 and store nothing
+    float cv[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
         const int64_t q = base + (int64_t)e * BLOCK + threadIdx.x;
-        if (q < lv.n) lv.x64[q] += s * (double)lv.x32[q];
+        const int64_t r = q < lv.n ? q : 0;
+        xv[e] = lv.x64[r];
+        cv[e] = lv.x32[r];
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int64_t q = base + (int64_t)e * BLOCK + threadIdx.x;
+        if (q < lv.n) lv.x64[q] = xv[e] + s * (double)cv[e];
     }
     END_ITEMS
 }

@@ -357,14 +357,22 @@ __device__ __forceinline__ void coarse_block(const CoarseSolver& cs, int Nc, con
     __syncthreads();
 }
 
-// Sum of squares of one norm tile (elements base + e*BLOCK + tid, e < 4).
+// Sum of squares of one norm tile (elements base + e*BLOCK + tid, e < 4,
+// added in e order).  The four loads go out together (a lane past n reads
+// element 0 and adds zero, which leaves the sum unchanged).
 template <typename T>
 __device__ __forceinline__ double sumsq_tile(const T* __restrict__ v, int64_t n, int64_t base) {
+    T w[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int64_t p = base + (int64_t)e * BLOCK + threadIdx.x;
+        w[e] = v[p < n ? p : 0];
+    }
     double s = 0.0;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
         const int64_t p = base + (int64_t)e * BLOCK + threadIdx.x;
-        if (p < n) s += (double)v[p] * (double)v[p];
+        s += p < n ? (double)w[e] * (double)w[e] : 0.0;
     }
     return s;
 }

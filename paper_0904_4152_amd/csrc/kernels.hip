@@ -529,15 +529,20 @@ __global__ __launch_bounds__(BLOCK) void k_cast_scaled_sumsq(const double* __res
     if (lb < 0) return;
     const double s = scal[slot + 1];
     const int64_t base = lb * (int64_t)dev::NORM_TILE;
+    // the four loads go out together; lanes past n read element 0 and add zero
+    double w[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int64_t p = base + (int64_t)e * BLOCK + threadIdx.x;
+        w[e] = d[p < n ? p : 0];
+    }
     double acc = 0.0;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
         const int64_t p = base + (int64_t)e * BLOCK + threadIdx.x;
-        if (p < n) {
-            const float v = s > 0.0 ? (float)(d[p] / s) : 0.0f;
-            d32[p] = v;
-            acc += (double)v * (double)v;
-        }
+        const float v = s > 0.0 ? (float)(w[e] / s) : 0.0f;
+        if (p < n) d32[p] = v;
+        acc += p < n ? (double)v * (double)v : 0.0;
     }
     const double t = dev::block_sum(acc);
     if (threadIdx.x == 0) partials[lb] = t;
@@ -574,11 +579,21 @@ __global__ __launch_bounds__(BLOCK) void k_dot(const double* __restrict__ u,
     const int64_t lb = xcd_block(nblk);
     if (lb < 0) return;
     const double s = zslot >= 0 ? scal[zslot + 1] : 1.0;
+    // loads first (lanes past n read element 0 and add zero), then the sum
+    // in e order
+    double uv[4], zv[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int64_t p = lb * (int64_t)dev::NORM_TILE + (int64_t)e * BLOCK + threadIdx.x;
+        const int64_t q = p < n ? p : 0;
+        uv[e] = u[q];
+        zv[e] = z_value(z, q, s);
+    }
     double acc = 0.0;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
         const int64_t p = lb * (int64_t)dev::NORM_TILE + (int64_t)e * BLOCK + threadIdx.x;
-        if (p < n) acc += u[p] * z_value(z, p, s);
+        acc += p < n ? uv[e] * zv[e] : 0.0;
     }
     const double t = dev::block_sum(acc);
     if (threadIdx.x == 0) partials[lb] = t;
