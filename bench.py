@@ -9,8 +9,9 @@ Prints one JSON line with solves/s (value), the roofline of the dominant
 kernel (the finest-level fused FP32 pre-smoothing pass: two damped Jacobi
 sweeps, the defect and its restriction in one sweep over the bands), the
 band-SpMV GB/s, the plain FP64 solve time beside the mixed one, the L = 10
-and L = 6 workloads, the batched and serving workloads and the oracle timed
-on the host CPU.
+and L = 6 workloads, the batched and serving workloads, and the oracle timed
+on the host CPU, whose FP64 solutions of the L = 12, 10 and 6 problems give
+each GPU result's error against the oracle.
 """
 from __future__ import annotations
 
