@@ -501,6 +501,52 @@ __global__ __launch_bounds__(BLOCK) void k_sumsq(const T* __restrict__ v, int64_
     if (threadIdx.x == 0) partials[lb] = s;
 }
 
+// Number of nonzero elements per norm tile (as a double: exact).
+__global__ __launch_bounds__(BLOCK) void k_count_nonzero(const double* __restrict__ v, int64_t n,
+                                                         double* __restrict__ partials,
+                                                         int64_t nblk) {
+    const int64_t lb = xcd_block(nblk);
+    if (lb < 0) return;
+    double c = 0.0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int64_t p = lb * (int64_t)dev::NORM_TILE + (int64_t)e * BLOCK + threadIdx.x;
+        c += (p < n && v[p < n ? p : 0] != 0.0) ? 1.0 : 0.0;
+    }
+    const double s = dev::block_sum(c);
+    if (threadIdx.x == 0) partials[lb] = s;
+}
+
+// The defect d = b - A x of a zero iterate, d = b, with the tiling, stores
+// and norm partials of k_stencil<T, OP_DEFECT, NORM, STORE>: with x = 0 every
+// band product sums exact zeros to +0 and b - (+0) = b, so the results are
+// the same bits without reading the bands or x.
+template <typename T, bool NORM, bool STORE>
+__global__ __launch_bounds__(BLOCK) void k_defect_zero_x(int64_t n, const T* __restrict__ b,
+                                                         T* __restrict__ out,
+                                                         double* __restrict__ partials,
+                                                         int64_t nblk) {
+    constexpr int W = dev::V16<T>::W;
+    const int64_t lb = xcd_block(nblk);
+    if (lb < 0) return;
+    const int64_t p0 = lb * (int64_t)dev::tile_rows<T>() + (int64_t)threadIdx.x * W;
+    double sq = 0.0;
+    if (p0 < n) {
+#pragma unroll
+        for (int v = 0; v < W; ++v) {
+            if (p0 + v < n) {
+                const T r = b[p0 + v];
+                if (NORM) sq += (double)r * (double)r;
+                if (STORE) out[p0 + v] = r;
+            }
+        }
+    }
+    if (NORM) {
+        const double s = dev::block_sum(sq);
+        if (threadIdx.x == 0) partials[lb] = s;
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_fill(T* __restrict__ v, int64_t n, T value) {
     const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
@@ -938,6 +984,30 @@ hipError_t launch_norm(const T* v, int64_t n, double* partials, double* scal, in
                        double* host, hipStream_t st) {
     const int64_t nb = norm_blocks(n);
     hipLaunchKernelGGL(k_sumsq<T>, dim3(grid8(nb)), dim3(BLOCK), 0, st, v, n, partials, nb);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_reduce(partials, nb, scal, slot, host, st);
+}
+
+hipError_t launch_count_nonzero(const double* v, int64_t n, double* partials, double* scal,
+                                int slot, double* host, hipStream_t st) {
+    const int64_t nb = norm_blocks(n);
+    hipLaunchKernelGGL(k_count_nonzero, dim3(grid8(nb)), dim3(BLOCK), 0, st, v, n, partials, nb);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_reduce(partials, nb, scal, slot, host, st);
+}
+
+hipError_t launch_defect_zero_x(const Level& lv, const double* b, double* d, double* partials,
+                                double* scal, int slot, double* host, hipStream_t st) {
+    const int64_t nb = stencil_blocks(lv.n, sizeof(double));
+    const dim3 g(grid8(nb)), blk(BLOCK);
+    if (d)
+        hipLaunchKernelGGL((k_defect_zero_x<double, true, true>), g, blk, 0, st, lv.n, b, d,
+                           partials, nb);
+    else
+        hipLaunchKernelGGL((k_defect_zero_x<double, true, false>), g, blk, 0, st, lv.n, b,
+                           (double*)nullptr, partials, nb);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_reduce(partials, nb, scal, slot, host, st);

@@ -104,7 +104,8 @@ enum : int {
     SC_PQ = 10,
     SC_RZ = 12,
     SC_RZ_OLD = 14,
-    SC_RR = 16
+    SC_RR = 16,
+    SC_XNZ = 18  // nonzero elements of the initial iterate
 };
 
 // How the hierarchy's coarsest level is solved.
@@ -168,6 +169,13 @@ hipError_t launch_fill(T* v, int64_t n, T value, hipStream_t st);
 // d32 = float(d64 / s) with s = scal[slot + 1] (0 if s == 0).
 hipError_t launch_cast_scaled(const double* d64, float* d32, int64_t n, const double* scal,
                               int slot, hipStream_t st);
+// scal[slot] = number of nonzero elements of v (FP64, exact).
+hipError_t launch_count_nonzero(const double* v, int64_t n, double* partials, double* scal,
+                                int slot, double* host, hipStream_t st);
+// launch_defect (FP64, with the norm; d may be null) for x = 0: the same
+// bits, from b alone.
+hipError_t launch_defect_zero_x(const Level& lv, const double* b, double* d, double* partials,
+                                double* scal, int slot, double* host, hipStream_t st);
 // The same, followed by launch_norm of d32 into out_scal[out_slot] (same
 // partials and sum, in one pass over the vectors).
 hipError_t launch_cast_scaled_norm(const double* d64, float* d32, int64_t n, const double* scal,

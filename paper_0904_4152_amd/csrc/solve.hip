@@ -417,8 +417,20 @@ extern "C" mg_status mg_solve(mg_hierarchy* h, const double* dev_b, double* dev_
     arm_scalar(h, SC_B);
     MG_HIPS(launch_norm<double>(B64, n, h->partials, h->scal, SC_B, h->host_scal, q.st));
     q.bytes += 8.0 * n;
-    double bn = 0.0;
+    // A zero initial iterate (the usual start) makes the first defect b
+    // itself: its kernel then reads b alone (same bits, see
+    // launch_defect_zero_x).  The solvers without a first FP64 defect skip
+    // the count.
+    const bool count_x = !o.krylov;
+    if (count_x) {
+        arm_scalar(h, SC_XNZ);
+        MG_HIPS(launch_count_nonzero(X64, n, h->partials, h->scal, SC_XNZ, h->host_scal, q.st));
+        q.bytes += 8.0 * n;
+    }
+    double bn = 0.0, xnz = 1.0;
     MG_HIPS(read_scalar(h, SC_B, q.st, &bn));
+    if (count_x) MG_HIPS(read_scalar(h, SC_XNZ, q.st, &xnz));
+    const bool x_zero = xnz == 0.0;
     st.bnorm = bn;
     mg_status result = MG_OK;
     if (!std::isfinite(bn)) {
@@ -467,9 +479,15 @@ extern "C" mg_status mg_solve(mg_hierarchy* h, const double* dev_b, double* dev_
     } else if (o.precision == MG_PREC_FP64) {
         double r = 0.0;
         arm_scalar(h, SC_R64);
-        MG_HIPS(launch_defect<double>(F, F.bands64, F.b64, F.x64, nullptr, h->partials, h->scal,
-                                      SC_R64, h->host_scal, q.st));
-        q.bytes += 11.0 * 8 * n;
+        if (x_zero) {
+            MG_HIPS(launch_defect_zero_x(F, F.b64, nullptr, h->partials, h->scal, SC_R64,
+                                         h->host_scal, q.st));
+            q.bytes += 8.0 * n;
+        } else {
+            MG_HIPS(launch_defect<double>(F, F.bands64, F.b64, F.x64, nullptr, h->partials,
+                                          h->scal, SC_R64, h->host_scal, q.st));
+            q.bytes += 11.0 * 8 * n;
+        }
         MG_HIPS(read_scalar(h, SC_R64, q.st, &r));
         st.rel_res = r / bn;
         for (int k = 1;; ++k) {
@@ -497,9 +515,15 @@ extern "C" mg_status mg_solve(mg_hierarchy* h, const double* dev_b, double* dev_
         for (int k = 1;; ++k) {
             double s = 0.0;
             arm_scalar(h, SC_R64);
-            MG_HIPS(launch_defect<double>(F, F.bands64, B64, X64, h->d64, h->partials, h->scal,
-                                          SC_R64, h->host_scal, q.st));
-            q.bytes += 12.0 * 8 * n;
+            if (k == 1 && x_zero) {
+                MG_HIPS(launch_defect_zero_x(F, B64, h->d64, h->partials, h->scal, SC_R64,
+                                             h->host_scal, q.st));
+                q.bytes += 16.0 * n;
+            } else {
+                MG_HIPS(launch_defect<double>(F, F.bands64, B64, X64, h->d64, h->partials,
+                                              h->scal, SC_R64, h->host_scal, q.st));
+                q.bytes += 12.0 * 8 * n;
+            }
             MG_HIPS(read_scalar(h, SC_R64, q.st, &s));
             st.rel_res = s / bn;
             if (k > 1 && st.n_hist < MG_HIST) st.res_hist[st.n_hist++] = s / bn;
