@@ -419,17 +419,13 @@ extern "C" mg_status mg_solve(mg_hierarchy* h, const double* dev_b, double* dev_
     q.bytes += 8.0 * n;
     // A zero initial iterate (the usual start) makes the first defect b
     // itself: its kernel then reads b alone (same bits, see
-    // launch_defect_zero_x).  The solvers without a first FP64 defect skip
-    // the count.
-    const bool count_x = !o.krylov;
-    if (count_x) {
-        arm_scalar(h, SC_XNZ);
-        MG_HIPS(launch_count_nonzero(X64, n, h->partials, h->scal, SC_XNZ, h->host_scal, q.st));
-        q.bytes += 8.0 * n;
-    }
+    // launch_defect_zero_x).
+    arm_scalar(h, SC_XNZ);
+    MG_HIPS(launch_count_nonzero(X64, n, h->partials, h->scal, SC_XNZ, h->host_scal, q.st));
+    q.bytes += 8.0 * n;
     double bn = 0.0, xnz = 1.0;
     MG_HIPS(read_scalar(h, SC_B, q.st, &bn));
-    if (count_x) MG_HIPS(read_scalar(h, SC_XNZ, q.st, &xnz));
+    MG_HIPS(read_scalar(h, SC_XNZ, q.st, &xnz));
     const bool x_zero = xnz == 0.0;
     st.bnorm = bn;
     mg_status result = MG_OK;
@@ -441,10 +437,16 @@ extern "C" mg_status mg_solve(mg_hierarchy* h, const double* dev_b, double* dev_
         // r0 = b - A x0 and its norm; the first direction is z (beta = 0)
         double r = 0.0;
         arm_scalar(h, SC_RR);
-        MG_HIPS(launch_defect<double>(F, F.bands64, F.b64, F.x64, h->d64, h->partials, h->scal,
-                                      SC_RR, h->host_scal, q.st));
+        if (x_zero) {
+            MG_HIPS(launch_defect_zero_x(F, F.b64, h->d64, h->partials, h->scal, SC_RR,
+                                         h->host_scal, q.st));
+            q.bytes += 16.0 * n;
+        } else {
+            MG_HIPS(launch_defect<double>(F, F.bands64, F.b64, F.x64, h->d64, h->partials,
+                                          h->scal, SC_RR, h->host_scal, q.st));
+            q.bytes += 12.0 * 8 * n;
+        }
         MG_HIPS(launch_fill<double>(h->scal + SC_RZ_OLD, 1, INFINITY, q.st));
-        q.bytes += 12.0 * 8 * n;
         MG_HIPS(read_scalar(h, SC_RR, q.st, &r));
         st.rel_res = r / bn;
         const int kind = o.precision == MG_PREC_FP64 ? 2 : 3;
