@@ -29,9 +29,17 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, published
-# Bytes per node a fused FP32 pass must move: 5 band streams, x and b read,
-# the iterate written (the coarse vector, a quarter node, added separately).
-FUSED_B = 8 * 4
+# Algorithmic bytes per finest node of one fused FP32 smoothing pass: the nine
+# stored bands, x and b read and the iterate written (12 scalars of 4 bytes);
+# the coarse vector (one scalar per coarse node) is added separately.
+FUSED_ALG_B = 12 * 4
+# What the pass must at least move: the matrix is symmetric bit for bit, so
+# it reads the diagonal and the four upper bands only (8 scalars per node).
+FUSED_MIN_B = 8 * 4
+# Sources the fused passes are built from: a counter record taken on other
+# sources is stale.
+TRAFFIC_SOURCES = ["csrc/kernels.hip", "csrc/fused_ops.h", "csrc/device_ops.h",
+                   "csrc/mg_internal.h", "build.py"]
 
 
 def parse():
@@ -43,6 +51,9 @@ def parse():
     ap.add_argument("--kernel-iters", type=int, default=50)
     ap.add_argument("--only-kernels", action="store_true",
                     help="time the band kernels only (for profiler runs)")
+    ap.add_argument("--only-step", action="store_true",
+                    help="set up the L = 12 workload and run the warm-up and timed steps "
+                         "only (for profiler runs of exactly the timed step)")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-rate", type=float, default=2000.0)
@@ -53,10 +64,13 @@ def parse():
 
 
 def kernel_source_hash() -> str:
+    """Hash of the sources and build flags of the band kernels and fused
+    passes whose HBM counters profiles/hbm_traffic.json records."""
     h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_0904_4152_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        with open(os.path.join(csrc, name), "rb") as f:
+    pkg = os.path.join(ROOT, "paper_0904_4152_amd")
+    for name in TRAFFIC_SOURCES:
+        with open(os.path.join(pkg, name), "rb") as f:
+            h.update(name.encode())
             h.update(f.read())
     return h.hexdigest()[:16]
 
@@ -96,7 +110,7 @@ def bench_blas1(ctx, torch, dev, sizes=None):
     axpy (asynchronous, HIP-event timed per launch; 3 streams, 2 flops per
     element) and dot / norm2 (synchronous calls, host wall time including the
     result's return; 2 / 1 streams)."""
-    sizes = sizes or [1 << k for k in range(10, 29, 2)]
+    sizes = sizes or [1 << 16, 1 << 20, 1 << 24, 1 << 28]
     rows = []
     for n in sizes:
         rec = {"n": n}
@@ -279,6 +293,60 @@ def bench_serving(mg, ctx, synth, args):
     return rec
 
 
+def progress(msg: str) -> None:
+    """One line per finished phase on stderr (stdout carries only the JSON)."""
+    print("bench: " + msg, file=sys.stderr, flush=True)
+
+
+def host_cpu():
+    try:
+        model = next(ln.split(":", 1)[1].strip() for ln in open("/proc/cpuinfo")
+                     if ln.startswith("model name"))
+    except (OSError, StopIteration):
+        model = "unknown"
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        affinity = os.cpu_count()
+    return {"nproc": affinity, "cpu_count": os.cpu_count(), "cpu_model": model,
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
+
+
+def oracle_baseline(L, jit, gseed, rseed, synth):
+    """The oracle's FP64 solve of the L = 12 problem on the host: once on one
+    thread (the paper's one-core protocol) and once on every host core (the
+    OpenMP build: element-wise loops threaded, same bits).  Assembly is
+    excluded from both timings.  Returns the baseline record and the
+    solution."""
+    import oracle
+    xy = synth.coords(L, jit, gseed)
+    bh = synth.rhs_gaussian(L, rseed)
+    runs = {}
+    xo = ost = None
+    for threaded in (False, True):
+        oh = oracle.Hierarchy(L, xy, threaded=threaded)
+        t0 = time.perf_counter()
+        x_, st_ = oh.solve_fp64(bh, o=oracle.opts(rel_tol=1e-8))
+        dt = time.perf_counter() - t0
+        oh.close()
+        runs[threaded] = (dt, st_.cycles, oracle.threads(threaded))
+        if xo is None:
+            xo, ost = x_, st_
+        elif not np.array_equal(xo, x_):
+            raise RuntimeError("threaded oracle differs from the one-thread oracle")
+    dt1, cyc, _ = runs[False]
+    dtn, _, nthr = runs[True]
+    cpu = {"value": 1.0 / dtn, "unit": "solves/s", "cores": nthr, "kind": "oracle",
+           "sample": "one plain FP64 V(2,2) solve to 1e-8 of the same L=12 problem "
+                     "(%d cycles, assembly excluded) on %d host threads: %.2f s; "
+                     "one thread: %.1f s" % (cyc, nthr, dtn, dt1),
+           "seconds": dtn,
+           "single_thread": {"value": 1.0 / dt1, "unit": "solves/s", "cores": 1,
+                             "seconds": dt1},
+           "host": host_cpu()}
+    return cpu, xo, ost
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -304,6 +372,33 @@ def main():
     n = h.n
     b = torch.from_numpy(synth.rhs_gaussian(L, rseed)).to(dev)
     x = torch.zeros_like(b)
+    mixed = mg.default_opts(precision=mg.MG_PREC_MIXED, rel_tol=1e-8)
+    fp64 = mg.default_opts(precision=mg.MG_PREC_FP64, rel_tol=1e-8)
+
+    def solve(hh, bb, xx, o):
+        xx.zero_()
+        st = hh.solve(bb, xx, o)
+        if st.status != 0 or st.rel_res > 1e-8:
+            raise RuntimeError("solve did not reach 1e-8: status %d rel_res %g"
+                               % (st.status, st.rel_res))
+        return st
+
+    def timed_step():
+        for _ in range(args.warmup):
+            solve(h, b, x, mixed)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        stats = [solve(h, b, x, mixed) for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / args.steps, stats[-1]
+
+    if args.only_step:
+        t_mixed, st_m = timed_step()
+        print(json.dumps({"only_step": True, "ms_per_step": t_mixed * 1e3,
+                          "steps": args.steps, "warmup": args.warmup,
+                          "outer_steps": st_m.outer_steps, "inner_cycles": st_m.cycles,
+                          "rel_res": st_m.rel_res}))
+        return
 
     # band kernels at full size (FP32 bands 604 MB: larger than the 256 MB
     # Infinity Cache, so these are HBM rates)
@@ -327,38 +422,30 @@ def main():
     bc32 = torch.zeros(Nc, dtype=torch.float32, device=dev)
     t_pre32 = time_launches(lambda: h.pre_smooth(L, b32, x32, y32, bc32), it, torch)
     t_post32 = time_launches(lambda: h.post_smooth(L, b32, x32, bc32, y32), it, torch)
-    bytes_spmv32 = 11 * 4 * n
-    bytes_spmv64 = 11 * 8 * n
-    bytes_jac32 = 12 * 4 * n
-    bytes_def64 = 8 * 8 * n
     gbs = lambda by, s: by / s / 1e9
+
+    def rec(t_, alg, minimum=None):
+        r = {"us": t_ * 1e6, "alg_bytes": alg, "GB_s": gbs(alg, t_),
+             "frac_hbm_peak": gbs(alg, t_) / PEAK_HBM_GBS}
+        if minimum is not None:
+            r["min_bytes"] = minimum
+            r["GB_s_min_bytes"] = gbs(minimum, t_)
+        return r
+
+    fused_alg = FUSED_ALG_B * n + 4 * Nc
+    fused_min = FUSED_MIN_B * n + 4 * Nc
     out["band_kernels"] = {
-        "spmv_fp32": {"us": t_spmv32 * 1e6, "alg_bytes": bytes_spmv32,
-                      "GB_s": gbs(bytes_spmv32, t_spmv32),
-                      "frac_hbm_peak": gbs(bytes_spmv32, t_spmv32) / PEAK_HBM_GBS},
-        "spmv_fp64": {"us": t_spmv64 * 1e6, "alg_bytes": bytes_spmv64,
-                      "GB_s": gbs(bytes_spmv64, t_spmv64),
-                      "frac_hbm_peak": gbs(bytes_spmv64, t_spmv64) / PEAK_HBM_GBS},
-        "jacobi_fp32": {"us": t_jac32 * 1e6, "alg_bytes": bytes_jac32,
-                        "GB_s": gbs(bytes_jac32, t_jac32),
-                        "frac_hbm_peak": gbs(bytes_jac32, t_jac32) / PEAK_HBM_GBS},
-        # 5 bands + x + b read, d written (8 B each)
-        "defect_fp64": {"us": t_def64 * 1e6, "alg_bytes": bytes_def64,
-                        "GB_s": gbs(bytes_def64, t_def64),
-                        "frac_hbm_peak": gbs(bytes_def64, t_def64) / PEAK_HBM_GBS,
-                        "GB_s_9band_equivalent": gbs(12 * 8 * n, t_def64)},
-        # the fused passes read the diagonal and upper bands only (the matrix is
-        # symmetric bit for bit; the lower bands come from the neighbours'):
-        # pre: 5 bands + x + b read, x2 written (4 B each), coarse rhs written
-        "fused_pre_fp32": {"us": t_pre32 * 1e6, "alg_bytes": FUSED_B * n + 4 * Nc,
-                           "GB_s": gbs(FUSED_B * n + 4 * Nc, t_pre32),
-                           "frac_hbm_peak": gbs(FUSED_B * n + 4 * Nc, t_pre32) / PEAK_HBM_GBS,
-                           "GB_s_9band_equivalent": gbs(12 * 4 * n + 4 * Nc, t_pre32)},
-        # post: 5 bands + x + b read, x written, coarse correction read
-        "fused_post_fp32": {"us": t_post32 * 1e6, "alg_bytes": FUSED_B * n + 4 * Nc,
-                            "GB_s": gbs(FUSED_B * n + 4 * Nc, t_post32),
-                            "frac_hbm_peak": gbs(FUSED_B * n + 4 * Nc, t_post32) / PEAK_HBM_GBS,
-                            "GB_s_9band_equivalent": gbs(12 * 4 * n + 4 * Nc, t_post32)},
+        # nine bands + x read, y written
+        "spmv_fp32": rec(t_spmv32, 11 * 4 * n),
+        "spmv_fp64": rec(t_spmv64, 11 * 8 * n),
+        # nine bands + x + b read, x' written
+        "jacobi_fp32": rec(t_jac32, 12 * 4 * n),
+        # nine bands + x + b read, d written; it reads 5 bands (the lower ones
+        # are the neighbours' upper ones): min_bytes
+        "defect_fp64": rec(t_def64, 12 * 8 * n, 8 * 8 * n),
+        # pre: 2 sweeps + defect + restriction; post: prolongation + 2 sweeps
+        "fused_pre_fp32": rec(t_pre32, fused_alg, fused_min),
+        "fused_post_fp32": rec(t_post32, fused_alg, fused_min),
     }
     del bc32
     del x32, y32, b32, x64, y64, b64
@@ -377,26 +464,10 @@ def main():
         print(json.dumps(out))
         return
 
-    mixed = mg.default_opts(precision=mg.MG_PREC_MIXED, rel_tol=1e-8)
-    fp64 = mg.default_opts(precision=mg.MG_PREC_FP64, rel_tol=1e-8)
-
-    def solve(hh, bb, xx, o):
-        xx.zero_()
-        st = hh.solve(bb, xx, o)
-        if st.status != 0 or st.rel_res > 1e-8:
-            raise RuntimeError("solve did not reach 1e-8: status %d rel_res %g"
-                               % (st.status, st.rel_res))
-        return st
-
-    for _ in range(args.warmup):
-        solve(h, b, x, mixed)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    stats = [solve(h, b, x, mixed) for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t_mixed = (time.perf_counter() - t0) / args.steps
-    st_m = stats[-1]
+    progress("band kernels timed")
+    t_mixed, st_m = timed_step()
     x_mixed = x.cpu().numpy()
+    progress("timed step: %.3f ms per mixed solve" % (t_mixed * 1e3))
 
     st_f = solve(h, b, x, fp64)  # warm the FP64 graphs
     t0 = time.perf_counter()
@@ -410,9 +481,9 @@ def main():
         "n": n, "setup_s": t_setup,
         "mixed": {"ms": t_mixed * 1e3, "outer_steps": st_m.outer_steps,
                   "inner_cycles": st_m.cycles, "rel_res": st_m.rel_res,
-                  "alg_GB_s": st_m.alg_bytes / t_mixed / 1e9},
+                  "alg_bytes": st_m.alg_bytes, "alg_GB_s": st_m.alg_bytes / t_mixed / 1e9},
         "fp64": {"ms": t_fp64 * 1e3, "cycles": st_f.cycles, "rel_res": st_f.rel_res,
-                 "alg_GB_s": st_f.alg_bytes / t_fp64 / 1e9},
+                 "alg_bytes": st_f.alg_bytes, "alg_GB_s": st_f.alg_bytes / t_fp64 / 1e9},
         "mixed_speedup_vs_fp64": t_fp64 / t_mixed,
     }
 
@@ -441,6 +512,7 @@ def main():
     h4.close()
     del b, x
     torch.cuda.empty_cache()
+    progress("L = 12 FP64, CG variants done")
 
     # ---------------- L = 10 (FP64 vs mixed) and L = 6 (sin sin, FP64)
     small_x = {}
@@ -453,7 +525,7 @@ def main():
             bb = torch.empty(hh.n, dtype=torch.float64, device=dev)
             hh.rhs_sinsin(bb)
         xx = torch.zeros_like(bb)
-        rec = {}
+        r_ = {}
         for pname, o in (("fp64", fp64), ("mixed", mixed)):
             solve(hh, bb, xx, o)
             torch.cuda.synchronize()
@@ -462,13 +534,14 @@ def main():
                 s = solve(hh, bb, xx, o)
             torch.cuda.synchronize()
             dt = (time.perf_counter() - t0) / reps
-            rec[pname] = {"ms": dt * 1e3, "solves_s": 1.0 / dt, "cycles": s.cycles,
-                          "outer_steps": s.outer_steps, "rel_res": s.rel_res}
+            r_[pname] = {"ms": dt * 1e3, "solves_s": 1.0 / dt, "cycles": s.cycles,
+                         "outer_steps": s.outer_steps, "rel_res": s.rel_res}
             small_x[(name, pname)] = xx.cpu().numpy()
-        out[name] = rec
+        out[name] = r_
         hh.close()
 
-    # ---------------- BLAS level 1 over lengths 2^10 .. 2^28
+    progress("L = 10 and L = 6 done")
+    # ---------------- BLAS level 1 at lengths from cache- to HBM-resident
     out["blas1"] = bench_blas1(ctx, torch, dev)
     # ---------------- shallow-water prediction step (four-band combination)
     out["swe_band4"] = bench_band4(ctx, torch, dev)
@@ -477,24 +550,20 @@ def main():
     if not args.no_batch:
         out["batch256"] = bench_batch(mg, ctx, synth, torch, dev, mixed)
         torch.cuda.empty_cache()
+        progress("batch done")
     # ---------------- serving: Poisson arrivals, P(L) ~ 1/L on 6..11
     if not args.no_serving:
         out["serving"] = bench_serving(mg, ctx, synth, args)
+        progress("serving done")
 
     # ---------------- oracle on the host CPU (bounded sample)
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
-        xy = synth.coords(L, jit, gseed)
-        bh = synth.rhs_gaussian(L, rseed)
-        oh = oracle.Hierarchy(L, xy)
-        t0 = time.perf_counter()
-        xo, ost = oh.solve_fp64(bh, o=oracle.opts(rel_tol=1e-8))
-        dt = time.perf_counter() - t0
-        cpu = {"value": 1.0 / dt, "unit": "solves/s", "cores": 1, "kind": "oracle",
-               "sample": "one plain FP64 V(2,2) solve to 1e-8 of the same L=12 problem "
-                         "(%d cycles, %.1f s, assembly excluded), single thread" % (ost.cycles, dt)}
-        oh.close()
+        cpu, xo, ost = oracle_baseline(L, jit, gseed, rseed, synth)
+        progress("oracle timed: %.1f s one thread, %.2f s on %d threads"
+                 % (cpu["single_thread"]["seconds"], cpu["seconds"], cpu["cores"]))
+
         # each GPU result against the oracle's FP64 solution of the same problem
         # (inputs from the host generators and the oracle's own load vector)
         def vs_oracle(xo_, ost_, xf, xm):
@@ -509,19 +578,29 @@ def main():
             Ns = (1 << LL) + 1
             b_s = (synth.rhs_uniform(LL, 2002) if name == "L10"
                    else oracle.load_vector(Ns, xy_s, fn=0))
-            oh_s = oracle.Hierarchy(LL, xy_s)
+            oh_s = oracle.Hierarchy(LL, xy_s, threaded=True)
             xo_s, ost_s = oh_s.solve_fp64(b_s, o=oracle.opts(rel_tol=1e-8))
             oh_s.close()
             out[name]["vs_oracle"] = vs_oracle(xo_s, ost_s, small_x[(name, "fp64")],
                                                small_x[(name, "mixed")])
-        try:
-            model = next(ln.split(":", 1)[1].strip() for ln in open("/proc/cpuinfo")
-                         if ln.startswith("model name"))
-        except (OSError, StopIteration):
-            model = "unknown"
-        cpu["host"] = {"nproc": os.cpu_count(), "cpu_model": model}
 
-    roof_achieved = out["band_kernels"]["fused_pre_fp32"]["GB_s"]
+    bk = out["band_kernels"]
+    pre = bk["fused_pre_fp32"]
+    traffic = traffic_from_profiles("fused_pre_fp32")
+    roof = {"bound": "hbm", "achieved": pre["GB_s"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": pre["GB_s"] / PEAK_HBM_GBS, "traffic": traffic,
+            "kernel": "k_pre<float, false, 256> (finest-level fused FP32 pre-smoothing pass: "
+                      "two damped Jacobi sweeps, defect, restriction)",
+            "us": pre["us"],
+            "alg_bytes": fused_alg,
+            "alg_bytes_model": "12 scalars per finest node (9 stored bands, x and b read, "
+                               "iterate written) + 1 per coarse node (coarse rhs written)",
+            "min_bytes": fused_min,
+            "frac_min_bytes": pre["GB_s_min_bytes"] / PEAK_HBM_GBS,
+            "min_bytes_model": "8 scalars per finest node (diagonal and 4 upper bands, x, b, "
+                               "iterate) + 1 per coarse node",
+            "frac_counter_traffic": (traffic / (pre["us"] * 1e-6) / 1e9 / PEAK_HBM_GBS
+                                     if traffic else None)}
     line = {
         "metric": "MG solves/s & band-SpMV GB/s (mixed vs FP64 @1e-8 rel.res); serving p99",
         "value": 1.0 / t_mixed,
@@ -539,15 +618,25 @@ def main():
                                "jitter 0.2h seed 1003, Gaussian RHS seed 2003, V(2,2) "
                                "omega 0.7, rel.res 1e-8",
                    "L": L, "unknowns": n},
-        "roofline": {"bound": "hbm", "achieved": roof_achieved, "peak": PEAK_HBM_GBS,
-                     "unit": "GB/s", "frac": roof_achieved / PEAK_HBM_GBS,
-                     "kernel": "k_pre<float, false, 256> (finest-level fused FP32 "
-                               "pre-smoothing pass)",
-                     "traffic": traffic_from_profiles("fused_pre_fp32")},
+        "roofline": roof,
         "cpu_baseline": cpu,
+        "spmv_fp32_GB_s": bk["spmv_fp32"]["GB_s"],
+        "spmv_fp32_frac": bk["spmv_fp32"]["frac_hbm_peak"],
+        "spmv_fp64_GB_s": bk["spmv_fp64"]["GB_s"],
+        "spmv_fp64_frac": bk["spmv_fp64"]["frac_hbm_peak"],
+        "mixed_ms": t_mixed * 1e3,
+        "fp64_ms": t_fp64 * 1e3,
+        "mixed_speedup_vs_fp64": t_fp64 / t_mixed,
+        "speedup_vs_oracle_all_cores": (cpu["seconds"] / t_mixed) if cpu else None,
     }
+    if "batch256" in out:
+        line["batch256_ms"] = out["batch256"]["ms"]
+        line["batch256_solves_s"] = out["batch256"]["solves_s"]
     if "serving" in out:
-        line["serving_p99_ms"] = out["serving"]["headline"]["p99_ms"]
+        hd = out["serving"]["headline"]
+        line["serving_solves_s"] = hd["achieved_solves_s"]
+        line["serving_p50_ms"] = hd["p50_ms"]
+        line["serving_p99_ms"] = hd["p99_ms"]
     line.update(out)
     print(json.dumps(line))
 

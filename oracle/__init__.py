@@ -16,20 +16,37 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "mg_oracle.c")
+_HDR = os.path.join(_HERE, "mg_oracle.h")
 _LIB = os.path.join(_HERE, "libmg_oracle.so")
+# The same source built with -fopenmp: element-wise loops on every host core,
+# sums sequential (bitwise the results of the one-thread build).
+_LIB_OMP = os.path.join(_HERE, "libmg_oracle_omp.so")
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _fp = ctypes.POINTER(ctypes.c_float)
 
 
-def build(force: bool = False) -> str:
-    """Compile the oracle with gcc (plain -O2, no FMA contraction)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp%d" % os.getpid()
+def _compile(out: str, extra, force: bool) -> str:
+    newest = max(os.path.getmtime(_SRC), os.path.getmtime(_HDR))
+    if force or not os.path.exists(out) or os.path.getmtime(out) < newest:
+        tmp = out + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared",
-                               "-ffp-contract=off", "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB)
-    return _LIB
+                               "-ffp-contract=off"] + list(extra) + ["-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, out)
+    return out
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (plain -O2, no FMA contraction), one
+    thread; with ``force`` also the OpenMP build."""
+    if force:
+        build_omp(force=True)
+    return _compile(_LIB, [], force)
+
+
+def build_omp(force: bool = False) -> str:
+    """The same source with -fopenmp (the all-core timing of the benchmark)."""
+    return _compile(_LIB_OMP, ["-fopenmp"], force)
 
 
 class OrOpts(ctypes.Structure):
@@ -49,63 +66,84 @@ class OrStats(ctypes.Structure):
 
 
 _lib = None
+_lib_omp = None
 
 
 def lib():
+    """The one-thread oracle library."""
     global _lib
     if _lib is None:
-        _lib = ctypes.CDLL(build())
-        L = _lib
-        L.or_element_stiffness.argtypes = [_dp, _dp, _dp]
-        L.or_assemble.argtypes = [ctypes.c_int, _dp, ctypes.c_int, _dp]
-        L.or_load_vector.argtypes = [ctypes.c_int, _dp, ctypes.c_int, ctypes.c_int, _dp]
-        L.or_l2_error_sinsin.argtypes = [ctypes.c_int, _dp, _dp]
-        L.or_l2_error_sinsin.restype = ctypes.c_double
-        L.or_spmv.argtypes = [ctypes.c_int, _dp, _dp, _dp]
-        L.or_defect.argtypes = [ctypes.c_int, _dp, _dp, _dp, _dp]
-        L.or_jacobi.argtypes = [ctypes.c_int, _dp, _dp, _dp, _dp, ctypes.c_double]
-        L.or_restrict.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_int]
-        L.or_prolong_add.argtypes = [ctypes.c_int, _dp, _dp]
-        L.or_norm2.argtypes = [ctypes.c_size_t, _dp]
-        L.or_norm2.restype = ctypes.c_double
-        L.or_cholesky.argtypes = [ctypes.c_int, _dp]
-        L.or_cholesky_solve.argtypes = [ctypes.c_int, _dp, _dp]
-        L.or_spmv_f32.argtypes = [ctypes.c_int, _fp, _fp, _fp]
-        L.or_jacobi_f32.argtypes = [ctypes.c_int, _fp, _fp, _fp, _fp, ctypes.c_float]
-        L.or_restrict_f32.argtypes = [ctypes.c_int, _fp, _fp]
-        L.or_prolong_add_f32.argtypes = [ctypes.c_int, _fp, _fp]
-        L.or_hier_create.argtypes = [ctypes.c_int, ctypes.c_int, _dp]
-        L.or_hier_create.restype = ctypes.c_void_p
-        L.or_hier_create_bc.argtypes = [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int]
-        L.or_hier_create_bc.restype = ctypes.c_void_p
-        L.or_assemble_bc.argtypes = [ctypes.c_int, _dp, ctypes.c_int, _dp]
-        L.or_load_vector_bc.argtypes = [ctypes.c_int, _dp, ctypes.c_int, ctypes.c_int, _dp]
-        L.or_l2_error.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_int]
-        L.or_l2_error.restype = ctypes.c_double
-        L.or_restrict_bc.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_int]
-        L.or_restrict_f32_bc.argtypes = [ctypes.c_int, _fp, _fp, ctypes.c_int]
-        L.or_hier_destroy.argtypes = [ctypes.c_void_p]
-        L.or_hier_N.argtypes = [ctypes.c_void_p, ctypes.c_int]
-        L.or_hier_bands.argtypes = [ctypes.c_void_p, ctypes.c_int]
-        L.or_hier_bands.restype = _dp
-        L.or_hier_coords.argtypes = [ctypes.c_void_p, ctypes.c_int]
-        L.or_hier_coords.restype = _dp
-        L.or_vcycle.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp, _dp, ctypes.POINTER(OrOpts)]
-        L.or_solve_fp64.argtypes = [ctypes.c_void_p, _dp, _dp, ctypes.POINTER(OrOpts),
-                                    ctypes.POINTER(OrStats)]
-        L.or_solve_mixed_emulated.argtypes = [ctypes.c_void_p, _dp, _dp,
-                                              ctypes.POINTER(OrOpts), ctypes.POINTER(OrStats)]
-        L.or_axpy.argtypes = [ctypes.c_size_t, ctypes.c_double, _dp, _dp]
-        L.or_band4_combine.argtypes = [ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(_dp),
-                                       ctypes.c_size_t, ctypes.POINTER(ctypes.c_int),
-                                       ctypes.POINTER(_dp), _dp, _dp, _dp]
-        L.or_dot.argtypes = [ctypes.c_size_t, _dp, _dp]
-        L.or_dot.restype = ctypes.c_double
-        L.or_cg.argtypes = [ctypes.c_int, _dp, _dp, _dp, ctypes.c_double, ctypes.c_int]
-        L.or_cg.restype = ctypes.c_int
-        L.or_solve_pcg.argtypes = [ctypes.c_void_p, _dp, _dp, ctypes.POINTER(OrOpts),
-                                   ctypes.c_int, ctypes.POINTER(OrStats)]
+        _lib = _declare(ctypes.CDLL(build()))
     return _lib
+
+
+def lib_omp():
+    """The OpenMP build of the same source (element-wise loops threaded)."""
+    global _lib_omp
+    if _lib_omp is None:
+        _lib_omp = _declare(ctypes.CDLL(build_omp()))
+    return _lib_omp
+
+
+def threads(threaded: bool = True) -> int:
+    """Host threads the chosen build's element-wise loops use."""
+    return (lib_omp() if threaded else lib()).or_threads()
+
+
+def _declare(L):
+    """Argument and result types of every exported function."""
+    L.or_element_stiffness.argtypes = [_dp, _dp, _dp]
+    L.or_assemble.argtypes = [ctypes.c_int, _dp, ctypes.c_int, _dp]
+    L.or_load_vector.argtypes = [ctypes.c_int, _dp, ctypes.c_int, ctypes.c_int, _dp]
+    L.or_l2_error_sinsin.argtypes = [ctypes.c_int, _dp, _dp]
+    L.or_l2_error_sinsin.restype = ctypes.c_double
+    L.or_spmv.argtypes = [ctypes.c_int, _dp, _dp, _dp]
+    L.or_defect.argtypes = [ctypes.c_int, _dp, _dp, _dp, _dp]
+    L.or_jacobi.argtypes = [ctypes.c_int, _dp, _dp, _dp, _dp, ctypes.c_double]
+    L.or_restrict.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_int]
+    L.or_prolong_add.argtypes = [ctypes.c_int, _dp, _dp]
+    L.or_norm2.argtypes = [ctypes.c_size_t, _dp]
+    L.or_norm2.restype = ctypes.c_double
+    L.or_cholesky.argtypes = [ctypes.c_int, _dp]
+    L.or_cholesky_solve.argtypes = [ctypes.c_int, _dp, _dp]
+    L.or_spmv_f32.argtypes = [ctypes.c_int, _fp, _fp, _fp]
+    L.or_jacobi_f32.argtypes = [ctypes.c_int, _fp, _fp, _fp, _fp, ctypes.c_float]
+    L.or_restrict_f32.argtypes = [ctypes.c_int, _fp, _fp]
+    L.or_prolong_add_f32.argtypes = [ctypes.c_int, _fp, _fp]
+    L.or_hier_create.argtypes = [ctypes.c_int, ctypes.c_int, _dp]
+    L.or_hier_create.restype = ctypes.c_void_p
+    L.or_hier_create_bc.argtypes = [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int]
+    L.or_hier_create_bc.restype = ctypes.c_void_p
+    L.or_assemble_bc.argtypes = [ctypes.c_int, _dp, ctypes.c_int, _dp]
+    L.or_load_vector_bc.argtypes = [ctypes.c_int, _dp, ctypes.c_int, ctypes.c_int, _dp]
+    L.or_l2_error.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_int]
+    L.or_l2_error.restype = ctypes.c_double
+    L.or_restrict_bc.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_int]
+    L.or_restrict_f32_bc.argtypes = [ctypes.c_int, _fp, _fp, ctypes.c_int]
+    L.or_hier_destroy.argtypes = [ctypes.c_void_p]
+    L.or_hier_N.argtypes = [ctypes.c_void_p, ctypes.c_int]
+    L.or_hier_bands.argtypes = [ctypes.c_void_p, ctypes.c_int]
+    L.or_hier_bands.restype = _dp
+    L.or_hier_coords.argtypes = [ctypes.c_void_p, ctypes.c_int]
+    L.or_hier_coords.restype = _dp
+    L.or_vcycle.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp, _dp, ctypes.POINTER(OrOpts)]
+    L.or_solve_fp64.argtypes = [ctypes.c_void_p, _dp, _dp, ctypes.POINTER(OrOpts),
+                                ctypes.POINTER(OrStats)]
+    L.or_solve_mixed_emulated.argtypes = [ctypes.c_void_p, _dp, _dp,
+                                          ctypes.POINTER(OrOpts), ctypes.POINTER(OrStats)]
+    L.or_axpy.argtypes = [ctypes.c_size_t, ctypes.c_double, _dp, _dp]
+    L.or_band4_combine.argtypes = [ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(_dp),
+                                   ctypes.c_size_t, ctypes.POINTER(ctypes.c_int),
+                                   ctypes.POINTER(_dp), _dp, _dp, _dp]
+    L.or_dot.argtypes = [ctypes.c_size_t, _dp, _dp]
+    L.or_dot.restype = ctypes.c_double
+    L.or_cg.argtypes = [ctypes.c_int, _dp, _dp, _dp, ctypes.c_double, ctypes.c_int]
+    L.or_cg.restype = ctypes.c_int
+    L.or_solve_pcg.argtypes = [ctypes.c_void_p, _dp, _dp, ctypes.POINTER(OrOpts),
+                               ctypes.c_int, ctypes.POINTER(OrStats)]
+    L.or_threads.argtypes = []
+    L.or_threads.restype = ctypes.c_int
+    return L
 
 
 def _d(a: np.ndarray):
@@ -241,17 +279,20 @@ def prolong_add_f32(Nf, x_c32, x_f32):
 class Hierarchy:
     """Oracle multigrid hierarchy on the finest coordinates ``xy`` (2*n)."""
 
-    def __init__(self, L: int, xy: np.ndarray, Lc: int = 1, dmask: int = ALL_DIRICHLET):
+    def __init__(self, L: int, xy: np.ndarray, Lc: int = 1, dmask: int = ALL_DIRICHLET,
+                 threaded: bool = False):
+        """threaded: run on the OpenMP build (all host cores; same results)."""
         self.L, self.Lc, self.dmask = L, Lc, dmask
+        self._lib = lib_omp() if threaded else lib()
         self._xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1)
-        self._h = lib().or_hier_create_bc(L, Lc, _d(self._xy), int(dmask))
+        self._h = self._lib.or_hier_create_bc(L, Lc, _d(self._xy), int(dmask))
         if not self._h:
             raise ValueError("oracle hierarchy creation failed (L=%d, Lc=%d, dmask=%d)"
                              % (L, Lc, dmask))
 
     def close(self):
-        if self._h:
-            lib().or_hier_destroy(self._h)
+        if getattr(self, "_h", None):
+            self._lib.or_hier_destroy(self._h)
             self._h = None
 
     def __del__(self):
@@ -262,17 +303,17 @@ class Hierarchy:
 
     def bands(self, l: int) -> np.ndarray:
         n = self.N(l) ** 2
-        ptr = lib().or_hier_bands(self._h, l)
+        ptr = self._lib.or_hier_bands(self._h, l)
         return np.ctypeslib.as_array(ptr, shape=(9 * n,)).copy().reshape(9, n)
 
     def coords(self, l: int) -> np.ndarray:
         n = self.N(l) ** 2
-        ptr = lib().or_hier_coords(self._h, l)
+        ptr = self._lib.or_hier_coords(self._h, l)
         return np.ctypeslib.as_array(ptr, shape=(2 * n,)).copy()
 
     def vcycle(self, l: int, x: np.ndarray, b: np.ndarray, o: OrOpts | None = None):
         x = np.array(x, dtype=np.float64, copy=True)
-        lib().or_vcycle(self._h, l, _d(x), _d(np.ascontiguousarray(b)),
+        self._lib.or_vcycle(self._h, l, _d(x), _d(np.ascontiguousarray(b)),
                         ctypes.byref(o or opts()))
         return x
 
@@ -280,7 +321,7 @@ class Hierarchy:
         n = self.N(self.L) ** 2
         x = np.zeros(n) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
         st = OrStats()
-        lib().or_solve_fp64(self._h, _d(np.ascontiguousarray(b)), _d(x),
+        self._lib.or_solve_fp64(self._h, _d(np.ascontiguousarray(b)), _d(x),
                             ctypes.byref(o or opts()), ctypes.byref(st))
         return x, st
 
@@ -289,7 +330,7 @@ class Hierarchy:
         n = self.N(self.L) ** 2
         x = np.zeros(n) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
         st = OrStats()
-        lib().or_solve_pcg(self._h, _d(np.ascontiguousarray(b)), _d(x),
+        self._lib.or_solve_pcg(self._h, _d(np.ascontiguousarray(b)), _d(x),
                            ctypes.byref(o or opts()), int(precond32), ctypes.byref(st))
         return x, st
 
@@ -297,7 +338,7 @@ class Hierarchy:
         n = self.N(self.L) ** 2
         x = np.zeros(n) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
         st = OrStats()
-        lib().or_solve_mixed_emulated(self._h, _d(np.ascontiguousarray(b)), _d(x),
+        self._lib.or_solve_mixed_emulated(self._h, _d(np.ascontiguousarray(b)), _d(x),
                                       ctypes.byref(o or opts()), ctypes.byref(st))
         return x, st
 

@@ -1,15 +1,31 @@
 /*
  * mg_oracle.c -- TEST INFRASTRUCTURE ONLY (see mg_oracle.h).
  *
- * Plain FP64 loops, one thread, no blocking or fusion: every function follows
- * the definition it cites so that it can be checked against the paper by eye.
- * Built with -O2 -ffp-contract=off so that no multiply-add is fused.
+ * Plain FP64 loops, no blocking or fusion: every function follows the
+ * definition it cites so that it can be checked against the paper by eye.
+ * Built with -O2 -ffp-contract=off so that no multiply-add is fused.  The
+ * plain build runs on one thread.  Built with -fopenmp, the loops whose
+ * iterations write disjoint outputs (band products, sweeps, transfers, one
+ * grid row or one node per iteration) are shared among the host's cores;
+ * every sum stays a sequential loop, so each output is the same arithmetic
+ * in the same order and the results are bitwise those of the plain build.
  */
 #include "mg_oracle.h"
 
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+int or_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 static const double OR_PI = 3.14159265358979323846;
 
@@ -244,6 +260,7 @@ double or_l2_error(int N, const double* xy, const double* u, int fn) {
  * skipped (their band entries are zero). */
 void or_spmv(int N, const double* bands, const double* x, double* y) {
     size_t n = (size_t)N * N;
+#pragma omp parallel for schedule(static)
     for (int j = 0; j < N; ++j) {
         for (int i = 0; i < N; ++i) {
             size_t p = (size_t)j * N + i;
@@ -261,6 +278,7 @@ void or_spmv(int N, const double* bands, const double* x, double* y) {
 void or_defect(int N, const double* bands, const double* b, const double* x, double* d) {
     size_t n = (size_t)N * N;
     or_spmv(N, bands, x, d);
+#pragma omp parallel for schedule(static)
     for (size_t p = 0; p < n; ++p) d[p] = b[p] - d[p];
 }
 
@@ -269,6 +287,7 @@ void or_jacobi(int N, const double* bands, const double* b, const double* x, dou
                double omega) {
     size_t n = (size_t)N * N;
     or_spmv(N, bands, x, x_out);
+#pragma omp parallel for schedule(static)
     for (size_t p = 0; p < n; ++p)
         x_out[p] = x[p] + omega * (b[p] - x_out[p]) / bands[4 * n + p];
 }
@@ -290,6 +309,7 @@ void or_restrict(int Nf, const double* d_f, double* b_c, int filter) {
 /* The same with the coarse Dirichlet nodes of the sides in dmask zeroed. */
 void or_restrict_bc(int Nf, const double* d_f, double* b_c, int dmask) {
     int Nc = (Nf - 1) / 2 + 1;
+#pragma omp parallel for schedule(static)
     for (int J = 0; J < Nc; ++J) {
         for (int I = 0; I < Nc; ++I) {
             double s = 0.0;
@@ -308,6 +328,7 @@ void or_restrict_bc(int Nf, const double* d_f, double* b_c, int dmask) {
 /* x_f[f,g] += sum_{(I,J)} P[(f,g),(I,J)] x_c[I,J]  (bilinear in index space). */
 void or_prolong_add(int Nf, const double* x_c, double* x_f) {
     int Nc = (Nf - 1) / 2 + 1;
+#pragma omp parallel for schedule(static)
     for (int g = 0; g < Nf; ++g) {
         for (int f = 0; f < Nf; ++f) {
             double s = 0.0;
@@ -422,6 +443,7 @@ int or_cg(int N, const double* bands, const double* b, double* x, double tol, in
 /* ---- single precision band operations (emulated FP32 inner cycles) ---- */
 void or_spmv_f32(int N, const float* bands, const float* x, float* y) {
     size_t n = (size_t)N * N;
+#pragma omp parallel for schedule(static)
     for (int j = 0; j < N; ++j) {
         for (int i = 0; i < N; ++i) {
             size_t p = (size_t)j * N + i;
@@ -440,6 +462,7 @@ void or_jacobi_f32(int N, const float* bands, const float* b, const float* x, fl
                    float omega) {
     size_t n = (size_t)N * N;
     or_spmv_f32(N, bands, x, x_out);
+#pragma omp parallel for schedule(static)
     for (size_t p = 0; p < n; ++p)
         x_out[p] = x[p] + omega * (b[p] - x_out[p]) / bands[4 * n + p];
 }
@@ -450,6 +473,7 @@ void or_restrict_f32(int Nf, const float* d_f, float* b_c) {
 
 void or_restrict_f32_bc(int Nf, const float* d_f, float* b_c, int dmask) {
     int Nc = (Nf - 1) / 2 + 1;
+#pragma omp parallel for schedule(static)
     for (int J = 0; J < Nc; ++J) {
         for (int I = 0; I < Nc; ++I) {
             float s = 0.0f;
@@ -467,6 +491,7 @@ void or_restrict_f32_bc(int Nf, const float* d_f, float* b_c, int dmask) {
 
 void or_prolong_add_f32(int Nf, const float* x_c, float* x_f) {
     int Nc = (Nf - 1) / 2 + 1;
+#pragma omp parallel for schedule(static)
     for (int g = 0; g < Nf; ++g) {
         for (int f = 0; f < Nf; ++f) {
             float s = 0.0f;

@@ -72,6 +72,9 @@ void or_restrict_bc(int Nf, const double* d_f, double* b_c, int dmask);
 /* Prolongation with correction: x_f += P x_c. */
 void or_prolong_add(int Nf, const double* x_c, double* x_f);
 double or_norm2(size_t n, const double* v);
+/* Host threads the element-wise loops use: 1 for the plain build, the
+ * OpenMP thread count for a -fopenmp build (same results either way). */
+int or_threads(void);
 
 /* Dense Cholesky (lower, in place, row-major m x m); returns 0 or -1 if a
  * pivot is not positive. */
