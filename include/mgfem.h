@@ -320,6 +320,20 @@ mg_status mg_dot(mg_context* ctx, mg_dtype dtype, int64_t n, const void* x, cons
                  double* host_out, void* stream);
 mg_status mg_norm2(mg_context* ctx, mg_dtype dtype, int64_t n, const void* x, double* host_out,
                    void* stream);
+/* mg_dot for callers that cannot allocate device or pinned memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same x . y, the same bits as mg_dot, written to the
+ * caller's device scalar dev_out[0] (8-byte aligned, on ctx's device)
+ * asynchronously on stream; the call allocates nothing and never waits.
+ * The tile partials live in one fixed device array of the library (1 MiB
+ * per device that runs the call, held until the process ends), so n is at
+ * most 2^27 (MG_F64) or 2^28 (MG_F32) elements: MG_ERR_INVALID above that.
+ * Every call on one device shares that array, and the array keeps the last
+ * call's partials: calls that may overlap on one device (other streams,
+ * other threads) race and must be ordered by the caller.  Other arguments
+ * and errors as for mg_dot. */
+mg_status mg_dot_noalloc(mg_context* ctx, mg_dtype dtype, int64_t n, const void* x,
+                         const void* y, double* dev_out, void* stream);
 
 /* ---- four-band combination (Sec. 2.2: the shallow-water prediction step,
  * u_new = u + M1 v + M2 w + M3 u + M4 u + S(u), with four-band matrices) ----

@@ -97,6 +97,7 @@ _SIGS = {
     "mg_axpy": (_i, [_vp, _i, _i64, _d, _vp, _vp, _vp]),
     "mg_dot": (_i, [_vp, _i, _i64, _vp, _vp, ctypes.POINTER(_d), _vp]),
     "mg_norm2": (_i, [_vp, _i, _i64, _vp, ctypes.POINTER(_d), _vp]),
+    "mg_dot_noalloc": (_i, [_vp, _i, _i64, _vp, _vp, _vp, _vp]),
     "mg_band4_combine": (_i, [_vp, _i, _i64, _i, ctypes.POINTER(_vp), _i64, ctypes.POINTER(_i),
                               ctypes.POINTER(_vp), _vp, _vp, _vp, _vp]),
     "mg_batch_autotune": (_i, [ctypes.POINTER(_vp), _i, ctypes.POINTER(SolveOpts), _i,
@@ -205,6 +206,16 @@ class Context:
         check(lib().mg_dot(self._h, _dt(x), x.numel(), _ptr(x), _ptr(y), ctypes.byref(out),
                            _stream(stream)))
         return out.value
+
+    def dot_noalloc(self, x, y, out, stream=None):
+        """out[0] = x . y (device float64 tensor), asynchronously; allocates
+        nothing (mg_dot_noalloc)."""
+        if x.numel() != y.numel() or x.dtype != y.dtype:
+            raise ValueError("x and y must have the same length and dtype")
+        if out.dtype != torch.float64 or out.numel() < 1:
+            raise ValueError("out must be a float64 device tensor with at least one element")
+        check(lib().mg_dot_noalloc(self._h, _dt(x), x.numel(), _ptr(x), _ptr(y), _ptr(out),
+                                   _stream(stream)))
 
     def band4_combine(self, bands, offsets, vs, u, u_new, s=None, stream=None):
         """u_new = u + sum_i M_i v_i (+ s): bands[i] a device tensor of shape

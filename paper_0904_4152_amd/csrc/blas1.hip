@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <string>
 
 #include "device_ops.h"
@@ -152,6 +153,68 @@ mg_status blas_reduce(mg_context* ctx, int64_t n, const T* x, const T* y, double
     return MG_OK;
 }
 
+// ---- the dot product without allocation (mg_dot_noalloc)
+// Tile partials of one call live in a file-scope device array instead of the
+// context's grown-on-demand scratch: 2^17 partials (1 MiB) cover 2^27 FP64 or
+// 2^28 FP32 elements.  Each device that runs the call holds its own copy of
+// the array until the process ends.  In host code the name `scratch` is only
+// a host-side stand-in: kernels get the device address looked up once per
+// device (noalloc_scratch).
+constexpr int64_t NOALLOC_MAX_TILES = int64_t(1) << 17;
+static __device__ __align__(256) double scratch[NOALLOC_MAX_TILES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_noalloc_mu;
+double* g_noalloc_ptr[MAX_DEVICES] = {};
+
+// Device address of `scratch` on `device` (current on entry), looked up on
+// the first call on that device and kept.
+mg_status noalloc_scratch(int device, double** out) {
+    if (device < 0 || device >= MAX_DEVICES)
+        return fail(MG_ERR_INVALID, "device " + std::to_string(device) + " outside [0, 64)");
+    std::lock_guard<std::mutex> g(g_noalloc_mu);
+    if (!g_noalloc_ptr[device]) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(MG_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") +
+                                           hipGetErrorString(e));
+        g_noalloc_ptr[device] = (double*)p;
+    }
+    *out = g_noalloc_ptr[device];
+    return MG_OK;
+}
+
+// out[0] = the fixed-order sum of np partials (dev::reduce_partials, the
+// order of launch_reduce), in one workgroup.
+__global__ __launch_bounds__(BLOCK) void k_reduce_one(const double* __restrict__ partials,
+                                                      int64_t np, double* __restrict__ out) {
+    const double s = dev::reduce_partials(partials, np);
+    if (threadIdx.x == 0) out[0] = s;
+}
+
+template <typename T>
+mg_status dot_noalloc(int device, int64_t n, const T* x, const T* y, double* dev_out,
+                      hipStream_t st) {
+    const int64_t tiles = (n + blas_tile<T>() - 1) / blas_tile<T>();
+    if (tiles > NOALLOC_MAX_TILES)
+        return fail(MG_ERR_INVALID,
+                    "n=" + std::to_string(n) + " above the no-allocation limit of " +
+                        std::to_string(NOALLOC_MAX_TILES * blas_tile<T>()) + " elements");
+    double* partials = nullptr;
+    if (mg_status s = noalloc_scratch(device, &partials)) return s;
+    // every partial the reduction reads is written by this call first, so
+    // nothing is cleared (n = 0 reduces no partials: out = 0)
+    if (tiles > 0) {
+        hipLaunchKernelGGL((k_dot_tiles<T, false>), dim3((unsigned)tiles), dim3(BLOCK), 0, st, n,
+                           x, y, partials);
+        MG_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_reduce_one, dim3(1), dim3(BLOCK), 0, st, partials, tiles, dev_out);
+    MG_HIP(hipGetLastError());
+    return MG_OK;
+}
+
 }  // namespace
 
 }  // namespace mg
@@ -199,4 +262,17 @@ extern "C" mg_status mg_norm2(mg_context* ctx, mg_dtype dtype, int64_t n, const 
                                          (hipStream_t)stream, true);
     return blas_reduce<float, true>(ctx, n, (const float*)x, nullptr, host_out,
                                     (hipStream_t)stream, true);
+}
+
+extern "C" mg_status mg_dot_noalloc(mg_context* ctx, mg_dtype dtype, int64_t n, const void* x,
+                                    const void* y, double* dev_out, void* stream) {
+    if (mg_status s = check_vectors(ctx, dtype, n, x, y)) return s;
+    if (!dev_out || ((uintptr_t)dev_out & 7))
+        return fail(MG_ERR_INVALID, "dev_out must be an 8-byte aligned device pointer");
+    MG_HIP(hipSetDevice(ctx->device));
+    if (dtype == MG_F64)
+        return dot_noalloc<double>(ctx->device, n, (const double*)x, (const double*)y, dev_out,
+                                   (hipStream_t)stream);
+    return dot_noalloc<float>(ctx->device, n, (const float*)x, (const float*)y, dev_out,
+                              (hipStream_t)stream);
 }
