@@ -19,6 +19,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -63,15 +64,25 @@ def parse():
     return ap.parse_args()
 
 
+def _code_only(src: str) -> str:
+    """C++ source without comments and with whitespace collapsed: what the
+    compiler sees of it (no string literal in the hashed sources holds a
+    comment marker)."""
+    src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", " ", src)
+    return " ".join(src.split())
+
+
 def kernel_source_hash() -> str:
-    """Hash of the sources and build flags of the band kernels and fused
-    passes whose HBM counters profiles/hbm_traffic.json records."""
+    """Hash of the code (comments excluded) and build flags of the band
+    kernels and fused passes whose HBM counters profiles/hbm_traffic.json
+    records."""
     h = hashlib.sha256()
     pkg = os.path.join(ROOT, "paper_0904_4152_amd")
     for name in TRAFFIC_SOURCES:
-        with open(os.path.join(pkg, name), "rb") as f:
+        with open(os.path.join(pkg, name)) as f:
             h.update(name.encode())
-            h.update(f.read())
+            h.update(_code_only(f.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -206,6 +206,8 @@ mg_status mg_solve(mg_hierarchy* h, const double* dev_b, double* dev_x,
                    const mg_solve_opts* opts, void* stream, mg_stats* stats);
 
 /* ---- batched solve ---------------------------------------------------------
+ * Not a passage of the paper: the library's entry point for many small
+ * solves at once, each exactly the mixed solve of Sec. 6.2.
  * Solve count independent problems A_p x_p = b_p (each with its own
  * assembled hierarchy; levels may differ, the coarse level must agree) with
  * the mixed-precision scheme of mg_solve, advancing all of them together:
@@ -227,37 +229,43 @@ mg_status mg_solve_batch(mg_hierarchy* const* hs, const double* const* b, double
                          int count, const mg_solve_opts* opts, void* stream, mg_stats* stats);
 
 /* ---- batched tiles: autotuner ----------------------------------------------
- * The fused passes of the batched solver (and of the server) process each
- * level in tiles of a strip of columns by a number of grid rows.  The rows
- * per tile come from a process-wide table filled by this autotuner, keyed by
- * level and by the number of problems at that level rounded down to a power
- * of two; levels without an entry use the rule "largest height in 4..64 that
- * still gives about 3500 wavefronts".  The wavefronts per grid row stay
- * with the rule that covers a row with the fewest threads: the residual
- * norm's summation order depends on them, and a batched result must equal
- * the single solve bit for bit.  Tile heights change no result bit.
+ * Sec. 3: the GPU thread-block partition is a runtime parameter.  The fused
+ * passes of the batched solver process each level in tiles of a strip of
+ * columns by a number of grid rows, with a workgroup of 1 to 4 wavefronts
+ * across a strip's row.  Both come from a process-wide table filled by this
+ * autotuner, keyed by level and by the number of problems at that level
+ * rounded down to a power of two; levels without an entry use the rules
+ * "fewest threads per row" (width) and "largest height in 4..64 that still
+ * gives about 3500 wavefronts" (rows).  No result bit depends on either: a
+ * batched result equals the single solve bit for bit whatever the table
+ * holds.  The server applies tuned rows only (a width change would
+ * re-capture its iteration graph while its mix changes).
  * mg_batch_autotune: for the composition of these problems (options as for
  * mg_solve_batch; NULL: defaults), times the fused pre- and post-smoothing
- * passes of every level with 4, 8, 16, 32 and 64 rows per tile (reps pairs
- * each, on the problems' FP32 work vectors, which no later solve reads before
- * writing), stores the fastest in the table and writes up to out_cap chosen
- * rows to out (*n_out = rows chosen).  Synchronous; thread safe with respect
- * to other batches on separate hierarchies.  Only V(2,2) cycles have tiles.
+ * passes of every level for each of 4, 8, 16, 32, 64 rows per tile and 1, 2,
+ * 3, 4 wavefronts per row (reps pairs each, on the problems' FP32 work
+ * vectors, which no later solve reads before writing), stores the fastest in
+ * the table and writes up to out_cap choices to out (*n_out = choices).
+ * Synchronous; thread safe with respect to other batches on separate
+ * hierarchies.  Only V(2,2) cycles have tiles.
  * mg_batch_set_tile: installs one entry (e.g. read back from a file);
- * tile_rows a power of two in [4, 256].  mg_batch_clear_tiles: empties the
- * table. */
+ * tile_rows a power of two in [4, 256], row_waves in 1..4, or 0 for the
+ * width rule.  mg_batch_clear_tiles: empties the table. */
 typedef struct {
     int level;
     int problems;     /* problems at this level in the tuned composition */
     int tile_rows;    /* chosen rows per tile */
-    double us;        /* one pre + post pass pair at that height, microseconds */
+    int row_waves;    /* chosen wavefronts across a strip's row (workgroup width / 64) */
+    double us;        /* one pre + post pass pair with that tile, microseconds */
 } mg_tile_choice;
 mg_status mg_batch_autotune(mg_hierarchy* const* hs, int count, const mg_solve_opts* opts,
                             int reps, mg_tile_choice* out, int out_cap, int* n_out);
-mg_status mg_batch_set_tile(int level, int problems, int tile_rows);
+mg_status mg_batch_set_tile(int level, int problems, int tile_rows, int row_waves);
 mg_status mg_batch_clear_tiles(void);
 
 /* ---- serving ---------------------------------------------------------------
+ * Not a passage of the paper: the library's continuous-batching service
+ * around the batched solve, under the device-memory limit of Sec. 4.2.
  * A server owns a BatchEngine of `slots` slots, a scheduler thread and a pool
  * of device-resident hierarchies of levels coarse_level..max_level charged
  * against hbm_budget_bytes (and the context budget).  Requests are admitted
@@ -386,11 +394,15 @@ mg_status mg_pre_smooth(const mg_hierarchy* h, int level, mg_dtype dtype, const 
 mg_status mg_post_smooth(const mg_hierarchy* h, int level, mg_dtype dtype, const void* b,
                          const void* x, const void* x_c, double omega, void* x_out,
                          double* host_norm, void* stream);
-/* b_c = P^T d_f with the coarse boundary set to 0; P is bilinear
- * interpolation in index space (weights 1, 1/2, 1/4). */
+/* b_c = P^T d_f with the coarse nodes on the Dirichlet sides set to 0; P is
+ * bilinear interpolation in index space (weights 1, 1/2, 1/4).  The paper
+ * names no transfer operators (Sec. 6.2 only says geometric multigrid): this
+ * is the library's reading, the exact transpose of mg_prolong, which makes
+ * P^T A_f P the coarse operator on uniform grids. */
 mg_status mg_restrict(const mg_hierarchy* h, int fine_level, mg_dtype dtype, const void* d_f,
                       void* b_c, void* stream);
-/* x_f += P x_c. */
+/* x_f += P x_c: bilinear interpolation in index space (the library's
+ * reading, as for mg_restrict). */
 mg_status mg_prolong(const mg_hierarchy* h, int fine_level, mg_dtype dtype, const void* x_c,
                      void* x_f, void* stream);
 /* Direct solve on the coarsest level (FP64 Cholesky, cast in/out for F32):

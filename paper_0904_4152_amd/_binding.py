@@ -35,7 +35,8 @@ class SolveOpts(ctypes.Structure):
 
 
 class TileChoice(ctypes.Structure):
-    _fields_ = [("level", _i), ("problems", _i), ("tile_rows", _i), ("us", _d)]
+    _fields_ = [("level", _i), ("problems", _i), ("tile_rows", _i), ("row_waves", _i),
+                ("us", _d)]
 
 
 class Stats(ctypes.Structure):
@@ -102,7 +103,7 @@ _SIGS = {
                               ctypes.POINTER(_vp), _vp, _vp, _vp, _vp]),
     "mg_batch_autotune": (_i, [ctypes.POINTER(_vp), _i, ctypes.POINTER(SolveOpts), _i,
                                ctypes.POINTER(TileChoice), _i, ctypes.POINTER(_i)]),
-    "mg_batch_set_tile": (_i, [_i, _i, _i]),
+    "mg_batch_set_tile": (_i, [_i, _i, _i, _i]),
     "mg_batch_clear_tiles": (_i, []),
     "mg_solve_batch": (_i, [ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp), _i,
                             ctypes.POINTER(SolveOpts), _vp, ctypes.POINTER(Stats)]),
@@ -379,8 +380,9 @@ class Hierarchy:
 
 
 def batch_autotune(hierarchies, opts=None, reps=10):
-    """Tune the batched solver's tile heights for this composition; returns the
-    chosen rows as dicts (level, problems, tile_rows, us)."""
+    """Tune the batched solver's tiles (rows and wavefronts per row) for this
+    composition; returns the choices as dicts (level, problems, tile_rows,
+    row_waves, us)."""
     n = len(hierarchies)
     hs = (_vp * n)(*[h.handle for h in hierarchies])
     out = (TileChoice * 16)()
@@ -388,13 +390,16 @@ def batch_autotune(hierarchies, opts=None, reps=10):
     check(lib().mg_batch_autotune(hs, n, ctypes.byref(opts) if opts is not None else None, reps,
                                   out, 16, ctypes.byref(got)))
     return [{"level": out[i].level, "problems": out[i].problems,
-             "tile_rows": out[i].tile_rows, "us": out[i].us} for i in range(min(got.value, 16))]
+             "tile_rows": out[i].tile_rows, "row_waves": out[i].row_waves, "us": out[i].us}
+            for i in range(min(got.value, 16))]
 
 
 def batch_set_tiles(rows):
-    """Install tile choices (the rows batch_autotune returns, e.g. from JSON)."""
+    """Install tile choices (the rows batch_autotune returns, e.g. from JSON;
+    a missing row_waves keeps the width rule)."""
     for r in rows:
-        check(lib().mg_batch_set_tile(int(r["level"]), int(r["problems"]), int(r["tile_rows"])))
+        check(lib().mg_batch_set_tile(int(r["level"]), int(r["problems"]), int(r["tile_rows"]),
+                                      int(r.get("row_waves", 0))))
 
 
 def batch_clear_tiles():

@@ -114,6 +114,10 @@ public:
     // tile height, keep the fastest in the process-wide tile table and
     // report it.  Uses only the FP32 work vectors (scratch); synchronous.
     mg_status tune(int reps, std::vector<mg_tile_choice>* out);
+    // Whether tuned workgroup widths apply (default on).  A width change
+    // re-captures the iteration graph, so an engine whose composition keeps
+    // changing (the server) keeps the width rule; tuned rows always apply.
+    void use_tuned_widths(bool on) { tuned_widths_ = on; }
     const BState& state(int s) const { return h_state_[s]; }
     int capacity() const { return cap_; }
     bool live(int s) const { return hp_[s].L > 0; }
@@ -159,13 +163,22 @@ private:
     uint32_t launch_mask_ = 0;
     double step_bytes_ = 0.0;
     int rh_override_[MG_MAX_LEVEL + 1] = {};  // tile heights under trial (0: none)
+    int bt_override_[MG_MAX_LEVEL + 1] = {};  // workgroup widths under trial (0: none)
+    int bt_[MG_MAX_LEVEL + 1] = {};           // workgroup width of each level's fused passes
+    int graph_bt_[MG_MAX_LEVEL + 1] = {};     // the widths the captured graph launches
+    bool tuned_widths_ = true;
 };
 
-// Process-wide table of tuned tile heights of the batched fused passes,
-// keyed by level and by the number of problems at that level (rounded down
-// to a power of two); 0 when the level has no entry.
-int tile_table_get(int level, int64_t problems);
-void tile_table_set(int level, int64_t problems, int rows);
+// Process-wide table of tuned tiles of the batched fused passes, keyed by
+// level and by the number of problems at that level (rounded down to a power
+// of two): rows per tile and workgroup width in threads; zeros when the level
+// has no entry.
+struct TileEntry {
+    int rows;
+    int bt;
+};
+TileEntry tile_table_get(int level, int64_t problems);
+void tile_table_set(int level, int64_t problems, int rows, int bt);
 void tile_table_clear();
 
 }  // namespace mg

@@ -418,8 +418,7 @@ __global__ __launch_bounds__(BLOCK) void kb_finalize(const BProb* __restrict__ p
                                : (n + TILE - 1) / TILE;
     // the inner residual comes from the fused post pass above the coarse level
     if (kind == K_S32 && fused_above >= 0 && P.L > fused_above)
-        np = (int64_t)F.nstrips * (F.bt / 64) *
-             ((F.N + dev::F_NORM_ROWS - 1) / dev::F_NORM_ROWS);  // fused post pass partials
+        np = dev::fused_norm_parts(F.N);  // fused post pass partials
     const double s = dev::reduce_partials(P.partials, np);
     if (threadIdx.x == 0) {
         const double r = sqrt(s);
@@ -597,6 +596,7 @@ mg_status BatchEngine::init(int device, int capacity, int Lmax, int Lc, int nu_p
     std::memset(h_ring_, 0, sizeof(int) * ring_ints);
     hp_.assign(cap_, BProb{});
     started_.assign(cap_, 0);
+    for (int l = 1; l <= MG_MAX_LEVEL; ++l) bt_[l] = graph_bt_[l] = fused_bt((1 << l) + 1);
     std::memset(h_state_, 0, sizeof(BState) * cap_);
     for (int s = 0; s < cap_; ++s) h_state_[s].flags = BF_DONE;
     MG_HIP(hipMemcpy(d_state_, h_state_, sizeof(BState) * cap_, hipMemcpyHostToDevice));
@@ -658,7 +658,7 @@ void BatchEngine::start_slot(int s) { started_[s] = 1; }
 namespace {
 struct TileTable {
     std::mutex mu;
-    std::map<std::pair<int, int>, int> rows;  // (level, log2 problems) -> tile rows
+    std::map<std::pair<int, int>, TileEntry> rows;  // (level, log2 problems) -> tile
 };
 TileTable& tile_table() {
     static TileTable* t = new TileTable();
@@ -674,17 +674,17 @@ int log2_floor(int64_t v) {
 }
 }  // namespace
 
-int tile_table_get(int level, int64_t problems) {
+TileEntry tile_table_get(int level, int64_t problems) {
     TileTable& t = tile_table();
     std::lock_guard<std::mutex> g(t.mu);
     auto it = t.rows.find({level, log2_floor(problems)});
-    return it == t.rows.end() ? 0 : it->second;
+    return it == t.rows.end() ? TileEntry{0, 0} : it->second;
 }
 
-void tile_table_set(int level, int64_t problems, int rows) {
+void tile_table_set(int level, int64_t problems, int rows, int bt) {
     TileTable& t = tile_table();
     std::lock_guard<std::mutex> g(t.mu);
-    t.rows[{level, log2_floor(problems)}] = rows;
+    t.rows[{level, log2_floor(problems)}] = {rows, bt};
 }
 
 void tile_table_clear() {
@@ -724,23 +724,31 @@ void BatchEngine::build_lists() {
     auto fused_here = [](const BProb& P, int l) {
         return P.L >= l && (l > dev::TAIL_MAX || l == P.L);
     };
-    // chunk heights of the fused passes for this composition: every problem
-    // at a level shares one (the solves do not depend on it): a height under
-    // trial by the autotuner, else the tuned one, else the wavefront rule
+    // tiles of the fused passes for this composition: every problem at a
+    // level shares one chunk height and one workgroup width (no result bit
+    // depends on either): a choice under trial by the autotuner, else the
+    // tuned one, else the rules (fewest threads per row; ~3500 wavefronts)
     for (int l = Lc_ + 1; l <= Lmax_; ++l) {
         int64_t count = 0;
         for (int s = 0; s < cap_; ++s)
             if (hp_[s].L > 0 && fused_here(hp_[s], l)) ++count;
         if (count == 0) continue;
-        const int N = (1 << l) + 1, bt = fused_bt(N);
-        int rh = rh_override_[l];
-        if (!rh) rh = tile_table_get(l, count);
+        const int N = (1 << l) + 1;
+        const TileEntry te = tile_table_get(l, count);
+        int bt = bt_override_[l] ? bt_override_[l] : (tuned_widths_ ? te.bt : 0);
+        if (!bt) bt = fused_bt(N);
+        int rh = rh_override_[l] ? rh_override_[l] : te.rows;
         if (!rh) rh = fused_rh(N, bt, count);
         const dev::FusedGeom g = dev::fused_geom(N, bt, rh);
+        bt_[l] = bt;
         for (int s = 0; s < cap_; ++s) {
             if (hp_[s].L == 0 || !fused_here(hp_[s], l)) continue;
-            hp_[s].lv[l].rh = g.rh;
-            hp_[s].lv[l].nchunks = g.nchunks;
+            BLevel& v = hp_[s].lv[l];
+            v.rh = g.rh;
+            v.nchunks = g.nchunks;
+            v.bt = g.bt;
+            v.cw = g.cw;
+            v.nstrips = g.nstrips;
         }
     }
     for (int l = Lc_ + 1; l <= Lmax_; ++l) {
@@ -763,7 +771,10 @@ void BatchEngine::build_lists() {
     for (int l = Lc_ + 1; l <= Lmax_; ++l)
         if (h_wl_[(size_t)wl_fused(l) * stride] > 0) need |= 1u << l;
     if (h_wl_[(size_t)WL_FINEST_COARSE * stride] > 0) need |= 1u;
-    if (need & ~launch_mask_) {
+    bool widths_changed = false;
+    for (int l = Lc_ + 1; l <= Lmax_; ++l)
+        if (bt_[l] != graph_bt_[l]) widths_changed = true;
+    if ((need & ~launch_mask_) || widths_changed) {
         launch_mask_ |= need;
         if (graph_) (void)hipGraphExecDestroy(graph_);
         graph_ = nullptr;
@@ -850,7 +861,7 @@ mg_status BatchEngine::fetch_state(int s, BState* out) {
 hipError_t BatchEngine::launch_fused(int l, bool pre, int mask) {
     const int stride = 3 + 2 * cap_;
     const int* wl = d_wl_ + (size_t)wl_fused(l) * stride;
-    const int bt = fused_bt((1 << l) + 1);
+    const int bt = bt_[l];
     const dim3 GF(STAGE_GRID * (dev::F_MAX_THREADS / bt)), BF(bt);
 #define ONE(BT)                                                                              \
     if (pre)                                                                                 \
@@ -869,6 +880,7 @@ hipError_t BatchEngine::launch_fused(int l, bool pre, int mask) {
 
 mg_status BatchEngine::tune(int reps, std::vector<mg_tile_choice>* out) {
     static const int kRows[] = {4, 8, 16, 32, 64};
+    static const int kWidths[] = {64, 128, 192, 256};
     MG_HIP(hipSetDevice(device_));
     if (mg_status s = upload()) return s;
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -885,36 +897,40 @@ mg_status BatchEngine::tune(int reps, std::vector<mg_tile_choice>* out) {
     for (int l = Lc_ + 1; l <= Lmax_; ++l) {
         const int count = problems_at(l);
         if (count == 0) continue;
-        int best = 0;
+        int best = 0, best_bt = 0;
         float best_ms = 0.0f;
-        for (int rh : kRows) {
-            rh_override_[l] = rh;
-            probs_dirty_ = true;
-            if (mg_status s = upload()) {
-                rh_override_[l] = 0;
-                return s;
-            }
-            for (int w = 0; w < 2; ++w) {  // warm-up
-                MG_HIP(launch_fused(l, true, BF_INIT));
-                MG_HIP(launch_fused(l, false, BF_INIT));
-            }
-            MG_HIP(hipEventRecord(e0, st_));
-            for (int r = 0; r < reps; ++r) {
-                MG_HIP(launch_fused(l, true, BF_INIT));
-                MG_HIP(launch_fused(l, false, BF_INIT));
-            }
-            MG_HIP(hipEventRecord(e1, st_));
-            MG_HIP(hipEventSynchronize(e1));
-            float ms = 0.0f;
-            MG_HIP(hipEventElapsedTime(&ms, e0, e1));
-            if (!best || ms < best_ms) {
-                best = rh;
-                best_ms = ms;
+        for (int bt : kWidths) {
+            for (int rh : kRows) {
+                rh_override_[l] = rh;
+                bt_override_[l] = bt;
+                probs_dirty_ = true;
+                if (mg_status s = upload()) {
+                    rh_override_[l] = bt_override_[l] = 0;
+                    return s;
+                }
+                for (int w = 0; w < 2; ++w) {  // warm-up
+                    MG_HIP(launch_fused(l, true, BF_INIT));
+                    MG_HIP(launch_fused(l, false, BF_INIT));
+                }
+                MG_HIP(hipEventRecord(e0, st_));
+                for (int r = 0; r < reps; ++r) {
+                    MG_HIP(launch_fused(l, true, BF_INIT));
+                    MG_HIP(launch_fused(l, false, BF_INIT));
+                }
+                MG_HIP(hipEventRecord(e1, st_));
+                MG_HIP(hipEventSynchronize(e1));
+                float ms = 0.0f;
+                MG_HIP(hipEventElapsedTime(&ms, e0, e1));
+                if (!best || ms < best_ms) {
+                    best = rh;
+                    best_bt = bt;
+                    best_ms = ms;
+                }
             }
         }
-        rh_override_[l] = 0;
-        tile_table_set(l, count, best);
-        if (out) out->push_back({l, count, best, 1e3 * best_ms / reps});
+        rh_override_[l] = bt_override_[l] = 0;
+        tile_table_set(l, count, best, best_bt);
+        if (out) out->push_back({l, count, best, best_bt / 64, 1e3 * best_ms / reps});
     }
     probs_dirty_ = true;
     return upload();
@@ -955,7 +971,7 @@ hipError_t BatchEngine::enqueue_iteration() {
     if (fused) {
 #define FUSED(KERNEL, l)                                                                  \
     {                                                                                     \
-        const int bt = fused_bt((1 << (l)) + 1);                                          \
+        const int bt = bt_[l];                                                            \
         const dim3 GF(STAGE_GRID * (dev::F_MAX_THREADS / bt)), BF(bt);                    \
         switch (bt) {                                                                     \
             case 64: LAUNCH(KERNEL<64>, GF, BF, 0, st_, P, S, W(wl_fused(l)), l, m); break;   \
@@ -1027,6 +1043,7 @@ mg_status BatchEngine::ensure_graph() {
             graph_ = nullptr;
             return fail(MG_ERR_DEVICE, std::string("batch graph capture: ") + hipGetErrorString(e));
         }
+        for (int l = 0; l <= MG_MAX_LEVEL; ++l) graph_bt_[l] = bt_[l];
     }
     return MG_OK;
 }
@@ -1355,12 +1372,14 @@ extern "C" mg_status mg_batch_autotune(mg_hierarchy* const* hs, int count,
     return MG_OK;
 }
 
-extern "C" mg_status mg_batch_set_tile(int level, int problems, int tile_rows) {
+extern "C" mg_status mg_batch_set_tile(int level, int problems, int tile_rows, int row_waves) {
     if (level < 2 || level > MG_MAX_LEVEL) return fail(MG_ERR_INVALID, "level outside [2, 14]");
     if (problems < 1) return fail(MG_ERR_INVALID, "problems must be >= 1");
     if (tile_rows < 4 || tile_rows > 256 || (tile_rows & (tile_rows - 1)))
         return fail(MG_ERR_INVALID, "tile_rows must be a power of two in [4, 256]");
-    tile_table_set(level, problems, tile_rows);
+    if (row_waves < 0 || row_waves > dev::F_MAX_THREADS / 64)
+        return fail(MG_ERR_INVALID, "row_waves must lie in [0, 4]");
+    tile_table_set(level, problems, tile_rows, 64 * row_waves);
     return MG_OK;
 }
 

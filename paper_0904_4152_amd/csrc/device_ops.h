@@ -378,7 +378,7 @@ __device__ __forceinline__ double sumsq_tile(const T* __restrict__ v, int64_t n,
 }
 
 constexpr int64_t RED_SEG = 8192;  // partials per first-stage segment
-constexpr int RED_MAX_SEGS = 1024;  // so at most 8M partials
+constexpr int RED_MAX_SEGS = 2048;  // so at most 16M partials
 
 // Thread-strided sum of p[lo, hi) then block_sum; valid in thread 0.  Each
 // thread adds its elements in index order; eight loads are in flight at a

@@ -38,23 +38,28 @@ constexpr int F_HALO = 4;           // columns / rows recomputed per side
 constexpr int F_MIN_THREADS = 64;   // workgroup widths: 64, 128, 192 or 256 threads,
 constexpr int F_MAX_THREADS = 256;  // one grid column per thread
 
+// Columns of one segment of the residual-norm partials (see post_tile);
+// strips own whole segments.
+constexpr int F_NORM_COLS = 8;
+
 struct FusedGeom {
     int bt;       // threads per workgroup
-    int cw;       // owned columns per strip (even, at most bt - 2 F_HALO)
+    int cw;       // owned columns per strip (a multiple of F_NORM_COLS, at most bt - 2 F_HALO)
     int nstrips;  // strips of cw columns (the last one may be narrower)
     int nchunks;  // chunks of rh rows
     int rh;       // owned rows per chunk (even)
 };
 
-// Strips of equal width (rounded up to even) as few as bt threads allow.
+// Strips of equal width (rounded up to a multiple of F_NORM_COLS) as few as
+// bt threads allow.
 __host__ __device__ inline FusedGeom fused_geom(int N, int bt, int rh) {
     FusedGeom g;
     g.bt = bt;
     g.rh = rh;
-    const int cmax = bt - 2 * F_HALO;
+    const int cmax = bt - 2 * F_HALO;  // a multiple of F_NORM_COLS
     g.nstrips = (N + cmax - 1) / cmax;
     g.cw = (N + g.nstrips - 1) / g.nstrips;
-    g.cw += g.cw & 1;
+    g.cw = (g.cw + F_NORM_COLS - 1) / F_NORM_COLS * F_NORM_COLS;
     g.nchunks = (N + rh - 1) / rh;
     return g;
 }
@@ -337,27 +342,22 @@ __device__ void pre_tile(const T* __restrict__ bands, int64_t bs, int N, const T
 // multiples of it, so no group of rows straddles two tiles.
 constexpr int F_NORM_ROWS = 4;
 
-// Partial sums of squares a fused post pass with NORM writes: one per
-// (strip, wavefront, group of F_NORM_ROWS grid rows).
-__host__ __device__ inline int64_t fused_norm_parts(const FusedGeom& g, int N) {
-    return (int64_t)g.nstrips * (g.bt / 64) * ((N + F_NORM_ROWS - 1) / F_NORM_ROWS);
-}
-
-// Sum over the 64 lanes of a wavefront (butterfly, fixed order).
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+// Partial sums of squares a fused post pass with NORM writes on a level of
+// N nodes per side: one per (group of F_NORM_ROWS grid rows, segment of
+// F_NORM_COLS grid columns), row groups outer.  The layout depends on N
+// alone, not on the tiling.
+__host__ __device__ inline int64_t fused_norm_parts(int N) {
+    return (int64_t)((N + F_NORM_ROWS - 1) / F_NORM_ROWS) * ((N + F_NORM_COLS - 1) / F_NORM_COLS);
 }
 
 // Post-smoothing tile: x_out = J(J(x + P x_c)) on owned nodes.  With NORM
-// also rowpart[(strip * (BT / 64) + w) * NG + G] = sum of (b - A x_out)^2
-// over the owned columns that wavefront w holds in the rows of group G (rows
-// 4G .. 4G+3; NG groups), each lane adding its rows in order before the
-// wavefront sum: the partial sums do not depend on how rows are split into
-// chunks, and need no workgroup barrier.  Same register ring as pre_tile;
-// a barrier before each of the first sweep (row jx-1), the second (row
-// jx-2) and the norm (row jx-3).
+// also rowpart[G * NSEG + m] = the sum of (b - A x_out)^2 over rows 4G ..
+// 4G+3 and columns 8m .. 8m+7 (NSEG segments per row), in one fixed order:
+// each column's rows in increasing order, then the eight column sums as
+// ((c0 + c1) + (c2 + c3)) + ((c4 + c5) + (c6 + c7)).  Neither the chunk
+// heights nor the strip widths change a bit of it.  Same register ring as
+// pre_tile; a barrier before each of the first sweep (row jx-1), the second
+// (row jx-2) and the norm (row jx-3).
 template <typename T, bool NORM, int BT>
 __device__ void post_tile(const T* __restrict__ bands, int64_t bs, int N, const T* __restrict__ x,
                           const T* __restrict__ xc, const T* __restrict__ b, T omega,
@@ -390,8 +390,21 @@ __device__ void post_tile(const T* __restrict__ bands, int64_t bs, int N, const 
     T bk[6][9], bb[6];
     // x and the four coarse values around each x row in flight (slot r mod 3)
     T pfx[3], pc0[3], pc1[3], pc2[3], pc3[3];
-    double nacc = 0.0;  // this lane's part of the current row group
-    const int ng = (N + F_NORM_ROWS - 1) / F_NORM_ROWS;
+    // Norm partials: at the end of a row group every lane leaves its
+    // column's sum in NS; after the next barrier the lane at the first
+    // column of each owned segment adds the segment's eight sums.
+    __shared__ double NS[BT];
+    double nacc = 0.0;  // this lane's column sum over the current row group
+    int pend = -1;      // row group whose sums wait in NS (uniform), or -1
+    const int nseg = (N + F_NORM_COLS - 1) / F_NORM_COLS;
+    const bool lead = c_own && ((col - c0) % F_NORM_COLS) == 0;
+    auto flush = [&]() {
+        if (lead) {
+            const double* v = NS + threadIdx.x;
+            const double s8 = ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
+            rowpart[(int64_t)pend * nseg + col / F_NORM_COLS] = s8;
+        }
+    };
     // first x row needed .. last row of the last step (the norm, or the
     // second sweep)
     const int jstart = r0 - H;
@@ -454,6 +467,10 @@ __device__ void post_tile(const T* __restrict__ bands, int64_t bs, int N, const 
             load_upper(R, node_off(jx + AHEAD - 1, N, col, sizeof(T)), needb(jx + AHEAD - 1),
                        bk[(ph + AHEAD - 1) % 6], bb[(ph + AHEAD - 1) % 6]);
             __syncthreads();
+            if (NORM && pend >= 0) {
+                flush();
+                pend = -1;
+            }
             lower.complete(bk[b1], bk[b2], ph & 1, t);
             // every lane computes each sweep (lanes and rows outside the
             // sweep's window select zero): no divergent branches
@@ -478,14 +495,16 @@ __device__ void post_tile(const T* __restrict__ bands, int64_t bs, int N, const 
                     nacc += c_own ? (double)d * (double)d : 0.0;
                 }
                 if ((j3 % F_NORM_ROWS) == F_NORM_ROWS - 1 || j3 == r1 - 1) {
-                    const double w = wave_sum(nacc);
-                    if ((threadIdx.x & 63) == 0)
-                        rowpart[((int64_t)strip * (BT / 64) + (threadIdx.x >> 6)) * ng +
-                                j3 / F_NORM_ROWS] = w;
+                    NS[threadIdx.x] = nacc;
                     nacc = 0.0;
+                    pend = j3 / F_NORM_ROWS;
                 }
             }
         }
+    }
+    if (NORM && pend >= 0) {
+        __syncthreads();
+        flush();
     }
 }
 
@@ -573,25 +592,79 @@ __device__ __forceinline__ void tail_jacobi(const TailLds<T>& v, const T* x, T* 
 
 // x_top = V(top, 0, b_top) over levels top..Lc (one workgroup of TAIL_THREADS
 // threads).
+// Elements per thread of one level's nine bands, and of the top level's b.
+__host__ __device__ constexpr int tail_band_loads(int l) {
+    return (9 * ((1 << l) + 1) * ((1 << l) + 1) + TAIL_THREADS - 1) / TAIL_THREADS;
+}
+__host__ __device__ constexpr int tail_all_loads() {
+    int c = ((1 << TAIL_MAX) + 1) * ((1 << TAIL_MAX) + 1) / TAIL_THREADS + 1;
+    for (int l = 1; l <= TAIL_MAX; ++l) c += tail_band_loads(l);
+    return c;
+}
+
+// The bands of levels Lc..top and b of level top from global memory into
+// LDS.  Every load is issued, unconditionally, before the first store (the
+// levels and the elements per thread are unrolled to constants; a load that
+// is not needed reads a valid element of the top level and is not stored), so
+// the copy costs about one memory latency instead of one per element a
+// thread moves.
 template <typename T>
-__device__ void tail_cycle(const TailLevels<T>& tl, T omega) {
-    __shared__ T lds[tail_lds_elems()];
-    for (int l = tl.Lc; l <= tl.top; ++l) {
-        const TailLds<T> v(lds, tl.Lc, l);
+__device__ __forceinline__ void tail_load(const TailLevels<T>& tl, T* lds) {
+    T r[tail_all_loads()];
+    const TailLevel<T>& gt = tl.lv[tl.top];
+    int o = 0;
+#pragma unroll
+    for (int l = 1; l <= TAIL_MAX; ++l) {
+        const int n = ((1 << l) + 1) * ((1 << l) + 1);
+        const bool on = l >= tl.Lc && l <= tl.top;
         const TailLevel<T>& g = tl.lv[l];
-        for (int e = threadIdx.x; e < 9 * v.n; e += TAIL_THREADS) {
-            const int k = e / v.n, p = e - k * v.n;
-            v.bands[e] = g.bands[k * g.bs + p];
+#pragma unroll
+        for (int u = 0; u < tail_band_loads(l); ++u) {
+            const int e = (int)threadIdx.x + u * TAIL_THREADS;
+            const int ec = min(e, 9 * n - 1);
+            const int k = ec / n, p = ec - k * n;
+            r[o + u] = *(on ? g.bands + (int64_t)k * g.bs + p : gt.bands);
         }
-        for (int e = threadIdx.x; e < v.N + 1; e += TAIL_THREADS) {
-            v.x[-v.N - 1 + e] = v.x[v.n + e] = T(0);
-            v.t[-v.N - 1 + e] = v.t[v.n + e] = T(0);
+        o += tail_band_loads(l);
+    }
+    constexpr int BL = ((1 << TAIL_MAX) + 1) * ((1 << TAIL_MAX) + 1) / TAIL_THREADS + 1;
+#pragma unroll
+    for (int u = 0; u < BL; ++u) {
+        const int p = (int)threadIdx.x + u * TAIL_THREADS;
+        r[o + u] = gt.b[min(p, (int)gt.n - 1)];
+    }
+    o = 0;
+#pragma unroll
+    for (int l = 1; l <= TAIL_MAX; ++l) {
+        const int n = ((1 << l) + 1) * ((1 << l) + 1);
+        if (l >= tl.Lc && l <= tl.top) {
+            const TailLds<T> v(lds, tl.Lc, l);
+#pragma unroll
+            for (int u = 0; u < tail_band_loads(l); ++u) {
+                const int e = (int)threadIdx.x + u * TAIL_THREADS;
+                if (e < 9 * n) v.bands[e] = r[o + u];
+            }
+            for (int e = threadIdx.x; e < v.N + 1; e += TAIL_THREADS) {
+                v.x[-v.N - 1 + e] = v.x[v.n + e] = T(0);
+                v.t[-v.N - 1 + e] = v.t[v.n + e] = T(0);
+            }
         }
+        o += tail_band_loads(l);
     }
     {
         const TailLds<T> v(lds, tl.Lc, tl.top);
-        for (int p = threadIdx.x; p < v.n; p += TAIL_THREADS) v.b[p] = tl.lv[tl.top].b[p];
+#pragma unroll
+        for (int u = 0; u < BL; ++u) {
+            const int p = (int)threadIdx.x + u * TAIL_THREADS;
+            if (p < v.n) v.b[p] = r[o + u];
+        }
     }
+}
+
+template <typename T>
+__device__ void tail_cycle(const TailLevels<T>& tl, T omega) {
+    __shared__ T lds[tail_lds_elems()];
+    tail_load(tl, lds);
     __syncthreads();
     for (int l = tl.top; l > tl.Lc; --l) {
         const TailLds<T> v(lds, tl.Lc, l);

@@ -143,9 +143,6 @@ __global__ __launch_bounds__(dev::TAIL_THREADS) void k_tail(dev::TailLevels<T> t
     dev::tail_cycle<T>(tl, omega);
 }
 
-// Dense block of the coarsest operator over its unknowns (the nodes off the
-// Dirichlet sides, in index order) and its Cholesky factor (one thread; at
-// most 72 unknowns).  flag = 1 if a pivot is not positive.
 // Dense Cholesky factor (lower triangle, row-major m x m) of the coarsest
 // level's operator restricted to its unknowns, by one wavefront.  Unknowns
 // are numbered in node order, so the matrix, and with it the factor, is
@@ -153,6 +150,7 @@ __global__ __launch_bounds__(dev::TAIL_THREADS) void k_tail(dev::TailLevels<T> t
 // stay zero.  Column by column: lane 0 forms the pivot, then the lanes form
 // the band's rows below it, each row's sum in increasing k as a plain dense
 // factorisation would (the terms skipped below the band are exact zeros).
+// At most 289 unknowns (level 4); flag = 1 if a pivot is not positive.
 __global__ __launch_bounds__(64) void k_chol_factor(const double* __restrict__ bands, int64_t bs,
                                                     int Nc, int dmask, double* __restrict__ A,
                                                     int* __restrict__ flag) {
@@ -852,12 +850,7 @@ int fused_bt(int N) {
     return best;
 }
 
-int64_t fused_max_norm_parts(int N) {
-    int64_t m = 0;
-    for (int bt = dev::F_MIN_THREADS; bt <= dev::F_MAX_THREADS; bt += 64)
-        m = std::max(m, dev::fused_norm_parts(dev::fused_geom(N, bt, 2), N));
-    return m;
-}
+int64_t fused_max_norm_parts(int N) { return dev::fused_norm_parts(N); }
 
 // Owned rows per chunk of a fused pass over `count` problems on a level with
 // N nodes per side: the longest chunk (a power of two from 64 down to 4)
@@ -926,7 +919,7 @@ hipError_t launch_post(const Level& lv, const T* bands, const T* x, const T* xc,
 #undef POST
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !partials) return e;
-    return launch_reduce(partials, dev::fused_norm_parts(g, lv.N), scal, slot, host, st);
+    return launch_reduce(partials, dev::fused_norm_parts(lv.N), scal, slot, host, st);
 }
 
 template <typename T>

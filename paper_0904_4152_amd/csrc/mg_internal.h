@@ -30,9 +30,9 @@ mg_status fail(mg_status s, const std::string& msg);
 
 // ---------------------------------------------------------------- layout
 // Band arrays of one level live in one allocation: band k starts at
-// k * band_stride elements.  The stride is n rounded up to 64 elements plus a
-// per-level skew of 64 elements times an odd factor, so that the nine
-// streams of a band product do not start on the same HBM channel.
+// k * band_stride elements.  The stride is n rounded up to 1024 elements plus
+// 64, so that the nine streams of a band product do not start on the same
+// HBM channel.
 int64_t band_stride(int64_t n);
 // Vectors are padded to a multiple of 64 elements (the tail stays zero).
 int64_t vec_len(int64_t n);
@@ -227,8 +227,8 @@ hipError_t launch_tail(const Level* lv, int top, int Lc, const dev::CoarseSolver
 int tail_max_level();
 // Tiling of the fused passes on a level of N nodes per side: workgroup
 // width, chunk height for a pass over `count` problems, geometry of a
-// single-problem pass, tiles per single-problem pass, and the most residual
-// partials any width gives.
+// single-problem pass, tiles per single-problem pass, and the residual
+// partials of a fused post pass (one layout for every width).
 namespace dev {
 struct FusedGeom;
 }  // namespace dev

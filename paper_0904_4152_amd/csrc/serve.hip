@@ -35,6 +35,7 @@ public:
         Lc_ = Lc;
         opts_ = o;
         done_.assign(slots, 0);
+        eng_.use_tuned_widths(false);  // the live mix changes every iteration
         return eng_.init(ctx->device, slots, Lmax, Lc, o.nu_pre, o.nu_post);
     }
     double now() override {

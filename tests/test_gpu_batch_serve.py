@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 import synth
+from gpu_common import U64, abs_band_product
 
 pytestmark = pytest.mark.gpu
 
@@ -134,6 +135,56 @@ def test_batch_of_config_shape(mg, ctx):
         assert 3 <= s.outer_steps <= 6
 
 
+def test_batch_of_config_shape_256_checked_by_oracle(mg, ctx, orc):
+    """The benchmark's batch at full shape: 256 problems, levels from {5..9}
+    (seed 4004), jitter U[0, 0.25) h (seed 4005), geometry seeds 4100 + p,
+    uniform right-hand sides 4200 + p.  Every problem's right-hand side equals
+    the host generator's and its final residual, recomputed with the oracle's
+    operator on the host coordinates, is within 1e-8 of ||b||; for 32 problems
+    (every level) the solution is compared with the oracle's FP64 solution."""
+    count = 256
+    levels = synth.batch_levels(count, 5, 9, 4004)
+    probs = make_problems(mg, ctx, levels)
+    opts = mg.default_opts(precision=mg.MG_PREC_MIXED, rel_tol=1e-8)
+    xs = [torch.zeros_like(b) for _, b, _, _ in probs]
+    print("batch of 256: levels %s" % np.bincount(levels, minlength=10)[5:].tolist(), flush=True)
+    stats = mg.solve_batch([p[0] for p in probs], [p[1] for p in probs], xs, opts)
+    sample = set()
+    for L in range(5, 10):
+        sample.update(np.nonzero(levels == L)[0][:7 if L < 9 else 4].tolist())
+    worst_res, worst_err = 0.0, 0.0
+    for k, (h, b, a, gs) in enumerate(probs):
+        L = int(levels[k])
+        N = (1 << L) + 1
+        xy = synth.coords(L, a, gs)
+        bh = host(b)
+        np.testing.assert_array_equal(bh, synth.rhs_uniform(L, 4200 + k))
+        xk = host(xs[k])
+        bands = orc.assemble(N, xy)
+        bn = orc.norm2(bh)
+        r = orc.norm2(orc.defect(N, bands, bh, xk)) / bn
+        assert stats[k].status == 0 and stats[k].rel_res <= 1e-8, k
+        assert r <= 1.05e-8, (k, L, r)
+        # the device's residual norm against the oracle's: the defect's
+        # forward error (9-term products, bands within 64 ulp of the
+        # oracle's) bounds the difference, whatever the residual's size
+        scale = np.linalg.norm(abs_band_product(N, bands, xk) + np.abs(bh))
+        assert abs(r - stats[k].rel_res) * bn <= 80 * U64 * scale, (k, r, stats[k].rel_res)
+        worst_res = max(worst_res, r)
+        if k in sample:
+            oh = orc.Hierarchy(L, xy)
+            xo, so = oh.solve_fp64(bh, o=orc.opts(rel_tol=1e-12))
+            oh.close()
+            err = float(np.linalg.norm(xk - xo) / np.linalg.norm(xo))
+            assert err <= 1e-6, (k, L, err)
+            worst_err = max(worst_err, err)
+    assert len(sample) == 32
+    print("batch of 256: worst oracle residual %.3e, worst solution error %.3e (32 problems)"
+          % (worst_res, worst_err))
+    for h, _, _, _ in probs:
+        h.close()
+
+
 def test_batch_errors(mg, ctx):
     probs = make_problems(mg, ctx, [4, 5])
     xs = [torch.zeros_like(b) for _, b, _, _ in probs]
@@ -147,7 +198,7 @@ def test_batch_errors(mg, ctx):
     assert e.value.status == mg.MG_ERR_INVALID
 
 
-def test_server_result_same_alone_and_in_the_mix(mg, ctx):
+def test_server_result_same_alone_and_in_the_mix(mg, ctx, orc):
     """Requests that overlap on the device (more requests than slots, so they
     are admitted as slots free up) give bit-identical results to the same
     problem solved alone."""
@@ -176,6 +227,12 @@ def test_server_result_same_alone_and_in_the_mix(mg, ctx):
         rc, st, x = results[t]
         assert rc == 0 and st.rel_res <= tol
         assert st.seconds >= st.queue_seconds >= 0.0
+        # the served solution against the oracle's operator on the host
+        # coordinates and right-hand side of the request
+        N = (1 << L) + 1
+        bh = synth.rhs_uniform(L, rs)
+        r = orc.norm2(orc.defect(N, orc.assemble(N, synth.coords(L, a, gs)), bh, x))
+        assert r <= 1.05 * tol * orc.norm2(bh), (t, L, tol, r)
         h = mg.Hierarchy(ctx, L, jitter=a, seed=gs)
         b = torch.empty(h.n, dtype=torch.float64, device="cuda")
         h.rhs_uniform(rs, b)
@@ -206,10 +263,10 @@ def test_server_budget_admission(mg, ctx):
 
 
 def test_autotuned_tiles_change_no_bit(mg, ctx, tmp_path):
-    """The autotuner picks a tile height per level of this composition; the
-    batch solved with the tuned table, with a forced odd choice and with the
-    rule's choice gives the same bits, and the table round-trips through a
-    file."""
+    """The autotuner picks a tile height and a workgroup width per level of
+    this composition; the batch solved with the tuned table, with forced odd
+    choices (rows and widths no rule picks) and with the rules' choices gives
+    the same bits, and the table round-trips through a file."""
     probs = make_problems(mg, ctx, [9, 8, 7, 6, 5, 9, 8, 7] * 3, seed0=5000)
     opts = mg.default_opts(precision=mg.MG_PREC_MIXED, rel_tol=1e-8)
     hs, bs_ = [p[0] for p in probs], [p[1] for p in probs]
@@ -226,6 +283,7 @@ def test_autotuned_tiles_change_no_bit(mg, ctx, tmp_path):
     assert sorted(r["level"] for r in rows) == [5, 6, 7, 8, 9]
     for r in rows:
         assert r["tile_rows"] in (4, 8, 16, 32, 64) and r["us"] > 0.0
+        assert r["row_waves"] in (1, 2, 3, 4)
     # problems per level: levels above the coarse tail (5) run for every
     # problem that has them, level 5 only as a finest level
     by_level = {r["level"]: r["problems"] for r in rows}
@@ -238,12 +296,20 @@ def test_autotuned_tiles_change_no_bit(mg, ctx, tmp_path):
     x2, s2 = run()
     mg.batch_set_tiles([{"level": 9, "problems": 6, "tile_rows": 128}])  # not a tuner candidate
     x3, s3 = run()
-    for xs, ss in ((x1, s1), (x2, s2), (x3, s3)):
+    # every width at every level of the composition, with odd heights
+    outs = [(x1, s1), (x2, s2), (x3, s3)]
+    for waves, rows_ in ((1, 8), (3, 16), (2, 64), (4, 4)):
+        mg.batch_set_tiles([{"level": l, "problems": p, "tile_rows": rows_, "row_waves": waves}
+                            for l, p in by_level.items()])
+        outs.append(run())
+    for xs, ss in outs:
         assert ss == ref_s
         for a, b in zip(xs, ref_x):
             np.testing.assert_array_equal(a, b)
     with pytest.raises(mg.MgError):
         mg.batch_set_tiles([{"level": 9, "problems": 6, "tile_rows": 12}])
+    with pytest.raises(mg.MgError):
+        mg.batch_set_tiles([{"level": 9, "problems": 6, "tile_rows": 16, "row_waves": 5}])
     mg.batch_clear_tiles()
     for h, _, _, _ in probs:
         h.close()
