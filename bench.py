@@ -380,6 +380,13 @@ def main():
     h = mg.Hierarchy(ctx, L, jitter=jit, seed=gseed)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t
+    # the fused passes' tiles (rows per tile, wavefronts per row) of every
+    # level, picked by the autotuner before anything is timed (no result bit
+    # depends on them)
+    mg.batch_clear_tiles()
+    t = time.perf_counter()
+    tiles = h.autotune(reps=10)
+    t_tune = time.perf_counter() - t
     n = h.n
     b = torch.from_numpy(synth.rhs_gaussian(L, rseed)).to(dev)
     x = torch.zeros_like(b)
@@ -490,6 +497,7 @@ def main():
     x_fp64 = x.cpu().numpy()
     out["L12"] = {
         "n": n, "setup_s": t_setup,
+        "autotune": {"seconds": t_tune, "tiles": tiles},
         "mixed": {"ms": t_mixed * 1e3, "outer_steps": st_m.outer_steps,
                   "inner_cycles": st_m.cycles, "rel_res": st_m.rel_res,
                   "alg_bytes": st_m.alg_bytes, "alg_GB_s": st_m.alg_bytes / t_mixed / 1e9},
@@ -598,10 +606,12 @@ def main():
     bk = out["band_kernels"]
     pre = bk["fused_pre_fp32"]
     traffic = traffic_from_profiles("fused_pre_fp32")
+    top = next(r for r in tiles if r["level"] == L)
     roof = {"bound": "hbm", "achieved": pre["GB_s"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": pre["GB_s"] / PEAK_HBM_GBS, "traffic": traffic,
-            "kernel": "k_pre<float, false, 256> (finest-level fused FP32 pre-smoothing pass: "
-                      "two damped Jacobi sweeps, defect, restriction)",
+            "kernel": "k_pre<float, false, %d> (finest-level fused FP32 pre-smoothing pass: "
+                      "two damped Jacobi sweeps, defect, restriction; tiles of %d rows)"
+                      % (64 * top["row_waves"], top["tile_rows"]),
             "us": pre["us"],
             "alg_bytes": fused_alg,
             "alg_bytes_model": "12 scalars per finest node (9 stored bands, x and b read, "

@@ -262,6 +262,16 @@ mg_status mg_batch_autotune(mg_hierarchy* const* hs, int count, const mg_solve_o
                             int reps, mg_tile_choice* out, int out_cap, int* n_out);
 mg_status mg_batch_set_tile(int level, int problems, int tile_rows, int row_waves);
 mg_status mg_batch_clear_tiles(void);
+/* The same tuning for the single-problem solver (mg_solve, mg_vcycle and
+ * the fused-pass entry points read the table's entries for one problem): for
+ * every level on which h's V(2,2) cycle runs fused passes, times the FP32
+ * pre- and post-smoothing passes as the mixed solve runs them (reps pairs
+ * per candidate, on h's FP32 work vectors) for 4 .. 256 rows per tile and 1
+ * .. 4 wavefronts per row, and stores the fastest under problems = 1.  Tiles
+ * change no result bit; solves captured before are captured again.
+ * Synchronous; not thread safe per hierarchy. */
+mg_status mg_hierarchy_autotune(mg_hierarchy* h, int reps, mg_tile_choice* out, int out_cap,
+                                int* n_out);
 
 /* ---- serving ---------------------------------------------------------------
  * Not a passage of the paper: the library's continuous-batching service

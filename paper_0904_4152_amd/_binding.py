@@ -105,6 +105,7 @@ _SIGS = {
                                ctypes.POINTER(TileChoice), _i, ctypes.POINTER(_i)]),
     "mg_batch_set_tile": (_i, [_i, _i, _i, _i]),
     "mg_batch_clear_tiles": (_i, []),
+    "mg_hierarchy_autotune": (_i, [_vp, _i, ctypes.POINTER(TileChoice), _i, ctypes.POINTER(_i)]),
     "mg_solve_batch": (_i, [ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp), _i,
                             ctypes.POINTER(SolveOpts), _vp, ctypes.POINTER(Stats)]),
 }
@@ -371,6 +372,16 @@ class Hierarchy:
 
     def coarse_solve(self, b, x, stream=None):
         check(lib().mg_coarse_solve(self._h, _dt(x), _ptr(b), _ptr(x), _stream(stream)))
+
+    def autotune(self, reps=10):
+        """Tune the single-problem fused passes' tiles of this hierarchy's
+        levels (mg_hierarchy_autotune); returns the choices as dicts."""
+        out = (TileChoice * 16)()
+        got = _i()
+        check(lib().mg_hierarchy_autotune(self._h, reps, out, 16, ctypes.byref(got)))
+        return [{"level": out[i].level, "problems": out[i].problems,
+                 "tile_rows": out[i].tile_rows, "row_waves": out[i].row_waves, "us": out[i].us}
+                for i in range(min(got.value, 16))]
 
     def vcycle(self, level, b, x, nu_pre=2, nu_post=2, omega=0.7, fused=None, stream=None):
         if fused is None:

@@ -56,7 +56,7 @@ static void hierarchy_arrays(int L, int Lc, std::vector<size_t>& sizes) {
         sizes.push_back(vl * sizeof(float));
     }
     sizes.push_back(vec_len(nL) * sizeof(double));                    // d64
-    sizes.push_back(partials_len(L) * sizeof(double));                  // partials
+    sizes.push_back((PARTIALS_FRONT + partials_len(L)) * sizeof(double));  // ticket + partials
     sizes.push_back(64 * sizeof(double));                             // scal
     const size_t nc = ((size_t(1) << Lc) + 1) * ((size_t(1) << Lc) + 1);
     sizes.push_back(nc * nc * sizeof(double));                         // chol (m <= nc)
@@ -274,7 +274,7 @@ mg_status mg_hierarchy_create_bc(mg_context* ctx, int L, int Lc, double jitter, 
         lv.t32 = (float*)ptrs[a++];
     }
     h->d64 = (double*)ptrs[a++];
-    h->partials = (double*)ptrs[a++];
+    h->partials = (double*)ptrs[a++] + PARTIALS_FRONT;
     h->n_partials = partials_len(L);
     h->scal = (double*)ptrs[a++];
     h->chol = (double*)ptrs[a++];

@@ -169,16 +169,6 @@ private:
     bool tuned_widths_ = true;
 };
 
-// Process-wide table of tuned tiles of the batched fused passes, keyed by
-// level and by the number of problems at that level (rounded down to a power
-// of two): rows per tile and workgroup width in threads; zeros when the level
-// has no entry.
-struct TileEntry {
-    int rows;
-    int bt;
-};
-TileEntry tile_table_get(int level, int64_t problems);
-void tile_table_set(int level, int64_t problems, int rows, int bt);
-void tile_table_clear();
+
 
 }  // namespace mg

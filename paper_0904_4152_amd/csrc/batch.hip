@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -29,10 +30,11 @@ namespace {
 
 using dev::BLOCK;
 
-constexpr int NLISTS = 51;
+constexpr int NLISTS = 52;
 constexpr int WL_FINEST = 32;
 constexpr int WL_ALL = 33;
 constexpr int WL_FINEST_COARSE = 50;  // finest tiles of problems with L = Lc
+constexpr int WL_SEGS32 = 51;         // segments of the fused passes' residual partials
 inline int wl_level(int l) { return l; }
 inline int wl_restrict(int l) { return 16 + l; }
 inline int wl_fused(int l) { return 34 + l; }
@@ -405,7 +407,34 @@ __global__ __launch_bounds__(BLOCK) void kb_io(const BProb* __restrict__ probs,
     }
 }
 
+// Residual partials of problem P's finest level: the fused post pass's
+// above the coarse level, the defect tiles' on it.
+__device__ __forceinline__ int64_t s32_parts(const BProb& P, int fused_above) {
+    const BLevel& F = P.lv[P.L];
+    if (fused_above >= 0 && P.L > fused_above) return dev::fused_norm_parts(F.N);
+    return (F.n + TILE - 1) / TILE;
+}
+
+// First stage of the inner residual's fixed-order sum for problems with more
+// than dev::RED_SEG partials: one work item per segment of RED_SEG partials,
+// its sum right after the partials (padded to 64), as k_reduce_segs does.
+__global__ __launch_bounds__(BLOCK) void kb_segsum(const BProb* __restrict__ probs,
+                                                   const BState* __restrict__ state,
+                                                   const int* __restrict__ wl, int mask,
+                                                   int fused_above) {
+    FOR_ITEMS(wl)
+    if (!(flags & mask)) continue;
+    const int64_t np = s32_parts(P, fused_above);
+    const int64_t lo = (int64_t)tile * dev::RED_SEG;
+    const double v = dev::strided_sum(P.partials, lo, min(np, lo + dev::RED_SEG));
+    if (threadIdx.x == 0) P.partials[(np + 63) / 64 * 64 + tile] = v;
+    END_ITEMS
+}
+
 // Norm of one problem from its partials (fixed order), into a state field.
+// The inner residual (K_S32) of a problem with more than dev::RED_SEG
+// partials adds the segment sums of kb_segsum (the same order as summing the
+// partials here).
 __global__ __launch_bounds__(BLOCK) void kb_finalize(const BProb* __restrict__ probs,
                                                      BState* __restrict__ state,
                                                      const int* __restrict__ wl, int kind,
@@ -416,10 +445,12 @@ __global__ __launch_bounds__(BLOCK) void kb_finalize(const BProb* __restrict__ p
     const int64_t n = F.n;
     int64_t np = kind == K_S64 ? (n + dev::tile_rows<double>() - 1) / dev::tile_rows<double>()
                                : (n + TILE - 1) / TILE;
-    // the inner residual comes from the fused post pass above the coarse level
-    if (kind == K_S32 && fused_above >= 0 && P.L > fused_above)
-        np = dev::fused_norm_parts(F.N);  // fused post pass partials
-    const double s = dev::reduce_partials(P.partials, np);
+    if (kind == K_S32) np = s32_parts(P, fused_above);
+    const double s =
+        (kind == K_S32 && np > dev::RED_SEG)
+            ? dev::strided_sum(P.partials + (np + 63) / 64 * 64, 0,
+                               (np + dev::RED_SEG - 1) / dev::RED_SEG)
+            : dev::reduce_partials(P.partials, np);
     if (threadIdx.x == 0) {
         const double r = sqrt(s);
         BState& S = state[p];
@@ -659,6 +690,7 @@ namespace {
 struct TileTable {
     std::mutex mu;
     std::map<std::pair<int, int>, TileEntry> rows;  // (level, log2 problems) -> tile
+    std::atomic<uint64_t> epoch{1};
 };
 TileTable& tile_table() {
     static TileTable* t = new TileTable();
@@ -685,13 +717,17 @@ void tile_table_set(int level, int64_t problems, int rows, int bt) {
     TileTable& t = tile_table();
     std::lock_guard<std::mutex> g(t.mu);
     t.rows[{level, log2_floor(problems)}] = {rows, bt};
+    ++t.epoch;
 }
 
 void tile_table_clear() {
     TileTable& t = tile_table();
     std::lock_guard<std::mutex> g(t.mu);
     t.rows.clear();
+    ++t.epoch;
 }
+
+uint64_t tile_table_epoch() { return tile_table().epoch.load(); }
 
 int BatchEngine::problems_at(int l) const {
     int count = 0;
@@ -766,11 +802,25 @@ void BatchEngine::build_lists() {
     fill(WL_FINEST_COARSE, [&](const BProb& P) { return P.L == Lc_; },
          [&](const BProb& P) { return ntiles(P.lv[P.L].n); });
     fill(WL_ALL, [](const BProb&) { return true; }, [](const BProb&) { return 1; });
+    {
+        // inner-residual partials per problem (as kb_finalize counts them)
+        const bool fused = nu_pre_ == 2 && nu_post_ == 2;
+        auto parts = [&](const BProb& P) -> int64_t {
+            const BLevel& F = P.lv[P.L];
+            if (fused && P.L > Lc_) return dev::fused_norm_parts(F.N);
+            return (F.n + TILE - 1) / TILE;
+        };
+        fill(WL_SEGS32, [&](const BProb& P) { return parts(P) > dev::RED_SEG; },
+             [&](const BProb& P) {
+                 return (int)((parts(P) + dev::RED_SEG - 1) / dev::RED_SEG);
+             });
+    }
     // optional launches this composition needs; a new one invalidates the graph
     uint32_t need = 0;
     for (int l = Lc_ + 1; l <= Lmax_; ++l)
         if (h_wl_[(size_t)wl_fused(l) * stride] > 0) need |= 1u << l;
     if (h_wl_[(size_t)WL_FINEST_COARSE * stride] > 0) need |= 1u;
+    if (h_wl_[(size_t)WL_SEGS32 * stride] > 0) need |= 1u << 31;
     bool widths_changed = false;
     for (int l = Lc_ + 1; l <= Lmax_; ++l)
         if (bt_[l] != graph_bt_[l]) widths_changed = true;
@@ -990,6 +1040,8 @@ hipError_t BatchEngine::enqueue_iteration() {
         // problems without a level above the coarse one: residual from a defect pass
         if (launch_mask_ & 1u)
             LAUNCH(kb_inner_norm, G, B, 0, st_, P, S, W(WL_FINEST_COARSE), m, Lc_);
+        if (launch_mask_ & (1u << 31))
+            LAUNCH(kb_segsum, G, B, 0, st_, P, S, W(WL_SEGS32), m, Lc_);
         LAUNCH(kb_finalize, GA, B, 0, st_, P, S, W(WL_ALL), (int)K_S32, (int)F_R32, m, Lc_);
         LAUNCH(kb_ctrl, G1, B, 0, st_, P, S, cap_, (int)PH_INNER, d_iter_, h_ring_);
         return hipSuccess;
@@ -1024,6 +1076,8 @@ hipError_t BatchEngine::enqueue_iteration() {
     }
     // inner residual and stop test
     LAUNCH(kb_inner_norm, G, B, 0, st_, P, S, W(WL_FINEST), m, -1);
+    if (launch_mask_ & (1u << 31))
+        LAUNCH(kb_segsum, G, B, 0, st_, P, S, W(WL_SEGS32), m, -1);
     LAUNCH(kb_finalize, GA, B, 0, st_, P, S, W(WL_ALL), (int)K_S32, (int)F_R32, m, -1);
     LAUNCH(kb_ctrl, G1, B, 0, st_, P, S, cap_, (int)PH_INNER, d_iter_, h_ring_);
 #undef LAUNCH

@@ -102,10 +102,12 @@ mg_status check_vectors(const mg_context* ctx, mg_dtype dtype, int64_t n, const 
     return MG_OK;
 }
 
-// The context's reduction scratch: partials of n elements (one per tile),
-// room for the segment sums, two result doubles, and a pinned mirror.
+// The context's reduction scratch: the reduction ticket, partials of n
+// elements (one per tile), room for the segment sums, two result doubles, and
+// a pinned mirror.  Zeroed when allocated (the ticket starts at zero).
 mg_status blas_scratch(mg_context* ctx, int64_t tiles) {
-    const size_t need = (size_t)((tiles + 63) / 64 * 64 + dev::RED_MAX_SEGS + 64) * sizeof(double);
+    const size_t need =
+        (size_t)(PARTIALS_FRONT + (tiles + 63) / 64 * 64 + dev::RED_MAX_SEGS + 64) * sizeof(double);
     if (ctx->blas_bytes >= need && ctx->blas_host) return MG_OK;
     if (!ctx->blas_host) {
         if (hipHostMalloc((void**)&ctx->blas_host, 64 * sizeof(double), hipHostMallocDefault) !=
@@ -122,6 +124,11 @@ mg_status blas_scratch(mg_context* ctx, int64_t tiles) {
         ctx->release(need);
         return fail(MG_ERR_NOMEM, "hipMalloc failed for the reduction scratch");
     }
+    if (hipMemset(p, 0, need) != hipSuccess) {
+        (void)hipFree(p);
+        ctx->release(need);
+        return fail(MG_ERR_DEVICE, "hipMemset failed for the reduction scratch");
+    }
     if (ctx->blas_scratch) {
         (void)hipDeviceSynchronize();
         (void)hipFree(ctx->blas_scratch);
@@ -137,7 +144,7 @@ mg_status blas_reduce(mg_context* ctx, int64_t n, const T* x, const T* y, double
                       hipStream_t st, bool root) {
     const int64_t tiles = std::max<int64_t>(1, (n + blas_tile<T>() - 1) / blas_tile<T>());
     if (mg_status s = blas_scratch(ctx, tiles)) return s;
-    double* partials = ctx->blas_scratch;
+    double* partials = ctx->blas_scratch + PARTIALS_FRONT;
     // two result slots after the partials and the segment sums
     double* scal = partials + (tiles + 63) / 64 * 64 + dev::RED_MAX_SEGS;
     if (n == 0) {

@@ -94,13 +94,40 @@ __global__ __launch_bounds__(BLOCK) void k_prolong(int Nf, const T* __restrict__
     if (i < Nf) dev::prolong_elem(Nf, xc, xf, i, (int)blockIdx.y);
 }
 
-// First stage of a segmented reduction: one block per RED_SEG partials.
+// Segmented reduction in one launch: one block per RED_SEG partials writes
+// its segment's sum; the block that finishes last (an integer ticket counts
+// the finished blocks) sums the segment sums as k_reduce_final would, and
+// resets the ticket for the next reduction.  The fences order each block's
+// segment sum before its ticket and the last block's reads after it, across
+// the XCDs' caches.
 __global__ __launch_bounds__(BLOCK) void k_reduce_segs(const double* __restrict__ partials,
-                                                       int64_t np, double* __restrict__ segs) {
+                                                       int64_t np, double* __restrict__ segs,
+                                                       unsigned* __restrict__ ticket,
+                                                       double* __restrict__ scal, int slot,
+                                                       double* __restrict__ host) {
     const int64_t sg = blockIdx.x;
     const double v = dev::strided_sum(partials, sg * dev::RED_SEG,
                                       std::min<int64_t>(np, (sg + 1) * dev::RED_SEG));
-    if (threadIdx.x == 0) segs[sg] = v;
+    __shared__ unsigned last;
+    if (threadIdx.x == 0) {
+        segs[sg] = v;
+        __threadfence();
+        last = atomicAdd(ticket, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    const double s = dev::strided_sum(segs, 0, gridDim.x);
+    if (threadIdx.x == 0) {
+        scal[slot] = s;
+        scal[slot + 1] = sqrt(s);
+        *ticket = 0u;
+        if (host) {
+            host[slot] = s;
+            host[slot + 1] = sqrt(s);
+            __threadfence_system();
+        }
+    }
 }
 
 
@@ -696,8 +723,9 @@ inline unsigned blocks1d(int64_t n) { return (unsigned)((n + BLOCK - 1) / BLOCK)
 }  // namespace
 
 // scal[slot] = sum of the np partials (the order of dev::reduce_partials),
-// scal[slot + 1] = its square root; the same into host[slot..] if not null.  Segment sums go right after the
-// partials, which the partials buffer leaves room for.
+// scal[slot + 1] = its square root; the same into host[slot..] if not null.
+// Segment sums go right after the partials, which the partials buffer leaves
+// room for; the word before the buffer is the ticket of k_reduce_segs.
 hipError_t launch_reduce(double* partials, int64_t np, double* scal, int slot, double* host,
                          hipStream_t st) {
     if (np <= dev::RED_SEG) {
@@ -708,10 +736,9 @@ hipError_t launch_reduce(double* partials, int64_t np, double* scal, int slot, d
     const int64_t ns = (np + dev::RED_SEG - 1) / dev::RED_SEG;
     if (ns > dev::RED_MAX_SEGS) return hipErrorInvalidValue;
     double* segs = partials + (np + 63) / 64 * 64;
-    hipLaunchKernelGGL(k_reduce_segs, dim3(ns), dim3(BLOCK), 0, st, partials, np, segs);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(BLOCK), 0, st, segs, ns, scal, slot, host);
+    unsigned* ticket = reinterpret_cast<unsigned*>(partials - 1);
+    hipLaunchKernelGGL(k_reduce_segs, dim3(ns), dim3(BLOCK), 0, st, partials, np, segs, ticket,
+                       scal, slot, host);
     return hipGetLastError();
 }
 
@@ -867,9 +894,35 @@ int fused_rh(int N, int bt, int64_t count) {
     return rh;
 }
 
+// The autotuner's trial of one level (per thread: the tuner launches from
+// the calling thread only).
+static thread_local int t_trial_N = 0, t_trial_rows = 0, t_trial_bt = 0;
+
+void set_single_trial(int N, int rows, int bt) {
+    t_trial_N = rows && bt ? N : 0;
+    t_trial_rows = rows;
+    t_trial_bt = bt;
+}
+
+static int level_of(int N) {
+    int l = 0;
+    while ((1 << l) + 1 < N) ++l;
+    return l;
+}
+
 dev::FusedGeom single_geom(int N) {
-    const int bt = fused_bt(N);
-    return dev::fused_geom(N, bt, fused_rh(N, bt, 1));
+    int bt = 0, rh = 0;
+    if (N == t_trial_N) {
+        bt = t_trial_bt;
+        rh = t_trial_rows;
+    } else {
+        const TileEntry te = tile_table_get(level_of(N), 1);
+        bt = te.bt;
+        rh = te.rows;
+    }
+    if (!bt) bt = fused_bt(N);
+    if (!rh) rh = fused_rh(N, bt, 1);
+    return dev::fused_geom(N, bt, rh);
 }
 
 int64_t fused_tiles(int N) {

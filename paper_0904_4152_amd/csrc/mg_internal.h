@@ -186,9 +186,13 @@ hipError_t launch_update(double* x, const float* c32, int64_t n, const double* s
                          hipStream_t st);
 
 // Deterministic sum of np partials (dev::reduce_partials' order; one
-// block, or segment blocks and a final block beyond dev::RED_SEG partials,
-// whose sums go right after the partials, padded to 64): scal[slot] = sum,
-// scal[slot + 1] = sqrt(sum), mirrored into host[slot..] when not null.
+// block, or beyond dev::RED_SEG partials one block per segment whose sums go
+// right after the partials, padded to 64, and are summed by the last of
+// them): scal[slot] = sum, scal[slot + 1] = sqrt(sum), mirrored into
+// host[slot..] when not null.  Every partials buffer is preceded by one
+// reserved 8-byte word, zero when allocated: the ticket of the segmented
+// form (back to zero after each reduction).
+constexpr int64_t PARTIALS_FRONT = 64;  // doubles reserved before a partials buffer
 hipError_t launch_reduce(double* partials, int64_t np, double* scal, int slot, double* host,
                          hipStream_t st);
 
@@ -234,7 +238,25 @@ struct FusedGeom;
 }  // namespace dev
 int fused_bt(int N);
 int fused_rh(int N, int bt, int64_t count);
+// Tiling of a single-problem fused pass: a choice under trial by the
+// autotuner (set_single_trial; 0, 0 ends it), else the tile table's entry
+// for one problem at the level, else the rules.
 dev::FusedGeom single_geom(int N);
+void set_single_trial(int N, int rows, int bt);
+
+// Process-wide table of tuned tiles of the fused passes, keyed by level and
+// by the number of problems at that level (rounded down to a power of two;
+// a single-problem solve counts as one): rows per tile and workgroup width
+// in threads; zeros when the level has no entry.  Every change advances the
+// table's epoch (captured cycles of an older epoch are captured again).
+struct TileEntry {
+    int rows;
+    int bt;
+};
+TileEntry tile_table_get(int level, int64_t problems);
+void tile_table_set(int level, int64_t problems, int rows, int bt);
+void tile_table_clear();
+uint64_t tile_table_epoch();
 int64_t fused_tiles(int N);
 int64_t fused_max_norm_parts(int N);
 

@@ -5,6 +5,7 @@
 // of the coarse levels (tens of tiny kernels per cycle).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <string>
@@ -20,6 +21,7 @@ struct GraphEntry {
     bool x_zero;
     hipGraphExec_t exec;
     double bytes;
+    uint64_t epoch;  // tile table epoch the fused passes were captured with
 };
 
 struct GraphCache {
@@ -258,11 +260,21 @@ static hipError_t run_unit(mg_hierarchy* h, int kind, const mg_solve_opts& o, bo
                            bool use_graph, Enq& q) {
     GraphCache* gc = cache(h);
     if (use_graph && gc->capture_ok) {
-        for (auto& e : gc->entries) {
+        const uint64_t epoch = tile_table_epoch();
+        for (size_t i = 0; i < gc->entries.size(); ++i) {
+            GraphEntry& e = gc->entries[i];
             if (e.kind == kind && e.nu_pre == o.nu_pre && e.nu_post == o.nu_post &&
                 e.omega == o.omega && e.x_zero == x_zero) {
-                q.bytes += e.bytes;
-                return hipGraphLaunch(e.exec, q.st);
+                if (e.epoch == epoch) {
+                    q.bytes += e.bytes;
+                    return hipGraphLaunch(e.exec, q.st);
+                }
+                // tiles changed since the capture: wait for earlier replays,
+                // then capture again below
+                MG_TRY(hipStreamSynchronize(q.st));
+                (void)hipGraphExecDestroy(e.exec);
+                gc->entries.erase(gc->entries.begin() + i);
+                break;
             }
         }
         Enq cq{q.st, 0.0};
@@ -276,7 +288,8 @@ static hipError_t run_unit(mg_hierarchy* h, int kind, const mg_solve_opts& o, bo
             if (e == hipSuccess) e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
             if (g) (void)hipGraphDestroy(g);
             if (e == hipSuccess) {
-                gc->entries.push_back({kind, o.nu_pre, o.nu_post, o.omega, x_zero, ex, cq.bytes});
+                gc->entries.push_back(
+                    {kind, o.nu_pre, o.nu_post, o.omega, x_zero, ex, cq.bytes, epoch});
                 q.bytes += cq.bytes;
                 return hipGraphLaunch(ex, q.st);
             }
@@ -574,4 +587,78 @@ extern "C" mg_status mg_solve(mg_hierarchy* h, const double* dev_b, double* dev_
     st.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (stats) *stats = st;
     return result;
+}
+
+// ---------------------------------------------------------------- tiles
+// Sec. 3: the thread-block partition of the GPU kernels is a runtime
+// parameter.  For every level on which the hierarchy's V(2,2) cycle runs
+// fused passes, time the FP32 pre- and post-smoothing passes (as the mixed
+// solve runs them: the finest level's pre pass from a given iterate and its
+// post pass with the residual norm, the others from zero and without) for
+// each candidate tile and keep the fastest in the tile table under one
+// problem.
+extern "C" mg_status mg_hierarchy_autotune(mg_hierarchy* h, int reps, mg_tile_choice* out,
+                                           int out_cap, int* n_out) {
+    if (n_out) *n_out = 0;
+    if (!h) return fail(MG_ERR_INVALID, "null hierarchy");
+    if (!h->assembled) return fail(MG_ERR_INVALID, "hierarchy not assembled");
+    if (reps < 1 || reps > 1000) return fail(MG_ERR_INVALID, "reps must lie in [1, 1000]");
+    if (out_cap < 0 || (out_cap > 0 && !out)) return fail(MG_ERR_INVALID, "bad output array");
+    static const int kRows[] = {4, 8, 16, 32, 64, 128, 256};
+    static const int kWidths[] = {64, 128, 192, 256};
+    MG_HIP(hipSetDevice(h->ctx->device));
+    GraphCache* gc = cache(h);
+    if (!gc->st) MG_HIP(hipStreamCreateWithFlags(&gc->st, hipStreamNonBlocking));
+    hipStream_t st = gc->st;
+    struct Guard {
+        hipEvent_t a = nullptr, b = nullptr;
+        ~Guard() {
+            set_single_trial(0, 0, 0);
+            if (a) (void)hipEventDestroy(a);
+            if (b) (void)hipEventDestroy(b);
+        }
+    } g;
+    MG_HIP(hipEventCreate(&g.a));
+    MG_HIP(hipEventCreate(&g.b));
+    const float om = 0.7f;
+    std::vector<mg_tile_choice> rows;
+    for (int l = h->L; l > h->Lc; --l) {
+        if (!(l > tail_max_level() || l == h->L)) continue;
+        Level& v = h->lv[l];
+        Level& c = h->lv[l - 1];
+        const bool finest = l == h->L;
+        auto pair = [&]() -> hipError_t {
+            MG_TRY(launch_pre<float>(v, v.bands32, v.x32, !finest, v.b32, om, v.t32, c.b32,
+                                     h->dmask, st));
+            return launch_post<float>(v, v.bands32, v.t32, c.x32, v.b32, om, v.x32,
+                                      finest ? h->partials : nullptr, h->scal, SC_USER, nullptr,
+                                      st);
+        };
+        int best_rows = 0, best_bt = 0;
+        float best_ms = 0.0f;
+        for (int bt : kWidths) {
+            for (int rh : kRows) {
+                set_single_trial(v.N, rh, bt);
+                for (int w = 0; w < 2; ++w) MG_HIP(pair());
+                MG_HIP(hipEventRecord(g.a, st));
+                for (int r = 0; r < reps; ++r) MG_HIP(pair());
+                MG_HIP(hipEventRecord(g.b, st));
+                MG_HIP(hipEventSynchronize(g.b));
+                float ms = 0.0f;
+                MG_HIP(hipEventElapsedTime(&ms, g.a, g.b));
+                if (!best_rows || ms < best_ms) {
+                    best_rows = rh;
+                    best_bt = bt;
+                    best_ms = ms;
+                }
+            }
+        }
+        set_single_trial(0, 0, 0);
+        tile_table_set(l, 1, best_rows, best_bt);
+        rows.push_back({l, 1, best_rows, best_bt / 64, 1e3 * best_ms / reps});
+    }
+    const int n = std::min<int>(out_cap, (int)rows.size());
+    for (int i = 0; i < n; ++i) out[i] = rows[i];
+    if (n_out) *n_out = (int)rows.size();
+    return MG_OK;
 }
