@@ -55,6 +55,11 @@ def parse():
     ap.add_argument("--only-step", action="store_true",
                     help="set up the L = 12 workload and run the warm-up and timed steps "
                          "only (for profiler runs of exactly the timed step)")
+    ap.add_argument("--tiles", default=None,
+                    help="install the L = 12 tiles from this file (written by --save-tiles) "
+                         "instead of autotuning them (for profiler runs)")
+    ap.add_argument("--save-tiles", default=None,
+                    help="write the L = 12 tiles the autotuner picked to this file")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-rate", type=float, default=2000.0)
@@ -385,7 +390,12 @@ def main():
     # depends on them)
     mg.batch_clear_tiles()
     t = time.perf_counter()
-    tiles = h.autotune(reps=10)
+    if args.tiles:
+        tiles = mg.load_tiles(args.tiles)
+    else:
+        tiles = h.autotune(reps=10)
+        if args.save_tiles:
+            mg.save_tiles(tiles, args.save_tiles)
     t_tune = time.perf_counter() - t
     n = h.n
     b = torch.from_numpy(synth.rhs_gaussian(L, rseed)).to(dev)

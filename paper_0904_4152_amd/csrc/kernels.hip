@@ -39,15 +39,21 @@ __device__ __forceinline__ int64_t xcd_block(int64_t nblk) {
 
 inline unsigned grid8(int64_t nblk) { return (unsigned)((nblk + 7) / 8 * 8); }
 
+// Kernels of a guarded sequence (see launch_inner_ctrl) take a guard
+// pointer: a nonzero *guard makes the whole launch return at once.  Null:
+// no guard.
+__device__ __forceinline__ bool skipped(const double* guard) { return guard && *guard != 0.0; }
+
 // One tile per workgroup of the band product family (see dev::stencil_tile).
 template <typename T, int OP, bool NORM, bool STORE, bool SYM = false>
 __global__ __launch_bounds__(BLOCK) void k_stencil(const T* __restrict__ bands, int64_t bs,
                                                    int N, int64_t n, const T* __restrict__ x,
                                                    const T* __restrict__ b,
                                                    T* __restrict__ out, T omega,
-                                                   double* __restrict__ partials, int64_t nblk) {
+                                                   double* __restrict__ partials, int64_t nblk,
+                                                   const double* __restrict__ guard) {
     const int64_t lb = xcd_block(nblk);
-    if (lb < 0) return;
+    if (lb < 0 || skipped(guard)) return;
     const double sq = dev::stencil_tile<T, OP, NORM, STORE, SYM>(
         bands, bs, N, n, x, b, out, omega, lb * (int64_t)dev::tile_rows<T>());
     if (NORM) {
@@ -58,7 +64,9 @@ __global__ __launch_bounds__(BLOCK) void k_stencil(const T* __restrict__ bands, 
 
 __global__ __launch_bounds__(BLOCK) void k_reduce_final(const double* __restrict__ partials,
                                                         int64_t np, double* __restrict__ scal,
-                                                        int slot, double* __restrict__ host) {
+                                                        int slot, double* __restrict__ host,
+                                                        const double* __restrict__ guard) {
+    if (skipped(guard)) return;
     const double s = dev::reduce_partials(partials, np);
     if (threadIdx.x == 0) {
         scal[slot] = s;
@@ -104,7 +112,9 @@ __global__ __launch_bounds__(BLOCK) void k_reduce_segs(const double* __restrict_
                                                        int64_t np, double* __restrict__ segs,
                                                        unsigned* __restrict__ ticket,
                                                        double* __restrict__ scal, int slot,
-                                                       double* __restrict__ host) {
+                                                       double* __restrict__ host,
+                                                       const double* __restrict__ guard) {
+    if (skipped(guard)) return;
     const int64_t sg = blockIdx.x;
     const double v = dev::strided_sum(partials, sg * dev::RED_SEG,
                                       std::min<int64_t>(np, (sg + 1) * dev::RED_SEG));
@@ -143,9 +153,10 @@ template <typename T, bool XZERO, int BT>
 __global__ __launch_bounds__(BT) void k_pre(const T* __restrict__ bands, int64_t bs, int N,
                                             const T* __restrict__ x, const T* __restrict__ b,
                                             T omega, T* __restrict__ x2out, T* __restrict__ bc,
-                                            int dmask, dev::FusedGeom g) {
+                                            int dmask, dev::FusedGeom g,
+                                            const double* __restrict__ guard) {
     const int64_t lb = xcd_block((int64_t)g.nstrips * g.nchunks);
-    if (lb < 0) return;
+    if (lb < 0 || skipped(guard)) return;
     dev::pre_tile<T, XZERO, BT>(bands, bs, N, x, b, omega, x2out, bc, dmask,
                                 (int)(lb % g.nstrips), (int)(lb / g.nstrips), g.rh, g.cw);
 }
@@ -157,16 +168,18 @@ __global__ __launch_bounds__(BT) void k_post(const T* __restrict__ bands, int64_
                                              const T* __restrict__ x, const T* __restrict__ xc,
                                              const T* __restrict__ b, T omega,
                                              T* __restrict__ xout, double* __restrict__ partials,
-                                             dev::FusedGeom g) {
+                                             dev::FusedGeom g, const double* __restrict__ guard) {
     const int64_t lb = xcd_block((int64_t)g.nstrips * g.nchunks);
-    if (lb < 0) return;
+    if (lb < 0 || skipped(guard)) return;
     dev::post_tile<T, NORM, BT>(bands, bs, N, x, xc, b, omega, xout, partials,
                                 (int)(lb % g.nstrips), (int)(lb / g.nstrips), g.rh, g.cw);
 }
 
 // Coarse tail: the V(2,2) sub-cycle over levels top..Lc in one workgroup.
 template <typename T>
-__global__ __launch_bounds__(dev::TAIL_THREADS) void k_tail(dev::TailLevels<T> tl, T omega) {
+__global__ __launch_bounds__(dev::TAIL_THREADS) void k_tail(dev::TailLevels<T> tl, T omega,
+                                                             const double* __restrict__ guard) {
+    if (skipped(guard)) return;
     dev::tail_cycle<T>(tl, omega);
 }
 
@@ -621,10 +634,41 @@ __global__ __launch_bounds__(BLOCK) void k_cast_scaled_sumsq(const double* __res
 
 __global__ __launch_bounds__(BLOCK) void k_update(double* __restrict__ x,
                                                   const float* __restrict__ c, int64_t n,
-                                                  const double* __restrict__ scal, int slot) {
+                                                  const double* __restrict__ scal, int slot,
+                                                  const double* __restrict__ guard) {
     const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    if (p >= n) return;
+    if (p >= n || skipped(guard)) return;
     x[p] += scal[slot + 1] * (double)c[p];
+}
+
+// Device control of the mixed solve's inner loop (Sec. 6.2.2: the FP32
+// solver runs until its residual has dropped by the requested factor).
+// scal[SC_STOP] != 0 once the loop is over (guard of the loop's cycles),
+// scal[SC_WAIT] != 0 while it runs (guard of the work after it),
+// scal[SC_ITER] counts the cycles run, scal[SC_RED] and scal[SC_CAP] hold
+// the reduction factor and the cycle cap.
+__global__ void k_inner_reset(double* __restrict__ scal, double red, int cap) {
+    scal[SC_STOP] = 0.0;
+    scal[SC_WAIT] = 1.0;
+    scal[SC_ITER] = 0.0;
+    scal[SC_RED] = red;
+    scal[SC_CAP] = (double)cap;
+}
+
+// After a cycle (skipped with it once the loop is over): count it and take
+// the host driver's decision on the device, from the cycle's residual norm
+// scal[SC_R32 + 1] and the cast defect's norm scal[SC_D32 + 1].  The host
+// mirror gets the count, plus ITER_DONE once the loop is over, in one store.
+__global__ void k_inner_ctrl(double* __restrict__ scal, double* __restrict__ host) {
+    if (scal[SC_STOP] != 0.0) return;
+    const double it = scal[SC_ITER] + 1.0;
+    const double r32 = scal[SC_R32 + 1], dn = scal[SC_D32 + 1];
+    const bool done = !isfinite(r32) || r32 <= scal[SC_RED] * dn || it >= scal[SC_CAP];
+    scal[SC_ITER] = it;
+    scal[SC_STOP] = done ? 1.0 : 0.0;
+    scal[SC_WAIT] = done ? 0.0 : 1.0;
+    host[SC_ITER] = done ? it + ITER_DONE : it;
+    __threadfence_system();
 }
 
 // ---------------------------------------------------------------- Krylov
@@ -727,10 +771,10 @@ inline unsigned blocks1d(int64_t n) { return (unsigned)((n + BLOCK - 1) / BLOCK)
 // Segment sums go right after the partials, which the partials buffer leaves
 // room for; the word before the buffer is the ticket of k_reduce_segs.
 hipError_t launch_reduce(double* partials, int64_t np, double* scal, int slot, double* host,
-                         hipStream_t st) {
+                         hipStream_t st, const double* guard) {
     if (np <= dev::RED_SEG) {
         hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(BLOCK), 0, st, partials, np, scal, slot,
-                           host);
+                           host, guard);
         return hipGetLastError();
     }
     const int64_t ns = (np + dev::RED_SEG - 1) / dev::RED_SEG;
@@ -738,7 +782,7 @@ hipError_t launch_reduce(double* partials, int64_t np, double* scal, int slot, d
     double* segs = partials + (np + 63) / 64 * 64;
     unsigned* ticket = reinterpret_cast<unsigned*>(partials - 1);
     hipLaunchKernelGGL(k_reduce_segs, dim3(ns), dim3(BLOCK), 0, st, partials, np, segs, ticket,
-                       scal, slot, host);
+                       scal, slot, host, guard);
     return hipGetLastError();
 }
 
@@ -810,31 +854,32 @@ hipError_t launch_spmv(const Level& lv, const T* bands, const T* x, T* y, hipStr
     if (sym)
         hipLaunchKernelGGL((k_stencil<T, OP_SPMV, false, true, true>), dim3(grid8(nb)),
                            dim3(BLOCK), 0, st, bands, lv.bs, lv.N, lv.n, x, (const T*)nullptr, y,
-                           T(0), (double*)nullptr, nb);
+                           T(0), (double*)nullptr, nb, (const double*)nullptr);
     else
         hipLaunchKernelGGL((k_stencil<T, OP_SPMV, false, true>), dim3(grid8(nb)), dim3(BLOCK), 0,
                            st, bands, lv.bs, lv.N, lv.n, x, (const T*)nullptr, y, T(0),
-                           (double*)nullptr, nb);
+                           (double*)nullptr, nb, (const double*)nullptr);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_defect(const Level& lv, const T* bands, const T* b, const T* x, T* d,
-                         double* partials, double* scal, int slot, double* host, hipStream_t st) {
+                         double* partials, double* scal, int slot, double* host, hipStream_t st,
+                         const double* guard) {
     const int64_t nb = stencil_blocks(lv.n, sizeof(T));
     const dim3 g(grid8(nb)), blk(BLOCK);
     if (partials && d)
         hipLaunchKernelGGL((k_stencil<T, OP_DEFECT, true, true, true>), g, blk, 0, st, bands,
-                           lv.bs, lv.N, lv.n, x, b, d, T(0), partials, nb);
+                           lv.bs, lv.N, lv.n, x, b, d, T(0), partials, nb, guard);
     else if (partials)
         hipLaunchKernelGGL((k_stencil<T, OP_DEFECT, true, false, true>), g, blk, 0, st, bands,
-                           lv.bs, lv.N, lv.n, x, b, (T*)nullptr, T(0), partials, nb);
+                           lv.bs, lv.N, lv.n, x, b, (T*)nullptr, T(0), partials, nb, guard);
     else
         hipLaunchKernelGGL((k_stencil<T, OP_DEFECT, false, true, true>), g, blk, 0, st, bands,
-                           lv.bs, lv.N, lv.n, x, b, d, T(0), (double*)nullptr, nb);
+                           lv.bs, lv.N, lv.n, x, b, d, T(0), (double*)nullptr, nb, guard);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !partials) return e;
-    return launch_reduce(partials, nb, scal, slot, host, st);
+    return launch_reduce(partials, nb, scal, slot, host, st, guard);
 }
 
 template <typename T>
@@ -842,7 +887,8 @@ hipError_t launch_jacobi(const Level& lv, const T* bands, const T* b, const T* x
                          T omega, hipStream_t st) {
     const int64_t nb = stencil_blocks(lv.n, sizeof(T));
     hipLaunchKernelGGL((k_stencil<T, OP_JACOBI, false, true>), dim3(grid8(nb)), dim3(BLOCK), 0,
-                       st, bands, lv.bs, lv.N, lv.n, x, b, xo, omega, (double*)nullptr, nb);
+                       st, bands, lv.bs, lv.N, lv.n, x, b, xo, omega, (double*)nullptr, nb,
+                       (const double*)nullptr);
     return hipGetLastError();
 }
 
@@ -940,16 +986,16 @@ int64_t fused_tiles(int N) {
 
 template <typename T>
 hipError_t launch_pre(const Level& lv, const T* bands, const T* x, bool x_zero, const T* b,
-                      T omega, T* x2out, T* bc, int dmask, hipStream_t st) {
+                      T omega, T* x2out, T* bc, int dmask, hipStream_t st, const double* guard) {
     const dev::FusedGeom g = single_geom(lv.N);
     const dim3 grid(grid8((int64_t)g.nstrips * g.nchunks)), block(g.bt);
 #define PRE(BT)                                                                               \
     if (x_zero)                                                                               \
         hipLaunchKernelGGL((k_pre<T, true, BT>), grid, block, 0, st, bands, lv.bs, lv.N, x, b, \
-                           omega, x2out, bc, dmask, g);                                       \
+                           omega, x2out, bc, dmask, g, guard);                                \
     else                                                                                      \
         hipLaunchKernelGGL((k_pre<T, false, BT>), grid, block, 0, st, bands, lv.bs, lv.N, x,   \
-                           b, omega, x2out, bc, dmask, g);
+                           b, omega, x2out, bc, dmask, g, guard);
     MG_FUSED_BT_SWITCH(g.bt, PRE)
 #undef PRE
     return hipGetLastError();
@@ -958,26 +1004,26 @@ hipError_t launch_pre(const Level& lv, const T* bands, const T* x, bool x_zero, 
 template <typename T>
 hipError_t launch_post(const Level& lv, const T* bands, const T* x, const T* xc, const T* b,
                        T omega, T* xout, double* partials, double* scal, int slot, double* host,
-                       hipStream_t st) {
+                       hipStream_t st, const double* guard) {
     const dev::FusedGeom g = single_geom(lv.N);
     const dim3 grid(grid8((int64_t)g.nstrips * g.nchunks)), block(g.bt);
 #define POST(BT)                                                                             \
     if (partials)                                                                            \
         hipLaunchKernelGGL((k_post<T, true, BT>), grid, block, 0, st, bands, lv.bs, lv.N, x, \
-                           xc, b, omega, xout, partials, g);                                 \
+                           xc, b, omega, xout, partials, g, guard);                          \
     else                                                                                     \
         hipLaunchKernelGGL((k_post<T, false, BT>), grid, block, 0, st, bands, lv.bs, lv.N,   \
-                           x, xc, b, omega, xout, (double*)nullptr, g);
+                           x, xc, b, omega, xout, (double*)nullptr, g, guard);
     MG_FUSED_BT_SWITCH(g.bt, POST)
 #undef POST
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !partials) return e;
-    return launch_reduce(partials, dev::fused_norm_parts(lv.N), scal, slot, host, st);
+    return launch_reduce(partials, dev::fused_norm_parts(lv.N), scal, slot, host, st, guard);
 }
 
 template <typename T>
 hipError_t launch_tail(const Level* lv, int top, int Lc, const dev::CoarseSolver& cs, T omega,
-                       hipStream_t st) {
+                       hipStream_t st, const double* guard) {
     dev::TailLevels<T> tl{};
     for (int l = Lc; l <= top; ++l) {
         dev::TailLevel<T>& d = tl.lv[l];
@@ -993,7 +1039,7 @@ hipError_t launch_tail(const Level* lv, int top, int Lc, const dev::CoarseSolver
     tl.cs = cs;
     tl.top = top;
     tl.Lc = Lc;
-    hipLaunchKernelGGL(k_tail<T>, dim3(1), dim3(dev::TAIL_THREADS), 0, st, tl, omega);
+    hipLaunchKernelGGL(k_tail<T>, dim3(1), dim3(dev::TAIL_THREADS), 0, st, tl, omega, guard);
     return hipGetLastError();
 }
 
@@ -1084,8 +1130,19 @@ hipError_t launch_cast_scaled_norm(const double* d64, float* d32, int64_t n, con
 }
 
 hipError_t launch_update(double* x, const float* c32, int64_t n, const double* scal, int slot,
-                         hipStream_t st) {
-    hipLaunchKernelGGL(k_update, dim3(blocks1d(n)), dim3(BLOCK), 0, st, x, c32, n, scal, slot);
+                         hipStream_t st, const double* guard) {
+    hipLaunchKernelGGL(k_update, dim3(blocks1d(n)), dim3(BLOCK), 0, st, x, c32, n, scal, slot,
+                       guard);
+    return hipGetLastError();
+}
+
+hipError_t launch_inner_reset(double* scal, double red, int cap, hipStream_t st) {
+    hipLaunchKernelGGL(k_inner_reset, dim3(1), dim3(1), 0, st, scal, red, cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_inner_ctrl(double* scal, double* host, hipStream_t st) {
+    hipLaunchKernelGGL(k_inner_ctrl, dim3(1), dim3(1), 0, st, scal, host);
     return hipGetLastError();
 }
 
@@ -1135,7 +1192,8 @@ hipError_t launch_scalar_copy(double* scal, int from, int to, hipStream_t st) {
 #define MG_INSTANTIATE(T)                                                                     \
     template hipError_t launch_spmv<T>(const Level&, const T*, const T*, T*, hipStream_t, bool); \
     template hipError_t launch_defect<T>(const Level&, const T*, const T*, const T*, T*,      \
-                                         double*, double*, int, double*, hipStream_t);        \
+                                         double*, double*, int, double*, hipStream_t,         \
+                                         const double*);                                      \
     template hipError_t launch_jacobi<T>(const Level&, const T*, const T*, const T*, T*, T,   \
                                          hipStream_t);                                        \
     template hipError_t launch_jacobi_zero<T>(const Level&, const T*, const T*, T*, T,        \
@@ -1149,11 +1207,12 @@ hipError_t launch_scalar_copy(double* scal, int from, int to, hipStream_t st) {
                                        hipStream_t);                                          \
     template hipError_t launch_fill<T>(T*, int64_t, T, hipStream_t);                          \
     template hipError_t launch_pre<T>(const Level&, const T*, const T*, bool, const T*, T, T*,  \
-                                      T*, int, hipStream_t);                                    \
+                                      T*, int, hipStream_t, const double*);                     \
     template hipError_t launch_post<T>(const Level&, const T*, const T*, const T*, const T*, T, \
-                                       T*, double*, double*, int, double*, hipStream_t);      \
+                                       T*, double*, double*, int, double*, hipStream_t,       \
+                                       const double*);                                        \
     template hipError_t launch_tail<T>(const Level*, int, int, const dev::CoarseSolver&, T,    \
-                                       hipStream_t);
+                                       hipStream_t, const double*);
 
 MG_INSTANTIATE(float)
 MG_INSTANTIATE(double)

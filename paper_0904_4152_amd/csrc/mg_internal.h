@@ -89,6 +89,9 @@ struct mg_hierarchy {
     int* flag = nullptr;           // device status flag of the coarse factorisation
     bool assembled = false;
     GraphCache* graphs = nullptr;
+    // FP32 cycles the mixed solve's inner loops took at outer steps 1..8 of
+    // the previous solve (the number of cycles queued at once next time)
+    int inner_pred[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 };
 
 namespace mg {
@@ -105,8 +108,15 @@ enum : int {
     SC_RZ = 12,
     SC_RZ_OLD = 14,
     SC_RR = 16,
-    SC_XNZ = 18  // nonzero elements of the initial iterate
+    SC_XNZ = 18,  // nonzero elements of the initial iterate
+    // device control of the mixed solve's inner loop (k_inner_ctrl)
+    SC_STOP = 20,  // nonzero: the loop is over (its remaining cycles return at once)
+    SC_WAIT = 21,  // nonzero: the loop is still running (the update waits)
+    SC_ITER = 22,  // cycles run; host mirror: the same, plus ITER_DONE once over
+    SC_RED = 23,   // FP32 residual reduction factor of the loop
+    SC_CAP = 24    // cycle cap of the loop
 };
+constexpr double ITER_DONE = 1000.0;
 
 // How the hierarchy's coarsest level is solved.
 dev::CoarseSolver coarse_solver(const mg_hierarchy* h);
@@ -141,9 +151,13 @@ hipError_t launch_spmv(const Level& lv, const T* bands, const T* x, T* y, hipStr
 // (pinned memory, for the host to read once the stream has synchronized).
 // d = b - A x (d may be null); if partials != null also writes per-block
 // sums of d^2 and reduces them.
+// A guard makes every kernel of the launch return at once while *guard != 0
+// (see launch_inner_ctrl); the fused passes, the tail, the reductions and
+// the update take one too.
 template <typename T>
 hipError_t launch_defect(const Level& lv, const T* bands, const T* b, const T* x, T* d,
-                         double* partials, double* scal, int slot, double* host, hipStream_t st);
+                         double* partials, double* scal, int slot, double* host, hipStream_t st,
+                         const double* guard = nullptr);
 template <typename T>
 hipError_t launch_jacobi(const Level& lv, const T* bands, const T* b, const T* x, T* xo,
                          T omega, hipStream_t st);
@@ -183,7 +197,14 @@ hipError_t launch_cast_scaled_norm(const double* d64, float* d32, int64_t n, con
                                    double* host, hipStream_t st);
 // x += s * double(c32), s = scal[slot + 1].
 hipError_t launch_update(double* x, const float* c32, int64_t n, const double* scal, int slot,
-                         hipStream_t st);
+                         hipStream_t st, const double* guard = nullptr);
+// The mixed solve's inner loop under device control: reset the loop state
+// (SC_STOP = 0, SC_WAIT = 1, SC_ITER = 0, reduction factor and cycle cap);
+// after each cycle, count it and decide as the host loop does (stop when
+// the FP32 residual is not finite, has dropped to red times the cast
+// defect's norm, or the cap is reached), mirroring the count into host.
+hipError_t launch_inner_reset(double* scal, double red, int cap, hipStream_t st);
+hipError_t launch_inner_ctrl(double* scal, double* host, hipStream_t st);
 
 // Deterministic sum of np partials (dev::reduce_partials' order; one
 // block, or beyond dev::RED_SEG partials one block per segment whose sums go
@@ -194,7 +215,7 @@ hipError_t launch_update(double* x, const float* c32, int64_t n, const double* s
 // form (back to zero after each reduction).
 constexpr int64_t PARTIALS_FRONT = 64;  // doubles reserved before a partials buffer
 hipError_t launch_reduce(double* partials, int64_t np, double* scal, int slot, double* host,
-                         hipStream_t st);
+                         hipStream_t st, const double* guard = nullptr);
 
 // Preconditioned CG vector operations.  z is FP64, or FP32 scaled by
 // zscal[zslot + 1] (zslot >= 0).  u . z into scal[slot]; p = z + beta p with
@@ -218,16 +239,17 @@ hipError_t launch_scalar_copy(double* scal, int from, int to, hipStream_t st);
 // residual norm reduced into scal[slot], scal[slot + 1].
 template <typename T>
 hipError_t launch_pre(const Level& lv, const T* bands, const T* x, bool x_zero, const T* b,
-                      T omega, T* x2out, T* bc, int dmask, hipStream_t st);
+                      T omega, T* x2out, T* bc, int dmask, hipStream_t st,
+                      const double* guard = nullptr);
 template <typename T>
 hipError_t launch_post(const Level& lv, const T* bands, const T* x, const T* xc, const T* b,
                        T omega, T* xout, double* partials, double* scal, int slot, double* host,
-                       hipStream_t st);
+                       hipStream_t st, const double* guard = nullptr);
 // The V(2,2) sub-cycle over levels top..Lc (top <= tail_max_level(), entered
 // with a zero iterate on level top) in one workgroup.  lv is indexed by level.
 template <typename T>
 hipError_t launch_tail(const Level* lv, int top, int Lc, const dev::CoarseSolver& cs, T omega,
-                       hipStream_t st);
+                       hipStream_t st, const double* guard = nullptr);
 int tail_max_level();
 // Tiling of the fused passes on a level of N nodes per side: workgroup
 // width, chunk height for a pass over `count` problems, geometry of a

@@ -10,6 +10,7 @@ namespace mg {
 struct Enq {
     hipStream_t st;
     double bytes = 0.0;
+    const double* guard = nullptr;  // device flag: the fused cycle's kernels skip while != 0
 };
 
 // One V(nu_pre, nu_post) cycle on level l with iterate x and right-hand side

@@ -15,7 +15,9 @@
 
 struct GraphEntry {
     int kind;  // 0: FP64 cycle + residual norm; 1: FP32 inner cycle + residual norm;
-               // 2, 3: preconditioned CG step with an FP64 / FP32 cycle
+               // 2, 3: preconditioned CG step with an FP64 / FP32 cycle;
+               // 4: `reps` guarded FP32 inner cycles, each with its norm and control
+    int reps;
     int nu_pre, nu_post;
     double omega;
     bool x_zero;
@@ -135,6 +137,7 @@ hipError_t enqueue_vcycle_fused(mg_hierarchy* h, int l, T* x, const T* b, bool x
     const T om = (T)omega;
     const T* bands = LV<T>::bands(lv);
     if (l == h->Lc) {
+        if (q.guard) return hipErrorInvalidValue;  // guarded cycles need a level above the tail
         MG_TRY(launch_coarse<T>(coarse_solver(h), lv.N, b, x, q.st));
         q.bytes += 2 * s * n;
         if (partials) {
@@ -145,18 +148,18 @@ hipError_t enqueue_vcycle_fused(mg_hierarchy* h, int l, T* x, const T* b, bool x
     }
     Level& lc = h->lv[l - 1];
     T* t = LV<T>::t(lv);
-    MG_TRY(launch_pre<T>(lv, bands, x, x_zero, b, om, t, LV<T>::b(lc), h->dmask, q.st));
+    MG_TRY(launch_pre<T>(lv, bands, x, x_zero, b, om, t, LV<T>::b(lc), h->dmask, q.st, q.guard));
     q.bytes += (x_zero ? 11 : 12) * s * n + s * (double)lc.n;
     if (l - 1 <= tail_max_level()) {
         // every coarser level in one workgroup; same bytes as the unfused cycle there
-        MG_TRY(launch_tail<T>(h->lv, l - 1, h->Lc, coarse_solver(h), om, q.st));
+        MG_TRY(launch_tail<T>(h->lv, l - 1, h->Lc, coarse_solver(h), om, q.st, q.guard));
         for (int k = h->Lc + 1; k < l; ++k) q.bytes += 84.0 * s * (double)h->lv[k].n;
     } else {
         MG_TRY(enqueue_vcycle_fused<T>(h, l - 1, LV<T>::x(lc), LV<T>::b(lc), true, omega, q,
                                        nullptr, nullptr, 0, nullptr));
     }
     MG_TRY(launch_post<T>(lv, bands, t, LV<T>::x(lc), b, om, x, partials, scal, slot, host,
-                          q.st));
+                          q.st, q.guard));
     q.bytes += 12 * s * n + s * (double)lc.n;
     return hipSuccess;
 }
@@ -215,11 +218,24 @@ static hipError_t enqueue_pcg_step(mg_hierarchy* h, bool mixed, int nu_pre, int 
 
 // The unit replayed per iteration: FP64 cycle + FP64 residual norm (kind 0)
 // or FP32 inner cycle + FP32 residual norm (kind 1), on the finest level's
-// own vectors, or a preconditioned CG step (kinds 2, 3).
-static hipError_t enqueue_unit(mg_hierarchy* h, int kind, int nu_pre, int nu_post, double omega,
-                               bool x_zero, Enq& q) {
+// own vectors, or a preconditioned CG step (kinds 2, 3), or `reps` fused
+// FP32 inner cycles under device control (kind 4: each cycle's kernels
+// return at once when scal[SC_STOP] is set, and k_inner_ctrl after its norm
+// decides whether the loop goes on).
+static hipError_t enqueue_unit(mg_hierarchy* h, int kind, int reps, int nu_pre, int nu_post,
+                               double omega, bool x_zero, Enq& q) {
     Level& F = h->lv[h->L];
     const double n = (double)F.n;
+    if (kind == 4) {
+        Enq g{q.st, 0.0, h->scal + SC_STOP};
+        for (int i = 0; i < reps; ++i) {
+            MG_TRY(enqueue_vcycle_fused<float>(h, h->L, F.x32, F.b32, x_zero && i == 0, omega, g,
+                                               h->partials, h->scal, SC_R32, h->host_scal));
+            MG_TRY(launch_inner_ctrl(h->scal, h->host_scal, q.st));
+        }
+        q.bytes += g.bytes;
+        return hipSuccess;
+    }
     if (kind >= 2) return enqueue_pcg_step(h, kind == 3, nu_pre, nu_post, omega, q);
     if (nu_pre == 2 && nu_post == 2) {
         if (kind == 0)
@@ -257,14 +273,14 @@ void destroy_graphs(mg_hierarchy* h) {
 
 // Run one unit, from a captured graph when allowed.
 static hipError_t run_unit(mg_hierarchy* h, int kind, const mg_solve_opts& o, bool x_zero,
-                           bool use_graph, Enq& q) {
+                           bool use_graph, Enq& q, int reps = 1) {
     GraphCache* gc = cache(h);
     if (use_graph && gc->capture_ok) {
         const uint64_t epoch = tile_table_epoch();
         for (size_t i = 0; i < gc->entries.size(); ++i) {
             GraphEntry& e = gc->entries[i];
-            if (e.kind == kind && e.nu_pre == o.nu_pre && e.nu_post == o.nu_post &&
-                e.omega == o.omega && e.x_zero == x_zero) {
+            if (e.kind == kind && e.reps == reps && e.nu_pre == o.nu_pre &&
+                e.nu_post == o.nu_post && e.omega == o.omega && e.x_zero == x_zero) {
                 if (e.epoch == epoch) {
                     q.bytes += e.bytes;
                     return hipGraphLaunch(e.exec, q.st);
@@ -280,7 +296,7 @@ static hipError_t run_unit(mg_hierarchy* h, int kind, const mg_solve_opts& o, bo
         Enq cq{q.st, 0.0};
         hipError_t e = hipStreamBeginCapture(q.st, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
-            hipError_t ee = enqueue_unit(h, kind, o.nu_pre, o.nu_post, o.omega, x_zero, cq);
+            hipError_t ee = enqueue_unit(h, kind, reps, o.nu_pre, o.nu_post, o.omega, x_zero, cq);
             hipGraph_t g = nullptr;
             e = hipStreamEndCapture(q.st, &g);
             if (ee != hipSuccess) e = ee;
@@ -289,7 +305,7 @@ static hipError_t run_unit(mg_hierarchy* h, int kind, const mg_solve_opts& o, bo
             if (g) (void)hipGraphDestroy(g);
             if (e == hipSuccess) {
                 gc->entries.push_back(
-                    {kind, o.nu_pre, o.nu_post, o.omega, x_zero, ex, cq.bytes, epoch});
+                    {kind, reps, o.nu_pre, o.nu_post, o.omega, x_zero, ex, cq.bytes, epoch});
                 q.bytes += cq.bytes;
                 return hipGraphLaunch(ex, q.st);
             }
@@ -297,7 +313,7 @@ static hipError_t run_unit(mg_hierarchy* h, int kind, const mg_solve_opts& o, bo
         (void)hipGetLastError();
         gc->capture_ok = false;  // fall back to direct launches for this hierarchy
     }
-    return enqueue_unit(h, kind, o.nu_pre, o.nu_post, o.omega, x_zero, q);
+    return enqueue_unit(h, kind, reps, o.nu_pre, o.nu_post, o.omega, x_zero, q);
 }
 
 // Host read-back of reduced norms.  Every reduction the drivers read writes
@@ -328,6 +344,29 @@ static hipError_t read_scalar(mg_hierarchy* h, int slot, hipStream_t st, double*
     }
     MG_TRY(hipStreamSynchronize(st));
     *out = *v;
+    return hipSuccess;
+}
+
+// The inner-loop state k_inner_ctrl mirrors (cycles run, plus ITER_DONE once
+// the loop is over): wait until the loop is over or has run `want` cycles.
+static void arm_iter(mg_hierarchy* h) { ((volatile double*)h->host_scal)[SC_ITER] = kArmed; }
+
+static hipError_t read_iter(mg_hierarchy* h, int want, hipStream_t st, int* cycles, bool* done) {
+    const volatile double* v = (const volatile double*)h->host_scal + SC_ITER;
+    const auto t0 = std::chrono::steady_clock::now();
+    double x = kArmed;
+    for (unsigned i = 1;; ++i) {
+        x = *v;
+        if (!(x == kArmed) && (x >= ITER_DONE || x == (double)want)) break;
+        if ((i & 4095u) == 0 &&
+            std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(50)) {
+            MG_TRY(hipStreamSynchronize(st));
+            x = *v;
+            break;
+        }
+    }
+    *done = x >= ITER_DONE;
+    *cycles = (int)(*done ? x - ITER_DONE : x);
     return hipSuccess;
 }
 
@@ -527,18 +566,32 @@ extern "C" mg_status mg_solve(mg_hierarchy* h, const double* dev_b, double* dev_
             }
         }
     } else {
+        // With the fused V(2,2) cycle the inner loop runs under device
+        // control: the FP32 cycles the same outer step took in the previous
+        // solve are queued at once (each returns at once after the loop is
+        // over), then the update and the next FP64 defect, which wait on the
+        // device for the loop's end; the host reads one state per loop and
+        // queues single cycles if the loop needs more.  Same kernels, same
+        // decisions, same bits as one host round trip per cycle.
+        const bool guarded = o.nu_pre == 2 && o.nu_post == 2 && h->L > tail_max_level() &&
+                             o.inner_max_cycles < (int)ITER_DONE;
+        bool queued = false;  // the outer defect of step k is already queued
+        int last = 0;         // cycles of the previous inner loop of this solve
         for (int k = 1;; ++k) {
             double s = 0.0;
-            arm_scalar(h, SC_R64);
-            if (k == 1 && x_zero) {
-                MG_HIPS(launch_defect_zero_x(F, B64, h->d64, h->partials, h->scal, SC_R64,
-                                             h->host_scal, q.st));
-                q.bytes += 16.0 * n;
-            } else {
-                MG_HIPS(launch_defect<double>(F, F.bands64, B64, X64, h->d64, h->partials,
-                                              h->scal, SC_R64, h->host_scal, q.st));
-                q.bytes += 12.0 * 8 * n;
+            if (!queued) {
+                arm_scalar(h, SC_R64);
+                if (k == 1 && x_zero) {
+                    MG_HIPS(launch_defect_zero_x(F, B64, h->d64, h->partials, h->scal, SC_R64,
+                                                 h->host_scal, q.st));
+                    q.bytes += 16.0 * n;
+                } else {
+                    MG_HIPS(launch_defect<double>(F, F.bands64, B64, X64, h->d64, h->partials,
+                                                  h->scal, SC_R64, h->host_scal, q.st));
+                    q.bytes += 12.0 * 8 * n;
+                }
             }
+            queued = false;
             MG_HIPS(read_scalar(h, SC_R64, q.st, &s));
             st.rel_res = s / bn;
             if (k > 1 && st.n_hist < MG_HIST) st.res_hist[st.n_hist++] = s / bn;
@@ -560,20 +613,59 @@ extern "C" mg_status mg_solve(mg_hierarchy* h, const double* dev_b, double* dev_
             MG_HIPS(launch_cast_scaled_norm(h->d64, F.b32, n, h->scal, SC_R64, h->partials,
                                             h->scal, SC_D32, h->host_scal, q.st));
             q.bytes += 12.0 * n;
-            // ||d32|| is first needed after the first inner cycle: read it then
-            double dn = 0.0;
-            for (int it = 1; it <= o.inner_max_cycles; ++it) {
-                double r32 = 0.0;
-                arm_scalar(h, SC_R32);
-                MG_HIPS(run_unit(h, 1, o, it == 1, graphs, q));
-                if (it == 1) MG_HIPS(read_scalar(h, SC_D32, q.st, &dn));
-                MG_HIPS(read_scalar(h, SC_R32, q.st, &r32));
-                st.cycles++;
-                if (!std::isfinite(r32)) break;
-                if (r32 <= o.inner_reduction * dn) break;
+            if (!guarded) {
+                // ||d32|| is first needed after the first inner cycle: read it then
+                double dn = 0.0;
+                for (int it = 1; it <= o.inner_max_cycles; ++it) {
+                    double r32 = 0.0;
+                    arm_scalar(h, SC_R32);
+                    MG_HIPS(run_unit(h, 1, o, it == 1, graphs, q));
+                    if (it == 1) MG_HIPS(read_scalar(h, SC_D32, q.st, &dn));
+                    MG_HIPS(read_scalar(h, SC_R32, q.st, &r32));
+                    st.cycles++;
+                    if (!std::isfinite(r32)) break;
+                    if (r32 <= o.inner_reduction * dn) break;
+                }
+                MG_HIPS(launch_update(X64, F.x32, n, h->scal, SC_R64, q.st));
+                q.bytes += 20.0 * n;
+                st.outer_steps = k;
+                continue;
             }
-            MG_HIPS(launch_update(X64, F.x32, n, h->scal, SC_R64, q.st));
-            q.bytes += 20.0 * n;
+            const int slot = std::min(k, 8) - 1;
+            int pred = h->inner_pred[slot] > 0 ? h->inner_pred[slot] : (last > 0 ? last : 2);
+            pred = std::min(pred, o.inner_max_cycles);
+            MG_HIPS(launch_inner_reset(h->scal, o.inner_reduction, o.inner_max_cycles, q.st));
+            arm_iter(h);
+            Enq cq{q.st, 0.0};
+            MG_HIPS(run_unit(h, 4, o, true, graphs, cq, pred));
+            const double per_cycle = cq.bytes / pred;
+            // the update and the next outer defect, run once the loop is over
+            const double* wait = h->scal + SC_WAIT;
+            arm_scalar(h, SC_R64);
+            MG_HIPS(launch_update(X64, F.x32, n, h->scal, SC_R64, q.st, wait));
+            MG_HIPS(launch_defect<double>(F, F.bands64, B64, X64, h->d64, h->partials, h->scal,
+                                          SC_R64, h->host_scal, q.st, wait));
+            int cycles = 0;
+            bool done = false;
+            MG_HIPS(read_iter(h, pred, q.st, &cycles, &done));
+            const bool ran_after = done;  // the queued update and defect ran
+            while (!done) {
+                arm_iter(h);
+                Enq c1{q.st, 0.0};
+                MG_HIPS(run_unit(h, 4, o, false, graphs, c1, 1));
+                MG_HIPS(read_iter(h, cycles + 1, q.st, &cycles, &done));
+            }
+            if (!ran_after) {
+                arm_scalar(h, SC_R64);
+                MG_HIPS(launch_update(X64, F.x32, n, h->scal, SC_R64, q.st, wait));
+                MG_HIPS(launch_defect<double>(F, F.bands64, B64, X64, h->d64, h->partials,
+                                              h->scal, SC_R64, h->host_scal, q.st, wait));
+            }
+            q.bytes += per_cycle * cycles + 20.0 * n + 12.0 * 8 * n;
+            queued = true;
+            st.cycles += cycles;
+            h->inner_pred[slot] = cycles;
+            last = cycles;
             st.outer_steps = k;
         }
     }

@@ -1,10 +1,10 @@
 // CPU tests of the server's scheduler (paper_0904_4152_amd/csrc/scheduler.h)
 // against a fake executor with a simulated clock: one tick per launched
 // iteration, problems that finish after a known number of iterations, and
-// failures injected through the request seeds.  Built with g++ (plain, with
-// -fsanitize=thread, and with -fsanitize=address,undefined) and run by
-// tests/test_scheduler_cpu.py; prints "PASS <scenario>" per scenario and
-// exits non-zero on the first failed check.
+// failures injected through the request seeds.  Built plain (g++), with
+// -fsanitize=thread (clang++) and with -fsanitize=address,undefined (g++),
+// and run by tests/test_native_sanitizers.py; prints "PASS <scenario>" per
+// scenario and exits non-zero on the first failed check.
 #include <atomic>
 #include <cmath>
 #include <cstdio>

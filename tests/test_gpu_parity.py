@@ -385,7 +385,15 @@ def test_full_size_L12_spmv_and_mixed_solve(mg, ctx, orc):
     yr = orc.spmv(N, dbands, x)
     scale = abs_band_product(N, dbands, x)
     assert_within(host(y)[idx], yr[idx], (12 * U64 * scale)[idx], "spmv64 L12")
-    del dbands, yr, scale
+    # the FP64 defect and its norm at full size (every row and strip tile)
+    bvec = rng.standard_normal(N * N)
+    d = torch.empty_like(xd)
+    nrm = h.defect(L, dev(bvec), xd, d, norm=True)
+    dref = orc.defect(N, dbands, bvec, x)
+    assert_within(host(d)[idx], dref[idx], (12 * U64 * (scale + np.abs(bvec)))[idx],
+                  "defect64 L12")
+    assert abs(nrm - orc.norm2(dref)) <= 1e-13 * orc.norm2(dref)
+    del dbands, yr, scale, dref, d
     x32 = x.astype(np.float32)
     y32 = torch.empty(N * N, dtype=torch.float32, device="cuda")
     h.spmv(L, dev(x32, torch.float32), y32)
