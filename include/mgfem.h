@@ -198,10 +198,15 @@ mg_status mg_rhs_uniform(const mg_hierarchy* h, uint64_t seed, double* dev_b, vo
  * residual ||r|| <= rel_tol ||b||; stats.cycles counts CG steps (one cycle
  * each), res_hist the recurrence residuals, rel_res the true residual at
  * exit; inner_reduction and inner_max_cycles are unused.
- * Returns after the result is in dev_x (synchronises stream).  The mixed
- * solver updates dev_x in place as it goes (the others write it at the
- * end), so dev_x holds the last iterate also after an error.  Not thread
- * safe per hierarchy.  stats may be NULL. */
+ * Returns after the result is in dev_x.  The solve runs on an internal
+ * stream that waits (on the device, not the host) for the work queued on
+ * `stream` before the call, and work queued on `stream` after the call waits
+ * for the solve's.  The mixed solver updates dev_x in place as it goes (the
+ * others write it at the end), so dev_x holds the last iterate also after
+ * an error.  With the V(2,2) cycle on a hierarchy with levels above 5 the
+ * mixed solver's inner loop is decided on the device (same decisions and
+ * bits as the host loop; the host reads one state per outer step).  Not
+ * thread safe per hierarchy.  stats may be NULL. */
 mg_status mg_solve(mg_hierarchy* h, const double* dev_b, double* dev_x,
                    const mg_solve_opts* opts, void* stream, mg_stats* stats);
 

@@ -125,7 +125,9 @@ public:
     double bytes_per_step() const { return step_bytes_; }
 
 private:
-    hipError_t enqueue_iteration();
+    // with_init: the phase that starts new problems (their ||b||); only the
+    // first iteration after an upload that started problems needs it
+    hipError_t enqueue_iteration(bool with_init);
     hipError_t launch_fused(int l, bool pre, int mask);
     int problems_at(int l) const;
     void build_lists();
@@ -156,7 +158,8 @@ private:
     std::vector<int> h_wl_;
     std::vector<char> started_;
     bool probs_dirty_ = true;
-    hipGraphExec_t graph_ = nullptr;
+    hipGraphExec_t graph_[2] = {};  // iteration graphs without / with the start phase
+    bool init_pending_ = false;     // problems started since the last launch
     // Optional launches present in the captured graph: bit l for the fused
     // passes at level l, bit 0 for the residual of problems with no level
     // above the coarse one.  The set only grows (a new bit recaptures).

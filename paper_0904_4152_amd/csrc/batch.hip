@@ -44,7 +44,7 @@ constexpr int TILE = 1024;  // elements per work item (one FP32 stencil tile)
 
 enum { K_NORM = 0, K_S32 = 1, K_S64 = 2 };
 enum { F_BN = 0, F_S = 1, F_DN = 2, F_R32 = 3 };
-enum { PH_INIT = 0, PH_UPDATE = 1, PH_OUTER = 2, PH_CAST = 3, PH_INNER = 4 };
+enum { PH_INIT = 0, PH_OUTER = 2, PH_CAST = 3, PH_INNER = 4 };
 
 // Work list: wl[0] = count, wl[1] = cap, prob[cap] at wl+2, tile prefix
 // start[cap+1] at wl+2+cap.  Item t belongs to the last k with start[k] <= t.
@@ -327,10 +327,13 @@ __global__ __launch_bounds__(BLOCK) void kb_sumsq(const BProb* __restrict__ prob
     END_ITEMS
 }
 
-// d32 = float(d64 / s), the scaled defect, into the finest FP32 rhs.
+// d32 = float(d64 / s), the scaled defect, into the finest FP32 rhs, with
+// the sum-of-squares partials of d32 (the order of dev::sumsq_tile on the
+// stored values, as the single-problem cast kernel sums them).
 __global__ __launch_bounds__(BLOCK) void kb_cast(const BProb* __restrict__ probs,
                                                  const BState* __restrict__ state,
                                                  const int* __restrict__ wl, int mask) {
+    static_assert(TILE == dev::NORM_TILE, "one cast tile = one norm tile");
     FOR_ITEMS(wl)
     if (!(flags & mask)) continue;
     const BLevel& lv = P.lv[P.L];
@@ -342,11 +345,16 @@ __global__ __launch_bounds__(BLOCK) void kb_cast(const BProb* __restrict__ probs
         const int64_t q = base + (int64_t)e * BLOCK + threadIdx.x;
         dv[e] = P.d64[q < lv.n ? q : 0];
     }
+    double acc = 0.0;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
         const int64_t q = base + (int64_t)e * BLOCK + threadIdx.x;
-        if (q < lv.n) lv.b32[q] = s > 0.0 ? (float)(dv[e] / s) : 0.0f;
+        const float v = s > 0.0 ? (float)(dv[e] / s) : 0.0f;
+        if (q < lv.n) lv.b32[q] = v;
+        acc += q < lv.n ? (double)v * (double)v : 0.0;
     }
+    const double t = dev::block_sum(acc);
+    if (threadIdx.x == 0) P.partials[tile] = t;
     END_ITEMS
 }
 
@@ -435,47 +443,52 @@ __global__ __launch_bounds__(BLOCK) void kb_segsum(const BProb* __restrict__ pro
 // The inner residual (K_S32) of a problem with more than dev::RED_SEG
 // partials adds the segment sums of kb_segsum (the same order as summing the
 // partials here).
-__global__ __launch_bounds__(BLOCK) void kb_finalize(const BProb* __restrict__ probs,
-                                                     BState* __restrict__ state,
-                                                     const int* __restrict__ wl, int kind,
-                                                     int field, int mask, int fused_above) {
-    FOR_ITEMS(wl)
-    if (!(flags & mask)) continue;
-    const BLevel& F = P.lv[P.L];
-    const int64_t n = F.n;
-    int64_t np = kind == K_S64 ? (n + dev::tile_rows<double>() - 1) / dev::tile_rows<double>()
-                               : (n + TILE - 1) / TILE;
-    if (kind == K_S32) np = s32_parts(P, fused_above);
-    const double s =
-        (kind == K_S32 && np > dev::RED_SEG)
-            ? dev::strided_sum(P.partials + (np + 63) / 64 * 64, 0,
-                               (np + dev::RED_SEG - 1) / dev::RED_SEG)
-            : dev::reduce_partials(P.partials, np);
-    if (threadIdx.x == 0) {
-        const double r = sqrt(s);
-        BState& S = state[p];
-        if (field == F_BN)
-            S.bn = r;
-        else if (field == F_S)
-            S.s = r;
-        else if (field == F_DN)
-            S.dn = r;
-        else
-            S.r32 = r;
+__device__ void finalize_items(const BProb* __restrict__ probs, BState* __restrict__ state,
+                               const int* __restrict__ wl, int kind, int field, int mask,
+                               int fused_above) {
+    const int total = wl_total(wl);
+    for (int t = blockIdx.x; t < total; t += gridDim.x) {
+        int p, tile;
+        wl_item(wl, t, &p, &tile);
+        const BProb& P = probs[p];
+        if (!(state[p].flags & mask)) continue;
+        const BLevel& F = P.lv[P.L];
+        const int64_t n = F.n;
+        int64_t np = kind == K_S64
+                         ? (n + dev::tile_rows<double>() - 1) / dev::tile_rows<double>()
+                         : (n + TILE - 1) / TILE;
+        if (kind == K_S32) np = s32_parts(P, fused_above);
+        const double s =
+            (kind == K_S32 && np > dev::RED_SEG)
+                ? dev::strided_sum(P.partials + (np + 63) / 64 * 64, 0,
+                                   (np + dev::RED_SEG - 1) / dev::RED_SEG)
+                : dev::reduce_partials(P.partials, np);
+        if (threadIdx.x == 0) {
+            const double r = sqrt(s);
+            BState& S = state[p];
+            if (field == F_BN)
+                S.bn = r;
+            else if (field == F_S)
+                S.s = r;
+            else if (field == F_DN)
+                S.dn = r;
+            else
+                S.r32 = r;
+        }
     }
-    END_ITEMS
 }
 
-// Per-problem transitions of the mixed scheme (one block; thread per slot).
+// Per-problem transitions of the mixed scheme (one block; thread per slot):
+// INIT -> OUTER (or DONE), OUTER -> CAST or DONE (a problem whose inner
+// loop ended in this iteration's update counts its outer step first), CAST
+// -> INNER, INNER -> INNER or UPDATE.
 // At the end of an iteration (PH_INNER) also reports to the host, in entry
 // k mod ITER_RING of the pinned ring (k = iterations so far; entries of
 // 2 + cap ints): the problems not done, those still in their inner loop,
 // which cannot finish in the next iteration (a problem finishes only at an
 // outer step), and every slot's flags (0 for an empty slot).
-__global__ __launch_bounds__(BLOCK) void kb_ctrl(const BProb* __restrict__ probs,
-                                                 BState* __restrict__ state, int cap, int phase,
-                                                 int* __restrict__ iter,
-                                                 int* __restrict__ ring) {
+__device__ void ctrl_all(const BProb* __restrict__ probs, BState* __restrict__ state, int cap,
+                         int phase, int* __restrict__ iter, int* __restrict__ ring) {
     int live = 0, sure = 0, present = 0;
     int* entry = nullptr;
     if (phase == PH_INNER) entry = ring + (int64_t)(*iter % ITER_RING) * (2 + cap);
@@ -497,10 +510,8 @@ __global__ __launch_bounds__(BLOCK) void kb_ctrl(const BProb* __restrict__ probs
             } else {
                 S.flags = BF_OUTER;
             }
-        } else if (phase == PH_UPDATE && (f & BF_UPDATE)) {
-            S.outer += 1;
-            S.flags = BF_OUTER;
-        } else if (phase == PH_OUTER && (f & BF_OUTER)) {
+        } else if (phase == PH_OUTER && (f & (BF_OUTER | BF_UPDATE))) {
+            if (f & BF_UPDATE) S.outer += 1;  // its update ran in this iteration
             const int k = S.outer + 1;
             const double rel = S.s / S.bn;
             if (k > 1 && S.n_hist < MG_HIST) S.hist[S.n_hist++] = rel;
@@ -560,10 +571,37 @@ __global__ __launch_bounds__(BLOCK) void kb_ctrl(const BProb* __restrict__ probs
     }
 }
 
+// The norms of a phase (finalize_items), then, in the block that finishes
+// last (an integer ticket counts the finished blocks; fences order every
+// block's norms before its ticket and the last block's reads after it), the
+// phase's transitions (ctrl_all).  The ticket is back to zero after.
+__global__ __launch_bounds__(BLOCK) void kb_finctl(const BProb* __restrict__ probs,
+                                                   BState* __restrict__ state,
+                                                   const int* __restrict__ wl, int kind,
+                                                   int field, int mask, int fused_above,
+                                                   int phase, int* __restrict__ iter,
+                                                   int* __restrict__ ring,
+                                                   unsigned* __restrict__ ticket) {
+    if (state[wl[1]].flags & mask) finalize_items(probs, state, wl, kind, field, mask,
+                                                  fused_above);
+    __shared__ unsigned last;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        last = atomicAdd(ticket, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    ctrl_all(probs, state, wl[1], phase, iter, ring);
+    if (threadIdx.x == 0) *ticket = 0u;
+}
+
 }  // namespace
 
 BatchEngine::~BatchEngine() {
-    if (graph_) (void)hipGraphExecDestroy(graph_);
+    for (hipGraphExec_t g : graph_)
+        if (g) (void)hipGraphExecDestroy(g);
     if (st_) (void)hipStreamDestroy(st_);
     if (d_probs_) (void)hipFree(d_probs_);
     if (d_state_) (void)hipFree(d_state_);
@@ -826,8 +864,10 @@ void BatchEngine::build_lists() {
         if (bt_[l] != graph_bt_[l]) widths_changed = true;
     if ((need & ~launch_mask_) || widths_changed) {
         launch_mask_ |= need;
-        if (graph_) (void)hipGraphExecDestroy(graph_);
-        graph_ = nullptr;
+        for (hipGraphExec_t& g : graph_) {
+            if (g) (void)hipGraphExecDestroy(g);
+            g = nullptr;
+        }
     }
 }
 
@@ -852,15 +892,25 @@ mg_status BatchEngine::upload_async() {
                               hipMemcpyHostToDevice, st_));
         probs_dirty_ = false;
     }
+    // initial states of the started slots, one copy per run of consecutive
+    // started slots (the others' states are live on the device)
     bool any_started = false;
-    for (int s = 0; s < cap_; ++s) {
-        if (!started_[s]) continue;
-        BState& S = h_start_stage_[b][s];
-        std::memset(&S, 0, sizeof(BState));
-        S.flags = BF_INIT;
-        MG_HIP(hipMemcpyAsync(d_state_ + s, &S, sizeof(BState), hipMemcpyHostToDevice, st_));
-        started_[s] = 0;
+    for (int s = 0; s < cap_;) {
+        if (!started_[s]) {
+            ++s;
+            continue;
+        }
+        int e = s;
+        for (; e < cap_ && started_[e]; ++e) {
+            BState& S = h_start_stage_[b][e];
+            std::memset(&S, 0, sizeof(BState));
+            S.flags = BF_INIT;
+            started_[e] = 0;
+        }
+        MG_HIP(hipMemcpyAsync(d_state_ + s, &h_start_stage_[b][s], sizeof(BState) * (e - s),
+                              hipMemcpyHostToDevice, st_));
         any_started = true;
+        s = e;
     }
     if (any_started) {
         // the union of flags now includes BF_INIT: mark every flag present
@@ -868,6 +918,7 @@ mg_status BatchEngine::upload_async() {
         std::memset(&A, 0, sizeof(BState));
         A.flags = -1;
         MG_HIP(hipMemcpyAsync(d_state_ + cap_, &A, sizeof(BState), hipMemcpyHostToDevice, st_));
+        init_pending_ = true;
     }
     MG_HIP(hipEventRecord(ev_upload_[b], st_));
     return MG_OK;
@@ -986,13 +1037,15 @@ mg_status BatchEngine::tune(int reps, std::vector<mg_tile_choice>* out) {
     return upload();
 }
 
-hipError_t BatchEngine::enqueue_iteration() {
+hipError_t BatchEngine::enqueue_iteration(bool with_init) {
     const int stride = 3 + 2 * cap_;
     auto W = [&](int id) { return (const int*)(d_wl_ + (size_t)id * stride); };
     const dim3 G(STAGE_GRID), B(BLOCK), G1(1);
     const dim3 GA(std::min(cap_, 1024));
     BProb* P = d_probs_;
     BState* S = d_state_;
+    // the ticket of kb_finctl: the word after the iteration counter
+    unsigned* ticket = reinterpret_cast<unsigned*>(d_iter_ + 1);
 #define LAUNCH(...)                                        \
     do {                                                   \
         hipLaunchKernelGGL(__VA_ARGS__);                   \
@@ -1000,21 +1053,22 @@ hipError_t BatchEngine::enqueue_iteration() {
         if (e_ != hipSuccess) return e_;                   \
     } while (0)
     // new problems: ||b||
-    LAUNCH(kb_sumsq, G, B, 0, st_, P, S, W(WL_FINEST), 0, (int)BF_INIT);
-    LAUNCH(kb_finalize, GA, B, 0, st_, P, S, W(WL_ALL), (int)K_NORM, (int)F_BN, (int)BF_INIT, -1);
-    LAUNCH(kb_ctrl, G1, B, 0, st_, P, S, cap_, (int)PH_INIT, d_iter_, h_ring_);
-    // finished inner loops: x += s c
+    if (with_init) {
+        LAUNCH(kb_sumsq, G, B, 0, st_, P, S, W(WL_FINEST), 0, (int)BF_INIT);
+        LAUNCH(kb_finctl, GA, B, 0, st_, P, S, W(WL_ALL), (int)K_NORM, (int)F_BN, (int)BF_INIT,
+               -1, (int)PH_INIT, d_iter_, h_ring_, ticket);
+    }
+    // finished inner loops: x += s c; then, for them and the new problems,
+    // the FP64 defect, its norm and the stop test
+    const int om = BF_OUTER | BF_UPDATE;
     LAUNCH(kb_update, G, B, 0, st_, P, S, W(WL_FINEST), (int)BF_UPDATE);
-    LAUNCH(kb_ctrl, G1, B, 0, st_, P, S, cap_, (int)PH_UPDATE, d_iter_, h_ring_);
-    // FP64 defect, norm and stop test
-    LAUNCH(kb_outer_defect, G, B, 0, st_, P, S, W(WL_FINEST), (int)BF_OUTER);
-    LAUNCH(kb_finalize, GA, B, 0, st_, P, S, W(WL_ALL), (int)K_S64, (int)F_S, (int)BF_OUTER, -1);
-    LAUNCH(kb_ctrl, G1, B, 0, st_, P, S, cap_, (int)PH_OUTER, d_iter_, h_ring_);
+    LAUNCH(kb_outer_defect, G, B, 0, st_, P, S, W(WL_FINEST), om);
+    LAUNCH(kb_finctl, GA, B, 0, st_, P, S, W(WL_ALL), (int)K_S64, (int)F_S, om, -1,
+           (int)PH_OUTER, d_iter_, h_ring_, ticket);
     // scaled FP32 defect and its norm
     LAUNCH(kb_cast, G, B, 0, st_, P, S, W(WL_FINEST), (int)BF_CAST);
-    LAUNCH(kb_sumsq, G, B, 0, st_, P, S, W(WL_FINEST), 1, (int)BF_CAST);
-    LAUNCH(kb_finalize, GA, B, 0, st_, P, S, W(WL_ALL), (int)K_NORM, (int)F_DN, (int)BF_CAST, -1);
-    LAUNCH(kb_ctrl, G1, B, 0, st_, P, S, cap_, (int)PH_CAST, d_iter_, h_ring_);
+    LAUNCH(kb_finctl, GA, B, 0, st_, P, S, W(WL_ALL), (int)K_NORM, (int)F_DN, (int)BF_CAST, -1,
+           (int)PH_CAST, d_iter_, h_ring_, ticket);
     // one FP32 V-cycle for every problem in its inner loop
     const int m = BF_INNER;
     const bool fused = nu_pre_ == 2 && nu_post_ == 2;
@@ -1042,8 +1096,8 @@ hipError_t BatchEngine::enqueue_iteration() {
             LAUNCH(kb_inner_norm, G, B, 0, st_, P, S, W(WL_FINEST_COARSE), m, Lc_);
         if (launch_mask_ & (1u << 31))
             LAUNCH(kb_segsum, G, B, 0, st_, P, S, W(WL_SEGS32), m, Lc_);
-        LAUNCH(kb_finalize, GA, B, 0, st_, P, S, W(WL_ALL), (int)K_S32, (int)F_R32, m, Lc_);
-        LAUNCH(kb_ctrl, G1, B, 0, st_, P, S, cap_, (int)PH_INNER, d_iter_, h_ring_);
+        LAUNCH(kb_finctl, GA, B, 0, st_, P, S, W(WL_ALL), (int)K_S32, (int)F_R32, m, Lc_,
+               (int)PH_INNER, d_iter_, h_ring_, ticket);
         return hipSuccess;
     }
     // roles of the unfused cycle: 0 = x, 1 = t
@@ -1078,32 +1132,36 @@ hipError_t BatchEngine::enqueue_iteration() {
     LAUNCH(kb_inner_norm, G, B, 0, st_, P, S, W(WL_FINEST), m, -1);
     if (launch_mask_ & (1u << 31))
         LAUNCH(kb_segsum, G, B, 0, st_, P, S, W(WL_SEGS32), m, -1);
-    LAUNCH(kb_finalize, GA, B, 0, st_, P, S, W(WL_ALL), (int)K_S32, (int)F_R32, m, -1);
-    LAUNCH(kb_ctrl, G1, B, 0, st_, P, S, cap_, (int)PH_INNER, d_iter_, h_ring_);
+    LAUNCH(kb_finctl, GA, B, 0, st_, P, S, W(WL_ALL), (int)K_S32, (int)F_R32, m, -1,
+           (int)PH_INNER, d_iter_, h_ring_, ticket);
 #undef LAUNCH
     return hipSuccess;
 }
 
 mg_status BatchEngine::ensure_graph() {
-    if (!graph_) {
+    for (int w = 0; w < 2; ++w) {
+        if (graph_[w]) continue;
         hipGraph_t g = nullptr;
         MG_HIP(hipStreamBeginCapture(st_, hipStreamCaptureModeThreadLocal));
-        hipError_t e = enqueue_iteration();
+        hipError_t e = enqueue_iteration(w == 1);
         hipError_t e2 = hipStreamEndCapture(st_, &g);
         if (e == hipSuccess) e = e2;
-        if (e == hipSuccess) e = hipGraphInstantiate(&graph_, g, nullptr, nullptr, 0);
+        if (e == hipSuccess) e = hipGraphInstantiate(&graph_[w], g, nullptr, nullptr, 0);
         if (g) (void)hipGraphDestroy(g);
         if (e != hipSuccess) {
-            graph_ = nullptr;
+            graph_[w] = nullptr;
             return fail(MG_ERR_DEVICE, std::string("batch graph capture: ") + hipGetErrorString(e));
         }
-        for (int l = 0; l <= MG_MAX_LEVEL; ++l) graph_bt_[l] = bt_[l];
     }
+    for (int l = 0; l <= MG_MAX_LEVEL; ++l) graph_bt_[l] = bt_[l];
     return MG_OK;
 }
 
+// One iteration; the first after an upload that started problems also runs
+// the start phase.
 mg_status BatchEngine::launch() {
-    MG_HIP(hipGraphLaunch(graph_, st_));
+    MG_HIP(hipGraphLaunch(graph_[init_pending_ ? 1 : 0], st_));
+    init_pending_ = false;
     MG_HIP(hipEventRecord(ev_[launched_ % ITER_RING], st_));
     ++launched_;
     return MG_OK;

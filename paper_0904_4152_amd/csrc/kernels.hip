@@ -39,10 +39,55 @@ __device__ __forceinline__ int64_t xcd_block(int64_t nblk) {
 
 inline unsigned grid8(int64_t nblk) { return (unsigned)((nblk + 7) / 8 * 8); }
 
-// Kernels of a guarded sequence (see launch_inner_ctrl) take a guard
-// pointer: a nonzero *guard makes the whole launch return at once.  Null:
-// no guard.
+// Kernels of a guarded sequence (the mixed solve under device control, see
+// red_control) take a guard pointer: a nonzero *guard makes the whole
+// launch return at once.  Null: no guard.
 __device__ __forceinline__ bool skipped(const double* guard) { return guard && *guard != 0.0; }
+
+// Device control of the mixed solve (Sec. 6.2.2), taken by the thread that
+// has just written a norm r = scal[slot + 1] (see RedCtl):
+//   RED_OUTER (the FP64 defect of an outer step): the solve is over when r
+//     is not finite, above c.div ||b|| (diverged), at most c.thr ||b||,
+//     zero, or when c.cap is set (the step count is used up) -- the host
+//     driver's own tests on the same values (||b|| = scal[SC_B + 1]).  Then
+//     SC_CONV, SC_STOP and SC_WAIT are set, so everything queued after
+//     returns at once.
+//   RED_ZFLAG (the count of nonzero initial iterate elements):
+//     scal[SC_XZ] = 1 if the iterate is zero, else 0.
+//   RED_RESET (the cast defect's norm): a new inner loop, reduction factor
+//     c.thr and cycle cap c.cap.
+//   RED_STEP (an inner cycle's FP32 residual): count the cycle; the loop is
+//     over when the residual is not finite, at most c.thr (= scal[SC_RED])
+//     times the cast defect's norm, or the cap is reached.  The host mirror
+//     gets the count, plus ITER_DONE once the loop is over, in one store.
+__device__ void red_control(const RedCtl& c, double* __restrict__ scal, double* __restrict__ host,
+                            double r) {
+    if (c.mode == RED_OUTER) {
+        const double bn = scal[SC_B + 1];
+        const bool conv =
+            !isfinite(r) || r > c.div * bn || r <= c.thr * bn || r == 0.0 || c.cap != 0;
+        scal[SC_CONV] = conv ? 1.0 : 0.0;
+        if (conv) {
+            scal[SC_STOP] = 1.0;
+            scal[SC_WAIT] = 1.0;
+        }
+    } else if (c.mode == RED_ZFLAG) {
+        scal[SC_XZ] = r == 0.0 ? 1.0 : 0.0;
+    } else if (c.mode == RED_RESET) {
+        scal[SC_STOP] = 0.0;
+        scal[SC_WAIT] = 1.0;
+        scal[SC_ITER] = 0.0;
+        scal[SC_RED] = c.thr;
+        scal[SC_CAP] = (double)c.cap;
+    } else if (c.mode == RED_STEP) {
+        const double it = scal[SC_ITER] + 1.0;
+        const bool done = !isfinite(r) || r <= scal[SC_RED] * scal[SC_D32 + 1] || it >= scal[SC_CAP];
+        scal[SC_ITER] = it;
+        scal[SC_STOP] = done ? 1.0 : 0.0;
+        scal[SC_WAIT] = done ? 0.0 : 1.0;
+        if (host) host[SC_ITER] = done ? it + ITER_DONE : it;
+    }
+}
 
 // One tile per workgroup of the band product family (see dev::stencil_tile).
 template <typename T, int OP, bool NORM, bool STORE, bool SYM = false>
@@ -65,12 +110,14 @@ __global__ __launch_bounds__(BLOCK) void k_stencil(const T* __restrict__ bands, 
 __global__ __launch_bounds__(BLOCK) void k_reduce_final(const double* __restrict__ partials,
                                                         int64_t np, double* __restrict__ scal,
                                                         int slot, double* __restrict__ host,
-                                                        const double* __restrict__ guard) {
+                                                        const double* __restrict__ guard,
+                                                        RedCtl ctl) {
     if (skipped(guard)) return;
     const double s = dev::reduce_partials(partials, np);
     if (threadIdx.x == 0) {
         scal[slot] = s;
         scal[slot + 1] = sqrt(s);
+        red_control(ctl, scal, host, sqrt(s));
         if (host) {
             host[slot] = s;
             host[slot + 1] = sqrt(s);
@@ -113,7 +160,8 @@ __global__ __launch_bounds__(BLOCK) void k_reduce_segs(const double* __restrict_
                                                        unsigned* __restrict__ ticket,
                                                        double* __restrict__ scal, int slot,
                                                        double* __restrict__ host,
-                                                       const double* __restrict__ guard) {
+                                                       const double* __restrict__ guard,
+                                                       RedCtl ctl) {
     if (skipped(guard)) return;
     const int64_t sg = blockIdx.x;
     const double v = dev::strided_sum(partials, sg * dev::RED_SEG,
@@ -131,6 +179,7 @@ __global__ __launch_bounds__(BLOCK) void k_reduce_segs(const double* __restrict_
     if (threadIdx.x == 0) {
         scal[slot] = s;
         scal[slot + 1] = sqrt(s);
+        red_control(ctl, scal, host, sqrt(s));
         *ticket = 0u;
         if (host) {
             host[slot] = s;
@@ -563,10 +612,11 @@ template <typename T, bool NORM, bool STORE>
 __global__ __launch_bounds__(BLOCK) void k_defect_zero_x(int64_t n, const T* __restrict__ b,
                                                          T* __restrict__ out,
                                                          double* __restrict__ partials,
-                                                         int64_t nblk) {
+                                                         int64_t nblk,
+                                                         const double* __restrict__ guard) {
     constexpr int W = dev::V16<T>::W;
     const int64_t lb = xcd_block(nblk);
-    if (lb < 0) return;
+    if (lb < 0 || skipped(guard)) return;
     const int64_t p0 = lb * (int64_t)dev::tile_rows<T>() + (int64_t)threadIdx.x * W;
     double sq = 0.0;
     if (p0 < n) {
@@ -608,9 +658,10 @@ __global__ __launch_bounds__(BLOCK) void k_cast_scaled_sumsq(const double* __res
                                                              const double* __restrict__ scal,
                                                              int slot,
                                                              double* __restrict__ partials,
-                                                             int64_t nblk) {
+                                                             int64_t nblk,
+                                                             const double* __restrict__ guard) {
     const int64_t lb = xcd_block(nblk);
-    if (lb < 0) return;
+    if (lb < 0 || skipped(guard)) return;
     const double s = scal[slot + 1];
     const int64_t base = lb * (int64_t)dev::NORM_TILE;
     // the four loads go out together; lanes past n read element 0 and add zero
@@ -641,35 +692,6 @@ __global__ __launch_bounds__(BLOCK) void k_update(double* __restrict__ x,
     x[p] += scal[slot + 1] * (double)c[p];
 }
 
-// Device control of the mixed solve's inner loop (Sec. 6.2.2: the FP32
-// solver runs until its residual has dropped by the requested factor).
-// scal[SC_STOP] != 0 once the loop is over (guard of the loop's cycles),
-// scal[SC_WAIT] != 0 while it runs (guard of the work after it),
-// scal[SC_ITER] counts the cycles run, scal[SC_RED] and scal[SC_CAP] hold
-// the reduction factor and the cycle cap.
-__global__ void k_inner_reset(double* __restrict__ scal, double red, int cap) {
-    scal[SC_STOP] = 0.0;
-    scal[SC_WAIT] = 1.0;
-    scal[SC_ITER] = 0.0;
-    scal[SC_RED] = red;
-    scal[SC_CAP] = (double)cap;
-}
-
-// After a cycle (skipped with it once the loop is over): count it and take
-// the host driver's decision on the device, from the cycle's residual norm
-// scal[SC_R32 + 1] and the cast defect's norm scal[SC_D32 + 1].  The host
-// mirror gets the count, plus ITER_DONE once the loop is over, in one store.
-__global__ void k_inner_ctrl(double* __restrict__ scal, double* __restrict__ host) {
-    if (scal[SC_STOP] != 0.0) return;
-    const double it = scal[SC_ITER] + 1.0;
-    const double r32 = scal[SC_R32 + 1], dn = scal[SC_D32 + 1];
-    const bool done = !isfinite(r32) || r32 <= scal[SC_RED] * dn || it >= scal[SC_CAP];
-    scal[SC_ITER] = it;
-    scal[SC_STOP] = done ? 1.0 : 0.0;
-    scal[SC_WAIT] = done ? 0.0 : 1.0;
-    host[SC_ITER] = done ? it + ITER_DONE : it;
-    __threadfence_system();
-}
 
 // ---------------------------------------------------------------- Krylov
 // Vector kernels of the preconditioned CG solver.  A preconditioned vector
@@ -771,10 +793,10 @@ inline unsigned blocks1d(int64_t n) { return (unsigned)((n + BLOCK - 1) / BLOCK)
 // Segment sums go right after the partials, which the partials buffer leaves
 // room for; the word before the buffer is the ticket of k_reduce_segs.
 hipError_t launch_reduce(double* partials, int64_t np, double* scal, int slot, double* host,
-                         hipStream_t st, const double* guard) {
+                         hipStream_t st, const double* guard, RedCtl ctl) {
     if (np <= dev::RED_SEG) {
         hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(BLOCK), 0, st, partials, np, scal, slot,
-                           host, guard);
+                           host, guard, ctl);
         return hipGetLastError();
     }
     const int64_t ns = (np + dev::RED_SEG - 1) / dev::RED_SEG;
@@ -782,7 +804,7 @@ hipError_t launch_reduce(double* partials, int64_t np, double* scal, int slot, d
     double* segs = partials + (np + 63) / 64 * 64;
     unsigned* ticket = reinterpret_cast<unsigned*>(partials - 1);
     hipLaunchKernelGGL(k_reduce_segs, dim3(ns), dim3(BLOCK), 0, st, partials, np, segs, ticket,
-                       scal, slot, host, guard);
+                       scal, slot, host, guard, ctl);
     return hipGetLastError();
 }
 
@@ -865,7 +887,7 @@ hipError_t launch_spmv(const Level& lv, const T* bands, const T* x, T* y, hipStr
 template <typename T>
 hipError_t launch_defect(const Level& lv, const T* bands, const T* b, const T* x, T* d,
                          double* partials, double* scal, int slot, double* host, hipStream_t st,
-                         const double* guard) {
+                         const double* guard, RedCtl ctl) {
     const int64_t nb = stencil_blocks(lv.n, sizeof(T));
     const dim3 g(grid8(nb)), blk(BLOCK);
     if (partials && d)
@@ -879,7 +901,7 @@ hipError_t launch_defect(const Level& lv, const T* bands, const T* b, const T* x
                            lv.bs, lv.N, lv.n, x, b, d, T(0), (double*)nullptr, nb, guard);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !partials) return e;
-    return launch_reduce(partials, nb, scal, slot, host, st, guard);
+    return launch_reduce(partials, nb, scal, slot, host, st, guard, ctl);
 }
 
 template <typename T>
@@ -1004,7 +1026,7 @@ hipError_t launch_pre(const Level& lv, const T* bands, const T* x, bool x_zero, 
 template <typename T>
 hipError_t launch_post(const Level& lv, const T* bands, const T* x, const T* xc, const T* b,
                        T omega, T* xout, double* partials, double* scal, int slot, double* host,
-                       hipStream_t st, const double* guard) {
+                       hipStream_t st, const double* guard, RedCtl ctl) {
     const dev::FusedGeom g = single_geom(lv.N);
     const dim3 grid(grid8((int64_t)g.nstrips * g.nchunks)), block(g.bt);
 #define POST(BT)                                                                             \
@@ -1018,7 +1040,7 @@ hipError_t launch_post(const Level& lv, const T* bands, const T* x, const T* xc,
 #undef POST
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !partials) return e;
-    return launch_reduce(partials, dev::fused_norm_parts(lv.N), scal, slot, host, st, guard);
+    return launch_reduce(partials, dev::fused_norm_parts(lv.N), scal, slot, host, st, guard, ctl);
 }
 
 template <typename T>
@@ -1082,27 +1104,28 @@ hipError_t launch_norm(const T* v, int64_t n, double* partials, double* scal, in
 }
 
 hipError_t launch_count_nonzero(const double* v, int64_t n, double* partials, double* scal,
-                                int slot, double* host, hipStream_t st) {
+                                int slot, double* host, hipStream_t st, RedCtl ctl) {
     const int64_t nb = norm_blocks(n);
     hipLaunchKernelGGL(k_count_nonzero, dim3(grid8(nb)), dim3(BLOCK), 0, st, v, n, partials, nb);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return launch_reduce(partials, nb, scal, slot, host, st);
+    return launch_reduce(partials, nb, scal, slot, host, st, nullptr, ctl);
 }
 
 hipError_t launch_defect_zero_x(const Level& lv, const double* b, double* d, double* partials,
-                                double* scal, int slot, double* host, hipStream_t st) {
+                                double* scal, int slot, double* host, hipStream_t st,
+                                const double* guard, RedCtl ctl) {
     const int64_t nb = stencil_blocks(lv.n, sizeof(double));
     const dim3 g(grid8(nb)), blk(BLOCK);
     if (d)
         hipLaunchKernelGGL((k_defect_zero_x<double, true, true>), g, blk, 0, st, lv.n, b, d,
-                           partials, nb);
+                           partials, nb, guard);
     else
         hipLaunchKernelGGL((k_defect_zero_x<double, true, false>), g, blk, 0, st, lv.n, b,
-                           (double*)nullptr, partials, nb);
+                           (double*)nullptr, partials, nb, guard);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return launch_reduce(partials, nb, scal, slot, host, st);
+    return launch_reduce(partials, nb, scal, slot, host, st, guard, ctl);
 }
 
 template <typename T>
@@ -1120,13 +1143,14 @@ hipError_t launch_cast_scaled(const double* d64, float* d32, int64_t n, const do
 
 hipError_t launch_cast_scaled_norm(const double* d64, float* d32, int64_t n, const double* scal,
                                    int slot, double* partials, double* out_scal, int out_slot,
-                                   double* host, hipStream_t st) {
+                                   double* host, hipStream_t st, const double* guard,
+                                   RedCtl ctl) {
     const int64_t nb = norm_blocks(n);
     hipLaunchKernelGGL(k_cast_scaled_sumsq, dim3(grid8(nb)), dim3(BLOCK), 0, st, d64, d32, n, scal,
-                       slot, partials, nb);
+                       slot, partials, nb, guard);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return launch_reduce(partials, nb, out_scal, out_slot, host, st);
+    return launch_reduce(partials, nb, out_scal, out_slot, host, st, guard, ctl);
 }
 
 hipError_t launch_update(double* x, const float* c32, int64_t n, const double* scal, int slot,
@@ -1136,15 +1160,6 @@ hipError_t launch_update(double* x, const float* c32, int64_t n, const double* s
     return hipGetLastError();
 }
 
-hipError_t launch_inner_reset(double* scal, double red, int cap, hipStream_t st) {
-    hipLaunchKernelGGL(k_inner_reset, dim3(1), dim3(1), 0, st, scal, red, cap);
-    return hipGetLastError();
-}
-
-hipError_t launch_inner_ctrl(double* scal, double* host, hipStream_t st) {
-    hipLaunchKernelGGL(k_inner_ctrl, dim3(1), dim3(1), 0, st, scal, host);
-    return hipGetLastError();
-}
 
 template <typename TZ>
 hipError_t launch_dot(const double* u, const TZ* z, int64_t n, const double* zscal, int zslot,
@@ -1193,7 +1208,7 @@ hipError_t launch_scalar_copy(double* scal, int from, int to, hipStream_t st) {
     template hipError_t launch_spmv<T>(const Level&, const T*, const T*, T*, hipStream_t, bool); \
     template hipError_t launch_defect<T>(const Level&, const T*, const T*, const T*, T*,      \
                                          double*, double*, int, double*, hipStream_t,         \
-                                         const double*);                                      \
+                                         const double*, RedCtl);                              \
     template hipError_t launch_jacobi<T>(const Level&, const T*, const T*, const T*, T*, T,   \
                                          hipStream_t);                                        \
     template hipError_t launch_jacobi_zero<T>(const Level&, const T*, const T*, T*, T,        \
@@ -1210,7 +1225,7 @@ hipError_t launch_scalar_copy(double* scal, int from, int to, hipStream_t st) {
                                       T*, int, hipStream_t, const double*);                     \
     template hipError_t launch_post<T>(const Level&, const T*, const T*, const T*, const T*, T, \
                                        T*, double*, double*, int, double*, hipStream_t,       \
-                                       const double*);                                        \
+                                       const double*, RedCtl);                                \
     template hipError_t launch_tail<T>(const Level*, int, int, const dev::CoarseSolver&, T,    \
                                        hipStream_t, const double*);
 

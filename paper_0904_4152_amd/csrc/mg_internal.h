@@ -92,6 +92,9 @@ struct mg_hierarchy {
     // FP32 cycles the mixed solve's inner loops took at outer steps 1..8 of
     // the previous solve (the number of cycles queued at once next time)
     int inner_pred[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    // outer steps of the previous such solve (0: none yet): later steps are
+    // not queued ahead of their defect's norm
+    int outer_prev = 0;
 };
 
 namespace mg {
@@ -114,9 +117,22 @@ enum : int {
     SC_WAIT = 21,  // nonzero: the loop is still running (the update waits)
     SC_ITER = 22,  // cycles run; host mirror: the same, plus ITER_DONE once over
     SC_RED = 23,   // FP32 residual reduction factor of the loop
-    SC_CAP = 24    // cycle cap of the loop
+    SC_CAP = 24,   // cycle cap of the loop
+    SC_CONV = 25,  // nonzero: the outer loop is over (the work queued after returns)
+    SC_R64B = 26,  // FP64 outer defect norm of even outer steps (odd ones: SC_R64)
+    SC_XZ = 28     // 1 if the initial iterate is zero (RED_ZFLAG), else 0
 };
 constexpr double ITER_DONE = 1000.0;
+
+// What the final kernel of a reduction does besides writing the norm: the
+// mixed solve's decisions on the device (see red_control in kernels.hip).
+enum : int { RED_NONE = 0, RED_OUTER = 1, RED_RESET = 2, RED_STEP = 3, RED_ZFLAG = 4 };
+struct RedCtl {
+    int mode = RED_NONE;
+    double thr = 0.0;  // OUTER: stop at norm <= thr ||b||; RESET: the inner reduction factor
+    double div = 0.0;  // OUTER: diverged above div ||b||
+    int cap = 0;       // OUTER: nonzero stops (step count used up); RESET: cycle cap
+};
 
 // How the hierarchy's coarsest level is solved.
 dev::CoarseSolver coarse_solver(const mg_hierarchy* h);
@@ -151,13 +167,13 @@ hipError_t launch_spmv(const Level& lv, const T* bands, const T* x, T* y, hipStr
 // (pinned memory, for the host to read once the stream has synchronized).
 // d = b - A x (d may be null); if partials != null also writes per-block
 // sums of d^2 and reduces them.
-// A guard makes every kernel of the launch return at once while *guard != 0
-// (see launch_inner_ctrl); the fused passes, the tail, the reductions and
-// the update take one too.
+// A guard makes every kernel of the launch return at once while *guard != 0;
+// the fused passes, the tail, the reductions, the cast and the update take
+// one too.  ctl: see RedCtl.
 template <typename T>
 hipError_t launch_defect(const Level& lv, const T* bands, const T* b, const T* x, T* d,
                          double* partials, double* scal, int slot, double* host, hipStream_t st,
-                         const double* guard = nullptr);
+                         const double* guard = nullptr, RedCtl ctl = {});
 template <typename T>
 hipError_t launch_jacobi(const Level& lv, const T* bands, const T* b, const T* x, T* xo,
                          T omega, hipStream_t st);
@@ -185,26 +201,21 @@ hipError_t launch_cast_scaled(const double* d64, float* d32, int64_t n, const do
                               int slot, hipStream_t st);
 // scal[slot] = number of nonzero elements of v (FP64, exact).
 hipError_t launch_count_nonzero(const double* v, int64_t n, double* partials, double* scal,
-                                int slot, double* host, hipStream_t st);
+                                int slot, double* host, hipStream_t st, RedCtl ctl = {});
 // launch_defect (FP64, with the norm; d may be null) for x = 0: the same
 // bits, from b alone.
 hipError_t launch_defect_zero_x(const Level& lv, const double* b, double* d, double* partials,
-                                double* scal, int slot, double* host, hipStream_t st);
+                                double* scal, int slot, double* host, hipStream_t st,
+                                const double* guard = nullptr, RedCtl ctl = {});
 // The same, followed by launch_norm of d32 into out_scal[out_slot] (same
 // partials and sum, in one pass over the vectors).
 hipError_t launch_cast_scaled_norm(const double* d64, float* d32, int64_t n, const double* scal,
                                    int slot, double* partials, double* out_scal, int out_slot,
-                                   double* host, hipStream_t st);
+                                   double* host, hipStream_t st, const double* guard = nullptr,
+                                   RedCtl ctl = {});
 // x += s * double(c32), s = scal[slot + 1].
 hipError_t launch_update(double* x, const float* c32, int64_t n, const double* scal, int slot,
                          hipStream_t st, const double* guard = nullptr);
-// The mixed solve's inner loop under device control: reset the loop state
-// (SC_STOP = 0, SC_WAIT = 1, SC_ITER = 0, reduction factor and cycle cap);
-// after each cycle, count it and decide as the host loop does (stop when
-// the FP32 residual is not finite, has dropped to red times the cast
-// defect's norm, or the cap is reached), mirroring the count into host.
-hipError_t launch_inner_reset(double* scal, double red, int cap, hipStream_t st);
-hipError_t launch_inner_ctrl(double* scal, double* host, hipStream_t st);
 
 // Deterministic sum of np partials (dev::reduce_partials' order; one
 // block, or beyond dev::RED_SEG partials one block per segment whose sums go
@@ -215,7 +226,7 @@ hipError_t launch_inner_ctrl(double* scal, double* host, hipStream_t st);
 // form (back to zero after each reduction).
 constexpr int64_t PARTIALS_FRONT = 64;  // doubles reserved before a partials buffer
 hipError_t launch_reduce(double* partials, int64_t np, double* scal, int slot, double* host,
-                         hipStream_t st, const double* guard = nullptr);
+                         hipStream_t st, const double* guard = nullptr, RedCtl ctl = {});
 
 // Preconditioned CG vector operations.  z is FP64, or FP32 scaled by
 // zscal[zslot + 1] (zslot >= 0).  u . z into scal[slot]; p = z + beta p with
@@ -244,7 +255,7 @@ hipError_t launch_pre(const Level& lv, const T* bands, const T* x, bool x_zero, 
 template <typename T>
 hipError_t launch_post(const Level& lv, const T* bands, const T* x, const T* xc, const T* b,
                        T omega, T* xout, double* partials, double* scal, int slot, double* host,
-                       hipStream_t st, const double* guard = nullptr);
+                       hipStream_t st, const double* guard = nullptr, RedCtl ctl = {});
 // The V(2,2) sub-cycle over levels top..Lc (top <= tail_max_level(), entered
 // with a zero iterate on level top) in one workgroup.  lv is indexed by level.
 template <typename T>

@@ -11,6 +11,7 @@ struct Enq {
     hipStream_t st;
     double bytes = 0.0;
     const double* guard = nullptr;  // device flag: the fused cycle's kernels skip while != 0
+    RedCtl ctl{};                   // what the top-level residual norm's reduction decides
 };
 
 // One V(nu_pre, nu_post) cycle on level l with iterate x and right-hand side

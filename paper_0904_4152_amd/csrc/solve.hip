@@ -28,6 +28,7 @@ struct GraphEntry {
 
 struct GraphCache {
     hipStream_t st = nullptr;  // internal non-blocking stream (capture needs one)
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;  // order st after / before the caller's stream
     bool capture_ok = true;
     std::vector<GraphEntry> entries;
 };
@@ -159,7 +160,7 @@ hipError_t enqueue_vcycle_fused(mg_hierarchy* h, int l, T* x, const T* b, bool x
                                        nullptr, nullptr, 0, nullptr));
     }
     MG_TRY(launch_post<T>(lv, bands, t, LV<T>::x(lc), b, om, x, partials, scal, slot, host,
-                          q.st, q.guard));
+                          q.st, q.guard, partials ? q.ctl : RedCtl{}));
     q.bytes += 12 * s * n + s * (double)lc.n;
     return hipSuccess;
 }
@@ -220,19 +221,18 @@ static hipError_t enqueue_pcg_step(mg_hierarchy* h, bool mixed, int nu_pre, int 
 // or FP32 inner cycle + FP32 residual norm (kind 1), on the finest level's
 // own vectors, or a preconditioned CG step (kinds 2, 3), or `reps` fused
 // FP32 inner cycles under device control (kind 4: each cycle's kernels
-// return at once when scal[SC_STOP] is set, and k_inner_ctrl after its norm
-// decides whether the loop goes on).
+// return at once when scal[SC_STOP] is set, and the reduction of its
+// residual norm decides whether the loop goes on: RED_STEP).
 static hipError_t enqueue_unit(mg_hierarchy* h, int kind, int reps, int nu_pre, int nu_post,
                                double omega, bool x_zero, Enq& q) {
     Level& F = h->lv[h->L];
     const double n = (double)F.n;
     if (kind == 4) {
         Enq g{q.st, 0.0, h->scal + SC_STOP};
-        for (int i = 0; i < reps; ++i) {
+        g.ctl.mode = RED_STEP;
+        for (int i = 0; i < reps; ++i)
             MG_TRY(enqueue_vcycle_fused<float>(h, h->L, F.x32, F.b32, x_zero && i == 0, omega, g,
                                                h->partials, h->scal, SC_R32, h->host_scal));
-            MG_TRY(launch_inner_ctrl(h->scal, h->host_scal, q.st));
-        }
         q.bytes += g.bytes;
         return hipSuccess;
     }
@@ -266,6 +266,8 @@ static GraphCache* cache(mg_hierarchy* h) {
 void destroy_graphs(mg_hierarchy* h) {
     if (!h->graphs) return;
     for (auto& e : h->graphs->entries) (void)hipGraphExecDestroy(e.exec);
+    if (h->graphs->ev_in) (void)hipEventDestroy(h->graphs->ev_in);
+    if (h->graphs->ev_out) (void)hipEventDestroy(h->graphs->ev_out);
     if (h->graphs->st) (void)hipStreamDestroy(h->graphs->st);
     delete h->graphs;
     h->graphs = nullptr;
@@ -448,8 +450,12 @@ extern "C" mg_status mg_solve(mg_hierarchy* h, const double* dev_b, double* dev_
     MG_HIP(hipSetDevice(h->ctx->device));
     GraphCache* gc = cache(h);
     if (!gc->st) MG_HIP(hipStreamCreateWithFlags(&gc->st, hipStreamNonBlocking));
-    // Wait for the caller's producers of b and x, then work on the internal stream.
-    MG_HIPS(hipStreamSynchronize((hipStream_t)stream));
+    if (!gc->ev_in) MG_HIP(hipEventCreateWithFlags(&gc->ev_in, hipEventDisableTiming));
+    if (!gc->ev_out) MG_HIP(hipEventCreateWithFlags(&gc->ev_out, hipEventDisableTiming));
+    // The internal stream waits (on the device) for the caller's producers
+    // of b and x.
+    MG_HIPS(hipEventRecord(gc->ev_in, (hipStream_t)stream));
+    MG_HIPS(hipStreamWaitEvent(gc->st, gc->ev_in, 0));
     Enq q{gc->st, 0.0};
     Level& F = h->lv[h->L];
     const int64_t n = F.n;
@@ -466,6 +472,52 @@ extern "C" mg_status mg_solve(mg_hierarchy* h, const double* dev_b, double* dev_
         MG_HIPS(launch_copy<double>(dev_x, F.x64, n, q.st));
         q.bytes += 8.0 * 4 * n;
     }
+    // the mixed solve under device control (see the last branch below)
+    const bool devctl = !o.krylov && o.precision == MG_PREC_MIXED && o.nu_pre == 2 &&
+                        o.nu_post == 2 && h->L > tail_max_level() &&
+                        o.inner_max_cycles < (int)ITER_DONE;
+    auto nslot = [](int k) { return (k & 1) ? SC_R64 : SC_R64B; };
+    auto outer_ctl = [&](int k) {
+        RedCtl c;
+        c.mode = RED_OUTER;
+        c.thr = o.fixed_cycles > 0 ? -1.0 : o.rel_tol;
+        c.div = 1e3;
+        c.cap = (o.fixed_cycles > 0 ? k > o.fixed_cycles : k > o.max_cycles) ? 1 : 0;
+        return c;
+    };
+    const double* wait = h->scal + SC_WAIT;
+    // the update of step k and the defect of step k + 1
+    auto queue_update_defect = [&](int k) -> hipError_t {
+        MG_TRY(launch_update(X64, F.x32, n, h->scal, nslot(k), q.st, wait));
+        arm_scalar(h, nslot(k + 1));
+        return launch_defect<double>(F, F.bands64, B64, X64, h->d64, h->partials, h->scal,
+                                     nslot(k + 1), h->host_scal, q.st, wait,
+                                     outer_ctl(k + 1));
+    };
+    int last = 0;      // cycles of the previous inner loop of this solve
+    int pred = 0;      // cycles queued at once for the latest queued step
+    double cycle_bytes = 0.0;
+    // the cast, the predicted cycles, the update and the next defect of step k
+    auto queue_step = [&](int k) -> hipError_t {
+        RedCtl reset;
+        reset.mode = RED_RESET;
+        reset.thr = o.inner_reduction;
+        reset.cap = o.inner_max_cycles;
+        MG_TRY(launch_cast_scaled_norm(h->d64, F.b32, n, h->scal, nslot(k), h->partials,
+                                       h->scal, SC_D32, h->host_scal, q.st,
+                                       h->scal + SC_CONV, reset));
+        const int slot = std::min(k, 8) - 1;
+        pred = h->inner_pred[slot] > 0 ? h->inner_pred[slot] : (last > 0 ? last : 2);
+        pred = std::min(pred, o.inner_max_cycles);
+        arm_iter(h);
+        Enq cq{q.st, 0.0};
+        MG_TRY(run_unit(h, 4, o, true, graphs, cq, pred));
+        cycle_bytes = cq.bytes / pred;
+        MG_TRY(queue_update_defect(k));
+        return hipSuccess;
+    };
+    auto ahead = [&](int k) { return h->outer_prev <= 0 || k <= h->outer_prev; };
+    bool queued = false;  // outer step k already queued
     arm_scalar(h, SC_B);
     MG_HIPS(launch_norm<double>(B64, n, h->partials, h->scal, SC_B, h->host_scal, q.st));
     q.bytes += 8.0 * n;
@@ -473,8 +525,24 @@ extern "C" mg_status mg_solve(mg_hierarchy* h, const double* dev_b, double* dev_
     // itself: its kernel then reads b alone (same bits, see
     // launch_defect_zero_x).
     arm_scalar(h, SC_XNZ);
-    MG_HIPS(launch_count_nonzero(X64, n, h->partials, h->scal, SC_XNZ, h->host_scal, q.st));
+    RedCtl zflag;
+    zflag.mode = devctl ? RED_ZFLAG : RED_NONE;
+    MG_HIPS(launch_count_nonzero(X64, n, h->partials, h->scal, SC_XNZ, h->host_scal, q.st,
+                                 zflag));
     q.bytes += 8.0 * n;
+    if (devctl) {
+        // the first defect (of the zero or the given iterate: the other
+        // kernel returns at once) and step 1, before ||b|| reaches the host;
+        // the device's tests read ||b|| from its own copy
+        arm_scalar(h, nslot(1));
+        MG_HIPS(launch_defect_zero_x(F, B64, h->d64, h->partials, h->scal, nslot(1),
+                                     h->host_scal, q.st, h->scal + SC_XNZ, outer_ctl(1)));
+        MG_HIPS(launch_defect<double>(F, F.bands64, B64, X64, h->d64, h->partials, h->scal,
+                                      nslot(1), h->host_scal, q.st, h->scal + SC_XZ,
+                                      outer_ctl(1)));
+        queued = ahead(1);
+        if (queued) MG_HIPS(queue_step(1));
+    }
     double bn = 0.0, xnz = 1.0;
     MG_HIPS(read_scalar(h, SC_B, q.st, &bn));
     MG_HIPS(read_scalar(h, SC_XNZ, q.st, &xnz));
@@ -565,33 +633,20 @@ extern "C" mg_status mg_solve(mg_hierarchy* h, const double* dev_b, double* dev_
                 break;
             }
         }
-    } else {
-        // With the fused V(2,2) cycle the inner loop runs under device
-        // control: the FP32 cycles the same outer step took in the previous
-        // solve are queued at once (each returns at once after the loop is
-        // over), then the update and the next FP64 defect, which wait on the
-        // device for the loop's end; the host reads one state per loop and
-        // queues single cycles if the loop needs more.  Same kernels, same
-        // decisions, same bits as one host round trip per cycle.
-        const bool guarded = o.nu_pre == 2 && o.nu_post == 2 && h->L > tail_max_level() &&
-                             o.inner_max_cycles < (int)ITER_DONE;
-        bool queued = false;  // the outer defect of step k is already queued
-        int last = 0;         // cycles of the previous inner loop of this solve
+    } else if (!devctl) {
+        // host-driven loop: one host read per FP64 defect and per FP32 cycle
         for (int k = 1;; ++k) {
             double s = 0.0;
-            if (!queued) {
-                arm_scalar(h, SC_R64);
-                if (k == 1 && x_zero) {
-                    MG_HIPS(launch_defect_zero_x(F, B64, h->d64, h->partials, h->scal, SC_R64,
-                                                 h->host_scal, q.st));
-                    q.bytes += 16.0 * n;
-                } else {
-                    MG_HIPS(launch_defect<double>(F, F.bands64, B64, X64, h->d64, h->partials,
-                                                  h->scal, SC_R64, h->host_scal, q.st));
-                    q.bytes += 12.0 * 8 * n;
-                }
+            arm_scalar(h, SC_R64);
+            if (k == 1 && x_zero) {
+                MG_HIPS(launch_defect_zero_x(F, B64, h->d64, h->partials, h->scal, SC_R64,
+                                             h->host_scal, q.st));
+                q.bytes += 16.0 * n;
+            } else {
+                MG_HIPS(launch_defect<double>(F, F.bands64, B64, X64, h->d64, h->partials,
+                                              h->scal, SC_R64, h->host_scal, q.st));
+                q.bytes += 12.0 * 8 * n;
             }
-            queued = false;
             MG_HIPS(read_scalar(h, SC_R64, q.st, &s));
             st.rel_res = s / bn;
             if (k > 1 && st.n_hist < MG_HIST) st.res_hist[st.n_hist++] = s / bn;
@@ -613,67 +668,96 @@ extern "C" mg_status mg_solve(mg_hierarchy* h, const double* dev_b, double* dev_
             MG_HIPS(launch_cast_scaled_norm(h->d64, F.b32, n, h->scal, SC_R64, h->partials,
                                             h->scal, SC_D32, h->host_scal, q.st));
             q.bytes += 12.0 * n;
-            if (!guarded) {
-                // ||d32|| is first needed after the first inner cycle: read it then
-                double dn = 0.0;
-                for (int it = 1; it <= o.inner_max_cycles; ++it) {
-                    double r32 = 0.0;
-                    arm_scalar(h, SC_R32);
-                    MG_HIPS(run_unit(h, 1, o, it == 1, graphs, q));
-                    if (it == 1) MG_HIPS(read_scalar(h, SC_D32, q.st, &dn));
-                    MG_HIPS(read_scalar(h, SC_R32, q.st, &r32));
-                    st.cycles++;
-                    if (!std::isfinite(r32)) break;
-                    if (r32 <= o.inner_reduction * dn) break;
-                }
-                MG_HIPS(launch_update(X64, F.x32, n, h->scal, SC_R64, q.st));
-                q.bytes += 20.0 * n;
-                st.outer_steps = k;
-                continue;
+            // ||d32|| is first needed after the first inner cycle: read it then
+            double dn = 0.0;
+            for (int it = 1; it <= o.inner_max_cycles; ++it) {
+                double r32 = 0.0;
+                arm_scalar(h, SC_R32);
+                MG_HIPS(run_unit(h, 1, o, it == 1, graphs, q));
+                if (it == 1) MG_HIPS(read_scalar(h, SC_D32, q.st, &dn));
+                MG_HIPS(read_scalar(h, SC_R32, q.st, &r32));
+                st.cycles++;
+                if (!std::isfinite(r32)) break;
+                if (r32 <= o.inner_reduction * dn) break;
             }
+            MG_HIPS(launch_update(X64, F.x32, n, h->scal, SC_R64, q.st));
+            q.bytes += 20.0 * n;
+            st.outer_steps = k;
+        }
+    } else {
+        // Device control (fused V(2,2) cycle): the decisions of the loop
+        // above, taken on the device by the reductions that produce the
+        // norms they test (RedCtl), with everything that follows a decision
+        // queued behind it under a guard.  After the FP64 defect of outer
+        // step k the host queues the cast, the FP32 cycles step k took in
+        // the previous solve (each returning at once after the loop is
+        // over), the update and the defect of step k + 1, which wait on the
+        // device for the loop's end -- before reading the defect's norm when
+        // the previous solve also took step k (then the device does not wait
+        // for the host between outer steps), after it otherwise (a converged
+        // solve leaves no skipped cycles behind).  The host reads the
+        // defect's norm (its tests are the device's), then the loop's state;
+        // if the loop needs more cycles than were queued, it queues single
+        // cycles and then the update and the next defect.  Same kernels,
+        // same decisions, same bits as the loop above.  Outer steps
+        // alternate between two norm slots, so queueing step k + 1 never
+        // overwrites a norm the host has yet to read.
+        q.bytes += x_zero ? 16.0 * n : 12.0 * 8 * n;  // the first defect
+        for (int k = 1;; ++k) {
+            double s = 0.0;
+            MG_HIPS(read_scalar(h, nslot(k), q.st, &s));
+            st.rel_res = s / bn;
+            if (k > 1 && st.n_hist < MG_HIST) st.res_hist[st.n_hist++] = s / bn;
+            if (!std::isfinite(s) || s > 1e3 * bn) {
+                result = fail(MG_ERR_NUMERIC, "residual diverged or became NaN");
+                break;
+            }
+            if (o.fixed_cycles > 0) {
+                if (k > o.fixed_cycles) break;
+            } else {
+                if (s <= o.rel_tol * bn) break;
+                if (k > o.max_cycles) {
+                    result = fail(MG_ERR_NOCONV, "no convergence within max_cycles");
+                    break;
+                }
+            }
+            if (s == 0.0) break;
+            if (!queued) MG_HIPS(queue_step(k));
+            q.bytes += 12.0 * n;  // the cast
             const int slot = std::min(k, 8) - 1;
-            int pred = h->inner_pred[slot] > 0 ? h->inner_pred[slot] : (last > 0 ? last : 2);
-            pred = std::min(pred, o.inner_max_cycles);
-            MG_HIPS(launch_inner_reset(h->scal, o.inner_reduction, o.inner_max_cycles, q.st));
-            arm_iter(h);
-            Enq cq{q.st, 0.0};
-            MG_HIPS(run_unit(h, 4, o, true, graphs, cq, pred));
-            const double per_cycle = cq.bytes / pred;
-            // the update and the next outer defect, run once the loop is over
-            const double* wait = h->scal + SC_WAIT;
-            arm_scalar(h, SC_R64);
-            MG_HIPS(launch_update(X64, F.x32, n, h->scal, SC_R64, q.st, wait));
-            MG_HIPS(launch_defect<double>(F, F.bands64, B64, X64, h->d64, h->partials, h->scal,
-                                          SC_R64, h->host_scal, q.st, wait));
             int cycles = 0;
             bool done = false;
             MG_HIPS(read_iter(h, pred, q.st, &cycles, &done));
-            const bool ran_after = done;  // the queued update and defect ran
-            while (!done) {
-                arm_iter(h);
-                Enq c1{q.st, 0.0};
-                MG_HIPS(run_unit(h, 4, o, false, graphs, c1, 1));
-                MG_HIPS(read_iter(h, cycles + 1, q.st, &cycles, &done));
+            if (!done) {
+                // the queued update and defect were skipped: more cycles, then those
+                while (!done) {
+                    arm_iter(h);
+                    Enq c1{q.st, 0.0};
+                    MG_HIPS(run_unit(h, 4, o, false, graphs, c1, 1));
+                    MG_HIPS(read_iter(h, cycles + 1, q.st, &cycles, &done));
+                }
+                MG_HIPS(queue_update_defect(k));
             }
-            if (!ran_after) {
-                arm_scalar(h, SC_R64);
-                MG_HIPS(launch_update(X64, F.x32, n, h->scal, SC_R64, q.st, wait));
-                MG_HIPS(launch_defect<double>(F, F.bands64, B64, X64, h->d64, h->partials,
-                                              h->scal, SC_R64, h->host_scal, q.st, wait));
-            }
-            q.bytes += per_cycle * cycles + 20.0 * n + 12.0 * 8 * n;
-            queued = true;
+            q.bytes += cycle_bytes * cycles + 20.0 * n + 12.0 * 8 * n;
             st.cycles += cycles;
             h->inner_pred[slot] = cycles;
             last = cycles;
             st.outer_steps = k;
+            queued = ahead(k + 1);
+            if (queued) MG_HIPS(queue_step(k + 1));
         }
+        if (result == MG_OK) h->outer_prev = st.outer_steps;
     }
     if (!direct) {
         MG_HIPS(launch_copy<double>(F.x64, dev_x, n, q.st));
         q.bytes += 16.0 * n;
     }
-    MG_HIPS(hipStreamSynchronize(q.st));
+    // Later work on the caller's stream runs after the solve's.  The mixed
+    // solve's last write of x came before the defect whose norm the host
+    // has read, so only the others wait here for their final copy.
+    MG_HIPS(hipEventRecord(gc->ev_out, q.st));
+    MG_HIPS(hipStreamWaitEvent((hipStream_t)stream, gc->ev_out, 0));
+    if (!direct || result != MG_OK || bn == 0.0) MG_HIPS(hipStreamSynchronize(q.st));
     st.status = result;
     st.alg_bytes = q.bytes;
     st.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

@@ -99,3 +99,52 @@ def test_device_control_warm_start_and_cap(mg, ctx):
     assert s1.cycles == s1.outer_steps  # one cycle per outer step
     assert s1.outer_steps > ref[1].outer_steps
     h.close()
+
+
+def test_device_control_step_limits(mg, ctx):
+    """fixed_cycles and an exhausted max_cycles end the outer loop at the
+    same step, with the same status, iterate and statistics, on the device
+    as on the host."""
+    L = 7
+    h = mg.Hierarchy(ctx, L, jitter=0.2, seed=840)
+    b = torch.from_numpy(synth.rhs_uniform(L, 841)).cuda()
+
+    def solve(**kw):
+        x = torch.zeros_like(b)
+        o = mg.default_opts(precision=mg.MG_PREC_MIXED, **kw)
+        st = h.solve(b, x, o, raise_on_error=False)
+        torch.cuda.synchronize()
+        return x.cpu().numpy(), st
+
+    for kw in (dict(fixed_cycles=2), dict(fixed_cycles=5, rel_tol=1e-3),
+               dict(max_cycles=2, rel_tol=1e-14)):
+        ref = solve(inner_max_cycles=1000, **kw)
+        got = solve(**kw)
+        same(got, ref)
+        if "max_cycles" in kw:
+            assert got[1].status == mg.MG_ERR_NOCONV
+        else:
+            assert got[1].status == 0 and got[1].outer_steps == kw["fixed_cycles"]
+    h.close()
+
+
+def test_solve_is_ordered_on_the_callers_stream(mg, ctx):
+    """The solve waits on the device for work queued before it on the
+    caller's stream, and work queued after it on that stream sees the
+    solution, without the host blocking in between."""
+    L = 9
+    h = mg.Hierarchy(ctx, L, jitter=0.2, seed=850)
+    b = torch.from_numpy(synth.rhs_uniform(L, 851)).cuda()
+    o = mg.default_opts(precision=mg.MG_PREC_MIXED, rel_tol=1e-9)
+    x_ref = torch.zeros_like(b)
+    h.solve(b, x_ref, o)
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        x = torch.full_like(b, 7.0)
+        x.zero_()                       # queued on s before the solve
+        h.solve(b, x, o, stream=s)
+        out = x * 1.0                   # queued on s after it
+    s.synchronize()
+    np.testing.assert_array_equal(out.cpu().numpy(), x_ref.cpu().numpy())
+    h.close()
