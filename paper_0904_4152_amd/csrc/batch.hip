@@ -439,13 +439,61 @@ __global__ __launch_bounds__(BLOCK) void kb_segsum(const BProb* __restrict__ pro
     END_ITEMS
 }
 
-// Norm of one problem from its partials (fixed order), into a state field.
-// The inner residual (K_S32) of a problem with more than dev::RED_SEG
-// partials adds the segment sums of kb_segsum (the same order as summing the
-// partials here).
+// Per-problem transition of the mixed scheme at the end of a phase:
+// INIT -> OUTER (or DONE), OUTER -> CAST or DONE (a problem whose inner
+// loop ended in this iteration's update counts its outer step first), CAST
+// -> INNER, INNER -> INNER or UPDATE.
+__device__ void transition(const BProb& P, BState& S, int phase) {
+    const int f = S.flags;
+    if (phase == PH_INIT && (f & BF_INIT)) {
+        if (!isfinite(S.bn)) {
+            S.status = MG_ERR_NUMERIC;
+            S.flags = BF_DONE;
+        } else if (S.bn == 0.0) {
+            S.status = MG_OK;
+            S.flags = BF_DONE;
+        } else {
+            S.flags = BF_OUTER;
+        }
+    } else if (phase == PH_OUTER && (f & (BF_OUTER | BF_UPDATE))) {
+        if (f & BF_UPDATE) S.outer += 1;  // its update ran in this iteration
+        const int k = S.outer + 1;
+        const double rel = S.s / S.bn;
+        if (k > 1 && S.n_hist < MG_HIST) S.hist[S.n_hist++] = rel;
+        int done = 0;
+        if (!isfinite(S.s) || S.s > 1e3 * S.bn) {
+            S.status = MG_ERR_NUMERIC;
+            done = 1;
+        } else if (P.fixed > 0) {
+            done = k > P.fixed;
+        } else if (S.s <= P.rel_tol * S.bn) {
+            done = 1;
+        } else if (k > P.max_outer) {
+            S.status = MG_ERR_NOCONV;
+            done = 1;
+        }
+        if (!done && S.s == 0.0) done = 1;
+        S.flags = done ? BF_DONE : BF_CAST;
+    } else if (phase == PH_CAST && (f & BF_CAST)) {
+        S.first = 1;
+        S.it = 0;
+        S.flags = BF_INNER;
+    } else if (phase == PH_INNER && (f & BF_INNER)) {
+        S.it += 1;
+        S.cycles += 1;
+        S.first = 0;
+        if (!isfinite(S.r32) || S.r32 <= P.inner_reduction * S.dn || S.it >= P.inner_max)
+            S.flags = BF_UPDATE;
+    }
+}
+
+// Norm of each problem in the phase from its partials (fixed order), into a
+// state field, and the problem's transition.  The inner residual (K_S32)
+// of a problem with more than dev::RED_SEG partials adds the segment sums of
+// kb_segsum (the same order as summing the partials here).
 __device__ void finalize_items(const BProb* __restrict__ probs, BState* __restrict__ state,
                                const int* __restrict__ wl, int kind, int field, int mask,
-                               int fused_above) {
+                               int fused_above, int phase) {
     const int total = wl_total(wl);
     for (int t = blockIdx.x; t < total; t += gridDim.x) {
         int p, tile;
@@ -474,76 +522,33 @@ __device__ void finalize_items(const BProb* __restrict__ probs, BState* __restri
                 S.dn = r;
             else
                 S.r32 = r;
+            transition(P, S, phase);
         }
     }
 }
 
-// Per-problem transitions of the mixed scheme (one block; thread per slot):
-// INIT -> OUTER (or DONE), OUTER -> CAST or DONE (a problem whose inner
-// loop ended in this iteration's update counts its outer step first), CAST
-// -> INNER, INNER -> INNER or UPDATE.
-// At the end of an iteration (PH_INNER) also reports to the host, in entry
-// k mod ITER_RING of the pinned ring (k = iterations so far; entries of
-// 2 + cap ints): the problems not done, those still in their inner loop,
-// which cannot finish in the next iteration (a problem finishes only at an
-// outer step), and every slot's flags (0 for an empty slot).
-__device__ void ctrl_all(const BProb* __restrict__ probs, BState* __restrict__ state, int cap,
-                         int phase, int* __restrict__ iter, int* __restrict__ ring) {
+// After a phase's transitions (one block; thread per slot): the union of
+// every live problem's flags into state[cap] (the early exit of the stage
+// kernels), and at the end of an iteration (PH_INNER) the report to the
+// host, in entry k mod ITER_RING of the pinned ring (k = iterations so far;
+// entries of 2 + cap ints): the problems not done, those still in their
+// inner loop, which cannot finish in the next iteration (a problem finishes
+// only at an outer step), and every slot's flags (0 for an empty slot).
+__device__ void report_all(const BProb* __restrict__ probs, BState* __restrict__ state, int cap,
+                           int phase, int* __restrict__ iter, int* __restrict__ ring) {
     int live = 0, sure = 0, present = 0;
     int* entry = nullptr;
     if (phase == PH_INNER) entry = ring + (int64_t)(*iter % ITER_RING) * (2 + cap);
     for (int p = threadIdx.x; p < cap; p += BLOCK) {
-        const BProb& P = probs[p];
-        if (P.L == 0) {
+        if (probs[p].L == 0) {
             if (entry) entry[2 + p] = 0;
             continue;
         }
-        BState& S = state[p];
-        const int f = S.flags;
-        if (phase == PH_INIT && (f & BF_INIT)) {
-            if (!isfinite(S.bn)) {
-                S.status = MG_ERR_NUMERIC;
-                S.flags = BF_DONE;
-            } else if (S.bn == 0.0) {
-                S.status = MG_OK;
-                S.flags = BF_DONE;
-            } else {
-                S.flags = BF_OUTER;
-            }
-        } else if (phase == PH_OUTER && (f & (BF_OUTER | BF_UPDATE))) {
-            if (f & BF_UPDATE) S.outer += 1;  // its update ran in this iteration
-            const int k = S.outer + 1;
-            const double rel = S.s / S.bn;
-            if (k > 1 && S.n_hist < MG_HIST) S.hist[S.n_hist++] = rel;
-            int done = 0;
-            if (!isfinite(S.s) || S.s > 1e3 * S.bn) {
-                S.status = MG_ERR_NUMERIC;
-                done = 1;
-            } else if (P.fixed > 0) {
-                done = k > P.fixed;
-            } else if (S.s <= P.rel_tol * S.bn) {
-                done = 1;
-            } else if (k > P.max_outer) {
-                S.status = MG_ERR_NOCONV;
-                done = 1;
-            }
-            if (!done && S.s == 0.0) done = 1;
-            S.flags = done ? BF_DONE : BF_CAST;
-        } else if (phase == PH_CAST && (f & BF_CAST)) {
-            S.first = 1;
-            S.it = 0;
-            S.flags = BF_INNER;
-        } else if (phase == PH_INNER && (f & BF_INNER)) {
-            S.it += 1;
-            S.cycles += 1;
-            S.first = 0;
-            if (!isfinite(S.r32) || S.r32 <= P.inner_reduction * S.dn || S.it >= P.inner_max)
-                S.flags = BF_UPDATE;
-        }
-        if (!(S.flags & BF_DONE)) ++live;
-        if (S.flags == BF_INNER) ++sure;
-        present |= S.flags;
-        if (entry) entry[2 + p] = S.flags;
+        const int f = state[p].flags;
+        if (!(f & BF_DONE)) ++live;
+        if (f == BF_INNER) ++sure;
+        present |= f;
+        if (entry) entry[2 + p] = f;
     }
     {
         __shared__ int wor[BLOCK / 64];
@@ -571,10 +576,11 @@ __device__ void ctrl_all(const BProb* __restrict__ probs, BState* __restrict__ s
     }
 }
 
-// The norms of a phase (finalize_items), then, in the block that finishes
-// last (an integer ticket counts the finished blocks; fences order every
-// block's norms before its ticket and the last block's reads after it), the
-// phase's transitions (ctrl_all).  The ticket is back to zero after.
+// The norms of a phase and each problem's transition (finalize_items),
+// then, in the block that finishes last (an integer ticket counts the
+// finished blocks; fences order every block's writes before its ticket and
+// the last block's reads after it), the flags' union and the report
+// (report_all).  The ticket is back to zero after.
 __global__ __launch_bounds__(BLOCK) void kb_finctl(const BProb* __restrict__ probs,
                                                    BState* __restrict__ state,
                                                    const int* __restrict__ wl, int kind,
@@ -582,8 +588,8 @@ __global__ __launch_bounds__(BLOCK) void kb_finctl(const BProb* __restrict__ pro
                                                    int phase, int* __restrict__ iter,
                                                    int* __restrict__ ring,
                                                    unsigned* __restrict__ ticket) {
-    if (state[wl[1]].flags & mask) finalize_items(probs, state, wl, kind, field, mask,
-                                                  fused_above);
+    if (state[wl[1]].flags & mask)
+        finalize_items(probs, state, wl, kind, field, mask, fused_above, phase);
     __shared__ unsigned last;
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -593,7 +599,7 @@ __global__ __launch_bounds__(BLOCK) void kb_finctl(const BProb* __restrict__ pro
     __syncthreads();
     if (!last) return;
     __threadfence();
-    ctrl_all(probs, state, wl[1], phase, iter, ring);
+    report_all(probs, state, wl[1], phase, iter, ring);
     if (threadIdx.x == 0) *ticket = 0u;
 }
 
