@@ -38,6 +38,21 @@ constexpr int tile_rows() {
 // Elements per reduction tile of a plain vector norm.
 constexpr int NORM_TILE = BLOCK * 4;
 
+// The damped Jacobi correction num / a_pp (num = omega (b - A x)): FP64
+// divides; FP32 multiplies by the hardware reciprocal of a_pp (within one
+// ulp of it; the FP32 sweeps are the inner solver of the mixed scheme, whose
+// result the FP64 defect correction checks and corrects).  Every FP32
+// Jacobi sweep (tile kernels, fused passes, coarse tail, batch) uses it, so
+// they all give the same bits.
+template <typename T>
+__device__ __forceinline__ T jacobi_div(T num, T diag) {
+    return num / diag;
+}
+template <>
+__device__ __forceinline__ float jacobi_div<float>(float num, float diag) {
+    return num * __builtin_amdgcn_rcpf(diag);
+}
+
 // Deterministic block sum (wave shuffles, then the waves in order); the
 // result is valid in thread 0.  Every thread of the block must call it; it
 // may be called repeatedly in a loop.
@@ -142,7 +157,7 @@ __device__ __forceinline__ double stencil_tile(const T* __restrict__ bands, int6
             if (OP == OP_DEFECT)
                 res[v] = bb[v] - res[v];
             else
-                res[v] = xv[1][v + 1] + omega * (bb[v] - res[v]) / bk[4][v];
+                res[v] = xv[1][v + 1] + jacobi_div(omega * (bb[v] - res[v]), bk[4][v]);
         }
     }
     if (NORM) {
@@ -169,7 +184,7 @@ template <typename T>
 __device__ __forceinline__ void jacobi_zero_elem(const T* __restrict__ diag,
                                                  const T* __restrict__ b, T* __restrict__ xo,
                                                  int64_t p, T omega) {
-    xo[p] = omega * b[p] / diag[p];
+    xo[p] = jacobi_div(omega * b[p], diag[p]);
 }
 
 // Dirichlet sides (bit 1: x = 0, bit 2: x = 1, bit 4: y = 0, bit 8: y = 1);

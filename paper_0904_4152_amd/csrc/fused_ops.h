@@ -298,10 +298,10 @@ __device__ void pre_tile(const T* __restrict__ bands, int64_t bs, int N, const T
             {
                 T v;
                 if (XZERO) {
-                    v = omega * bb[b1] / bk[b1][4];
+                    v = jacobi_div(omega * bb[b1], bk[b1][4]);
                 } else {
                     const T acc = band_row_product(bk[b1], X[l2], X[l1], X[x3], t);
-                    v = X[l1][t] + omega * (bb[b1] - acc) / bk[b1][4];
+                    v = X[l1][t] + jacobi_div(omega * (bb[b1] - acc), bk[b1][4]);
                 }
                 A[l1][t] = (c_op1 & in_win(j1, lo1, hi1)) ? v : T(0);
             }
@@ -317,7 +317,7 @@ __device__ void pre_tile(const T* __restrict__ bands, int64_t bs, int N, const T
             // second sweep at row j2 (written on owned nodes)
             {
                 const T acc = band_row_product(bk[b2], A[x3], A[l2], A[l1], t);
-                T v = A[l2][t] + omega * (bb[b2] - acc) / bk[b2][4];
+                T v = A[l2][t] + jacobi_div(omega * (bb[b2] - acc), bk[b2][4]);
                 v = (c_op2 & in_win(j2, lo2, hi2)) ? v : T(0);
                 if (in_win(j2, r0, r1) && c_own) x2out[(int64_t)j2 * N + col] = v;
                 B[l2][t] = v;
@@ -476,13 +476,13 @@ __device__ void post_tile(const T* __restrict__ bands, int64_t bs, int N, const 
             // sweep's window select zero): no divergent branches
             {
                 const T acc = band_row_product(bk[b1], X[l2], X[l1], X[x3], t);
-                const T v = X[l1][t] + omega * (bb[b1] - acc) / bk[b1][4];
+                const T v = X[l1][t] + jacobi_div(omega * (bb[b1] - acc), bk[b1][4]);
                 A[l1][t] = (c_op1 & in_win(j1, lo1, hi1)) ? v : T(0);
             }
             __syncthreads();
             {
                 const T acc = band_row_product(bk[b2], A[x3], A[l2], A[l1], t);
-                T v = A[l2][t] + omega * (bb[b2] - acc) / bk[b2][4];
+                T v = A[l2][t] + jacobi_div(omega * (bb[b2] - acc), bk[b2][4]);
                 v = (c_op2 & in_win(j2, lo2, hi2)) ? v : T(0);
                 if (in_win(j2, r0, r1) && c_own) xout[(int64_t)j2 * N + col] = v;
                 if (NORM) B[l2][t] = v;
@@ -586,7 +586,7 @@ template <typename T>
 __device__ __forceinline__ void tail_jacobi(const TailLds<T>& v, const T* x, T* xo, T omega) {
     for (int p = threadIdx.x; p < v.n; p += TAIL_THREADS) {
         const T acc = tail_product(v, x, p);
-        xo[p] = x[p] + omega * (v.b[p] - acc) / v.bands[4 * v.n + p];
+        xo[p] = x[p] + jacobi_div(omega * (v.b[p] - acc), v.bands[4 * v.n + p]);
     }
 }
 
