@@ -1199,6 +1199,7 @@ mg_status BatchEngine::step(int* active_left) {
 // the device does not idle between iterations; at outer steps the host
 // waits for the decision.  No iteration is queued that is not needed.
 mg_status BatchEngine::run(int64_t iter_cap, int64_t* iterations) {
+    const TraceRange trace("batch iterations");
     MG_HIP(hipSetDevice(device_));
     if (mg_status s = ensure_graph()) return s;
     const int64_t first = launched_;
@@ -1347,6 +1348,7 @@ EnginePool& engine_pool() {
 extern "C" mg_status mg_solve_batch(mg_hierarchy* const* hs, const double* const* b,
                                     double* const* x, int count, const mg_solve_opts* opts,
                                     void* stream, mg_stats* stats) {
+    const TraceRange trace("mg_solve_batch");
     if (!hs || !b || !x || count < 1) return fail(MG_ERR_INVALID, "empty or null batch");
     mg_solve_opts def;
     mg_default_opts(&def);

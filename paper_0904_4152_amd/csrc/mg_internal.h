@@ -11,6 +11,8 @@
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "device_ops.h"
 #include "mgfem.h"
 
@@ -65,6 +67,17 @@ struct mg_context {
     bool reserve(size_t bytes);
     void release(size_t bytes);
 };
+
+namespace mg {
+// A named host range in profiler traces (rocprofv3 --marker-trace): the
+// span of a solve, an outer step, an iteration, a host wait.
+struct TraceRange {
+    explicit TraceRange(const char* name) { roctxRangePushA(name); }
+    ~TraceRange() { roctxRangePop(); }
+    TraceRange(const TraceRange&) = delete;
+    TraceRange& operator=(const TraceRange&) = delete;
+};
+}  // namespace mg
 
 struct GraphCache;  // defined in solve.hip
 

@@ -71,7 +71,10 @@ public:
         return MG_OK;
     }
     mg_status upload() override { return eng_.upload_async(); }
-    mg_status launch_iteration() override { return eng_.launch_iteration(); }
+    mg_status launch_iteration() override {
+        const TraceRange trace("serve iteration launch");
+        return eng_.launch_iteration();
+    }
     int64_t launched() const override { return eng_.launched(); }
     mg_status wait_iteration(int64_t k, const int** done) override {
         int nlive = 0, sure = 0;

@@ -332,6 +332,7 @@ static void arm_scalar(mg_hierarchy* h, int slot) {
 }
 
 static hipError_t read_scalar(mg_hierarchy* h, int slot, hipStream_t st, double* out) {
+    const TraceRange trace("host waits for a norm");
     const volatile double* v = (const volatile double*)h->host_scal + slot + 1;
     const auto t0 = std::chrono::steady_clock::now();
     for (unsigned i = 1;; ++i) {
@@ -354,6 +355,7 @@ static hipError_t read_scalar(mg_hierarchy* h, int slot, hipStream_t st, double*
 static void arm_iter(mg_hierarchy* h) { ((volatile double*)h->host_scal)[SC_ITER] = kArmed; }
 
 static hipError_t read_iter(mg_hierarchy* h, int want, hipStream_t st, int* cycles, bool* done) {
+    const TraceRange trace("host waits for the inner loop");
     const volatile double* v = (const volatile double*)h->host_scal + SC_ITER;
     const auto t0 = std::chrono::steady_clock::now();
     double x = kArmed;
@@ -434,6 +436,7 @@ extern "C" mg_status mg_vcycle(mg_hierarchy* h, int level, mg_dtype dtype, const
 
 extern "C" mg_status mg_solve(mg_hierarchy* h, const double* dev_b, double* dev_x,
                               const mg_solve_opts* opts, void* stream, mg_stats* stats) {
+    const TraceRange trace("mg_solve");
     const auto t0 = std::chrono::steady_clock::now();
     mg_stats st{};
     if (stats) *stats = st;
@@ -636,6 +639,7 @@ extern "C" mg_status mg_solve(mg_hierarchy* h, const double* dev_b, double* dev_
     } else if (!devctl) {
         // host-driven loop: one host read per FP64 defect and per FP32 cycle
         for (int k = 1;; ++k) {
+            const TraceRange step("mixed outer step");
             double s = 0.0;
             arm_scalar(h, SC_R64);
             if (k == 1 && x_zero) {
@@ -704,6 +708,7 @@ extern "C" mg_status mg_solve(mg_hierarchy* h, const double* dev_b, double* dev_
         // overwrites a norm the host has yet to read.
         q.bytes += x_zero ? 16.0 * n : 12.0 * 8 * n;  // the first defect
         for (int k = 1;; ++k) {
+            const TraceRange step("mixed outer step");
             double s = 0.0;
             MG_HIPS(read_scalar(h, nslot(k), q.st, &s));
             st.rel_res = s / bn;
@@ -780,6 +785,7 @@ extern "C" mg_status mg_hierarchy_autotune(mg_hierarchy* h, int reps, mg_tile_ch
     if (!h->assembled) return fail(MG_ERR_INVALID, "hierarchy not assembled");
     if (reps < 1 || reps > 1000) return fail(MG_ERR_INVALID, "reps must lie in [1, 1000]");
     if (out_cap < 0 || (out_cap > 0 && !out)) return fail(MG_ERR_INVALID, "bad output array");
+    const TraceRange trace("mg_hierarchy_autotune");
     static const int kRows[] = {4, 8, 16, 32, 64, 128, 256};
     static const int kWidths[] = {64, 128, 192, 256};
     MG_HIP(hipSetDevice(h->ctx->device));
