@@ -235,44 +235,52 @@ mg_status mg_solve_batch(mg_hierarchy* const* hs, const double* const* b, double
 
 /* ---- batched tiles: autotuner ----------------------------------------------
  * Sec. 3: the GPU thread-block partition is a runtime parameter.  The fused
- * passes of the batched solver process each level in tiles of a strip of
- * columns by a number of grid rows, with a workgroup of 1 to 4 wavefronts
- * across a strip's row.  Both come from a process-wide table filled by this
- * autotuner, keyed by level and by the number of problems at that level
- * rounded down to a power of two; levels without an entry use the rules
+ * passes of the batched solver process each level in marching tiles, a
+ * strip of columns by a number of grid rows with a workgroup of 1 to 4
+ * wavefronts across a strip's row, or in block tiles of 8, 16 or 32 rows by
+ * 32 columns (one 256-thread workgroup, the tile and its halo in LDS).  The
+ * choice comes from a process-wide table filled by this autotuner, keyed by
+ * level and by the number of problems at that level rounded down to a power
+ * of two; levels without an entry use marching tiles with the rules
  * "fewest threads per row" (width) and "largest height in 4..64 that still
- * gives about 3500 wavefronts" (rows).  No result bit depends on either: a
- * batched result equals the single solve bit for bit whatever the table
- * holds.  The server applies tuned rows only (a width change would
+ * gives about 3500 wavefronts" (rows).  No result bit depends on the tiles:
+ * a batched result equals the single solve bit for bit whatever the table
+ * holds.  The server applies tuned rows only (a width or shape change would
  * re-capture its iteration graph while its mix changes).
  * mg_batch_autotune: for the composition of these problems (options as for
  * mg_solve_batch; NULL: defaults), times the fused pre- and post-smoothing
  * passes of every level for each of 4, 8, 16, 32, 64 rows per tile and 1, 2,
- * 3, 4 wavefronts per row (reps pairs each, on the problems' FP32 work
- * vectors, which no later solve reads before writing), stores the fastest in
- * the table and writes up to out_cap choices to out (*n_out = choices).
+ * 3, 4 wavefronts per row, and on levels of at most 1025 nodes per side for
+ * each block tile (reps pairs each, on the problems' FP32 work vectors,
+ * which no later solve reads before writing), stores the fastest in the
+ * table and writes up to out_cap choices to out (*n_out = choices).
  * Synchronous; thread safe with respect to other batches on separate
  * hierarchies.  Only V(2,2) cycles have tiles.
- * mg_batch_set_tile: installs one entry (e.g. read back from a file);
- * tile_rows a power of two in [4, 256], row_waves in 1..4, or 0 for the
- * width rule.  mg_batch_clear_tiles: empties the table. */
+ * mg_batch_set_tile: installs one entry (e.g. read back from a file): with
+ * tile_cols = 0 a marching tile, tile_rows a power of two in [4, 256],
+ * row_waves in 1..4 or 0 for the width rule; with tile_cols = 32 a block
+ * tile, tile_rows 8, 16 or 32, row_waves 0 or 4.  mg_batch_clear_tiles:
+ * empties the table. */
 typedef struct {
     int level;
     int problems;     /* problems at this level in the tuned composition */
     int tile_rows;    /* chosen rows per tile */
-    int row_waves;    /* chosen wavefronts across a strip's row (workgroup width / 64) */
+    int row_waves;    /* chosen wavefronts per workgroup (across a strip's row when marching) */
+    int tile_cols;    /* 0: marching tile; else columns of a block tile */
     double us;        /* one pre + post pass pair with that tile, microseconds */
 } mg_tile_choice;
 mg_status mg_batch_autotune(mg_hierarchy* const* hs, int count, const mg_solve_opts* opts,
                             int reps, mg_tile_choice* out, int out_cap, int* n_out);
-mg_status mg_batch_set_tile(int level, int problems, int tile_rows, int row_waves);
+mg_status mg_batch_set_tile(int level, int problems, int tile_rows, int row_waves,
+                            int tile_cols);
 mg_status mg_batch_clear_tiles(void);
 /* The same tuning for the single-problem solver (mg_solve, mg_vcycle and
  * the fused-pass entry points read the table's entries for one problem): for
  * every level on which h's V(2,2) cycle runs fused passes, times the FP32
  * pre- and post-smoothing passes as the mixed solve runs them (reps pairs
  * per candidate, on h's FP32 work vectors) for 4 .. 256 rows per tile and 1
- * .. 4 wavefronts per row, and stores the fastest under problems = 1.  Tiles
+ * .. 4 wavefronts per row, and on levels of at most 1025 nodes per side for
+ * each block tile, and stores the fastest under problems = 1.  Tiles
  * change no result bit; solves captured before are captured again.
  * Synchronous; not thread safe per hierarchy. */
 mg_status mg_hierarchy_autotune(mg_hierarchy* h, int reps, mg_tile_choice* out, int out_cap,

@@ -36,7 +36,7 @@ class SolveOpts(ctypes.Structure):
 
 class TileChoice(ctypes.Structure):
     _fields_ = [("level", _i), ("problems", _i), ("tile_rows", _i), ("row_waves", _i),
-                ("us", _d)]
+                ("tile_cols", _i), ("us", _d)]
 
 
 class Stats(ctypes.Structure):
@@ -103,7 +103,7 @@ _SIGS = {
                               ctypes.POINTER(_vp), _vp, _vp, _vp, _vp]),
     "mg_batch_autotune": (_i, [ctypes.POINTER(_vp), _i, ctypes.POINTER(SolveOpts), _i,
                                ctypes.POINTER(TileChoice), _i, ctypes.POINTER(_i)]),
-    "mg_batch_set_tile": (_i, [_i, _i, _i, _i]),
+    "mg_batch_set_tile": (_i, [_i, _i, _i, _i, _i]),
     "mg_batch_clear_tiles": (_i, []),
     "mg_hierarchy_autotune": (_i, [_vp, _i, ctypes.POINTER(TileChoice), _i, ctypes.POINTER(_i)]),
     "mg_solve_batch": (_i, [ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp), _i,
@@ -379,9 +379,7 @@ class Hierarchy:
         out = (TileChoice * 16)()
         got = _i()
         check(lib().mg_hierarchy_autotune(self._h, reps, out, 16, ctypes.byref(got)))
-        return [{"level": out[i].level, "problems": out[i].problems,
-                 "tile_rows": out[i].tile_rows, "row_waves": out[i].row_waves, "us": out[i].us}
-                for i in range(min(got.value, 16))]
+        return [_choice(out[i]) for i in range(min(got.value, 16))]
 
     def vcycle(self, level, b, x, nu_pre=2, nu_post=2, omega=0.7, fused=None, stream=None):
         if fused is None:
@@ -390,27 +388,31 @@ class Hierarchy:
                               int(fused), _stream(stream)))
 
 
+def _choice(c):
+    return {"level": c.level, "problems": c.problems, "tile_rows": c.tile_rows,
+            "row_waves": c.row_waves, "tile_cols": c.tile_cols, "us": c.us}
+
+
 def batch_autotune(hierarchies, opts=None, reps=10):
-    """Tune the batched solver's tiles (rows and wavefronts per row) for this
-    composition; returns the choices as dicts (level, problems, tile_rows,
-    row_waves, us)."""
+    """Tune the batched solver's tiles (marching tiles: rows and wavefronts
+    per row; block tiles: rows and columns) for this composition; returns the
+    choices as dicts (level, problems, tile_rows, row_waves, tile_cols, us)."""
     n = len(hierarchies)
     hs = (_vp * n)(*[h.handle for h in hierarchies])
     out = (TileChoice * 16)()
     got = _i()
     check(lib().mg_batch_autotune(hs, n, ctypes.byref(opts) if opts is not None else None, reps,
                                   out, 16, ctypes.byref(got)))
-    return [{"level": out[i].level, "problems": out[i].problems,
-             "tile_rows": out[i].tile_rows, "row_waves": out[i].row_waves, "us": out[i].us}
-            for i in range(min(got.value, 16))]
+    return [_choice(out[i]) for i in range(min(got.value, 16))]
 
 
 def batch_set_tiles(rows):
     """Install tile choices (the rows batch_autotune returns, e.g. from JSON;
-    a missing row_waves keeps the width rule)."""
+    a missing row_waves keeps the width rule, a missing tile_cols means a
+    marching tile)."""
     for r in rows:
         check(lib().mg_batch_set_tile(int(r["level"]), int(r["problems"]), int(r["tile_rows"]),
-                                      int(r.get("row_waves", 0))))
+                                      int(r.get("row_waves", 0)), int(r.get("tile_cols", 0))))
 
 
 def batch_clear_tiles():

@@ -26,6 +26,7 @@ struct BLevel {
     int bt;        // threads per fused workgroup
     int nstrips;   // fused tiles: nstrips x nchunks
     int nchunks;
+    int blk;       // 0: marching tiles; else the block tile shape
 };
 
 struct BProb {
@@ -167,8 +168,11 @@ private:
     double step_bytes_ = 0.0;
     int rh_override_[MG_MAX_LEVEL + 1] = {};  // tile heights under trial (0: none)
     int bt_override_[MG_MAX_LEVEL + 1] = {};  // workgroup widths under trial (0: none)
+    int cols_override_[MG_MAX_LEVEL + 1] = {};  // block tile columns under trial (0: march)
     int bt_[MG_MAX_LEVEL + 1] = {};           // workgroup width of each level's fused passes
     int graph_bt_[MG_MAX_LEVEL + 1] = {};     // the widths the captured graph launches
+    int blk_[MG_MAX_LEVEL + 1] = {};          // block tile shape of each level's fused passes (0: march)
+    int graph_blk_[MG_MAX_LEVEL + 1] = {};    // the shapes the captured graph launches
     bool tuned_widths_ = true;
 };
 

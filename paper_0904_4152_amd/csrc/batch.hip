@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <cmath>
 #include <cstring>
@@ -272,6 +273,49 @@ __global__ __launch_bounds__(BT) void kb_fpost(const BProb* __restrict__ probs,
     else
         dev::post_tile<float, false, BT>(lv.bands32, lv.bs, lv.N, lv.t32, P.lv[l - 1].x32,
                                          lv.b32, om, lv.x32, nullptr, strip, chunk, lv.rh, lv.cw);
+    END_ITEMS
+}
+
+// The same passes in block tiles of BR x BC owned nodes.
+template <int BR, int BC>
+__global__ __launch_bounds__(dev::BLK_THREADS) void kb_fpre_blk(const BProb* __restrict__ probs,
+                                                               const BState* __restrict__ state,
+                                                               const int* __restrict__ wl, int l,
+                                                               int mask) {
+    __shared__ dev::BlockLds<float, BR, BC> s;
+    FOR_ITEMS(wl)
+    if (!(flags & mask)) continue;
+    const BLevel& lv = P.lv[l];
+    const int strip = tile % lv.nstrips, chunk = tile / lv.nstrips;
+    const float om = (float)P.omega;
+    if (l < P.L || state[p].first)
+        dev::pre_block<float, true, BR, BC>(s, lv.bands32, lv.bs, lv.N, lv.x32, lv.b32, om,
+                                            lv.t32, P.lv[l - 1].b32, P.dmask, strip, chunk);
+    else
+        dev::pre_block<float, false, BR, BC>(s, lv.bands32, lv.bs, lv.N, lv.x32, lv.b32, om,
+                                             lv.t32, P.lv[l - 1].b32, P.dmask, strip, chunk);
+    END_ITEMS
+}
+
+template <int BR, int BC>
+__global__ __launch_bounds__(dev::BLK_THREADS) void kb_fpost_blk(const BProb* __restrict__ probs,
+                                                                const BState* __restrict__ state,
+                                                                const int* __restrict__ wl, int l,
+                                                                int mask) {
+    __shared__ dev::BlockLds<float, BR, BC> s;
+    FOR_ITEMS(wl)
+    if (!(flags & mask)) continue;
+    const BLevel& lv = P.lv[l];
+    const int strip = tile % lv.nstrips, chunk = tile / lv.nstrips;
+    const float om = (float)P.omega;
+    if (l == P.L)
+        dev::post_block<float, true, BR, BC>(s, lv.bands32, lv.bs, lv.N, lv.t32,
+                                             P.lv[l - 1].x32, lv.b32, om, lv.x32, P.partials,
+                                             strip, chunk);
+    else
+        dev::post_block<float, false, BR, BC>(s, lv.bands32, lv.bs, lv.N, lv.t32,
+                                              P.lv[l - 1].x32, lv.b32, om, lv.x32, nullptr, strip,
+                                              chunk);
     END_ITEMS
 }
 
@@ -706,6 +750,7 @@ void BatchEngine::set_slot(int s, mg_hierarchy* h, const mg_solve_opts& o) {
         b.bt = g.bt;
         b.nstrips = g.nstrips;
         b.nchunks = g.nchunks;
+        b.blk = 0;
     }
     P.d64 = h->d64;
     P.partials = h->partials;
@@ -754,13 +799,13 @@ TileEntry tile_table_get(int level, int64_t problems) {
     TileTable& t = tile_table();
     std::lock_guard<std::mutex> g(t.mu);
     auto it = t.rows.find({level, log2_floor(problems)});
-    return it == t.rows.end() ? TileEntry{0, 0} : it->second;
+    return it == t.rows.end() ? TileEntry{0, 0, 0} : it->second;
 }
 
-void tile_table_set(int level, int64_t problems, int rows, int bt) {
+void tile_table_set(int level, int64_t problems, int rows, int bt, int cols) {
     TileTable& t = tile_table();
     std::lock_guard<std::mutex> g(t.mu);
-    t.rows[{level, log2_floor(problems)}] = {rows, bt};
+    t.rows[{level, log2_floor(problems)}] = {rows, bt, cols};
     ++t.epoch;
 }
 
@@ -819,8 +864,11 @@ void BatchEngine::build_lists() {
         if (!bt) bt = fused_bt(N);
         int rh = rh_override_[l] ? rh_override_[l] : te.rows;
         if (!rh) rh = fused_rh(N, bt, count);
-        const dev::FusedGeom g = dev::fused_geom(N, bt, rh);
-        bt_[l] = bt;
+        const int cols = rh_override_[l] ? cols_override_[l] : (tuned_widths_ ? te.cols : 0);
+        const int shape = cols ? dev::block_shape(rh, cols) : 0;
+        const dev::FusedGeom g = shape ? dev::block_geom(N, shape) : dev::fused_geom(N, bt, rh);
+        bt_[l] = g.bt;
+        blk_[l] = g.blk;
         for (int s = 0; s < cap_; ++s) {
             if (hp_[s].L == 0 || !fused_here(hp_[s], l)) continue;
             BLevel& v = hp_[s].lv[l];
@@ -829,6 +877,7 @@ void BatchEngine::build_lists() {
             v.bt = g.bt;
             v.cw = g.cw;
             v.nstrips = g.nstrips;
+            v.blk = g.blk;
         }
     }
     for (int l = Lc_ + 1; l <= Lmax_; ++l) {
@@ -867,7 +916,7 @@ void BatchEngine::build_lists() {
     if (h_wl_[(size_t)WL_SEGS32 * stride] > 0) need |= 1u << 31;
     bool widths_changed = false;
     for (int l = Lc_ + 1; l <= Lmax_; ++l)
-        if (bt_[l] != graph_bt_[l]) widths_changed = true;
+        if (bt_[l] != graph_bt_[l] || blk_[l] != graph_blk_[l]) widths_changed = true;
     if ((need & ~launch_mask_) || widths_changed) {
         launch_mask_ |= need;
         for (hipGraphExec_t& g : graph_) {
@@ -969,6 +1018,23 @@ hipError_t BatchEngine::launch_fused(int l, bool pre, int mask) {
     const int stride = 3 + 2 * cap_;
     const int* wl = d_wl_ + (size_t)wl_fused(l) * stride;
     const int bt = bt_[l];
+    if (blk_[l]) {
+        const dim3 GB(STAGE_GRID), BB(dev::BLK_THREADS);
+#define BLK(BR)                                                                                 \
+    if (pre)                                                                                    \
+        hipLaunchKernelGGL((kb_fpre_blk<BR, dev::BLK_COLS>), GB, BB, 0, st_, d_probs_, d_state_, \
+                           wl, l, mask);                                                        \
+    else                                                                                        \
+        hipLaunchKernelGGL((kb_fpost_blk<BR, dev::BLK_COLS>), GB, BB, 0, st_, d_probs_,          \
+                           d_state_, wl, l, mask);
+        switch (blk_[l]) {
+            case 1: BLK(8) break;
+            case 2: BLK(16) break;
+            default: BLK(32) break;
+        }
+#undef BLK
+        return hipGetLastError();
+    }
     const dim3 GF(STAGE_GRID * (dev::F_MAX_THREADS / bt)), BF(bt);
 #define ONE(BT)                                                                              \
     if (pre)                                                                                 \
@@ -1004,15 +1070,25 @@ mg_status BatchEngine::tune(int reps, std::vector<mg_tile_choice>* out) {
     for (int l = Lc_ + 1; l <= Lmax_; ++l) {
         const int count = problems_at(l);
         if (count == 0) continue;
-        int best = 0, best_bt = 0;
+        int best = 0, best_bt = 0, best_cols = 0;
         float best_ms = 0.0f;
-        for (int bt : kWidths) {
-            for (int rh : kRows) {
+        // marching tiles (width x rows), then block tiles on levels of at
+        // most BLK_MAX_N nodes per side
+        std::vector<std::array<int, 3>> cand;
+        for (int bt : kWidths)
+            for (int rh : kRows) cand.push_back({bt, rh, 0});
+        if ((1 << l) + 1 <= dev::BLK_MAX_N)
+            for (int s = 1; s <= dev::BLK_SHAPES; ++s)
+                cand.push_back({dev::BLK_THREADS, dev::block_rows(s), dev::BLK_COLS});
+        for (const auto& c : cand) {
+            {
+                const int bt = c[0], rh = c[1];
                 rh_override_[l] = rh;
                 bt_override_[l] = bt;
+                cols_override_[l] = c[2];
                 probs_dirty_ = true;
                 if (mg_status s = upload()) {
-                    rh_override_[l] = bt_override_[l] = 0;
+                    rh_override_[l] = bt_override_[l] = cols_override_[l] = 0;
                     return s;
                 }
                 for (int w = 0; w < 2; ++w) {  // warm-up
@@ -1031,13 +1107,14 @@ mg_status BatchEngine::tune(int reps, std::vector<mg_tile_choice>* out) {
                 if (!best || ms < best_ms) {
                     best = rh;
                     best_bt = bt;
+                    best_cols = c[2];
                     best_ms = ms;
                 }
             }
         }
-        rh_override_[l] = bt_override_[l] = 0;
-        tile_table_set(l, count, best, best_bt);
-        if (out) out->push_back({l, count, best, best_bt / 64, 1e3 * best_ms / reps});
+        rh_override_[l] = bt_override_[l] = cols_override_[l] = 0;
+        tile_table_set(l, count, best, best_bt, best_cols);
+        if (out) out->push_back({l, count, best, best_bt / 64, best_cols, 1e3 * best_ms / reps});
     }
     probs_dirty_ = true;
     return upload();
@@ -1046,7 +1123,7 @@ mg_status BatchEngine::tune(int reps, std::vector<mg_tile_choice>* out) {
 hipError_t BatchEngine::enqueue_iteration(bool with_init) {
     const int stride = 3 + 2 * cap_;
     auto W = [&](int id) { return (const int*)(d_wl_ + (size_t)id * stride); };
-    const dim3 G(STAGE_GRID), B(BLOCK), G1(1);
+    const dim3 G(STAGE_GRID), B(BLOCK);
     const dim3 GA(std::min(cap_, 1024));
     BProb* P = d_probs_;
     BState* S = d_state_;
@@ -1079,23 +1156,17 @@ hipError_t BatchEngine::enqueue_iteration(bool with_init) {
     const int m = BF_INNER;
     const bool fused = nu_pre_ == 2 && nu_post_ == 2;
     if (fused) {
-#define FUSED(KERNEL, l)                                                                  \
-    {                                                                                     \
-        const int bt = bt_[l];                                                            \
-        const dim3 GF(STAGE_GRID * (dev::F_MAX_THREADS / bt)), BF(bt);                    \
-        switch (bt) {                                                                     \
-            case 64: LAUNCH(KERNEL<64>, GF, BF, 0, st_, P, S, W(wl_fused(l)), l, m); break;   \
-            case 128: LAUNCH(KERNEL<128>, GF, BF, 0, st_, P, S, W(wl_fused(l)), l, m); break; \
-            case 192: LAUNCH(KERNEL<192>, GF, BF, 0, st_, P, S, W(wl_fused(l)), l, m); break; \
-            default: LAUNCH(KERNEL<256>, GF, BF, 0, st_, P, S, W(wl_fused(l)), l, m); break;  \
-        }                                                                                 \
+#define FUSED(pre, l)                                   \
+    {                                                   \
+        const hipError_t e_ = launch_fused(l, pre, m);  \
+        if (e_ != hipSuccess) return e_;                \
     }
         for (int l = Lmax_; l > Lc_; --l)
-            if (launch_mask_ & (1u << l)) FUSED(kb_fpre, l)
+            if (launch_mask_ & (1u << l)) FUSED(true, l)
         LAUNCH(kb_tail, GA, dim3(dev::TAIL_THREADS), 0, st_, P, S, W(WL_ALL), Lc_, m);
         LAUNCH(kb_coarse, GA, B, 0, st_, P, S, W(WL_ALL), Lc_, m, Lc_);
         for (int l = Lc_ + 1; l <= Lmax_; ++l)
-            if (launch_mask_ & (1u << l)) FUSED(kb_fpost, l)
+            if (launch_mask_ & (1u << l)) FUSED(false, l)
 #undef FUSED
         // problems without a level above the coarse one: residual from a defect pass
         if (launch_mask_ & 1u)
@@ -1159,7 +1230,10 @@ mg_status BatchEngine::ensure_graph() {
             return fail(MG_ERR_DEVICE, std::string("batch graph capture: ") + hipGetErrorString(e));
         }
     }
-    for (int l = 0; l <= MG_MAX_LEVEL; ++l) graph_bt_[l] = bt_[l];
+    for (int l = 0; l <= MG_MAX_LEVEL; ++l) {
+        graph_bt_[l] = bt_[l];
+        graph_blk_[l] = blk_[l];
+    }
     return MG_OK;
 }
 
@@ -1492,9 +1566,18 @@ extern "C" mg_status mg_batch_autotune(mg_hierarchy* const* hs, int count,
     return MG_OK;
 }
 
-extern "C" mg_status mg_batch_set_tile(int level, int problems, int tile_rows, int row_waves) {
+extern "C" mg_status mg_batch_set_tile(int level, int problems, int tile_rows, int row_waves,
+                                       int tile_cols) {
     if (level < 2 || level > MG_MAX_LEVEL) return fail(MG_ERR_INVALID, "level outside [2, 14]");
     if (problems < 1) return fail(MG_ERR_INVALID, "problems must be >= 1");
+    if (tile_cols) {
+        if (!dev::block_shape(tile_rows, tile_cols))
+            return fail(MG_ERR_INVALID, "a block tile is 8, 16 or 32 rows by 32 columns");
+        if (row_waves != 0 && row_waves != dev::BLK_THREADS / 64)
+            return fail(MG_ERR_INVALID, "a block tile has 4 wavefronts (row_waves 0 or 4)");
+        tile_table_set(level, problems, tile_rows, dev::BLK_THREADS, tile_cols);
+        return MG_OK;
+    }
     if (tile_rows < 4 || tile_rows > 256 || (tile_rows & (tile_rows - 1)))
         return fail(MG_ERR_INVALID, "tile_rows must be a power of two in [4, 256]");
     if (row_waves < 0 || row_waves > dev::F_MAX_THREADS / 64)

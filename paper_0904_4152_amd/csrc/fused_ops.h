@@ -48,6 +48,7 @@ struct FusedGeom {
     int nstrips;  // strips of cw columns (the last one may be narrower)
     int nchunks;  // chunks of rh rows
     int rh;       // owned rows per chunk (even)
+    int blk;      // 0: marching tiles; else a block tile shape (block_geom)
 };
 
 // Strips of equal width (rounded up to a multiple of F_NORM_COLS) as few as
@@ -61,6 +62,32 @@ __host__ __device__ inline FusedGeom fused_geom(int N, int bt, int rh) {
     g.cw = (N + g.nstrips - 1) / g.nstrips;
     g.cw = (g.cw + F_NORM_COLS - 1) / F_NORM_COLS * F_NORM_COLS;
     g.nchunks = (N + rh - 1) / rh;
+    g.blk = 0;
+    return g;
+}
+
+// Block tiles (see pre_block): shape s in 1..BLK_SHAPES owns 4 << s rows
+// (8, 16 or 32) by BLK_COLS columns; 0 is no block shape.
+constexpr int BLK_SHAPES = 3;
+constexpr int BLK_COLS = 32;
+// Largest level side the autotuners try block tiles on: above it the halo
+// (at least 0.9 x the owned nodes recomputed) outweighs the shorter chain.
+constexpr int BLK_MAX_N = 1025;
+__host__ __device__ constexpr int block_rows(int shape) { return 4 << shape; }
+__host__ __device__ inline int block_shape(int rows, int cols) {
+    if (cols != BLK_COLS) return 0;
+    for (int s = 1; s <= BLK_SHAPES; ++s)
+        if (rows == block_rows(s)) return s;
+    return 0;
+}
+__host__ __device__ inline FusedGeom block_geom(int N, int shape) {
+    FusedGeom g;
+    g.bt = 256;
+    g.rh = block_rows(shape);
+    g.cw = BLK_COLS;
+    g.nstrips = (N + g.cw - 1) / g.cw;
+    g.nchunks = (N + g.rh - 1) / g.rh;
+    g.blk = shape;
     return g;
 }
 
@@ -505,6 +532,295 @@ __device__ void post_tile(const T* __restrict__ bands, int64_t bs, int N, const 
     if (NORM && pend >= 0) {
         __syncthreads();
         flush();
+    }
+}
+
+// ---------------------------------------------------------------- block tiles
+// On small levels a marching tile is bound by the latency of its chain of
+// row steps (each step waits on loads issued a few steps earlier), not by
+// bytes.  A block tile of BR x BC owned nodes instead loads its whole region
+// (the owned nodes and F_HALO rows and columns on every side) into LDS at
+// once and runs each fused step over the region, a workgroup barrier
+// between steps: one memory latency per pass plus a few steps at LDS
+// latency.  The steps, their windows, the per-node arithmetic and the
+// layout and summation order of the norm partials are those of pre_tile
+// and post_tile, so both kinds of tile give the same bits.
+constexpr int BLK_THREADS = 256;
+
+template <int BR, int BC>
+struct BlockRegion {
+    static constexpr int W = BC + 2 * F_HALO;  // LDS row length
+    static constexpr int H = BR + 2 * F_HALO;
+    static constexpr int E = W * H;
+};
+
+// LDS image of a block region: five band streams, b and two work arrays
+// (each holds two iterates whose lives do not overlap); nodes outside the
+// grid hold zeros.  The post pass also keeps the coarse values around the
+// region (coarse rows r0/2 - 2 .. r0/2 + BR/2 + 2, likewise columns) and,
+// with the norm, each column's sum over a group of rows.  A kernel declares
+// one image and passes it to whichever pass it runs.
+template <typename T, int BR, int BC>
+struct BlockLds {
+    static constexpr int E = BlockRegion<BR, BC>::E;
+    static constexpr int CR = BR / 2 + 5, CC = BC / 2 + 5;
+    T dg[E], u5[E], u6[E], u7[E], u8[E], b[E], p[E], q[E];
+    T sc[CR * CC];
+    double ns[(BR / F_NORM_ROWS) * BC];
+};
+
+// Band product at LDS node e from an LDS iterate: the fma chain of
+// band_row_product, the lower bands taken from the neighbours' upper ones.
+template <typename T, int BR, int BC>
+__device__ __forceinline__ T block_product(const BlockLds<T, BR, BC>& s, const T* __restrict__ x,
+                                           int e) {
+    constexpr int W = BlockRegion<BR, BC>::W;
+    const T bk[9] = {s.u8[e - W - 1], s.u7[e - W], s.u6[e - W + 1], s.u5[e - 1], s.dg[e],
+                     s.u5[e],         s.u6[e],     s.u7[e],         s.u8[e]};
+    T acc = T(0);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) acc = fma(bk[k], x[e + (k / 3 - 1) * W + (k % 3 - 1)], acc);
+    return acc;
+}
+
+// The thread's index, opaque to the compiler: everything derived from it is
+// computed where it is used.  (Inside the batched engine's loop over tiles
+// the compiler would otherwise hoist every per-thread index of every step
+// out of the loop and hold them all in registers.)
+__device__ __forceinline__ int block_tid() {
+    int t = (int)threadIdx.x;
+    asm volatile("" : "+v"(t));
+    return t;
+}
+
+// Runs f(e, j, col) for every node of the owned block widened by h on each
+// side (rows r0-h .. r0+BR+h-1, columns c0-h .. c0+BC+h-1, grid or not),
+// spread over the workgroup's threads (tid: this thread).
+template <int BR, int BC, int h, typename F>
+__device__ __forceinline__ void block_window(int tid, int r0, int c0, F&& f) {
+    constexpr int W = BlockRegion<BR, BC>::W;
+    constexpr int ww = BC + 2 * h, cnt = (BR + 2 * h) * ww;
+#pragma unroll
+    for (int u = 0; u < (cnt + BLK_THREADS - 1) / BLK_THREADS; ++u) {
+        const int i = tid + u * BLK_THREADS;
+        if (cnt % BLK_THREADS == 0 || i < cnt) {
+            const int lr = F_HALO - h + i / ww, lc = F_HALO - h + i % ww;
+            f(lr * W + lc, r0 - F_HALO + lr, c0 - F_HALO + lc);
+        }
+    }
+}
+
+// The region's bands, b and (unless XZERO) iterate into LDS: every load is
+// issued before the first store.
+template <typename T, int BR, int BC, bool WITH_X>
+__device__ __forceinline__ void block_load(BlockLds<T, BR, BC>& s, int tid,
+                                           const T* __restrict__ bands, int64_t bs, int N,
+                                           const T* __restrict__ b, const T* __restrict__ x,
+                                           int r0, int c0) {
+    constexpr int W = BlockRegion<BR, BC>::W, E = BlockRegion<BR, BC>::E;
+    constexpr int U = (E + BLK_THREADS - 1) / BLK_THREADS;
+    const int64_t n = (int64_t)N * N;
+    const RowRsrc<T> R(bands, bs, b, n);
+    const rsrc_t Rx = make_rsrc(x, n * (int64_t)sizeof(T));
+    T r[U][7];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int e = tid + u * BLK_THREADS;
+        const int j = r0 - F_HALO + e / W, col = c0 - F_HALO + e % W;
+        const bool in = e < E && in_range(j, 0, N) && in_range(col, 0, N);
+        const uint32_t o = in ? node_off(j, N, col, sizeof(T)) : OFF_NONE;
+#pragma unroll
+        for (int k = 4; k < 9; ++k) r[u][k - 4] = bload<T>(R.band[k], o);
+        r[u][5] = bload<T>(R.b, o);
+        r[u][6] = WITH_X ? bload<T>(Rx, o) : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int e = tid + u * BLK_THREADS;
+        if (E % BLK_THREADS == 0 || e < E) {
+            s.dg[e] = r[u][0];
+            s.u5[e] = r[u][1];
+            s.u6[e] = r[u][2];
+            s.u7[e] = r[u][3];
+            s.u8[e] = r[u][4];
+            s.b[e] = r[u][5];
+            s.p[e] = r[u][6];
+        }
+    }
+}
+
+// Pre-smoothing block (tile row chunk, column strip): what pre_tile computes
+// for the same owned nodes.
+template <typename T, bool XZERO, int BR, int BC>
+__device__ void pre_block(BlockLds<T, BR, BC>& s, const T* __restrict__ bands, int64_t bs, int N,
+                          const T* __restrict__ x, const T* __restrict__ b, T omega,
+                          T* __restrict__ x2out, T* __restrict__ bc, int dmask, int strip,
+                          int chunk) {
+    constexpr int W = BlockRegion<BR, BC>::W;
+    __syncthreads();  // a workgroup may run several tiles in turn
+    const int tid = block_tid();
+    const int c0 = strip * BC, c1 = min(c0 + BC, N);
+    const int r0 = chunk * BR, r1 = min(r0 + BR, N);
+    block_load<T, BR, BC, !XZERO>(s, tid, bands, bs, N, b, x, r0, c0);
+    __syncthreads();
+    // first sweep (x in p) on the owned nodes widened by 3 -> q
+    block_window<BR, BC, 3>(tid, r0, c0, [&](int e, int j, int col) {
+        const bool w = in_range(j, max(r0 - 3, 0), min(r1 + 3, N)) &&
+                       in_range(col, max(c0 - 3, 0), min(c1 + 3, N));
+        T v;
+        if (XZERO) {
+            v = jacobi_div(omega * s.b[e], s.dg[e]);
+        } else {
+            const T acc = block_product(s, s.p, e);
+            v = s.p[e] + jacobi_div(omega * (s.b[e] - acc), s.dg[e]);
+        }
+        s.q[e] = w ? v : T(0);
+    });
+    __syncthreads();
+    // second sweep (q) widened by 2 -> p, owned nodes to x2out
+    block_window<BR, BC, 2>(tid, r0, c0, [&](int e, int j, int col) {
+        const bool w = in_range(j, max(r0 - 2, 0), min(r1 + 2, N)) &&
+                       in_range(col, max(c0 - 2, 0), min(c1 + 2, N));
+        const T acc = block_product(s, s.q, e);
+        T v = s.q[e] + jacobi_div(omega * (s.b[e] - acc), s.dg[e]);
+        v = w ? v : T(0);
+        if (in_range(j, r0, r1) && in_range(col, c0, c1)) x2out[(int64_t)j * N + col] = v;
+        s.p[e] = v;
+    });
+    __syncthreads();
+    // defect (p) widened by 1 -> q
+    block_window<BR, BC, 1>(tid, r0, c0, [&](int e, int j, int col) {
+        const bool w = in_range(j, max(r0 - 1, 0), min(r1 + 1, N)) &&
+                       in_range(col, max(c0 - 1, 0), min(c1 + 1, N));
+        const T acc = block_product(s, s.p, e);
+        s.q[e] = w ? s.b[e] - acc : T(0);
+    });
+    __syncthreads();
+    // restriction to the owned coarse nodes
+    const int Nc = (N >> 1) + 1;
+    constexpr int CW = BC / 2, CN = (BR / 2) * (BC / 2);
+#pragma unroll
+    for (int u = 0; u < (CN + BLK_THREADS - 1) / BLK_THREADS; ++u) {
+        const int i = tid + u * BLK_THREADS;
+        const int j = r0 + 2 * (i / CW), col = c0 + 2 * (i % CW);
+        if ((CN % BLK_THREADS == 0 || i < CN) && j < r1 && col < c1) {
+            const int e = (j - r0 + F_HALO) * W + (col - c0 + F_HALO);
+            const T* u = s.q + e - W;  // row j - 1
+            const T* c = s.q + e;      // row j
+            const T* o = s.q + e + W;  // row j + 1
+            const T corner = (u[-1] + u[1]) + (o[-1] + o[1]);
+            const T edge = (u[0] + o[0]) + (c[-1] + c[1]);
+            const T sres = c[0] + T(0.5) * edge + T(0.25) * corner;
+            const int I = col >> 1, J = j >> 1;
+            bc[(int64_t)J * Nc + I] = is_dirichlet(Nc, I, J, dmask) ? T(0) : sres;
+        }
+    }
+}
+
+// Post-smoothing block: what post_tile computes for the same owned nodes,
+// with NORM the same partial sums of squares.
+template <typename T, bool NORM, int BR, int BC>
+__device__ void post_block(BlockLds<T, BR, BC>& s, const T* __restrict__ bands, int64_t bs, int N,
+                           const T* __restrict__ x, const T* __restrict__ xc,
+                           const T* __restrict__ b, T omega, T* __restrict__ xout,
+                           double* __restrict__ rowpart, int strip, int chunk) {
+    constexpr int CR = BlockLds<T, BR, BC>::CR, CC = BlockLds<T, BR, BC>::CC;
+    T* const sc = s.sc;
+    double* const ns = s.ns;
+    constexpr int H = NORM ? 3 : 2;  // halo the last step needs
+    const int c0 = strip * BC, c1 = min(c0 + BC, N);
+    const int r0 = chunk * BR, r1 = min(r0 + BR, N);
+    const int Nc = (N >> 1) + 1;
+    __syncthreads();  // a workgroup may run several tiles in turn
+    const int tid = block_tid();
+    {
+        const int J0 = r0 / 2 - 2, I0 = c0 / 2 - 2;
+        const rsrc_t Rc = make_rsrc(xc, (int64_t)Nc * Nc * (int64_t)sizeof(T));
+        constexpr int U = (CR * CC + BLK_THREADS - 1) / BLK_THREADS;
+        T r[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = tid + u * BLK_THREADS;
+            const int J = J0 + i / CC, I = I0 + i % CC;
+            const bool in = i < CR * CC && in_range(J, 0, Nc) && in_range(I, 0, Nc);
+            r[u] = bload<T>(Rc, in ? (uint32_t)(J * Nc + I) * (uint32_t)sizeof(T) : OFF_NONE);
+        }
+        block_load<T, BR, BC, true>(s, tid, bands, bs, N, b, x, r0, c0);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = tid + u * BLK_THREADS;
+            if ((CR * CC) % BLK_THREADS == 0 || i < CR * CC) sc[i] = r[u];
+        }
+    }
+    __syncthreads();
+    // x + P x_c on the owned nodes widened by H (the arithmetic of
+    // prolong_elem), in place in p
+    block_window<BR, BC, H>(tid, r0, c0, [&](int e, int j, int col) {
+        const bool use = in_range(j, max(r0 - H, 0), min(r1 + H, N)) &&
+                         in_range(col, max(c0 - H, 0), min(c1 + H, N));
+        const int ci = ((j >> 1) - (r0 / 2 - 2)) * CC + ((col >> 1) - (c0 / 2 - 2));
+        const int cs = use ? ci : 0;
+        const T k0 = sc[cs], k1 = sc[cs + 1], k2 = sc[cs + CC], k3 = sc[cs + CC + 1];
+        const bool c_even = !(col & 1);
+        const T v_row = c_even ? k0 : T(0.5) * (k0 + k1);
+        const T v_odd = c_even ? T(0.5) * (k0 + k2) : T(0.25) * ((k0 + k1) + (k2 + k3));
+        const T v = (j & 1) ? v_odd : v_row;
+        s.p[e] = use ? s.p[e] + v : T(0);
+    });
+    __syncthreads();
+    // first sweep (p) widened by H-1 -> q
+    block_window<BR, BC, H - 1>(tid, r0, c0, [&](int e, int j, int col) {
+        const bool w = in_range(j, max(r0 - (H - 1), 0), min(r1 + (H - 1), N)) &&
+                       in_range(col, max(c0 - (H - 1), 0), min(c1 + (H - 1), N));
+        const T acc = block_product(s, s.p, e);
+        const T v = s.p[e] + jacobi_div(omega * (s.b[e] - acc), s.dg[e]);
+        s.q[e] = w ? v : T(0);
+    });
+    __syncthreads();
+    // second sweep (q) widened by H-2 -> p, owned nodes to xout
+    block_window<BR, BC, H - 2>(tid, r0, c0, [&](int e, int j, int col) {
+        const bool w = in_range(j, max(r0 - (H - 2), 0), min(r1 + (H - 2), N)) &&
+                       in_range(col, max(c0 - (H - 2), 0), min(c1 + (H - 2), N));
+        const T acc = block_product(s, s.q, e);
+        T v = s.q[e] + jacobi_div(omega * (s.b[e] - acc), s.dg[e]);
+        v = w ? v : T(0);
+        if (in_range(j, r0, r1) && in_range(col, c0, c1)) xout[(int64_t)j * N + col] = v;
+        s.p[e] = v;
+    });
+    if (!NORM) return;
+    __syncthreads();
+    // each column's sum of squares over a group of F_NORM_ROWS rows, rows in
+    // increasing order, then the segments' eight column sums
+    constexpr int W = BlockRegion<BR, BC>::W;
+    constexpr int NG = BR / F_NORM_ROWS, NC = NG * BC;
+#pragma unroll
+    for (int u = 0; u < (NC + BLK_THREADS - 1) / BLK_THREADS; ++u) {
+        const int i = tid + u * BLK_THREADS;
+        if (NC % BLK_THREADS == 0 || i < NC) {
+            const int g = i / BC, c = i % BC;
+            const bool own = c0 + c < c1;
+            double acc2 = 0.0;
+#pragma unroll
+            for (int k = 0; k < F_NORM_ROWS; ++k) {
+                const int j = r0 + g * F_NORM_ROWS + k;
+                const int e = (j - r0 + F_HALO) * W + c + F_HALO;
+                const T d = s.b[e] - block_product(s, s.p, e);
+                if (j < r1) acc2 += own ? (double)d * (double)d : 0.0;
+            }
+            ns[i] = acc2;
+        }
+    }
+    __syncthreads();
+    constexpr int NSG = BC / F_NORM_COLS, NP = NG * NSG;
+    const int nseg = (N + F_NORM_COLS - 1) / F_NORM_COLS;
+    if (tid < NP) {
+        const int g = tid / NSG, m = tid % NSG;
+        if (r0 + g * F_NORM_ROWS < r1 && c0 + m * F_NORM_COLS < c1) {
+            const double* v = ns + g * BC + m * F_NORM_COLS;
+            const double s8 =
+                ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
+            rowpart[(int64_t)(r0 / F_NORM_ROWS + g) * nseg + c0 / F_NORM_COLS + m] = s8;
+        }
     }
 }
 

@@ -224,6 +224,31 @@ __global__ __launch_bounds__(BT) void k_post(const T* __restrict__ bands, int64_
                                 (int)(lb % g.nstrips), (int)(lb / g.nstrips), g.rh, g.cw);
 }
 
+// The same passes in block tiles of BR x BC owned nodes.
+template <typename T, bool XZERO, int BR, int BC>
+__global__ __launch_bounds__(dev::BLK_THREADS) void k_pre_blk(
+    const T* __restrict__ bands, int64_t bs, int N, const T* __restrict__ x,
+    const T* __restrict__ b, T omega, T* __restrict__ x2out, T* __restrict__ bc, int dmask,
+    dev::FusedGeom g, const double* __restrict__ guard) {
+    const int64_t lb = xcd_block((int64_t)g.nstrips * g.nchunks);
+    if (lb < 0 || skipped(guard)) return;
+    __shared__ dev::BlockLds<T, BR, BC> s;
+    dev::pre_block<T, XZERO, BR, BC>(s, bands, bs, N, x, b, omega, x2out, bc, dmask,
+                                     (int)(lb % g.nstrips), (int)(lb / g.nstrips));
+}
+
+template <typename T, bool NORM, int BR, int BC>
+__global__ __launch_bounds__(dev::BLK_THREADS) void k_post_blk(
+    const T* __restrict__ bands, int64_t bs, int N, const T* __restrict__ x,
+    const T* __restrict__ xc, const T* __restrict__ b, T omega, T* __restrict__ xout,
+    double* __restrict__ partials, dev::FusedGeom g, const double* __restrict__ guard) {
+    const int64_t lb = xcd_block((int64_t)g.nstrips * g.nchunks);
+    if (lb < 0 || skipped(guard)) return;
+    __shared__ dev::BlockLds<T, BR, BC> s;
+    dev::post_block<T, NORM, BR, BC>(s, bands, bs, N, x, xc, b, omega, xout, partials,
+                                     (int)(lb % g.nstrips), (int)(lb / g.nstrips));
+}
+
 // Coarse tail: the V(2,2) sub-cycle over levels top..Lc in one workgroup.
 template <typename T>
 __global__ __launch_bounds__(dev::TAIL_THREADS) void k_tail(dev::TailLevels<T> tl, T omega,
@@ -964,12 +989,13 @@ int fused_rh(int N, int bt, int64_t count) {
 
 // The autotuner's trial of one level (per thread: the tuner launches from
 // the calling thread only).
-static thread_local int t_trial_N = 0, t_trial_rows = 0, t_trial_bt = 0;
+static thread_local int t_trial_N = 0, t_trial_rows = 0, t_trial_bt = 0, t_trial_cols = 0;
 
-void set_single_trial(int N, int rows, int bt) {
-    t_trial_N = rows && bt ? N : 0;
+void set_single_trial(int N, int rows, int bt, int cols) {
+    t_trial_N = rows && (bt || cols) ? N : 0;
     t_trial_rows = rows;
     t_trial_bt = bt;
+    t_trial_cols = cols;
 }
 
 static int level_of(int N) {
@@ -979,15 +1005,18 @@ static int level_of(int N) {
 }
 
 dev::FusedGeom single_geom(int N) {
-    int bt = 0, rh = 0;
+    int bt = 0, rh = 0, cols = 0;
     if (N == t_trial_N) {
         bt = t_trial_bt;
         rh = t_trial_rows;
+        cols = t_trial_cols;
     } else {
         const TileEntry te = tile_table_get(level_of(N), 1);
         bt = te.bt;
         rh = te.rows;
+        cols = te.cols;
     }
+    if (const int shape = cols ? dev::block_shape(rh, cols) : 0) return dev::block_geom(N, shape);
     if (!bt) bt = fused_bt(N);
     if (!rh) rh = fused_rh(N, bt, 1);
     return dev::fused_geom(N, bt, rh);
@@ -1018,7 +1047,23 @@ hipError_t launch_pre(const Level& lv, const T* bands, const T* x, bool x_zero, 
     else                                                                                      \
         hipLaunchKernelGGL((k_pre<T, false, BT>), grid, block, 0, st, bands, lv.bs, lv.N, x,   \
                            b, omega, x2out, bc, dmask, g, guard);
-    MG_FUSED_BT_SWITCH(g.bt, PRE)
+#define PRE_BLK(BR, BC)                                                                        \
+    if (x_zero)                                                                                \
+        hipLaunchKernelGGL((k_pre_blk<T, true, BR, BC>), grid, block, 0, st, bands, lv.bs,     \
+                           lv.N, x, b, omega, x2out, bc, dmask, g, guard);                     \
+    else                                                                                       \
+        hipLaunchKernelGGL((k_pre_blk<T, false, BR, BC>), grid, block, 0, st, bands, lv.bs,    \
+                           lv.N, x, b, omega, x2out, bc, dmask, g, guard);
+    if (g.blk == 1) {
+        PRE_BLK(8, 32)
+    } else if (g.blk == 2) {
+        PRE_BLK(16, 32)
+    } else if (g.blk == 3) {
+        PRE_BLK(32, 32)
+    } else {
+        MG_FUSED_BT_SWITCH(g.bt, PRE)
+    }
+#undef PRE_BLK
 #undef PRE
     return hipGetLastError();
 }
@@ -1036,7 +1081,23 @@ hipError_t launch_post(const Level& lv, const T* bands, const T* x, const T* xc,
     else                                                                                     \
         hipLaunchKernelGGL((k_post<T, false, BT>), grid, block, 0, st, bands, lv.bs, lv.N,   \
                            x, xc, b, omega, xout, (double*)nullptr, g, guard);
-    MG_FUSED_BT_SWITCH(g.bt, POST)
+#define POST_BLK(BR, BC)                                                                      \
+    if (partials)                                                                             \
+        hipLaunchKernelGGL((k_post_blk<T, true, BR, BC>), grid, block, 0, st, bands, lv.bs,   \
+                           lv.N, x, xc, b, omega, xout, partials, g, guard);                  \
+    else                                                                                      \
+        hipLaunchKernelGGL((k_post_blk<T, false, BR, BC>), grid, block, 0, st, bands, lv.bs,  \
+                           lv.N, x, xc, b, omega, xout, (double*)nullptr, g, guard);
+    if (g.blk == 1) {
+        POST_BLK(8, 32)
+    } else if (g.blk == 2) {
+        POST_BLK(16, 32)
+    } else if (g.blk == 3) {
+        POST_BLK(32, 32)
+    } else {
+        MG_FUSED_BT_SWITCH(g.bt, POST)
+    }
+#undef POST_BLK
 #undef POST
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !partials) return e;

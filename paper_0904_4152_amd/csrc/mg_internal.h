@@ -285,22 +285,24 @@ struct FusedGeom;
 int fused_bt(int N);
 int fused_rh(int N, int bt, int64_t count);
 // Tiling of a single-problem fused pass: a choice under trial by the
-// autotuner (set_single_trial; 0, 0 ends it), else the tile table's entry
-// for one problem at the level, else the rules.
+// autotuner (set_single_trial; 0, 0, 0 ends it), else the tile table's
+// entry for one problem at the level, else the rules.
 dev::FusedGeom single_geom(int N);
-void set_single_trial(int N, int rows, int bt);
+void set_single_trial(int N, int rows, int bt, int cols = 0);
 
 // Process-wide table of tuned tiles of the fused passes, keyed by level and
 // by the number of problems at that level (rounded down to a power of two;
 // a single-problem solve counts as one): rows per tile and workgroup width
-// in threads; zeros when the level has no entry.  Every change advances the
-// table's epoch (captured cycles of an older epoch are captured again).
+// in threads of a marching tile, or rows and columns of a block tile; zeros
+// when the level has no entry.  Every change advances the table's epoch
+// (captured cycles of an older epoch are captured again).
 struct TileEntry {
     int rows;
     int bt;
+    int cols;  // > 0: a block tile of rows x cols owned nodes
 };
 TileEntry tile_table_get(int level, int64_t problems);
-void tile_table_set(int level, int64_t problems, int rows, int bt);
+void tile_table_set(int level, int64_t problems, int rows, int bt, int cols = 0);
 void tile_table_clear();
 uint64_t tile_table_epoch();
 int64_t fused_tiles(int N);

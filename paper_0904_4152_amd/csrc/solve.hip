@@ -6,11 +6,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <string>
 #include <vector>
 
+#include "fused_ops.h"
 #include "solve.h"
 
 struct GraphEntry {
@@ -816,11 +818,19 @@ extern "C" mg_status mg_hierarchy_autotune(mg_hierarchy* h, int reps, mg_tile_ch
                                       finest ? h->partials : nullptr, h->scal, SC_USER, nullptr,
                                       st);
         };
-        int best_rows = 0, best_bt = 0;
+        int best_rows = 0, best_bt = 0, best_cols = 0;
         float best_ms = 0.0f;
-        for (int bt : kWidths) {
-            for (int rh : kRows) {
-                set_single_trial(v.N, rh, bt);
+        // marching tiles (width x rows), then block tiles on small levels
+        std::vector<std::array<int, 3>> cand;
+        for (int bt : kWidths)
+            for (int rh : kRows) cand.push_back({bt, rh, 0});
+        if (v.N <= dev::BLK_MAX_N)
+            for (int s = 1; s <= dev::BLK_SHAPES; ++s)
+                cand.push_back({dev::BLK_THREADS, dev::block_rows(s), dev::BLK_COLS});
+        for (const auto& c : cand) {
+            {
+                const int bt = c[0], rh = c[1];
+                set_single_trial(v.N, rh, bt, c[2]);
                 for (int w = 0; w < 2; ++w) MG_HIP(pair());
                 MG_HIP(hipEventRecord(g.a, st));
                 for (int r = 0; r < reps; ++r) MG_HIP(pair());
@@ -831,13 +841,14 @@ extern "C" mg_status mg_hierarchy_autotune(mg_hierarchy* h, int reps, mg_tile_ch
                 if (!best_rows || ms < best_ms) {
                     best_rows = rh;
                     best_bt = bt;
+                    best_cols = c[2];
                     best_ms = ms;
                 }
             }
         }
         set_single_trial(0, 0, 0);
-        tile_table_set(l, 1, best_rows, best_bt);
-        rows.push_back({l, 1, best_rows, best_bt / 64, 1e3 * best_ms / reps});
+        tile_table_set(l, 1, best_rows, best_bt, best_cols);
+        rows.push_back({l, 1, best_rows, best_bt / 64, best_cols, 1e3 * best_ms / reps});
     }
     const int n = std::min<int>(out_cap, (int)rows.size());
     for (int i = 0; i < n; ++i) out[i] = rows[i];

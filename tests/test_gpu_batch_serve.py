@@ -263,10 +263,11 @@ def test_server_budget_admission(mg, ctx):
 
 
 def test_autotuned_tiles_change_no_bit(mg, ctx, tmp_path):
-    """The autotuner picks a tile height and a workgroup width per level of
-    this composition; the batch solved with the tuned table, with forced odd
-    choices (rows and widths no rule picks) and with the rules' choices gives
-    the same bits, and the table round-trips through a file."""
+    """The autotuner picks a tile per level of this composition (a marching
+    tile's height and workgroup width, or a block tile's shape); the batch
+    solved with the tuned table, with forced odd choices (rows and widths no
+    rule picks, every block shape) and with the rules' choices gives the
+    same bits, and the table round-trips through a file."""
     probs = make_problems(mg, ctx, [9, 8, 7, 6, 5, 9, 8, 7] * 3, seed0=5000)
     opts = mg.default_opts(precision=mg.MG_PREC_MIXED, rel_tol=1e-8)
     hs, bs_ = [p[0] for p in probs], [p[1] for p in probs]
@@ -282,8 +283,12 @@ def test_autotuned_tiles_change_no_bit(mg, ctx, tmp_path):
     rows = mg.batch_autotune(hs, opts, reps=3)
     assert sorted(r["level"] for r in rows) == [5, 6, 7, 8, 9]
     for r in rows:
-        assert r["tile_rows"] in (4, 8, 16, 32, 64) and r["us"] > 0.0
-        assert r["row_waves"] in (1, 2, 3, 4)
+        assert r["us"] > 0.0
+        if r["tile_cols"]:
+            assert r["tile_cols"] == 32 and r["tile_rows"] in (8, 16, 32)
+            assert r["row_waves"] == 4
+        else:
+            assert r["tile_rows"] in (4, 8, 16, 32, 64) and r["row_waves"] in (1, 2, 3, 4)
     # problems per level: levels above the coarse tail (5) run for every
     # problem that has them, level 5 only as a finest level
     by_level = {r["level"]: r["problems"] for r in rows}
@@ -302,6 +307,14 @@ def test_autotuned_tiles_change_no_bit(mg, ctx, tmp_path):
         mg.batch_set_tiles([{"level": l, "problems": p, "tile_rows": rows_, "row_waves": waves}
                             for l, p in by_level.items()])
         outs.append(run())
+    # block tiles at every level, and block and marching tiles mixed
+    for rows_ in (8, 16, 32):
+        mg.batch_set_tiles([{"level": l, "problems": p, "tile_rows": rows_, "tile_cols": 32}
+                            for l, p in by_level.items()])
+        outs.append(run())
+    mg.batch_set_tiles([{"level": l, "problems": p, "tile_rows": 16, "tile_cols": 32 * (l % 2)}
+                        for l, p in by_level.items()])
+    outs.append(run())
     for xs, ss in outs:
         assert ss == ref_s
         for a, b in zip(xs, ref_x):
@@ -310,6 +323,10 @@ def test_autotuned_tiles_change_no_bit(mg, ctx, tmp_path):
         mg.batch_set_tiles([{"level": 9, "problems": 6, "tile_rows": 12}])
     with pytest.raises(mg.MgError):
         mg.batch_set_tiles([{"level": 9, "problems": 6, "tile_rows": 16, "row_waves": 5}])
+    for bad in ({"tile_rows": 64, "tile_cols": 32}, {"tile_rows": 16, "tile_cols": 16},
+                {"tile_rows": 16, "tile_cols": 32, "row_waves": 2}):
+        with pytest.raises(mg.MgError):
+            mg.batch_set_tiles([dict(level=9, problems=6, **bad)])
     mg.batch_clear_tiles()
     for h, _, _, _ in probs:
         h.close()

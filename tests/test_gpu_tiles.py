@@ -1,8 +1,9 @@
 """Tiles of the single-problem fused passes (Sec. 3: the thread-block
 partition is a runtime parameter): the autotuner's choices, forced odd
-choices and the rules give the same bits in the cycle, the FP64 solve, the
-mixed solve and the post pass's residual norm, and a tuned solve captured
-before a table change is captured again with the new tiles."""
+choices (marching tiles and every block tile shape) and the rules give the
+same bits in the cycle, the FP64 solve, the mixed solve and the post pass's
+residual norm, and a tuned solve captured before a table change is captured
+again with the new tiles."""
 import numpy as np
 import pytest
 
@@ -68,15 +69,20 @@ def test_single_tiles_change_no_bit(mg, ctx, L):
     levels = sorted(r["level"] for r in rows)
     assert levels == list(range(6, L + 1)), levels
     for r in rows:
-        assert r["problems"] == 1 and r["tile_rows"] in (4, 8, 16, 32, 64, 128, 256)
-        assert r["row_waves"] in (1, 2, 3, 4) and r["us"] > 0.0
+        assert r["problems"] == 1 and r["us"] > 0.0
+        if r["tile_cols"]:
+            assert r["level"] <= 10 and r["tile_cols"] == 32 and r["tile_rows"] in (8, 16, 32)
+        else:
+            assert r["tile_rows"] in (4, 8, 16, 32, 64, 128, 256)
+            assert r["row_waves"] in (1, 2, 3, 4)
     tuned = run_all(mg, h, L, b)
     # forced choices no rule picks, every level at once
     forced = []
-    for waves, rows_ in ((1, 128), (3, 4), (2, 32)):
+    for waves, rows_, cols in ((1, 128, 0), (3, 4, 0), (2, 32, 0), (4, 8, 32), (0, 16, 32),
+                               (4, 32, 32)):
         for lv in levels:
             mg.batch_set_tiles([{"level": lv, "problems": 1, "tile_rows": rows_,
-                                 "row_waves": waves}])
+                                 "row_waves": waves, "tile_cols": cols}])
         forced.append(run_all(mg, h, L, b))
     mg.batch_clear_tiles()
     again = run_all(mg, h, L, b)
