@@ -51,17 +51,25 @@ enum { PH_INIT = 0, PH_OUTER = 2, PH_CAST = 3, PH_INNER = 4 };
 // start[cap+1] at wl+2+cap.  Item t belongs to the last k with start[k] <= t.
 __device__ __forceinline__ int wl_total(const int* wl) { return wl[2 + wl[1] + wl[0]]; }
 
+//
+// Found by a 64-way search: each round the wavefront's lanes test 64 evenly
+// spaced entries of the range at once and keep the segment after the last
+// one that is <= t (the entries are non-decreasing and start[0] = 0), so a
+// list of up to 4096 problems takes two rounds of loads, not twelve
+// dependent ones.  Every lane of the wavefront must call it with the same t.
 __device__ __forceinline__ void wl_item(const int* wl, int t, int* p, int* tile) {
     const int count = wl[0], cap = wl[1];
     const int* prob = wl + 2;
     const int* start = wl + 2 + cap;
-    int lo = 0, hi = count - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (start[mid] <= t)
-            lo = mid;
-        else
-            hi = mid - 1;
+    const int lane = (int)(threadIdx.x & 63);
+    int lo = 0, len = count;
+    while (len > 1) {
+        const int step = (len + 63) >> 6;
+        const int off = lane * step;
+        const bool ok = off < len && start[lo + off] <= t;
+        const int last = 63 - __clzll(__ballot(ok));  // lane 0 always holds
+        lo += last * step;
+        len = min(step, len - last * step);
     }
     *p = prob[lo];
     *tile = t - start[lo];
