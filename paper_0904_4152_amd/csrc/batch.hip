@@ -211,21 +211,27 @@ __global__ __launch_bounds__(BLOCK) void kb_copy(const BProb* __restrict__ probs
 }
 
 // Coarse tail of every problem above the coarse level (one block each): the
-// sub-cycle over levels min(L - 1, TAIL_MAX) .. Lc.
+// sub-cycle over levels min(L - 1, TAIL_MAX) .. Lc.  The levels' descriptors
+// are staged in LDS: the cycle indexes them by a run-time level, which in
+// registers would put them in per-lane scratch memory.
 __global__ __launch_bounds__(dev::TAIL_THREADS) void kb_tail(const BProb* __restrict__ probs,
                                                  const BState* __restrict__ state,
                                                  const int* __restrict__ wl, int Lc, int mask) {
+    __shared__ dev::TailLevels<float> tl;
     FOR_ITEMS(wl)
     if (!(flags & mask) || P.L <= Lc) continue;
-    dev::TailLevels<float> tl;
-    const int top = min(P.L - 1, dev::TAIL_MAX);
-    for (int l = Lc; l <= top; ++l) {
-        const BLevel& v = P.lv[l];
-        tl.lv[l] = dev::TailLevel<float>{v.bands32, v.x32, v.b32, v.t32, v.bs, v.n, v.N, 0};
+    __syncthreads();  // the previous item's cycle has read tl
+    if (threadIdx.x == 0) {
+        const int top = min(P.L - 1, dev::TAIL_MAX);
+        for (int l = Lc; l <= top; ++l) {
+            const BLevel& v = P.lv[l];
+            tl.lv[l] = dev::TailLevel<float>{v.bands32, v.x32, v.b32, v.t32, v.bs, v.n, v.N, 0};
+        }
+        tl.cs = P.cs;
+        tl.top = top;
+        tl.Lc = Lc;
     }
-    tl.cs = P.cs;
-    tl.top = top;
-    tl.Lc = Lc;
+    __syncthreads();
     dev::tail_cycle<float>(tl, (float)P.omega);
     END_ITEMS
 }
