@@ -57,22 +57,71 @@ __device__ __forceinline__ int wl_total(const int* wl) { return wl[2 + wl[1] + w
 // one that is <= t (the entries are non-decreasing and start[0] = 0), so a
 // list of up to 4096 problems takes two rounds of loads, not twelve
 // dependent ones.  Every lane of the wavefront must call it with the same t.
-__device__ __forceinline__ void wl_item(const int* wl, int t, int* p, int* tile) {
-    const int count = wl[0], cap = wl[1];
-    const int* prob = wl + 2;
-    const int* start = wl + 2 + cap;
+__device__ __forceinline__ int find_last_le(const int* a, int count, int t) {
     const int lane = (int)(threadIdx.x & 63);
     int lo = 0, len = count;
     while (len > 1) {
         const int step = (len + 63) >> 6;
         const int off = lane * step;
-        const bool ok = off < len && start[lo + off] <= t;
+        const bool ok = off < len && a[lo + off] <= t;
         const int last = 63 - __clzll(__ballot(ok));  // lane 0 always holds
         lo += last * step;
         len = min(step, len - last * step);
     }
-    *p = prob[lo];
-    *tile = t - start[lo];
+    return lo;
+}
+
+__device__ __forceinline__ void wl_item(const int* wl, int t, int* p, int* tile) {
+    const int cap = wl[1];
+    const int* start = wl + 2 + cap;
+    const int k = find_last_le(start, wl[0], t);
+    *p = wl[2 + k];
+    *tile = t - start[k];
+}
+
+// Compacted items: the items of the listed problems whose flags meet mask,
+// in list order.  Every workgroup reads the flags of all listed problems
+// (entries split in runs over its BLOCK threads) and writes cum[k] = active
+// items of the entries before k; item t of the compacted list belongs to
+// the last entry k with cum[k] <= t.  Returns the number of active items.
+// Lists of up to ACTIVE_MAX problems; every thread of the workgroup calls it.
+constexpr int ACTIVE_MAX = 4096;
+
+__device__ int active_prefix(const int* wl, const BState* __restrict__ state, int mask,
+                             int* cum) {
+    __shared__ int wsum[BLOCK / 64];
+    const int count = wl[0], cap = wl[1];
+    const int* prob = wl + 2;
+    const int* start = wl + 2 + cap;
+    const int per = (count + BLOCK - 1) / BLOCK;
+    const int k0 = min((int)threadIdx.x * per, count), k1 = min(k0 + per, count);
+    int mine = 0;
+    for (int k = k0; k < k1; ++k)
+        mine += (state[prob[k]].flags & mask) ? start[k + 1] - start[k] : 0;
+    // exclusive scan of the threads' sums: within each wavefront, then
+    // across the wavefronts
+    const int lane = (int)(threadIdx.x & 63), w = (int)(threadIdx.x >> 6);
+    int inc = mine;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int v = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += v;
+    }
+    if (lane == 63) wsum[w] = inc;
+    __syncthreads();
+    int base = 0, total = 0;
+#pragma unroll
+    for (int i = 0; i < BLOCK / 64; ++i) {
+        base += i < w ? wsum[i] : 0;
+        total += wsum[i];
+    }
+    int run = base + inc - mine;
+    for (int k = k0; k < k1; ++k) {
+        cum[k] = run;
+        run += (state[prob[k]].flags & mask) ? start[k + 1] - start[k] : 0;
+    }
+    __syncthreads();
+    return total;
 }
 
 __device__ __forceinline__ float* role32(const BLevel& lv, int r) { return r ? lv.t32 : lv.x32; }
@@ -89,6 +138,25 @@ __device__ __forceinline__ float* role32(const BLevel& lv, int r) { return r ? l
         int p, tile;                                               \
         wl_item(wl, t_, &p, &tile);                                \
         const BProb& P = probs[p];                                 \
+        const int flags = state[p].flags;
+
+// The same for the listed problems whose flags meet `mask` only: the items
+// of the others are never visited (see active_prefix).
+#define FOR_ACTIVE_ITEMS(wl)                                                           \
+    if (!(state[wl[1]].flags & mask)) return;                                          \
+    __shared__ int cum_[ACTIVE_MAX];                                                   \
+    const bool compact_ = wl[0] <= ACTIVE_MAX;                                         \
+    const int total_ = compact_ ? active_prefix(wl, state, mask, cum_) : wl_total(wl); \
+    for (int t_ = blockIdx.x; t_ < total_; t_ += gridDim.x) {                          \
+        int p, tile;                                                                   \
+        if (compact_) {                                                                \
+            const int k_ = find_last_le(cum_, wl[0], t_);                              \
+            p = wl[2 + k_];                                                            \
+            tile = t_ - cum_[k_];                                                      \
+        } else {                                                                       \
+            wl_item(wl, t_, &p, &tile);                                                \
+        }                                                                              \
+        const BProb& P = probs[p];                                                     \
         const int flags = state[p].flags;
 
 #define END_ITEMS }
@@ -355,7 +423,7 @@ __global__ __launch_bounds__(BLOCK) void kb_inner_norm(const BProb* __restrict__
 __global__ __launch_bounds__(BLOCK) void kb_outer_defect(const BProb* __restrict__ probs,
                                                          const BState* __restrict__ state,
                                                          const int* __restrict__ wl, int mask) {
-    FOR_ITEMS(wl)
+    FOR_ACTIVE_ITEMS(wl)
     if (!(flags & mask)) continue;
     const BLevel& lv = P.lv[P.L];
     for (int sub = 0; sub < 2; ++sub) {
@@ -392,7 +460,7 @@ __global__ __launch_bounds__(BLOCK) void kb_cast(const BProb* __restrict__ probs
                                                  const BState* __restrict__ state,
                                                  const int* __restrict__ wl, int mask) {
     static_assert(TILE == dev::NORM_TILE, "one cast tile = one norm tile");
-    FOR_ITEMS(wl)
+    FOR_ACTIVE_ITEMS(wl)
     if (!(flags & mask)) continue;
     const BLevel& lv = P.lv[P.L];
     const double s = state[p].s;
@@ -420,7 +488,7 @@ __global__ __launch_bounds__(BLOCK) void kb_cast(const BProb* __restrict__ probs
 __global__ __launch_bounds__(BLOCK) void kb_update(const BProb* __restrict__ probs,
                                                    const BState* __restrict__ state,
                                                    const int* __restrict__ wl, int mask) {
-    FOR_ITEMS(wl)
+    FOR_ACTIVE_ITEMS(wl)
     if (!(flags & mask)) continue;
     const BLevel& lv = P.lv[P.L];
     const double s = state[p].s;
