@@ -61,6 +61,9 @@ def parse():
     ap.add_argument("--save-tiles", default=None,
                     help="write the L = 12 tiles the autotuner picked to this file")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--only-batch", action="store_true",
+                    help="set up the 256-problem batch, tune its tiles and run --warmup untimed "
+                         "and --steps timed batched solves only (for profiler runs)")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--serve-count", type=int, default=20000)
@@ -176,9 +179,9 @@ def bench_band4(ctx, torch, dev, N=4096, iters=50):
     return res
 
 
-def bench_batch(mg, ctx, synth, torch, dev, opts, count=256):
-    """256 independent mixed solves advanced together (one persistent launch
-    per V-cycle stage), against the same problems solved one after another."""
+def batch_problems(mg, ctx, synth, torch, dev, count=256):
+    """The 256-problem composition: levels U{5..9} (seed 4004), jitter
+    U[0, 0.25) h (seed 4005), geometry seed 4100+p, uniform RHS seed 4200+p."""
     levels = synth.batch_levels(count, 5, 9, 4004)
     amps = synth.batch_jitter(count, 0.25, 4005)
     hs, bs, xs = [], [], []
@@ -189,6 +192,38 @@ def bench_batch(mg, ctx, synth, torch, dev, opts, count=256):
         hs.append(h)
         bs.append(b)
         xs.append(torch.zeros_like(b))
+    return levels, hs, bs, xs
+
+
+def bench_batch_only(mg, ctx, synth, torch, dev, args):
+    """The batch alone: tuned tiles, then --warmup and --steps batched
+    solves (each from zero initial guesses set outside the timed call)."""
+    opts = mg.default_opts(precision=mg.MG_PREC_MIXED, rel_tol=1e-8)
+    _, hs, bs, xs = batch_problems(mg, ctx, synth, torch, dev)
+    mg.batch_clear_tiles()
+    mg.solve_batch(hs, bs, xs, opts)
+    mg.batch_autotune(hs, opts, reps=10)
+    dts = []
+    for i in range(args.warmup + args.steps):
+        for x in xs:
+            x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        stats = mg.solve_batch(hs, bs, xs, opts)
+        torch.cuda.synchronize()
+        if i >= args.warmup:
+            dts.append(time.perf_counter() - t0)
+    ok = all(s.status == 0 and s.rel_res <= opts.rel_tol for s in stats)
+    print(json.dumps({"only_batch": True, "ms_per_batch": float(np.median(dts)) * 1e3,
+                      "steps": args.steps, "warmup": args.warmup, "all_reached_tol": ok}))
+    for h in hs:
+        h.close()
+
+
+def bench_batch(mg, ctx, synth, torch, dev, opts, count=256):
+    """256 independent mixed solves advanced together (one persistent launch
+    per V-cycle stage), against the same problems solved one after another."""
+    levels, hs, bs, xs = batch_problems(mg, ctx, synth, torch, dev, count)
     # tile heights picked by the autotuner for this composition (no result
     # bit depends on them); the rule's choice is timed as well, for reference
     mg.batch_clear_tiles()
@@ -378,6 +413,9 @@ def main():
     torch.cuda.set_device(dev)
     ctx = mg.Context(0)
     out = {}
+    if args.only_batch:
+        bench_batch_only(mg, ctx, synth, torch, dev, args)
+        return
 
     # ---------------- headline workload: L = 12, jitter 0.2 h, Gaussian RHS
     L, jit, gseed, rseed = 12, 0.2, 1003, 2003

@@ -61,7 +61,7 @@ struct BState {
     int cycles;
     int status;
     int n_hist;
-    int pad;
+    int xnz;  // the initial iterate has a nonzero entry (set by the INIT norm pass)
     double bn, s, dn, r32;
     double hist[MG_HIST];
 };

@@ -426,10 +426,15 @@ __global__ __launch_bounds__(BLOCK) void kb_outer_defect(const BProb* __restrict
     FOR_ACTIVE_ITEMS(wl)
     if (!(flags & mask)) continue;
     const BLevel& lv = P.lv[P.L];
+    // the first defect of a zero initial iterate is b (b - A 0 gives the
+    // same bits): b is copied and its squares summed in the tile's order
+    const bool zero_x = state[p].outer == 0 && !(flags & BF_UPDATE) && state[p].xnz == 0;
     for (int sub = 0; sub < 2; ++sub) {
         const int64_t blo = (int64_t)(2 * tile + sub) * dev::tile_rows<double>();
-        const double sq = dev::stencil_tile<double, dev::OP_DEFECT, true, true, true>(
-            lv.bands64, lv.bs, lv.N, lv.n, lv.x64, lv.b64, P.d64, 0.0, blo);
+        const double sq =
+            zero_x ? dev::copy_tile_sumsq(lv.b64, P.d64, lv.n, blo)
+                   : dev::stencil_tile<double, dev::OP_DEFECT, true, true, true>(
+                         lv.bands64, lv.bs, lv.N, lv.n, lv.x64, lv.b64, P.d64, 0.0, blo);
         const double s = dev::block_sum(sq);
         if (threadIdx.x == 0) P.partials[2 * tile + sub] = s;
     }
@@ -437,9 +442,11 @@ __global__ __launch_bounds__(BLOCK) void kb_outer_defect(const BProb* __restrict
 }
 
 // Sum-of-squares partials of b64 (which = 0) or of the scaled FP32 defect
-// (which = 1) on the finest level.
+// (which = 1) on the finest level.  With which = 0 (a new problem) also
+// whether the initial iterate x64 has a nonzero entry (state.xnz, an
+// integer OR over the tiles), so that its first defect can be b itself.
 __global__ __launch_bounds__(BLOCK) void kb_sumsq(const BProb* __restrict__ probs,
-                                                  const BState* __restrict__ state,
+                                                  BState* __restrict__ state,
                                                   const int* __restrict__ wl, int which,
                                                   int mask) {
     FOR_ITEMS(wl)
@@ -448,6 +455,15 @@ __global__ __launch_bounds__(BLOCK) void kb_sumsq(const BProb* __restrict__ prob
     const int64_t base = (int64_t)tile * dev::NORM_TILE;
     const double sq = which == 0 ? dev::sumsq_tile<double>(lv.b64, lv.n, base)
                                  : dev::sumsq_tile<float>(lv.b32, lv.n, base);
+    if (which == 0) {
+        int nz = 0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int64_t q = base + (int64_t)e * BLOCK + threadIdx.x;
+            nz |= q < lv.n && lv.x64[q] != 0.0;
+        }
+        if (__syncthreads_or(nz) && threadIdx.x == 0) atomicOr(&state[p].xnz, 1);
+    }
     const double s = dev::block_sum(sq);
     if (threadIdx.x == 0) P.partials[tile] = s;
     END_ITEMS

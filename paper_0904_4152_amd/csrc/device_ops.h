@@ -179,6 +179,27 @@ __device__ __forceinline__ double stencil_tile(const T* __restrict__ bands, int6
     return sq;
 }
 
+// The defect tile of a zero iterate, d = b on rows [blo, blo + tile_rows):
+// the same nodes per thread as stencil_tile and the thread's sum of squares
+// in the same order, so the bits equal stencil_tile's OP_DEFECT with x = 0
+// (b - 0 is b).  out may be null (norm only).
+template <typename T>
+__device__ __forceinline__ double copy_tile_sumsq(const T* __restrict__ b, T* __restrict__ out,
+                                                  int64_t n, int64_t blo) {
+    constexpr int W = V16<T>::W;
+    const int64_t p0 = blo + (int64_t)threadIdx.x * W;
+    double sq = 0.0;
+#pragma unroll
+    for (int v = 0; v < W; ++v) {
+        if (p0 + v < n) {
+            const T r = b[p0 + v];
+            sq += (double)r * (double)r;
+            if (out) out[p0 + v] = r;
+        }
+    }
+    return sq;
+}
+
 // Damped Jacobi sweep from a zero iterate: x' = omega b / a_pp.
 template <typename T>
 __device__ __forceinline__ void jacobi_zero_elem(const T* __restrict__ diag,

@@ -639,21 +639,10 @@ __global__ __launch_bounds__(BLOCK) void k_defect_zero_x(int64_t n, const T* __r
                                                          double* __restrict__ partials,
                                                          int64_t nblk,
                                                          const double* __restrict__ guard) {
-    constexpr int W = dev::V16<T>::W;
     const int64_t lb = xcd_block(nblk);
     if (lb < 0 || skipped(guard)) return;
-    const int64_t p0 = lb * (int64_t)dev::tile_rows<T>() + (int64_t)threadIdx.x * W;
-    double sq = 0.0;
-    if (p0 < n) {
-#pragma unroll
-        for (int v = 0; v < W; ++v) {
-            if (p0 + v < n) {
-                const T r = b[p0 + v];
-                if (NORM) sq += (double)r * (double)r;
-                if (STORE) out[p0 + v] = r;
-            }
-        }
-    }
+    const double sq =
+        dev::copy_tile_sumsq<T>(b, STORE ? out : nullptr, n, lb * (int64_t)dev::tile_rows<T>());
     if (NORM) {
         const double s = dev::block_sum(sq);
         if (threadIdx.x == 0) partials[lb] = s;
