@@ -179,6 +179,121 @@ __device__ __forceinline__ double stencil_tile(const T* __restrict__ bands, int6
     return sq;
 }
 
+// stencil_tile with SYM on an interior tile (every neighbour inside the
+// vector), its scattered loads staged through LDS: each workgroup loads the
+// three rows of x and the previous row's bands 6, 7 and 8 that the tile
+// touches with aligned 16-byte loads (one or two per thread and row) and
+// passes band 5 to the next node through LDS, instead of per-element loads
+// of every neighbour.  Every node's operands and fma chain are those of
+// stencil_tile, so the results are the same bits.  Tiles at either end of
+// the vector take stencil_tile itself.  Every thread of the workgroup must
+// call it (barriers inside).
+template <typename T, int OP, bool NORM, bool STORE>
+__device__ __forceinline__ double stencil_tile_staged(const T* __restrict__ bands, int64_t bs,
+                                                      int N, int64_t n,
+                                                      const T* __restrict__ x,
+                                                      const T* __restrict__ b,
+                                                      T* __restrict__ out, T omega, int64_t blo) {
+    constexpr int W = V16<T>::W, R = tile_rows<T>();
+    constexpr int SL = R + 2 * W;  // elements of one staged segment
+    typedef typename V16<T>::type VT;
+    // segment starts, rounded down to a vector: x rows at offsets -N-1, -1,
+    // N-1 and the previous row's bands at -N-1 (floor division)
+    auto seg0 = [&](int64_t o) -> int64_t {
+        const int64_t q = blo + o;
+        return (q >= 0 ? q / W : -((-q + W - 1) / W)) * W;
+    };
+    const int64_t ax[3] = {seg0(-(int64_t)N - 1), seg0(-1), seg0((int64_t)N - 1)};
+    const int64_t ab = ax[0];
+    const bool inner = ab - W >= 0 && ax[2] + SL <= n;  // uniform per tile
+    if (!inner) return stencil_tile<T, OP, NORM, STORE, true>(bands, bs, N, n, x, b, out, omega, blo);
+    __shared__ T sx[3][SL];
+    __shared__ T sb[3][SL];      // bands 8, 7, 6 of the previous row
+    __shared__ T s5[R + W];      // band 5 at blo - W .. blo + R - 1
+    const int t = threadIdx.x;
+    const int64_t p0 = blo + (int64_t)t * W;
+    // this thread's own band vectors (diagonal and upper bands) and b
+    T bk[9][W];
+#pragma unroll
+    for (int k = 4; k < 9; ++k) {
+        const VT* src = reinterpret_cast<const VT*>(bands + k * bs + p0);
+        VT v = k == 4 ? __builtin_nontemporal_load(src) : *src;
+        __builtin_memcpy(bk[k], &v, sizeof(VT));
+    }
+    T bb[W];
+    if (OP != OP_SPMV) {
+        VT v = *reinterpret_cast<const VT*>(b + p0);
+        __builtin_memcpy(bb, &v, sizeof(VT));
+    }
+    __syncthreads();  // a previous tile of this workgroup is done with LDS
+    // staged segments: vector j of each, j = t and (t < SL/W - BLOCK) t + BLOCK
+#pragma unroll
+    for (int rep = 0; rep < 2; ++rep) {
+        const int j = t + rep * BLOCK;
+        if (rep == 0 || j < SL / W) {
+#pragma unroll
+            for (int r = 0; r < 3; ++r)
+                *reinterpret_cast<VT*>(&sx[r][j * W]) =
+                    *reinterpret_cast<const VT*>(x + ax[r] + (int64_t)j * W);
+            const int up[3] = {8, 7, 6};
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                *reinterpret_cast<VT*>(&sb[k][j * W]) =
+                    *reinterpret_cast<const VT*>(bands + up[k] * bs + ab + (int64_t)j * W);
+        }
+    }
+    *reinterpret_cast<VT*>(&s5[W + t * W]) = *reinterpret_cast<const VT*>(bk[5]);
+    if (t == 0) *reinterpret_cast<VT*>(&s5[0]) = *reinterpret_cast<const VT*>(bands + 5 * bs + blo - W);
+    __syncthreads();
+    T xv[3][W + 2];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        const int o = (int)(p0 + (int64_t)(r - 1) * N - 1 - ax[r]);
+#pragma unroll
+        for (int e = 0; e < W + 2; ++e) xv[r][e] = sx[r][o + e];
+    }
+    {
+        // A[p][p-N-1] = band 8 at p-N-1, A[p][p-N] = band 7 at p-N,
+        // A[p][p-N+1] = band 6 at p-N+1, A[p][p-1] = band 5 at p-1
+        const int o = (int)(p0 - (int64_t)N - 1 - ab);
+#pragma unroll
+        for (int v = 0; v < W; ++v) {
+            bk[0][v] = sb[0][o + v];
+            bk[1][v] = sb[1][o + v + 1];
+            bk[2][v] = sb[2][o + v + 2];
+            bk[3][v] = s5[W + t * W + v - 1];
+        }
+    }
+    T res[W];
+#pragma unroll
+    for (int v = 0; v < W; ++v) {
+        T acc = T(0);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) acc = fma(bk[k][v], xv[k / 3][v + k % 3], acc);
+        res[v] = acc;
+    }
+    double sq = 0.0;
+    if (OP != OP_SPMV) {
+#pragma unroll
+        for (int v = 0; v < W; ++v) {
+            if (OP == OP_DEFECT)
+                res[v] = bb[v] - res[v];
+            else
+                res[v] = xv[1][v + 1] + jacobi_div(omega * (bb[v] - res[v]), bk[4][v]);
+        }
+    }
+    if (NORM) {
+#pragma unroll
+        for (int v = 0; v < W; ++v) sq += (double)res[v] * (double)res[v];
+    }
+    if (STORE) {
+        VT v;
+        __builtin_memcpy(&v, res, sizeof(VT));
+        *reinterpret_cast<VT*>(out + p0) = v;
+    }
+    return sq;
+}
+
 // The defect tile of a zero iterate, d = b on rows [blo, blo + tile_rows):
 // the same nodes per thread as stencil_tile and the thread's sum of squares
 // in the same order, so the bits equal stencil_tile's OP_DEFECT with x = 0

@@ -99,8 +99,12 @@ __global__ __launch_bounds__(BLOCK) void k_stencil(const T* __restrict__ bands, 
                                                    const double* __restrict__ guard) {
     const int64_t lb = xcd_block(nblk);
     if (lb < 0 || skipped(guard)) return;
-    const double sq = dev::stencil_tile<T, OP, NORM, STORE, SYM>(
-        bands, bs, N, n, x, b, out, omega, lb * (int64_t)dev::tile_rows<T>());
+    const int64_t blo = lb * (int64_t)dev::tile_rows<T>();
+    double sq;
+    if constexpr (SYM)
+        sq = dev::stencil_tile_staged<T, OP, NORM, STORE>(bands, bs, N, n, x, b, out, omega, blo);
+    else
+        sq = dev::stencil_tile<T, OP, NORM, STORE, SYM>(bands, bs, N, n, x, b, out, omega, blo);
     if (NORM) {
         const double s = dev::block_sum(sq);
         if (threadIdx.x == 0) partials[lb] = s;
