@@ -74,6 +74,15 @@ __device__ __forceinline__ double block_sum(double v) {
 
 enum { OP_SPMV = 0, OP_DEFECT = 1, OP_JACOBI = 2 };
 
+// s + r * r in two roundings (product, then sum).  The norm partials of the
+// stencil tile kinds must agree bit for bit, and whether the compiler fuses
+// a product and a sum into one fma depends on the code around them, so it
+// is not left to it here.
+__device__ __forceinline__ double add_sq(double s, double r) {
+#pragma clang fp contract(off)
+    return s + r * r;
+}
+
 // One stencil tile: rows [blo, blo + tile_rows) of y = A x (SPMV),
 // d = b - A x (DEFECT) or x' = x + omega (b - A x) / a_pp (JACOBI).  Each
 // thread owns W consecutive rows.  Tiles at least N+1 rows away from both
@@ -163,7 +172,7 @@ __device__ __forceinline__ double stencil_tile(const T* __restrict__ bands, int6
     if (NORM) {
 #pragma unroll
         for (int v = 0; v < W; ++v)
-            if (p0 + v < n) sq += (double)res[v] * (double)res[v];
+            if (p0 + v < n) sq = add_sq(sq, (double)res[v]);
     }
     if (STORE) {
         if (fast) {
@@ -284,7 +293,7 @@ __device__ __forceinline__ double stencil_tile_staged(const T* __restrict__ band
     }
     if (NORM) {
 #pragma unroll
-        for (int v = 0; v < W; ++v) sq += (double)res[v] * (double)res[v];
+        for (int v = 0; v < W; ++v) sq = add_sq(sq, (double)res[v]);
     }
     if (STORE) {
         VT v;
@@ -308,7 +317,7 @@ __device__ __forceinline__ double copy_tile_sumsq(const T* __restrict__ b, T* __
     for (int v = 0; v < W; ++v) {
         if (p0 + v < n) {
             const T r = b[p0 + v];
-            sq += (double)r * (double)r;
+            sq = add_sq(sq, (double)r);
             if (out) out[p0 + v] = r;
         }
     }
