@@ -249,15 +249,15 @@ mg_status mg_solve_batch(mg_hierarchy* const* hs, const double* const* b, double
  * re-capture its iteration graph while its mix changes).
  * mg_batch_autotune: for the composition of these problems (options as for
  * mg_solve_batch; NULL: defaults), times the fused pre- and post-smoothing
- * passes of every level for each of 4, 8, 16, 32, 64 rows per tile and 1, 2,
- * 3, 4 wavefronts per row, and on levels of at most 1025 nodes per side for
+ * passes of every level for each of 4, 8, 12, 16, 24, 32, 48, 64, 96 rows per
+ * tile and 1, 2, 3, 4 wavefronts per row, and on levels of at most 1025 nodes per side for
  * each block tile (reps pairs each, on the problems' FP32 work vectors,
  * which no later solve reads before writing), stores the fastest in the
  * table and writes up to out_cap choices to out (*n_out = choices).
  * Synchronous; thread safe with respect to other batches on separate
  * hierarchies.  Only V(2,2) cycles have tiles.
  * mg_batch_set_tile: installs one entry (e.g. read back from a file): with
- * tile_cols = 0 a marching tile, tile_rows a power of two in [4, 256],
+ * tile_cols = 0 a marching tile, tile_rows a multiple of 4 in [4, 256],
  * row_waves in 1..4 or 0 for the width rule; with tile_cols = 32 a block
  * tile, tile_rows 8, 16 or 32, row_waves 0 or 4.  mg_batch_clear_tiles:
  * empties the table. */
@@ -278,8 +278,9 @@ mg_status mg_batch_clear_tiles(void);
  * the fused-pass entry points read the table's entries for one problem): for
  * every level on which h's V(2,2) cycle runs fused passes, times the FP32
  * pre- and post-smoothing passes as the mixed solve runs them (reps pairs
- * per candidate, on h's FP32 work vectors) for 4 .. 256 rows per tile and 1
- * .. 4 wavefronts per row, and on levels of at most 1025 nodes per side for
+ * per candidate, on h's FP32 work vectors) for 4, 8, 12, 16, 24, 32, 40, 48,
+ * 64, 80, 96, 128, 160, 192 and 256 rows per tile and 1 .. 4 wavefronts per
+ * row, and on levels of at most 1025 nodes per side for
  * each block tile, and stores the fastest under problems = 1.  Tiles
  * change no result bit; solves captured before are captured again.
  * Synchronous; not thread safe per hierarchy. */

@@ -1150,7 +1150,7 @@ hipError_t BatchEngine::launch_fused(int l, bool pre, int mask) {
 }
 
 mg_status BatchEngine::tune(int reps, std::vector<mg_tile_choice>* out) {
-    static const int kRows[] = {4, 8, 16, 32, 64};
+    static const int kRows[] = {4, 8, 12, 16, 24, 32, 48, 64, 96};
     static const int kWidths[] = {64, 128, 192, 256};
     MG_HIP(hipSetDevice(device_));
     if (mg_status s = upload()) return s;
@@ -1676,8 +1676,8 @@ extern "C" mg_status mg_batch_set_tile(int level, int problems, int tile_rows, i
         tile_table_set(level, problems, tile_rows, dev::BLK_THREADS, tile_cols);
         return MG_OK;
     }
-    if (tile_rows < 4 || tile_rows > 256 || (tile_rows & (tile_rows - 1)))
-        return fail(MG_ERR_INVALID, "tile_rows must be a power of two in [4, 256]");
+    if (tile_rows < 4 || tile_rows > 256 || tile_rows % 4)
+        return fail(MG_ERR_INVALID, "tile_rows must be a multiple of 4 in [4, 256]");
     if (row_waves < 0 || row_waves > dev::F_MAX_THREADS / 64)
         return fail(MG_ERR_INVALID, "row_waves must lie in [0, 4]");
     tile_table_set(level, problems, tile_rows, 64 * row_waves);

@@ -788,7 +788,7 @@ extern "C" mg_status mg_hierarchy_autotune(mg_hierarchy* h, int reps, mg_tile_ch
     if (reps < 1 || reps > 1000) return fail(MG_ERR_INVALID, "reps must lie in [1, 1000]");
     if (out_cap < 0 || (out_cap > 0 && !out)) return fail(MG_ERR_INVALID, "bad output array");
     const TraceRange trace("mg_hierarchy_autotune");
-    static const int kRows[] = {4, 8, 16, 32, 64, 128, 256};
+    static const int kRows[] = {4, 8, 12, 16, 24, 32, 40, 48, 64, 80, 96, 128, 160, 192, 256};
     static const int kWidths[] = {64, 128, 192, 256};
     MG_HIP(hipSetDevice(h->ctx->device));
     GraphCache* gc = cache(h);

@@ -317,7 +317,8 @@ def test_autotuned_tiles_change_no_bit(mg, ctx, tmp_path):
             assert r["tile_cols"] == 32 and r["tile_rows"] in (8, 16, 32)
             assert r["row_waves"] == 4
         else:
-            assert r["tile_rows"] in (4, 8, 16, 32, 64) and r["row_waves"] in (1, 2, 3, 4)
+            assert r["tile_rows"] in (4, 8, 12, 16, 24, 32, 48, 64, 96)
+            assert r["row_waves"] in (1, 2, 3, 4)
     # problems per level: levels above the coarse tail (5) run for every
     # problem that has them, level 5 only as a finest level
     by_level = {r["level"]: r["problems"] for r in rows}
@@ -332,7 +333,7 @@ def test_autotuned_tiles_change_no_bit(mg, ctx, tmp_path):
     x3, s3 = run()
     # every width at every level of the composition, with odd heights
     outs = [(x1, s1), (x2, s2), (x3, s3)]
-    for waves, rows_ in ((1, 8), (3, 16), (2, 64), (4, 4)):
+    for waves, rows_ in ((1, 8), (3, 16), (2, 64), (4, 4), (2, 12), (1, 40), (3, 100)):
         mg.batch_set_tiles([{"level": l, "problems": p, "tile_rows": rows_, "row_waves": waves}
                             for l, p in by_level.items()])
         outs.append(run())
@@ -349,7 +350,10 @@ def test_autotuned_tiles_change_no_bit(mg, ctx, tmp_path):
         for a, b in zip(xs, ref_x):
             np.testing.assert_array_equal(a, b)
     with pytest.raises(mg.MgError):
-        mg.batch_set_tiles([{"level": 9, "problems": 6, "tile_rows": 12}])
+        mg.batch_set_tiles([{"level": 9, "problems": 6, "tile_rows": 14}])
+    for bad_rows in (0, 2, 260):
+        with pytest.raises(mg.MgError):
+            mg.batch_set_tiles([{"level": 9, "problems": 6, "tile_rows": bad_rows}])
     with pytest.raises(mg.MgError):
         mg.batch_set_tiles([{"level": 9, "problems": 6, "tile_rows": 16, "row_waves": 5}])
     for bad in ({"tile_rows": 64, "tile_cols": 32}, {"tile_rows": 16, "tile_cols": 16},

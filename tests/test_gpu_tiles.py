@@ -73,13 +73,14 @@ def test_single_tiles_change_no_bit(mg, ctx, L):
         if r["tile_cols"]:
             assert r["level"] <= 10 and r["tile_cols"] == 32 and r["tile_rows"] in (8, 16, 32)
         else:
-            assert r["tile_rows"] in (4, 8, 16, 32, 64, 128, 256)
+            assert r["tile_rows"] in (4, 8, 12, 16, 24, 32, 40, 48, 64, 80, 96, 128, 160,
+                                      192, 256)
             assert r["row_waves"] in (1, 2, 3, 4)
     tuned = run_all(mg, h, L, b)
     # forced choices no rule picks, every level at once
     forced = []
-    for waves, rows_, cols in ((1, 128, 0), (3, 4, 0), (2, 32, 0), (4, 8, 32), (0, 16, 32),
-                               (4, 32, 32)):
+    for waves, rows_, cols in ((1, 128, 0), (3, 4, 0), (2, 32, 0), (2, 12, 0), (1, 44, 0),
+                               (4, 8, 32), (0, 16, 32), (4, 32, 32)):
         for lv in levels:
             mg.batch_set_tiles([{"level": lv, "problems": 1, "tile_rows": rows_,
                                  "row_waves": waves, "tile_cols": cols}])
