@@ -187,10 +187,12 @@ mg_status mg_rhs_uniform(const mg_hierarchy* h, uint64_t seed, double* dev_b, vo
 /* ---- solve (Sec. 6.2) -------------------------------------------------------
  * Solve A x = b on the finest level.  dev_x is in/out (initial guess, then
  * the solution).  FP64: V-cycles until ||b - A x|| <= rel_tol ||b||.  Mixed:
- * FP64 defect d = b - A x and norm s, d32 = float(d / s), FP32 V-cycles on
- * A32 c = d32 from c = 0 until the FP32 residual drops by inner_reduction
- * (at most inner_max_cycles), x += s * double(c); the coarsest solve is
- * always FP64.
+ * FP64 defect d = b - A x and norm s, d32 = float(d 2^-e) with e the binary
+ * exponent of ||b|| (||b|| = m 2^e, m in [0.5, 1); a power of two scales
+ * exactly, it only keeps the FP32 values in range), FP32 V-cycles on
+ * A32 c = d32 from c = 0 until the FP32 residual is at most inner_reduction
+ * 2^-e s (at most inner_max_cycles), x += 2^e double(c); the coarsest solve
+ * is always FP64.
  * krylov = 1: conjugate gradients preconditioned by one V(nu_pre, nu_post)
  * cycle from a zero iterate (Sec. 4.1: a solver plugged into another as its
  * preconditioner), in FP64; the cycle is FP64, or with MG_PREC_MIXED an FP32

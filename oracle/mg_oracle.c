@@ -733,9 +733,22 @@ static double norm_f32_in_f64(size_t n, const float* v) {
     return sqrt(s);
 }
 
+/* The power of two that brings the defects into single-precision range
+ * (the paper does not say how; a power of two scales exactly in binary
+ * arithmetic, so the single-precision cycles compute the same digits for
+ * any exponent): 2^-e for ||b|| = m 2^e, m in [0.5, 1), e clamped to
+ * [-1020, 1020]. */
+static int pow2_exponent(double v) {
+    int e = 0;
+    (void)frexp(v, &e);
+    return e < -1020 ? -1020 : (e > 1020 ? 1020 : e);
+}
+
 /* Mixed precision defect correction (Sec. 6.2): FP64 defect d = b - A x,
- * single-precision multigrid cycles on the scaled defect until the FP32
- * residual has dropped by inner_reduction, FP64 update x += s c. */
+ * single-precision multigrid cycles on d scaled by sc = 2^-e (e from
+ * ||b||, pow2_exponent) until the FP32 residual has dropped by
+ * inner_reduction relative to the scaled defect's norm sc ||d||, FP64
+ * update x += 2^e c. */
 int or_solve_mixed_emulated(or_hier* h, const double* b, double* x, const or_opts* o,
                             or_stats* st) {
     int N = h->N[h->L];
@@ -747,6 +760,8 @@ int or_solve_mixed_emulated(or_hier* h, const double* b, double* x, const or_opt
         memset(x, 0, n * sizeof(double));
         return 0;
     }
+    const double sc = ldexp(1.0, -pow2_exponent(bn));
+    const double unscale = ldexp(1.0, pow2_exponent(bn));
     double* d = (double*)malloc(n * sizeof(double));
     float* d32 = (float*)malloc(n * sizeof(float));
     float* c32 = (float*)malloc(n * sizeof(float));
@@ -764,9 +779,9 @@ int or_solve_mixed_emulated(or_hier* h, const double* b, double* x, const or_opt
             if (k > o->max_cycles) { st->status = 3; break; }
         }
         if (s == 0.0) break;
-        for (size_t p = 0; p < n; ++p) d32[p] = (float)(d[p] / s);
+        for (size_t p = 0; p < n; ++p) d32[p] = (float)(d[p] * sc);
         memset(c32, 0, n * sizeof(float));
-        double dn = norm_f32_in_f64(n, d32);
+        const double dn = sc * s;
         for (int it = 1; it <= o->inner_max_cycles; ++it) {
             vcycle32(h, h->L, c32, d32, o);
             st->cycles++;
@@ -774,7 +789,7 @@ int or_solve_mixed_emulated(or_hier* h, const double* b, double* x, const or_opt
             for (size_t p = 0; p < n; ++p) r32[p] = d32[p] - r32[p];
             if (norm_f32_in_f64(n, r32) <= o->inner_reduction * dn) break;
         }
-        for (size_t p = 0; p < n; ++p) x[p] += s * (double)c32[p];
+        for (size_t p = 0; p < n; ++p) x[p] += unscale * (double)c32[p];
         st->outer_steps = k;
     }
     free(d); free(d32); free(c32); free(r32);

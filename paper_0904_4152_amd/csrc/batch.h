@@ -31,7 +31,6 @@ struct BLevel {
 
 struct BProb {
     BLevel lv[MG_MAX_LEVEL + 1];
-    double* d64;
     double* partials;
     dev::CoarseSolver cs;  // coarsest solve
     int L;
@@ -47,7 +46,6 @@ struct BProb {
 enum : int {
     BF_INIT = 1,
     BF_OUTER = 2,
-    BF_CAST = 4,
     BF_INNER = 8,
     BF_UPDATE = 16,
     BF_DONE = 32

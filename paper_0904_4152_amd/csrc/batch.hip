@@ -44,8 +44,8 @@ constexpr int STAGE_GRID = 2048;
 constexpr int TILE = 1024;  // elements per work item (one FP32 stencil tile)
 
 enum { K_NORM = 0, K_S32 = 1, K_S64 = 2 };
-enum { F_BN = 0, F_S = 1, F_DN = 2, F_R32 = 3 };
-enum { PH_INIT = 0, PH_OUTER = 2, PH_CAST = 3, PH_INNER = 4 };
+enum { F_BN = 0, F_S = 1, F_R32 = 3 };
+enum { PH_INIT = 0, PH_OUTER = 2, PH_INNER = 4 };
 
 // Work list: wl[0] = count, wl[1] = cap, prob[cap] at wl+2, tile prefix
 // start[cap+1] at wl+2+cap.  Item t belongs to the last k with start[k] <= t.
@@ -418,8 +418,10 @@ __global__ __launch_bounds__(BLOCK) void kb_inner_norm(const BProb* __restrict__
     END_ITEMS
 }
 
-// FP64 defect d = b - A x on the finest level with norm partials: two FP64
-// stencil tiles (512 rows each) per work item.
+// FP64 defect d = b - A x on the finest level with norm partials, written
+// as float(d sc) into the finest FP32 right-hand side (sc = pow2_scale of
+// ||b||, as the single-problem mixed solve writes it): two FP64 stencil
+// tiles (512 rows each) per work item.
 __global__ __launch_bounds__(BLOCK) void kb_outer_defect(const BProb* __restrict__ probs,
                                                          const BState* __restrict__ state,
                                                          const int* __restrict__ wl, int mask) {
@@ -429,12 +431,13 @@ __global__ __launch_bounds__(BLOCK) void kb_outer_defect(const BProb* __restrict
     // the first defect of a zero initial iterate is b (b - A 0 gives the
     // same bits): b is copied and its squares summed in the tile's order
     const bool zero_x = state[p].outer == 0 && !(flags & BF_UPDATE) && state[p].xnz == 0;
+    const dev::Cast32 cast{lv.b32, dev::pow2_scale(state[p].bn)};
     for (int sub = 0; sub < 2; ++sub) {
         const int64_t blo = (int64_t)(2 * tile + sub) * dev::tile_rows<double>();
         const double sq =
-            zero_x ? dev::copy_tile_sumsq(lv.b64, P.d64, lv.n, blo)
-                   : dev::stencil_tile<double, dev::OP_DEFECT, true, true, true>(
-                         lv.bands64, lv.bs, lv.N, lv.n, lv.x64, lv.b64, P.d64, 0.0, blo);
+            zero_x ? dev::copy_tile_sumsq<double, true>(lv.b64, nullptr, lv.n, blo, cast)
+                   : dev::stencil_tile<double, dev::OP_DEFECT, true, true, true, true>(
+                         lv.bands64, lv.bs, lv.N, lv.n, lv.x64, lv.b64, nullptr, 0.0, blo, cast);
         const double s = dev::block_sum(sq);
         if (threadIdx.x == 0) P.partials[2 * tile + sub] = s;
     }
@@ -469,45 +472,15 @@ __global__ __launch_bounds__(BLOCK) void kb_sumsq(const BProb* __restrict__ prob
     END_ITEMS
 }
 
-// d32 = float(d64 / s), the scaled defect, into the finest FP32 rhs, with
-// the sum-of-squares partials of d32 (the order of dev::sumsq_tile on the
-// stored values, as the single-problem cast kernel sums them).
-__global__ __launch_bounds__(BLOCK) void kb_cast(const BProb* __restrict__ probs,
-                                                 const BState* __restrict__ state,
-                                                 const int* __restrict__ wl, int mask) {
-    static_assert(TILE == dev::NORM_TILE, "one cast tile = one norm tile");
-    FOR_ACTIVE_ITEMS(wl)
-    if (!(flags & mask)) continue;
-    const BLevel& lv = P.lv[P.L];
-    const double s = state[p].s;
-    const int64_t base = (int64_t)tile * TILE;
-    double dv[4];  // loads first; lanes past n read element 0 and store nothing
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        const int64_t q = base + (int64_t)e * BLOCK + threadIdx.x;
-        dv[e] = P.d64[q < lv.n ? q : 0];
-    }
-    double acc = 0.0;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        const int64_t q = base + (int64_t)e * BLOCK + threadIdx.x;
-        const float v = s > 0.0 ? (float)(dv[e] / s) : 0.0f;
-        if (q < lv.n) lv.b32[q] = v;
-        acc += q < lv.n ? (double)v * (double)v : 0.0;
-    }
-    const double t = dev::block_sum(acc);
-    if (threadIdx.x == 0) P.partials[tile] = t;
-    END_ITEMS
-}
-
-// x64 += s * double(c32).
+// x64 += u double(c32), u = pow2_unscale(||b||) (the single solve's
+// update).
 __global__ __launch_bounds__(BLOCK) void kb_update(const BProb* __restrict__ probs,
                                                    const BState* __restrict__ state,
                                                    const int* __restrict__ wl, int mask) {
     FOR_ACTIVE_ITEMS(wl)
     if (!(flags & mask)) continue;
     const BLevel& lv = P.lv[P.L];
-    const double s = state[p].s;
+    const double s = dev::pow2_unscale(state[p].bn);
     const int64_t base = (int64_t)tile * TILE;
     double xv[4];  // loads first; lanes past n read element 0 and store nothing
     float cv[4];
@@ -615,11 +588,16 @@ __device__ void transition(const BProb& P, BState& S, int phase) {
             done = 1;
         }
         if (!done && S.s == 0.0) done = 1;
-        S.flags = done ? BF_DONE : BF_CAST;
-    } else if (phase == PH_CAST && (f & BF_CAST)) {
-        S.first = 1;
-        S.it = 0;
-        S.flags = BF_INNER;
+        if (done) {
+            S.flags = BF_DONE;
+        } else {
+            // the defect kernel wrote the scaled FP32 right-hand side: the
+            // inner loop starts, relative to the scaled defect's norm
+            S.dn = dev::pow2_scale(S.bn) * S.s;
+            S.first = 1;
+            S.it = 0;
+            S.flags = BF_INNER;
+        }
     } else if (phase == PH_INNER && (f & BF_INNER)) {
         S.it += 1;
         S.cycles += 1;
@@ -660,8 +638,6 @@ __device__ void finalize_items(const BProb* __restrict__ probs, BState* __restri
                 S.bn = r;
             else if (field == F_S)
                 S.s = r;
-            else if (field == F_DN)
-                S.dn = r;
             else
                 S.r32 = r;
             transition(P, S, phase);
@@ -850,7 +826,6 @@ void BatchEngine::set_slot(int s, mg_hierarchy* h, const mg_solve_opts& o) {
         b.nchunks = g.nchunks;
         b.blk = 0;
     }
-    P.d64 = h->d64;
     P.partials = h->partials;
     P.cs = coarse_solver(h);
     P.dmask = h->dmask;
@@ -1246,10 +1221,6 @@ hipError_t BatchEngine::enqueue_iteration(bool with_init) {
     LAUNCH(kb_outer_defect, G, B, 0, st_, P, S, W(WL_FINEST), om);
     LAUNCH(kb_finctl, GA, B, 0, st_, P, S, W(WL_ALL), (int)K_S64, (int)F_S, om, -1,
            (int)PH_OUTER, d_iter_, h_ring_, ticket);
-    // scaled FP32 defect and its norm
-    LAUNCH(kb_cast, G, B, 0, st_, P, S, W(WL_FINEST), (int)BF_CAST);
-    LAUNCH(kb_finctl, GA, B, 0, st_, P, S, W(WL_ALL), (int)K_NORM, (int)F_DN, (int)BF_CAST, -1,
-           (int)PH_CAST, d_iter_, h_ring_, ticket);
     // one FP32 V-cycle for every problem in its inner loop
     const int m = BF_INNER;
     const bool fused = nu_pre_ == 2 && nu_post_ == 2;

@@ -83,11 +83,43 @@ __device__ __forceinline__ double add_sq(double s, double r) {
     return s + r * r;
 }
 
+// The mixed scheme rounds each FP64 defect to FP32 after scaling it by a
+// power of two fixed per solve by ||b||: 2^-e for ||b|| = m 2^e with m in
+// [0.5, 1) (e clamped so that 2^e and 2^-e stay normal), and scales the FP32
+// correction back by 2^e.  Scaling by a power of two is exact in binary
+// floating point, so the FP32 inner solve computes the same digits whatever
+// e is; the scale only keeps the FP32 values in range.
+__host__ __device__ inline int pow2_exponent(double v) {
+    int e = 0;
+    (void)frexp(v, &e);
+    return e < -1020 ? -1020 : (e > 1020 ? 1020 : e);
+}
+__host__ __device__ inline double pow2_scale(double v) { return ldexp(1.0, -pow2_exponent(v)); }
+__host__ __device__ inline double pow2_unscale(double v) { return ldexp(1.0, pow2_exponent(v)); }
+
+// Destination of a defect tile's values rounded to FP32 after scaling by sc
+// (the mixed scheme's FP32 right-hand side), written in place of the FP64
+// values when a tile function's CAST is set.
+struct Cast32 {
+    float* out = nullptr;
+    double sc = 1.0;
+};
+
+// W consecutive floats at p (p aligned to W floats) in one store.
+template <int W>
+__device__ __forceinline__ void store_floats(float* __restrict__ p, const float* f) {
+    typedef float VF __attribute__((ext_vector_type(W)));
+    VF v;
+    __builtin_memcpy(&v, f, sizeof(VF));
+    *reinterpret_cast<VF*>(p) = v;
+}
+
 // One stencil tile: rows [blo, blo + tile_rows) of y = A x (SPMV),
 // d = b - A x (DEFECT) or x' = x + omega (b - A x) / a_pp (JACOBI).  Each
 // thread owns W consecutive rows.  Tiles at least N+1 rows away from both
 // ends of the vector read the x halo without bounds checks.  Returns the
-// thread's sum of squares of its outputs when NORM.
+// thread's sum of squares of its outputs when NORM.  With CAST (FP64 only)
+// STORE writes float(v sc) to cast.out instead of v to out.
 //
 // SYM: the matrix is symmetric bit for bit, so the lower bands at p are
 // read as upper bands of the neighbours (band 8 at p-N-1, 7 at p-N, 6 at
@@ -95,11 +127,12 @@ __device__ __forceinline__ double add_sq(double s, double r) {
 // streamed by the tiles just before (same XCD), so the shifted reads are
 // served by the cache and HBM sees 5 band streams instead of 9.  Same
 // values, same results.
-template <typename T, int OP, bool NORM, bool STORE, bool SYM = false>
+template <typename T, int OP, bool NORM, bool STORE, bool SYM = false, bool CAST = false>
 __device__ __forceinline__ double stencil_tile(const T* __restrict__ bands, int64_t bs, int N,
                                                int64_t n, const T* __restrict__ x,
                                                const T* __restrict__ b, T* __restrict__ out,
-                                               T omega, int64_t blo) {
+                                               T omega, int64_t blo, Cast32 cast = Cast32{}) {
+    static_assert(!CAST || (sizeof(T) == 8 && OP == OP_DEFECT), "CAST: FP64 defects");
     constexpr int W = V16<T>::W;
     typedef typename V16<T>::type VT;
     const int64_t p0 = blo + (int64_t)threadIdx.x * W;
@@ -174,7 +207,18 @@ __device__ __forceinline__ double stencil_tile(const T* __restrict__ bands, int6
         for (int v = 0; v < W; ++v)
             if (p0 + v < n) sq = add_sq(sq, (double)res[v]);
     }
-    if (STORE) {
+    if (STORE && CAST) {
+        float f[W];
+#pragma unroll
+        for (int v = 0; v < W; ++v) f[v] = (float)((double)res[v] * cast.sc);
+        if (fast) {
+            store_floats<W>(cast.out + p0, f);
+        } else {
+#pragma unroll
+            for (int v = 0; v < W; ++v)
+                if (p0 + v < n) cast.out[p0 + v] = f[v];
+        }
+    } else if (STORE) {
         if (fast) {
             VT v;
             __builtin_memcpy(&v, res, sizeof(VT));
@@ -197,12 +241,13 @@ __device__ __forceinline__ double stencil_tile(const T* __restrict__ bands, int6
 // stencil_tile, so the results are the same bits.  Tiles at either end of
 // the vector take stencil_tile itself.  Every thread of the workgroup must
 // call it (barriers inside).
-template <typename T, int OP, bool NORM, bool STORE>
+template <typename T, int OP, bool NORM, bool STORE, bool CAST = false>
 __device__ __forceinline__ double stencil_tile_staged(const T* __restrict__ bands, int64_t bs,
                                                       int N, int64_t n,
                                                       const T* __restrict__ x,
                                                       const T* __restrict__ b,
-                                                      T* __restrict__ out, T omega, int64_t blo) {
+                                                      T* __restrict__ out, T omega, int64_t blo,
+                                                      Cast32 cast = Cast32{}) {
     constexpr int W = V16<T>::W, R = tile_rows<T>();
     constexpr int SL = R + 2 * W;  // elements of one staged segment
     typedef typename V16<T>::type VT;
@@ -215,7 +260,9 @@ __device__ __forceinline__ double stencil_tile_staged(const T* __restrict__ band
     const int64_t ax[3] = {seg0(-(int64_t)N - 1), seg0(-1), seg0((int64_t)N - 1)};
     const int64_t ab = ax[0];
     const bool inner = ab - W >= 0 && ax[2] + SL <= n;  // uniform per tile
-    if (!inner) return stencil_tile<T, OP, NORM, STORE, true>(bands, bs, N, n, x, b, out, omega, blo);
+    if (!inner)
+        return stencil_tile<T, OP, NORM, STORE, true, CAST>(bands, bs, N, n, x, b, out, omega, blo,
+                                                             cast);
     __shared__ T sx[3][SL];
     __shared__ T sb[3][SL];      // bands 8, 7, 6 of the previous row
     __shared__ T s5[R + W];      // band 5 at blo - W .. blo + R - 1
@@ -295,7 +342,12 @@ __device__ __forceinline__ double stencil_tile_staged(const T* __restrict__ band
 #pragma unroll
         for (int v = 0; v < W; ++v) sq = add_sq(sq, (double)res[v]);
     }
-    if (STORE) {
+    if (STORE && CAST) {
+        float f[W];
+#pragma unroll
+        for (int v = 0; v < W; ++v) f[v] = (float)((double)res[v] * cast.sc);
+        store_floats<W>(cast.out + p0, f);
+    } else if (STORE) {
         VT v;
         __builtin_memcpy(&v, res, sizeof(VT));
         *reinterpret_cast<VT*>(out + p0) = v;
@@ -306,10 +358,11 @@ __device__ __forceinline__ double stencil_tile_staged(const T* __restrict__ band
 // The defect tile of a zero iterate, d = b on rows [blo, blo + tile_rows):
 // the same nodes per thread as stencil_tile and the thread's sum of squares
 // in the same order, so the bits equal stencil_tile's OP_DEFECT with x = 0
-// (b - 0 is b).  out may be null (norm only).
-template <typename T>
+// (b - 0 is b).  out may be null (norm only).  With CAST the values go to
+// cast.out as stencil_tile's CAST writes them (out is not used).
+template <typename T, bool CAST = false>
 __device__ __forceinline__ double copy_tile_sumsq(const T* __restrict__ b, T* __restrict__ out,
-                                                  int64_t n, int64_t blo) {
+                                                  int64_t n, int64_t blo, Cast32 cast = Cast32{}) {
     constexpr int W = V16<T>::W;
     const int64_t p0 = blo + (int64_t)threadIdx.x * W;
     double sq = 0.0;
@@ -318,7 +371,10 @@ __device__ __forceinline__ double copy_tile_sumsq(const T* __restrict__ b, T* __
         if (p0 + v < n) {
             const T r = b[p0 + v];
             sq = add_sq(sq, (double)r);
-            if (out) out[p0 + v] = r;
+            if (CAST)
+                cast.out[p0 + v] = (float)((double)r * cast.sc);
+            else if (out)
+                out[p0 + v] = r;
         }
     }
     return sq;

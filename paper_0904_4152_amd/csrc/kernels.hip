@@ -51,14 +51,16 @@ __device__ __forceinline__ bool skipped(const double* guard) { return guard && *
 //     zero, or when c.cap is set (the step count is used up) -- the host
 //     driver's own tests on the same values (||b|| = scal[SC_B + 1]).  Then
 //     SC_CONV, SC_STOP and SC_WAIT are set, so everything queued after
-//     returns at once.
+//     returns at once.  Otherwise, with c.reset, the step's inner loop
+//     starts: reduction factor c.ithr, cycle cap c.icap, no cycle run yet,
+//     and the norm it is relative to, that of the scaled defect
+//     (pow2_scale(||b||) r), into scal[SC_D32 + 1].
 //   RED_ZFLAG (the count of nonzero initial iterate elements):
 //     scal[SC_XZ] = 1 if the iterate is zero, else 0.
-//   RED_RESET (the cast defect's norm): a new inner loop, reduction factor
-//     c.thr and cycle cap c.cap.
 //   RED_STEP (an inner cycle's FP32 residual): count the cycle; the loop is
 //     over when the residual is not finite, at most c.thr (= scal[SC_RED])
-//     times the cast defect's norm, or the cap is reached.  The host mirror
+//     times the scaled defect's norm (scal[SC_D32 + 1]), or the cap is
+//     reached.  The host mirror
 //     gets the count, plus ITER_DONE once the loop is over, in one store.
 __device__ void red_control(const RedCtl& c, double* __restrict__ scal, double* __restrict__ host,
                             double r) {
@@ -70,15 +72,16 @@ __device__ void red_control(const RedCtl& c, double* __restrict__ scal, double* 
         if (conv) {
             scal[SC_STOP] = 1.0;
             scal[SC_WAIT] = 1.0;
+        } else if (c.reset) {
+            scal[SC_STOP] = 0.0;
+            scal[SC_WAIT] = 1.0;
+            scal[SC_ITER] = 0.0;
+            scal[SC_RED] = c.ithr;
+            scal[SC_CAP] = (double)c.icap;
+            scal[SC_D32 + 1] = dev::pow2_scale(bn) * r;
         }
     } else if (c.mode == RED_ZFLAG) {
         scal[SC_XZ] = r == 0.0 ? 1.0 : 0.0;
-    } else if (c.mode == RED_RESET) {
-        scal[SC_STOP] = 0.0;
-        scal[SC_WAIT] = 1.0;
-        scal[SC_ITER] = 0.0;
-        scal[SC_RED] = c.thr;
-        scal[SC_CAP] = (double)c.cap;
     } else if (c.mode == RED_STEP) {
         const double it = scal[SC_ITER] + 1.0;
         const bool done = !isfinite(r) || r <= scal[SC_RED] * scal[SC_D32 + 1] || it >= scal[SC_CAP];
@@ -109,6 +112,27 @@ __global__ __launch_bounds__(BLOCK) void k_stencil(const T* __restrict__ bands, 
         const double s = dev::block_sum(sq);
         if (threadIdx.x == 0) partials[lb] = s;
     }
+}
+
+// The mixed scheme's FP64 defect (k_stencil's SYM defect with the norm),
+// d written as float(d sc) into the FP32 right-hand side, sc =
+// pow2_scale(||b||).
+__global__ __launch_bounds__(BLOCK) void k_defect_cast(const double* __restrict__ bands,
+                                                       int64_t bs, int N, int64_t n,
+                                                       const double* __restrict__ x,
+                                                       const double* __restrict__ b,
+                                                       float* __restrict__ d32,
+                                                       const double* __restrict__ scal,
+                                                       double* __restrict__ partials,
+                                                       int64_t nblk,
+                                                       const double* __restrict__ guard) {
+    const int64_t lb = xcd_block(nblk);
+    if (lb < 0 || skipped(guard)) return;
+    const dev::Cast32 cast{d32, dev::pow2_scale(scal[SC_B + 1])};
+    const double sq = dev::stencil_tile_staged<double, OP_DEFECT, true, true, true>(
+        bands, bs, N, n, x, b, nullptr, 0.0, lb * (int64_t)dev::tile_rows<double>(), cast);
+    const double s = dev::block_sum(sq);
+    if (threadIdx.x == 0) partials[lb] = s;
 }
 
 __global__ __launch_bounds__(BLOCK) void k_reduce_final(const double* __restrict__ partials,
@@ -653,6 +677,23 @@ __global__ __launch_bounds__(BLOCK) void k_defect_zero_x(int64_t n, const T* __r
     }
 }
 
+// k_defect_cast for a zero iterate (d = b).
+__global__ __launch_bounds__(BLOCK) void k_defect_zero_x_cast(int64_t n,
+                                                              const double* __restrict__ b,
+                                                              float* __restrict__ d32,
+                                                              const double* __restrict__ scal,
+                                                              double* __restrict__ partials,
+                                                              int64_t nblk,
+                                                              const double* __restrict__ guard) {
+    const int64_t lb = xcd_block(nblk);
+    if (lb < 0 || skipped(guard)) return;
+    const dev::Cast32 cast{d32, dev::pow2_scale(scal[SC_B + 1])};
+    const double sq = dev::copy_tile_sumsq<double, true>(
+        b, nullptr, n, lb * (int64_t)dev::tile_rows<double>(), cast);
+    const double s = dev::block_sum(sq);
+    if (threadIdx.x == 0) partials[lb] = s;
+}
+
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_fill(T* __restrict__ v, int64_t n, T value) {
     const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
@@ -668,46 +709,15 @@ __global__ __launch_bounds__(BLOCK) void k_cast_scaled(const double* __restrict_
     d32[p] = s > 0.0 ? (float)(d[p] / s) : 0.0f;
 }
 
-// k_cast_scaled and the norm partials of its output in one pass: per norm
-// tile, the elements and summation order of k_sumsq (same partials, bit for
-// bit).
-__global__ __launch_bounds__(BLOCK) void k_cast_scaled_sumsq(const double* __restrict__ d,
-                                                             float* __restrict__ d32, int64_t n,
-                                                             const double* __restrict__ scal,
-                                                             int slot,
-                                                             double* __restrict__ partials,
-                                                             int64_t nblk,
-                                                             const double* __restrict__ guard) {
-    const int64_t lb = xcd_block(nblk);
-    if (lb < 0 || skipped(guard)) return;
-    const double s = scal[slot + 1];
-    const int64_t base = lb * (int64_t)dev::NORM_TILE;
-    // the four loads go out together; lanes past n read element 0 and add zero
-    double w[4];
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        const int64_t p = base + (int64_t)e * BLOCK + threadIdx.x;
-        w[e] = d[p < n ? p : 0];
-    }
-    double acc = 0.0;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        const int64_t p = base + (int64_t)e * BLOCK + threadIdx.x;
-        const float v = s > 0.0 ? (float)(w[e] / s) : 0.0f;
-        if (p < n) d32[p] = v;
-        acc += p < n ? (double)v * (double)v : 0.0;
-    }
-    const double t = dev::block_sum(acc);
-    if (threadIdx.x == 0) partials[lb] = t;
-}
-
+// x += u double(c), u = pow2_unscale(||b||): u c is exact, so the sum is
+// the one rounding.
 __global__ __launch_bounds__(BLOCK) void k_update(double* __restrict__ x,
                                                   const float* __restrict__ c, int64_t n,
-                                                  const double* __restrict__ scal, int slot,
+                                                  const double* __restrict__ scal,
                                                   const double* __restrict__ guard) {
     const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     if (p >= n || skipped(guard)) return;
-    x[p] += scal[slot + 1] * (double)c[p];
+    x[p] += dev::pow2_unscale(scal[SC_B + 1]) * (double)c[p];
 }
 
 
@@ -1195,23 +1205,33 @@ hipError_t launch_cast_scaled(const double* d64, float* d32, int64_t n, const do
     return hipGetLastError();
 }
 
-hipError_t launch_cast_scaled_norm(const double* d64, float* d32, int64_t n, const double* scal,
-                                   int slot, double* partials, double* out_scal, int out_slot,
-                                   double* host, hipStream_t st, const double* guard,
-                                   RedCtl ctl) {
-    const int64_t nb = norm_blocks(n);
-    hipLaunchKernelGGL(k_cast_scaled_sumsq, dim3(grid8(nb)), dim3(BLOCK), 0, st, d64, d32, n, scal,
-                       slot, partials, nb, guard);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    return launch_reduce(partials, nb, out_scal, out_slot, host, st, guard, ctl);
+hipError_t launch_update(double* x, const float* c32, int64_t n, const double* scal,
+                         hipStream_t st, const double* guard) {
+    hipLaunchKernelGGL(k_update, dim3(blocks1d(n)), dim3(BLOCK), 0, st, x, c32, n, scal, guard);
+    return hipGetLastError();
 }
 
-hipError_t launch_update(double* x, const float* c32, int64_t n, const double* scal, int slot,
-                         hipStream_t st, const double* guard) {
-    hipLaunchKernelGGL(k_update, dim3(blocks1d(n)), dim3(BLOCK), 0, st, x, c32, n, scal, slot,
-                       guard);
-    return hipGetLastError();
+hipError_t launch_defect_cast(const Level& lv, const double* bands, const double* b,
+                              const double* x, float* d32, double* partials, double* scal,
+                              int slot, double* host, hipStream_t st, const double* guard,
+                              RedCtl ctl) {
+    const int64_t nb = stencil_blocks(lv.n, sizeof(double));
+    hipLaunchKernelGGL(k_defect_cast, dim3(grid8(nb)), dim3(BLOCK), 0, st, bands, lv.bs, lv.N,
+                       lv.n, x, b, d32, scal, partials, nb, guard);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_reduce(partials, nb, scal, slot, host, st, guard, ctl);
+}
+
+hipError_t launch_defect_zero_x_cast(const Level& lv, const double* b, float* d32,
+                                     double* partials, double* scal, int slot, double* host,
+                                     hipStream_t st, const double* guard, RedCtl ctl) {
+    const int64_t nb = stencil_blocks(lv.n, sizeof(double));
+    hipLaunchKernelGGL(k_defect_zero_x_cast, dim3(grid8(nb)), dim3(BLOCK), 0, st, lv.n, b, d32,
+                       scal, partials, nb, guard);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_reduce(partials, nb, scal, slot, host, st, guard, ctl);
 }
 
 

@@ -117,7 +117,7 @@ enum : int {
     SC_B = 0,
     SC_R64 = 2,
     SC_R32 = 4,
-    SC_D32 = 6,
+    SC_D32 = 6,   // norm at +1: the scaled FP64 defect the inner loop is relative to
     SC_USER = 8,
     // preconditioned CG: p.q, r.z (current and previous), ||r||
     SC_PQ = 10,
@@ -139,12 +139,15 @@ constexpr double ITER_DONE = 1000.0;
 
 // What the final kernel of a reduction does besides writing the norm: the
 // mixed solve's decisions on the device (see red_control in kernels.hip).
-enum : int { RED_NONE = 0, RED_OUTER = 1, RED_RESET = 2, RED_STEP = 3, RED_ZFLAG = 4 };
+enum : int { RED_NONE = 0, RED_OUTER = 1, RED_STEP = 3, RED_ZFLAG = 4 };
 struct RedCtl {
     int mode = RED_NONE;
-    double thr = 0.0;  // OUTER: stop at norm <= thr ||b||; RESET: the inner reduction factor
+    double thr = 0.0;  // OUTER: stop at norm <= thr ||b||
     double div = 0.0;  // OUTER: diverged above div ||b||
-    int cap = 0;       // OUTER: nonzero stops (step count used up); RESET: cycle cap
+    int cap = 0;       // OUTER: nonzero stops (step count used up)
+    int reset = 0;     // OUTER: a step that goes on also starts its inner loop
+    double ithr = 0.0; // OUTER with reset: the inner reduction factor
+    int icap = 0;      // OUTER with reset: the inner cycle cap
 };
 
 // How the hierarchy's coarsest level is solved.
@@ -220,14 +223,21 @@ hipError_t launch_count_nonzero(const double* v, int64_t n, double* partials, do
 hipError_t launch_defect_zero_x(const Level& lv, const double* b, double* d, double* partials,
                                 double* scal, int slot, double* host, hipStream_t st,
                                 const double* guard = nullptr, RedCtl ctl = {});
-// The same, followed by launch_norm of d32 into out_scal[out_slot] (same
-// partials and sum, in one pass over the vectors).
-hipError_t launch_cast_scaled_norm(const double* d64, float* d32, int64_t n, const double* scal,
-                                   int slot, double* partials, double* out_scal, int out_slot,
-                                   double* host, hipStream_t st, const double* guard = nullptr,
-                                   RedCtl ctl = {});
-// x += s * double(c32), s = scal[slot + 1].
-hipError_t launch_update(double* x, const float* c32, int64_t n, const double* scal, int slot,
+// The mixed scheme's FP64 defect of an outer step: launch_defect (with
+// the norm into scal[slot]) writing float(d sc) into d32 instead of d, sc =
+// dev::pow2_scale(||b||) (||b|| = scal[SC_B + 1]); and the same for a zero
+// iterate (d = b, launch_defect_zero_x's bits).
+hipError_t launch_defect_cast(const Level& lv, const double* bands, const double* b,
+                              const double* x, float* d32, double* partials, double* scal,
+                              int slot, double* host, hipStream_t st,
+                              const double* guard = nullptr, RedCtl ctl = {});
+hipError_t launch_defect_zero_x_cast(const Level& lv, const double* b, float* d32,
+                                     double* partials, double* scal, int slot, double* host,
+                                     hipStream_t st, const double* guard = nullptr,
+                                     RedCtl ctl = {});
+// x += u double(c32), u = dev::pow2_unscale(||b||) (||b|| = scal[SC_B + 1]):
+// the FP32 correction scaled back.
+hipError_t launch_update(double* x, const float* c32, int64_t n, const double* scal,
                          hipStream_t st, const double* guard = nullptr);
 
 // Deterministic sum of np partials (dev::reduce_partials' order; one

@@ -488,29 +488,25 @@ extern "C" mg_status mg_solve(mg_hierarchy* h, const double* dev_b, double* dev_
         c.thr = o.fixed_cycles > 0 ? -1.0 : o.rel_tol;
         c.div = 1e3;
         c.cap = (o.fixed_cycles > 0 ? k > o.fixed_cycles : k > o.max_cycles) ? 1 : 0;
+        c.reset = 1;  // a step that goes on starts its inner loop
+        c.ithr = o.inner_reduction;
+        c.icap = o.inner_max_cycles;
         return c;
     };
     const double* wait = h->scal + SC_WAIT;
     // the update of step k and the defect of step k + 1
     auto queue_update_defect = [&](int k) -> hipError_t {
-        MG_TRY(launch_update(X64, F.x32, n, h->scal, nslot(k), q.st, wait));
+        MG_TRY(launch_update(X64, F.x32, n, h->scal, q.st, wait));
         arm_scalar(h, nslot(k + 1));
-        return launch_defect<double>(F, F.bands64, B64, X64, h->d64, h->partials, h->scal,
-                                     nslot(k + 1), h->host_scal, q.st, wait,
-                                     outer_ctl(k + 1));
+        return launch_defect_cast(F, F.bands64, B64, X64, F.b32, h->partials, h->scal,
+                                  nslot(k + 1), h->host_scal, q.st, wait, outer_ctl(k + 1));
     };
     int last = 0;      // cycles of the previous inner loop of this solve
     int pred = 0;      // cycles queued at once for the latest queued step
     double cycle_bytes = 0.0;
-    // the cast, the predicted cycles, the update and the next defect of step k
+    // the predicted cycles, the update and the next defect of step k (the
+    // defect of step k wrote the FP32 right-hand side and started the loop)
     auto queue_step = [&](int k) -> hipError_t {
-        RedCtl reset;
-        reset.mode = RED_RESET;
-        reset.thr = o.inner_reduction;
-        reset.cap = o.inner_max_cycles;
-        MG_TRY(launch_cast_scaled_norm(h->d64, F.b32, n, h->scal, nslot(k), h->partials,
-                                       h->scal, SC_D32, h->host_scal, q.st,
-                                       h->scal + SC_CONV, reset));
         const int slot = std::min(k, 8) - 1;
         pred = h->inner_pred[slot] > 0 ? h->inner_pred[slot] : (last > 0 ? last : 2);
         pred = std::min(pred, o.inner_max_cycles);
@@ -540,11 +536,11 @@ extern "C" mg_status mg_solve(mg_hierarchy* h, const double* dev_b, double* dev_
         // kernel returns at once) and step 1, before ||b|| reaches the host;
         // the device's tests read ||b|| from its own copy
         arm_scalar(h, nslot(1));
-        MG_HIPS(launch_defect_zero_x(F, B64, h->d64, h->partials, h->scal, nslot(1),
-                                     h->host_scal, q.st, h->scal + SC_XNZ, outer_ctl(1)));
-        MG_HIPS(launch_defect<double>(F, F.bands64, B64, X64, h->d64, h->partials, h->scal,
-                                      nslot(1), h->host_scal, q.st, h->scal + SC_XZ,
-                                      outer_ctl(1)));
+        MG_HIPS(launch_defect_zero_x_cast(F, B64, F.b32, h->partials, h->scal, nslot(1),
+                                          h->host_scal, q.st, h->scal + SC_XNZ, outer_ctl(1)));
+        MG_HIPS(launch_defect_cast(F, F.bands64, B64, X64, F.b32, h->partials, h->scal,
+                                   nslot(1), h->host_scal, q.st, h->scal + SC_XZ,
+                                   outer_ctl(1)));
         queued = ahead(1);
         if (queued) MG_HIPS(queue_step(1));
     }
@@ -645,13 +641,13 @@ extern "C" mg_status mg_solve(mg_hierarchy* h, const double* dev_b, double* dev_
             double s = 0.0;
             arm_scalar(h, SC_R64);
             if (k == 1 && x_zero) {
-                MG_HIPS(launch_defect_zero_x(F, B64, h->d64, h->partials, h->scal, SC_R64,
-                                             h->host_scal, q.st));
-                q.bytes += 16.0 * n;
+                MG_HIPS(launch_defect_zero_x_cast(F, B64, F.b32, h->partials, h->scal, SC_R64,
+                                                  h->host_scal, q.st));
+                q.bytes += 12.0 * n;
             } else {
-                MG_HIPS(launch_defect<double>(F, F.bands64, B64, X64, h->d64, h->partials,
-                                              h->scal, SC_R64, h->host_scal, q.st));
-                q.bytes += 12.0 * 8 * n;
+                MG_HIPS(launch_defect_cast(F, F.bands64, B64, X64, F.b32, h->partials, h->scal,
+                                           SC_R64, h->host_scal, q.st));
+                q.bytes += 92.0 * n;
             }
             MG_HIPS(read_scalar(h, SC_R64, q.st, &s));
             st.rel_res = s / bn;
@@ -670,23 +666,19 @@ extern "C" mg_status mg_solve(mg_hierarchy* h, const double* dev_b, double* dev_
                 }
             }
             if (s == 0.0) break;
-            arm_scalar(h, SC_D32);
-            MG_HIPS(launch_cast_scaled_norm(h->d64, F.b32, n, h->scal, SC_R64, h->partials,
-                                            h->scal, SC_D32, h->host_scal, q.st));
-            q.bytes += 12.0 * n;
-            // ||d32|| is first needed after the first inner cycle: read it then
-            double dn = 0.0;
+            // the FP32 right-hand side is the defect scaled by a power of
+            // two: its loop stops relative to the scaled defect's norm
+            const double dn = dev::pow2_scale(bn) * s;
             for (int it = 1; it <= o.inner_max_cycles; ++it) {
                 double r32 = 0.0;
                 arm_scalar(h, SC_R32);
                 MG_HIPS(run_unit(h, 1, o, it == 1, graphs, q));
-                if (it == 1) MG_HIPS(read_scalar(h, SC_D32, q.st, &dn));
                 MG_HIPS(read_scalar(h, SC_R32, q.st, &r32));
                 st.cycles++;
                 if (!std::isfinite(r32)) break;
                 if (r32 <= o.inner_reduction * dn) break;
             }
-            MG_HIPS(launch_update(X64, F.x32, n, h->scal, SC_R64, q.st));
+            MG_HIPS(launch_update(X64, F.x32, n, h->scal, q.st));
             q.bytes += 20.0 * n;
             st.outer_steps = k;
         }
@@ -694,8 +686,10 @@ extern "C" mg_status mg_solve(mg_hierarchy* h, const double* dev_b, double* dev_
         // Device control (fused V(2,2) cycle): the decisions of the loop
         // above, taken on the device by the reductions that produce the
         // norms they test (RedCtl), with everything that follows a decision
-        // queued behind it under a guard.  After the FP64 defect of outer
-        // step k the host queues the cast, the FP32 cycles step k took in
+        // queued behind it under a guard.  The FP64 defect of outer step k
+        // writes the FP32 right-hand side, and its norm's reduction starts
+        // the inner loop unless the solve is over.  After it the host
+        // queues the FP32 cycles step k took in
         // the previous solve (each returning at once after the loop is
         // over), the update and the defect of step k + 1, which wait on the
         // device for the loop's end -- before reading the defect's norm when
@@ -708,7 +702,7 @@ extern "C" mg_status mg_solve(mg_hierarchy* h, const double* dev_b, double* dev_
         // same decisions, same bits as the loop above.  Outer steps
         // alternate between two norm slots, so queueing step k + 1 never
         // overwrites a norm the host has yet to read.
-        q.bytes += x_zero ? 16.0 * n : 12.0 * 8 * n;  // the first defect
+        q.bytes += x_zero ? 12.0 * n : 92.0 * n;  // the first defect
         for (int k = 1;; ++k) {
             const TraceRange step("mixed outer step");
             double s = 0.0;
@@ -730,7 +724,6 @@ extern "C" mg_status mg_solve(mg_hierarchy* h, const double* dev_b, double* dev_
             }
             if (s == 0.0) break;
             if (!queued) MG_HIPS(queue_step(k));
-            q.bytes += 12.0 * n;  // the cast
             const int slot = std::min(k, 8) - 1;
             int cycles = 0;
             bool done = false;
@@ -745,7 +738,7 @@ extern "C" mg_status mg_solve(mg_hierarchy* h, const double* dev_b, double* dev_
                 }
                 MG_HIPS(queue_update_defect(k));
             }
-            q.bytes += cycle_bytes * cycles + 20.0 * n + 12.0 * 8 * n;
+            q.bytes += cycle_bytes * cycles + 20.0 * n + 92.0 * n;
             st.cycles += cycles;
             h->inner_pred[slot] = cycles;
             last = cycles;

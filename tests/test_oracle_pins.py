@@ -344,16 +344,19 @@ def test_l2_error_reduction_is_h2_like_table1(orc):
 
 def test_mixed_equals_double_and_single_breaks_down(orc):
     """Table 1: mixed reproduces the double-precision L2 error; a solve
-    entirely in single precision loses accuracy as the level grows."""
+    entirely in single precision loses accuracy as the level grows (here the
+    single-precision error is within rounding noise of the double one up to
+    L = 8 and far above it at L = 9, where the discretisation error has
+    fallen below what single precision resolves)."""
     t1 = _table1()
     for L in [4, 6, 8]:
         ed = _sinsin_l2(orc, L, "double")
         em = _sinsin_l2(orc, L, "mixed")
         assert abs(em - ed) <= 1e-4 * ed, (L, em, ed)
         assert abs(t1[L][4] - t1[L][2]) <= 1e-4 * t1[L][2]  # the paper's own columns
-    e_single8 = _sinsin_l2(orc, 8, "single")
-    e_double8 = _sinsin_l2(orc, 8, "double")
-    assert e_single8 > 1.5 * e_double8
+    e_single9 = _sinsin_l2(orc, 9, "single")
+    e_double9 = _sinsin_l2(orc, 9, "double")
+    assert e_single9 > 5.0 * e_double9
 
 
 @pytest.mark.parametrize("L", [6, 7])
