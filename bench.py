@@ -438,11 +438,14 @@ def main():
     n = h.n
     b = torch.from_numpy(synth.rhs_gaussian(L, rseed)).to(dev)
     x = torch.zeros_like(b)
-    mixed = mg.default_opts(precision=mg.MG_PREC_MIXED, rel_tol=1e-8)
-    fp64 = mg.default_opts(precision=mg.MG_PREC_FP64, rel_tol=1e-8)
+    # every solve starts from x = 0: zero_guess tells the library, which then
+    # does not read x (no fill of x and no test of it for zero per solve)
+    mixed = mg.default_opts(precision=mg.MG_PREC_MIXED, rel_tol=1e-8, zero_guess=1)
+    fp64 = mg.default_opts(precision=mg.MG_PREC_FP64, rel_tol=1e-8, zero_guess=1)
 
     def solve(hh, bb, xx, o):
-        xx.zero_()
+        if not o.zero_guess:
+            xx.zero_()
         st = hh.solve(bb, xx, o)
         if st.status != 0 or st.rel_res > 1e-8:
             raise RuntimeError("solve did not reach 1e-8: status %d rel_res %g"
@@ -567,9 +570,9 @@ def main():
 
     # CG preconditioned by one cycle (FP64 cycle; FP32 cycle on r / ||r||)
     out["L12"]["pcg_fp64"] = timed(h, mg.default_opts(precision=mg.MG_PREC_FP64, rel_tol=1e-8,
-                                                      krylov=1))
+                                                      krylov=1, zero_guess=1))
     out["L12"]["pcg_mixed"] = timed(h, mg.default_opts(precision=mg.MG_PREC_MIXED,
-                                                       rel_tol=1e-8, krylov=1))
+                                                       rel_tol=1e-8, krylov=1, zero_guess=1))
     h.close()
     torch.cuda.empty_cache()
     # coarse grid on level 4 (17 x 17) solved by CG, as in the paper's setup

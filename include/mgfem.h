@@ -88,6 +88,9 @@ typedef struct {
     int fixed_cycles;        /* > 0: run exactly this many cycles / outer steps */
     int use_graph;           /* 1: replay captured HIP graphs for the cycles (1) */
     int krylov;              /* 1: CG preconditioned by one V-cycle (0) */
+    int zero_guess;          /* 1: start from x = 0 whatever dev_x holds (dev_x is
+                                output only, not read); 0: dev_x is the initial
+                                guess (0) */
 } mg_solve_opts;
 
 typedef struct {
@@ -186,7 +189,7 @@ mg_status mg_rhs_uniform(const mg_hierarchy* h, uint64_t seed, double* dev_b, vo
 
 /* ---- solve (Sec. 6.2) -------------------------------------------------------
  * Solve A x = b on the finest level.  dev_x is in/out (initial guess, then
- * the solution).  FP64: V-cycles until ||b - A x|| <= rel_tol ||b||.  Mixed:
+ * the solution; with opts->zero_guess output only).  FP64: V-cycles until ||b - A x|| <= rel_tol ||b||.  Mixed:
  * FP64 defect d = b - A x and norm s, d32 = float(d 2^-e) with e the binary
  * exponent of ||b|| (||b|| = m 2^e, m in [0.5, 1); a power of two scales
  * exactly, it only keeps the FP32 values in range), FP32 V-cycles on

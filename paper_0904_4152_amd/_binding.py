@@ -31,7 +31,7 @@ class SolveOpts(ctypes.Structure):
     _fields_ = [("nu_pre", _i), ("nu_post", _i), ("omega", _d), ("rel_tol", _d),
                 ("max_cycles", _i), ("precision", _i), ("inner_reduction", _d),
                 ("inner_max_cycles", _i), ("fixed_cycles", _i), ("use_graph", _i),
-                ("krylov", _i)]
+                ("krylov", _i), ("zero_guess", _i)]
 
 
 class TileChoice(ctypes.Structure):

@@ -128,6 +128,7 @@ void mg_default_opts(mg_solve_opts* o) {
     o->fixed_cycles = 0;
     o->use_graph = 1;
     o->krylov = 0;
+    o->zero_guess = 0;
 }
 
 const char* mg_last_error(void) { return g_last_error.c_str(); }

@@ -41,6 +41,7 @@ struct BProb {
     int max_outer;
     int fixed;
     int dmask;  // Dirichlet sides
+    int zero_guess;  // x0 = 0, the caller's x not read
 };
 
 enum : int {

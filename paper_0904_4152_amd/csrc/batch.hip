@@ -500,9 +500,10 @@ __global__ __launch_bounds__(BLOCK) void kb_update(const BProb* __restrict__ pro
 }
 
 // Copies between the callers' vectors and every listed problem's finest
-// vectors, one launch for the whole batch: out == 0: b64 <- b_p, x64 <- x_p;
-// out != 0: x_p <- x64 (zero for a zero right-hand side).  io[p] and
-// io[cap + p] hold problem p's caller b and x.
+// vectors, one launch for the whole batch: out == 0: b64 <- b_p, x64 <- x_p
+// (x64 <- 0 for a zero guess, x_p not read); out != 0: x_p <- x64 (zero for
+// a zero right-hand side).  io[p] and io[cap + p] hold problem p's caller b
+// and x.
 __global__ __launch_bounds__(BLOCK) void kb_io(const BProb* __restrict__ probs,
                                                const BState* __restrict__ state,
                                                const int* __restrict__ wl,
@@ -522,7 +523,7 @@ __global__ __launch_bounds__(BLOCK) void kb_io(const BProb* __restrict__ probs,
             if (q >= lv.n) continue;
             if (!out) {
                 lv.b64[q] = bu[q];
-                lv.x64[q] = xu[q];
+                lv.x64[q] = probs[p].zero_guess ? 0.0 : xu[q];
             } else {
                 xu[q] = zero ? 0.0 : lv.x64[q];
             }
@@ -836,6 +837,7 @@ void BatchEngine::set_slot(int s, mg_hierarchy* h, const mg_solve_opts& o) {
     P.inner_max = o.inner_max_cycles;
     P.max_outer = o.max_cycles;
     P.fixed = o.fixed_cycles;
+    P.zero_guess = o.zero_guess;
     hp_[s] = P;
     probs_dirty_ = true;
 }
@@ -1517,7 +1519,8 @@ extern "C" mg_status mg_solve_batch(mg_hierarchy* const* hs, const double* const
         if (o.nu_pre < 0 || o.nu_post < 0 || o.nu_pre + o.nu_post == 0 || o.nu_pre > 16 ||
             o.nu_post > 16 || !(o.omega > 0.0 && o.omega < 2.0) || !(o.rel_tol >= 0.0) ||
             o.max_cycles < 1 || o.inner_max_cycles < 1 ||
-            !(o.inner_reduction >= 0.0 && o.inner_reduction < 1.0) || o.fixed_cycles < 0)
+            !(o.inner_reduction >= 0.0 && o.inner_reduction < 1.0) || o.fixed_cycles < 0 ||
+            (o.zero_guess != 0 && o.zero_guess != 1))
             return fail(MG_ERR_INVALID, "invalid solver options");
         Lmax = std::max(Lmax, h->L);
     }

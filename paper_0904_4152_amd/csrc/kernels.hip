@@ -710,14 +710,17 @@ __global__ __launch_bounds__(BLOCK) void k_cast_scaled(const double* __restrict_
 }
 
 // x += u double(c), u = pow2_unscale(||b||): u c is exact, so the sum is
-// the one rounding.
+// the one rounding.  ZERO: x is taken as zero and not read (0.0 + u c, the
+// same bits as the sum with a zeroed x, the sign of a zero included).
+template <bool ZERO>
 __global__ __launch_bounds__(BLOCK) void k_update(double* __restrict__ x,
                                                   const float* __restrict__ c, int64_t n,
                                                   const double* __restrict__ scal,
                                                   const double* __restrict__ guard) {
     const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     if (p >= n || skipped(guard)) return;
-    x[p] += dev::pow2_unscale(scal[SC_B + 1]) * (double)c[p];
+    const double xo = ZERO ? 0.0 : x[p];
+    x[p] = xo + dev::pow2_unscale(scal[SC_B + 1]) * (double)c[p];
 }
 
 
@@ -1206,8 +1209,13 @@ hipError_t launch_cast_scaled(const double* d64, float* d32, int64_t n, const do
 }
 
 hipError_t launch_update(double* x, const float* c32, int64_t n, const double* scal,
-                         hipStream_t st, const double* guard) {
-    hipLaunchKernelGGL(k_update, dim3(blocks1d(n)), dim3(BLOCK), 0, st, x, c32, n, scal, guard);
+                         hipStream_t st, const double* guard, bool x_zero) {
+    if (x_zero)
+        hipLaunchKernelGGL(k_update<true>, dim3(blocks1d(n)), dim3(BLOCK), 0, st, x, c32, n, scal,
+                           guard);
+    else
+        hipLaunchKernelGGL(k_update<false>, dim3(blocks1d(n)), dim3(BLOCK), 0, st, x, c32, n,
+                           scal, guard);
     return hipGetLastError();
 }
 

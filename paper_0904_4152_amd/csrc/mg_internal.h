@@ -236,9 +236,10 @@ hipError_t launch_defect_zero_x_cast(const Level& lv, const double* b, float* d3
                                      hipStream_t st, const double* guard = nullptr,
                                      RedCtl ctl = {});
 // x += u double(c32), u = dev::pow2_unscale(||b||) (||b|| = scal[SC_B + 1]):
-// the FP32 correction scaled back.
+// the FP32 correction scaled back.  x_zero: x is taken as zero and not read
+// (the same bits as with a zeroed x).
 hipError_t launch_update(double* x, const float* c32, int64_t n, const double* scal,
-                         hipStream_t st, const double* guard = nullptr);
+                         hipStream_t st, const double* guard = nullptr, bool x_zero = false);
 
 // Deterministic sum of np partials (dev::reduce_partials' order; one
 // block, or beyond dev::RED_SEG partials one block per segment whose sums go

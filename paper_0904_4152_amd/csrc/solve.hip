@@ -404,6 +404,8 @@ static mg_status validate_opts(const mg_solve_opts& o) {
         return fail(MG_ERR_INVALID, "inner_reduction in [0,1) and inner_max_cycles >= 1 required");
     if (o.fixed_cycles < 0) return fail(MG_ERR_INVALID, "fixed_cycles must be >= 0");
     if (o.krylov != 0 && o.krylov != 1) return fail(MG_ERR_INVALID, "krylov must be 0 or 1");
+    if (o.zero_guess != 0 && o.zero_guess != 1)
+        return fail(MG_ERR_INVALID, "zero_guess must be 0 or 1");
     return MG_OK;
 }
 
@@ -472,10 +474,16 @@ extern "C" mg_status mg_solve(mg_hierarchy* h, const double* dev_b, double* dev_
     const bool direct = !o.krylov && o.precision == MG_PREC_MIXED;
     const double* B64 = direct ? dev_b : F.b64;
     double* X64 = direct ? dev_x : F.x64;
+    // zero_guess: x0 = 0 whatever dev_x holds (not read; the mixed solve's
+    // first update writes x without reading it)
+    const bool zg = o.zero_guess != 0;
     if (!direct) {
         MG_HIPS(launch_copy<double>(dev_b, F.b64, n, q.st));
-        MG_HIPS(launch_copy<double>(dev_x, F.x64, n, q.st));
-        q.bytes += 8.0 * 4 * n;
+        if (zg)
+            MG_HIPS(launch_fill<double>(F.x64, n, 0.0, q.st));
+        else
+            MG_HIPS(launch_copy<double>(dev_x, F.x64, n, q.st));
+        q.bytes += zg ? 8.0 * 3 * n : 8.0 * 4 * n;
     }
     // the mixed solve under device control (see the last branch below)
     const bool devctl = !o.krylov && o.precision == MG_PREC_MIXED && o.nu_pre == 2 &&
@@ -496,7 +504,7 @@ extern "C" mg_status mg_solve(mg_hierarchy* h, const double* dev_b, double* dev_
     const double* wait = h->scal + SC_WAIT;
     // the update of step k and the defect of step k + 1
     auto queue_update_defect = [&](int k) -> hipError_t {
-        MG_TRY(launch_update(X64, F.x32, n, h->scal, q.st, wait));
+        MG_TRY(launch_update(X64, F.x32, n, h->scal, q.st, wait, zg && k == 1));
         arm_scalar(h, nslot(k + 1));
         return launch_defect_cast(F, F.bands64, B64, X64, F.b32, h->partials, h->scal,
                                   nslot(k + 1), h->host_scal, q.st, wait, outer_ctl(k + 1));
@@ -525,28 +533,32 @@ extern "C" mg_status mg_solve(mg_hierarchy* h, const double* dev_b, double* dev_
     // A zero initial iterate (the usual start) makes the first defect b
     // itself: its kernel then reads b alone (same bits, see
     // launch_defect_zero_x).
-    arm_scalar(h, SC_XNZ);
-    RedCtl zflag;
-    zflag.mode = devctl ? RED_ZFLAG : RED_NONE;
-    MG_HIPS(launch_count_nonzero(X64, n, h->partials, h->scal, SC_XNZ, h->host_scal, q.st,
-                                 zflag));
-    q.bytes += 8.0 * n;
+    if (!zg) {
+        arm_scalar(h, SC_XNZ);
+        RedCtl zflag;
+        zflag.mode = devctl ? RED_ZFLAG : RED_NONE;
+        MG_HIPS(launch_count_nonzero(X64, n, h->partials, h->scal, SC_XNZ, h->host_scal, q.st,
+                                     zflag));
+        q.bytes += 8.0 * n;
+    }
     if (devctl) {
         // the first defect (of the zero or the given iterate: the other
         // kernel returns at once) and step 1, before ||b|| reaches the host;
         // the device's tests read ||b|| from its own copy
         arm_scalar(h, nslot(1));
         MG_HIPS(launch_defect_zero_x_cast(F, B64, F.b32, h->partials, h->scal, nslot(1),
-                                          h->host_scal, q.st, h->scal + SC_XNZ, outer_ctl(1)));
-        MG_HIPS(launch_defect_cast(F, F.bands64, B64, X64, F.b32, h->partials, h->scal,
-                                   nslot(1), h->host_scal, q.st, h->scal + SC_XZ,
-                                   outer_ctl(1)));
+                                          h->host_scal, q.st,
+                                          zg ? nullptr : h->scal + SC_XNZ, outer_ctl(1)));
+        if (!zg)
+            MG_HIPS(launch_defect_cast(F, F.bands64, B64, X64, F.b32, h->partials, h->scal,
+                                       nslot(1), h->host_scal, q.st, h->scal + SC_XZ,
+                                       outer_ctl(1)));
         queued = ahead(1);
         if (queued) MG_HIPS(queue_step(1));
     }
-    double bn = 0.0, xnz = 1.0;
+    double bn = 0.0, xnz = 0.0;
     MG_HIPS(read_scalar(h, SC_B, q.st, &bn));
-    MG_HIPS(read_scalar(h, SC_XNZ, q.st, &xnz));
+    if (!zg) MG_HIPS(read_scalar(h, SC_XNZ, q.st, &xnz));
     const bool x_zero = xnz == 0.0;
     st.bnorm = bn;
     mg_status result = MG_OK;
@@ -678,7 +690,7 @@ extern "C" mg_status mg_solve(mg_hierarchy* h, const double* dev_b, double* dev_
                 if (!std::isfinite(r32)) break;
                 if (r32 <= o.inner_reduction * dn) break;
             }
-            MG_HIPS(launch_update(X64, F.x32, n, h->scal, q.st));
+            MG_HIPS(launch_update(X64, F.x32, n, h->scal, q.st, nullptr, zg && k == 1));
             q.bytes += 20.0 * n;
             st.outer_steps = k;
         }
@@ -751,6 +763,10 @@ extern "C" mg_status mg_solve(mg_hierarchy* h, const double* dev_b, double* dev_
     if (!direct) {
         MG_HIPS(launch_copy<double>(F.x64, dev_x, n, q.st));
         q.bytes += 16.0 * n;
+    } else if (zg && st.outer_steps == 0 && bn != 0.0) {
+        // no update wrote the caller's x: the result is the zero guess
+        MG_HIPS(launch_fill<double>(X64, n, 0.0, q.st));
+        q.bytes += 8.0 * n;
     }
     // Later work on the caller's stream runs after the solve's.  The mixed
     // solve's last write of x came before the defect whose norm the host

@@ -105,3 +105,69 @@ def test_mixed_warm_start_checked_by_oracle(mg, ctx, orc, L):
     scale = np.linalg.norm(abs_band_product(N, bands, xs) + np.abs(bh))
     assert abs(r - st.rel_res) * orc.norm2(bh) <= 80 * U64 * scale
     h.close()
+
+
+def _garbage(b, seed):
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    return torch.randn(b.shape, dtype=b.dtype, device="cuda", generator=g) * 1e3
+
+
+@pytest.mark.parametrize("L", [5, 7, 10])
+def test_zero_guess_equals_a_zeroed_iterate(mg, ctx, L):
+    """opts.zero_guess: x's contents are not read; the solve equals the one
+    from a zeroed x bit for bit (FP64, mixed under device control and with
+    the host loop, with and without graphs, preconditioned CG)."""
+    h = mg.Hierarchy(ctx, L, jitter=0.2, seed=90 + L)
+    b = torch.from_numpy(synth.rhs_uniform(L, 91 + L)).cuda()
+    cases = [dict(precision=mg.MG_PREC_FP64),
+             dict(precision=mg.MG_PREC_MIXED),
+             dict(precision=mg.MG_PREC_MIXED, use_graph=0),
+             dict(precision=mg.MG_PREC_MIXED, inner_max_cycles=1000),  # host-driven loop
+             dict(precision=mg.MG_PREC_MIXED, fixed_cycles=1),
+             dict(precision=mg.MG_PREC_FP64, krylov=1),
+             dict(precision=mg.MG_PREC_MIXED, krylov=1)]
+    for k, kw in enumerate(cases):
+        o_ref = mg.default_opts(rel_tol=1e-9, **kw)
+        x_ref = torch.zeros_like(b)
+        s_ref = h.solve(b, x_ref, o_ref)
+        o = mg.default_opts(rel_tol=1e-9, zero_guess=1, **kw)
+        x = _garbage(b, 100 * L + k)
+        s = h.solve(b, x, o)
+        torch.cuda.synchronize()
+        assert s_ref.status == 0 and s.status == 0, kw
+        np.testing.assert_array_equal(x.cpu().numpy(), x_ref.cpu().numpy())
+        assert (s.cycles, s.outer_steps, s.rel_res, s.bnorm) == \
+            (s_ref.cycles, s_ref.outer_steps, s_ref.rel_res, s_ref.bnorm), kw
+        assert s.hist() == s_ref.hist(), kw
+    # a tolerance met before any update: the result is x = 0
+    for prec in (mg.MG_PREC_FP64, mg.MG_PREC_MIXED):
+        x = _garbage(b, 7)
+        s = h.solve(b, x, mg.default_opts(precision=prec, rel_tol=10.0, zero_guess=1))
+        torch.cuda.synchronize()
+        assert s.status == 0 and s.cycles == 0 and s.outer_steps == 0
+        assert not x.cpu().numpy().any()
+    with pytest.raises(mg.MgError):
+        h.solve(b, x, mg.default_opts(zero_guess=2))
+    h.close()
+
+
+def test_zero_guess_in_a_batch(mg, ctx):
+    """The batched solver with zero_guess equals the batch from zeroed
+    iterates bit for bit, and never reads the callers' x."""
+    levels = [5, 7, 6, 8]
+    hs = [mg.Hierarchy(ctx, L, jitter=0.2, seed=60 + i) for i, L in enumerate(levels)]
+    bs = [torch.from_numpy(synth.rhs_uniform(L, 70 + i)).cuda() for i, L in enumerate(levels)]
+    o_ref = mg.default_opts(precision=mg.MG_PREC_MIXED, rel_tol=1e-9)
+    xr = [torch.zeros_like(b) for b in bs]
+    sr = mg.solve_batch(hs, bs, xr, o_ref)
+    o = mg.default_opts(precision=mg.MG_PREC_MIXED, rel_tol=1e-9, zero_guess=1)
+    xs = [_garbage(b, 50 + i) for i, b in enumerate(bs)]
+    ss = mg.solve_batch(hs, bs, xs, o)
+    torch.cuda.synchronize()
+    for a, c, s1, s2 in zip(xs, xr, ss, sr):
+        assert s1.status == 0 and s2.status == 0
+        np.testing.assert_array_equal(a.cpu().numpy(), c.cpu().numpy())
+        assert (s1.cycles, s1.outer_steps, s1.rel_res) == (s2.cycles, s2.outer_steps, s2.rel_res)
+    for h in hs:
+        h.close()
