@@ -171,3 +171,29 @@ def test_zero_guess_in_a_batch(mg, ctx):
         assert (s1.cycles, s1.outer_steps, s1.rel_res) == (s2.cycles, s2.outer_steps, s2.rel_res)
     for h in hs:
         h.close()
+
+
+@pytest.mark.parametrize("k", [-60, 45])
+def test_solution_scales_exactly_with_b(mg, ctx, k):
+    """Powers of two scale exactly in binary arithmetic, and the mixed
+    scheme brings defects into FP32 range by a power of two from ||b||: the
+    solve for 2^k b is exactly 2^k times the solve for b (same residuals
+    and cycle counts) in every solver path."""
+    L = 9
+    h = mg.Hierarchy(ctx, L, jitter=0.2, seed=120)
+    b = torch.from_numpy(synth.rhs_uniform(L, 121)).cuda()
+    bk = torch.ldexp(b, torch.tensor(k, device="cuda"))
+    for kw in (dict(precision=mg.MG_PREC_FP64), dict(precision=mg.MG_PREC_MIXED),
+               dict(precision=mg.MG_PREC_MIXED, inner_max_cycles=1000),
+               dict(precision=mg.MG_PREC_MIXED, krylov=1)):
+        o = mg.default_opts(rel_tol=1e-9, zero_guess=1, **kw)
+        x1 = torch.empty_like(b)
+        s1 = h.solve(b, x1, o)
+        x2 = torch.empty_like(b)
+        s2 = h.solve(bk, x2, o)
+        torch.cuda.synchronize()
+        assert s1.status == 0 and s2.status == 0, kw
+        np.testing.assert_array_equal(x2.cpu().numpy(), np.ldexp(x1.cpu().numpy(), k))
+        assert s2.bnorm == np.ldexp(s1.bnorm, k)
+        assert (s2.rel_res, s2.cycles, s2.outer_steps) == (s1.rel_res, s1.cycles, s1.outer_steps), kw
+    h.close()

@@ -371,6 +371,25 @@ def test_mixed_reaches_1e8_and_fp32_alone_stalls(orc, L):
     assert st32.rel_res > 1e-8
 
 
+@pytest.mark.parametrize("k", [-60, -1, 1, 45])
+def test_mixed_solution_scales_exactly_with_b(orc, k):
+    """The mixed scheme brings defects into single-precision range with a
+    power of two taken from ||b||; powers of two scale exactly in binary
+    arithmetic, so solving for 2^k b gives exactly 2^k times the solution
+    for b, with the same relative residuals and cycle counts.  A correction
+    not scaled back (or scaled by another factor) breaks it."""
+    L = 6
+    h = orc.Hierarchy(L, synth.coords(L, 0.2, seed=5))
+    b = synth.rhs_uniform(L, 6)
+    o = orc.opts(rel_tol=1e-9)
+    x1, s1 = h.solve_mixed_emulated(b, o=o)
+    x2, s2 = h.solve_mixed_emulated(np.ldexp(b, k), o=o)
+    assert s1.status == 0 and s2.status == 0
+    np.testing.assert_array_equal(x2, np.ldexp(x1, k))
+    assert s2.bnorm == np.ldexp(s1.bnorm, k)
+    assert (s2.rel_res, s2.cycles, s2.outer_steps) == (s1.rel_res, s1.cycles, s1.outer_steps)
+
+
 def test_no_convergence_status(orc):
     L = 5
     h = orc.Hierarchy(L, synth.coords(L))
