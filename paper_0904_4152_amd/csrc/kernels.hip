@@ -238,8 +238,9 @@ __global__ __launch_bounds__(BT) void k_pre(const T* __restrict__ bands, int64_t
                                 (int)(lb % g.nstrips), (int)(lb / g.nstrips), g.rh, g.cw);
 }
 
-// Fused post-smoothing pass; with NORM one partial sum of squares per
-// (strip, wavefront, group of F_NORM_ROWS grid rows) in partials.
+// Fused post-smoothing pass; with NORM the residual partials of
+// dev::post_tile (one per group of F_NORM_ROWS rows and F_NORM_COLS
+// columns, dev::fused_norm_parts(N) in all).
 template <typename T, bool NORM, int BT>
 __global__ __launch_bounds__(BT) void k_post(const T* __restrict__ bands, int64_t bs, int N,
                                              const T* __restrict__ x, const T* __restrict__ xc,
