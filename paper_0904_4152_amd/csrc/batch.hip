@@ -3,7 +3,8 @@
 // transfer at one level) is one persistent launch over a work list of
 // (problem, tile) items covering every problem that has that level; the
 // problems are aligned at the coarse end, so one coarse-solve launch serves
-// them all.  Per-problem control (outer defect, cast, inner cycles, update,
+// them all.  Per-problem control (outer defect with the scaled FP32 cast,
+// inner cycles, update,
 // stop tests of Sec. 6.2's mixed scheme) is a state machine advanced on the
 // device by tiny controller kernels, so one iteration is a fixed sequence of
 // launches: it is captured once into a HIP graph and replayed.  A problem's
