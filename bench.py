@@ -197,8 +197,8 @@ def batch_problems(mg, ctx, synth, torch, dev, count=256):
 
 def bench_batch_only(mg, ctx, synth, torch, dev, args):
     """The batch alone: tuned tiles, then --warmup and --steps batched
-    solves (each from zero initial guesses set outside the timed call)."""
-    opts = mg.default_opts(precision=mg.MG_PREC_MIXED, rel_tol=1e-8)
+    solves (each from zero initial guesses, which the library does not read)."""
+    opts = mg.default_opts(precision=mg.MG_PREC_MIXED, rel_tol=1e-8, zero_guess=1)
     _, hs, bs, xs = batch_problems(mg, ctx, synth, torch, dev)
     mg.batch_clear_tiles()
     mg.solve_batch(hs, bs, xs, opts)

@@ -448,7 +448,8 @@ __global__ __launch_bounds__(BLOCK) void kb_outer_defect(const BProb* __restrict
 // Sum-of-squares partials of b64 (which = 0) or of the scaled FP32 defect
 // (which = 1) on the finest level.  With which = 0 (a new problem) also
 // whether the initial iterate x64 has a nonzero entry (state.xnz, an
-// integer OR over the tiles), so that its first defect can be b itself.
+// integer OR over the tiles), so that its first defect can be b itself; a
+// zero guess is known to be zero (x64 is not read).
 __global__ __launch_bounds__(BLOCK) void kb_sumsq(const BProb* __restrict__ probs,
                                                   BState* __restrict__ state,
                                                   const int* __restrict__ wl, int which,
@@ -459,7 +460,7 @@ __global__ __launch_bounds__(BLOCK) void kb_sumsq(const BProb* __restrict__ prob
     const int64_t base = (int64_t)tile * dev::NORM_TILE;
     const double sq = which == 0 ? dev::sumsq_tile<double>(lv.b64, lv.n, base)
                                  : dev::sumsq_tile<float>(lv.b32, lv.n, base);
-    if (which == 0) {
+    if (which == 0 && !P.zero_guess) {
         int nz = 0;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
