@@ -227,7 +227,10 @@ mg_status mg_solve(mg_hierarchy* h, const double* dev_b, double* dev_x,
  * the batch (its result equals a batch of one bit for bit).  opts: NULL
  * (defaults, mixed) or an array of count entries; precision must be
  * MG_PREC_MIXED, krylov 0, and nu_pre/nu_post must agree.  b[p], x[p]: device vectors
- * of that problem's finest n; x is in/out.  stats: NULL or count entries.
+ * of that problem's finest n; x is in/out (with opts zero_guess output
+ * only) and is updated in place as the solve goes, b is read in place: no
+ * x may be another problem's x or any problem's b (MG_ERR_INVALID), and
+ * neither may change during the call.  stats: NULL or count entries.
  * Synchronous.  Returns the first non-OK per-problem status, if any.
  * The batch machinery (device descriptors of the problems, work lists and
  * the captured iteration graph; a few MB of device memory outside any

@@ -74,8 +74,12 @@ public:
     mg_status init(int device, int capacity, int Lmax, int Lc, int nu_pre, int nu_post);
     ~BatchEngine();
 
-    // Describe slot s (host side); takes effect at the next upload().
-    void set_slot(int s, mg_hierarchy* h, const mg_solve_opts& o);
+    // Describe slot s (host side); takes effect at the next upload().  b and
+    // x (both or neither): the caller's finest right-hand side and iterate,
+    // used in place of the hierarchy's (b read; x read unless o.zero_guess,
+    // updated in place).
+    void set_slot(int s, mg_hierarchy* h, const mg_solve_opts& o, const double* b = nullptr,
+                  double* x = nullptr);
     void clear_slot(int s);
     // Mark slot s to start a solve from its hierarchy's finest b64 / x64.
     void start_slot(int s);
@@ -105,10 +109,10 @@ public:
     mg_status run(int64_t iter_cap, int64_t* iterations);
     // Copy the device states to the host mirror; returns it.
     mg_status read_states();
-    // One launch copying the callers' b and x of slots 0..count-1 into the
-    // problems' finest vectors (out = false; after upload), or the
-    // solutions back into x (out = true: x = 0 for a zero right-hand side).
-    mg_status io(const double* const* b, double* const* x, int count, bool out);
+    // After run(): one launch writing x = 0 for the slots whose solution is
+    // zero but whose x no update wrote (a zero right-hand side, or a zero
+    // guess that stopped before its first update).
+    mg_status zero_unwritten();
     // Autotuner: for every level the fused passes run on in the current
     // composition (after upload), time the pre and post passes with each
     // tile height, keep the fastest in the process-wide tile table and
@@ -152,8 +156,6 @@ private:
     int* h_wl_stage_[2] = {};        // work lists
     BState* h_start_stage_[2] = {};  // and started states
     BState* h_fetch_ = nullptr;      // pinned, one state
-    double** d_io_ = nullptr;        // callers' b and x of every slot
-    double** h_io_ = nullptr;        // pinned staging of d_io_
     std::vector<BProb> hp_;
     std::vector<int> h_wl_;
     std::vector<char> started_;

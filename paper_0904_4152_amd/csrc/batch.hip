@@ -21,6 +21,7 @@
 #include <map>
 #include <mutex>
 #include <new>
+#include <unordered_set>
 
 #include "batch.h"
 #include "device_ops.h"
@@ -475,7 +476,8 @@ __global__ __launch_bounds__(BLOCK) void kb_sumsq(const BProb* __restrict__ prob
 }
 
 // x64 += u double(c32), u = pow2_unscale(||b||) (the single solve's
-// update).
+// update); a zero guess's first update takes x64 as zero without reading
+// it (0.0 + u c, as the single solve's).
 __global__ __launch_bounds__(BLOCK) void kb_update(const BProb* __restrict__ probs,
                                                    const BState* __restrict__ state,
                                                    const int* __restrict__ wl, int mask) {
@@ -483,6 +485,7 @@ __global__ __launch_bounds__(BLOCK) void kb_update(const BProb* __restrict__ pro
     if (!(flags & mask)) continue;
     const BLevel& lv = P.lv[P.L];
     const double s = dev::pow2_unscale(state[p].bn);
+    const bool x_zero = P.zero_guess && state[p].outer == 0;
     const int64_t base = (int64_t)tile * TILE;
     double xv[4];  // loads first; lanes past n read element 0 and store nothing
     float cv[4];
@@ -490,7 +493,7 @@ __global__ __launch_bounds__(BLOCK) void kb_update(const BProb* __restrict__ pro
     for (int e = 0; e < 4; ++e) {
         const int64_t q = base + (int64_t)e * BLOCK + threadIdx.x;
         const int64_t r = q < lv.n ? q : 0;
-        xv[e] = lv.x64[r];
+        xv[e] = x_zero ? 0.0 : lv.x64[r];
         cv[e] = lv.x32[r];
     }
 #pragma unroll
@@ -501,34 +504,26 @@ __global__ __launch_bounds__(BLOCK) void kb_update(const BProb* __restrict__ pro
     END_ITEMS
 }
 
-// Copies between the callers' vectors and every listed problem's finest
-// vectors, one launch for the whole batch: out == 0: b64 <- b_p, x64 <- x_p
-// (x64 <- 0 for a zero guess, x_p not read); out != 0: x_p <- x64 (zero for
-// a zero right-hand side).  io[p] and io[cap + p] hold problem p's caller b
-// and x.
-__global__ __launch_bounds__(BLOCK) void kb_io(const BProb* __restrict__ probs,
-                                               const BState* __restrict__ state,
-                                               const int* __restrict__ wl,
-                                               double* const* __restrict__ io, int out) {
-    const int total = wl_total(wl), cap = wl[1];
+// x64 = 0 on every listed problem whose solution is zero but whose x64 no
+// update wrote: a zero right-hand side (solved at once), or a zero guess
+// (x64 not read) that stopped before its first update.
+__global__ __launch_bounds__(BLOCK) void kb_zero_unwritten(const BProb* __restrict__ probs,
+                                                           const BState* __restrict__ state,
+                                                           const int* __restrict__ wl) {
+    const int total = wl_total(wl);
     for (int t = blockIdx.x; t < total; t += gridDim.x) {
         int p, tile;
         wl_item(wl, t, &p, &tile);
-        const BLevel& lv = probs[p].lv[probs[p].L];
-        const double* bu = io[p];
-        double* xu = io[cap + p];
-        const bool zero = state[p].bn == 0.0 && state[p].status == MG_OK;
+        const BProb& P = probs[p];
+        const BState& S = state[p];
+        const bool zero = (S.bn == 0.0 && S.status == MG_OK) || (P.zero_guess && S.outer == 0);
+        if (!zero) continue;
+        const BLevel& lv = P.lv[P.L];
         const int64_t base = (int64_t)tile * TILE;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const int64_t q = base + (int64_t)e * BLOCK + threadIdx.x;
-            if (q >= lv.n) continue;
-            if (!out) {
-                lv.b64[q] = bu[q];
-                lv.x64[q] = probs[p].zero_guess ? 0.0 : xu[q];
-            } else {
-                xu[q] = zero ? 0.0 : lv.x64[q];
-            }
+            if (q < lv.n) lv.x64[q] = 0.0;
         }
     }
 }
@@ -741,8 +736,6 @@ BatchEngine::~BatchEngine() {
         if (e) (void)hipEventDestroy(e);
     if (ev_setup_) (void)hipEventDestroy(ev_setup_);
     if (d_iter_) (void)hipFree(d_iter_);
-    if (d_io_) (void)hipFree(d_io_);
-    if (h_io_) (void)hipHostFree(h_io_);
     if (h_state_) (void)hipHostFree(h_state_);
     if (h_ring_) (void)hipHostFree(h_ring_);
     for (int b = 0; b < 2; ++b) {
@@ -777,8 +770,6 @@ mg_status BatchEngine::init(int device, int capacity, int Lmax, int Lc, int nu_p
                              hipHostMallocDefault));
     }
     MG_HIP(hipHostMalloc((void**)&h_fetch_, sizeof(BState), hipHostMallocDefault));
-    MG_HIP(hipMalloc(&d_io_, sizeof(double*) * 2 * cap_));
-    MG_HIP(hipHostMalloc((void**)&h_io_, sizeof(double*) * 2 * cap_, hipHostMallocDefault));
     MG_HIP(hipMalloc(&d_probs_, sizeof(BProb) * cap_));
     MG_HIP(hipMalloc(&d_state_, sizeof(BState) * (cap_ + 1)));  // + flags union
     MG_HIP(hipMalloc(&d_wl_, sizeof(int) * NLISTS * (3 + 2 * cap_)));
@@ -805,7 +796,8 @@ mg_status BatchEngine::init(int device, int capacity, int Lmax, int Lc, int nu_p
     return MG_OK;
 }
 
-void BatchEngine::set_slot(int s, mg_hierarchy* h, const mg_solve_opts& o) {
+void BatchEngine::set_slot(int s, mg_hierarchy* h, const mg_solve_opts& o, const double* b,
+                           double* x) {
     BProb P{};
     for (int l = h->Lc; l <= h->L; ++l) {
         const Level& v = h->lv[l];
@@ -840,6 +832,10 @@ void BatchEngine::set_slot(int s, mg_hierarchy* h, const mg_solve_opts& o) {
     P.max_outer = o.max_cycles;
     P.fixed = o.fixed_cycles;
     P.zero_guess = o.zero_guess;
+    if (b) {
+        P.lv[P.L].b64 = const_cast<double*>(b);
+        P.lv[P.L].x64 = x;
+    }
     hp_[s] = P;
     probs_dirty_ = true;
 }
@@ -1368,21 +1364,11 @@ mg_status BatchEngine::run(int64_t iter_cap, int64_t* iterations) {
     return MG_OK;
 }
 
-mg_status BatchEngine::io(const double* const* b, double* const* x, int count, bool out) {
+mg_status BatchEngine::zero_unwritten() {
     MG_HIP(hipSetDevice(device_));
-    if (!out) {
-        // previous copies from the staging area have completed: read_states
-        // synchronised the stream after the last call
-        for (int p = 0; p < cap_; ++p) {
-            h_io_[p] = p < count ? const_cast<double*>(b[p]) : nullptr;
-            h_io_[cap_ + p] = p < count ? x[p] : nullptr;
-        }
-        MG_HIP(hipMemcpyAsync(d_io_, h_io_, sizeof(double*) * 2 * cap_, hipMemcpyHostToDevice,
-                              st_));
-    }
     const int stride = 3 + 2 * cap_;
-    hipLaunchKernelGGL(kb_io, dim3(STAGE_GRID), dim3(BLOCK), 0, st_, d_probs_, d_state_,
-                       (const int*)(d_wl_ + (size_t)WL_FINEST * stride), d_io_, (int)out);
+    hipLaunchKernelGGL(kb_zero_unwritten, dim3(STAGE_GRID), dim3(BLOCK), 0, st_, d_probs_,
+                       d_state_, (const int*)(d_wl_ + (size_t)WL_FINEST * stride));
     MG_HIP(hipGetLastError());
     return MG_OK;
 }
@@ -1526,6 +1512,17 @@ extern "C" mg_status mg_solve_batch(mg_hierarchy* const* hs, const double* const
             return fail(MG_ERR_INVALID, "invalid solver options");
         Lmax = std::max(Lmax, h->L);
     }
+    {
+        // the problems work in place on the callers' vectors: no x may be
+        // another problem's x or any problem's b
+        std::unordered_set<const void*> xs;
+        for (int p = 0; p < count; ++p)
+            if (!xs.insert(x[p]).second)
+                return fail(MG_ERR_INVALID, "two problems of the batch share an x vector");
+        for (int p = 0; p < count; ++p)
+            if (xs.count(b[p]))
+                return fail(MG_ERR_INVALID, "a problem's b is another problem's x");
+    }
     const int device = hs[0]->ctx->device, Lc = hs[0]->Lc;
     MG_HIP(hipSetDevice(device));
     MG_HIP(hipStreamSynchronize((hipStream_t)stream));
@@ -1558,15 +1555,14 @@ extern "C" mg_status mg_solve_batch(mg_hierarchy* const* hs, const double* const
     for (int p = 0; p < count; ++p) {
         mg_hierarchy* h = hs[p];
         const mg_solve_opts& o = opts ? opts[p] : def;
-        eng.set_slot(p, h, o);
+        eng.set_slot(p, h, o, b[p], x[p]);
         eng.start_slot(p);
         const int outer = o.fixed_cycles > 0 ? o.fixed_cycles : o.max_cycles;
         iter_cap = std::max<int64_t>(iter_cap, (int64_t)(outer + 1) * (o.inner_max_cycles + 1) + 4);
     }
     if (mg_status s = eng.upload()) return s;
-    if (mg_status s = eng.io(b, x, count, false)) return s;
     if (mg_status s = eng.run(iter_cap, nullptr)) return s;
-    if (mg_status s = eng.io(b, x, count, true)) return s;
+    if (mg_status s = eng.zero_unwritten()) return s;
     if (mg_status s = eng.read_states()) return s;
     mg_status worst = MG_OK;
     for (int p = 0; p < count; ++p) {

@@ -225,6 +225,39 @@ def test_batch_errors(mg, ctx):
         mg.solve_batch([probs[0][0], probs[0][0]], [probs[0][1]] * 2, xs,
                        mg.default_opts(precision=mg.MG_PREC_MIXED))
     assert e.value.status == mg.MG_ERR_INVALID
+    # the problems work in place: no shared x, no x that is another's b
+    hs2 = [probs[0][0], probs[1][0]]
+    same = [torch.zeros_like(probs[1][1])] * 2
+    for bs_, xs_ in (([probs[0][1], probs[1][1]], same),
+                     ([probs[0][1], xs[0]], [xs[0], xs[1]])):
+        with pytest.raises(mg.MgError) as e:
+            mg.solve_batch(hs2, bs_, xs_, mg.default_opts(precision=mg.MG_PREC_MIXED))
+        assert e.value.status == mg.MG_ERR_INVALID
+
+
+def test_batch_zero_rhs_and_early_stop_give_zero_x(mg, ctx):
+    """A zero right-hand side gives x = 0 (whatever x held); a zero guess
+    whose first defect already meets the tolerance gives x = 0 too; the
+    other problems of the batch are unaffected."""
+    probs = make_problems(mg, ctx, [5, 6, 7])
+    hs = [p[0] for p in probs]
+    bs = [p[1] for p in probs]
+    bs[0] = torch.zeros_like(bs[0])
+    ref = torch.zeros_like(bs[2])
+    st_ref = hs[2].solve(bs[2], ref, mg.default_opts(precision=mg.MG_PREC_MIXED))
+    for zg in (0, 1):
+        xs = [torch.full_like(b, 3.0) for b in bs]
+        xs[2].zero_()
+        opts = [mg.default_opts(precision=mg.MG_PREC_MIXED, zero_guess=zg),
+                mg.default_opts(precision=mg.MG_PREC_MIXED, zero_guess=1, rel_tol=10.0),
+                mg.default_opts(precision=mg.MG_PREC_MIXED, zero_guess=zg)]
+        st = mg.solve_batch(hs, bs, xs, opts)
+        torch.cuda.synchronize()
+        assert all(s.status == 0 for s in st)
+        assert not xs[0].cpu().numpy().any() and not xs[1].cpu().numpy().any()
+        assert st[1].outer_steps == 0
+        np.testing.assert_array_equal(xs[2].cpu().numpy(), ref.cpu().numpy())
+        assert (st[2].cycles, st[2].rel_res) == (st_ref.cycles, st_ref.rel_res)
 
 
 def test_server_result_same_alone_and_in_the_mix(mg, ctx, orc):
