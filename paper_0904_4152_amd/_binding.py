@@ -170,6 +170,17 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _ptr_array(ts):
+    """Device addresses of a list of contiguous device tensors, as a C array
+    (the batched calls marshal hundreds per call)."""
+    addrs = []
+    for t in ts:
+        if not t.is_cuda or not t.is_contiguous():
+            raise ValueError("expected contiguous device tensors")
+        addrs.append(t.data_ptr())
+    return (_vp * len(addrs))(*addrs)
+
+
 def _dt(t) -> int:
     if t.dtype == torch.float64:
         return MG_F64
@@ -439,12 +450,13 @@ def solve_batch(hierarchies, bs, xs, opts=None, stream=None, raise_on_error=True
     opts: None, one SolveOpts for all, or a list.  Returns the Stats list."""
     n = len(hierarchies)
     H = (_vp * n)(*[h.handle for h in hierarchies])
-    B = (_vp * n)(*[_ptr(t) for t in bs])
-    X = (_vp * n)(*[_ptr(t) for t in xs])
+    B = _ptr_array(bs)
+    X = _ptr_array(xs)
     O = None
-    if opts is not None:
-        lst = opts if isinstance(opts, (list, tuple)) else [opts] * n
-        O = (SolveOpts * n)(*lst)
+    if isinstance(opts, (list, tuple)):
+        O = (SolveOpts * n)(*opts)
+    elif opts is not None:  # one struct for all: n copies in one buffer copy
+        O = (SolveOpts * n).from_buffer_copy(bytes(opts) * n)
     S = (Stats * n)()
     rc = lib().mg_solve_batch(H, B, X, n, O, _stream(stream), S)
     if raise_on_error:
